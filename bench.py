@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the IMEX HDG-DG step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one ARS(2,3,2) IMEX step of Algorithm 1 over the whole mesh: three
+nonlinear DG residuals, two HDG stage solves (condensation, block-Jacobi
+BiCGStab with FP64 refinement on the trace system, local recovery) and the
+stage combinations.  The state is resident in HBM before the timed region.
+Prints one JSON line; progress goes to stderr.
+
+The roofline object covers the kernel class with the largest device time in
+a short all-classes profiling pass; its launches are then timed with HIP
+events on the library's stream inside the timed region.  The CPU baseline is
+the FP64 oracle on a bounded sample of the same workload recipe.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per IMEX step, mixed vs FP64 at fixed L2 err; HBM GB/s, MFMA %"
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_cost(name, wl, n_dof):
+    """(bytes, flops) one launch of a kernel class must move / compute:
+    every input read once and every output written once, FP64 values."""
+    K = wl.k + 1
+    nel = wl.n * wl.n
+    N = n_dof
+    T = 6 * K * nel
+    nfaces = 2 * nel
+    b3 = 3 * K
+    table = {
+        # read r, p, v, rh; write p, v
+        "bicg_k1": (6 * T * 8, 2.0 * 7 * b3 * b3 * nfaces),
+        # read r, v; write s, t
+        "bicg_k2": (4 * T * 8, 2.0 * 7 * b3 * b3 * nfaces),
+        # read d, p, s, t, rh; write d, r
+        "bicg_k3": (7 * T * 8, 8.0 * T),
+        "trace_residual": (5 * T * 8, 4.0 * 7 * b3 * b3 * nfaces),
+        "local_apply": (2 * N * 8, 2.0 * (3 * K * K) ** 2 * nel),
+        "recover": ((2 * N + T) * 8, 2.0 * (3 * K * K) * 12 * K * nel),
+        "trace_rhs": (4 * T * 8, 2.0 * b3 * b3 * nfaces),
+        "axpy": (3 * T * 8, 2.0 * T),
+    }
+    return table.get(name)
+
+
+def cpu_baseline(wl_name, seconds=15.0):
+    """FP64 oracle on a bounded sample: the same recipe (physics, degree,
+    dt = 5 dx_min, seed) on a 64 x 64 mesh, single-threaded, timed after its
+    one-off factorisation."""
+    from threadpoolctl import threadpool_limits
+    from oracle import imex, swe
+    from paper_1711_02751_amd import workloads as W
+    wl = W.WORKLOADS[wl_name]
+    n = min(wl.n, 64)
+    dt = wl.dt * wl.n / n
+    with threadpool_limits(limits=1):
+        P = imex.Problem(n, n, wl.L, wl.L, wl.k, wl.g, wl.H, dt, nonlinear=wl.nonlinear,
+                         solver="circulant")
+        x, y = P.mesh.coords()
+        h, hu, hv = W.bump_flow(x, y, wl.seed, H=wl.H, n_bumps=wl.n_bumps, Lx=wl.L, Ly=wl.L)
+        q = swe.from_user(h, hu, hv, wl.g, wl.H)
+        q = P.step(q)  # first step outside the clock
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            q = P.step(q)
+            steps += 1
+        el = time.perf_counter() - t0
+    ndof = 3 * n * n * (wl.k + 1) ** 2
+    return {"value": ndof * steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n}x{n} mesh, k={wl.k}, same recipe and CFL, {steps} ARS2 steps "
+                      f"after one warm step (block-circulant direct stage solve)",
+            "seconds": el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bump_256x256_k4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs and "
+              f"measures a single GPU (the multi-GPU decomposition is design only).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1711_02751_amd import imexhdg as m
+    from paper_1711_02751_amd import workloads as W
+
+    wl = W.WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
+                           dt=wl.dt, scheme=m.SCHEME_ARS232,
+                           physics=m.PHYSICS_NONLINEAR if wl.nonlinear else m.PHYSICS_LINEARIZED,
+                           precision=m.PREC_FP64)
+    log(f"[bench] workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
+    S = m.Solver(cfg)
+    x, y = S.nodes()
+    h, hu, hv = wl.initial_state(x, y)
+    S.set_state(h, hu, hv)
+    n_dof = 3 * S.n_nodes
+    log(f"[bench] state set: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {args.warmup}")
+    S.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # short all-classes pass to find the dominant kernel
+    S.profile(-1)
+    S.step(2)
+    per = {}
+    for name in m.KERNELS:
+        n, ms = S.profile_read(name)
+        if n:
+            per[name] = {"launches": n, "total_ms": ms, "avg_us": 1000.0 * ms / n}
+    dominant = max(per, key=lambda k: per[k]["total_ms"])
+    log(f"[bench] dominant kernel class: {dominant} "
+        f"({per[dominant]['avg_us']:.2f} us avg over {per[dominant]['launches']} launches)")
+
+    d0 = S.diag()
+    S.profile(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    el = t1 - t0
+    nl, ms = S.profile_read(dominant)
+    d1 = S.diag()
+    value = n_dof * args.steps / el
+    log(f"[bench] {args.steps} steps in {el:.3f} s -> {value:.4g} DOF-updates/s")
+
+    avg_s = ms / 1000.0 / nl
+    nbytes, nflops = algorithmic_cost(dominant, wl, n_dof)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = nflops / (FP64_VALU_PEAK_TFLOPS * 1e12)
+    if t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": nflops / avg_s / 1e12,
+                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dominant
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = nl
+    roof["algorithmic_bytes_per_launch"] = nbytes
+    roof["algorithmic_flops_per_launch"] = nflops
+
+    iters = (d1["krylov_iters"] - d0["krylov_iters"]) / max(1, d1["stage_solves"] - d0["stage_solves"])
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "mesh": f"{wl.n}x{wl.n}", "degree": wl.k,
+                   "n_dof": n_dof, "n_trace": S.n_trace, "dt": wl.dt, "scheme": "ARS232",
+                   "precision": "fp64", "parallelism": "single GPU"},
+        "roofline": roof,
+        "krylov_iters_per_stage": iters,
+        "max_trace_relres": d1["max_relres"],
+        "kernels": per,
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        out["cpu_baseline"] = cpu_baseline(wl.name, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    S.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

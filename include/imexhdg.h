@@ -1,0 +1,217 @@
+/*
+ * imexhdg.h - C ABI of the MI355X (gfx950) IMEX HDG-DG shallow-water step.
+ *
+ * The library advances the planar shallow-water equations in geopotential
+ * form (Kang, Giraldo & Bui-Thanh, arXiv:1711.02751, Sec. 3.1) on a periodic
+ * nx-by-ny grid of affine rectangles with degree-k nodal DG/HDG spaces
+ * (Sec. 4), one IMEX Runge-Kutta step at a time (Sec. 5, Algorithm 1):
+ *   - explicit DG residual of the nonlinear part with the Rusanov flux
+ *     (Sec. 4.3, eqs. Full_russanov / Linear_russanov);
+ *   - implicit HDG solve of the linear gravity-wave part: element-local
+ *     static condensation, the global trace system
+ *     (eq. linearizedHDGsystem_schur) and local recovery
+ *     (eq. recover_volume_unknowns);
+ *   - the stage combination (eqs. hdgIMEXRK_qi / hdgIMEXRK_qn).
+ *
+ * Discretisation choices (the paper leaves them open): LGL nodes with
+ * collocated LGL quadrature on elements and edges, trace nodes = LGL edge
+ * nodes, flat bottom phi_B = g H, periodic boundaries.
+ *
+ * Conventions
+ *   - Every call returns an int status: IMEXHDG_OK (0) or a negative code.
+ *     No exception or abort crosses the ABI.  imexhdg_last_error() returns a
+ *     thread-local message for the last failing call on the calling thread.
+ *   - Host arrays are caller owned and only read/written during the call.
+ *   - Node ordering of host state arrays is row-major over elements and,
+ *     inside an element, over LGL nodes: index ((ey*nx + ex)*K + j)*K + i,
+ *     K = k + 1, i along x and j along y.  n_nodes = nx*ny*K*K.
+ *   - Device arrays in "device layout" (operator-level calls) are
+ *     structure-of-arrays with the element index fastest:
+ *       volume  v[c][j*K + i][e]        c in (phi_eta, U, V), e = ey*nx + ex
+ *       trace   t[d][c][j][e]           d = 0: x-face e (west face of e),
+ *                                        d = 1: y-face e (south face of e),
+ *                                        j = LGL node index along the face.
+ *   - A context is bound to one HIP stream; calls on one context must not
+ *     overlap.  Distinct contexts are independent.
+ */
+#ifndef IMEXHDG_H
+#define IMEXHDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IMEXHDG_OK            0
+#define IMEXHDG_E_INVAL      -1  /* bad argument or configuration          */
+#define IMEXHDG_E_NOMEM      -2  /* device or host allocation failed        */
+#define IMEXHDG_E_DEVICE     -3  /* HIP runtime error                      */
+#define IMEXHDG_E_NOCONV     -4  /* trace solve missed its tolerance        */
+#define IMEXHDG_E_NONFINITE  -5  /* state became NaN or Inf                 */
+#define IMEXHDG_E_STATE      -6  /* call out of order (e.g. step before set) */
+
+/* IMEX tableaux named in Sec. 5 (Ascher, Ruuth & Spiteri 1997) */
+#define IMEXHDG_SCHEME_ARS232 0
+#define IMEXHDG_SCHEME_ARS443 1
+
+/* physics: linearized = only the linear (stiff) part, NL(q) = 0 */
+#define IMEXHDG_PHYSICS_LINEARIZED 0
+#define IMEXHDG_PHYSICS_NONLINEAR  1
+
+/* precision of the step */
+#define IMEXHDG_PREC_FP64   0  /* everything in FP64                        */
+#define IMEXHDG_PREC_MIXED  1  /* FP32 residual, local solves and inner
+                                  Krylov; FP64 state, trace residual,
+                                  iterative refinement and diagnostics      */
+
+/* variables of host state arrays */
+#define IMEXHDG_VARS_DEPTH       0  /* (h, hu, hv): depth and momenta        */
+#define IMEXHDG_VARS_GEOPOTENTIAL 1 /* (phi_eta, U, V) = (g(h-H), g hu, g hv) */
+
+typedef struct imexhdg_config {
+    int32_t nx, ny;          /* elements per direction, >= 1               */
+    double  Lx, Ly;          /* periodic domain [0,Lx) x [0,Ly), > 0       */
+    int32_t degree;          /* polynomial degree k, 1 <= k <= 8           */
+    double  g, H;            /* gravity and mean depth: phi_B = g H > 0    */
+    double  dt;              /* time step, > 0                             */
+    int32_t scheme;          /* IMEXHDG_SCHEME_*                           */
+    int32_t physics;         /* IMEXHDG_PHYSICS_*                          */
+    int32_t precision;       /* IMEXHDG_PREC_*                             */
+    double  krylov_rtol;     /* inner Krylov tolerance (preconditioned)    */
+    int32_t krylov_max_iter; /* inner iteration budget per solve           */
+    int32_t check_every;     /* iterations between convergence checks      */
+    double  refine_rtol;     /* FP64 true-residual tolerance ||g-Gx||/||g|| */
+    int32_t refine_max;      /* max refinement sweeps per stage solve      */
+} imexhdg_config;
+
+typedef struct imexhdg_diag {
+    double  mass[3];         /* FP64 sum of M q_c, c = phi_eta, U, V       */
+    double  energy;          /* E^h = ||phi_eta||^2 + ||U||^2_{1/phi_B}    */
+    int64_t steps;           /* steps taken since set_state                */
+    int64_t krylov_iters;    /* inner iterations, cumulative               */
+    int64_t stage_solves;    /* implicit stage solves, cumulative          */
+    int64_t refine_sweeps;   /* FP64 refinement sweeps, cumulative         */
+    double  last_relres;     /* last FP64 true relative trace residual     */
+    double  max_relres;      /* largest final relative residual so far     */
+    int32_t nonfinite;       /* 1 if the state holds NaN/Inf               */
+} imexhdg_diag;
+
+typedef struct imexhdg_ctx imexhdg_ctx;
+
+/* Fill *cfg with defaults (ARS232, nonlinear, FP64, 1 x 1 unit square,
+ * k = 2, g = H = 1, dt = 1e-3, krylov_rtol = 1e-14, refine_rtol = 1e-13). */
+int imexhdg_config_init(imexhdg_config *cfg);
+
+/* Validate cfg without touching a device.  Subcritical flow (|u| < sqrt(phi),
+ * Sec. 3) is a property of the state and is checked by set_state.          */
+int imexhdg_validate(const imexhdg_config *cfg);
+
+/* Device workspace the context needs for cfg, in bytes (host only).       */
+int imexhdg_workspace_bytes(const imexhdg_config *cfg, size_t *bytes);
+
+/* Create a context: validate, precompute the element operators in FP64 on
+ * the host (local solver A^-1, A^-1 B, Schur blocks of the trace system and
+ * their block-Jacobi inverses) and upload them.
+ *   stream      hipStream_t the context enqueues on (NULL = null stream);
+ *               caller owned, must outlive the context.
+ *   workspace   device buffer of >= imexhdg_workspace_bytes() bytes,
+ *               256-byte aligned, caller owned and outliving the context;
+ *               NULL makes the library allocate (and free) its own.
+ *   ws_bytes    size of `workspace` (ignored when it is NULL).            */
+int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace,
+                   size_t ws_bytes, imexhdg_ctx **out);
+
+/* NULL-safe; synchronises the context's stream first.                    */
+void imexhdg_destroy(imexhdg_ctx *ctx);
+
+int imexhdg_sizes(const imexhdg_ctx *ctx, int64_t *n_nodes, int64_t *n_trace);
+
+/* Node coordinates (host, n_nodes each, host state ordering).            */
+int imexhdg_get_nodes(const imexhdg_ctx *ctx, double *x, double *y);
+
+/* Copy a state in (host arrays of n_nodes doubles, host state ordering);
+ * `vars` is IMEXHDG_VARS_*.  Rejects non-finite values, h <= 0 and
+ * supercritical nodes |u| >= sqrt(g h) with IMEXHDG_E_INVAL.              */
+int imexhdg_set_state(imexhdg_ctx *ctx, int vars, const double *a,
+                      const double *b, const double *c);
+
+/* Copy the state out; synchronises the stream.                           */
+int imexhdg_get_state(imexhdg_ctx *ctx, int vars, double *a, double *b,
+                      double *c);
+
+/* Enqueue nsteps IMEX steps (Algorithm 1) on the context's stream.  The
+ * trace solves check convergence every `check_every` inner iterations,
+ * which synchronises the stream; IMEXHDG_E_NOCONV if a stage solve ends
+ * above refine_rtol after refine_max sweeps (the state is still advanced). */
+int imexhdg_step(imexhdg_ctx *ctx, int32_t nsteps);
+
+/* FP64 mass and energy of the current state plus solver counters;
+ * synchronises the stream.                                               */
+int imexhdg_get_diag(imexhdg_ctx *ctx, imexhdg_diag *d);
+
+/* Thread-local text of the last error ("" if none).                      */
+const char *imexhdg_last_error(void);
+
+/* ---------------- operator-level calls (device pointers, device layout)
+ * All pointers are device memory of the sizes stated, caller owned; the
+ * work is enqueued on the context's stream and these calls do not
+ * synchronise unless stated.                                             */
+
+/* Device layout base of the context's current state q^n (3*n_nodes FP64,
+ * volume device layout).  Valid until the context is destroyed.          */
+int imexhdg_state_device(imexhdg_ctx *ctx, double **d_q);
+
+/* out = M^-1 NL(q) (Sec. 4.3): volume term (F_NL(q), grad v)_K and the
+ * Rusanov surface flux F*_NL = F* - F*_L.  q, out: 3*n_nodes FP64.       */
+int imexhdg_nl_residual(imexhdg_ctx *ctx, const double *d_q, double *d_out);
+
+/* out = M^-1 L(Q, Qhat) (Sec. 4.3): (F_L(Q), grad v)_K minus the lifted
+ * hybridized flux of eq. linear_hdgflux3.  Q: 3*n_nodes, Qhat: n_trace.   */
+int imexhdg_linear_residual(imexhdg_ctx *ctx, const double *d_Q,
+                            const double *d_qhat, double *d_out);
+
+/* One implicit stage (eq. IMEXRKDiscretizedForm) with coefficient
+ * dt*a_ii of the configured scheme: condense Res0, solve the trace system,
+ * recover Q.  d_qhat holds the initial guess on entry and the trace on
+ * exit.  Synchronises; *iters and *relres (FP64 true relative residual)
+ * may be NULL.                                                            */
+int imexhdg_stage_solve(imexhdg_ctx *ctx, const double *d_res0, double *d_Q,
+                        double *d_qhat, int32_t *iters, double *relres);
+
+/* ---------------- per-kernel event profiler
+ * Kernel classes timed with HIP events recorded on the context's stream
+ * around each launch of the selected class(es).                          */
+#define IMEXHDG_K_NL           0  /* NL residual + stage combination       */
+#define IMEXHDG_K_COMBINE      1  /* stage combination (linearized)        */
+#define IMEXHDG_K_LOCAL_APPLY  2  /* Z = A^-1 Res0 per element             */
+#define IMEXHDG_K_TRACE_RHS    3  /* g = sum C Z, ghat = P^-1 g            */
+#define IMEXHDG_K_TRACE_RESID  4  /* FP64 r = g - G x, rin = ghat - Ghat x  */
+#define IMEXHDG_K_BICG_INIT    5
+#define IMEXHDG_K_BICG_K1      6  /* p update + v = Ghat p, rh . v         */
+#define IMEXHDG_K_BICG_K2      7  /* s update + t = Ghat s, t . s, t . t   */
+#define IMEXHDG_K_BICG_K3      8  /* d, r update, rh . r, r . r            */
+#define IMEXHDG_K_AXPY         9  /* x += d after a refinement sweep       */
+#define IMEXHDG_K_RECOVER     10  /* Q = Z - A^-1 B Qhat per element       */
+#define IMEXHDG_K_DIAG        11
+#define IMEXHDG_K_LINRES      12  /* M^-1 L(Q, Qhat)                       */
+#define IMEXHDG_K_COUNT       13
+
+/* Select the class to time (0..IMEXHDG_K_COUNT-1), -1 for all classes or
+ * -2 to switch timing off; clears the accumulated times.                 */
+int imexhdg_profile(imexhdg_ctx *ctx, int32_t kernel);
+
+/* Launch count and summed device time (ms) of a class since the last
+ * imexhdg_profile(); synchronises the stream.                            */
+int imexhdg_profile_read(imexhdg_ctx *ctx, int32_t kernel, int64_t *launches,
+                         double *total_ms);
+
+/* Static name of a kernel class, or NULL for an unknown id.              */
+const char *imexhdg_kernel_name(int32_t kernel);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMEXHDG_H */

@@ -1,0 +1,808 @@
+// C ABI of the IMEX HDG-DG step: context, workspace, stage orchestration.
+#include "../../include/imexhdg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "element.hpp"
+#include "kernels.hpp"
+
+using namespace imexhdg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                            \
+    do {                                                                         \
+        hipError_t _e = (expr);                                                  \
+        if (_e != hipSuccess)                                                    \
+            return fail(IMEXHDG_E_DEVICE, std::string(#expr) + ": " +            \
+                                              hipGetErrorString(_e));            \
+    } while (0)
+
+// IMEX tableau: explicit A (strictly lower), implicit At (SDIRK), b, bt.
+struct Tableau {
+    int s = 0;
+    std::vector<double> A, At, b, bt;   // s x s row-major, s
+    double a(int i, int j) const { return A[i * s + j]; }
+    double at(int i, int j) const { return At[i * s + j]; }
+};
+
+Tableau make_tableau(int scheme) {
+    Tableau t;
+    if (scheme == IMEXHDG_SCHEME_ARS232) {
+        // ARS(2,3,2): gamma = 1 - 1/sqrt(2), delta = -2 sqrt(2)/3
+        const double g = 1.0 - 1.0 / std::sqrt(2.0), d = -2.0 * std::sqrt(2.0) / 3.0;
+        t.s = 3;
+        t.A = {0, 0, 0, g, 0, 0, d, 1 - d, 0};
+        t.At = {0, 0, 0, 0, g, 0, 0, 1 - g, g};
+        t.b = {0, 1 - g, g};
+        t.bt = {0, 1 - g, g};
+    } else {
+        // ARS(4,4,3), both parts stiffly accurate
+        t.s = 5;
+        t.A = {0, 0, 0, 0, 0,  0.5, 0, 0, 0, 0,  11.0 / 18, 1.0 / 18, 0, 0, 0,
+               5.0 / 6, -5.0 / 6, 0.5, 0, 0,  0.25, 1.75, 0.75, -1.75, 0};
+        t.At = {0, 0, 0, 0, 0,  0, 0.5, 0, 0, 0,  0, 1.0 / 6, 0.5, 0, 0,
+                0, -0.5, 0.5, 0.5, 0,  0, 1.5, -1.5, 0.5, 0.5};
+        t.b = {0.25, 1.75, 0.75, -1.75, 0};
+        t.bt = {0, 1.5, -1.5, 0.5, 0.5};
+    }
+    return t;
+}
+
+// A linear combination over the step's vectors.  Vector ids:
+//   QN (q^n), NLV+j (NL_j), QV+j (Q_j), RV+j (Res0_j), SELF (kernel result).
+enum { QN = 0, NLV = 1, QV = 17, RV = 33, SELF = 49 };
+struct Term { int id; double coef; };
+using Plan = std::vector<Term>;
+
+void add(Plan &p, int id, double c) {
+    if (c == 0.0) return;
+    for (Term &t : p)
+        if (t.id == id) { t.coef += c; return; }
+    p.push_back({id, c});
+}
+
+void cleanup(Plan &p) {
+    Plan out;
+    for (const Term &t : p)
+        if (t.coef != 0.0) out.push_back(t);
+    p.swap(out);
+}
+
+}  // namespace
+
+struct imexhdg_ctx {
+    imexhdg_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool own_ws = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    LGL ref;
+    StageOperators op;
+    Geom geom{};
+    Tableau tab;
+    double aii = 0.0;
+    size_t N = 0, T = 0, nnodes = 0;
+    // device buffers
+    double *q = nullptr, *Z = nullptr, *tmp = nullptr;
+    std::vector<double *> NLb, Qb, Rb;
+    double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr, *rin = nullptr;
+    double *kr = nullptr, *krh = nullptr, *kp[2] = {nullptr, nullptr},
+           *kv[2] = {nullptr, nullptr}, *ks_ = nullptr, *kt = nullptr, *kd = nullptr;
+    double *dAinv = nullptr, *dW = nullptr, *dG = nullptr, *dGh = nullptr, *dPx = nullptr,
+           *dPy = nullptr;
+    KrylovState *ks = nullptr;
+    KrylovBufs kb{};
+    double *dpart = nullptr;          // [5][kPartStride] residual / diagnostics partials
+    // host mirrors
+    KrylovState *hks = nullptr;
+    double *hpart = nullptr;
+    bool have_state = false;
+    // plans: after stage i the NL kernel writes plan_out[i]
+    std::vector<Plan> plans;
+    std::vector<bool> store_nl;
+    // counters
+    int64_t steps = 0, kiters = 0, solves = 0, sweeps = 0;
+    double last_relres = 0.0, max_relres = 0.0;
+    // event profiler
+    int prof_target = -2;
+    std::vector<hipEvent_t> ev0, ev1;
+    std::vector<int> ev_id;
+    int ev_used = 0;
+    double prof_ms[IMEXHDG_K_COUNT] = {};
+    int64_t prof_n[IMEXHDG_K_COUNT] = {};
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// stride of every partial-sum array; no launch has a larger grid
+constexpr int kPartStride = 1024;
+
+struct Layout {
+    size_t N, T, n_loc, n_tr, max_blocks, total;
+    int s;
+};
+
+Layout layout_of(const imexhdg_config &c) {
+    Layout L{};
+    const size_t K = (size_t)c.degree + 1, nel = (size_t)c.nx * c.ny;
+    L.N = 3 * K * K * nel;
+    L.T = 6 * K * nel;
+    L.n_loc = 3 * K * K;
+    L.n_tr = 12 * K;
+    L.s = (c.scheme == IMEXHDG_SCHEME_ARS443) ? 5 : 3;
+    L.max_blocks = kPartStride;
+    size_t t = 0;
+    t += 3 * align256(L.N * 8);                       // q, Z, tmp
+    t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
+    t += 14 * align256(L.T * 8);                       // trace vectors
+    t += align256(L.n_loc * L.n_loc * 8) + align256(L.n_loc * L.n_tr * 8);
+    t += 2 * align256(2 * 7 * 9 * K * K * 8) + 2 * align256(9 * K * K * 8);
+    t += 5 * align256(kPartStride * 8) + align256(5 * kPartStride * 8);
+    t += align256(sizeof(KrylovState));
+    L.total = t;
+    return L;
+}
+
+int validate(const imexhdg_config *c) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1) return fail(IMEXHDG_E_INVAL, "nx and ny must be >= 1");
+    if ((int64_t)c->nx * c->ny > (int64_t)1 << 28)
+        return fail(IMEXHDG_E_INVAL, "too many elements");
+    if (c->degree < 1 || c->degree > 8) return fail(IMEXHDG_E_INVAL, "degree must be in [1, 8]");
+    if (!(c->Lx > 0) || !(c->Ly > 0) || !std::isfinite(c->Lx) || !std::isfinite(c->Ly))
+        return fail(IMEXHDG_E_INVAL, "domain lengths must be positive and finite");
+    if (!(c->g > 0) || !(c->H > 0) || !std::isfinite(c->g * c->H))
+        return fail(IMEXHDG_E_INVAL, "g and H must be positive (phi_B = g H > 0)");
+    if (!(c->dt > 0) || !std::isfinite(c->dt)) return fail(IMEXHDG_E_INVAL, "dt must be > 0");
+    if (c->scheme != IMEXHDG_SCHEME_ARS232 && c->scheme != IMEXHDG_SCHEME_ARS443)
+        return fail(IMEXHDG_E_INVAL, "unknown scheme");
+    if (c->physics != IMEXHDG_PHYSICS_LINEARIZED && c->physics != IMEXHDG_PHYSICS_NONLINEAR)
+        return fail(IMEXHDG_E_INVAL, "unknown physics");
+    if (c->precision != IMEXHDG_PREC_FP64)
+        return fail(IMEXHDG_E_INVAL, "precision not supported by this build");
+    if (!(c->krylov_rtol > 0) || !(c->krylov_rtol < 1))
+        return fail(IMEXHDG_E_INVAL, "krylov_rtol must be in (0, 1)");
+    if (!(c->refine_rtol > 0) || !(c->refine_rtol < 1))
+        return fail(IMEXHDG_E_INVAL, "refine_rtol must be in (0, 1)");
+    if (c->krylov_max_iter < 1 || c->check_every < 1 || c->refine_max < 1)
+        return fail(IMEXHDG_E_INVAL, "iteration budgets must be >= 1");
+    return IMEXHDG_OK;
+}
+
+// Build the combination plans of Algorithm 1 for the configured tableau.
+// After stage i (0-based) the NL kernel (or a plain combination when the
+// physics is linearized) writes Res0_{i+1}, or q^{n+1} after the last stage.
+// The implicit residual of an implicit stage j is taken from its local
+// equation (eq. IMEXRKDiscretizedForm_localSolver):
+//   dt M^-1 L_j = (Q_j - Res0_j) / a~_jj.
+int build_plans(imexhdg_ctx *c) {
+    const Tableau &t = c->tab;
+    const double dt = c->cfg.dt;
+    const int s = t.s;
+    for (int j = 0; j < s; ++j)
+        if (t.at(j, j) == 0.0 && j != 0)
+            return fail(IMEXHDG_E_INVAL, "explicit-only stage after the first");
+    for (int i = 1; i < s; ++i)
+        if (t.at(i, 0) != 0.0)
+            return fail(IMEXHDG_E_INVAL, "tableau needs L(q^n) (a~_i1 != 0)");
+    c->plans.assign(s, Plan());
+    for (int i = 0; i < s; ++i) {
+        Plan p;
+        if (i + 1 < s) {
+            const int m = i + 1;   // Res0_m
+            add(p, QN, 1.0);
+            for (int j = 0; j <= i; ++j) {
+                add(p, j == i ? SELF : NLV + j, dt * t.a(m, j));
+                if (j > 0) {
+                    const double r = t.at(m, j) / t.at(j, j);
+                    add(p, QV + j, r);
+                    add(p, RV + j, -r);
+                }
+            }
+        } else {
+            // q^{n+1}; if the implicit weights equal the last implicit row
+            // (stiffly accurate), q^{n+1} = Q_s + dt sum (b_j - a_sj) NL_j.
+            bool stiff = s > 1;
+            for (int j = 0; j < s; ++j)
+                if (std::fabs(t.bt[j] - t.at(s - 1, j)) > 1e-15) stiff = false;
+            if (stiff) {
+                add(p, QV + (s - 1), 1.0);
+                for (int j = 0; j < s; ++j)
+                    add(p, j == s - 1 ? SELF : NLV + j, dt * (t.b[j] - t.a(s - 1, j)));
+            } else {
+                add(p, QN, 1.0);
+                for (int j = 0; j < s; ++j) {
+                    add(p, j == s - 1 ? SELF : NLV + j, dt * t.b[j]);
+                    if (j > 0) {
+                        add(p, QV + j, t.bt[j] / t.at(j, j));
+                        add(p, RV + j, -t.bt[j] / t.at(j, j));
+                    }
+                }
+            }
+        }
+        cleanup(p);
+        c->plans[i] = p;
+    }
+    c->store_nl.assign(s, false);
+    for (const Plan &p : c->plans)
+        for (const Term &tm : p)
+            if (tm.id >= NLV && tm.id < QV) c->store_nl[tm.id - NLV] = true;
+    return IMEXHDG_OK;
+}
+
+// ---- event profiler: events are read back at the library's own stream
+// synchronisations, so timing adds no extra host-device round trips.
+constexpr int kEventPool = 1024;
+
+void prof_harvest(imexhdg_ctx *c) {
+    for (int i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev0[i], c->ev1[i]) == hipSuccess) {
+            c->prof_ms[c->ev_id[i]] += ms;
+            c->prof_n[c->ev_id[i]] += 1;
+        }
+    }
+    c->ev_used = 0;
+}
+
+bool prof_on(const imexhdg_ctx *c, int id) {
+    return c->prof_target == -1 || c->prof_target == id;
+}
+
+hipError_t prof_begin(imexhdg_ctx *c, int id) {
+    if (!prof_on(c, id)) return hipSuccess;
+    if (c->ev_used == kEventPool) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return e;
+        prof_harvest(c);
+    }
+    return hipEventRecord(c->ev0[c->ev_used], c->stream);
+}
+
+hipError_t prof_end(imexhdg_ctx *c, int id) {
+    if (!prof_on(c, id)) return hipSuccess;
+    hipError_t e = hipEventRecord(c->ev1[c->ev_used], c->stream);
+    c->ev_id[c->ev_used] = id;
+    c->ev_used += 1;
+    return e;
+}
+
+hipError_t stream_sync(imexhdg_ctx *c) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) prof_harvest(c);
+    return e;
+}
+
+#define LAUNCH(id, expr)                \
+    do {                                \
+        HIP_TRY(prof_begin(c, id));     \
+        HIP_TRY(expr);                  \
+        HIP_TRY(prof_end(c, id));       \
+    } while (0)
+
+const double *vec_of(imexhdg_ctx *c, int id) {
+    if (id == QN) return c->q;
+    if (id >= NLV && id < QV) return c->NLb[id - NLV];
+    if (id >= QV && id < RV) return c->Qb[id - QV];
+    return c->Rb[id - RV];
+}
+
+int sync_read_ks(imexhdg_ctx *c) {
+    HIP_TRY(hipMemcpyAsync(c->hks, c->ks, sizeof(KrylovState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(stream_sync(c));
+    return IMEXHDG_OK;
+}
+
+// Sum partials [nq][n] on the host in a fixed order (deterministic).
+int read_partials(imexhdg_ctx *c, int nq, unsigned n, double *out) {
+    HIP_TRY(hipMemcpyAsync(c->hpart, c->dpart, (size_t)nq * kPartStride * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(stream_sync(c));
+    for (int q = 0; q < nq; ++q) {
+        double s = 0.0;
+        for (unsigned i = 0; i < n; ++i) s += c->hpart[(size_t)q * kPartStride + i];
+        out[q] = s;
+    }
+    return IMEXHDG_OK;
+}
+
+// Trace solve by FP64 iterative refinement around block-Jacobi BiCGStab.
+// x holds the initial guess and receives the solution.  Each sweep: FP64
+// residual r = g - G x (and its preconditioned form rin), stop if
+// ||r|| <= refine_rtol ||g||, else solve Ghat d = rin and set x += d.
+int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
+    const imexhdg_config &cf = c->cfg;
+    const Geom &g = c->geom;
+    int iters = 0;
+    double relres = 0.0;
+    for (int sweep = 0;; ++sweep) {
+        int rc;
+        LAUNCH(IMEXHDG_K_TRACE_RESID,
+               launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64, c->rin,
+                                     c->dpart, kPartStride, c->stream));
+        double nrm[4];
+        if ((rc = read_partials(c, 4, face_grid(g), nrm))) return rc;
+        const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
+        if (!std::isfinite(gg) || !std::isfinite(rr) || !std::isfinite(rinrin)) {
+            c->last_relres = NAN;
+            return fail(IMEXHDG_E_NONFINITE, "non-finite trace residual");
+        }
+        relres = gg > 0.0 ? std::sqrt(rr / gg) : std::sqrt(rr);
+        if (relres <= cf.refine_rtol || sweep >= cf.refine_max) break;
+        c->sweeps += 1;
+        // inner tolerance: krylov_rtol relative to the sweep's right-hand
+        // side, floored at 0.1 refine_rtol relative to ||ghat||
+        const double fl = 0.1 * cf.refine_rtol;
+        const double tol2 = std::max(cf.krylov_rtol * cf.krylov_rtol * rinrin, fl * fl * ghh);
+        LAUNCH(IMEXHDG_K_BICG_INIT, launch_bicg_init(g, c->rin, c->kr, c->krh, c->kp[0], c->kv[0],
+                                                     c->kd, c->ks, tol2, c->kb, c->stream));
+        int par = 0;     // p, v of the current iteration live in kp[par], kv[par]
+        LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, c->dGh, c->kr, c->krh, c->kp[par], c->kv[par],
+                                                 c->kp[1 - par], c->kv[1 - par], c->ks, c->kb,
+                                                 c->stream));
+        par = 1 - par;
+        int done = 0;
+        while (done < cf.krylov_max_iter) {
+            const int n = std::min(cf.check_every, cf.krylov_max_iter - done);
+            for (int it = 0; it < n; ++it) {
+                LAUNCH(IMEXHDG_K_BICG_K2, launch_bicg_k2(g, c->dGh, c->kr, c->kv[par], c->ks_,
+                                                         c->kt, c->ks, c->kb, c->stream));
+                LAUNCH(IMEXHDG_K_BICG_K3, launch_bicg_k3(g, c->kd, c->kr, c->krh, c->kp[par],
+                                                         c->ks_, c->kt, c->ks, c->kb, c->stream));
+                LAUNCH(IMEXHDG_K_BICG_K1,
+                       launch_bicg_k1(g, c->dGh, c->kr, c->krh, c->kp[par], c->kv[par],
+                                      c->kp[1 - par], c->kv[1 - par], c->ks, c->kb, c->stream));
+                par = 1 - par;
+            }
+            done += n;
+            if ((rc = sync_read_ks(c))) return rc;
+            if (c->hks->conv) break;
+        }
+        iters += c->hks->iters;
+        LAUNCH(IMEXHDG_K_AXPY, launch_axpy(c->x, c->kd, 1.0, c->T, c->stream));
+    }
+    c->kiters += iters;
+    c->solves += 1;
+    c->last_relres = relres;
+    if (relres > c->max_relres) c->max_relres = relres;
+    if (iters_out) *iters_out = iters;
+    if (relres_out) *relres_out = relres;
+    if (relres > cf.refine_rtol)
+        return fail(IMEXHDG_E_NOCONV, "trace solve above refine_rtol after refine_max sweeps");
+    return IMEXHDG_OK;
+}
+
+// One implicit stage: Z = A^-1 R, g = C Z, solve G x = g, Q = Z - W x.
+int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres) {
+    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->dAinv, R, c->Z, c->stream));
+    LAUNCH(IMEXHDG_K_TRACE_RHS,
+           launch_trace_rhs(c->geom, c->Z, c->dPx, c->dPy, c->gv, c->gh, c->stream));
+    int rc = trace_solve(c, iters, relres);
+    if (rc && rc != IMEXHDG_E_NOCONV) return rc;
+    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->dW, c->Z, c->x, Q, c->stream));
+    return rc;
+}
+
+int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
+    Comb cb{};
+    cb.n = 0;
+    cb.self = 0.0;
+    cb.out = out;
+    cb.store = c->store_nl[i] ? c->NLb[i] : nullptr;
+    const bool nonlinear = c->cfg.physics == IMEXHDG_PHYSICS_NONLINEAR;
+    for (const Term &t : c->plans[i]) {
+        if (t.id == SELF) { cb.self = t.coef; continue; }
+        if (!nonlinear && t.id >= NLV && t.id < QV) continue;
+        if (cb.n >= kMaxComb) return fail(IMEXHDG_E_INVAL, "combination too long");
+        cb.in[cb.n] = vec_of(c, t.id);
+        cb.coef[cb.n] = t.coef;
+        cb.n += 1;
+    }
+    if (nonlinear) {
+        LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, Qi, cb, c->stream));
+    } else {
+        LAUNCH(IMEXHDG_K_COMBINE, launch_combine(c->geom, cb, c->N, c->stream));
+    }
+    return IMEXHDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int imexhdg_config_init(imexhdg_config *c) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "config is NULL");
+    std::memset(c, 0, sizeof(*c));
+    c->nx = c->ny = 1;
+    c->Lx = c->Ly = 1.0;
+    c->degree = 2;
+    c->g = c->H = 1.0;
+    c->dt = 1e-3;
+    c->scheme = IMEXHDG_SCHEME_ARS232;
+    c->physics = IMEXHDG_PHYSICS_NONLINEAR;
+    c->precision = IMEXHDG_PREC_FP64;
+    c->krylov_rtol = 1e-14;
+    c->krylov_max_iter = 500;
+    c->check_every = 8;
+    c->refine_rtol = 1e-13;
+    c->refine_max = 4;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_validate(const imexhdg_config *cfg) { return validate(cfg); }
+
+int imexhdg_workspace_bytes(const imexhdg_config *cfg, size_t *bytes) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!bytes) return fail(IMEXHDG_E_INVAL, "bytes is NULL");
+    *bytes = layout_of(*cfg).total;
+    return IMEXHDG_OK;
+}
+
+const char *imexhdg_last_error(void) { return g_last_error.c_str(); }
+
+int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, size_t ws_bytes,
+                   imexhdg_ctx **out) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!out) return fail(IMEXHDG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    const Layout L = layout_of(*cfg);
+    if (workspace && ws_bytes < L.total)
+        return fail(IMEXHDG_E_INVAL, "workspace smaller than imexhdg_workspace_bytes()");
+    if (workspace && ((uintptr_t)workspace & 255))
+        return fail(IMEXHDG_E_INVAL, "workspace must be 256-byte aligned");
+    imexhdg_ctx *c = new (std::nothrow) imexhdg_ctx();
+    if (!c) return fail(IMEXHDG_E_NOMEM, "host allocation failed");
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        imexhdg_destroy(c);
+        return code;
+    };
+    try {
+        c->ref = make_lgl(cfg->degree);
+        c->tab = make_tableau(cfg->scheme);
+        double aii = 0.0;
+        for (int i = 0; i < c->tab.s; ++i)
+            if (c->tab.at(i, i) != 0.0) {
+                if (aii != 0.0 && std::fabs(aii - c->tab.at(i, i)) > 1e-15)
+                    return bail(fail(IMEXHDG_E_INVAL, "tableau is not SDIRK"));
+                aii = c->tab.at(i, i);
+            }
+        c->aii = aii;
+        const double hx = cfg->Lx / cfg->nx, hy = cfg->Ly / cfg->ny;
+        c->op = make_stage_operators(c->ref, hx, hy, cfg->g * cfg->H, cfg->dt * aii);
+    } catch (const std::exception &e) {
+        return bail(fail(IMEXHDG_E_INVAL, std::string("precompute: ") + e.what()));
+    }
+    if ((rc = build_plans(c))) return bail(rc);
+    const int K = cfg->degree + 1;
+    Geom &g = c->geom;
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nel = cfg->nx * cfg->ny;
+    g.K = K;
+    g.sx = 2.0 * cfg->nx / cfg->Lx;
+    g.sy = 2.0 * cfg->ny / cfg->Ly;
+    g.phiB = cfg->g * cfg->H;
+    g.tau = std::sqrt(g.phiB);
+    g.winv0 = 1.0 / c->ref.w[0];
+    g.winvk = 1.0 / c->ref.w[K - 1];
+    for (int m = 0; m < K; ++m)
+        for (int a = 0; a < K; ++a)
+            g.Dw[m * K + a] = c->ref.w[m] * c->ref.D[m * K + a] / c->ref.w[a];
+    for (int j = 0; j < K; ++j)
+        for (int i = 0; i < K; ++i)
+            g.mass[j * K + i] = (cfg->Lx / cfg->nx / 2.0) * (cfg->Ly / cfg->ny / 2.0) *
+                                c->ref.w[i] * c->ref.w[j];
+    c->N = L.N;
+    c->T = L.T;
+    c->nnodes = L.N / 3;
+
+    if (hipGetDevice(&c->device) != hipSuccess)
+        return bail(fail(IMEXHDG_E_DEVICE, "no HIP device"));
+    if (workspace) {
+        c->ws = (char *)workspace;
+        c->ws_bytes = ws_bytes;
+    } else {
+        if (hipMalloc((void **)&c->ws, L.total) != hipSuccess) {
+            c->ws = nullptr;
+            return bail(fail(IMEXHDG_E_NOMEM, "hipMalloc of the workspace failed"));
+        }
+        c->own_ws = true;
+        c->ws_bytes = L.total;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = c->ws + off;
+        off += align256(bytes);
+        return p;
+    };
+    c->q = (double *)take(L.N * 8);
+    c->Z = (double *)take(L.N * 8);
+    c->tmp = (double *)take(L.N * 8);
+    for (int i = 0; i < L.s; ++i) c->NLb.push_back((double *)take(L.N * 8));
+    for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
+    for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
+    double **tv[14] = {&c->x,     &c->gv,    &c->gh,    &c->r64, &c->rin,
+                       &c->kr,    &c->krh,   &c->kp[0], &c->kp[1], &c->kv[0],
+                       &c->kv[1], &c->ks_,   &c->kt,    &c->kd};
+    for (double **p : tv) *p = (double *)take(L.T * 8);
+    c->dAinv = (double *)take(L.n_loc * L.n_loc * 8);
+    c->dW = (double *)take(L.n_loc * L.n_tr * 8);
+    c->dG = (double *)take(2 * 7 * 9 * K * K * 8);
+    c->dGh = (double *)take(2 * 7 * 9 * K * K * 8);
+    c->dPx = (double *)take(9 * K * K * 8);
+    c->dPy = (double *)take(9 * K * K * 8);
+    c->kb.P1 = (double *)take(kPartStride * 8);
+    c->kb.P2 = (double *)take(2 * kPartStride * 8);
+    c->kb.P3 = (double *)take(2 * kPartStride * 8);
+    c->kb.stride = kPartStride;
+    c->dpart = (double *)take(5 * kPartStride * 8);
+    c->ks = (KrylovState *)take(sizeof(KrylovState));
+    if (off > c->ws_bytes) return bail(fail(IMEXHDG_E_INVAL, "internal: workspace overflow"));
+
+    if (hipHostMalloc((void **)&c->hks, sizeof(KrylovState)) != hipSuccess ||
+        hipHostMalloc((void **)&c->hpart, 5 * kPartStride * 8) != hipSuccess)
+        return bail(fail(IMEXHDG_E_NOMEM, "hipHostMalloc failed"));
+
+    const StageOperators &op = c->op;
+    std::vector<double> G(op.Gx), Gh(op.Gxh);
+    G.insert(G.end(), op.Gy.begin(), op.Gy.end());
+    Gh.insert(Gh.end(), op.Gyh.begin(), op.Gyh.end());
+    auto up = [&](double *d, const std::vector<double> &h) {
+        return hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream);
+    };
+    if (up(c->dAinv, op.Ainv) || up(c->dW, op.W) || up(c->dG, G) || up(c->dGh, Gh) ||
+        up(c->dPx, op.Pxinv) || up(c->dPy, op.Pyinv) ||
+        hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
+        hipMemsetAsync(c->q, 0, L.N * 8, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+    *out = c;
+    g_last_error.clear();
+    return IMEXHDG_OK;
+}
+
+void imexhdg_destroy(imexhdg_ctx *c) {
+    if (!c) return;
+    if (c->ws || c->hks) (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < c->ev0.size(); ++i) {
+        (void)hipEventDestroy(c->ev0[i]);
+        (void)hipEventDestroy(c->ev1[i]);
+    }
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->hks) (void)hipHostFree(c->hks);
+    if (c->hpart) (void)hipHostFree(c->hpart);
+    delete c;
+}
+
+int imexhdg_sizes(const imexhdg_ctx *c, int64_t *n_nodes, int64_t *n_trace) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (n_nodes) *n_nodes = (int64_t)c->nnodes;
+    if (n_trace) *n_trace = (int64_t)c->T;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_get_nodes(const imexhdg_ctx *c, double *x, double *y) {
+    if (!c || !x || !y) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    const int K = c->geom.K, nx = c->cfg.nx, ny = c->cfg.ny;
+    const double hx = c->cfg.Lx / nx, hy = c->cfg.Ly / ny;
+    size_t o = 0;
+    for (int ey = 0; ey < ny; ++ey)
+        for (int ex = 0; ex < nx; ++ex)
+            for (int j = 0; j < K; ++j)
+                for (int i = 0; i < K; ++i, ++o) {
+                    x[o] = (ex + (c->ref.x[i] + 1.0) / 2.0) * hx;
+                    y[o] = (ey + (c->ref.x[j] + 1.0) / 2.0) * hy;
+                }
+    return IMEXHDG_OK;
+}
+
+int imexhdg_set_state(imexhdg_ctx *c, int vars, const double *a, const double *b,
+                      const double *cc) {
+    if (!c || !a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
+        return fail(IMEXHDG_E_INVAL, "unknown vars");
+    const int K = c->geom.K, nel = c->geom.nel;
+    const double g = c->cfg.g, H = c->cfg.H, phiB = g * H;
+    std::vector<double> h(c->N);
+    const size_t NN = c->nnodes;
+    for (int e = 0; e < nel; ++e)
+        for (int n = 0; n < K * K; ++n) {
+            const size_t src = (size_t)e * K * K + n, dst = (size_t)n * nel + e;
+            double p, U, V;
+            if (vars == IMEXHDG_VARS_DEPTH) {
+                p = g * (a[src] - H);
+                U = g * b[src];
+                V = g * cc[src];
+            } else {
+                p = a[src];
+                U = b[src];
+                V = cc[src];
+            }
+            const double phi = p + phiB;
+            if (!std::isfinite(p) || !std::isfinite(U) || !std::isfinite(V))
+                return fail(IMEXHDG_E_INVAL, "state holds NaN or Inf");
+            if (!(phi > 0)) return fail(IMEXHDG_E_INVAL, "total depth must be positive");
+            if (U * U + V * V >= phi * phi * phi)
+                return fail(IMEXHDG_E_INVAL, "supercritical state: |u| >= sqrt(phi)");
+            h[dst] = p;
+            h[NN + dst] = U;
+            h[2 * NN + dst] = V;
+        }
+    HIP_TRY(hipMemcpyAsync(c->q, h.data(), c->N * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
+    HIP_TRY(stream_sync(c));
+    c->have_state = true;
+    c->steps = 0;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_get_state(imexhdg_ctx *c, int vars, double *a, double *b, double *cc) {
+    if (!c || !a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
+        return fail(IMEXHDG_E_INVAL, "unknown vars");
+    if (!c->have_state) return fail(IMEXHDG_E_STATE, "no state set");
+    std::vector<double> h(c->N);
+    HIP_TRY(hipMemcpyAsync(h.data(), c->q, c->N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(stream_sync(c));
+    const int K = c->geom.K, nel = c->geom.nel;
+    const double g = c->cfg.g, H = c->cfg.H;
+    const size_t NN = c->nnodes;
+    for (int e = 0; e < nel; ++e)
+        for (int n = 0; n < K * K; ++n) {
+            const size_t dst = (size_t)e * K * K + n, src = (size_t)n * nel + e;
+            const double p = h[src], U = h[NN + src], V = h[2 * NN + src];
+            if (vars == IMEXHDG_VARS_DEPTH) {
+                a[dst] = H + p / g;
+                b[dst] = U / g;
+                cc[dst] = V / g;
+            } else {
+                a[dst] = p;
+                b[dst] = U;
+                cc[dst] = V;
+            }
+        }
+    return IMEXHDG_OK;
+}
+
+int imexhdg_step(imexhdg_ctx *c, int32_t nsteps) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(IMEXHDG_E_INVAL, "nsteps must be >= 0");
+    if (!c->have_state) return fail(IMEXHDG_E_STATE, "step before set_state");
+    int status = IMEXHDG_OK;
+    const int s = c->tab.s;
+    for (int n = 0; n < nsteps; ++n) {
+        for (int i = 0; i < s; ++i) {
+            const double *Qi = c->q;
+            if (i > 0) {
+                int rc = stage_solve(c, c->Rb[i], c->Qb[i], nullptr, nullptr);
+                if (rc == IMEXHDG_E_NOCONV) status = rc;
+                else if (rc) return rc;
+                Qi = c->Qb[i];
+            }
+            double *out = (i + 1 < s) ? c->Rb[i + 1] : c->q;
+            int rc = run_plan(c, i, Qi, out);
+            if (rc) return rc;
+        }
+        c->steps += 1;
+    }
+    if (status) return fail(status, "a trace solve missed refine_rtol");
+    return IMEXHDG_OK;
+}
+
+int imexhdg_get_diag(imexhdg_ctx *c, imexhdg_diag *d) {
+    if (!c || !d) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (!c->have_state) return fail(IMEXHDG_E_STATE, "no state set");
+    LAUNCH(IMEXHDG_K_DIAG, launch_diag(c->geom, c->q, c->dpart, kPartStride, c->stream));
+    double t[5];
+    int rc = read_partials(c, 5, diag_grid(c->geom), t);
+    if (rc) return rc;
+    std::memset(d, 0, sizeof(*d));
+    for (int i = 0; i < 3; ++i) d->mass[i] = t[i];
+    d->energy = t[3];
+    d->nonfinite = (t[4] != 0.0 || !std::isfinite(t[3])) ? 1 : 0;
+    d->steps = c->steps;
+    d->krylov_iters = c->kiters;
+    d->stage_solves = c->solves;
+    d->refine_sweeps = c->sweeps;
+    d->last_relres = c->last_relres;
+    d->max_relres = c->max_relres;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_state_device(imexhdg_ctx *c, double **d_q) {
+    if (!c || !d_q) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    *d_q = c->q;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
+    if (!c || !d_q || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    Comb cb{};
+    cb.n = 0;
+    cb.self = 1.0;
+    cb.out = d_out;
+    cb.store = nullptr;
+    LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, d_q, cb, c->stream));
+    return IMEXHDG_OK;
+}
+
+int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_qhat,
+                            double *d_out) {
+    if (!c || !d_Q || !d_qhat || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    LAUNCH(IMEXHDG_K_LINRES, launch_linear_residual(c->geom, d_Q, d_qhat, d_out, c->stream));
+    return IMEXHDG_OK;
+}
+
+int imexhdg_stage_solve(imexhdg_ctx *c, const double *d_res0, double *d_Q, double *d_qhat,
+                        int32_t *iters, double *relres) {
+    if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(c->x, d_qhat, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    int rc = stage_solve(c, d_res0, d_Q, iters, relres);
+    if (rc && rc != IMEXHDG_E_NOCONV) return rc;
+    HIP_TRY(hipMemcpyAsync(d_qhat, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(stream_sync(c));
+    return rc;
+}
+
+static const char *kKernelNames[IMEXHDG_K_COUNT] = {
+    "nl_residual", "combine", "local_apply", "trace_rhs", "trace_residual", "bicg_init",
+    "bicg_k1", "bicg_k2", "bicg_k3", "axpy", "recover", "diag", "linear_residual"};
+
+const char *imexhdg_kernel_name(int32_t k) {
+    return (k >= 0 && k < IMEXHDG_K_COUNT) ? kKernelNames[k] : nullptr;
+}
+
+int imexhdg_profile(imexhdg_ctx *c, int32_t kernel) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (kernel < -2 || kernel >= IMEXHDG_K_COUNT) return fail(IMEXHDG_E_INVAL, "bad kernel id");
+    HIP_TRY(stream_sync(c));
+    if (kernel != -2 && c->ev0.empty()) {
+        c->ev0.resize(kEventPool);
+        c->ev1.resize(kEventPool);
+        c->ev_id.resize(kEventPool);
+        for (int i = 0; i < kEventPool; ++i) {
+            HIP_TRY(hipEventCreate(&c->ev0[i]));
+            HIP_TRY(hipEventCreate(&c->ev1[i]));
+        }
+    }
+    c->prof_target = kernel;
+    c->ev_used = 0;
+    for (int i = 0; i < IMEXHDG_K_COUNT; ++i) {
+        c->prof_ms[i] = 0.0;
+        c->prof_n[i] = 0;
+    }
+    return IMEXHDG_OK;
+}
+
+int imexhdg_profile_read(imexhdg_ctx *c, int32_t kernel, int64_t *launches, double *total_ms) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (kernel < 0 || kernel >= IMEXHDG_K_COUNT) return fail(IMEXHDG_E_INVAL, "bad kernel id");
+    HIP_TRY(stream_sync(c));
+    if (launches) *launches = c->prof_n[kernel];
+    if (total_ms) *total_ms = c->prof_ms[kernel];
+    return IMEXHDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,997 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of one IMEX HDG-DG step.
+//
+// Layouts (element index e = ey*nx + ex fastest, so a wave of 64 lanes that
+// handles 64 consecutive elements reads 64 consecutive doubles per access):
+//   volume v[c][j*K + i][e]     c = phi_eta, U, V;  N = 3 K^2 nel values
+//   trace  t[d][c][j][e]        d = 0 x-face e (west face of element e),
+//                               d = 1 y-face e (south face of element e)
+// Workgroups are 64 lanes (elements or faces) x K "rows"; the row index is
+// wave-uniform, so every reference-element matrix entry a wave needs is the
+// same for all its lanes and is read through the scalar unit.
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace imexhdg {
+
+namespace {
+
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Matrices shared by all lanes of a wave are read through the constant
+// address space, so wave-uniform indices compile to scalar loads.
+typedef const __attribute__((address_space(4))) double cdouble;
+
+__device__ __forceinline__ const cdouble *as_const(const double *p) {
+    return (const cdouble *)(p);
+}
+
+struct Nbr {
+    int e, east, west, north, south;
+};
+
+__device__ __forceinline__ Nbr neighbours(int e, int nx, int ny) {
+    Nbr n;
+    const int ex = e % nx, ey = e / nx;
+    n.e = e;
+    n.east = ey * nx + (ex + 1 == nx ? 0 : ex + 1);
+    n.west = ey * nx + (ex == 0 ? nx - 1 : ex - 1);
+    n.north = (ey + 1 == ny ? 0 : ey + 1) * nx + ex;
+    n.south = (ey == 0 ? ny - 1 : ey - 1) * nx + ex;
+    return n;
+}
+
+// Deterministic reductions without fences or atomics.  A producer kernel
+// stores one partial sum per block with a plain store; the partials become
+// visible to the next kernel on the stream at the launch boundary, where
+// every block of the consumer reduces them again in the same fixed order
+// (consumer grids are capped, so this costs a few KB of L2 reads per block).
+constexpr int kMaxGrid = 1024;
+
+// Block sum of NV values per thread; the result is returned to every thread.
+template <int NV>
+__device__ void block_sum(double (&v)[NV]) {
+    __shared__ double sred[16][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    for (int q = 0; q < NV; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) sred[w][q] = s;
+    }
+    __syncthreads();
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += sred[i][q];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+// partials[q * stride + blockIdx.x] = block sum of v[q]
+template <int NV>
+__device__ void store_partials(double (&v)[NV], double *partials, int stride) {
+    block_sum<NV>(v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NV; ++q) partials[q * stride + blockIdx.x] = v[q];
+}
+
+// out[q] = sum_{b < n} partials[q * stride + b], identical in every block
+template <int NV>
+__device__ void reduce_partials(const double *__restrict__ partials, int stride, int n,
+                                double (&out)[NV]) {
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[q * stride + i];
+        out[q] = s;
+    }
+    block_sum<NV>(out);
+}
+
+// ------------------------------------------------------------- physics
+// Nonlinear remainder of the flux, F_NL = F - F_L (Sec. 4.3), in closed form:
+//   x: (0, U^2/phi + phi_eta^2/2, U V/phi),  y: (0, U V/phi, V^2/phi + phi_eta^2/2)
+// Rusanov flux of the remainder (eqs. Full_russanov, Linear_russanov):
+//   F*_NL . n = {F_NL} . n + (tau* - tau_L*) / 2 (q- - q+)
+//   tau* = max over both sides of |u . n| + sqrt(phi),  tau_L* = sqrt(phi_B)
+__device__ __forceinline__ void nl_flux_n(double p, double U, double V, double phiB,
+                                          double nx, double ny, double &f1, double &f2,
+                                          double &speed) {
+    const double phi = p + phiB;
+    const double inv = 1.0 / phi;
+    const double uu = U * U * inv, uv = U * V * inv, vv = V * V * inv;
+    const double hp = 0.5 * p * p;
+    f1 = (uu + hp) * nx + uv * ny;
+    f2 = uv * nx + (vv + hp) * ny;
+    speed = fabs((U * nx + V * ny) * inv) + sqrt(phi);
+}
+
+__device__ __forceinline__ void rusanov_nl(const double qm[3], const double qp[3],
+                                           double nx, double ny, double phiB, double tauL,
+                                           double out[3]) {
+    double fm1, fm2, sm, fp1, fp2, sp;
+    nl_flux_n(qm[0], qm[1], qm[2], phiB, nx, ny, fm1, fm2, sm);
+    nl_flux_n(qp[0], qp[1], qp[2], phiB, nx, ny, fp1, fp2, sp);
+    const double diss = 0.5 * (fmax(sm, sp) - tauL);
+    out[0] = diss * (qm[0] - qp[0]);
+    out[1] = 0.5 * (fm1 + fp1) + diss * (qm[1] - qp[1]);
+    out[2] = 0.5 * (fm2 + fp2) + diss * (qm[2] - qp[2]);
+}
+
+// -------------------------------------------------- NL residual kernel
+// One thread per (element, node row j).  Volume term in weak form,
+//   M^-1 (F, grad v)_K at (a, b) = (2/hx) sum_m Dw[m][a] F_x(m, b)
+//                                + (2/hy) sum_m Dw[m][b] F_y(a, m),
+// with F_y exchanged through LDS; surface term -(2/h) Phi / w_end at the
+// face nodes.  The epilogue applies the stage combination `comb`.
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, const Geom g,
+                                               const Comb comb) {
+    __shared__ double sFy[2][K][K][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const int e = blockIdx.x * 64 + lane;
+    const bool active = e < g.nel;
+    const Nbr nb = neighbours(active ? e : 0, g.nx, g.ny);
+    const size_t nel = g.nel, NN = (size_t)K * K * nel;
+    const double phiB = g.phiB;
+
+    double p[K], U[K], V[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const size_t o = (size_t)(j * K + i) * nel + nb.e;
+        p[i] = q[o];
+        U[i] = q[NN + o];
+        V[i] = q[2 * NN + o];
+    }
+    double fx1[K], fx2[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const double inv = 1.0 / (p[i] + phiB);
+        const double hp = 0.5 * p[i] * p[i];
+        const double uv = U[i] * V[i] * inv;
+        fx1[i] = U[i] * U[i] * inv + hp;
+        fx2[i] = uv;
+        sFy[0][j][i][lane] = uv;
+        sFy[1][j][i][lane] = V[i] * V[i] * inv + hp;
+    }
+    double o0[K], o1[K], o2[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            s1 += g.Dw[m * K + a] * fx1[m];
+            s2 += g.Dw[m * K + a] * fx2[m];
+        }
+        o0[a] = 0.0;
+        o1[a] = g.sx * s1;
+        o2[a] = g.sx * s2;
+    }
+    // east and west faces of row j
+    {
+        double qm[3], qp[3], f[3];
+        size_t o = (size_t)(j * K + 0) * nel + nb.east;
+        qm[0] = p[K - 1]; qm[1] = U[K - 1]; qm[2] = V[K - 1];
+        qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
+        rusanov_nl(qm, qp, 1.0, 0.0, phiB, g.tau, f);
+        const double se = g.sx * g.winvk;
+        o0[K - 1] -= se * f[0]; o1[K - 1] -= se * f[1]; o2[K - 1] -= se * f[2];
+        o = (size_t)(j * K + K - 1) * nel + nb.west;
+        qm[0] = p[0]; qm[1] = U[0]; qm[2] = V[0];
+        qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
+        rusanov_nl(qm, qp, -1.0, 0.0, phiB, g.tau, f);
+        const double sw = g.sx * g.winv0;
+        o0[0] -= sw * f[0]; o1[0] -= sw * f[1]; o2[0] -= sw * f[2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            s1 += g.Dw[m * K + j] * sFy[0][m][i][lane];
+            s2 += g.Dw[m * K + j] * sFy[1][m][i][lane];
+        }
+        o1[i] += g.sy * s1;
+        o2[i] += g.sy * s2;
+    }
+    if (j == K - 1 || j == 0) {
+        const bool north = (j == K - 1);
+        const int other = north ? nb.north : nb.south;
+        const int orow = north ? 0 : K - 1;
+        const double ny = north ? 1.0 : -1.0;
+        const double sc = g.sy * (north ? g.winvk : g.winv0);
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            double qm[3] = {p[i], U[i], V[i]}, qp[3], f[3];
+            const size_t o = (size_t)(orow * K + i) * nel + other;
+            qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
+            rusanov_nl(qm, qp, 0.0, ny, phiB, g.tau, f);
+            o0[i] -= sc * f[0]; o1[i] -= sc * f[1]; o2[i] -= sc * f[2];
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const size_t o = (size_t)(j * K + i) * nel + e;
+        const double val[3] = {o0[i], o1[i], o2[i]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t oc = c * NN + o;
+            if (comb.store) comb.store[oc] = val[c];
+            double acc = comb.self * val[c];
+            for (int t = 0; t < comb.n; ++t) acc += comb.coef[t] * comb.in[t][oc];
+            comb.out[oc] = acc;
+        }
+    }
+}
+
+__global__ void k_combine(const Comb comb, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int t = 0; t < comb.n; ++t) acc += comb.coef[t] * comb.in[t][i];
+    comb.out[i] = acc;
+}
+
+// ------------------------------------------- linear HDG residual kernel
+// M^-1 L(Q, Qhat) = M^-1 [ (F_L(Q), grad v)_K - <Fhat_L . n, v>_dK ] with
+// n . Fhat_L = F_L(Q) . n + tau (Q - Qhat) (eq. linear_hdgflux3).
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
+                                                   const double *__restrict__ qh,
+                                                   const Geom g, double *__restrict__ out) {
+    __shared__ double sV[2][K][K][64];     // V and phi_B p, for d/dy
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const int e = blockIdx.x * 64 + lane;
+    const bool active = e < g.nel;
+    const Nbr nb = neighbours(active ? e : 0, g.nx, g.ny);
+    const size_t nel = g.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
+    const double phiB = g.phiB, tau = g.tau;
+    double p[K], U[K], V[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const size_t o = (size_t)(j * K + i) * nel + nb.e;
+        p[i] = Q[o]; U[i] = Q[NN + o]; V[i] = Q[2 * NN + o];
+        sV[0][j][i][lane] = V[i];
+        sV[1][j][i][lane] = phiB * p[i];
+    }
+    double o0[K], o1[K], o2[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            s0 += g.Dw[m * K + a] * U[m];
+            s1 += g.Dw[m * K + a] * p[m];
+        }
+        o0[a] = g.sx * s0;
+        o1[a] = g.sx * phiB * s1;
+        o2[a] = 0.0;
+    }
+    // west face = x-face e, east face = x-face east(e); node j
+    {
+        const size_t ow = (size_t)j * nel + nb.e, oe = (size_t)j * nel + nb.east;
+        // east: n = (1, 0)
+        double f0 = U[K - 1] + tau * (p[K - 1] - qh[oe]);
+        double f1 = phiB * p[K - 1] + tau * (U[K - 1] - qh[nel * K + oe]);
+        double f2 = tau * (V[K - 1] - qh[2 * nel * K + oe]);
+        const double se = g.sx * g.winvk;
+        o0[K - 1] -= se * f0; o1[K - 1] -= se * f1; o2[K - 1] -= se * f2;
+        // west: n = (-1, 0)
+        f0 = -U[0] + tau * (p[0] - qh[ow]);
+        f1 = -phiB * p[0] + tau * (U[0] - qh[nel * K + ow]);
+        f2 = tau * (V[0] - qh[2 * nel * K + ow]);
+        const double sw = g.sx * g.winv0;
+        o0[0] -= sw * f0; o1[0] -= sw * f1; o2[0] -= sw * f2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double s0 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            s0 += g.Dw[m * K + j] * sV[0][m][i][lane];
+            s2 += g.Dw[m * K + j] * sV[1][m][i][lane];
+        }
+        o0[i] += g.sy * s0;
+        o2[i] += g.sy * s2;
+    }
+    if (j == K - 1 || j == 0) {
+        const bool north = (j == K - 1);
+        const int face = north ? nb.north : nb.e;      // y-face index
+        const double ny = north ? 1.0 : -1.0;
+        const double sc = g.sy * (north ? g.winvk : g.winv0);
+        const double *qy = qh + TT;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const size_t o = (size_t)i * nel + face;
+            const double f0 = ny * V[i] + tau * (p[i] - qy[o]);
+            const double f1 = tau * (U[i] - qy[nel * K + o]);
+            const double f2 = ny * phiB * p[i] + tau * (V[i] - qy[2 * nel * K + o]);
+            o0[i] -= sc * f0; o1[i] -= sc * f1; o2[i] -= sc * f2;
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const size_t o = (size_t)(j * K + i) * nel + e;
+        out[o] = o0[i];
+        out[NN + o] = o1[i];
+        out[2 * NN + o] = o2[i];
+    }
+}
+
+// ------------------------------------------------- local solver kernels
+// Z = A^-1 R per element: the shared (3K^2)-square inverse applied to every
+// element.  Thread (element, row j) produces the 3K outputs of node row j.
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_local_apply(const double *__restrict__ Ainv,
+                                                        const double *__restrict__ R,
+                                                        const Geom g, double *__restrict__ Z) {
+    constexpr int NL = 3 * K * K;
+    __shared__ double sR[NL][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const int e = blockIdx.x * 64 + lane;
+    const bool active = e < g.nel;
+    const size_t nel = g.nel, NN = (size_t)K * K * nel;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            sR[c * K * K + j * K + i][lane] =
+                active ? R[c * NN + (size_t)(j * K + i) * nel + e] : 0.0;
+    __syncthreads();
+    double acc[3][K];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[c][i] = 0.0;
+    const cdouble *A = as_const(Ainv) + (size_t)(j * K) * NL;
+#pragma unroll 3
+    for (int col = 0; col < NL; ++col) {
+        const double r = sR[col][lane];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                acc[c][i] += A[(size_t)(c * K * K + i) * NL + col] * r;
+    }
+    if (!active) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < K; ++i) Z[c * NN + (size_t)(j * K + i) * nel + e] = acc[c][i];
+}
+
+// Q = Z - W Qhat_dK per element, W = A^-1 B (eq. recover_volume_unknowns).
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_recover(const double *__restrict__ W,
+                                                    const double *__restrict__ Z,
+                                                    const double *__restrict__ qh,
+                                                    const Geom g, double *__restrict__ Q) {
+    constexpr int NT = 12 * K;
+    __shared__ double sT[NT][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const int e = blockIdx.x * 64 + lane;
+    const bool active = e < g.nel;
+    const Nbr nb = neighbours(active ? e : 0, g.nx, g.ny);
+    const size_t nel = g.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
+    // local trace t(f, c, j) = (f*3 + c)*K + j, faces W, E, S, N
+    const int face[4] = {nb.e, nb.east, nb.e, nb.north};
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            sT[(f * 3 + c) * K + j][lane] =
+                qh[(f >= 2 ? TT : 0) + (size_t)(c * K + j) * nel + face[f]];
+    __syncthreads();
+    double acc[3][K];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[c][i] = 0.0;
+    const cdouble *Wr = as_const(W) + (size_t)(j * K) * NT;
+#pragma unroll 3
+    for (int col = 0; col < NT; ++col) {
+        const double t = sT[col][lane];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                acc[c][i] += Wr[(size_t)(c * K * K + i) * NT + col] * t;
+    }
+    if (!active) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const size_t o = c * NN + (size_t)(j * K + i) * nel + e;
+            Q[o] = Z[o] - acc[c][i];
+        }
+}
+
+// ---------------------------------------------------- trace kernels
+// Face tiles: tiles [0, nb) hold x-faces, [nb, 2 nb) y-faces, 64 faces
+// each; thread (face lane, node j).  Krylov kernels loop over tiles with a
+// capped grid.
+struct FaceIdx {
+    int d, f;            // direction, face index (= its element)
+    bool active;
+};
+
+__device__ __forceinline__ FaceIdx face_of_tile(int tile, int nel) {
+    const int nb = (nel + 63) / 64;
+    FaceIdx fi;
+    fi.d = tile >= nb ? 1 : 0;
+    const int b = tile - fi.d * nb;
+    fi.f = b * 64 + (threadIdx.x & 63);
+    fi.active = fi.f < nel;
+    if (!fi.active) fi.f = 0;
+    return fi;
+}
+
+// Neighbour faces of the 7 slots of a face row block (see element.hpp).
+__device__ __forceinline__ void slot_faces(const FaceIdx &fi, int nx, int ny, int dir[7],
+                                           int idx[7]) {
+    const Nbr n = neighbours(fi.f, nx, ny);
+    if (fi.d == 0) {
+        const Nbr w = neighbours(n.west, nx, ny);
+        dir[0] = 0; idx[0] = n.e;
+        dir[1] = 0; idx[1] = n.east;
+        dir[2] = 1; idx[2] = n.e;
+        dir[3] = 1; idx[3] = n.north;
+        dir[4] = 0; idx[4] = n.west;
+        dir[5] = 1; idx[5] = n.west;
+        dir[6] = 1; idx[6] = w.north;
+    } else {
+        const Nbr s = neighbours(n.south, nx, ny);
+        dir[0] = 1; idx[0] = n.e;
+        dir[1] = 0; idx[1] = n.e;
+        dir[2] = 0; idx[2] = n.east;
+        dir[3] = 1; idx[3] = n.north;
+        dir[4] = 1; idx[4] = n.south;
+        dir[5] = 0; idx[5] = n.south;
+        dir[6] = 0; idx[6] = s.east;
+    }
+}
+
+// g = sum over the two elements of C_K Z_K = F_L(Z) . n_K + tau Z at the
+// face node; ghat = P^-1 g with the block-Jacobi inverse of the face.
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__ Z,
+                                                      const double *__restrict__ Pxinv,
+                                                      const double *__restrict__ Pyinv,
+                                                      const Geom g, double *__restrict__ gv,
+                                                      double *__restrict__ gh) {
+    constexpr int B3 = 3 * K;
+    __shared__ double sG[B3][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const FaceIdx fi = face_of_tile(blockIdx.x, g.nel);
+    const Nbr n = neighbours(fi.f, g.nx, g.ny);
+    const size_t nel = g.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
+    const double phiB = g.phiB, tau = g.tau;
+    // plus side: element f (face is its west / south), minus side: west /
+    // south neighbour (face is its east / north)
+    int np, nm;
+    double nx, ny;
+    if (fi.d == 0) { np = j * K + 0; nm = j * K + K - 1; nx = 1.0; ny = 0.0; }
+    else { np = 0 * K + j; nm = (K - 1) * K + j; nx = 0.0; ny = 1.0; }
+    const int em = fi.d == 0 ? n.west : n.south;
+    const size_t op = (size_t)np * nel + n.e, om = (size_t)nm * nel + em;
+    const double pp = Z[op], Up = Z[NN + op], Vp = Z[2 * NN + op];
+    const double pm = Z[om], Um = Z[NN + om], Vm = Z[2 * NN + om];
+    // minus side outward normal (nx, ny), plus side (-nx, -ny)
+    const double g0 = (Um * nx + Vm * ny + tau * pm) + (-(Up * nx + Vp * ny) + tau * pp);
+    const double g1 = (nx * phiB * pm + tau * Um) + (-nx * phiB * pp + tau * Up);
+    const double g2 = (ny * phiB * pm + tau * Vm) + (-ny * phiB * pp + tau * Vp);
+    sG[0 * K + j][lane] = g0;
+    sG[1 * K + j][lane] = g1;
+    sG[2 * K + j][lane] = g2;
+    const size_t base = fi.d * TT + (size_t)j * nel + fi.f;
+    if (fi.active) {
+        gv[base] = g0;
+        gv[base + nel * K] = g1;
+        gv[base + 2 * nel * K] = g2;
+    }
+    __syncthreads();
+    const cdouble *P = as_const(fi.d == 0 ? Pxinv : Pyinv) + j * B3;
+    double h[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int col = 0; col < B3; ++col) {
+        const double x = sG[col][lane];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[c] += P[c * K * B3 + col] * x;
+    }
+    if (fi.active) {
+        gh[base] = h[0];
+        gh[base + nel * K] = h[1];
+        gh[base + 2 * nel * K] = h[2];
+    }
+}
+
+// y(c, j) = sum_slots sum_col M[slot][(c K + j)][col] sX[slot][col]
+template <int K>
+__device__ __forceinline__ void apply7(const double *__restrict__ M, int j, int lane,
+                                       double (*sX)[3 * K][64], double y[3]) {
+    constexpr int B3 = 3 * K;
+    const cdouble *Mc = as_const(M);
+    y[0] = y[1] = y[2] = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < 7; ++s) {
+        const cdouble *Ms = Mc + (size_t)s * B3 * B3 + j * B3;
+#pragma unroll
+        for (int col = 0; col < B3; ++col) {
+            const double x = sX[s][col][lane];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) y[c] += Ms[c * K * B3 + col] * x;
+        }
+    }
+}
+
+struct TraceMats {
+    const double *Gx, *Gy;        // 7 (3K)^2 blocks each
+};
+
+__device__ __forceinline__ size_t trace_off(int d, int c, int j, int f, int K, size_t nel) {
+    return (size_t)d * 3 * K * nel + (size_t)(c * K + j) * nel + f;
+}
+
+// FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
+// partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_trace_residual(
+    const TraceMats G, const TraceMats Gh, const double *__restrict__ x,
+    const double *__restrict__ gv, const double *__restrict__ gh, const Geom g,
+    double *__restrict__ r, double *__restrict__ rin, double *partials, int stride) {
+    __shared__ double sX[7][3 * K][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const size_t nel = g.nel;
+    const int ntiles = 2 * ((g.nel + 63) / 64);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const FaceIdx fi = face_of_tile(tile, g.nel);
+        int dir[7], idx[7];
+        slot_faces(fi, g.nx, g.ny, dir, idx);
+#pragma unroll
+        for (int s = 0; s < 7; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                sX[s][c * K + j][lane] = x[trace_off(dir[s], c, j, idx[s], K, nel)];
+        __syncthreads();
+        double y[3], yh[3];
+        apply7<K>(fi.d == 0 ? G.Gx : G.Gy, j, lane, sX, y);
+        apply7<K>(fi.d == 0 ? Gh.Gx : Gh.Gy, j, lane, sX, yh);
+        if (fi.active) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = trace_off(fi.d, c, j, fi.f, K, nel);
+                const double rr = gv[o] - y[c];
+                const double ri = gh[o] - yh[c];
+                r[o] = rr;
+                rin[o] = ri;
+                acc[0] += rr * rr;
+                acc[1] += gv[o] * gv[o];
+                acc[2] += gh[o] * gh[o];
+                acc[3] += ri * ri;
+            }
+        }
+        __syncthreads();
+    }
+    store_partials<4>(acc, partials, stride);
+}
+
+// ------------------------------------------------------------ BiCGStab
+// Left-preconditioned BiCGStab (van der Vorst 1992) on Ghat d = rin, d0 = 0,
+// with the block-Jacobi preconditioner folded into Ghat.  One iteration is
+// three launches:
+//   K1: beta from (rh.r) [partials P3];  p <- r + beta (p - omega v) at the
+//       seven faces each row block reads, v = Ghat p;  partials P1 = rh.v
+//   K2: alpha = rho / (rh.v);  s = r - alpha v on the fly, t = Ghat s;
+//       partials P2 = (t.s, t.t)
+//   K3: omega = (t.s)/(t.t);  d += alpha p + omega s;  r = s - omega t;
+//       partials P3 = (rh.r, r.r)
+// p and v are double buffered because K1 reads the old values at
+// neighbouring faces while writing the new ones.  Convergence (r.r <= tol2)
+// is detected at the start of K1; every later kernel returns at entry.
+__global__ void k_bicg_init(const double *__restrict__ rin, double *__restrict__ r,
+                            double *__restrict__ rh, double *__restrict__ p,
+                            double *__restrict__ v, double *__restrict__ d, size_t n,
+                            KrylovState *ks, double tol2, double *P3, int stride) {
+    double acc[2] = {0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double x = rin[i];
+        r[i] = x; rh[i] = x; p[i] = 0.0; v[i] = 0.0; d[i] = 0.0;
+        acc[0] += x * x;
+        acc[1] += x * x;
+    }
+    store_partials<2>(acc, P3, stride);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ks->rho = 1.0;
+        ks->alpha = 1.0;
+        ks->omega = 1.0;
+        ks->rr = 0.0;
+        ks->tol2 = tol2;
+        ks->conv = 0;
+        ks->breakdown = 0;
+        ks->iters = 0;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_bicg_k1(const TraceMats Gh,
+                                                    const double *__restrict__ r,
+                                                    const double *__restrict__ rh,
+                                                    const double *__restrict__ pin,
+                                                    const double *__restrict__ vin,
+                                                    double *__restrict__ pout,
+                                                    double *__restrict__ vout, const Geom g,
+                                                    KrylovState *ks, const double *P3, int n3,
+                                                    double *P1, int stride) {
+    double red[2];
+    reduce_partials<2>(P3, stride, n3, red);
+    if (ks->conv) return;
+    const double rho_new = red[0], rr = red[1];
+    const double rho = ks->rho, alpha = ks->alpha, omega = ks->omega;
+    if (rr <= ks->tol2 || rho_new == 0.0 || omega == 0.0 || !isfinite(rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ks->rr = rr;
+            ks->breakdown = (rr <= ks->tol2) ? 0 : 1;
+            ks->conv = 1;
+        }
+        return;
+    }
+    const double beta = (rho_new / rho) * (alpha / omega);
+    __shared__ double sX[7][3 * K][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const size_t nel = g.nel;
+    const int ntiles = 2 * ((g.nel + 63) / 64);
+    double acc[1] = {0.0};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const FaceIdx fi = face_of_tile(tile, g.nel);
+        int dir[7], idx[7];
+        slot_faces(fi, g.nx, g.ny, dir, idx);
+#pragma unroll
+        for (int s = 0; s < 7; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = trace_off(dir[s], c, j, idx[s], K, nel);
+                sX[s][c * K + j][lane] = r[o] + beta * (pin[o] - omega * vin[o]);
+            }
+        __syncthreads();
+        double y[3];
+        apply7<K>(fi.d == 0 ? Gh.Gx : Gh.Gy, j, lane, sX, y);
+        if (fi.active) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = trace_off(fi.d, c, j, fi.f, K, nel);
+                pout[o] = sX[0][c * K + j][lane];
+                vout[o] = y[c];
+                acc[0] += rh[o] * y[c];
+            }
+        }
+        __syncthreads();
+    }
+    store_partials<1>(acc, P1, stride);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_bicg_k2(const TraceMats Gh,
+                                                    const double *__restrict__ r,
+                                                    const double *__restrict__ v,
+                                                    double *__restrict__ sv,
+                                                    double *__restrict__ t, const Geom g,
+                                                    KrylovState *ks, const double *P1, int n1,
+                                                    const double *P3, int n3, double *P2,
+                                                    int stride) {
+    double red1[1], red3[2];
+    reduce_partials<1>(P1, stride, n1, red1);
+    reduce_partials<2>(P3, stride, n3, red3);
+    if (ks->conv) return;
+    const double rv = red1[0], rho_new = red3[0];
+    if (rv == 0.0 || !isfinite(rv)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ks->breakdown = 1;
+            ks->conv = 1;
+        }
+        return;
+    }
+    const double alpha = rho_new / rv;
+    __shared__ double sX[7][3 * K][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const size_t nel = g.nel;
+    const int ntiles = 2 * ((g.nel + 63) / 64);
+    double acc[2] = {0.0, 0.0};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const FaceIdx fi = face_of_tile(tile, g.nel);
+        int dir[7], idx[7];
+        slot_faces(fi, g.nx, g.ny, dir, idx);
+#pragma unroll
+        for (int s = 0; s < 7; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = trace_off(dir[s], c, j, idx[s], K, nel);
+                sX[s][c * K + j][lane] = r[o] - alpha * v[o];
+            }
+        __syncthreads();
+        double y[3];
+        apply7<K>(fi.d == 0 ? Gh.Gx : Gh.Gy, j, lane, sX, y);
+        if (fi.active) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = trace_off(fi.d, c, j, fi.f, K, nel);
+                const double sval = sX[0][c * K + j][lane];
+                sv[o] = sval;
+                t[o] = y[c];
+                acc[0] += y[c] * sval;
+                acc[1] += y[c] * y[c];
+            }
+        }
+        __syncthreads();
+    }
+    store_partials<2>(acc, P2, stride);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ks->rho = rho_new;
+        ks->alpha = alpha;
+    }
+}
+
+__global__ void k_bicg_k3(double *__restrict__ d, double *__restrict__ r,
+                          const double *__restrict__ rh, const double *__restrict__ p,
+                          const double *__restrict__ sv, const double *__restrict__ t, size_t n,
+                          KrylovState *ks, const double *P2, int n2, double *P3, int stride) {
+    double red[2];
+    reduce_partials<2>(P2, stride, n2, red);
+    if (ks->conv) return;
+    const double omega = red[1] > 0.0 ? red[0] / red[1] : 0.0;
+    const double alpha = ks->alpha;
+    double acc[2] = {0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double si = sv[i];
+        d[i] += alpha * p[i] + omega * si;
+        const double rr = si - omega * t[i];
+        r[i] = rr;
+        acc[0] += rh[i] * rr;
+        acc[1] += rr * rr;
+    }
+    store_partials<2>(acc, P3, stride);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ks->omega = omega;
+        ks->iters += 1;
+    }
+}
+
+__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
+// --------------------------------------------------------- diagnostics
+// Partials of (mass phi_eta, mass U, mass V, energy, non-finite count).
+template <int K>
+__global__ __launch_bounds__(64 * K) void k_diag(const double *__restrict__ q, const Geom g,
+                                                 double *partials, int stride) {
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    const size_t nel = g.nel, NN = (size_t)K * K * nel;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = blockIdx.x * 64 + lane; e < g.nel; e += gridDim.x * 64) {
+        for (int i = 0; i < K; ++i) {
+            const size_t o = (size_t)(j * K + i) * nel + e;
+            const double m = g.mass[j * K + i];
+            const double p = q[o], U = q[NN + o], V = q[2 * NN + o];
+            acc[0] += m * p;
+            acc[1] += m * U;
+            acc[2] += m * V;
+            acc[3] += m * (p * p + (U * U + V * V) / g.phiB);
+            if (!isfinite(p) || !isfinite(U) || !isfinite(V)) acc[4] += 1.0;
+        }
+    }
+    store_partials<5>(acc, partials, stride);
+}
+
+inline unsigned grid1(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+template <template <int> class F, typename... Args>
+hipError_t dispatch(int K, Args &&...args) {
+    switch (K) {
+        case 2: return F<2>::run(args...);
+        case 3: return F<3>::run(args...);
+        case 4: return F<4>::run(args...);
+        case 5: return F<5>::run(args...);
+        case 6: return F<6>::run(args...);
+        case 7: return F<7>::run(args...);
+        case 8: return F<8>::run(args...);
+        case 9: return F<9>::run(args...);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+TraceMats split_mats(const double *G, int K) {
+    const size_t B = (size_t)7 * 9 * K * K;
+    return TraceMats{G, G + B};
+}
+
+template <int K> struct RunNL {
+    static hipError_t run(const Geom &g, const double *q, const Comb &c, hipStream_t s) {
+        hipLaunchKernelGGL(k_nl<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, q, g, c);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunLinres {
+    static hipError_t run(const Geom &g, const double *Q, const double *qh, double *out,
+                          hipStream_t s) {
+        hipLaunchKernelGGL(k_linres<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, Q, qh, g, out);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunLocal {
+    static hipError_t run(const Geom &g, const double *A, const double *R, double *Z,
+                          hipStream_t s) {
+        hipLaunchKernelGGL(k_local_apply<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, A, R, g, Z);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunRecover {
+    static hipError_t run(const Geom &g, const double *W, const double *Z, const double *qh,
+                          double *Q, hipStream_t s) {
+        hipLaunchKernelGGL(k_recover<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, W, Z, qh, g, Q);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunTraceRhs {
+    static hipError_t run(const Geom &g, const double *Z, const double *Px, const double *Py,
+                          double *gv, double *gh, hipStream_t s) {
+        hipLaunchKernelGGL(k_trace_rhs<K>, dim3(2 * grid1(g.nel, 64)), dim3(64 * K), 0, s, Z, Px,
+                           Py, g, gv, gh);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunTraceResidual {
+    static hipError_t run(const Geom &g, const double *G, const double *Gh, const double *x,
+                          const double *gv, const double *gh, double *r, double *rin,
+                          double *partials, int stride, hipStream_t s) {
+        hipLaunchKernelGGL(k_trace_residual<K>, dim3(face_grid(g)), dim3(64 * K), 0, s,
+                           split_mats(G, K), split_mats(Gh, K), x, gv, gh, g, r, rin, partials,
+                           stride);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunK1 {
+    static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *rh,
+                          const double *pin, const double *vin, double *pout, double *vout,
+                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+        hipLaunchKernelGGL(k_bicg_k1<K>, dim3(face_grid(g)), dim3(64 * K), 0, s,
+                           split_mats(Gh, K), r, rh, pin, vin, pout, vout, g, ks, kb.P3,
+                           (int)elem_grid(g), kb.P1, kb.stride);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunK2 {
+    static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *v,
+                          double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
+                          hipStream_t s) {
+        hipLaunchKernelGGL(k_bicg_k2<K>, dim3(face_grid(g)), dim3(64 * K), 0, s,
+                           split_mats(Gh, K), r, v, sv, t, g, ks, kb.P1, (int)face_grid(g),
+                           kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
+        return hipGetLastError();
+    }
+};
+template <int K> struct RunDiag {
+    static hipError_t run(const Geom &g, const double *q, double *partials, int stride,
+                          hipStream_t s) {
+        hipLaunchKernelGGL(k_diag<K>, dim3(diag_grid(g)), dim3(64 * K), 0, s, q, g, partials,
+                           stride);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+unsigned face_grid(const Geom &g) {
+    return std::min<unsigned>(2 * grid1(g.nel, 64), kMaxGrid);
+}
+
+unsigned elem_grid(const Geom &g) {
+    const size_t n = (size_t)6 * g.K * g.nel;
+    return std::min<unsigned>(grid1(n, 256), kMaxGrid);
+}
+
+unsigned diag_grid(const Geom &g) { return std::min<unsigned>(grid1(g.nel, 64), kMaxGrid); }
+
+hipError_t launch_nl(const Geom &g, const double *q, const Comb &comb, hipStream_t s) {
+    return dispatch<RunNL>(g.K, g, q, comb, s);
+}
+
+hipError_t launch_combine(const Geom &g, const Comb &comb, size_t n, hipStream_t s) {
+    (void)g;
+    hipLaunchKernelGGL(k_combine, dim3(grid1(n, 256)), dim3(256), 0, s, comb, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_linear_residual(const Geom &g, const double *Q, const double *qhat,
+                                  double *out, hipStream_t s) {
+    return dispatch<RunLinres>(g.K, g, Q, qhat, out, s);
+}
+
+hipError_t launch_local_apply(const Geom &g, const double *Ainv, const double *R, double *Z,
+                              hipStream_t s) {
+    return dispatch<RunLocal>(g.K, g, Ainv, R, Z, s);
+}
+
+hipError_t launch_trace_rhs(const Geom &g, const double *Z, const double *Pxinv,
+                            const double *Pyinv, double *gvec, double *ghat, hipStream_t s) {
+    return dispatch<RunTraceRhs>(g.K, g, Z, Pxinv, Pyinv, gvec, ghat, s);
+}
+
+hipError_t launch_recover(const Geom &g, const double *W, const double *Z, const double *qhat,
+                          double *Q, hipStream_t s) {
+    return dispatch<RunRecover>(g.K, g, W, Z, qhat, Q, s);
+}
+
+hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,
+                                 const double *x, const double *gvec, const double *ghat,
+                                 double *r, double *rin, double *partials, int stride,
+                                 hipStream_t s) {
+    return dispatch<RunTraceResidual>(g.K, g, G, Gh, x, gvec, ghat, r, rin, partials, stride, s);
+}
+
+hipError_t launch_bicg_init(const Geom &g, const double *rin, double *r, double *rh, double *p,
+                            double *v, double *d, KrylovState *ks, double tol2,
+                            const KrylovBufs &kb, hipStream_t s) {
+    const size_t n = (size_t)6 * g.K * g.nel;
+    hipLaunchKernelGGL(k_bicg_init, dim3(elem_grid(g)), dim3(256), 0, s, rin, r, rh, p, v, d, n,
+                       ks, tol2, kb.P3, kb.stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_k1(const Geom &g, const double *Gh, const double *r, const double *rh,
+                          const double *pin, const double *vin, double *pout, double *vout,
+                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+    return dispatch<RunK1>(g.K, g, Gh, r, rh, pin, vin, pout, vout, ks, kb, s);
+}
+
+hipError_t launch_bicg_k2(const Geom &g, const double *Gh, const double *r, const double *v,
+                          double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
+                          hipStream_t s) {
+    return dispatch<RunK2>(g.K, g, Gh, r, v, sv, t, ks, kb, s);
+}
+
+hipError_t launch_bicg_k3(const Geom &g, double *d, double *r, const double *rh, const double *p,
+                          const double *sv, const double *t, KrylovState *ks,
+                          const KrylovBufs &kb, hipStream_t s) {
+    const size_t n = (size_t)6 * g.K * g.nel;
+    hipLaunchKernelGGL(k_bicg_k3, dim3(elem_grid(g)), dim3(256), 0, s, d, r, rh, p, sv, t, n, ks,
+                       kb.P2, (int)face_grid(g), kb.P3, kb.stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
+                       hipStream_t s) {
+    return dispatch<RunDiag>(g.K, g, q, partials, stride, s);
+}
+
+}  // namespace imexhdg

@@ -1,0 +1,92 @@
+// Device kernels of one IMEX HDG-DG step and their launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace imexhdg {
+
+constexpr int kMaxK = 9;        // K = degree + 1 <= 9
+constexpr int kLanes = 64;      // elements (or faces) per workgroup, one per lane
+constexpr int kMaxComb = 12;    // inputs of a stage combination
+
+// Mesh geometry and the small reference-element tables, passed by value.
+struct Geom {
+    int nx, ny, nel, K;
+    double sx, sy;              // 2/hx, 2/hy
+    double phiB, tau;           // phi_B, sqrt(phi_B)
+    double winv0, winvk;        // 1/w_0, 1/w_k
+    double Dw[kMaxK * kMaxK];   // Dw[m*K + a] = w_m D[m][a] / w_a (weak derivative)
+    double mass[kMaxK * kMaxK]; // (hx/2)(hy/2) w_i w_j at node j*K + i
+};
+
+// out = self * X + sum_p coef[p] * in[p]   (X the kernel's own result)
+// and, if store != nullptr, store = X.  Volume device layout.
+struct Comb {
+    const double *in[kMaxComb];
+    double coef[kMaxComb];
+    int n;
+    double self;
+    double *out;
+    double *store;
+};
+
+// BiCGStab recurrence scalars in device memory.  Each field is written by
+// block 0 of exactly one kernel and read only by later kernels.
+struct KrylovState {
+    double rho, alpha, omega;   // rho = rh.r of the last K2, alpha, omega
+    double rr;                  // last ||r||^2 seen by K1
+    double tol2;                // stop when ||r||^2 <= tol2
+    int32_t conv, breakdown, iters, pad;
+};
+
+// Per-block partial sums of the three BiCGStab reductions, [quantity][block].
+struct KrylovBufs {
+    double *P1, *P2, *P3;
+    int stride;                 // >= max grid of any Krylov launch
+};
+
+// Capped grid sizes of the face-tile kernels, the elementwise Krylov
+// kernels and the diagnostics kernel; partial arrays hold this many blocks.
+struct Geom;
+unsigned face_grid(const Geom &g);
+unsigned elem_grid(const Geom &g);
+unsigned diag_grid(const Geom &g);
+
+// ---------------------------------------------------------------- launchers
+// All return hipError_t of the launch.
+hipError_t launch_nl(const Geom &g, const double *q, const Comb &comb, hipStream_t s);
+hipError_t launch_combine(const Geom &g, const Comb &comb, size_t n, hipStream_t s);
+hipError_t launch_linear_residual(const Geom &g, const double *Q, const double *qhat,
+                                  double *out, hipStream_t s);
+hipError_t launch_local_apply(const Geom &g, const double *Ainv, const double *R,
+                              double *Z, hipStream_t s);
+hipError_t launch_trace_rhs(const Geom &g, const double *Z, const double *Pxinv,
+                            const double *Pyinv, double *gvec, double *ghat, hipStream_t s);
+hipError_t launch_recover(const Geom &g, const double *W, const double *Z,
+                          const double *qhat, double *Q, hipStream_t s);
+// FP64 r = g - G x and rin = ghat - Ghat x; partials [4][face_grid] of
+// ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
+hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,
+                                 const double *x, const double *gvec, const double *ghat,
+                                 double *r, double *rin, double *partials, int stride,
+                                 hipStream_t s);
+// BiCGStab on Ghat d = rin with d0 = 0: init, then per iteration K1, K2, K3.
+hipError_t launch_bicg_init(const Geom &g, const double *rin, double *r, double *rh,
+                            double *p, double *v, double *d, KrylovState *ks, double tol2,
+                            const KrylovBufs &kb, hipStream_t s);
+hipError_t launch_bicg_k1(const Geom &g, const double *Gh, const double *r, const double *rh,
+                          const double *pin, const double *vin, double *pout, double *vout,
+                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s);
+hipError_t launch_bicg_k2(const Geom &g, const double *Gh, const double *r, const double *v,
+                          double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
+                          hipStream_t s);
+hipError_t launch_bicg_k3(const Geom &g, double *d, double *r, const double *rh,
+                          const double *p, const double *sv, const double *t,
+                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s);
+hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s);
+// partials [5][diag_grid]: mass of phi_eta, U, V; energy; non-finite count
+hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
+                       hipStream_t s);
+
+}  // namespace imexhdg
