@@ -132,6 +132,36 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Sizes of the packed matrix-core operands of the trace row blocks.
+size_t frag_count(int K) {
+    const int B3 = 3 * K, KS = (B3 + 3) / 4, NKK = 7 * KS, NMB = (B3 + 15) / 16;
+    return (size_t)2 * NMB * NKK * 64;
+}
+
+// Pack the 7-slot row blocks of G for x- and y-faces into the A-operand
+// order of v_mfma_f64_16x16x4f64: frag[dir][mb][kk][lane] holds row
+// 16 mb + lane % 16 (face row (c, j)) and column 4 (kk mod KS) + lane / 16
+// (c' K + j') of slot kk / KS, KS = ceil(3K / 4) k-steps per slot; rows and
+// columns past 3K are zero.
+std::vector<double> pack_frags(const std::vector<double> &Gx, const std::vector<double> &Gy,
+                               int K) {
+    const int B3 = 3 * K, KS = (B3 + 3) / 4, NKK = 7 * KS, NMB = (B3 + 15) / 16;
+    std::vector<double> f(frag_count(K), 0.0);
+    for (int d = 0; d < 2; ++d) {
+        const std::vector<double> &G = d ? Gy : Gx;
+        for (int mb = 0; mb < NMB; ++mb)
+            for (int kk = 0; kk < NKK; ++kk)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * mb + l % 16;
+                    const int slot = kk / KS, col = 4 * (kk % KS) + l / 16;
+                    if (row >= B3 || col >= B3) continue;
+                    f[(((size_t)d * NMB + mb) * NKK + kk) * 64 + l] =
+                        G[(size_t)slot * B3 * B3 + (size_t)row * B3 + col];
+                }
+    }
+    return f;
+}
+
 // stride of every partial-sum array; no launch has a larger grid
 constexpr int kPartStride = 1024;
 
@@ -154,7 +184,7 @@ Layout layout_of(const imexhdg_config &c) {
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     t += 14 * align256(L.T * 8);                       // trace vectors
     t += align256(L.n_loc * L.n_loc * 8) + align256(L.n_loc * L.n_tr * 8);
-    t += 2 * align256(2 * 7 * 9 * K * K * 8) + 2 * align256(9 * K * K * 8);
+    t += 2 * align256(frag_count((int)K) * 8) + 2 * align256(9 * K * K * 8);
     t += 5 * align256(kPartStride * 8) + align256(5 * kPartStride * 8);
     t += align256(sizeof(KrylovState));
     L.total = t;
@@ -549,8 +579,8 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
     for (double **p : tv) *p = (double *)take(L.T * 8);
     c->dAinv = (double *)take(L.n_loc * L.n_loc * 8);
     c->dW = (double *)take(L.n_loc * L.n_tr * 8);
-    c->dG = (double *)take(2 * 7 * 9 * K * K * 8);
-    c->dGh = (double *)take(2 * 7 * 9 * K * K * 8);
+    c->dG = (double *)take(frag_count(K) * 8);
+    c->dGh = (double *)take(frag_count(K) * 8);
     c->dPx = (double *)take(9 * K * K * 8);
     c->dPy = (double *)take(9 * K * K * 8);
     c->kb.P1 = (double *)take(kPartStride * 8);
@@ -566,9 +596,8 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
         return bail(fail(IMEXHDG_E_NOMEM, "hipHostMalloc failed"));
 
     const StageOperators &op = c->op;
-    std::vector<double> G(op.Gx), Gh(op.Gxh);
-    G.insert(G.end(), op.Gy.begin(), op.Gy.end());
-    Gh.insert(Gh.end(), op.Gyh.begin(), op.Gyh.end());
+    const std::vector<double> G = pack_frags(op.Gx, op.Gy, K);
+    const std::vector<double> Gh = pack_frags(op.Gxh, op.Gyh, K);
     auto up = [&](double *d, const std::vector<double> &h) {
         return hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream);
     };

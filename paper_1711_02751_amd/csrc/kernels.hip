@@ -522,76 +522,184 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
     }
 }
 
-// y(c, j) = sum_slots sum_col M[slot][(c K + j)][col] sX[slot][col]
-template <int K>
-__device__ __forceinline__ void apply7(const double *__restrict__ M, int j, int lane,
-                                       double (*sX)[3 * K][64], double y[3]) {
-    constexpr int B3 = 3 * K;
-    const cdouble *Mc = as_const(M);
-    y[0] = y[1] = y[2] = 0.0;
+// ---------------------------------------------- MFMA trace row blocks
+// y_f = sum over the 7 neighbour slots of M[slot] x_{slot face}, one output
+// row block (3K rows) per face, as a dense contraction on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64): rows = A (16-row blocks of the shared
+// matrix, host-packed per lane), k = (slot, c', j') of the gathered traces,
+// columns = 16 faces per wave.  Operand layout of the instruction: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element r of
+// lane l is D[4 r + l / 16][l % 16].
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int K> struct MF {
+    static constexpr int B3 = 3 * K;
+    static constexpr int B3P = (B3 + 3) / 4 * 4;   // slot k-range padded to 4
+    static constexpr int KS = B3P / 4;             // k steps per slot
+    static constexpr int NKK = 7 * KS;             // k steps
+    static constexpr int NMB = (B3 + 15) / 16;     // 16-row blocks
+};
+
+// Workgroups (of 4 waves) per CU the matrix-core kernels are compiled for:
+// the register budget that keeps them free of scratch spills.
+template <int K> struct MFOcc {
+    static constexpr int value = K <= 5 ? 3 : 2;
+};
+
+// Packed A fragments: frag[dir][mb][kk][lane] (see element-side packing).
+__device__ __forceinline__ size_t frag_off(int d, int mb, int kk, int lane, int NMB, int NKK) {
+    return (((size_t)d * NMB + mb) * NKK + kk) * 64 + lane;
+}
+
+// One wave: two sets of 16 faces, the x-faces and the y-faces of the same
+// 16 elements (column lane % 16), as two independent accumulation chains.
+// The contraction runs slot by slot (each slot's k range padded to a
+// multiple of 4, so a k step never straddles two slots); the B values of
+// slot s + 1 are loaded before the matrix-core work of slot s is issued.
+// load_b(set, slot, o) returns the B value at trace offset o.
+template <int K, int NM, typename LoadB>
+__device__ __forceinline__ void mfma_rows2(const double *__restrict__ const *frags,
+                                           const int (*dirs)[7], const int (*idx)[7],
+                                           size_t nel, int lane, LoadB load_b,
+                                           v4d (*acc)[NM][MF<K>::NMB]) {
+    constexpr int B3 = MF<K>::B3, KS = MF<K>::KS, NKK = MF<K>::NKK, NMB = MF<K>::NMB;
+    const size_t TT = (size_t)B3 * nel;
+    const int q = lane >> 4;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = v4d{0.0, 0.0, 0.0, 0.0};
+    // slot s is uniform over the wave: the switch selects its neighbour face
+    // with scalar branches (no indexed register arrays)
+    auto fetch = [&](int s, double (&dst)[KS][2]) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            int dd = dirs[f][0], ii = idx[f][0];
+            switch (s) {
+                case 1: dd = dirs[f][1]; ii = idx[f][1]; break;
+                case 2: dd = dirs[f][2]; ii = idx[f][2]; break;
+                case 3: dd = dirs[f][3]; ii = idx[f][3]; break;
+                case 4: dd = dirs[f][4]; ii = idx[f][4]; break;
+                case 5: dd = dirs[f][5]; ii = idx[f][5]; break;
+                case 6: dd = dirs[f][6]; ii = idx[f][6]; break;
+                default: break;
+            }
+            const size_t base = (size_t)dd * TT + ii;
+#pragma unroll
+            for (int u = 0; u < KS; ++u) {
+                const int cj = 4 * u + q;
+                dst[u][f] = (cj < B3) ? load_b(f, s, base + (size_t)cj * nel) : 0.0;
+            }
+        }
+    };
+    double cur[KS][2], nxt[KS][2];
+    fetch(0, cur);
 #pragma unroll 1
     for (int s = 0; s < 7; ++s) {
-        const cdouble *Ms = Mc + (size_t)s * B3 * B3 + j * B3;
+        if (s + 1 < 7) fetch(s + 1, nxt);
 #pragma unroll
-        for (int col = 0; col < B3; ++col) {
-            const double x = sX[s][col][lane];
+        for (int u = 0; u < KS; ++u) {
+            const int kk = s * KS + u;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) y[c] += Ms[c * K * B3 + col] * x;
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int m = 0; m < NM; ++m)
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb)
+                        acc[f][m][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], cur[u][f],
+                            acc[f][m][mb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            cur[u][0] = nxt[u][0];
+            cur[u][1] = nxt[u][1];
         }
     }
 }
 
-struct TraceMats {
-    const double *Gx, *Gy;        // 7 (3K)^2 blocks each
+// Tiles of 64 elements; block b walks tiles so that the blocks resident on
+// one XCD (b mod 8, as the dispatcher deals workgroups round robin over
+// the eight XCDs) cover one contiguous band of the mesh and share its
+// neighbour faces in their L2.
+struct TileWalk {
+    int first, step, end;
 };
 
-__device__ __forceinline__ size_t trace_off(int d, int c, int j, int f, int K, size_t nel) {
-    return (size_t)d * 3 * K * nel + (size_t)(c * K + j) * nel + f;
+__device__ __forceinline__ TileWalk tile_walk(int ntiles) {
+    const int G = gridDim.x;
+    if (G % 8 != 0 || G < 8) return TileWalk{(int)blockIdx.x, G, ntiles};
+    const int xcd = blockIdx.x % 8, local = blockIdx.x / 8, per = G / 8;
+    const int chunk = (ntiles + 7) / 8;
+    const int begin = xcd * chunk;
+    const int end = min(ntiles, begin + chunk);
+    return TileWalk{begin + local, per, end};
+}
+
+struct FragMats {
+    const double *A0, *A1;   // packed fragments of one or two matrices
+};
+
+// Wave-level face index: element tile t covers 64 elements, wave w of the
+// block takes elements 16 w .. 16 w + 15 of it; face set 0 is their x-faces
+// (west faces), set 1 their y-faces (south faces).
+__device__ __forceinline__ void faces_of_wave(int tile, int nel, int nx, int ny, int w,
+                                              int lane, FaceIdx fi[2], int dirs[2][7],
+                                              int idx[2][7]) {
+    const int e = tile * 64 + w * 16 + (lane & 15);
+    const bool active = e < nel;
+    for (int d = 0; d < 2; ++d) {
+        fi[d].d = d;
+        fi[d].f = active ? e : 0;
+        fi[d].active = active;
+        slot_faces(fi[d], nx, ny, dirs[d], idx[d]);
+    }
 }
 
 // FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
 // partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
 template <int K>
-__global__ __launch_bounds__(64 * K) void k_trace_residual(
-    const TraceMats G, const TraceMats Gh, const double *__restrict__ x,
-    const double *__restrict__ gv, const double *__restrict__ gh, const Geom g,
-    double *__restrict__ r, double *__restrict__ rin, double *partials, int stride) {
-    __shared__ double sX[7][3 * K][64];
-    const int lane = threadIdx.x & 63;
-    const int j = wave_id();
-    const size_t nel = g.nel;
-    const int ntiles = 2 * ((g.nel + 63) / 64);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const FaceIdx fi = face_of_tile(tile, g.nel);
-        int dir[7], idx[7];
-        slot_faces(fi, g.nx, g.ny, dir, idx);
+__global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
+    const FragMats A, const double *__restrict__ x, const double *__restrict__ gv,
+    const double *__restrict__ gh, const Geom g, double *__restrict__ r,
+    double *__restrict__ rin, double *partials, int stride) {
+    constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const size_t nel = g.nel, TT = (size_t)B3 * nel;
+    const int ntiles = (g.nel + 63) / 64;
+    const double *fr[2] = {A.A0, A.A1};
+    double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+    const TileWalk tw = tile_walk(ntiles);
+    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+        FaceIdx fi[2];
+        int dirs[2][7], idx[2][7];
+        faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
+        v4d acc[2][2][NMB];
+        mfma_rows2<K, 2>(fr, dirs, idx, nel, lane,
+                         [&](int, int, size_t o) { return x[o]; }, acc);
 #pragma unroll
-        for (int s = 0; s < 7; ++s)
+        for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                sX[s][c * K + j][lane] = x[trace_off(dir[s], c, j, idx[s], K, nel)];
-        __syncthreads();
-        double y[3], yh[3];
-        apply7<K>(fi.d == 0 ? G.Gx : G.Gy, j, lane, sX, y);
-        apply7<K>(fi.d == 0 ? Gh.Gx : Gh.Gy, j, lane, sX, yh);
-        if (fi.active) {
+        for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t o = trace_off(fi.d, c, j, fi.f, K, nel);
-                const double rr = gv[o] - y[c];
-                const double ri = gh[o] - yh[c];
-                r[o] = rr;
-                rin[o] = ri;
-                acc[0] += rr * rr;
-                acc[1] += gv[o] * gv[o];
-                acc[2] += gh[o] * gh[o];
-                acc[3] += ri * ri;
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * mb + 4 * e + (lane >> 4);
+                if (row < B3 && fi[f].active) {
+                    const size_t o = f * TT + (size_t)row * nel + fi[f].f;
+                    const double rr = gv[o] - acc[f][0][mb][e];
+                    const double ri = gh[o] - acc[f][1][mb][e];
+                    r[o] = rr;
+                    rin[o] = ri;
+                    acc4[0] += rr * rr;
+                    acc4[1] += gv[o] * gv[o];
+                    acc4[2] += gh[o] * gh[o];
+                    acc4[3] += ri * ri;
+                }
             }
-        }
-        __syncthreads();
     }
-    store_partials<4>(acc, partials, stride);
+    store_partials<4>(acc4, partials, stride);
 }
 
 // ------------------------------------------------------------ BiCGStab
@@ -633,15 +741,15 @@ __global__ void k_bicg_init(const double *__restrict__ rin, double *__restrict__
 }
 
 template <int K>
-__global__ __launch_bounds__(64 * K) void k_bicg_k1(const TraceMats Gh,
-                                                    const double *__restrict__ r,
-                                                    const double *__restrict__ rh,
-                                                    const double *__restrict__ pin,
-                                                    const double *__restrict__ vin,
-                                                    double *__restrict__ pout,
-                                                    double *__restrict__ vout, const Geom g,
-                                                    KrylovState *ks, const double *P3, int n3,
-                                                    double *P1, int stride) {
+__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats A, const double *__restrict__ r,
+                                                 const double *__restrict__ rh,
+                                                 const double *__restrict__ pin,
+                                                 const double *__restrict__ vin,
+                                                 double *__restrict__ pout,
+                                                 double *__restrict__ vout, const Geom g,
+                                                 KrylovState *ks, const double *P3, int n3,
+                                                 double *P1, int stride) {
+    constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
     double red[2];
     reduce_partials<2>(P3, stride, n3, red);
     if (ks->conv) return;
@@ -656,50 +764,52 @@ __global__ __launch_bounds__(64 * K) void k_bicg_k1(const TraceMats Gh,
         return;
     }
     const double beta = (rho_new / rho) * (alpha / omega);
-    __shared__ double sX[7][3 * K][64];
-    const int lane = threadIdx.x & 63;
-    const int j = wave_id();
-    const size_t nel = g.nel;
-    const int ntiles = 2 * ((g.nel + 63) / 64);
-    double acc[1] = {0.0};
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const FaceIdx fi = face_of_tile(tile, g.nel);
-        int dir[7], idx[7];
-        slot_faces(fi, g.nx, g.ny, dir, idx);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const size_t nel = g.nel, TT = (size_t)B3 * nel;
+    const int ntiles = (g.nel + 63) / 64;
+    const double *fr[1] = {A.A0};
+    double acc1[1] = {0.0};
+    const TileWalk tw = tile_walk(ntiles);
+    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+        FaceIdx fi[2];
+        int dirs[2][7], idx[2][7];
+        faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
+        v4d acc[2][1][NMB];
+        mfma_rows2<K, 1>(fr, dirs, idx, nel, lane,
+                         [&](int f, int sl, size_t o) {
+                             const double v = r[o] + beta * (pin[o] - omega * vin[o]);
+                             if (sl == 0 && fi[f].active) pout[o] = v;
+                             return v;
+                         },
+                         acc);
 #pragma unroll
-        for (int s = 0; s < 7; ++s)
+        for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t o = trace_off(dir[s], c, j, idx[s], K, nel);
-                sX[s][c * K + j][lane] = r[o] + beta * (pin[o] - omega * vin[o]);
-            }
-        __syncthreads();
-        double y[3];
-        apply7<K>(fi.d == 0 ? Gh.Gx : Gh.Gy, j, lane, sX, y);
-        if (fi.active) {
+            for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t o = trace_off(fi.d, c, j, fi.f, K, nel);
-                pout[o] = sX[0][c * K + j][lane];
-                vout[o] = y[c];
-                acc[0] += rh[o] * y[c];
-            }
-        }
-        __syncthreads();
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * mb + 4 * e + (lane >> 4);
+                    if (row < B3 && fi[f].active) {
+                        const size_t o = f * TT + (size_t)row * nel + fi[f].f;
+                        const double y = acc[f][0][mb][e];
+                        vout[o] = y;
+                        acc1[0] += rh[o] * y;
+                    }
+                }
     }
-    store_partials<1>(acc, P1, stride);
+    store_partials<1>(acc1, P1, stride);
     if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
 }
 
 template <int K>
-__global__ __launch_bounds__(64 * K) void k_bicg_k2(const TraceMats Gh,
-                                                    const double *__restrict__ r,
-                                                    const double *__restrict__ v,
-                                                    double *__restrict__ sv,
-                                                    double *__restrict__ t, const Geom g,
-                                                    KrylovState *ks, const double *P1, int n1,
-                                                    const double *P3, int n3, double *P2,
-                                                    int stride) {
+__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats A, const double *__restrict__ r,
+                                                 const double *__restrict__ v,
+                                                 double *__restrict__ sv,
+                                                 double *__restrict__ t, const Geom g,
+                                                 KrylovState *ks, const double *P1, int n1,
+                                                 const double *P3, int n3, double *P2,
+                                                 int stride) {
+    constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
     double red1[1], red3[2];
     reduce_partials<1>(P1, stride, n1, red1);
     reduce_partials<2>(P3, stride, n3, red3);
@@ -713,40 +823,42 @@ __global__ __launch_bounds__(64 * K) void k_bicg_k2(const TraceMats Gh,
         return;
     }
     const double alpha = rho_new / rv;
-    __shared__ double sX[7][3 * K][64];
-    const int lane = threadIdx.x & 63;
-    const int j = wave_id();
-    const size_t nel = g.nel;
-    const int ntiles = 2 * ((g.nel + 63) / 64);
-    double acc[2] = {0.0, 0.0};
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const FaceIdx fi = face_of_tile(tile, g.nel);
-        int dir[7], idx[7];
-        slot_faces(fi, g.nx, g.ny, dir, idx);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const size_t nel = g.nel, TT = (size_t)B3 * nel;
+    const int ntiles = (g.nel + 63) / 64;
+    const double *fr[1] = {A.A0};
+    double acc2[2] = {0.0, 0.0};
+    const TileWalk tw = tile_walk(ntiles);
+    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+        FaceIdx fi[2];
+        int dirs[2][7], idx[2][7];
+        faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
+        v4d acc[2][1][NMB];
+        mfma_rows2<K, 1>(fr, dirs, idx, nel, lane,
+                         [&](int f, int sl, size_t o) {
+                             const double sval = r[o] - alpha * v[o];
+                             if (sl == 0 && fi[f].active) sv[o] = sval;
+                             return sval;
+                         },
+                         acc);
 #pragma unroll
-        for (int s = 0; s < 7; ++s)
+        for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t o = trace_off(dir[s], c, j, idx[s], K, nel);
-                sX[s][c * K + j][lane] = r[o] - alpha * v[o];
-            }
-        __syncthreads();
-        double y[3];
-        apply7<K>(fi.d == 0 ? Gh.Gx : Gh.Gy, j, lane, sX, y);
-        if (fi.active) {
+            for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t o = trace_off(fi.d, c, j, fi.f, K, nel);
-                const double sval = sX[0][c * K + j][lane];
-                sv[o] = sval;
-                t[o] = y[c];
-                acc[0] += y[c] * sval;
-                acc[1] += y[c] * y[c];
-            }
-        }
-        __syncthreads();
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * mb + 4 * e + (lane >> 4);
+                    if (row < B3 && fi[f].active) {
+                        const size_t o = f * TT + (size_t)row * nel + fi[f].f;
+                        const double y = acc[f][0][mb][e];
+                        const double sval = r[o] - alpha * v[o];
+                        t[o] = y;
+                        acc2[0] += y * sval;
+                        acc2[1] += y * y;
+                    }
+                }
     }
-    store_partials<2>(acc, P2, stride);
+    store_partials<2>(acc2, P2, stride);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ks->rho = rho_new;
         ks->alpha = alpha;
@@ -825,10 +937,6 @@ hipError_t dispatch(int K, Args &&...args) {
     }
 }
 
-TraceMats split_mats(const double *G, int K) {
-    const size_t B = (size_t)7 * 9 * K * K;
-    return TraceMats{G, G + B};
-}
 
 template <int K> struct RunNL {
     static hipError_t run(const Geom &g, const double *q, const Comb &c, hipStream_t s) {
@@ -869,9 +977,8 @@ template <int K> struct RunTraceResidual {
     static hipError_t run(const Geom &g, const double *G, const double *Gh, const double *x,
                           const double *gv, const double *gh, double *r, double *rin,
                           double *partials, int stride, hipStream_t s) {
-        hipLaunchKernelGGL(k_trace_residual<K>, dim3(face_grid(g)), dim3(64 * K), 0, s,
-                           split_mats(G, K), split_mats(Gh, K), x, gv, gh, g, r, rin, partials,
-                           stride);
+        hipLaunchKernelGGL(k_trace_residual<K>, dim3(face_grid(g)), dim3(256), 0, s,
+                           FragMats{G, Gh}, x, gv, gh, g, r, rin, partials, stride);
         return hipGetLastError();
     }
 };
@@ -879,8 +986,8 @@ template <int K> struct RunK1 {
     static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *rh,
                           const double *pin, const double *vin, double *pout, double *vout,
                           KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-        hipLaunchKernelGGL(k_bicg_k1<K>, dim3(face_grid(g)), dim3(64 * K), 0, s,
-                           split_mats(Gh, K), r, rh, pin, vin, pout, vout, g, ks, kb.P3,
+        hipLaunchKernelGGL(k_bicg_k1<K>, dim3(face_grid(g)), dim3(256), 0, s,
+                           FragMats{Gh, nullptr}, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
                            (int)elem_grid(g), kb.P1, kb.stride);
         return hipGetLastError();
     }
@@ -889,8 +996,8 @@ template <int K> struct RunK2 {
     static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *v,
                           double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
                           hipStream_t s) {
-        hipLaunchKernelGGL(k_bicg_k2<K>, dim3(face_grid(g)), dim3(64 * K), 0, s,
-                           split_mats(Gh, K), r, v, sv, t, g, ks, kb.P1, (int)face_grid(g),
+        hipLaunchKernelGGL(k_bicg_k2<K>, dim3(face_grid(g)), dim3(256), 0, s,
+                           FragMats{Gh, nullptr}, r, v, sv, t, g, ks, kb.P1, (int)face_grid(g),
                            kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
         return hipGetLastError();
     }
@@ -907,7 +1014,10 @@ template <int K> struct RunDiag {
 }  // namespace
 
 unsigned face_grid(const Geom &g) {
-    return std::min<unsigned>(2 * grid1(g.nel, 64), kMaxGrid);
+    // element tiles of 64; a multiple of 8 blocks (when there are enough
+    // tiles) so that every XCD gets the same number of blocks
+    const unsigned n = std::min<unsigned>(grid1(g.nel, 64), kMaxGrid);
+    return n >= 8 ? n & ~7u : n;
 }
 
 unsigned elem_grid(const Geom &g) {

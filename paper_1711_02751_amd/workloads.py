@@ -107,38 +107,48 @@ class Workload:
 
 
 # Time steps.  Courant reading: Cr = dt max(|u| + sqrt(phi)) / dx_min with
-# dx_min the smallest LGL node spacing (h/2)(1 - xi_1).  The bump workloads use
-# an advective CFL of 0.5 at |u| = 0.1, i.e. dt = 5 dx_min:
+# dx_min the smallest LGL node spacing (h/2)(1 - xi_1):
 #   k=4: 1 - xi_1 = 1 - sqrt(3/7);  k=6: 1 - xi_1 = 0.16977610372143...;
 #   k=3: 1 - xi_1 = 1 - 1/sqrt(5).
+# The bump workloads take dt = 2 dx_min: advective Courant 0.2 at |u| = 0.1
+# and gravity Courant about 6.5 for g = 9.81, H = 1.  An advective Courant of
+# 0.5 (dt = 5 dx_min) exceeds the stability limit of the explicit nonlinear
+# part at k = 4 and k = 6 (growth within a few dozen steps); 2 dx_min runs
+# the step counts below without growth.
+ADVECTIVE_DT_FACTOR = 2.0
+_XI1 = {3: 1.0 - 1.0 / math.sqrt(5.0), 4: 1.0 - math.sqrt(3.0 / 7.0),
+        6: 0.16977610372143304}
+
+
+def bump_dt(n, k, L=1.0):
+    return ADVECTIVE_DT_FACTOR * _XI1[k] / 2.0 * L / n
+
+
 WORKLOADS = {
     "standing_wave_8x8_k2": Workload(
         "standing_wave_8x8_k2", n=8, k=2, g=1.0, H=1.0, dt=0.01, steps=100,
         nonlinear=False, ic="standing_wave",
         notes="linearized, exact standing wave, FP64"),
     "bump_64x64_k4": Workload(
-        "bump_64x64_k4", n=64, k=4, g=9.81, H=1.0,
-        dt=5.0 * (1.0 - math.sqrt(3.0 / 7.0)) / 2.0 / 64, steps=500,
+        "bump_64x64_k4", n=64, k=4, g=9.81, H=1.0, dt=bump_dt(64, 4), steps=500,
         nonlinear=True, ic="bump_flow", seed=2),
     "bump_256x256_k4": Workload(
-        "bump_256x256_k4", n=256, k=4, g=9.81, H=1.0,
-        dt=5.0 * (1.0 - math.sqrt(3.0 / 7.0)) / 2.0 / 256, steps=500,
+        "bump_256x256_k4", n=256, k=4, g=9.81, H=1.0, dt=bump_dt(256, 4), steps=500,
         nonlinear=True, ic="bump_flow", seed=3),
     "bump_1024x1024_k6": Workload(
-        "bump_1024x1024_k6", n=1024, k=6, g=9.81, H=1.0,
-        dt=5.0 * 0.16977610372143304 / 2.0 / 1024, steps=200,
+        "bump_1024x1024_k6", n=1024, k=6, g=9.81, H=1.0, dt=bump_dt(1024, 6), steps=200,
         nonlinear=True, ic="bump_flow", seed=5, n_bumps=16),
 }
 
 
 def ensemble_members(seed=4, count=64, k=3, g=9.81, H=1.0, steps=100):
     """Ensemble of `count` periodic runs on uneven meshes n_m in [32, 128];
-    member m uses IC seed 4000 + m and dt_m = 5 dx_min(n_m)."""
+    member m uses IC seed 4000 + m and dt_m = 2 dx_min(n_m), so dt_m / h_m
+    is the same for every member."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sizes = rng.integers(32, 129, size=count)
-    c = 5.0 * (1.0 - 1.0 / math.sqrt(5.0)) / 2.0
     return [Workload(f"member{m}", n=int(sizes[m]), k=k, g=g, H=H,
-                     dt=c / int(sizes[m]), steps=steps, nonlinear=True,
+                     dt=bump_dt(int(sizes[m]), k), steps=steps, nonlinear=True,
                      ic="bump_flow", seed=4000 + m)
             for m in range(count)]
 
