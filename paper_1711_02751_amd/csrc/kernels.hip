@@ -658,9 +658,137 @@ __device__ __forceinline__ void faces_of_wave(int tile, int nel, int nx, int ny,
     }
 }
 
+// ------------------------------------- LDS-staged tiles of 16 x 4 elements
+// When the mesh is a whole number of 16 x 4 element tiles, a workgroup
+// stages once into LDS every trace face its tile's row blocks read (the
+// union over the 7 slots of the x- and y-faces of its 64 elements: 18 x 5
+// x-faces and 17 x 6 y-faces), with coalesced loads of whole face rows, and
+// the matrix cores read their B operands from LDS.  Each trace value then
+// crosses L2 about 1.5 times per launch instead of 7.
+constexpr int kTX = 16, kTY = 4;
+
+template <int K> struct Tile {
+    static constexpr int B3 = 3 * K;
+    static constexpr int XR = kTY + 1, XC = kTX + 2;   // x-faces: rows ey0-1.., cols ex0-1..
+    static constexpr int YR = kTY + 2, YC = kTX + 1;   // y-faces
+    static constexpr int NX = XR * XC, NY = YR * YC, NF = NX + NY;
+};
+
+__device__ __forceinline__ bool tiled_mesh(const Geom &g) {
+    return g.nx % kTX == 0 && g.ny % kTY == 0;
+}
+
+// Staged face f of the tile with corner (ex0, ey0) -> direction, global face
+// (element) index, and whether the tile owns it (it is a face of one of the
+// tile's own elements).
+__device__ __forceinline__ void staged_face(int f, int ex0, int ey0, int nx, int ny, int NX,
+                                            int XC, int YC, int &dir, int &elem, bool &own) {
+    int r, c;
+    if (f < NX) { dir = 0; r = f / XC; c = f % XC; }
+    else { dir = 1; r = (f - NX) / YC; c = (f - NX) % YC; }
+    const int ex = (ex0 - 1 + c + nx) % nx, ey = (ey0 - 1 + r + ny) % ny;
+    elem = ey * nx + ex;
+    own = r >= 1 && r <= kTY && c >= 1 && c <= kTX;
+}
+
+// LDS face index of slot `s` of face set `set` for tile element (lx, ly).
+__device__ __forceinline__ int slot_lds(int set, int s, int lx, int ly, int NX, int XC, int YC) {
+    // (dir, dx, dy) of each slot, from the neighbour lists of the row blocks
+    int d = 0, dx = 0, dy = 0;
+    if (set == 0) {
+        switch (s) {
+            case 0: d = 0; dx = 0; dy = 0; break;
+            case 1: d = 0; dx = 1; dy = 0; break;
+            case 2: d = 1; dx = 0; dy = 0; break;
+            case 3: d = 1; dx = 0; dy = 1; break;
+            case 4: d = 0; dx = -1; dy = 0; break;
+            case 5: d = 1; dx = -1; dy = 0; break;
+            default: d = 1; dx = -1; dy = 1; break;
+        }
+    } else {
+        switch (s) {
+            case 0: d = 1; dx = 0; dy = 0; break;
+            case 1: d = 0; dx = 0; dy = 0; break;
+            case 2: d = 0; dx = 1; dy = 0; break;
+            case 3: d = 1; dx = 0; dy = 1; break;
+            case 4: d = 1; dx = 0; dy = -1; break;
+            case 5: d = 0; dx = 0; dy = -1; break;
+            default: d = 0; dx = 1; dy = -1; break;
+        }
+    }
+    return d == 0 ? (ly + dy + 1) * XC + (lx + dx + 1)
+                  : NX + (ly + dy + 1) * YC + (lx + dx + 1);
+}
+
+// Stage the tile: sB[cj][f] = stage(o, own) for every staged face f and row
+// cj (c' K + j'); then the wave's two row-block sets (x- and y-faces of its
+// 16 elements) by the matrix cores from LDS.
+template <int K, int NM, typename Stage>
+__device__ __forceinline__ void tiled_rows(const double *__restrict__ const *frags, int tile,
+                                           const Geom &g, double (*sB)[Tile<K>::NF],
+                                           Stage stage, v4d (*acc)[NM][MF<K>::NMB]) {
+    using T = Tile<K>;
+    constexpr int B3 = T::B3, NF = T::NF, KS = MF<K>::KS, NKK = MF<K>::NKK,
+                  NMB = MF<K>::NMB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tpr = g.nx / kTX;
+    const int ex0 = (tile % tpr) * kTX, ey0 = (tile / tpr) * kTY;
+    const size_t nel = g.nel, TT = (size_t)B3 * nel;
+    __syncthreads();   // previous tile's LDS reads are done
+    for (int v = threadIdx.x; v < B3 * NF; v += blockDim.x) {
+        const int cj = v / NF, f = v - cj * NF;
+        int dir, elem;
+        bool own;
+        staged_face(f, ex0, ey0, g.nx, g.ny, T::NX, T::XC, T::YC, dir, elem, own);
+        sB[cj][f] = stage((size_t)dir * TT + (size_t)cj * nel + elem, own);
+    }
+    __syncthreads();
+    const int q = lane >> 4, lx = lane & 15;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int s = 0; s < 7; ++s) {
+        int li[2];
+        li[0] = slot_lds(0, s, lx, w, T::NX, T::XC, T::YC);
+        li[1] = slot_lds(1, s, lx, w, T::NX, T::XC, T::YC);
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int cj = 4 * u + q, kk = s * KS + u;
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const double b = (cj < B3) ? sB[cj][li[f]] : 0.0;
+#pragma unroll
+                for (int m = 0; m < NM; ++m)
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb)
+                        acc[f][m][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], b, acc[f][m][mb],
+                            0, 0, 0);
+            }
+        }
+    }
+}
+
+// Global face element of set `f` of this wave's lane: (ex0 + lx, ey0 + w).
+__device__ __forceinline__ int tile_elem(int tile, const Geom &g) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tpr = g.nx / kTX;
+    return ((tile / tpr) * kTY + w) * g.nx + (tile % tpr) * kTX + (lane & 15);
+}
+
+template <int K>
+__device__ __forceinline__ int own_lds(int set, int lx, int ly) {
+    using T = Tile<K>;
+    return set == 0 ? (ly + 1) * T::XC + (lx + 1) : T::NX + (ly + 1) * T::YC + (lx + 1);
+}
+
 // FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
 // partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
-template <int K>
+template <int K, bool TILED>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
     const FragMats A, const double *__restrict__ x, const double *__restrict__ gv,
     const double *__restrict__ gh, const Geom g, double *__restrict__ r,
@@ -671,6 +799,38 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
     const int ntiles = (g.nel + 63) / 64;
     const double *fr[2] = {A.A0, A.A1};
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (TILED) {
+        __shared__ double sB[B3][Tile<K>::NF];
+        const int nt = (g.nx / kTX) * (g.ny / kTY);
+        const TileWalk tt = tile_walk(nt);
+        const int q = lane >> 4;
+        for (int tile = tt.first; tile < tt.end; tile += tt.step) {
+            v4d acc[2][2][NMB];
+            tiled_rows<K, 2>(fr, tile, g, sB, [&](size_t o, bool) { return x[o]; }, acc);
+            const int e = tile_elem(tile, g);
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        const int row = 16 * mb + 4 * e4 + q;
+                        if (row < B3) {
+                            const size_t o = f * TT + (size_t)row * nel + e;
+                            const double rr = gv[o] - acc[f][0][mb][e4];
+                            const double ri = gh[o] - acc[f][1][mb][e4];
+                            r[o] = rr;
+                            rin[o] = ri;
+                            acc4[0] += rr * rr;
+                            acc4[1] += gv[o] * gv[o];
+                            acc4[2] += gh[o] * gh[o];
+                            acc4[3] += ri * ri;
+                        }
+                    }
+        }
+        store_partials<4>(acc4, partials, stride);
+        return;
+    }
     const TileWalk tw = tile_walk(ntiles);
     for (int tile = tw.first; tile < tw.end; tile += tw.step) {
         FaceIdx fi[2];
@@ -740,7 +900,7 @@ __global__ void k_bicg_init(const double *__restrict__ rin, double *__restrict__
     }
 }
 
-template <int K>
+template <int K, bool TILED>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats A, const double *__restrict__ r,
                                                  const double *__restrict__ rh,
                                                  const double *__restrict__ pin,
@@ -769,6 +929,40 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
     const int ntiles = (g.nel + 63) / 64;
     const double *fr[1] = {A.A0};
     double acc1[1] = {0.0};
+    if constexpr (TILED) {
+        __shared__ double sB[B3][Tile<K>::NF];
+        const int nt = (g.nx / kTX) * (g.ny / kTY);
+        const TileWalk tt = tile_walk(nt);
+        const int q = lane >> 4;
+        for (int tile = tt.first; tile < tt.end; tile += tt.step) {
+            v4d acc[2][1][NMB];
+            tiled_rows<K, 1>(fr, tile, g, sB,
+                             [&](size_t o, bool own) {
+                                 const double v = r[o] + beta * (pin[o] - omega * vin[o]);
+                                 if (own) pout[o] = v;
+                                 return v;
+                             },
+                             acc);
+            const int e = tile_elem(tile, g);
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        const int row = 16 * mb + 4 * e4 + q;
+                        if (row < B3) {
+                            const size_t o = f * TT + (size_t)row * nel + e;
+                            const double y = acc[f][0][mb][e4];
+                            vout[o] = y;
+                            acc1[0] += rh[o] * y;
+                        }
+                    }
+        }
+        store_partials<1>(acc1, P1, stride);
+        if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
+        return;
+    }
     const TileWalk tw = tile_walk(ntiles);
     for (int tile = tw.first; tile < tw.end; tile += tw.step) {
         FaceIdx fi[2];
@@ -801,7 +995,7 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
     if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
 }
 
-template <int K>
+template <int K, bool TILED>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats A, const double *__restrict__ r,
                                                  const double *__restrict__ v,
                                                  double *__restrict__ sv,
@@ -828,6 +1022,47 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
     const int ntiles = (g.nel + 63) / 64;
     const double *fr[1] = {A.A0};
     double acc2[2] = {0.0, 0.0};
+    if constexpr (TILED) {
+        __shared__ double sB[B3][Tile<K>::NF];
+        const int nt = (g.nx / kTX) * (g.ny / kTY);
+        const TileWalk tt = tile_walk(nt);
+        const int q = lane >> 4;
+        for (int tile = tt.first; tile < tt.end; tile += tt.step) {
+            v4d acc[2][1][NMB];
+            tiled_rows<K, 1>(fr, tile, g, sB,
+                             [&](size_t o, bool own) {
+                                 const double sval = r[o] - alpha * v[o];
+                                 if (own) sv[o] = sval;
+                                 return sval;
+                             },
+                             acc);
+            const int e = tile_elem(tile, g);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const int li = own_lds<K>(f, lane & 15, w);
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        const int row = 16 * mb + 4 * e4 + q;
+                        if (row < B3) {
+                            const size_t o = f * TT + (size_t)row * nel + e;
+                            const double y = acc[f][0][mb][e4];
+                            const double sval = sB[row][li];
+                            t[o] = y;
+                            acc2[0] += y * sval;
+                            acc2[1] += y * y;
+                        }
+                    }
+            }
+        }
+        store_partials<2>(acc2, P2, stride);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ks->rho = rho_new;
+            ks->alpha = alpha;
+        }
+        return;
+    }
     const TileWalk tw = tile_walk(ntiles);
     for (int tile = tw.first; tile < tw.end; tile += tw.step) {
         FaceIdx fi[2];
@@ -977,8 +1212,12 @@ template <int K> struct RunTraceResidual {
     static hipError_t run(const Geom &g, const double *G, const double *Gh, const double *x,
                           const double *gv, const double *gh, double *r, double *rin,
                           double *partials, int stride, hipStream_t s) {
-        hipLaunchKernelGGL(k_trace_residual<K>, dim3(face_grid(g)), dim3(256), 0, s,
-                           FragMats{G, Gh}, x, gv, gh, g, r, rin, partials, stride);
+        if (is_tiled(g))
+            hipLaunchKernelGGL((k_trace_residual<K, true>), dim3(face_grid(g)), dim3(256), 0, s,
+                               FragMats{G, Gh}, x, gv, gh, g, r, rin, partials, stride);
+        else
+            hipLaunchKernelGGL((k_trace_residual<K, false>), dim3(face_grid(g)), dim3(256), 0,
+                               s, FragMats{G, Gh}, x, gv, gh, g, r, rin, partials, stride);
         return hipGetLastError();
     }
 };
@@ -986,9 +1225,14 @@ template <int K> struct RunK1 {
     static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *rh,
                           const double *pin, const double *vin, double *pout, double *vout,
                           KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-        hipLaunchKernelGGL(k_bicg_k1<K>, dim3(face_grid(g)), dim3(256), 0, s,
-                           FragMats{Gh, nullptr}, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
-                           (int)elem_grid(g), kb.P1, kb.stride);
+        if (is_tiled(g))
+            hipLaunchKernelGGL((k_bicg_k1<K, true>), dim3(face_grid(g)), dim3(256), 0, s,
+                               FragMats{Gh, nullptr}, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
+                               (int)elem_grid(g), kb.P1, kb.stride);
+        else
+            hipLaunchKernelGGL((k_bicg_k1<K, false>), dim3(face_grid(g)), dim3(256), 0, s,
+                               FragMats{Gh, nullptr}, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
+                               (int)elem_grid(g), kb.P1, kb.stride);
         return hipGetLastError();
     }
 };
@@ -996,9 +1240,14 @@ template <int K> struct RunK2 {
     static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *v,
                           double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
                           hipStream_t s) {
-        hipLaunchKernelGGL(k_bicg_k2<K>, dim3(face_grid(g)), dim3(256), 0, s,
-                           FragMats{Gh, nullptr}, r, v, sv, t, g, ks, kb.P1, (int)face_grid(g),
-                           kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
+        if (is_tiled(g))
+            hipLaunchKernelGGL((k_bicg_k2<K, true>), dim3(face_grid(g)), dim3(256), 0, s,
+                               FragMats{Gh, nullptr}, r, v, sv, t, g, ks, kb.P1,
+                               (int)face_grid(g), kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
+        else
+            hipLaunchKernelGGL((k_bicg_k2<K, false>), dim3(face_grid(g)), dim3(256), 0, s,
+                               FragMats{Gh, nullptr}, r, v, sv, t, g, ks, kb.P1,
+                               (int)face_grid(g), kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
         return hipGetLastError();
     }
 };
@@ -1013,10 +1262,14 @@ template <int K> struct RunDiag {
 
 }  // namespace
 
+bool is_tiled(const Geom &g) { return g.nx % kTX == 0 && g.ny % kTY == 0; }
+
 unsigned face_grid(const Geom &g) {
-    // element tiles of 64; a multiple of 8 blocks (when there are enough
-    // tiles) so that every XCD gets the same number of blocks
-    const unsigned n = std::min<unsigned>(grid1(g.nel, 64), kMaxGrid);
+    // 64-element tiles (16 x 4 when the mesh is tiled, else 64 consecutive
+    // elements); a multiple of 8 blocks when there are enough tiles, so that
+    // every XCD gets the same number of blocks
+    const unsigned t = is_tiled(g) ? (unsigned)((g.nx / kTX) * (g.ny / kTY)) : grid1(g.nel, 64);
+    const unsigned n = std::min<unsigned>(t, kMaxGrid);
     return n >= 8 ? n & ~7u : n;
 }
 

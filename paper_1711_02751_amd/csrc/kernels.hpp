@@ -49,6 +49,7 @@ struct KrylovBufs {
 // Capped grid sizes of the face-tile kernels, the elementwise Krylov
 // kernels and the diagnostics kernel; partial arrays hold this many blocks.
 struct Geom;
+bool is_tiled(const Geom &g);   // mesh is a whole number of 16 x 4 tiles
 unsigned face_grid(const Geom &g);
 unsigned elem_grid(const Geom &g);
 unsigned diag_grid(const Geom &g);
