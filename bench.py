@@ -59,6 +59,31 @@ def algorithmic_cost(name, wl, n_dof):
     return table.get(name)
 
 
+KERNEL_SYMBOL = {"nl_residual": "k_nl", "combine": "k_combine", "local_apply": "k_local_apply",
+                 "trace_rhs": "k_trace_rhs", "trace_residual": "k_trace_residual",
+                 "bicg_init": "k_bicg_init", "bicg_k1": "k_bicg_k1", "bicg_k2": "k_bicg_k2",
+                 "bicg_k3": "k_bicg_k3", "axpy": "k_axpy", "recover": "k_recover"}
+
+
+def measured_traffic(kernel_class, wl_name):
+    """HBM bytes per dispatch from the committed FETCH_SIZE / WRITE_SIZE
+    profile of this workload, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl_name}.json")
+    src = os.path.join(ROOT, "paper_1711_02751_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if d.get("kernels_hip_sha256") != sha:
+        return None
+    rec = d["per_dispatch"].get(KERNEL_SYMBOL.get(kernel_class, ""))
+    return None if rec is None else rec["hbm_bytes"]
+
+
 def cpu_baseline(wl_name, seconds=15.0):
     """FP64 oracle on a bounded sample: the same recipe (physics, degree,
     dt = 5 dx_min, seed) on a 64 x 64 mesh, single-threaded, timed after its
@@ -96,6 +121,8 @@ def main():
     ap.add_argument("--workload", default="bump_256x256_k4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs and "
@@ -122,6 +149,14 @@ def main():
     log(f"[bench] state set: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {args.warmup}")
     S.step(args.warmup)
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)     # reads and writes calib_copy_mib MiB once
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+        del src, dst
 
     # short all-classes pass to find the dominant kernel
     S.profile(-1)
@@ -159,7 +194,7 @@ def main():
         roof = {"bound": "alu", "achieved": nflops / avg_s / 1e12,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dominant, wl.name)
     roof["kernel"] = dominant
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = nl
