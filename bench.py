@@ -21,22 +21,29 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "DOF-updates/s per IMEX step, mixed vs FP64 at fixed L2 err; HBM GB/s, MFMA %"
 HBM_PEAK_GBS = 8000.0
-FP64_VALU_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6          # FP64 vector and matrix-core peak
+FP32_MFMA_PEAK_TFLOPS = 157.3    # dense FP32 matrix-core peak
+MIXED_KRYLOV_RTOL = 1e-6
+MIXED_REFINE_RTOL = 1e-10
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_cost(name, wl, n_dof):
+def algorithmic_cost(name, wl, n_dof, isz=8):
     """(bytes, flops) one launch of a kernel class must move / compute:
-    every input read once and every output written once, FP64 values."""
+    every input read once and every output written once.  FP64 state and
+    trace right-hand sides; `isz` bytes per value of the inner-solve vectors
+    (8 FP64, 4 FP32)."""
     K = wl.k + 1
     nel = wl.n * wl.n
     N = n_dof
@@ -45,16 +52,19 @@ def algorithmic_cost(name, wl, n_dof):
     b3 = 3 * K
     table = {
         # read r, p, v, rh; write p, v
-        "bicg_k1": (6 * T * 8, 2.0 * 7 * b3 * b3 * nfaces),
+        "bicg_k1": (6 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
         # read r, v; write s, t
-        "bicg_k2": (4 * T * 8, 2.0 * 7 * b3 * b3 * nfaces),
+        "bicg_k2": (4 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
         # read d, p, s, t, rh; write d, r
-        "bicg_k3": (7 * T * 8, 8.0 * T),
-        "trace_residual": (5 * T * 8, 4.0 * 7 * b3 * b3 * nfaces),
+        "bicg_k3": (7 * T * isz, 8.0 * T),
+        # read x, g, ghat (FP64); write r (FP64), rin (inner)
+        "trace_residual": (4 * T * 8 + T * isz, 4.0 * 7 * b3 * b3 * nfaces),
         "local_apply": (2 * N * 8, 2.0 * (3 * K * K) ** 2 * nel),
         "recover": ((2 * N + T) * 8, 2.0 * (3 * K * K) * 12 * K * nel),
         "trace_rhs": (4 * T * 8, 2.0 * b3 * b3 * nfaces),
-        "axpy": (3 * T * 8, 2.0 * T),
+        "axpy": (2 * T * 8 + T * isz, 2.0 * T),
+        # read Q, write NL and the combination, read about 2.5 inputs on average
+        "nl_residual": (5.5 * N * 8, 60.0 * N),
     }
     return table.get(name)
 
@@ -65,12 +75,12 @@ KERNEL_SYMBOL = {"nl_residual": "k_nl", "combine": "k_combine", "local_apply": "
                  "bicg_k3": "k_bicg_k3", "axpy": "k_axpy", "recover": "k_recover"}
 
 
-def measured_traffic(kernel_class, wl_name):
+def measured_traffic(kernel_class, wl_name, precision="fp64"):
     """HBM bytes per dispatch from the committed FETCH_SIZE / WRITE_SIZE
     profile of this workload, or None when the kernel source has changed
     since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{wl_name}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl_name}_{precision}.json")
     src = os.path.join(ROOT, "paper_1711_02751_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
@@ -113,12 +123,90 @@ def cpu_baseline(wl_name, seconds=15.0):
             "seconds": el}
 
 
+def run_path(m, wl, precision, steps, warmup):
+    """Run one precision path; returns (result dict, final state, solver)."""
+    import torch
+    mixed = precision == "mixed"
+    cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
+                           dt=wl.dt, scheme=m.SCHEME_ARS232,
+                           physics=m.PHYSICS_NONLINEAR if wl.nonlinear else m.PHYSICS_LINEARIZED,
+                           precision=m.PREC_MIXED if mixed else m.PREC_FP64)
+    if mixed:
+        cfg.krylov_rtol = MIXED_KRYLOV_RTOL
+        cfg.refine_rtol = MIXED_REFINE_RTOL
+        cfg.refine_max = 8
+    S = m.Solver(cfg)
+    x, y = S.nodes()
+    h, hu, hv = wl.initial_state(x, y)
+    S.set_state(h, hu, hv)
+    n_dof = 3 * S.n_nodes
+    log(f"[bench] {precision}: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {warmup}")
+    S.step(warmup)
+    torch.cuda.synchronize()
+    # short all-classes pass to find the dominant kernel
+    S.profile(-1)
+    S.step(2)
+    per = {}
+    for name in m.KERNELS:
+        n, ms = S.profile_read(name)
+        if n:
+            per[name] = {"launches": n, "total_ms": ms, "avg_us": 1000.0 * ms / n}
+    dominant = max(per, key=lambda k: per[k]["total_ms"])
+    log(f"[bench] {precision}: dominant kernel class {dominant} "
+        f"({per[dominant]['avg_us']:.2f} us avg over {per[dominant]['launches']} launches)")
+    # the timed run restarts from the initial state
+    S.set_state(h, hu, hv)
+    d0 = S.diag()
+    S.profile(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    el = t1 - t0
+    nl, ms = S.profile_read(dominant)
+    d1 = S.diag()
+    state = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
+    value = n_dof * steps / el
+    log(f"[bench] {precision}: {steps} steps in {el:.3f} s -> {value:.4g} DOF-updates/s")
+    isz = 4 if mixed else 8
+    avg_s = ms / 1000.0 / nl
+    nbytes, nflops = algorithmic_cost(dominant, wl, n_dof, isz)
+    matrix = dominant in ("bicg_k1", "bicg_k2", "trace_residual")
+    fpeak = (FP32_MFMA_PEAK_TFLOPS if mixed and dominant != "trace_residual"
+             else FP64_PEAK_TFLOPS)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = nflops / (fpeak * 1e12)
+    if t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma" if matrix else "alu", "achieved": nflops / avg_s / 1e12,
+                "peak": fpeak, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(dominant, wl.name, precision)
+    roof["kernel"] = dominant
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = nl
+    roof["algorithmic_bytes_per_launch"] = nbytes
+    roof["algorithmic_flops_per_launch"] = nflops
+    iters = ((d1["krylov_iters"] - d0["krylov_iters"])
+             / max(1, d1["stage_solves"] - d0["stage_solves"]))
+    res = {"value": value, "ms_per_step": 1000.0 * el / steps, "roofline": roof,
+           "krylov_iters_per_stage": iters, "max_trace_relres": d1["max_relres"],
+           "kernels": per, "n_dof": n_dof, "n_trace": S.n_trace}
+    S.close()
+    return res, state
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bump_256x256_k4")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed",
+                    help="headline path; the FP64 path is always measured too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -136,99 +224,51 @@ def main():
 
     wl = W.WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
-                           dt=wl.dt, scheme=m.SCHEME_ARS232,
-                           physics=m.PHYSICS_NONLINEAR if wl.nonlinear else m.PHYSICS_LINEARIZED,
-                           precision=m.PREC_FP64)
     log(f"[bench] workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
-    S = m.Solver(cfg)
-    x, y = S.nodes()
-    h, hu, hv = wl.initial_state(x, y)
-    S.set_state(h, hu, hv)
-    n_dof = 3 * S.n_nodes
-    log(f"[bench] state set: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {args.warmup}")
-    S.step(args.warmup)
-    torch.cuda.synchronize()
-    if args.calib_copy_mib > 0:
-        n = args.calib_copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.neg(src, out=dst)     # reads and writes calib_copy_mib MiB once
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
-        del src, dst
-
-    # short all-classes pass to find the dominant kernel
-    S.profile(-1)
-    S.step(2)
-    per = {}
-    for name in m.KERNELS:
-        n, ms = S.profile_read(name)
-        if n:
-            per[name] = {"launches": n, "total_ms": ms, "avg_us": 1000.0 * ms / n}
-    dominant = max(per, key=lambda k: per[k]["total_ms"])
-    log(f"[bench] dominant kernel class: {dominant} "
-        f"({per[dominant]['avg_us']:.2f} us avg over {per[dominant]['launches']} launches)")
-
-    d0 = S.diag()
-    S.profile(dominant)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    S.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    el = t1 - t0
-    nl, ms = S.profile_read(dominant)
-    d1 = S.diag()
-    value = n_dof * args.steps / el
-    log(f"[bench] {args.steps} steps in {el:.3f} s -> {value:.4g} DOF-updates/s")
-
-    avg_s = ms / 1000.0 / nl
-    nbytes, nflops = algorithmic_cost(dominant, wl, n_dof)
-    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-    t_alu = nflops / (FP64_VALU_PEAK_TFLOPS * 1e12)
-    if t_hbm >= t_alu:
-        roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
+    fp64, s64 = run_path(m, wl, "fp64", args.steps, args.warmup)
+    if args.precision == "fp64":
+        head, smx = fp64, None
     else:
-        roof = {"bound": "alu", "achieved": nflops / avg_s / 1e12,
-                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dominant, wl.name)
-    roof["kernel"] = dominant
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["launches"] = nl
-    roof["algorithmic_bytes_per_launch"] = nbytes
-    roof["algorithmic_flops_per_launch"] = nflops
-
-    iters = (d1["krylov_iters"] - d0["krylov_iters"]) / max(1, d1["stage_solves"] - d0["stage_solves"])
+        head, smx = run_path(m, wl, "mixed", args.steps, args.warmup)
+    from oracle import swe   # only for the mass-weighted norm of the comparison
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "DOF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1000.0 * el / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if smx is None else "f64+f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "mesh": f"{wl.n}x{wl.n}", "degree": wl.k,
-                   "n_dof": n_dof, "n_trace": S.n_trace, "dt": wl.dt, "scheme": "ARS232",
-                   "precision": "fp64", "parallelism": "single GPU"},
-        "roofline": roof,
-        "krylov_iters_per_stage": iters,
-        "max_trace_relres": d1["max_relres"],
-        "kernels": per,
+                   "n_dof": head["n_dof"], "n_trace": head["n_trace"], "dt": wl.dt,
+                   "scheme": "ARS232",
+                   "precision": "fp64" if smx is None else
+                   f"mixed (FP32 inner Krylov rtol {MIXED_KRYLOV_RTOL:g}, FP64 refinement to "
+                   f"{MIXED_REFINE_RTOL:g})",
+                   "parallelism": "single GPU"},
+        "roofline": head["roofline"],
+        "krylov_iters_per_stage": head["krylov_iters_per_stage"],
+        "max_trace_relres": head["max_trace_relres"],
+        "kernels": head["kernels"],
     }
+    if smx is not None:
+        mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
+        err = swe.rel_l2(mesh, smx.reshape(mesh.shape), s64.reshape(mesh.shape))
+        out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+                       "roofline": fp64["roofline"],
+                       "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
+        out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]
+        out["mixed_rel_l2_vs_fp64"] = [float(e) for e in err]
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(wl.name, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
-    S.close()
     print(json.dumps(out))
 
 

@@ -63,9 +63,11 @@ extern "C" {
 
 /* precision of the step */
 #define IMEXHDG_PREC_FP64   0  /* everything in FP64                        */
-#define IMEXHDG_PREC_MIXED  1  /* FP32 residual, local solves and inner
-                                  Krylov; FP64 state, trace residual,
-                                  iterative refinement and diagnostics      */
+#define IMEXHDG_PREC_MIXED  1  /* FP32 inner Krylov solve of the trace
+                                  system (FP32 matrix cores); FP64 state,
+                                  DG residuals, local solves, trace
+                                  residual, iterative refinement, mass and
+                                  energy sums                               */
 
 /* variables of host state arrays */
 #define IMEXHDG_VARS_DEPTH       0  /* (h, hu, hv): depth and momenta        */
@@ -80,7 +82,8 @@ typedef struct imexhdg_config {
     int32_t scheme;          /* IMEXHDG_SCHEME_*                           */
     int32_t physics;         /* IMEXHDG_PHYSICS_*                          */
     int32_t precision;       /* IMEXHDG_PREC_*                             */
-    double  krylov_rtol;     /* inner Krylov tolerance (preconditioned)    */
+    double  krylov_rtol;     /* inner Krylov tolerance (preconditioned);
+                                at least 1e-6 with IMEXHDG_PREC_MIXED      */
     int32_t krylov_max_iter; /* inner iteration budget per solve           */
     int32_t check_every;     /* iterations between convergence checks      */
     double  refine_rtol;     /* FP64 true-residual tolerance ||g-Gx||/||g|| */

@@ -101,9 +101,12 @@ struct imexhdg_ctx {
     // device buffers
     double *q = nullptr, *Z = nullptr, *tmp = nullptr;
     std::vector<double *> NLb, Qb, Rb;
-    double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr, *rin = nullptr;
-    double *kr = nullptr, *krh = nullptr, *kp[2] = {nullptr, nullptr},
-           *kv[2] = {nullptr, nullptr}, *ks_ = nullptr, *kt = nullptr, *kd = nullptr;
+    double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr;
+    // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
+    bool mixed = false;
+    void *rin = nullptr, *kr = nullptr, *krh = nullptr, *kp[2] = {nullptr, nullptr},
+         *kv[2] = {nullptr, nullptr}, *ks_ = nullptr, *kt = nullptr, *kd = nullptr;
+    float *dGhf = nullptr;   // FP32 packed Ghat fragments for the inner solve
     double *dAinv = nullptr, *dW = nullptr, *dG = nullptr, *dGh = nullptr, *dPx = nullptr,
            *dPy = nullptr;
     KrylovState *ks = nullptr;
@@ -183,9 +186,12 @@ Layout layout_of(const imexhdg_config &c) {
     size_t t = 0;
     t += 3 * align256(L.N * 8);                       // q, Z, tmp
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
-    t += 14 * align256(L.T * 8);                       // trace vectors
+    const size_t isz = (c.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
+    t += 4 * align256(L.T * 8);                        // FP64 trace vectors
+    t += 10 * align256(L.T * isz);                     // inner-solve vectors
     t += align256(L.n_loc * L.n_loc * 8) + align256(L.n_loc * L.n_tr * 8);
     t += 2 * align256(frag_count((int)K) * 8) + 2 * align256(9 * K * K * 8);
+    t += align256(frag_count((int)K) * 4);             // FP32 Ghat fragments
     t += 5 * align256(kPartStride * 8) + align256(5 * kPartStride * 8);
     t += align256(sizeof(KrylovState));
     L.total = t;
@@ -207,8 +213,8 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "unknown scheme");
     if (c->physics != IMEXHDG_PHYSICS_LINEARIZED && c->physics != IMEXHDG_PHYSICS_NONLINEAR)
         return fail(IMEXHDG_E_INVAL, "unknown physics");
-    if (c->precision != IMEXHDG_PREC_FP64)
-        return fail(IMEXHDG_E_INVAL, "precision not supported by this build");
+    if (c->precision != IMEXHDG_PREC_FP64 && c->precision != IMEXHDG_PREC_MIXED)
+        return fail(IMEXHDG_E_INVAL, "unknown precision");
     if (!(c->krylov_rtol > 0) || !(c->krylov_rtol < 1))
         return fail(IMEXHDG_E_INVAL, "krylov_rtol must be in (0, 1)");
     if (!(c->refine_rtol > 0) || !(c->refine_rtol < 1))
@@ -355,6 +361,48 @@ int read_partials(imexhdg_ctx *c, int nq, unsigned n, double *out) {
     return IMEXHDG_OK;
 }
 
+// Inner BiCGStab on Ghat d = rin in precision T, d0 = 0.  The operator is
+// the same for every stage and step, so the first sweep's iteration count
+// is predictable: run one less than last time before the first convergence
+// check, then check every two iterations (a converged solve turns the
+// remaining launches into no-ops, so few are wasted).
+template <typename T>
+int inner_solve(imexhdg_ctx *c, const T *Gh, double tol2, int sweep) {
+    const imexhdg_config &cf = c->cfg;
+    const Geom &g = c->geom;
+    T *rin = (T *)c->rin, *r = (T *)c->kr, *rh = (T *)c->krh, *sv = (T *)c->ks_,
+      *t = (T *)c->kt, *d = (T *)c->kd;
+    T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
+    int rc;
+    LAUNCH(IMEXHDG_K_BICG_INIT,
+           launch_bicg_init(g, (const T *)rin, r, rh, p[0], v[0], d, c->ks, tol2, c->kb, c->stream));
+    int par = 0;     // p, v of the current iteration live in p[par], v[par]
+    LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par],
+                                             v[1 - par], c->ks, c->kb, c->stream));
+    par = 1 - par;
+    int done = 0;
+    int chunk = (sweep == 0 && c->iter_pred > 1) ? c->iter_pred - 1 : cf.check_every;
+    while (done < cf.krylov_max_iter) {
+        const int n = std::min(chunk, cf.krylov_max_iter - done);
+        chunk = std::min(2, cf.check_every);
+        for (int it = 0; it < n; ++it) {
+            LAUNCH(IMEXHDG_K_BICG_K2,
+                   launch_bicg_k2(g, Gh, r, v[par], sv, t, c->ks, c->kb, c->stream));
+            LAUNCH(IMEXHDG_K_BICG_K3,
+                   launch_bicg_k3(g, d, r, rh, p[par], sv, t, c->ks, c->kb, c->stream));
+            LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par],
+                                                     v[1 - par], c->ks, c->kb, c->stream));
+            par = 1 - par;
+        }
+        done += n;
+        if ((rc = sync_read_ks(c))) return rc;
+        if (c->hks->conv) break;
+    }
+    if (sweep == 0) c->iter_pred = c->hks->iters;
+    LAUNCH(IMEXHDG_K_AXPY, launch_axpy(c->x, (const T *)d, 1.0, c->T, c->stream));
+    return IMEXHDG_OK;
+}
+
 // Trace solve by FP64 iterative refinement around block-Jacobi BiCGStab.
 // x holds the initial guess and receives the solution.  Each sweep: FP64
 // residual r = g - G x (and its preconditioned form rin), stop if
@@ -367,8 +415,12 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
     for (int sweep = 0;; ++sweep) {
         int rc;
         LAUNCH(IMEXHDG_K_TRACE_RESID,
-               launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64, c->rin,
-                                     c->dpart, kPartStride, c->stream));
+               c->mixed ? launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
+                                                (float *)c->rin, c->dpart, kPartStride,
+                                                c->stream)
+                        : launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
+                                                (double *)c->rin, c->dpart, kPartStride,
+                                                c->stream));
         double nrm[4];
         if ((rc = read_partials(c, 4, face_grid(g), nrm))) return rc;
         const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
@@ -381,42 +433,15 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
         c->sweeps += 1;
         // inner tolerance: krylov_rtol relative to the sweep's right-hand
         // side, floored at 0.1 refine_rtol relative to ||ghat||
+        // (an FP32 inner solve is held to at least 1e-6, its attainable
+        // accuracy; the FP64 sweeps recover the rest)
         const double fl = 0.1 * cf.refine_rtol;
-        const double tol2 = std::max(cf.krylov_rtol * cf.krylov_rtol * rinrin, fl * fl * ghh);
-        LAUNCH(IMEXHDG_K_BICG_INIT, launch_bicg_init(g, c->rin, c->kr, c->krh, c->kp[0], c->kv[0],
-                                                     c->kd, c->ks, tol2, c->kb, c->stream));
-        int par = 0;     // p, v of the current iteration live in kp[par], kv[par]
-        LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, c->dGh, c->kr, c->krh, c->kp[par], c->kv[par],
-                                                 c->kp[1 - par], c->kv[1 - par], c->ks, c->kb,
-                                                 c->stream));
-        par = 1 - par;
-        // The operator is the same for every stage and step, so the first
-        // sweep's iteration count is predictable: run one less than last
-        // time before the first convergence check, then check every two
-        // iterations (a converged solve turns the remaining launches into
-        // no-ops, so few are wasted).
-        int done = 0;
-        int chunk = (sweep == 0 && c->iter_pred > 1) ? c->iter_pred - 1 : cf.check_every;
-        while (done < cf.krylov_max_iter) {
-            const int n = std::min(chunk, cf.krylov_max_iter - done);
-            chunk = std::min(2, cf.check_every);
-            for (int it = 0; it < n; ++it) {
-                LAUNCH(IMEXHDG_K_BICG_K2, launch_bicg_k2(g, c->dGh, c->kr, c->kv[par], c->ks_,
-                                                         c->kt, c->ks, c->kb, c->stream));
-                LAUNCH(IMEXHDG_K_BICG_K3, launch_bicg_k3(g, c->kd, c->kr, c->krh, c->kp[par],
-                                                         c->ks_, c->kt, c->ks, c->kb, c->stream));
-                LAUNCH(IMEXHDG_K_BICG_K1,
-                       launch_bicg_k1(g, c->dGh, c->kr, c->krh, c->kp[par], c->kv[par],
-                                      c->kp[1 - par], c->kv[1 - par], c->ks, c->kb, c->stream));
-                par = 1 - par;
-            }
-            done += n;
-            if ((rc = sync_read_ks(c))) return rc;
-            if (c->hks->conv) break;
-        }
+        const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
+        const double tol2 = std::max(irt * irt * rinrin, fl * fl * ghh);
+        rc = c->mixed ? inner_solve<float>(c, c->dGhf, tol2, sweep)
+                      : inner_solve<double>(c, c->dGh, tol2, sweep);
+        if (rc) return rc;
         iters += c->hks->iters;
-        if (sweep == 0) c->iter_pred = c->hks->iters;
-        LAUNCH(IMEXHDG_K_AXPY, launch_axpy(c->x, c->kd, 1.0, c->T, c->stream));
     }
     c->kiters += iters;
     c->solves += 1;
@@ -582,14 +607,17 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
     for (int i = 0; i < L.s; ++i) c->NLb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
-    double **tv[14] = {&c->x,     &c->gv,    &c->gh,    &c->r64, &c->rin,
-                       &c->kr,    &c->krh,   &c->kp[0], &c->kp[1], &c->kv[0],
-                       &c->kv[1], &c->ks_,   &c->kt,    &c->kd};
+    c->mixed = cfg->precision == IMEXHDG_PREC_MIXED;
+    double **tv[4] = {&c->x, &c->gv, &c->gh, &c->r64};
     for (double **p : tv) *p = (double *)take(L.T * 8);
+    void **iv[10] = {&c->rin, &c->kr, &c->krh, &c->kp[0], &c->kp[1],
+                     &c->kv[0], &c->kv[1], &c->ks_, &c->kt, &c->kd};
+    for (void **p : iv) *p = take(L.T * (c->mixed ? 4 : 8));
     c->dAinv = (double *)take(L.n_loc * L.n_loc * 8);
     c->dW = (double *)take(L.n_loc * L.n_tr * 8);
     c->dG = (double *)take(frag_count(K) * 8);
     c->dGh = (double *)take(frag_count(K) * 8);
+    c->dGhf = (float *)take(frag_count(K) * 4);
     c->dPx = (double *)take(9 * K * K * 8);
     c->dPy = (double *)take(9 * K * K * 8);
     c->kb.P1 = (double *)take(kPartStride * 8);
@@ -607,10 +635,12 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
     const StageOperators &op = c->op;
     const std::vector<double> G = pack_frags(op.Gx, op.Gy, K);
     const std::vector<double> Gh = pack_frags(op.Gxh, op.Gyh, K);
+    const std::vector<float> Ghf(Gh.begin(), Gh.end());
     auto up = [&](double *d, const std::vector<double> &h) {
         return hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream);
     };
     if (up(c->dAinv, op.Ainv) || up(c->dW, op.W) || up(c->dG, G) || up(c->dGh, Gh) ||
+        hipMemcpyAsync(c->dGhf, Ghf.data(), Ghf.size() * 4, hipMemcpyHostToDevice, c->stream) ||
         up(c->dPx, op.Pxinv) || up(c->dPy, op.Pyinv) ||
         hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
         hipMemsetAsync(c->q, 0, L.N * 8, c->stream) ||

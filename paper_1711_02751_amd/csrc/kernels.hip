@@ -529,8 +529,28 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
 // matrix, host-packed per lane), k = (slot, c', j') of the gathered traces,
 // columns = 16 faces per wave.  Operand layout of the instruction: lane l
 // holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element r of
-// lane l is D[4 r + l / 16][l % 16].
+// lane l is D[4 r + l / 16][l % 16] for FP64 (see MfmaT for FP32).
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Matrix-core 16x16x4 step per element type.  A and B operand layouts are
+// the same for FP64 and FP32; the accumulator rows differ: lane l, element
+// r holds row 4 r + l/16 (FP64) or 4 (l/16) + r (FP32), column l % 16.
+template <typename T> struct MfmaT;
+template <> struct MfmaT<double> {
+    typedef v4d v4;
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct MfmaT<float> {
+    typedef v4f v4;
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 template <int K> struct MF {
     static constexpr int B3 = 3 * K;
@@ -557,11 +577,11 @@ __device__ __forceinline__ size_t frag_off(int d, int mb, int kk, int lane, int 
 // multiple of 4, so a k step never straddles two slots); the B values of
 // slot s + 1 are loaded before the matrix-core work of slot s is issued.
 // load_b(set, slot, o) returns the B value at trace offset o.
-template <int K, int NM, typename LoadB>
-__device__ __forceinline__ void mfma_rows2(const double *__restrict__ const *frags,
+template <int K, int NM, typename T, typename LoadB>
+__device__ __forceinline__ void mfma_rows2(const T *__restrict__ const *frags,
                                            const int (*dirs)[7], const int (*idx)[7],
                                            size_t nel, int lane, LoadB load_b,
-                                           v4d (*acc)[NM][MF<K>::NMB]) {
+                                           typename MfmaT<T>::v4 (*acc)[NM][MF<K>::NMB]) {
     constexpr int B3 = MF<K>::B3, KS = MF<K>::KS, NKK = MF<K>::NKK, NMB = MF<K>::NMB;
     const size_t TT = (size_t)B3 * nel;
     const int q = lane >> 4;
@@ -570,10 +590,10 @@ __device__ __forceinline__ void mfma_rows2(const double *__restrict__ const *fra
 #pragma unroll
         for (int m = 0; m < NM; ++m)
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = typename MfmaT<T>::v4{0, 0, 0, 0};
     // slot s is uniform over the wave: the switch selects its neighbour face
     // with scalar branches (no indexed register arrays)
-    auto fetch = [&](int s, double (&dst)[KS][2]) {
+    auto fetch = [&](int s, T (&dst)[KS][2]) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
             int dd = dirs[f][0], ii = idx[f][0];
@@ -590,11 +610,11 @@ __device__ __forceinline__ void mfma_rows2(const double *__restrict__ const *fra
 #pragma unroll
             for (int u = 0; u < KS; ++u) {
                 const int cj = 4 * u + q;
-                dst[u][f] = (cj < B3) ? load_b(f, s, base + (size_t)cj * nel) : 0.0;
+                dst[u][f] = (cj < B3) ? load_b(f, s, base + (size_t)cj * nel) : T(0);
             }
         }
     };
-    double cur[KS][2], nxt[KS][2];
+    T cur[KS][2], nxt[KS][2];
     fetch(0, cur);
 #pragma unroll 1
     for (int s = 0; s < 7; ++s) {
@@ -608,9 +628,9 @@ __device__ __forceinline__ void mfma_rows2(const double *__restrict__ const *fra
                 for (int m = 0; m < NM; ++m)
 #pragma unroll
                     for (int mb = 0; mb < NMB; ++mb)
-                        acc[f][m][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        acc[f][m][mb] = MfmaT<T>::mma(
                             frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], cur[u][f],
-                            acc[f][m][mb], 0, 0, 0);
+                            acc[f][m][mb]);
         }
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
@@ -638,9 +658,10 @@ __device__ __forceinline__ TileWalk tile_walk(int ntiles) {
     return TileWalk{begin + local, per, end};
 }
 
-struct FragMats {
-    const double *A0, *A1;   // packed fragments of one or two matrices
+template <typename T> struct FragMatsT {
+    const T *A0, *A1;        // packed fragments of one or two matrices
 };
+typedef FragMatsT<double> FragMats;
 
 // Wave-level face index: element tile t covers 64 elements, wave w of the
 // block takes elements 16 w .. 16 w + 15 of it; face set 0 is their x-faces
@@ -723,12 +744,12 @@ __device__ __forceinline__ int slot_lds(int set, int s, int lx, int ly, int NX, 
 // Stage the tile: sB[cj][f] = stage(o, own) for every staged face f and row
 // cj (c' K + j'); then the wave's two row-block sets (x- and y-faces of its
 // 16 elements) by the matrix cores from LDS.
-template <int K, int NM, typename Stage>
-__device__ __forceinline__ void tiled_rows(const double *__restrict__ const *frags, int tile,
-                                           const Geom &g, double (*sB)[Tile<K>::NF],
-                                           Stage stage, v4d (*acc)[NM][MF<K>::NMB]) {
-    using T = Tile<K>;
-    constexpr int B3 = T::B3, NF = T::NF, KS = MF<K>::KS, NKK = MF<K>::NKK,
+template <int K, int NM, typename T, typename Stage>
+__device__ __forceinline__ void tiled_rows(const T *__restrict__ const *frags, int tile,
+                                           const Geom &g, T (*sB)[Tile<K>::NF], Stage stage,
+                                           typename MfmaT<T>::v4 (*acc)[NM][MF<K>::NMB]) {
+    using TL = Tile<K>;
+    constexpr int B3 = TL::B3, NF = TL::NF, KS = MF<K>::KS, NKK = MF<K>::NKK,
                   NMB = MF<K>::NMB;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tpr = g.nx / kTX;
@@ -739,7 +760,7 @@ __device__ __forceinline__ void tiled_rows(const double *__restrict__ const *fra
         const int cj = v / NF, f = v - cj * NF;
         int dir, elem;
         bool own;
-        staged_face(f, ex0, ey0, g.nx, g.ny, T::NX, T::XC, T::YC, dir, elem, own);
+        staged_face(f, ex0, ey0, g.nx, g.ny, TL::NX, TL::XC, TL::YC, dir, elem, own);
         sB[cj][f] = stage((size_t)dir * TT + (size_t)cj * nel + elem, own);
     }
     __syncthreads();
@@ -749,25 +770,24 @@ __device__ __forceinline__ void tiled_rows(const double *__restrict__ const *fra
 #pragma unroll
         for (int m = 0; m < NM; ++m)
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = typename MfmaT<T>::v4{0, 0, 0, 0};
 #pragma unroll 1
     for (int s = 0; s < 7; ++s) {
         int li[2];
-        li[0] = slot_lds(0, s, lx, w, T::NX, T::XC, T::YC);
-        li[1] = slot_lds(1, s, lx, w, T::NX, T::XC, T::YC);
+        li[0] = slot_lds(0, s, lx, w, TL::NX, TL::XC, TL::YC);
+        li[1] = slot_lds(1, s, lx, w, TL::NX, TL::XC, TL::YC);
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
             const int cj = 4 * u + q, kk = s * KS + u;
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                const double b = (cj < B3) ? sB[cj][li[f]] : 0.0;
+                const T b = (cj < B3) ? sB[cj][li[f]] : T(0);
 #pragma unroll
                 for (int m = 0; m < NM; ++m)
 #pragma unroll
                     for (int mb = 0; mb < NMB; ++mb)
-                        acc[f][m][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                            frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], b, acc[f][m][mb],
-                            0, 0, 0);
+                        acc[f][m][mb] = MfmaT<T>::mma(
+                            frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], b, acc[f][m][mb]);
             }
         }
     }
@@ -788,11 +808,12 @@ __device__ __forceinline__ int own_lds(int set, int lx, int ly) {
 
 // FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
 // partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
-template <int K, bool TILED>
+template <int K, bool TILED, typename RT>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
     const FragMats A, const double *__restrict__ x, const double *__restrict__ gv,
     const double *__restrict__ gh, const Geom g, double *__restrict__ r,
-    double *__restrict__ rin, double *partials, int stride) {
+    RT *__restrict__ rin, double *partials, int stride) {
+    using T = double;
     constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const size_t nel = g.nel, TT = (size_t)B3 * nel;
@@ -814,13 +835,13 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
                 for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
                     for (int e4 = 0; e4 < 4; ++e4) {
-                        const int row = 16 * mb + 4 * e4 + q;
+                        const int row = 16 * mb + MfmaT<T>::row(lane, e4);
                         if (row < B3) {
                             const size_t o = f * TT + (size_t)row * nel + e;
                             const double rr = gv[o] - acc[f][0][mb][e4];
                             const double ri = gh[o] - acc[f][1][mb][e4];
                             r[o] = rr;
-                            rin[o] = ri;
+                            rin[o] = (RT)ri;
                             acc4[0] += rr * rr;
                             acc4[1] += gv[o] * gv[o];
                             acc4[2] += gh[o] * gh[o];
@@ -845,13 +866,13 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
         for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = 16 * mb + 4 * e + (lane >> 4);
+                const int row = 16 * mb + MfmaT<T>::row(lane, e);
                 if (row < B3 && fi[f].active) {
                     const size_t o = f * TT + (size_t)row * nel + fi[f].f;
                     const double rr = gv[o] - acc[f][0][mb][e];
                     const double ri = gh[o] - acc[f][1][mb][e];
                     r[o] = rr;
-                    rin[o] = ri;
+                    rin[o] = (RT)ri;
                     acc4[0] += rr * rr;
                     acc4[1] += gv[o] * gv[o];
                     acc4[2] += gh[o] * gh[o];
@@ -875,15 +896,16 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
 // p and v are double buffered because K1 reads the old values at
 // neighbouring faces while writing the new ones.  Convergence (r.r <= tol2)
 // is detected at the start of K1; every later kernel returns at entry.
-__global__ void k_bicg_init(const double *__restrict__ rin, double *__restrict__ r,
-                            double *__restrict__ rh, double *__restrict__ p,
-                            double *__restrict__ v, double *__restrict__ d, size_t n,
+template <typename T>
+__global__ void k_bicg_init(const T *__restrict__ rin, T *__restrict__ r,
+                            T *__restrict__ rh, T *__restrict__ p,
+                            T *__restrict__ v, T *__restrict__ d, size_t n,
                             KrylovState *ks, double tol2, double *P3, int stride) {
     double acc[2] = {0.0, 0.0};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const double x = rin[i];
-        r[i] = x; rh[i] = x; p[i] = 0.0; v[i] = 0.0; d[i] = 0.0;
+        r[i] = (T)x; rh[i] = (T)x; p[i] = T(0); v[i] = T(0); d[i] = T(0);
         acc[0] += x * x;
         acc[1] += x * x;
     }
@@ -900,13 +922,14 @@ __global__ void k_bicg_init(const double *__restrict__ rin, double *__restrict__
     }
 }
 
-template <int K, bool TILED>
-__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats A, const double *__restrict__ r,
-                                                 const double *__restrict__ rh,
-                                                 const double *__restrict__ pin,
-                                                 const double *__restrict__ vin,
-                                                 double *__restrict__ pout,
-                                                 double *__restrict__ vout, const Geom g,
+template <int K, bool TILED, typename T>
+__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMatsT<T> A,
+                                                 const T *__restrict__ r,
+                                                 const T *__restrict__ rh,
+                                                 const T *__restrict__ pin,
+                                                 const T *__restrict__ vin,
+                                                 T *__restrict__ pout,
+                                                 T *__restrict__ vout, const Geom g,
                                                  KrylovState *ks, const double *P3, int n3,
                                                  double *P1, int stride) {
     constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
@@ -927,18 +950,18 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const size_t nel = g.nel, TT = (size_t)B3 * nel;
     const int ntiles = (g.nel + 63) / 64;
-    const double *fr[1] = {A.A0};
+    const T *fr[1] = {A.A0};
     double acc1[1] = {0.0};
     if constexpr (TILED) {
-        __shared__ double sB[B3][Tile<K>::NF];
+        __shared__ T sB[B3][Tile<K>::NF];
         const int nt = (g.nx / kTX) * (g.ny / kTY);
         const TileWalk tt = tile_walk(nt);
         const int q = lane >> 4;
         for (int tile = tt.first; tile < tt.end; tile += tt.step) {
-            v4d acc[2][1][NMB];
+            typename MfmaT<T>::v4 acc[2][1][NMB];
             tiled_rows<K, 1>(fr, tile, g, sB,
                              [&](size_t o, bool own) {
-                                 const double v = r[o] + beta * (pin[o] - omega * vin[o]);
+                                 const T v = r[o] + (T)beta * (pin[o] - (T)omega * vin[o]);
                                  if (own) pout[o] = v;
                                  return v;
                              },
@@ -950,11 +973,11 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
                 for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
                     for (int e4 = 0; e4 < 4; ++e4) {
-                        const int row = 16 * mb + 4 * e4 + q;
+                        const int row = 16 * mb + MfmaT<T>::row(lane, e4);
                         if (row < B3) {
                             const size_t o = f * TT + (size_t)row * nel + e;
                             const double y = acc[f][0][mb][e4];
-                            vout[o] = y;
+                            vout[o] = (T)y;
                             acc1[0] += rh[o] * y;
                         }
                     }
@@ -968,10 +991,10 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
         FaceIdx fi[2];
         int dirs[2][7], idx[2][7];
         faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
-        v4d acc[2][1][NMB];
+        typename MfmaT<T>::v4 acc[2][1][NMB];
         mfma_rows2<K, 1>(fr, dirs, idx, nel, lane,
                          [&](int f, int sl, size_t o) {
-                             const double v = r[o] + beta * (pin[o] - omega * vin[o]);
+                             const T v = r[o] + (T)beta * (pin[o] - (T)omega * vin[o]);
                              if (sl == 0 && fi[f].active) pout[o] = v;
                              return v;
                          },
@@ -982,11 +1005,11 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
             for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * mb + 4 * e + (lane >> 4);
+                    const int row = 16 * mb + MfmaT<T>::row(lane, e);
                     if (row < B3 && fi[f].active) {
                         const size_t o = f * TT + (size_t)row * nel + fi[f].f;
                         const double y = acc[f][0][mb][e];
-                        vout[o] = y;
+                        vout[o] = (T)y;
                         acc1[0] += rh[o] * y;
                     }
                 }
@@ -995,11 +1018,12 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
     if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
 }
 
-template <int K, bool TILED>
-__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats A, const double *__restrict__ r,
-                                                 const double *__restrict__ v,
-                                                 double *__restrict__ sv,
-                                                 double *__restrict__ t, const Geom g,
+template <int K, bool TILED, typename T>
+__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMatsT<T> A,
+                                                 const T *__restrict__ r,
+                                                 const T *__restrict__ v,
+                                                 T *__restrict__ sv,
+                                                 T *__restrict__ t, const Geom g,
                                                  KrylovState *ks, const double *P1, int n1,
                                                  const double *P3, int n3, double *P2,
                                                  int stride) {
@@ -1020,18 +1044,18 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const size_t nel = g.nel, TT = (size_t)B3 * nel;
     const int ntiles = (g.nel + 63) / 64;
-    const double *fr[1] = {A.A0};
+    const T *fr[1] = {A.A0};
     double acc2[2] = {0.0, 0.0};
     if constexpr (TILED) {
-        __shared__ double sB[B3][Tile<K>::NF];
+        __shared__ T sB[B3][Tile<K>::NF];
         const int nt = (g.nx / kTX) * (g.ny / kTY);
         const TileWalk tt = tile_walk(nt);
         const int q = lane >> 4;
         for (int tile = tt.first; tile < tt.end; tile += tt.step) {
-            v4d acc[2][1][NMB];
+            typename MfmaT<T>::v4 acc[2][1][NMB];
             tiled_rows<K, 1>(fr, tile, g, sB,
                              [&](size_t o, bool own) {
-                                 const double sval = r[o] - alpha * v[o];
+                                 const T sval = r[o] - (T)alpha * v[o];
                                  if (own) sv[o] = sval;
                                  return sval;
                              },
@@ -1044,12 +1068,12 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
                 for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
                     for (int e4 = 0; e4 < 4; ++e4) {
-                        const int row = 16 * mb + 4 * e4 + q;
+                        const int row = 16 * mb + MfmaT<T>::row(lane, e4);
                         if (row < B3) {
                             const size_t o = f * TT + (size_t)row * nel + e;
                             const double y = acc[f][0][mb][e4];
                             const double sval = sB[row][li];
-                            t[o] = y;
+                            t[o] = (T)y;
                             acc2[0] += y * sval;
                             acc2[1] += y * y;
                         }
@@ -1068,10 +1092,10 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
         FaceIdx fi[2];
         int dirs[2][7], idx[2][7];
         faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
-        v4d acc[2][1][NMB];
+        typename MfmaT<T>::v4 acc[2][1][NMB];
         mfma_rows2<K, 1>(fr, dirs, idx, nel, lane,
                          [&](int f, int sl, size_t o) {
-                             const double sval = r[o] - alpha * v[o];
+                             const T sval = r[o] - (T)alpha * v[o];
                              if (sl == 0 && fi[f].active) sv[o] = sval;
                              return sval;
                          },
@@ -1082,12 +1106,12 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
             for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * mb + 4 * e + (lane >> 4);
+                    const int row = 16 * mb + MfmaT<T>::row(lane, e);
                     if (row < B3 && fi[f].active) {
                         const size_t o = f * TT + (size_t)row * nel + fi[f].f;
                         const double y = acc[f][0][mb][e];
-                        const double sval = r[o] - alpha * v[o];
-                        t[o] = y;
+                        const T sval = r[o] - (T)alpha * v[o];
+                        t[o] = (T)y;
                         acc2[0] += y * sval;
                         acc2[1] += y * y;
                     }
@@ -1100,9 +1124,10 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
     }
 }
 
-__global__ void k_bicg_k3(double *__restrict__ d, double *__restrict__ r,
-                          const double *__restrict__ rh, const double *__restrict__ p,
-                          const double *__restrict__ sv, const double *__restrict__ t, size_t n,
+template <typename T>
+__global__ void k_bicg_k3(T *__restrict__ d, T *__restrict__ r,
+                          const T *__restrict__ rh, const T *__restrict__ p,
+                          const T *__restrict__ sv, const T *__restrict__ t, size_t n,
                           KrylovState *ks, const double *P2, int n2, double *P3, int stride) {
     double red[2];
     reduce_partials<2>(P2, stride, n2, red);
@@ -1113,9 +1138,9 @@ __global__ void k_bicg_k3(double *__restrict__ d, double *__restrict__ r,
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const double si = sv[i];
-        d[i] += alpha * p[i] + omega * si;
-        const double rr = si - omega * t[i];
-        r[i] = rr;
+        d[i] = (T)((double)d[i] + alpha * (double)p[i] + omega * si);
+        const double rr = si - omega * (double)t[i];
+        r[i] = (T)rr;
         acc[0] += rh[i] * rr;
         acc[1] += rr * rr;
     }
@@ -1126,7 +1151,8 @@ __global__ void k_bicg_k3(double *__restrict__ d, double *__restrict__ r,
     }
 }
 
-__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
+template <typename T>
+__global__ void k_axpy(double *__restrict__ y, const T *__restrict__ x, double a, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] += a * x[i];
 }
@@ -1208,48 +1234,57 @@ template <int K> struct RunTraceRhs {
         return hipGetLastError();
     }
 };
-template <int K> struct RunTraceResidual {
-    static hipError_t run(const Geom &g, const double *G, const double *Gh, const double *x,
-                          const double *gv, const double *gh, double *r, double *rin,
-                          double *partials, int stride, hipStream_t s) {
-        if (is_tiled(g))
-            hipLaunchKernelGGL((k_trace_residual<K, true>), dim3(face_grid(g)), dim3(256), 0, s,
-                               FragMats{G, Gh}, x, gv, gh, g, r, rin, partials, stride);
-        else
-            hipLaunchKernelGGL((k_trace_residual<K, false>), dim3(face_grid(g)), dim3(256), 0,
-                               s, FragMats{G, Gh}, x, gv, gh, g, r, rin, partials, stride);
-        return hipGetLastError();
-    }
+template <typename RT> struct RunTraceResidual {
+    template <int K> struct F {
+        static hipError_t run(const Geom &g, const double *G, const double *Gh,
+                              const double *x, const double *gv, const double *gh, double *r,
+                              RT *rin, double *partials, int stride, hipStream_t s) {
+            if (is_tiled(g))
+                hipLaunchKernelGGL((k_trace_residual<K, true, RT>), dim3(face_grid(g)),
+                                   dim3(256), 0, s, FragMats{G, Gh}, x, gv, gh, g, r, rin,
+                                   partials, stride);
+            else
+                hipLaunchKernelGGL((k_trace_residual<K, false, RT>), dim3(face_grid(g)),
+                                   dim3(256), 0, s, FragMats{G, Gh}, x, gv, gh, g, r, rin,
+                                   partials, stride);
+            return hipGetLastError();
+        }
+    };
 };
-template <int K> struct RunK1 {
-    static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *rh,
-                          const double *pin, const double *vin, double *pout, double *vout,
-                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-        if (is_tiled(g))
-            hipLaunchKernelGGL((k_bicg_k1<K, true>), dim3(face_grid(g)), dim3(256), 0, s,
-                               FragMats{Gh, nullptr}, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
-                               (int)elem_grid(g), kb.P1, kb.stride);
-        else
-            hipLaunchKernelGGL((k_bicg_k1<K, false>), dim3(face_grid(g)), dim3(256), 0, s,
-                               FragMats{Gh, nullptr}, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
-                               (int)elem_grid(g), kb.P1, kb.stride);
-        return hipGetLastError();
-    }
+template <typename T> struct RunK1 {
+    template <int K> struct F {
+        static hipError_t run(const Geom &g, const T *Gh, const T *r, const T *rh,
+                              const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,
+                              const KrylovBufs &kb, hipStream_t s) {
+            const FragMatsT<T> A{Gh, nullptr};
+            if (is_tiled(g))
+                hipLaunchKernelGGL((k_bicg_k1<K, true, T>), dim3(face_grid(g)), dim3(256), 0, s,
+                                   A, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
+                                   (int)elem_grid(g), kb.P1, kb.stride);
+            else
+                hipLaunchKernelGGL((k_bicg_k1<K, false, T>), dim3(face_grid(g)), dim3(256), 0,
+                                   s, A, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
+                                   (int)elem_grid(g), kb.P1, kb.stride);
+            return hipGetLastError();
+        }
+    };
 };
-template <int K> struct RunK2 {
-    static hipError_t run(const Geom &g, const double *Gh, const double *r, const double *v,
-                          double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
-                          hipStream_t s) {
-        if (is_tiled(g))
-            hipLaunchKernelGGL((k_bicg_k2<K, true>), dim3(face_grid(g)), dim3(256), 0, s,
-                               FragMats{Gh, nullptr}, r, v, sv, t, g, ks, kb.P1,
-                               (int)face_grid(g), kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
-        else
-            hipLaunchKernelGGL((k_bicg_k2<K, false>), dim3(face_grid(g)), dim3(256), 0, s,
-                               FragMats{Gh, nullptr}, r, v, sv, t, g, ks, kb.P1,
-                               (int)face_grid(g), kb.P3, (int)elem_grid(g), kb.P2, kb.stride);
-        return hipGetLastError();
-    }
+template <typename T> struct RunK2 {
+    template <int K> struct F {
+        static hipError_t run(const Geom &g, const T *Gh, const T *r, const T *v, T *sv, T *t,
+                              KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+            const FragMatsT<T> A{Gh, nullptr};
+            if (is_tiled(g))
+                hipLaunchKernelGGL((k_bicg_k2<K, true, T>), dim3(face_grid(g)), dim3(256), 0, s,
+                                   A, r, v, sv, t, g, ks, kb.P1, (int)face_grid(g), kb.P3,
+                                   (int)elem_grid(g), kb.P2, kb.stride);
+            else
+                hipLaunchKernelGGL((k_bicg_k2<K, false, T>), dim3(face_grid(g)), dim3(256), 0,
+                                   s, A, r, v, sv, t, g, ks, kb.P1, (int)face_grid(g), kb.P3,
+                                   (int)elem_grid(g), kb.P2, kb.stride);
+            return hipGetLastError();
+        }
+    };
 };
 template <int K> struct RunDiag {
     static hipError_t run(const Geom &g, const double *q, double *partials, int stride,
@@ -1310,47 +1345,77 @@ hipError_t launch_recover(const Geom &g, const double *W, const double *Z, const
     return dispatch<RunRecover>(g.K, g, W, Z, qhat, Q, s);
 }
 
-hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,
-                                 const double *x, const double *gvec, const double *ghat,
-                                 double *r, double *rin, double *partials, int stride,
-                                 hipStream_t s) {
-    return dispatch<RunTraceResidual>(g.K, g, G, Gh, x, gvec, ghat, r, rin, partials, stride, s);
+namespace {
+
+template <typename T>
+hipError_t trace_residual_impl(const Geom &g, const double *G, const double *Gh,
+                               const double *x, const double *gvec, const double *ghat,
+                               double *r, T *rin, double *partials, int stride,
+                               hipStream_t s) {
+    return dispatch<RunTraceResidual<T>::template F>(g.K, g, G, Gh, x, gvec, ghat, r, rin,
+                                                      partials, stride, s);
 }
 
-hipError_t launch_bicg_init(const Geom &g, const double *rin, double *r, double *rh, double *p,
-                            double *v, double *d, KrylovState *ks, double tol2,
-                            const KrylovBufs &kb, hipStream_t s) {
+template <typename T>
+hipError_t bicg_init_impl(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,
+                          KrylovState *ks, double tol2, const KrylovBufs &kb, hipStream_t s) {
     const size_t n = (size_t)6 * g.K * g.nel;
-    hipLaunchKernelGGL(k_bicg_init, dim3(elem_grid(g)), dim3(256), 0, s, rin, r, rh, p, v, d, n,
-                       ks, tol2, kb.P3, kb.stride);
+    hipLaunchKernelGGL(k_bicg_init<T>, dim3(elem_grid(g)), dim3(256), 0, s, rin, r, rh, p, v, d,
+                       n, ks, tol2, kb.P3, kb.stride);
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_k1(const Geom &g, const double *Gh, const double *r, const double *rh,
-                          const double *pin, const double *vin, double *pout, double *vout,
-                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-    return dispatch<RunK1>(g.K, g, Gh, r, rh, pin, vin, pout, vout, ks, kb, s);
-}
-
-hipError_t launch_bicg_k2(const Geom &g, const double *Gh, const double *r, const double *v,
-                          double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
-                          hipStream_t s) {
-    return dispatch<RunK2>(g.K, g, Gh, r, v, sv, t, ks, kb, s);
-}
-
-hipError_t launch_bicg_k3(const Geom &g, double *d, double *r, const double *rh, const double *p,
-                          const double *sv, const double *t, KrylovState *ks,
-                          const KrylovBufs &kb, hipStream_t s) {
+template <typename T>
+hipError_t bicg_k3_impl(const Geom &g, T *d, T *r, const T *rh, const T *p, const T *sv,
+                        const T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
     const size_t n = (size_t)6 * g.K * g.nel;
-    hipLaunchKernelGGL(k_bicg_k3, dim3(elem_grid(g)), dim3(256), 0, s, d, r, rh, p, sv, t, n, ks,
-                       kb.P2, (int)face_grid(g), kb.P3, kb.stride);
+    hipLaunchKernelGGL(k_bicg_k3<T>, dim3(elem_grid(g)), dim3(256), 0, s, d, r, rh, p, sv, t, n,
+                       ks, kb.P2, (int)face_grid(g), kb.P3, kb.stride);
     return hipGetLastError();
 }
 
-hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);
+template <typename T>
+hipError_t axpy_impl(double *y, const T *x, double a, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);
     return hipGetLastError();
 }
+
+}  // namespace
+
+#define IMEXHDG_KRYLOV_LAUNCHERS(T)                                                            \
+    hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,        \
+                                     const double *x, const double *gvec,                     \
+                                     const double *ghat, double *r, T *rin, double *partials, \
+                                     int stride, hipStream_t s) {                             \
+        return trace_residual_impl<T>(g, G, Gh, x, gvec, ghat, r, rin, partials, stride, s);  \
+    }                                                                                          \
+    hipError_t launch_bicg_init(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,  \
+                                KrylovState *ks, double tol2, const KrylovBufs &kb,           \
+                                hipStream_t s) {                                              \
+        return bicg_init_impl<T>(g, rin, r, rh, p, v, d, ks, tol2, kb, s);                    \
+    }                                                                                          \
+    hipError_t launch_bicg_k1(const Geom &g, const T *Gh, const T *r, const T *rh,            \
+                              const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,  \
+                              const KrylovBufs &kb, hipStream_t s) {                          \
+        return dispatch<RunK1<T>::template F>(g.K, g, Gh, r, rh, pin, vin, pout, vout, ks, kb,  \
+                                              s);                                             \
+    }                                                                                          \
+    hipError_t launch_bicg_k2(const Geom &g, const T *Gh, const T *r, const T *v, T *sv,      \
+                              T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {   \
+        return dispatch<RunK2<T>::template F>(g.K, g, Gh, r, v, sv, t, ks, kb, s);            \
+    }                                                                                          \
+    hipError_t launch_bicg_k3(const Geom &g, T *d, T *r, const T *rh, const T *p,             \
+                              const T *sv, const T *t, KrylovState *ks, const KrylovBufs &kb, \
+                              hipStream_t s) {                                                \
+        return bicg_k3_impl<T>(g, d, r, rh, p, sv, t, ks, kb, s);                             \
+    }                                                                                          \
+    hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s) {        \
+        return axpy_impl<T>(y, x, a, n, s);                                                   \
+    }
+
+IMEXHDG_KRYLOV_LAUNCHERS(double)
+IMEXHDG_KRYLOV_LAUNCHERS(float)
+#undef IMEXHDG_KRYLOV_LAUNCHERS
 
 hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
                        hipStream_t s) {

@@ -66,26 +66,31 @@ hipError_t launch_trace_rhs(const Geom &g, const double *Z, const double *Pxinv,
                             const double *Pyinv, double *gvec, double *ghat, hipStream_t s);
 hipError_t launch_recover(const Geom &g, const double *W, const double *Z,
                           const double *qhat, double *Q, hipStream_t s);
-// FP64 r = g - G x and rin = ghat - Ghat x; partials [4][face_grid] of
-// ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
-hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,
-                                 const double *x, const double *gvec, const double *ghat,
-                                 double *r, double *rin, double *partials, int stride,
-                                 hipStream_t s);
-// BiCGStab on Ghat d = rin with d0 = 0: init, then per iteration K1, K2, K3.
-hipError_t launch_bicg_init(const Geom &g, const double *rin, double *r, double *rh,
-                            double *p, double *v, double *d, KrylovState *ks, double tol2,
-                            const KrylovBufs &kb, hipStream_t s);
-hipError_t launch_bicg_k1(const Geom &g, const double *Gh, const double *r, const double *rh,
-                          const double *pin, const double *vin, double *pout, double *vout,
-                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s);
-hipError_t launch_bicg_k2(const Geom &g, const double *Gh, const double *r, const double *v,
-                          double *sv, double *t, KrylovState *ks, const KrylovBufs &kb,
-                          hipStream_t s);
-hipError_t launch_bicg_k3(const Geom &g, double *d, double *r, const double *rh,
-                          const double *p, const double *sv, const double *t,
-                          KrylovState *ks, const KrylovBufs &kb, hipStream_t s);
-hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s);
+// FP64 r = g - G x and rin = ghat - Ghat x (stored in the inner solve's
+// precision); partials [4][face_grid] of ||r||^2, ||g||^2, ||ghat||^2,
+// ||rin||^2.  BiCGStab on Ghat d = rin with d0 = 0: init, then per
+// iteration K1, K2, K3; x += d after the sweep.  Each exists for an FP64
+// and an FP32 inner solve (matrix-core fragments in the same precision).
+#define IMEXHDG_KRYLOV_DECLS(T)                                                                \
+    hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,        \
+                                     const double *x, const double *gvec,                     \
+                                     const double *ghat, double *r, T *rin, double *partials, \
+                                     int stride, hipStream_t s);                              \
+    hipError_t launch_bicg_init(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,  \
+                                KrylovState *ks, double tol2, const KrylovBufs &kb,           \
+                                hipStream_t s);                                               \
+    hipError_t launch_bicg_k1(const Geom &g, const T *Gh, const T *r, const T *rh,            \
+                              const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,  \
+                              const KrylovBufs &kb, hipStream_t s);                           \
+    hipError_t launch_bicg_k2(const Geom &g, const T *Gh, const T *r, const T *v, T *sv,      \
+                              T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s);    \
+    hipError_t launch_bicg_k3(const Geom &g, T *d, T *r, const T *rh, const T *p,             \
+                              const T *sv, const T *t, KrylovState *ks, const KrylovBufs &kb, \
+                              hipStream_t s);                                                 \
+    hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s);
+IMEXHDG_KRYLOV_DECLS(double)
+IMEXHDG_KRYLOV_DECLS(float)
+#undef IMEXHDG_KRYLOV_DECLS
 // partials [5][diag_grid]: mass of phi_eta, U, V; energy; non-finite count
 hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
                        hipStream_t s);

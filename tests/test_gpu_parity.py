@@ -155,3 +155,28 @@ def test_error_paths():
     with pytest.raises(m.ImexError) as e:
         S2.step(1)
     assert e.value.code == m.E_NOCONV
+
+
+# ------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("nx,ny,k", [(16, 16, 4), (10, 7, 3), (16, 8, 6)])
+def test_mixed_stage_solve(nx, ny, k):
+    """FP32 inner BiCGStab with FP64 refinement reaches the FP64 tolerance."""
+    print(f"mixed stage_solve nx={nx} ny={ny} k={k}", flush=True)
+    P, S = make_pair(nx, ny, k, 9.81, 1.0, 0.02, precision=m.PREC_MIXED,
+                     krylov_rtol=1e-6, refine_rtol=1e-12, refine_max=8)
+    R = bump_state(P, seed=k)
+    Q, qh, iters, relres = S.stage_solve(to_dev(R, S))
+    assert relres <= 1e-12
+    assert rel_err(from_dev(Q, S, P.mesh), P.stage_solve(R)) < 1e-10
+
+
+def test_mixed_steps_bound():
+    """Mixed path (refine_rtol 1e-10) stays within 1e-8 of the FP64 oracle
+    after 20 nonlinear steps."""
+    P, S = make_pair(16, 16, 4, 9.81, 1.0, 0.004, precision=m.PREC_MIXED,
+                     krylov_rtol=1e-6, refine_rtol=1e-10, refine_max=8)
+    q0 = bump_state(P, seed=3, umax=0.1)
+    got, ref = _run_both(P, S, q0, 20)
+    err = swe.rel_l2(P.mesh, got, ref)
+    print("mixed rel L2 after 20 steps", err, S.diag(), flush=True)
+    assert np.all(err < 1e-8)
