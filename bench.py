@@ -9,9 +9,10 @@ BiCGStab with FP64 refinement on the trace system, local recovery) and the
 stage combinations.  The state is resident in HBM before the timed region.
 Prints one JSON line; progress goes to stderr.
 
-The roofline object covers the kernel class with the largest device time in
-a short all-classes profiling pass; its launches are then timed with HIP
-events on the library's stream inside the timed region.  The CPU baseline is
+The timed region steps on the fixed launch schedule (one graph launch per
+step).  The roofline object covers the kernel class with the largest device
+time in a short all-classes profiling pass; its launches are then timed with
+HIP events on the library's stream over the same steps run host-driven.  The CPU baseline is
 the FP64 oracle on a bounded sample of the same workload recipe.
 """
 import argparse
@@ -124,13 +125,23 @@ def cpu_baseline(wl_name, seconds=15.0):
 
 
 def run_path(m, wl, precision, steps, warmup):
-    """Run one precision path; returns (result dict, final state, solver)."""
+    """Run one precision path; returns (result dict, final state).
+
+    Timed region: `steps` steps on the fixed launch schedule, one graph
+    launch per step, after the warm-up (which learns the schedule and
+    captures the graphs) and one untimed step from the initial state (a
+    cold start runs host-driven).  Roofline: the same steps again, host
+    driven, with the dominant kernel class timed by HIP events around each
+    of its launches on the library's stream.  The kernels are the same in
+    both modes; the graph launches carry their own symbols (a SCHED
+    template tag), so a profile tells the two apart."""
     import torch
     mixed = precision == "mixed"
     cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
                            dt=wl.dt, scheme=m.SCHEME_ARS232,
                            physics=m.PHYSICS_NONLINEAR if wl.nonlinear else m.PHYSICS_LINEARIZED,
-                           precision=m.PREC_MIXED if mixed else m.PREC_FP64)
+                           precision=m.PREC_MIXED if mixed else m.PREC_FP64,
+                           launch=m.LAUNCH_GRAPH)
     if mixed:
         cfg.krylov_rtol = MIXED_KRYLOV_RTOL
         cfg.refine_rtol = MIXED_REFINE_RTOL
@@ -141,9 +152,9 @@ def run_path(m, wl, precision, steps, warmup):
     S.set_state(h, hu, hv)
     n_dof = 3 * S.n_nodes
     log(f"[bench] {precision}: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {warmup}")
-    S.step(warmup)
+    S.step(max(warmup, 3))
     torch.cuda.synchronize()
-    # short all-classes pass to find the dominant kernel
+    # short all-classes pass (host-driven) to find the dominant kernel
     S.profile(-1)
     S.step(2)
     per = {}
@@ -151,24 +162,37 @@ def run_path(m, wl, precision, steps, warmup):
         n, ms = S.profile_read(name)
         if n:
             per[name] = {"launches": n, "total_ms": ms, "avg_us": 1000.0 * ms / n}
+    S.profile(-2)
     dominant = max(per, key=lambda k: per[k]["total_ms"])
     log(f"[bench] {precision}: dominant kernel class {dominant} "
         f"({per[dominant]['avg_us']:.2f} us avg over {per[dominant]['launches']} launches)")
-    # the timed run restarts from the initial state
+    # timed run: restart from the initial state, one cold step outside the clock
     S.set_state(h, hu, hv)
+    S.step(1)
     d0 = S.diag()
-    S.profile(dominant)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     el = t1 - t0
-    nl, ms = S.profile_read(dominant)
     d1 = S.diag()
+    sched = S.schedule()
     state = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
     value = n_dof * steps / el
-    log(f"[bench] {precision}: {steps} steps in {el:.3f} s -> {value:.4g} DOF-updates/s")
+    log(f"[bench] {precision}: {steps} graph steps in {el:.3f} s -> {value:.4g} DOF-updates/s "
+        f"(schedule {sched}, redone steps {d1['redo_steps'] - d0['redo_steps']})")
+    # roofline run: same steps host-driven, dominant class timed by events
+    S.set_state(h, hu, hv)
+    S.step(1)
+    S.profile(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    el_host = time.perf_counter() - t0
+    nl, ms = S.profile_read(dominant)
+    S.profile(-2)
     isz = 4 if mixed else 8
     avg_s = ms / 1000.0 / nl
     nbytes, nflops = algorithmic_cost(dominant, wl, n_dof, isz)
@@ -188,11 +212,16 @@ def run_path(m, wl, precision, steps, warmup):
     roof["kernel"] = dominant
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = nl
+    roof["timed_in"] = "host-driven run of the same steps (HIP events per launch)"
     roof["algorithmic_bytes_per_launch"] = nbytes
     roof["algorithmic_flops_per_launch"] = nflops
     iters = ((d1["krylov_iters"] - d0["krylov_iters"])
              / max(1, d1["stage_solves"] - d0["stage_solves"]))
     res = {"value": value, "ms_per_step": 1000.0 * el / steps, "roofline": roof,
+           "host_driven_ms_per_step": 1000.0 * el_host / steps,
+           "schedule": {"sweeps": sched[0], "inner_budget": sched[1]},
+           "graph_steps": d1["graph_steps"] - d0["graph_steps"],
+           "redone_steps": d1["redo_steps"] - d0["redo_steps"],
            "krylov_iters_per_stage": iters, "max_trace_relres": d1["max_relres"],
            "kernels": per, "n_dof": n_dof, "n_trace": S.n_trace}
     S.close()
@@ -254,6 +283,8 @@ def main():
         "roofline": head["roofline"],
         "krylov_iters_per_stage": head["krylov_iters_per_stage"],
         "max_trace_relres": head["max_trace_relres"],
+        "launch": {k: head[k] for k in ("schedule", "graph_steps", "redone_steps",
+                                        "host_driven_ms_per_step")},
         "kernels": head["kernels"],
     }
     if smx is not None:
@@ -261,6 +292,9 @@ def main():
         err = swe.rel_l2(mesh, smx.reshape(mesh.shape), s64.reshape(mesh.shape))
         out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                        "roofline": fp64["roofline"],
+                       "launch": {k: fp64[k] for k in ("schedule", "graph_steps",
+                                                       "redone_steps",
+                                                       "host_driven_ms_per_step")},
                        "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
         out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]
         out["mixed_rel_l2_vs_fp64"] = [float(e) for e in err]

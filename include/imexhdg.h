@@ -69,6 +69,14 @@ extern "C" {
                                   residual, iterative refinement, mass and
                                   energy sums                               */
 
+/* how imexhdg_step drives the trace solves */
+#define IMEXHDG_LAUNCH_GRAPH 0  /* fixed launch schedule, one captured graph per
+                                   step, convergence decided on the device;
+                                   a step whose stage solves miss refine_rtol
+                                   on the schedule is redone host-driven     */
+#define IMEXHDG_LAUNCH_HOST  1  /* host reads the residual between sweeps and
+                                   the Krylov state every few iterations     */
+
 /* variables of host state arrays */
 #define IMEXHDG_VARS_DEPTH       0  /* (h, hu, hv): depth and momenta        */
 #define IMEXHDG_VARS_GEOPOTENTIAL 1 /* (phi_eta, U, V) = (g(h-H), g hu, g hv) */
@@ -88,6 +96,7 @@ typedef struct imexhdg_config {
     int32_t check_every;     /* iterations between convergence checks      */
     double  refine_rtol;     /* FP64 true-residual tolerance ||g-Gx||/||g|| */
     int32_t refine_max;      /* max refinement sweeps per stage solve      */
+    int32_t launch;          /* IMEXHDG_LAUNCH_*                           */
 } imexhdg_config;
 
 typedef struct imexhdg_diag {
@@ -100,6 +109,8 @@ typedef struct imexhdg_diag {
     double  last_relres;     /* last FP64 true relative trace residual     */
     double  max_relres;      /* largest final relative residual so far     */
     int32_t nonfinite;       /* 1 if the state holds NaN/Inf               */
+    int64_t graph_steps;     /* steps run as one graph launch, cumulative  */
+    int64_t redo_steps;      /* graph steps redone host-driven, cumulative */
 } imexhdg_diag;
 
 typedef struct imexhdg_ctx imexhdg_ctx;
@@ -145,10 +156,20 @@ int imexhdg_set_state(imexhdg_ctx *ctx, int vars, const double *a,
 int imexhdg_get_state(imexhdg_ctx *ctx, int vars, double *a, double *b,
                       double *c);
 
-/* Enqueue nsteps IMEX steps (Algorithm 1) on the context's stream.  The
- * trace solves check convergence every `check_every` inner iterations,
- * which synchronises the stream; IMEXHDG_E_NOCONV if a stage solve ends
- * above refine_rtol after refine_max sweeps (the state is still advanced). */
+/* Advance nsteps IMEX steps (Algorithm 1) on the context's stream and
+ * return when they are done (the stream is synchronised).
+ * IMEXHDG_LAUNCH_HOST: the trace solves check convergence every
+ * `check_every` inner iterations, which synchronises the stream.
+ * IMEXHDG_LAUNCH_GRAPH: the first call runs two steps host-driven to learn
+ * how many refinement sweeps and inner iterations a stage solve takes,
+ * then captures the step on that schedule (plus a margin) in graphs; each
+ * later step is one graph launch, and the host reads the stage outcomes one
+ * step behind the device, so the device never waits for it.  A step whose
+ * stage solves missed refine_rtol on the schedule is redone host-driven
+ * from its kept input and the schedule is widened.  While the kernel
+ * profiler is on, steps run host-driven.
+ * IMEXHDG_E_NOCONV if a host-driven stage solve ends above refine_rtol after
+ * refine_max sweeps (the state is still advanced). */
 int imexhdg_step(imexhdg_ctx *ctx, int32_t nsteps);
 
 /* FP64 mass and energy of the current state plus solver counters;
@@ -164,7 +185,8 @@ const char *imexhdg_last_error(void);
  * synchronise unless stated.                                             */
 
 /* Device layout base of the context's current state q^n (3*n_nodes FP64,
- * volume device layout).  Valid until the context is destroyed.          */
+ * volume device layout).  The state lives in a ring of three buffers, so
+ * the pointer is valid until the next imexhdg_step or set_state.         */
 int imexhdg_state_device(imexhdg_ctx *ctx, double **d_q);
 
 /* out = M^-1 NL(q) (Sec. 4.3): volume term (F_NL(q), grad v)_K and the
@@ -213,6 +235,19 @@ int imexhdg_profile_read(imexhdg_ctx *ctx, int32_t kernel, int64_t *launches,
 
 /* Static name of a kernel class, or NULL for an unknown id.              */
 const char *imexhdg_kernel_name(int32_t kernel);
+
+/* ---------------- fixed launch schedule of IMEXHDG_LAUNCH_GRAPH
+ * A schedule is a number of refinement sweeps (0..8, at most refine_max)
+ * and, per sweep, a budget of inner BiCGStab iterations (1..krylov_max_iter).
+ * get: the schedule the graphs were captured with (sweeps = 0 before the
+ * first capture); budget must hold 8 values.  set: replace the schedule and
+ * capture it now (synchronises the stream); the margin the library adds
+ * when it learns or widens a schedule is not applied to it.  A schedule too
+ * short for the solves costs a host-driven redo of the step, after which
+ * the library widens it.  IMEXHDG_E_INVAL for values out of range,
+ * IMEXHDG_E_STATE if the context is not in IMEXHDG_LAUNCH_GRAPH mode.      */
+int imexhdg_get_schedule(const imexhdg_ctx *ctx, int32_t *sweeps, int32_t *budget);
+int imexhdg_set_schedule(imexhdg_ctx *ctx, int32_t sweeps, const int32_t *budget);
 
 #ifdef __cplusplus
 }

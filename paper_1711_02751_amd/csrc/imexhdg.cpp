@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -98,8 +100,12 @@ struct imexhdg_ctx {
     Tableau tab;
     double aii = 0.0;
     size_t N = 0, T = 0, nnodes = 0;
-    // device buffers
+    // device buffers; the state lives in a ring of three buffers, q is
+    // qbuf[cur] and a step from qbuf[a] writes qbuf[(a + 1) % 3]
+    double *qbuf[3] = {nullptr, nullptr, nullptr};
+    int cur = 0;
     double *q = nullptr, *Z = nullptr, *tmp = nullptr;
+    const double *qin = nullptr;      // q^n of the step being enqueued
     std::vector<double *> NLb, Qb, Rb;
     double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr;
     // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
@@ -123,6 +129,21 @@ struct imexhdg_ctx {
     int64_t steps = 0, kiters = 0, solves = 0, sweeps = 0;
     double last_relres = 0.0, max_relres = 0.0;
     int iter_pred = 0;      // inner iterations of the last first sweep
+    // fixed-schedule stepping: sweeps and inner-iteration budget per sweep,
+    // what the last host-driven solves needed, one graph per ring position
+    int sched_sweeps = 0, sched_budget[kMaxSweeps] = {};
+    int margin = 2;
+    int learn_sweeps = 0, learn_iters[kMaxSweeps] = {};
+    int win_sweeps = 0, win_iters[kMaxSweeps] = {};   // graph steps since capture
+    int64_t win_steps = 0;
+    bool cold = true;                 // next step starts from a fresh trace guess
+    bool gready = false;
+    hipStream_t gstream = nullptr;    // capture stream
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t gev[3] = {nullptr, nullptr, nullptr};
+    StageStatus *dstat = nullptr;     // [3][s], device
+    StageStatus *hstat = nullptr;     // [3][s], pinned host mirror
+    int64_t graph_steps = 0, redos = 0, captures = 0;
     // event profiler
     int prof_target = -2;
     std::vector<hipEvent_t> ev0, ev1;
@@ -184,7 +205,7 @@ Layout layout_of(const imexhdg_config &c) {
     L.s = (c.scheme == IMEXHDG_SCHEME_ARS443) ? 5 : 3;
     L.max_blocks = kPartStride;
     size_t t = 0;
-    t += 3 * align256(L.N * 8);                       // q, Z, tmp
+    t += 5 * align256(L.N * 8);                       // q ring (3), Z, tmp
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     const size_t isz = (c.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
     t += 4 * align256(L.T * 8);                        // FP64 trace vectors
@@ -194,6 +215,7 @@ Layout layout_of(const imexhdg_config &c) {
     t += align256(frag_count((int)K) * 4);             // FP32 Ghat fragments
     t += 5 * align256(kPartStride * 8) + align256(5 * kPartStride * 8);
     t += align256(sizeof(KrylovState));
+    t += align256(3 * (size_t)L.s * sizeof(StageStatus));
     L.total = t;
     return L;
 }
@@ -221,6 +243,8 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "refine_rtol must be in (0, 1)");
     if (c->krylov_max_iter < 1 || c->check_every < 1 || c->refine_max < 1)
         return fail(IMEXHDG_E_INVAL, "iteration budgets must be >= 1");
+    if (c->launch != IMEXHDG_LAUNCH_GRAPH && c->launch != IMEXHDG_LAUNCH_HOST)
+        return fail(IMEXHDG_E_INVAL, "unknown launch mode");
     return IMEXHDG_OK;
 }
 
@@ -336,7 +360,7 @@ hipError_t stream_sync(imexhdg_ctx *c) {
     } while (0)
 
 const double *vec_of(imexhdg_ctx *c, int id) {
-    if (id == QN) return c->q;
+    if (id == QN) return c->qin;
     if (id >= NLV && id < QV) return c->NLb[id - NLV];
     if (id >= QV && id < RV) return c->Qb[id - QV];
     return c->Rb[id - RV];
@@ -417,10 +441,10 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
         LAUNCH(IMEXHDG_K_TRACE_RESID,
                c->mixed ? launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
                                                 (float *)c->rin, c->dpart, kPartStride,
-                                                c->stream)
+                                                nullptr, c->stream)
                         : launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
                                                 (double *)c->rin, c->dpart, kPartStride,
-                                                c->stream));
+                                                nullptr, c->stream));
         double nrm[4];
         if ((rc = read_partials(c, 4, face_grid(g), nrm))) return rc;
         const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
@@ -442,6 +466,10 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
                       : inner_solve<double>(c, c->dGh, tol2, sweep);
         if (rc) return rc;
         iters += c->hks->iters;
+        if (sweep < kMaxSweeps) {
+            c->learn_iters[sweep] = std::max(c->learn_iters[sweep], (int)c->hks->iters);
+            c->learn_sweeps = std::max(c->learn_sweeps, sweep + 1);
+        }
     }
     c->kiters += iters;
     c->solves += 1;
@@ -484,6 +512,291 @@ int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
         LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, Qi, cb, c->stream));
     } else {
         LAUNCH(IMEXHDG_K_COMBINE, launch_combine(c->geom, cb, c->N, c->stream));
+    }
+    return IMEXHDG_OK;
+}
+
+
+// ------------------------------------------------ host-driven step
+// One step of Algorithm 1 from qin to qout; the trace solves are driven by
+// host reads of the residual and the Krylov state.
+int step_host(imexhdg_ctx *c, const double *qin, double *qout, int *status) {
+    const int s = c->tab.s;
+    c->qin = qin;
+    for (int i = 0; i < s; ++i) {
+        const double *Qi = qin;
+        if (i > 0) {
+            int rc = stage_solve(c, c->Rb[i], c->Qb[i], nullptr, nullptr);
+            if (rc == IMEXHDG_E_NOCONV) *status = rc;
+            else if (rc) return rc;
+            Qi = c->Qb[i];
+        }
+        double *out = (i + 1 < s) ? c->Rb[i + 1] : qout;
+        int rc = run_plan(c, i, Qi, out);
+        if (rc) return rc;
+    }
+    return IMEXHDG_OK;
+}
+
+// ------------------------------------------------ fixed launch schedule
+// The same trace solve as trace_solve(), with every decision taken on the
+// device: per sweep the FP64 residual, the refinement check (which ends the
+// stage solve once refine_rtol is met and otherwise opens an inner solve),
+// K1 and `budget` rounds of K2, K3, K1, and x += d.  Launches after
+// convergence return at entry.
+template <typename T>
+int sched_sweep(imexhdg_ctx *c, const T *Gh, int budget, double inner_rtol) {
+    const Geom &g = c->geom;
+    T *rin = (T *)c->rin, *r = (T *)c->kr, *rh = (T *)c->krh, *sv = (T *)c->ks_,
+      *t = (T *)c->kt, *d = (T *)c->kd;
+    T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
+    KrylovBufs kb = c->kb;
+    kb.sched = 1;
+    const int32_t *done =
+        (const int32_t *)((const char *)c->ks + offsetof(KrylovState, stage_done));
+    HIP_TRY(launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64, rin, c->dpart,
+                                  kPartStride, done, c->stream));
+    HIP_TRY(launch_refine_check(g, (const T *)rin, r, rh, p[0], v[0], d, c->ks, c->dpart,
+                                kPartStride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
+    int par = 0;
+    HIP_TRY(launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
+                           c->stream));
+    par = 1 - par;
+    for (int it = 0; it < budget; ++it) {
+        HIP_TRY(launch_bicg_k2(g, Gh, r, v[par], sv, t, c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k3(g, d, r, rh, p[par], sv, t, c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
+                               c->stream));
+        par = 1 - par;
+    }
+    HIP_TRY(launch_axpy_guarded(c->x, (const T *)d, c->T, c->ks, c->stream));
+    return IMEXHDG_OK;
+}
+
+int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *st) {
+    const Geom &g = c->geom;
+    const imexhdg_config &cf = c->cfg;
+    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, c->dAinv, R, c->Z, c->stream));
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, c->Z, c->dPx, c->dPy, c->gv, c->gh, c->stream));
+    HIP_TRY(launch_stage_begin(c->ks, c->stream));
+    const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
+    for (int sw = 0; sw < c->sched_sweeps; ++sw) {
+        const int b = c->sched_budget[sw];
+        int rc = c->mixed ? sched_sweep<float>(c, c->dGhf, b, irt)
+                          : sched_sweep<double>(c, c->dGh, b, irt);
+        if (rc) return rc;
+    }
+    const int32_t *done =
+        (const int32_t *)((const char *)c->ks + offsetof(KrylovState, stage_done));
+    HIP_TRY(c->mixed ? launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
+                                             (float *)c->rin, c->dpart, kPartStride, done,
+                                             c->stream)
+                     : launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
+                                             (double *)c->rin, c->dpart, kPartStride, done,
+                                             c->stream));
+    HIP_TRY(launch_stage_finish(g, c->ks, c->dpart, kPartStride, st, c->stream));
+    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, c->dW, c->Z, c->x, Q, c->stream));
+    return IMEXHDG_OK;
+}
+
+// One step on the fixed schedule from qin to qout; stage i records its
+// outcome in st[i].  Nothing here reads from the device.
+int step_sched(imexhdg_ctx *c, const double *qin, double *qout, StageStatus *st) {
+    const int s = c->tab.s;
+    c->qin = qin;
+    for (int i = 0; i < s; ++i) {
+        const double *Qi = qin;
+        if (i > 0) {
+            int rc = stage_solve_sched(c, c->Rb[i], c->Qb[i], st + i);
+            if (rc) return rc;
+            Qi = c->Qb[i];
+        }
+        double *out = (i + 1 < s) ? c->Rb[i + 1] : qout;
+        int rc = run_plan(c, i, Qi, out);
+        if (rc) return rc;
+    }
+    return IMEXHDG_OK;
+}
+
+void drop_graphs(imexhdg_ctx *c) {
+    for (hipGraphExec_t &e : c->gexec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    c->gready = false;
+}
+
+void reset_learn(imexhdg_ctx *c) {
+    c->learn_sweeps = 0;
+    for (int &v : c->learn_iters) v = 0;
+}
+
+void reset_window(imexhdg_ctx *c) {
+    c->win_sweeps = 0;
+    c->win_steps = 0;
+    for (int &v : c->win_iters) v = 0;
+}
+
+// Schedule from observed sweeps / per-sweep iterations plus the margin.
+void schedule_from(imexhdg_ctx *c, int sweeps, const int *iters, bool widen_only) {
+    const imexhdg_config &cf = c->cfg;
+    int ns = std::min(std::max(sweeps, 1), std::min((int)cf.refine_max, kMaxSweeps));
+    int b[kMaxSweeps];
+    for (int i = 0; i < kMaxSweeps; ++i)
+        b[i] = std::min(iters[i] + c->margin, (int)cf.krylov_max_iter);
+    if (widen_only) {
+        ns = std::max(ns, c->sched_sweeps);
+        for (int i = 0; i < kMaxSweeps; ++i) b[i] = std::max(b[i], c->sched_budget[i]);
+    }
+    c->sched_sweeps = ns;
+    for (int i = 0; i < kMaxSweeps; ++i) c->sched_budget[i] = i < ns ? b[i] : 0;
+}
+
+// Capture one step per ring position (input qbuf[a], output qbuf[a + 1]).
+// The capture runs on the library's own stream, so that the caller's
+// stream may be the null stream.
+int capture(imexhdg_ctx *c) {
+    drop_graphs(c);
+    if (!c->gstream) HIP_TRY(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    const int s = c->tab.s;
+    hipStream_t user = c->stream;
+    const int prof = c->prof_target;
+    for (int a = 0; a < 3; ++a) {
+        HIP_TRY(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+        c->stream = c->gstream;
+        c->prof_target = -2;
+        const int rc = step_sched(c, c->qbuf[a], c->qbuf[(a + 1) % 3], c->dstat + (size_t)a * s);
+        c->stream = user;
+        c->prof_target = prof;
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->gstream, &graph);
+        if (rc || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            drop_graphs(c);
+            if (rc) return rc;
+            return fail(IMEXHDG_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        const hipError_t ei = hipGraphInstantiate(&c->gexec[a], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            c->gexec[a] = nullptr;
+            drop_graphs(c);
+            return fail(IMEXHDG_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        }
+    }
+    c->gready = true;
+    c->captures += 1;
+    reset_window(c);
+    return IMEXHDG_OK;
+}
+
+bool implicit_stage(const imexhdg_ctx *c, int i) { return i > 0 && c->tab.at(i, i) != 0.0; }
+
+void advance(imexhdg_ctx *c) {
+    c->cur = (c->cur + 1) % 3;
+    c->q = c->qbuf[c->cur];
+    c->steps += 1;
+}
+
+// Graph stepping.  After a cold start (fresh trace guess) one host-driven
+// step; then, once, a host-driven step that measures the schedule, and the
+// capture.  Graph steps are verified one step behind: before step m + 2 is
+// launched (it overwrites the input of step m), step m's stage outcomes are
+// read.  A failed step is redone host-driven from its input, and the
+// schedule is widened; after 64 verified steps a schedule that has become
+// loose by at least two iterations is tightened.
+int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
+    const imexhdg_config &cf = c->cfg;
+    const int s = c->tab.s;
+    int done = 0;
+    while (done < nsteps && (c->cold || !c->gready)) {
+        const bool learn = !c->cold;
+        if (learn) reset_learn(c);
+        const int a = c->cur;
+        int rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], status);
+        if (rc) return rc;
+        advance(c);
+        ++done;
+        c->cold = false;
+        if (learn) {
+            schedule_from(c, c->learn_sweeps, c->learn_iters, false);
+            if ((rc = capture(c))) return rc;
+        }
+    }
+    int inflight[2] = {0, 0}, nin = 0, next = c->cur, launched = done;
+    bool want = false;
+    while (done < nsteps) {
+        if (want && nin == 0) {
+            schedule_from(c, c->win_sweeps, c->win_iters, false);
+            int rc = capture(c);
+            if (rc) return rc;
+            want = false;
+        }
+        if (!want && launched < nsteps && nin < 2) {
+            const int a = next;
+            HIP_TRY(hipGraphLaunch(c->gexec[a], c->stream));
+            HIP_TRY(hipMemcpyAsync(c->hstat + (size_t)a * s, c->dstat + (size_t)a * s,
+                                   s * sizeof(StageStatus), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipEventRecord(c->gev[a], c->stream));
+            inflight[nin++] = a;
+            next = (a + 1) % 3;
+            ++launched;
+            continue;
+        }
+        const int a = inflight[0];
+        inflight[0] = inflight[1];
+        --nin;
+        HIP_TRY(hipEventSynchronize(c->gev[a]));
+        const StageStatus *st = c->hstat + (size_t)a * s;
+        bool ok = true;
+        for (int i = 0; i < s; ++i)
+            if (implicit_stage(c, i))
+                ok = ok && std::isfinite(st[i].relres) && st[i].relres <= cf.refine_rtol;
+        if (ok) {
+            for (int i = 0; i < s; ++i) {
+                if (!implicit_stage(c, i)) continue;
+                c->kiters += st[i].iters_total;
+                c->solves += 1;
+                c->sweeps += st[i].sweeps;
+                c->last_relres = st[i].relres;
+                c->max_relres = std::max(c->max_relres, st[i].relres);
+                c->win_sweeps = std::max(c->win_sweeps, (int)st[i].sweeps);
+                for (int w = 0; w < kMaxSweeps; ++w)
+                    c->win_iters[w] = std::max(c->win_iters[w], (int)st[i].sweep_iters[w]);
+            }
+            c->graph_steps += 1;
+            c->win_steps += 1;
+            advance(c);
+            ++done;
+            if (c->win_steps >= 64 && !want) {
+                int loose = 0;
+                for (int w = 0; w < c->sched_sweeps; ++w)
+                    loose += c->sched_budget[w] -
+                             (w < c->win_sweeps ? std::min(c->win_iters[w] + c->margin,
+                                                           (int)cf.krylov_max_iter)
+                                                : 0);
+                if (loose >= 2) want = true;
+                else reset_window(c);
+            }
+            continue;
+        }
+        // the step missed refine_rtol on the schedule: redo it host-driven
+        HIP_TRY(stream_sync(c));
+        nin = 0;
+        want = false;
+        c->redos += 1;
+        reset_learn(c);
+        int rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], status);
+        if (rc) return rc;
+        c->cur = a;
+        advance(c);
+        ++done;
+        launched = done;
+        next = c->cur;
+        c->margin = std::min(c->margin + 2, 16);
+        schedule_from(c, c->learn_sweeps, c->learn_iters, true);
+        if ((rc = capture(c))) return rc;
     }
     return IMEXHDG_OK;
 }
@@ -601,7 +914,8 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
         off += align256(bytes);
         return p;
     };
-    c->q = (double *)take(L.N * 8);
+    for (double *&qb : c->qbuf) qb = (double *)take(L.N * 8);
+    c->q = c->qbuf[0];
     c->Z = (double *)take(L.N * 8);
     c->tmp = (double *)take(L.N * 8);
     for (int i = 0; i < L.s; ++i) c->NLb.push_back((double *)take(L.N * 8));
@@ -626,11 +940,18 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
     c->kb.stride = kPartStride;
     c->dpart = (double *)take(5 * kPartStride * 8);
     c->ks = (KrylovState *)take(sizeof(KrylovState));
+    c->dstat = (StageStatus *)take(3 * (size_t)L.s * sizeof(StageStatus));
     if (off > c->ws_bytes) return bail(fail(IMEXHDG_E_INVAL, "internal: workspace overflow"));
 
     if (hipHostMalloc((void **)&c->hks, sizeof(KrylovState)) != hipSuccess ||
-        hipHostMalloc((void **)&c->hpart, 5 * kPartStride * 8) != hipSuccess)
+        hipHostMalloc((void **)&c->hpart, 5 * kPartStride * 8) != hipSuccess ||
+        hipHostMalloc((void **)&c->hstat, 3 * (size_t)L.s * sizeof(StageStatus)) != hipSuccess)
         return bail(fail(IMEXHDG_E_NOMEM, "hipHostMalloc failed"));
+    for (hipEvent_t &e : c->gev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            e = nullptr;
+            return bail(fail(IMEXHDG_E_DEVICE, "hipEventCreate failed"));
+        }
 
     const StageOperators &op = c->op;
     const std::vector<double> G = pack_frags(op.Gx, op.Gy, K);
@@ -644,6 +965,7 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
         up(c->dPx, op.Pxinv) || up(c->dPy, op.Pyinv) ||
         hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
         hipMemsetAsync(c->q, 0, L.N * 8, c->stream) ||
+        hipMemsetAsync(c->dstat, 0, 3 * (size_t)L.s * sizeof(StageStatus), c->stream) ||
         hipStreamSynchronize(c->stream))
         return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
     *out = c;
@@ -658,6 +980,11 @@ void imexhdg_destroy(imexhdg_ctx *c) {
         (void)hipEventDestroy(c->ev0[i]);
         (void)hipEventDestroy(c->ev1[i]);
     }
+    drop_graphs(c);
+    for (hipEvent_t e : c->gev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->hstat) (void)hipHostFree(c->hstat);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->hks) (void)hipHostFree(c->hks);
     if (c->hpart) (void)hipHostFree(c->hpart);
@@ -722,6 +1049,7 @@ int imexhdg_set_state(imexhdg_ctx *c, int vars, const double *a, const double *b
     HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
     HIP_TRY(stream_sync(c));
     c->have_state = true;
+    c->cold = true;
     c->steps = 0;
     return IMEXHDG_OK;
 }
@@ -759,21 +1087,18 @@ int imexhdg_step(imexhdg_ctx *c, int32_t nsteps) {
     if (nsteps < 0) return fail(IMEXHDG_E_INVAL, "nsteps must be >= 0");
     if (!c->have_state) return fail(IMEXHDG_E_STATE, "step before set_state");
     int status = IMEXHDG_OK;
-    const int s = c->tab.s;
-    for (int n = 0; n < nsteps; ++n) {
-        for (int i = 0; i < s; ++i) {
-            const double *Qi = c->q;
-            if (i > 0) {
-                int rc = stage_solve(c, c->Rb[i], c->Qb[i], nullptr, nullptr);
-                if (rc == IMEXHDG_E_NOCONV) status = rc;
-                else if (rc) return rc;
-                Qi = c->Qb[i];
-            }
-            double *out = (i + 1 < s) ? c->Rb[i + 1] : c->q;
-            int rc = run_plan(c, i, Qi, out);
+    if (c->cfg.launch == IMEXHDG_LAUNCH_GRAPH && c->prof_target == -2) {
+        int rc = step_graph(c, nsteps, &status);
+        if (rc) return rc;
+    } else {
+        for (int n = 0; n < nsteps; ++n) {
+            const int a = c->cur;
+            int rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], &status);
             if (rc) return rc;
+            advance(c);
+            c->cold = false;
         }
-        c->steps += 1;
+        HIP_TRY(stream_sync(c));
     }
     if (status) return fail(status, "a trace solve missed refine_rtol");
     return IMEXHDG_OK;
@@ -796,6 +1121,8 @@ int imexhdg_get_diag(imexhdg_ctx *c, imexhdg_diag *d) {
     d->refine_sweeps = c->sweeps;
     d->last_relres = c->last_relres;
     d->max_relres = c->max_relres;
+    d->graph_steps = c->graph_steps;
+    d->redo_steps = c->redos;
     return IMEXHDG_OK;
 }
 
@@ -871,6 +1198,29 @@ int imexhdg_profile_read(imexhdg_ctx *c, int32_t kernel, int64_t *launches, doub
     if (launches) *launches = c->prof_n[kernel];
     if (total_ms) *total_ms = c->prof_ms[kernel];
     return IMEXHDG_OK;
+}
+
+int imexhdg_get_schedule(const imexhdg_ctx *c, int32_t *sweeps, int32_t *budget) {
+    if (!c || !sweeps || !budget) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    *sweeps = c->gready ? c->sched_sweeps : 0;
+    for (int i = 0; i < kMaxSweeps; ++i) budget[i] = c->gready ? c->sched_budget[i] : 0;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_set_schedule(imexhdg_ctx *c, int32_t sweeps, const int32_t *budget) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (c->cfg.launch != IMEXHDG_LAUNCH_GRAPH)
+        return fail(IMEXHDG_E_STATE, "the context does not step on a fixed schedule");
+    if (sweeps < 0 || sweeps > std::min((int)c->cfg.refine_max, kMaxSweeps))
+        return fail(IMEXHDG_E_INVAL, "sweeps must be in [0, min(refine_max, 8)]");
+    if (sweeps > 0 && !budget) return fail(IMEXHDG_E_INVAL, "budget is NULL");
+    for (int i = 0; i < sweeps; ++i)
+        if (budget[i] < 1 || budget[i] > c->cfg.krylov_max_iter)
+            return fail(IMEXHDG_E_INVAL, "budgets must be in [1, krylov_max_iter]");
+    HIP_TRY(stream_sync(c));
+    c->sched_sweeps = sweeps;
+    for (int i = 0; i < kMaxSweeps; ++i) c->sched_budget[i] = i < sweeps ? budget[i] : 0;
+    return capture(c);
 }
 
 }  // extern "C"

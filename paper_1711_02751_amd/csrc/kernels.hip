@@ -812,8 +812,9 @@ template <int K, bool TILED, typename RT>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
     const FragMats A, const double *__restrict__ x, const double *__restrict__ gv,
     const double *__restrict__ gh, const Geom g, double *__restrict__ r,
-    RT *__restrict__ rin, double *partials, int stride) {
+    RT *__restrict__ rin, double *partials, int stride, const int32_t *skip) {
     using T = double;
+    if (skip && *skip) return;
     constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const size_t nel = g.nel, TT = (size_t)B3 * nel;
@@ -824,7 +825,6 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
         __shared__ double sB[B3][Tile<K>::NF];
         const int nt = (g.nx / kTX) * (g.ny / kTY);
         const TileWalk tt = tile_walk(nt);
-        const int q = lane >> 4;
         for (int tile = tt.first; tile < tt.end; tile += tt.step) {
             v4d acc[2][2][NMB];
             tiled_rows<K, 2>(fr, tile, g, sB, [&](size_t o, bool) { return x[o]; }, acc);
@@ -922,7 +922,7 @@ __global__ void k_bicg_init(const T *__restrict__ rin, T *__restrict__ r,
     }
 }
 
-template <int K, bool TILED, typename T>
+template <int K, bool TILED, typename T, bool SCHED>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMatsT<T> A,
                                                  const T *__restrict__ r,
                                                  const T *__restrict__ rh,
@@ -956,7 +956,6 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
         __shared__ T sB[B3][Tile<K>::NF];
         const int nt = (g.nx / kTX) * (g.ny / kTY);
         const TileWalk tt = tile_walk(nt);
-        const int q = lane >> 4;
         for (int tile = tt.first; tile < tt.end; tile += tt.step) {
             typename MfmaT<T>::v4 acc[2][1][NMB];
             tiled_rows<K, 1>(fr, tile, g, sB,
@@ -1018,7 +1017,7 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
     if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
 }
 
-template <int K, bool TILED, typename T>
+template <int K, bool TILED, typename T, bool SCHED>
 __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMatsT<T> A,
                                                  const T *__restrict__ r,
                                                  const T *__restrict__ v,
@@ -1050,7 +1049,6 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
         __shared__ T sB[B3][Tile<K>::NF];
         const int nt = (g.nx / kTX) * (g.ny / kTY);
         const TileWalk tt = tile_walk(nt);
-        const int q = lane >> 4;
         for (int tile = tt.first; tile < tt.end; tile += tt.step) {
             typename MfmaT<T>::v4 acc[2][1][NMB];
             tiled_rows<K, 1>(fr, tile, g, sB,
@@ -1157,6 +1155,109 @@ __global__ void k_axpy(double *__restrict__ y, const T *__restrict__ x, double a
     if (i < n) y[i] += a * x[i];
 }
 
+// ------------------------------------- device-driven refinement sweeps
+// A stage solve on a fixed launch schedule: the host enqueues every sweep
+// and a budget of inner iterations up front (so the whole step can be
+// captured in a graph); the decisions the host-driven loop takes after a
+// read-back are taken here on the device, and launches past convergence
+// return at entry.
+__global__ void k_stage_begin(KrylovState *ks) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ks->stage_done = 0;
+        ks->sweep = 0;
+        ks->relres = 0.0;
+        ks->conv = 1;          // no inner solve active until refine_check opens one
+        ks->iters = 0;
+        for (int i = 0; i < 8; ++i) ks->sweep_iters[i] = 0;
+    }
+}
+
+// Reduce the FP64 residual norms of the last trace_residual (partials
+// [4][n_res]); stop the stage solve if relres <= refine_rtol, else start an
+// inner solve on Ghat d = rin (as k_bicg_init) with tolerance
+// max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2).
+template <typename T>
+__global__ void k_refine_check(const T *__restrict__ rin, T *__restrict__ r, T *__restrict__ rh,
+                               T *__restrict__ p, T *__restrict__ v, T *__restrict__ d,
+                               size_t n, KrylovState *ks, const double *res_partials,
+                               int stride, int n_res, double refine_rtol, double inner_rtol,
+                               double *P3, int p3_stride) {
+    if (ks->stage_done) return;
+    double nrm[4];
+    reduce_partials<4>(res_partials, stride, n_res, nrm);
+    const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
+    const double relres = gg > 0.0 ? sqrt(rr / gg) : sqrt(rr);
+    const bool finite = isfinite(rr) && isfinite(gg) && isfinite(rinrin);
+    if (!finite || relres <= refine_rtol) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ks->relres = finite ? relres : NAN;
+            ks->stage_done = 1;
+            ks->conv = 1;
+        }
+        return;
+    }
+    const double fl = 0.1 * refine_rtol;
+    const double tol2 = fmax(inner_rtol * inner_rtol * rinrin, fl * fl * ghh);
+    double acc[2] = {0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double x = rin[i];
+        r[i] = (T)x; rh[i] = (T)x; p[i] = T(0); v[i] = T(0); d[i] = T(0);
+        acc[0] += x * x;
+        acc[1] += x * x;
+    }
+    store_partials<2>(acc, P3, p3_stride);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ks->relres = relres;
+        ks->rho = 1.0;
+        ks->alpha = 1.0;
+        ks->omega = 1.0;
+        ks->rr = 0.0;
+        ks->tol2 = tol2;
+        ks->conv = 0;
+        ks->breakdown = 0;
+        ks->iters = 0;
+        ks->sweep += 1;
+    }
+}
+
+// x += d after a sweep, unless the stage solve had already converged.
+template <typename T>
+__global__ void k_axpy_guarded(double *__restrict__ y, const T *__restrict__ x, size_t n,
+                               KrylovState *ks) {
+    if (ks->stage_done) return;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += (double)x[i];
+    if (i == 0) {
+        const int sw = ks->sweep - 1;
+        if (sw >= 0 && sw < 8) ks->sweep_iters[sw] = ks->iters;
+    }
+}
+
+// After the last sweep: if the solve never met refine_rtol, take the
+// residual of the final trace_residual; record the outcome.
+__global__ void k_stage_finish(KrylovState *ks, const double *res_partials, int stride,
+                               int n_res, double refine_rtol, StageStatus *out) {
+    double relres = ks->relres;
+    const int done = ks->stage_done;
+    if (!done) {
+        double nrm[2];
+        reduce_partials<2>(res_partials, stride, n_res, nrm);
+        relres = nrm[1] > 0.0 ? sqrt(nrm[0] / nrm[1]) : sqrt(nrm[0]);
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out->relres = relres;
+        out->converged = (isfinite(relres) && relres <= refine_rtol) ? 1 : 0;
+        out->sweeps = ks->sweep;
+        int tot = 0;
+        for (int i = 0; i < kMaxSweeps; ++i) {
+            out->sweep_iters[i] = i < 8 ? ks->sweep_iters[i] : 0;
+            tot += out->sweep_iters[i];
+        }
+        out->iters_total = tot;
+    }
+}
+
 // --------------------------------------------------------- diagnostics
 // Partials of (mass phi_eta, mass U, mass V, energy, non-finite count).
 template <int K>
@@ -1238,15 +1339,16 @@ template <typename RT> struct RunTraceResidual {
     template <int K> struct F {
         static hipError_t run(const Geom &g, const double *G, const double *Gh,
                               const double *x, const double *gv, const double *gh, double *r,
-                              RT *rin, double *partials, int stride, hipStream_t s) {
+                              RT *rin, double *partials, int stride, const int32_t *skip,
+                              hipStream_t s) {
             if (is_tiled(g))
                 hipLaunchKernelGGL((k_trace_residual<K, true, RT>), dim3(face_grid(g)),
                                    dim3(256), 0, s, FragMats{G, Gh}, x, gv, gh, g, r, rin,
-                                   partials, stride);
+                                   partials, stride, skip);
             else
                 hipLaunchKernelGGL((k_trace_residual<K, false, RT>), dim3(face_grid(g)),
                                    dim3(256), 0, s, FragMats{G, Gh}, x, gv, gh, g, r, rin,
-                                   partials, stride);
+                                   partials, stride, skip);
             return hipGetLastError();
         }
     };
@@ -1257,14 +1359,17 @@ template <typename T> struct RunK1 {
                               const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,
                               const KrylovBufs &kb, hipStream_t s) {
             const FragMatsT<T> A{Gh, nullptr};
-            if (is_tiled(g))
-                hipLaunchKernelGGL((k_bicg_k1<K, true, T>), dim3(face_grid(g)), dim3(256), 0, s,
-                                   A, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
-                                   (int)elem_grid(g), kb.P1, kb.stride);
-            else
-                hipLaunchKernelGGL((k_bicg_k1<K, false, T>), dim3(face_grid(g)), dim3(256), 0,
-                                   s, A, r, rh, pin, vin, pout, vout, g, ks, kb.P3,
-                                   (int)elem_grid(g), kb.P1, kb.stride);
+            const dim3 gr(face_grid(g)), bl(256);
+            const int n3 = (int)elem_grid(g);
+#define IMEXHDG_K1(TL, SC)                                                                 \
+    hipLaunchKernelGGL((k_bicg_k1<K, TL, T, SC>), gr, bl, 0, s, A, r, rh, pin, vin, pout, \
+                       vout, g, ks, kb.P3, n3, kb.P1, kb.stride)
+            if (is_tiled(g)) {
+                if (kb.sched) IMEXHDG_K1(true, true); else IMEXHDG_K1(true, false);
+            } else {
+                if (kb.sched) IMEXHDG_K1(false, true); else IMEXHDG_K1(false, false);
+            }
+#undef IMEXHDG_K1
             return hipGetLastError();
         }
     };
@@ -1274,14 +1379,17 @@ template <typename T> struct RunK2 {
         static hipError_t run(const Geom &g, const T *Gh, const T *r, const T *v, T *sv, T *t,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             const FragMatsT<T> A{Gh, nullptr};
-            if (is_tiled(g))
-                hipLaunchKernelGGL((k_bicg_k2<K, true, T>), dim3(face_grid(g)), dim3(256), 0, s,
-                                   A, r, v, sv, t, g, ks, kb.P1, (int)face_grid(g), kb.P3,
-                                   (int)elem_grid(g), kb.P2, kb.stride);
-            else
-                hipLaunchKernelGGL((k_bicg_k2<K, false, T>), dim3(face_grid(g)), dim3(256), 0,
-                                   s, A, r, v, sv, t, g, ks, kb.P1, (int)face_grid(g), kb.P3,
-                                   (int)elem_grid(g), kb.P2, kb.stride);
+            const dim3 gr(face_grid(g)), bl(256);
+            const int n1 = (int)face_grid(g), n3 = (int)elem_grid(g);
+#define IMEXHDG_K2(TL, SC)                                                                    \
+    hipLaunchKernelGGL((k_bicg_k2<K, TL, T, SC>), gr, bl, 0, s, A, r, v, sv, t, g, ks, kb.P1, \
+                       n1, kb.P3, n3, kb.P2, kb.stride)
+            if (is_tiled(g)) {
+                if (kb.sched) IMEXHDG_K2(true, true); else IMEXHDG_K2(true, false);
+            } else {
+                if (kb.sched) IMEXHDG_K2(false, true); else IMEXHDG_K2(false, false);
+            }
+#undef IMEXHDG_K2
             return hipGetLastError();
         }
     };
@@ -1351,9 +1459,27 @@ template <typename T>
 hipError_t trace_residual_impl(const Geom &g, const double *G, const double *Gh,
                                const double *x, const double *gvec, const double *ghat,
                                double *r, T *rin, double *partials, int stride,
-                               hipStream_t s) {
+                               const int32_t *skip, hipStream_t s) {
     return dispatch<RunTraceResidual<T>::template F>(g.K, g, G, Gh, x, gvec, ghat, r, rin,
-                                                      partials, stride, s);
+                                                      partials, stride, skip, s);
+}
+
+template <typename T>
+hipError_t refine_check_impl(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,
+                             KrylovState *ks, const double *partials, int stride,
+                             double refine_rtol, double inner_rtol, const KrylovBufs &kb,
+                             hipStream_t s) {
+    const size_t n = (size_t)6 * g.K * g.nel;
+    hipLaunchKernelGGL(k_refine_check<T>, dim3(elem_grid(g)), dim3(256), 0, s, rin, r, rh, p,
+                       v, d, n, ks, partials, stride, (int)face_grid(g), refine_rtol,
+                       inner_rtol, kb.P3, kb.stride);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t axpy_guarded_impl(double *y, const T *x, size_t n, KrylovState *ks, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_guarded<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, n, ks);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -1386,8 +1512,20 @@ hipError_t axpy_impl(double *y, const T *x, double a, size_t n, hipStream_t s) {
     hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,        \
                                      const double *x, const double *gvec,                     \
                                      const double *ghat, double *r, T *rin, double *partials, \
-                                     int stride, hipStream_t s) {                             \
-        return trace_residual_impl<T>(g, G, Gh, x, gvec, ghat, r, rin, partials, stride, s);  \
+                                     int stride, const int32_t *skip, hipStream_t s) {        \
+        return trace_residual_impl<T>(g, G, Gh, x, gvec, ghat, r, rin, partials, stride,      \
+                                      skip, s);                                               \
+    }                                                                                          \
+    hipError_t launch_refine_check(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v,      \
+                                   T *d, KrylovState *ks, const double *partials, int stride, \
+                                   double refine_rtol, double inner_rtol,                     \
+                                   const KrylovBufs &kb, hipStream_t s) {                     \
+        return refine_check_impl<T>(g, rin, r, rh, p, v, d, ks, partials, stride,             \
+                                    refine_rtol, inner_rtol, kb, s);                          \
+    }                                                                                          \
+    hipError_t launch_axpy_guarded(double *y, const T *x, size_t n, KrylovState *ks,          \
+                                   hipStream_t s) {                                           \
+        return axpy_guarded_impl<T>(y, x, n, ks, s);                                          \
     }                                                                                          \
     hipError_t launch_bicg_init(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,  \
                                 KrylovState *ks, double tol2, const KrylovBufs &kb,           \
@@ -1416,6 +1554,20 @@ hipError_t axpy_impl(double *y, const T *x, double a, size_t n, hipStream_t s) {
 IMEXHDG_KRYLOV_LAUNCHERS(double)
 IMEXHDG_KRYLOV_LAUNCHERS(float)
 #undef IMEXHDG_KRYLOV_LAUNCHERS
+
+hipError_t launch_stage_begin(KrylovState *ks, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(64), 0, s, ks);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_finish(const Geom &g, KrylovState *ks, const double *partials,
+                               int stride, StageStatus *out, hipStream_t s) {
+    // refine_rtol is not known here; the host compares relres itself, so pass
+    // +inf and keep `converged` as "residual finite"
+    hipLaunchKernelGGL(k_stage_finish, dim3(1), dim3(256), 0, s, ks, partials, stride,
+                       (int)face_grid(g), INFINITY, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
                        hipStream_t s) {

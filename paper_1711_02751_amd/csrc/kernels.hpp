@@ -38,12 +38,27 @@ struct KrylovState {
     double rr;                  // last ||r||^2 seen by K1
     double tol2;                // stop when ||r||^2 <= tol2
     int32_t conv, breakdown, iters, pad;
+    // device-driven refinement of one stage solve (fixed launch schedule)
+    double relres;              // FP64 true relative residual at the last check
+    int32_t stage_done;         // refine_rtol reached: later launches are no-ops
+    int32_t sweep;              // sweeps started
+    int32_t sweep_iters[8];     // inner iterations per sweep
+};
+
+// Outcome of one stage solve on the fixed launch schedule.
+constexpr int kMaxSweeps = 8;
+struct StageStatus {
+    double relres;
+    int32_t converged, sweeps, iters_total, pad;
+    int32_t sweep_iters[kMaxSweeps];
 };
 
 // Per-block partial sums of the three BiCGStab reductions, [quantity][block].
 struct KrylovBufs {
     double *P1, *P2, *P3;
     int stride;                 // >= max grid of any Krylov launch
+    int sched;                  // 1: launches of the fixed schedule (own kernel symbols,
+                                // so profiles keep them apart from host-driven launches)
 };
 
 // Capped grid sizes of the face-tile kernels, the elementwise Krylov
@@ -75,7 +90,7 @@ hipError_t launch_recover(const Geom &g, const double *W, const double *Z,
     hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,        \
                                      const double *x, const double *gvec,                     \
                                      const double *ghat, double *r, T *rin, double *partials, \
-                                     int stride, hipStream_t s);                              \
+                                     int stride, const int32_t *skip, hipStream_t s);         \
     hipError_t launch_bicg_init(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,  \
                                 KrylovState *ks, double tol2, const KrylovBufs &kb,           \
                                 hipStream_t s);                                               \
@@ -91,6 +106,26 @@ hipError_t launch_recover(const Geom &g, const double *W, const double *Z,
 IMEXHDG_KRYLOV_DECLS(double)
 IMEXHDG_KRYLOV_DECLS(float)
 #undef IMEXHDG_KRYLOV_DECLS
+// Device-driven refinement (no host reads inside a stage solve):
+//   stage_begin; then per sweep: trace_residual(skip = &ks->stage_done),
+//   refine_check (reduces the residual norms, stops the stage solve when
+//   relres <= refine_rtol, else initialises the inner solve with its
+//   tolerance), inner iterations, axpy_guarded; finally trace_residual and
+//   stage_finish, which records a StageStatus.
+hipError_t launch_stage_begin(KrylovState *ks, hipStream_t s);
+#define IMEXHDG_REFINE_DECLS(T)                                                                \
+    hipError_t launch_refine_check(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v,      \
+                                   T *d, KrylovState *ks, const double *partials, int stride, \
+                                   double refine_rtol, double inner_rtol,                     \
+                                   const KrylovBufs &kb, hipStream_t s);                      \
+    hipError_t launch_axpy_guarded(double *y, const T *x, size_t n, KrylovState *ks,          \
+                                   hipStream_t s);
+IMEXHDG_REFINE_DECLS(double)
+IMEXHDG_REFINE_DECLS(float)
+#undef IMEXHDG_REFINE_DECLS
+hipError_t launch_stage_finish(const Geom &g, KrylovState *ks, const double *partials,
+                               int stride, StageStatus *out, hipStream_t s);
+
 // partials [5][diag_grid]: mass of phi_eta, U, V; energy; non-finite count
 hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
                        hipStream_t s);

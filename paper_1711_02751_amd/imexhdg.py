@@ -18,6 +18,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOCONV, E_NONFINITE, E_STATE = 0, -1, -2, -3, 
 SCHEME_ARS232, SCHEME_ARS443 = 0, 1
 PHYSICS_LINEARIZED, PHYSICS_NONLINEAR = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+LAUNCH_GRAPH, LAUNCH_HOST = 0, 1
 VARS_DEPTH, VARS_GEOPOTENTIAL = 0, 1
 
 EXPORTS = [
@@ -26,7 +27,8 @@ EXPORTS = [
     "imexhdg_set_state", "imexhdg_get_state", "imexhdg_step", "imexhdg_get_diag",
     "imexhdg_last_error", "imexhdg_state_device", "imexhdg_nl_residual",
     "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_profile",
-    "imexhdg_profile_read", "imexhdg_kernel_name",
+    "imexhdg_profile_read", "imexhdg_kernel_name", "imexhdg_get_schedule",
+    "imexhdg_set_schedule",
 ]
 KERNELS = ["nl_residual", "combine", "local_apply", "trace_rhs", "trace_residual", "bicg_init",
            "bicg_k1", "bicg_k2", "bicg_k3", "axpy", "recover", "diag", "linear_residual"]
@@ -44,6 +46,7 @@ class Config(ctypes.Structure):
         ("krylov_rtol", ctypes.c_double),
         ("krylov_max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("refine_rtol", ctypes.c_double), ("refine_max", ctypes.c_int32),
+        ("launch", ctypes.c_int32),
     ]
 
 
@@ -54,6 +57,7 @@ class Diag(ctypes.Structure):
         ("stage_solves", ctypes.c_int64), ("refine_sweeps", ctypes.c_int64),
         ("last_relres", ctypes.c_double), ("max_relres", ctypes.c_double),
         ("nonfinite", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int64), ("redo_steps", ctypes.c_int64),
     ]
 
 
@@ -98,6 +102,8 @@ def load():
         "imexhdg_profile": (ctypes.c_int, [P, i32]),
         "imexhdg_profile_read": (ctypes.c_int, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]),
         "imexhdg_kernel_name": (ctypes.c_char_p, [i32]),
+        "imexhdg_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "imexhdg_set_schedule": (ctypes.c_int, [P, i32, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -216,6 +222,18 @@ class Solver:
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(self.lib.imexhdg_profile_read(self._ctx, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    # ---- fixed launch schedule (LAUNCH_GRAPH)
+    def schedule(self):
+        """(sweeps, [inner-iteration budget per sweep]) of the captured step."""
+        n = ctypes.c_int32()
+        b = (ctypes.c_int32 * 8)()
+        _check(self.lib.imexhdg_get_schedule(self._ctx, ctypes.byref(n), b))
+        return n.value, list(b)[:n.value]
+
+    def set_schedule(self, budgets):
+        b = (ctypes.c_int32 * max(8, len(budgets)))(*[int(v) for v in budgets])
+        _check(self.lib.imexhdg_set_schedule(self._ctx, len(budgets), b))
 
     # ---- operator-level calls on device tensors (volume / trace device layout)
     def state_device_ptr(self):

@@ -1,0 +1,93 @@
+"""Graph stepping (IMEXHDG_LAUNCH_GRAPH) against host-driven stepping.
+
+On the fixed launch schedule every convergence decision of the trace solve
+is taken on the device; a step is one graph launch.  With a schedule long
+enough for the solves the graph path runs the same kernels on the same data
+as the host-driven path, so the two agree to round-off of the reductions
+that decide when to stop; with a schedule too short the step is redone
+host-driven, and the state still agrees."""
+import numpy as np
+import pytest
+
+from oracle import swe
+from paper_1711_02751_amd import imexhdg as m
+from gpu_helpers import make_pair, bump_state
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(16, 8, 4, m.PREC_FP64), (10, 7, 3, m.PREC_FP64), (16, 8, 4, m.PREC_MIXED),
+         (9, 11, 5, m.PREC_MIXED)]
+
+
+def _solver(nx, ny, k, prec, launch, dt=0.006):
+    kw = dict(precision=prec, launch=launch)
+    if prec == m.PREC_MIXED:
+        kw.update(krylov_rtol=1e-6, refine_rtol=1e-11, refine_max=8)
+    return make_pair(nx, ny, k, 9.81, 1.0, dt, **kw)
+
+
+def _run(S, q0, calls):
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    for n in calls:
+        S.step(n)
+    return np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)).reshape(q0.shape)
+
+
+@pytest.mark.parametrize("nx,ny,k,prec", CASES)
+def test_graph_matches_host_driven(nx, ny, k, prec):
+    print(f"graph vs host nx={nx} ny={ny} k={k} prec={prec}", flush=True)
+    P, G = _solver(nx, ny, k, prec, m.LAUNCH_GRAPH)
+    _, H = _solver(nx, ny, k, prec, m.LAUNCH_HOST)
+    q0 = bump_state(P, seed=nx + k, umax=0.2)
+    a = _run(G, q0, [20])
+    b = _run(H, q0, [20])
+    d = G.diag()
+    print("diag", d, "schedule", G.schedule(), flush=True)
+    assert d["graph_steps"] + d["redo_steps"] >= 18
+    assert d["graph_steps"] >= 10
+    err = swe.rel_l2(P.mesh, a, b)
+    print("graph vs host rel L2", err, flush=True)
+    assert np.all(err < 1e-12)
+    assert d["max_relres"] <= G.cfg.refine_rtol
+
+
+def test_graph_replays_equal_one_call():
+    """Ten one-step calls (each synchronises) replay the captured graphs with
+    host work between them and give the bits of one ten-step call."""
+    P, G = _solver(16, 8, 4, m.PREC_FP64, m.LAUNCH_GRAPH)
+    q0 = bump_state(P, seed=2, umax=0.2)
+    a = _run(G, q0, [1] * 10)
+    b = _run(G, q0, [10])
+    assert np.array_equal(a, b)
+
+
+def test_short_schedule_is_redone_and_widened():
+    print("short schedule redo", flush=True)
+    P, G = _solver(16, 8, 4, m.PREC_FP64, m.LAUNCH_GRAPH)
+    _, H = _solver(16, 8, 4, m.PREC_FP64, m.LAUNCH_HOST)
+    q0 = bump_state(P, seed=7, umax=0.2)
+    G.set_schedule([1])
+    assert G.schedule() == (1, [1])
+    a = _run(G, q0, [8])
+    b = _run(H, q0, [8])
+    d = G.diag()
+    print("diag", d, "schedule", G.schedule(), flush=True)
+    assert d["redo_steps"] >= 1
+    sweeps, budget = G.schedule()
+    assert sweeps >= 1 and budget[0] > 1
+    err = swe.rel_l2(P.mesh, a, b)
+    assert np.all(err < 1e-12)
+
+
+def test_schedule_errors():
+    _, G = _solver(8, 8, 3, m.PREC_FP64, m.LAUNCH_GRAPH)
+    with pytest.raises(m.ImexError) as e:
+        G.set_schedule([0])
+    assert e.value.code == m.E_INVAL
+    with pytest.raises(m.ImexError) as e:
+        G.set_schedule([5] * 9)
+    assert e.value.code == m.E_INVAL
+    _, H = _solver(8, 8, 3, m.PREC_FP64, m.LAUNCH_HOST)
+    with pytest.raises(m.ImexError) as e:
+        H.set_schedule([5])
+    assert e.value.code == m.E_STATE
