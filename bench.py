@@ -153,6 +153,9 @@ def run_path(m, wl, precision, steps, warmup):
     n_dof = 3 * S.n_nodes
     log(f"[bench] {precision}: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {warmup}")
     S.step(max(warmup, 3))
+    fg, eg = S.autotune()
+    log(f"[bench] {precision}: autotuned grid caps: face {fg}, elementwise {eg}")
+    S.step(2)
     torch.cuda.synchronize()
     # short all-classes pass (host-driven) to find the dominant kernel
     S.profile(-1)
@@ -220,6 +223,7 @@ def run_path(m, wl, precision, steps, warmup):
     res = {"value": value, "ms_per_step": 1000.0 * el / steps, "roofline": roof,
            "host_driven_ms_per_step": 1000.0 * el_host / steps,
            "schedule": {"sweeps": sched[0], "inner_budget": sched[1]},
+           "grid_caps": {"face": fg, "elementwise": eg},
            "graph_steps": d1["graph_steps"] - d0["graph_steps"],
            "redone_steps": d1["redo_steps"] - d0["redo_steps"],
            "krylov_iters_per_stage": iters, "max_trace_relres": d1["max_relres"],
@@ -283,8 +287,8 @@ def main():
         "roofline": head["roofline"],
         "krylov_iters_per_stage": head["krylov_iters_per_stage"],
         "max_trace_relres": head["max_trace_relres"],
-        "launch": {k: head[k] for k in ("schedule", "graph_steps", "redone_steps",
-                                        "host_driven_ms_per_step")},
+        "launch": {k: head[k] for k in ("schedule", "grid_caps", "graph_steps",
+                                        "redone_steps", "host_driven_ms_per_step")},
         "kernels": head["kernels"],
     }
     if smx is not None:
@@ -292,8 +296,8 @@ def main():
         err = swe.rel_l2(mesh, smx.reshape(mesh.shape), s64.reshape(mesh.shape))
         out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                        "roofline": fp64["roofline"],
-                       "launch": {k: fp64[k] for k in ("schedule", "graph_steps",
-                                                       "redone_steps",
+                       "launch": {k: fp64[k] for k in ("schedule", "grid_caps",
+                                                       "graph_steps", "redone_steps",
                                                        "host_driven_ms_per_step")},
                        "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
         out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]

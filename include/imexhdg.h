@@ -249,6 +249,28 @@ const char *imexhdg_kernel_name(int32_t kernel);
 int imexhdg_get_schedule(const imexhdg_ctx *ctx, int32_t *sweeps, int32_t *budget);
 int imexhdg_set_schedule(imexhdg_ctx *ctx, int32_t sweeps, const int32_t *budget);
 
+/* ---------------- launch geometry and its autotuner
+ * The face-tile Krylov kernels (trace residual, BiCGStab K1 and K2) deal
+ * 64-element tiles to at most `face_grid` blocks; the elementwise Krylov
+ * kernels run grid-stride loops over at most `elem_grid` blocks.  Both
+ * default to 1024.  Larger grids put more waves in flight, smaller ones
+ * shorten the per-block re-reduction of the previous kernel's partial sums.
+ * set: each value in [8, 4096]; recaptures the step graphs if any.
+ * autotune: times two host-driven steps from the current state for each
+ * candidate (256 ... 4096 blocks, first face_grid, then elem_grid) with the
+ * kernel event profiler, weighting each kernel class's mean launch time by
+ * its launch count, and keeps the fastest.  The state is restored and the
+ * trace guess reset afterwards, as by set_state; the solver counters are
+ * kept.  If cache_path is not NULL and the file holds a line for this
+ * device, degree, mesh and precision, that choice is applied without
+ * timing; otherwise the choice is appended to the file (created if
+ * missing).  Chosen values are returned through face_grid / elem_grid when
+ * those are not NULL.  IMEXHDG_E_STATE without a state; IMEXHDG_E_INVAL
+ * for a malformed cache line.                                             */
+int imexhdg_set_launch_geometry(imexhdg_ctx *ctx, int32_t face_grid, int32_t elem_grid);
+int imexhdg_autotune(imexhdg_ctx *ctx, const char *cache_path, int32_t *face_grid,
+                     int32_t *elem_grid);
+
 #ifdef __cplusplus
 }
 #endif

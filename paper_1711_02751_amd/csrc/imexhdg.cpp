@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -104,7 +106,7 @@ struct imexhdg_ctx {
     // qbuf[cur] and a step from qbuf[a] writes qbuf[(a + 1) % 3]
     double *qbuf[3] = {nullptr, nullptr, nullptr};
     int cur = 0;
-    double *q = nullptr, *Z = nullptr, *tmp = nullptr;
+    double *q = nullptr, *Z = nullptr, *save = nullptr;   // save: autotuner's copy of q
     const double *qin = nullptr;      // q^n of the step being enqueued
     std::vector<double *> NLb, Qb, Rb;
     double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr;
@@ -188,7 +190,7 @@ std::vector<double> pack_frags(const std::vector<double> &Gx, const std::vector<
 }
 
 // stride of every partial-sum array; no launch has a larger grid
-constexpr int kPartStride = 1024;
+constexpr int kPartStride = kMaxLaunchGrid;
 
 struct Layout {
     size_t N, T, n_loc, n_tr, max_blocks, total;
@@ -205,7 +207,7 @@ Layout layout_of(const imexhdg_config &c) {
     L.s = (c.scheme == IMEXHDG_SCHEME_ARS443) ? 5 : 3;
     L.max_blocks = kPartStride;
     size_t t = 0;
-    t += 5 * align256(L.N * 8);                       // q ring (3), Z, tmp
+    t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     const size_t isz = (c.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
     t += 4 * align256(L.T * 8);                        // FP64 trace vectors
@@ -374,8 +376,8 @@ int sync_read_ks(imexhdg_ctx *c) {
 
 // Sum partials [nq][n] on the host in a fixed order (deterministic).
 int read_partials(imexhdg_ctx *c, int nq, unsigned n, double *out) {
-    HIP_TRY(hipMemcpyAsync(c->hpart, c->dpart, (size_t)nq * kPartStride * 8,
-                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpy2DAsync(c->hpart, kPartStride * 8, c->dpart, kPartStride * 8, (size_t)n * 8,
+                             nq, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(stream_sync(c));
     for (int q = 0; q < nq; ++q) {
         double s = 0.0;
@@ -891,6 +893,8 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
         for (int i = 0; i < K; ++i)
             g.mass[j * K + i] = (cfg->Lx / cfg->nx / 2.0) * (cfg->Ly / cfg->ny / 2.0) *
                                 c->ref.w[i] * c->ref.w[j];
+    g.fgrid = 1024;
+    g.egrid = 1024;
     c->N = L.N;
     c->T = L.T;
     c->nnodes = L.N / 3;
@@ -917,7 +921,7 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
     for (double *&qb : c->qbuf) qb = (double *)take(L.N * 8);
     c->q = c->qbuf[0];
     c->Z = (double *)take(L.N * 8);
-    c->tmp = (double *)take(L.N * 8);
+    c->save = (double *)take(L.N * 8);
     for (int i = 0; i < L.s; ++i) c->NLb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
@@ -1221,6 +1225,147 @@ int imexhdg_set_schedule(imexhdg_ctx *c, int32_t sweeps, const int32_t *budget) 
     c->sched_sweeps = sweeps;
     for (int i = 0; i < kMaxSweeps; ++i) c->sched_budget[i] = i < sweeps ? budget[i] : 0;
     return capture(c);
+}
+
+int imexhdg_set_launch_geometry(imexhdg_ctx *c, int32_t face_grid, int32_t elem_grid) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (face_grid < 8 || face_grid > kMaxLaunchGrid || elem_grid < 8 || elem_grid > kMaxLaunchGrid)
+        return fail(IMEXHDG_E_INVAL, "grid caps must be in [8, 4096]");
+    HIP_TRY(stream_sync(c));
+    c->geom.fgrid = face_grid;
+    c->geom.egrid = elem_grid;
+    if (c->gready) return capture(c);
+    return IMEXHDG_OK;
+}
+
+// Two host-driven steps from the saved state with every kernel class
+// timed; per-class mean launch time (ms) and launch count.
+static int tune_trial(imexhdg_ctx *c, int fg, int eg, double *avg, int64_t *cnt) {
+    c->geom.fgrid = fg;
+    c->geom.egrid = eg;
+    HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
+    int rc = imexhdg_profile(c, -1);
+    if (rc) return rc;
+    int status = IMEXHDG_OK;
+    for (int i = 0; i < 2; ++i) {
+        const int a = c->cur;
+        rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], &status);
+        if (rc) return rc;
+        c->cur = (a + 1) % 3;
+        c->q = c->qbuf[c->cur];
+    }
+    HIP_TRY(stream_sync(c));
+    for (int k = 0; k < IMEXHDG_K_COUNT; ++k) {
+        cnt[k] = c->prof_n[k];
+        avg[k] = c->prof_n[k] ? c->prof_ms[k] / (double)c->prof_n[k] : 0.0;
+    }
+    return IMEXHDG_OK;
+}
+
+int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
+                     int32_t *elem_grid) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (!c->have_state) return fail(IMEXHDG_E_STATE, "autotune needs a state");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+    std::ostringstream ks;
+    ks << prop.gcnArchName << "/" << prop.multiProcessorCount << "cu k=" << c->cfg.degree
+       << " mesh=" << c->cfg.nx << "x" << c->cfg.ny << " prec=" << c->cfg.precision;
+    const std::string key = ks.str();
+    int best_f = -1, best_e = -1;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (in && std::getline(in, line)) {
+            const size_t t1 = line.find('\t');
+            if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size())
+                continue;
+            std::istringstream rest(line.substr(t1 + 1));
+            int f = 0, e = 0;
+            if (!(rest >> f >> e) || f < 8 || f > kMaxLaunchGrid || e < 8 || e > kMaxLaunchGrid)
+                return fail(IMEXHDG_E_INVAL, "malformed autotune cache line: " + line);
+            best_f = f;
+            best_e = e;
+        }
+    }
+    if (best_f < 0) {
+        // time the candidates from a copy of the current state
+        HIP_TRY(stream_sync(c));
+        HIP_TRY(hipMemcpyAsync(c->save, c->q, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+        const int64_t keep[4] = {c->steps, c->kiters, c->solves, c->sweeps};
+        const double keep_r[2] = {c->last_relres, c->max_relres};
+        double avg[IMEXHDG_K_COUNT], base_avg[IMEXHDG_K_COUNT];
+        int64_t cnt[IMEXHDG_K_COUNT], w[IMEXHDG_K_COUNT];
+        const int face_k[3] = {IMEXHDG_K_TRACE_RESID, IMEXHDG_K_BICG_K1, IMEXHDG_K_BICG_K2};
+        const int elem_k[2] = {IMEXHDG_K_BICG_INIT, IMEXHDG_K_BICG_K3};
+        const int cand[5] = {256, 512, 1024, 2048, 4096};
+        const int f0 = c->geom.fgrid, e0 = c->geom.egrid;
+        int rc = tune_trial(c, f0, e0, base_avg, w);
+        auto score = [&](const double *a, const int *ks_, int nk) {
+            double s = 0.0;
+            for (int i = 0; i < nk; ++i) s += a[ks_[i]] * (double)w[ks_[i]];
+            return s;
+        };
+        best_f = f0;
+        best_e = e0;
+        double best = rc ? 0.0 : score(base_avg, face_k, 3);
+        Geom probe = c->geom;
+        for (int i = 0; i < 5 && !rc; ++i) {
+            probe.fgrid = cand[i];
+            Geom cur = c->geom;
+            cur.fgrid = best_f;
+            if (imexhdg::face_grid(probe) == imexhdg::face_grid(cur)) continue;
+            if ((rc = tune_trial(c, cand[i], e0, avg, cnt))) break;
+            const double sc = score(avg, face_k, 3);
+            if (sc < best) {
+                best = sc;
+                best_f = cand[i];
+            }
+        }
+        if (!rc) best = score(base_avg, elem_k, 2);
+        for (int i = 0; i < 5 && !rc; ++i) {
+            probe.egrid = cand[i];
+            Geom cur = c->geom;
+            cur.egrid = best_e;
+            if (imexhdg::elem_grid(probe) == imexhdg::elem_grid(cur)) continue;
+            if ((rc = tune_trial(c, best_f, cand[i], avg, cnt))) break;
+            const double sc = score(avg, elem_k, 2);
+            if (sc < best) {
+                best = sc;
+                best_e = cand[i];
+            }
+        }
+        // restore the state, the counters and the profiler
+        c->prof_target = -2;
+        c->ev_used = 0;
+        for (int k = 0; k < IMEXHDG_K_COUNT; ++k) {
+            c->prof_ms[k] = 0.0;
+            c->prof_n[k] = 0;
+        }
+        HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
+        HIP_TRY(stream_sync(c));
+        c->steps = keep[0];
+        c->kiters = keep[1];
+        c->solves = keep[2];
+        c->sweeps = keep[3];
+        c->last_relres = keep_r[0];
+        c->max_relres = keep_r[1];
+        c->cold = true;
+        if (rc) {
+            c->geom.fgrid = f0;
+            c->geom.egrid = e0;
+            return rc;
+        }
+        if (cache_path) {
+            std::ofstream out(cache_path, std::ios::app);
+            if (out) out << key << '\t' << best_f << '\t' << best_e << '\n';
+        }
+    }
+    if (face_grid) *face_grid = best_f;
+    if (elem_grid) *elem_grid = best_e;
+    return imexhdg_set_launch_geometry(c, best_f, best_e);
 }
 
 }  // extern "C"

@@ -84,13 +84,28 @@ __device__ void store_partials(double (&v)[NV], double *partials, int stride) {
 }
 
 // out[q] = sum_{b < n} partials[q * stride + b], identical in every block
+// (four loads per quantity in flight per thread, in a fixed order)
 template <int NV>
 __device__ void reduce_partials(const double *__restrict__ partials, int stride, int n,
                                 double (&out)[NV]) {
-    for (int q = 0; q < NV; ++q) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[q * stride + i];
-        out[q] = s;
+    const int bd = blockDim.x;
+    for (int q = 0; q < NV; ++q) out[q] = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * bd < n; i += 4 * bd) {
+        double a[NV][4];
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[q][u] = partials[q * stride + i + u * bd];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q] += (a[q][0] + a[q][1]) + (a[q][2] + a[q][3]);
+    }
+    for (; i < n; i += bd) {
+        double a[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) a[q] = partials[q * stride + i];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q] += a[q];
     }
     block_sum<NV>(out);
 }
@@ -560,84 +575,15 @@ template <int K> struct MF {
     static constexpr int NMB = (B3 + 15) / 16;     // 16-row blocks
 };
 
-// Workgroups (of 4 waves) per CU the matrix-core kernels are compiled for:
-// the register budget that keeps them free of scratch spills.
+// Workgroups per CU the matrix-core kernels are compiled for (8 waves
+// each): the register budget that keeps them free of scratch spills.
 template <int K> struct MFOcc {
-    static constexpr int value = K <= 5 ? 3 : 2;
+    static constexpr int value = K <= 5 ? 2 : 1;
 };
 
 // Packed A fragments: frag[dir][mb][kk][lane] (see element-side packing).
 __device__ __forceinline__ size_t frag_off(int d, int mb, int kk, int lane, int NMB, int NKK) {
     return (((size_t)d * NMB + mb) * NKK + kk) * 64 + lane;
-}
-
-// One wave: two sets of 16 faces, the x-faces and the y-faces of the same
-// 16 elements (column lane % 16), as two independent accumulation chains.
-// The contraction runs slot by slot (each slot's k range padded to a
-// multiple of 4, so a k step never straddles two slots); the B values of
-// slot s + 1 are loaded before the matrix-core work of slot s is issued.
-// load_b(set, slot, o) returns the B value at trace offset o.
-template <int K, int NM, typename T, typename LoadB>
-__device__ __forceinline__ void mfma_rows2(const T *__restrict__ const *frags,
-                                           const int (*dirs)[7], const int (*idx)[7],
-                                           size_t nel, int lane, LoadB load_b,
-                                           typename MfmaT<T>::v4 (*acc)[NM][MF<K>::NMB]) {
-    constexpr int B3 = MF<K>::B3, KS = MF<K>::KS, NKK = MF<K>::NKK, NMB = MF<K>::NMB;
-    const size_t TT = (size_t)B3 * nel;
-    const int q = lane >> 4;
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int m = 0; m < NM; ++m)
-#pragma unroll
-            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = typename MfmaT<T>::v4{0, 0, 0, 0};
-    // slot s is uniform over the wave: the switch selects its neighbour face
-    // with scalar branches (no indexed register arrays)
-    auto fetch = [&](int s, T (&dst)[KS][2]) {
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            int dd = dirs[f][0], ii = idx[f][0];
-            switch (s) {
-                case 1: dd = dirs[f][1]; ii = idx[f][1]; break;
-                case 2: dd = dirs[f][2]; ii = idx[f][2]; break;
-                case 3: dd = dirs[f][3]; ii = idx[f][3]; break;
-                case 4: dd = dirs[f][4]; ii = idx[f][4]; break;
-                case 5: dd = dirs[f][5]; ii = idx[f][5]; break;
-                case 6: dd = dirs[f][6]; ii = idx[f][6]; break;
-                default: break;
-            }
-            const size_t base = (size_t)dd * TT + ii;
-#pragma unroll
-            for (int u = 0; u < KS; ++u) {
-                const int cj = 4 * u + q;
-                dst[u][f] = (cj < B3) ? load_b(f, s, base + (size_t)cj * nel) : T(0);
-            }
-        }
-    };
-    T cur[KS][2], nxt[KS][2];
-    fetch(0, cur);
-#pragma unroll 1
-    for (int s = 0; s < 7; ++s) {
-        if (s + 1 < 7) fetch(s + 1, nxt);
-#pragma unroll
-        for (int u = 0; u < KS; ++u) {
-            const int kk = s * KS + u;
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-#pragma unroll
-                for (int m = 0; m < NM; ++m)
-#pragma unroll
-                    for (int mb = 0; mb < NMB; ++mb)
-                        acc[f][m][mb] = MfmaT<T>::mma(
-                            frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], cur[u][f],
-                            acc[f][m][mb]);
-        }
-#pragma unroll
-        for (int u = 0; u < KS; ++u) {
-            cur[u][0] = nxt[u][0];
-            cur[u][1] = nxt[u][1];
-        }
-    }
 }
 
 // Tiles of 64 elements; block b walks tiles so that the blocks resident on
@@ -663,20 +609,80 @@ template <typename T> struct FragMatsT {
 };
 typedef FragMatsT<double> FragMats;
 
-// Wave-level face index: element tile t covers 64 elements, wave w of the
-// block takes elements 16 w .. 16 w + 15 of it; face set 0 is their x-faces
-// (west faces), set 1 their y-faces (south faces).
-__device__ __forceinline__ void faces_of_wave(int tile, int nel, int nx, int ny, int w,
-                                              int lane, FaceIdx fi[2], int dirs[2][7],
-                                              int idx[2][7]) {
-    const int e = tile * 64 + w * 16 + (lane & 15);
-    const bool active = e < nel;
-    for (int d = 0; d < 2; ++d) {
-        fi[d].d = d;
-        fi[d].f = active ? e : 0;
-        fi[d].active = active;
-        slot_faces(fi[d], nx, ny, dirs[d], idx[d]);
+// ------------------------------------------------------------ face blocks
+// A face kernel runs blocks of 8 waves over 64-element tiles: wave w takes
+// face set w / 4 (0: the x-faces, 1: the y-faces of the elements) of the 16
+// elements in row w % 4 of the tile, so every wave runs one accumulation
+// chain and the two sets proceed in parallel.
+constexpr int kFaceThreads = 512;
+constexpr int kTX = 16, kTY = 4;     // element tile of a tiled mesh (below)
+
+struct WaveFaces {
+    int set, sub;            // face set (wave-uniform), tile row
+    int e;                   // element (= face index) of this lane
+    bool active;             // e < nel
+};
+
+template <bool TILED>
+__device__ __forceinline__ WaveFaces wave_faces(int tile, const Geom &g) {
+    WaveFaces wf;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    wf.set = w >> 2;
+    wf.sub = w & 3;
+    if constexpr (TILED) {
+        const int tpr = g.nx / kTX;
+        wf.e = ((tile / tpr) * kTY + wf.sub) * g.nx + (tile % tpr) * kTX + (lane & 15);
+        wf.active = true;
+    } else {
+        const int e = tile * 64 + wf.sub * 16 + (lane & 15);
+        wf.active = e < g.nel;
+        wf.e = wf.active ? e : 0;
     }
+    return wf;
+}
+
+// Trace offset of accumulator element (mb, r) of this lane: row 16 mb +
+// row(lane, r) of the row block of face (set, e); valid if that row < 3K.
+template <int K, typename T>
+__device__ __forceinline__ uint32_t own_off(const WaveFaces &wf, int mb, int r, uint32_t nel,
+                                            bool &valid) {
+    const int row = 16 * mb + MfmaT<T>::row(threadIdx.x & 63, r);
+    valid = row < MF<K>::B3 && wf.active;
+    return (uint32_t)wf.set * MF<K>::B3 * nel + (uint32_t)row * nel + wf.e;
+}
+
+// A operands of one slot for this wave's face set, all row blocks and k
+// steps, for NM matrices.
+template <int K, int NM, typename T> struct FragSlot {
+    T v[NM][MF<K>::NMB][MF<K>::KS];
+};
+
+template <int K, int NM, typename T>
+__device__ __forceinline__ void load_frags(const T *__restrict__ const *frags, int set, int s,
+                                           FragSlot<K, NM, T> &b) {
+    constexpr int KS = MF<K>::KS, NKK = MF<K>::NKK, NMB = MF<K>::NMB;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int u = 0; u < KS; ++u)
+                b.v[m][mb][u] = frags[m][frag_off(set, mb, s * KS + u, lane, NMB, NKK)];
+}
+
+// Double buffer the A operands of the next slot when they fit in 24 VGPRs.
+template <int K, int NM, typename T> struct FragPrefetch {
+    static constexpr bool value = NM * MF<K>::NMB * MF<K>::KS * (int)sizeof(T) / 4 <= 24;
+};
+
+template <int K, int NM, typename T>
+__device__ __forceinline__ void zero_acc(typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int mb = 0; mb < MF<K>::NMB; ++mb) acc[m][mb] = typename MfmaT<T>::v4{0, 0, 0, 0};
 }
 
 // ------------------------------------- LDS-staged tiles of 16 x 4 elements
@@ -686,7 +692,6 @@ __device__ __forceinline__ void faces_of_wave(int tile, int nel, int nx, int ny,
 // x-faces and 17 x 6 y-faces), with coalesced loads of whole face rows, and
 // the matrix cores read their B operands from LDS.  Each trace value then
 // crosses L2 about 1.5 times per launch instead of 7.
-constexpr int kTX = 16, kTY = 4;
 
 template <int K> struct Tile {
     static constexpr int B3 = 3 * K;
@@ -694,10 +699,6 @@ template <int K> struct Tile {
     static constexpr int YR = kTY + 2, YC = kTX + 1;   // y-faces
     static constexpr int NX = XR * XC, NY = YR * YC, NF = NX + NY;
 };
-
-__device__ __forceinline__ bool tiled_mesh(const Geom &g) {
-    return g.nx % kTX == 0 && g.ny % kTY == 0;
-}
 
 // Staged face f of the tile with corner (ex0, ey0) -> direction, global face
 // (element) index, and whether the tile owns it (it is a face of one of the
@@ -741,144 +742,237 @@ __device__ __forceinline__ int slot_lds(int set, int s, int lx, int ly, int NX, 
                   : NX + (ly + dy + 1) * YC + (lx + dx + 1);
 }
 
-// Stage the tile: sB[cj][f] = stage(o, own) for every staged face f and row
-// cj (c' K + j'); then the wave's two row-block sets (x- and y-faces of its
-// 16 elements) by the matrix cores from LDS.
-template <int K, int NM, typename T, typename Stage>
-__device__ __forceinline__ void tiled_rows(const T *__restrict__ const *frags, int tile,
-                                           const Geom &g, T (*sB)[Tile<K>::NF], Stage stage,
-                                           typename MfmaT<T>::v4 (*acc)[NM][MF<K>::NMB]) {
+// Stage the tile: sB[cj NF + f] = comb(raw, o, own) for every staged face
+// f and row cj (c' K + j'), where raw holds the NA source arrays at trace
+// offset o; comb may store the value at o when the tile owns the face.  All
+// loads of a chunk of up to 8 values per thread are issued before any is
+// used.
+template <int K, typename T, int NA, typename Comb>
+__device__ __forceinline__ void stage_tile(int tile, const Geom &g, T *sB,
+                                           const T *__restrict__ const (&src)[NA], Comb comb) {
     using TL = Tile<K>;
-    constexpr int B3 = TL::B3, NF = TL::NF, KS = MF<K>::KS, NKK = MF<K>::NKK,
-                  NMB = MF<K>::NMB;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int NV = TL::B3 * TL::NF, PER = (NV + kFaceThreads - 1) / kFaceThreads;
+    constexpr int CH = PER < 8 ? PER : 8;
     const int tpr = g.nx / kTX;
     const int ex0 = (tile % tpr) * kTX, ey0 = (tile / tpr) * kTY;
-    const size_t nel = g.nel, TT = (size_t)B3 * nel;
-    __syncthreads();   // previous tile's LDS reads are done
-    for (int v = threadIdx.x; v < B3 * NF; v += blockDim.x) {
-        const int cj = v / NF, f = v - cj * NF;
-        int dir, elem;
-        bool own;
-        staged_face(f, ex0, ey0, g.nx, g.ny, TL::NX, TL::XC, TL::YC, dir, elem, own);
-        sB[cj][f] = stage((size_t)dir * TT + (size_t)cj * nel + elem, own);
+    const uint32_t nel = g.nel, TT = TL::B3 * nel;
+#pragma unroll
+    for (int i0 = 0; i0 < PER; i0 += CH) {
+        uint32_t off[CH];
+        bool own[CH], ok[CH];
+        T raw[CH][NA];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int v = threadIdx.x + kFaceThreads * (i0 + u);
+            ok[u] = (i0 + u < PER) && v < NV;
+            const int vv = ok[u] ? v : 0;
+            const int cj = vv / TL::NF, fc = vv - cj * TL::NF;
+            int dir, elem;
+            staged_face(fc, ex0, ey0, g.nx, g.ny, TL::NX, TL::XC, TL::YC, dir, elem, own[u]);
+            off[u] = (uint32_t)dir * TT + (uint32_t)cj * nel + (uint32_t)elem;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) raw[u][a] = ok[u] ? src[a][off[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (ok[u]) sB[threadIdx.x + kFaceThreads * (i0 + u)] = comb(raw[u], off[u], own[u]);
     }
-    __syncthreads();
-    const int q = lane >> 4, lx = lane & 15;
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int m = 0; m < NM; ++m)
-#pragma unroll
-            for (int mb = 0; mb < NMB; ++mb) acc[f][m][mb] = typename MfmaT<T>::v4{0, 0, 0, 0};
+}
+
+// This wave's row blocks from the staged tile: the matrix cores read the B
+// operands from LDS, slot by slot; the A operands of slot s + 1 are loaded
+// while slot s is computed.
+template <int K, int NM, typename T>
+__device__ __forceinline__ void tile_rows(const T *__restrict__ const *frags, const T *sB,
+                                          const WaveFaces &wf,
+                                          typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
+    using TL = Tile<K>;
+    constexpr int B3 = TL::B3, NF = TL::NF, KS = MF<K>::KS, NMB = MF<K>::NMB;
+    constexpr bool PF = FragPrefetch<K, NM, T>::value;
+    const int lane = threadIdx.x & 63, q = lane >> 4, lx = lane & 15;
+    zero_acc<K, NM, T>(acc);
+    FragSlot<K, NM, T> cur, nxt;
+    if (PF) load_frags<K, NM, T>(frags, wf.set, 0, cur);
 #pragma unroll 1
     for (int s = 0; s < 7; ++s) {
-        int li[2];
-        li[0] = slot_lds(0, s, lx, w, TL::NX, TL::XC, TL::YC);
-        li[1] = slot_lds(1, s, lx, w, TL::NX, TL::XC, TL::YC);
+        if (PF) {
+            if (s + 1 < 7) load_frags<K, NM, T>(frags, wf.set, s + 1, nxt);
+        } else {
+            load_frags<K, NM, T>(frags, wf.set, s, cur);
+        }
+        const int li = slot_lds(wf.set, s, lx, wf.sub, TL::NX, TL::XC, TL::YC);
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
-            const int cj = 4 * u + q, kk = s * KS + u;
+            const int cj = 4 * u + q;
+            const T b = cj < B3 ? sB[cj * NF + li] : T(0);
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                const T b = (cj < B3) ? sB[cj][li[f]] : T(0);
+            for (int m = 0; m < NM; ++m)
 #pragma unroll
-                for (int m = 0; m < NM; ++m)
-#pragma unroll
-                    for (int mb = 0; mb < NMB; ++mb)
-                        acc[f][m][mb] = MfmaT<T>::mma(
-                            frags[m][frag_off(f, mb, kk, lane, NMB, NKK)], b, acc[f][m][mb]);
-            }
+                for (int mb = 0; mb < NMB; ++mb)
+                    acc[m][mb] = MfmaT<T>::mma(cur.v[m][mb][u], b, acc[m][mb]);
         }
+        if (PF) cur = nxt;
     }
 }
 
-// Global face element of set `f` of this wave's lane: (ex0 + lx, ey0 + w).
-__device__ __forceinline__ int tile_elem(int tile, const Geom &g) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int tpr = g.nx / kTX;
-    return ((tile / tpr) * kTY + w) * g.nx + (tile % tpr) * kTX + (lane & 15);
+// LDS index of this lane's own face of its wave's set.
+template <int K>
+__device__ __forceinline__ int own_lds(const WaveFaces &wf) {
+    using TL = Tile<K>;
+    const int lx = threadIdx.x & 15;
+    return wf.set == 0 ? (wf.sub + 1) * TL::XC + (lx + 1)
+                       : TL::NX + (wf.sub + 1) * TL::YC + (lx + 1);
 }
 
-template <int K>
-__device__ __forceinline__ int own_lds(int set, int lx, int ly) {
-    using T = Tile<K>;
-    return set == 0 ? (ly + 1) * T::XC + (lx + 1) : T::NX + (ly + 1) * T::YC + (lx + 1);
+// Without tiles: this wave's row blocks with B operands gathered from
+// global memory, slot by slot; the raw values of slot s + 1 and the A
+// operands of slot s + 1 are loaded while slot s is computed.  Slot 0 is
+// the face itself, whose combined value comb may store.
+template <int K, int NM, typename T, int NA, typename Comb>
+__device__ __forceinline__ void gather_rows(const T *__restrict__ const *frags, const Geom &g,
+                                            const WaveFaces &wf,
+                                            const T *__restrict__ const (&src)[NA], Comb comb,
+                                            typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
+    constexpr int B3 = MF<K>::B3, KS = MF<K>::KS, NMB = MF<K>::NMB;
+    constexpr bool PF = FragPrefetch<K, NM, T>::value;
+    const int lane = threadIdx.x & 63, q = lane >> 4;
+    const uint32_t nel = g.nel, TT = (uint32_t)B3 * nel;
+    FaceIdx fi;
+    fi.d = wf.set;
+    fi.f = wf.e;
+    fi.active = wf.active;
+    int dirs[7], idx[7];
+    slot_faces(fi, g.nx, g.ny, dirs, idx);
+    zero_acc<K, NM, T>(acc);
+    // slot s is uniform over the wave: the switch selects its neighbour face
+    // with scalar branches (no indexed register arrays)
+    auto fetch = [&](int s, T (&raw)[KS][NA], uint32_t (&off)[KS]) {
+        int dd = dirs[0], ii = idx[0];
+        switch (s) {
+            case 1: dd = dirs[1]; ii = idx[1]; break;
+            case 2: dd = dirs[2]; ii = idx[2]; break;
+            case 3: dd = dirs[3]; ii = idx[3]; break;
+            case 4: dd = dirs[4]; ii = idx[4]; break;
+            case 5: dd = dirs[5]; ii = idx[5]; break;
+            case 6: dd = dirs[6]; ii = idx[6]; break;
+            default: break;
+        }
+        const uint32_t base = (uint32_t)dd * TT + (uint32_t)ii;
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int cj = 4 * u + q;
+            off[u] = base + (uint32_t)cj * nel;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) raw[u][a] = (cj < B3) ? src[a][off[u]] : T(0);
+        }
+    };
+    T raw[KS][NA], rawn[KS][NA];
+    uint32_t off[KS], offn[KS];
+    FragSlot<K, NM, T> cur, nxt;
+    fetch(0, raw, off);
+    if (PF) load_frags<K, NM, T>(frags, wf.set, 0, cur);
+#pragma unroll 1
+    for (int s = 0; s < 7; ++s) {
+        if (s + 1 < 7) {
+            fetch(s + 1, rawn, offn);
+            if (PF) load_frags<K, NM, T>(frags, wf.set, s + 1, nxt);
+        }
+        if (!PF) load_frags<K, NM, T>(frags, wf.set, s, cur);
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int cj = 4 * u + q;
+            const T b = (cj < B3) ? comb(raw[u], off[u], s == 0 && wf.active) : T(0);
+#pragma unroll
+            for (int m = 0; m < NM; ++m)
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+                    acc[m][mb] = MfmaT<T>::mma(cur.v[m][mb][u], b, acc[m][mb]);
+        }
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            off[u] = offn[u];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) raw[u][a] = rawn[u][a];
+        }
+        if (PF) cur = nxt;
+    }
 }
+
+// Row blocks of this wave for one tile, staged (TILED) or gathered.
+template <int K, int NM, bool TILED, typename T, int NA, typename Comb>
+__device__ __forceinline__ void face_rows(const T *__restrict__ const *frags, int tile,
+                                          const Geom &g, const WaveFaces &wf, T *sB,
+                                          const T *__restrict__ const (&src)[NA], Comb comb,
+                                          typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
+    if constexpr (TILED) {
+        __syncthreads();   // the previous tile's LDS reads are done
+        stage_tile<K, T, NA>(tile, g, sB, src, comb);
+        __syncthreads();
+        tile_rows<K, NM, T>(frags, sB, wf, acc);
+    } else {
+        gather_rows<K, NM, T, NA>(frags, g, wf, src, comb, acc);
+    }
+}
+
+template <int K, bool TILED>
+__device__ __forceinline__ int face_tiles(const Geom &g) {
+    return TILED ? (g.nx / kTX) * (g.ny / kTY) : (g.nel + 63) / 64;
+}
+
+// LDS of a staged tile (unused without tiles).
+template <int K, bool TILED, typename T> struct TileLds {
+    static constexpr int n = TILED ? MF<K>::B3 * Tile<K>::NF : 1;
+};
 
 // FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
 // partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
 template <int K, bool TILED, typename RT>
-__global__ __launch_bounds__(256, MFOcc<K>::value) void k_trace_residual(
+__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residual(
     const FragMats A, const double *__restrict__ x, const double *__restrict__ gv,
     const double *__restrict__ gh, const Geom g, double *__restrict__ r,
     RT *__restrict__ rin, double *partials, int stride, const int32_t *skip) {
     using T = double;
     if (skip && *skip) return;
-    constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const size_t nel = g.nel, TT = (size_t)B3 * nel;
-    const int ntiles = (g.nel + 63) / 64;
+    constexpr int NMB = MF<K>::NMB;
+    __shared__ double sB[TileLds<K, TILED, T>::n];
+    const uint32_t nel = g.nel;
     const double *fr[2] = {A.A0, A.A1};
+    const double *src[1] = {x};
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-    if constexpr (TILED) {
-        __shared__ double sB[B3][Tile<K>::NF];
-        const int nt = (g.nx / kTX) * (g.ny / kTY);
-        const TileWalk tt = tile_walk(nt);
-        for (int tile = tt.first; tile < tt.end; tile += tt.step) {
-            v4d acc[2][2][NMB];
-            tiled_rows<K, 2>(fr, tile, g, sB, [&](size_t o, bool) { return x[o]; }, acc);
-            const int e = tile_elem(tile, g);
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-                    for (int e4 = 0; e4 < 4; ++e4) {
-                        const int row = 16 * mb + MfmaT<T>::row(lane, e4);
-                        if (row < B3) {
-                            const size_t o = f * TT + (size_t)row * nel + e;
-                            const double rr = gv[o] - acc[f][0][mb][e4];
-                            const double ri = gh[o] - acc[f][1][mb][e4];
-                            r[o] = rr;
-                            rin[o] = (RT)ri;
-                            acc4[0] += rr * rr;
-                            acc4[1] += gv[o] * gv[o];
-                            acc4[2] += gh[o] * gh[o];
-                            acc4[3] += ri * ri;
-                        }
-                    }
-        }
-        store_partials<4>(acc4, partials, stride);
-        return;
-    }
-    const TileWalk tw = tile_walk(ntiles);
+    const TileWalk tw = tile_walk(face_tiles<K, TILED>(g));
     for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-        FaceIdx fi[2];
-        int dirs[2][7], idx[2][7];
-        faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
-        v4d acc[2][2][NMB];
-        mfma_rows2<K, 2>(fr, dirs, idx, nel, lane,
-                         [&](int, int, size_t o) { return x[o]; }, acc);
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
+        const WaveFaces wf = wave_faces<TILED>(tile, g);
+        // right-hand sides at the own rows, loaded ahead of the contraction
+        double gvv[NMB][4], ghv[NMB][4];
+        uint32_t o[NMB][4];
+        bool ok[NMB][4];
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = 16 * mb + MfmaT<T>::row(lane, e);
-                if (row < B3 && fi[f].active) {
-                    const size_t o = f * TT + (size_t)row * nel + fi[f].f;
-                    const double rr = gv[o] - acc[f][0][mb][e];
-                    const double ri = gh[o] - acc[f][1][mb][e];
-                    r[o] = rr;
-                    rin[o] = (RT)ri;
+            for (int e4 = 0; e4 < 4; ++e4) {
+                o[mb][e4] = own_off<K, T>(wf, mb, e4, nel, ok[mb][e4]);
+                gvv[mb][e4] = ok[mb][e4] ? gv[o[mb][e4]] : 0.0;
+                ghv[mb][e4] = ok[mb][e4] ? gh[o[mb][e4]] : 0.0;
+            }
+        v4d acc[2][NMB];
+        face_rows<K, 2, TILED>(fr, tile, g, wf, sB, src,
+                               [](const double (&a)[1], uint32_t, bool) { return a[0]; }, acc);
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4)
+                if (ok[mb][e4]) {
+                    const double rr = gvv[mb][e4] - acc[0][mb][e4];
+                    const double ri = ghv[mb][e4] - acc[1][mb][e4];
+                    r[o[mb][e4]] = rr;
+                    rin[o[mb][e4]] = (RT)ri;
                     acc4[0] += rr * rr;
-                    acc4[1] += gv[o] * gv[o];
-                    acc4[2] += gh[o] * gh[o];
+                    acc4[1] += gvv[mb][e4] * gvv[mb][e4];
+                    acc4[2] += ghv[mb][e4] * ghv[mb][e4];
                     acc4[3] += ri * ri;
                 }
-            }
     }
     store_partials<4>(acc4, partials, stride);
 }
@@ -923,16 +1017,12 @@ __global__ void k_bicg_init(const T *__restrict__ rin, T *__restrict__ r,
 }
 
 template <int K, bool TILED, typename T, bool SCHED>
-__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMatsT<T> A,
-                                                 const T *__restrict__ r,
-                                                 const T *__restrict__ rh,
-                                                 const T *__restrict__ pin,
-                                                 const T *__restrict__ vin,
-                                                 T *__restrict__ pout,
-                                                 T *__restrict__ vout, const Geom g,
-                                                 KrylovState *ks, const double *P3, int n3,
-                                                 double *P1, int stride) {
-    constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
+__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
+    const FragMatsT<T> A, const T *__restrict__ r, const T *__restrict__ rh,
+    const T *__restrict__ pin, const T *__restrict__ vin, T *__restrict__ pout,
+    T *__restrict__ vout, const Geom g, KrylovState *ks, const double *P3, int n3, double *P1,
+    int stride) {
+    constexpr int NMB = MF<K>::NMB;
     double red[2];
     reduce_partials<2>(P3, stride, n3, red);
     if (ks->conv) return;
@@ -946,71 +1036,41 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
         }
         return;
     }
-    const double beta = (rho_new / rho) * (alpha / omega);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const size_t nel = g.nel, TT = (size_t)B3 * nel;
-    const int ntiles = (g.nel + 63) / 64;
+    const T beta = (T)((rho_new / rho) * (alpha / omega)), om = (T)omega;
+    __shared__ T sB[TileLds<K, TILED, T>::n];
+    const uint32_t nel = g.nel;
     const T *fr[1] = {A.A0};
+    const T *src[3] = {r, pin, vin};
     double acc1[1] = {0.0};
-    if constexpr (TILED) {
-        __shared__ T sB[B3][Tile<K>::NF];
-        const int nt = (g.nx / kTX) * (g.ny / kTY);
-        const TileWalk tt = tile_walk(nt);
-        for (int tile = tt.first; tile < tt.end; tile += tt.step) {
-            typename MfmaT<T>::v4 acc[2][1][NMB];
-            tiled_rows<K, 1>(fr, tile, g, sB,
-                             [&](size_t o, bool own) {
-                                 const T v = r[o] + (T)beta * (pin[o] - (T)omega * vin[o]);
-                                 if (own) pout[o] = v;
-                                 return v;
-                             },
-                             acc);
-            const int e = tile_elem(tile, g);
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-                    for (int e4 = 0; e4 < 4; ++e4) {
-                        const int row = 16 * mb + MfmaT<T>::row(lane, e4);
-                        if (row < B3) {
-                            const size_t o = f * TT + (size_t)row * nel + e;
-                            const double y = acc[f][0][mb][e4];
-                            vout[o] = (T)y;
-                            acc1[0] += rh[o] * y;
-                        }
-                    }
-        }
-        store_partials<1>(acc1, P1, stride);
-        if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
-        return;
-    }
-    const TileWalk tw = tile_walk(ntiles);
+    const TileWalk tw = tile_walk(face_tiles<K, TILED>(g));
     for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-        FaceIdx fi[2];
-        int dirs[2][7], idx[2][7];
-        faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
-        typename MfmaT<T>::v4 acc[2][1][NMB];
-        mfma_rows2<K, 1>(fr, dirs, idx, nel, lane,
-                         [&](int f, int sl, size_t o) {
-                             const T v = r[o] + (T)beta * (pin[o] - (T)omega * vin[o]);
-                             if (sl == 0 && fi[f].active) pout[o] = v;
-                             return v;
-                         },
-                         acc);
+        const WaveFaces wf = wave_faces<TILED>(tile, g);
+        T rhv[NMB][4];
+        uint32_t o[NMB][4];
+        bool ok[NMB][4];
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
+        for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
+            for (int e4 = 0; e4 < 4; ++e4) {
+                o[mb][e4] = own_off<K, T>(wf, mb, e4, nel, ok[mb][e4]);
+                rhv[mb][e4] = ok[mb][e4] ? rh[o[mb][e4]] : T(0);
+            }
+        typename MfmaT<T>::v4 acc[1][NMB];
+        face_rows<K, 1, TILED>(fr, tile, g, wf, sB, src,
+                               [&](const T (&a)[3], uint32_t off, bool own) {
+                                   const T p = a[0] + beta * (a[1] - om * a[2]);
+                                   if (own) pout[off] = p;
+                                   return p;
+                               },
+                               acc);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * mb + MfmaT<T>::row(lane, e);
-                    if (row < B3 && fi[f].active) {
-                        const size_t o = f * TT + (size_t)row * nel + fi[f].f;
-                        const double y = acc[f][0][mb][e];
-                        vout[o] = (T)y;
-                        acc1[0] += rh[o] * y;
-                    }
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4)
+                if (ok[mb][e4]) {
+                    const double y = acc[0][mb][e4];
+                    vout[o[mb][e4]] = (T)y;
+                    acc1[0] += (double)rhv[mb][e4] * y;
                 }
     }
     store_partials<1>(acc1, P1, stride);
@@ -1018,15 +1078,11 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k1(const FragMats
 }
 
 template <int K, bool TILED, typename T, bool SCHED>
-__global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMatsT<T> A,
-                                                 const T *__restrict__ r,
-                                                 const T *__restrict__ v,
-                                                 T *__restrict__ sv,
-                                                 T *__restrict__ t, const Geom g,
-                                                 KrylovState *ks, const double *P1, int n1,
-                                                 const double *P3, int n3, double *P2,
-                                                 int stride) {
-    constexpr int B3 = MF<K>::B3, NMB = MF<K>::NMB;
+__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
+    const FragMatsT<T> A, const T *__restrict__ r, const T *__restrict__ v,
+    T *__restrict__ sv, T *__restrict__ t, const Geom g, KrylovState *ks, const double *P1,
+    int n1, const double *P3, int n3, double *P2, int stride) {
+    constexpr int NMB = MF<K>::NMB;
     double red1[1], red3[2];
     reduce_partials<1>(P1, stride, n1, red1);
     reduce_partials<2>(P3, stride, n3, red3);
@@ -1040,79 +1096,54 @@ __global__ __launch_bounds__(256, MFOcc<K>::value) void k_bicg_k2(const FragMats
         return;
     }
     const double alpha = rho_new / rv;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const size_t nel = g.nel, TT = (size_t)B3 * nel;
-    const int ntiles = (g.nel + 63) / 64;
+    const T al = (T)alpha;
+    __shared__ T sB[TileLds<K, TILED, T>::n];
+    const uint32_t nel = g.nel;
     const T *fr[1] = {A.A0};
+    const T *src[2] = {r, v};
     double acc2[2] = {0.0, 0.0};
-    if constexpr (TILED) {
-        __shared__ T sB[B3][Tile<K>::NF];
-        const int nt = (g.nx / kTX) * (g.ny / kTY);
-        const TileWalk tt = tile_walk(nt);
-        for (int tile = tt.first; tile < tt.end; tile += tt.step) {
-            typename MfmaT<T>::v4 acc[2][1][NMB];
-            tiled_rows<K, 1>(fr, tile, g, sB,
-                             [&](size_t o, bool own) {
-                                 const T sval = r[o] - (T)alpha * v[o];
-                                 if (own) sv[o] = sval;
-                                 return sval;
-                             },
-                             acc);
-            const int e = tile_elem(tile, g);
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                const int li = own_lds<K>(f, lane & 15, w);
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-                    for (int e4 = 0; e4 < 4; ++e4) {
-                        const int row = 16 * mb + MfmaT<T>::row(lane, e4);
-                        if (row < B3) {
-                            const size_t o = f * TT + (size_t)row * nel + e;
-                            const double y = acc[f][0][mb][e4];
-                            const double sval = sB[row][li];
-                            t[o] = (T)y;
-                            acc2[0] += y * sval;
-                            acc2[1] += y * y;
-                        }
-                    }
-            }
-        }
-        store_partials<2>(acc2, P2, stride);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            ks->rho = rho_new;
-            ks->alpha = alpha;
-        }
-        return;
-    }
-    const TileWalk tw = tile_walk(ntiles);
+    const TileWalk tw = tile_walk(face_tiles<K, TILED>(g));
     for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-        FaceIdx fi[2];
-        int dirs[2][7], idx[2][7];
-        faces_of_wave(tile, g.nel, g.nx, g.ny, w, lane, fi, dirs, idx);
-        typename MfmaT<T>::v4 acc[2][1][NMB];
-        mfma_rows2<K, 1>(fr, dirs, idx, nel, lane,
-                         [&](int f, int sl, size_t o) {
-                             const T sval = r[o] - (T)alpha * v[o];
-                             if (sl == 0 && fi[f].active) sv[o] = sval;
-                             return sval;
-                         },
-                         acc);
+        const WaveFaces wf = wave_faces<TILED>(tile, g);
+        uint32_t o[NMB][4];
+        bool ok[NMB][4];
+        T sown[NMB][4];
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                o[mb][e4] = own_off<K, T>(wf, mb, e4, nel, ok[mb][e4]);
+                if constexpr (!TILED)
+                    sown[mb][e4] = ok[mb][e4] ? r[o[mb][e4]] - al * v[o[mb][e4]] : T(0);
+            }
+        typename MfmaT<T>::v4 acc[1][NMB];
+        face_rows<K, 1, TILED>(fr, tile, g, wf, sB, src,
+                               [&](const T (&a)[2], uint32_t off, bool own) {
+                                   const T s = a[0] - al * a[1];
+                                   if (own) sv[off] = s;
+                                   return s;
+                               },
+                               acc);
+        if constexpr (TILED) {
+            const int li = own_lds<K>(wf);
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * mb + MfmaT<T>::row(lane, e);
-                    if (row < B3 && fi[f].active) {
-                        const size_t o = f * TT + (size_t)row * nel + fi[f].f;
-                        const double y = acc[f][0][mb][e];
-                        const T sval = r[o] - (T)alpha * v[o];
-                        t[o] = (T)y;
-                        acc2[0] += y * sval;
-                        acc2[1] += y * y;
-                    }
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    const int row = 16 * mb + MfmaT<T>::row(threadIdx.x & 63, e4);
+                    if (ok[mb][e4]) sown[mb][e4] = sB[row * Tile<K>::NF + li];
+                }
+        }
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4)
+                if (ok[mb][e4]) {
+                    const double y = acc[0][mb][e4];
+                    const double sval = sown[mb][e4];
+                    t[o[mb][e4]] = (T)y;
+                    acc2[0] += y * sval;
+                    acc2[1] += y * y;
                 }
     }
     store_partials<2>(acc2, P2, stride);
@@ -1133,14 +1164,33 @@ __global__ void k_bicg_k3(T *__restrict__ d, T *__restrict__ r,
     const double omega = red[1] > 0.0 ? red[0] / red[1] : 0.0;
     const double alpha = ks->alpha;
     double acc[2] = {0.0, 0.0};
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double si = sv[i];
-        d[i] = (T)((double)d[i] + alpha * (double)p[i] + omega * si);
-        const double rr = si - omega * (double)t[i];
-        r[i] = (T)rr;
-        acc[0] += rh[i] * rr;
-        acc[1] += rr * rr;
+    // four elements per thread and pass, all loads issued before use
+    constexpr int U = 4;
+    const size_t bd = blockDim.x, span = (size_t)gridDim.x * bd * U;
+    for (size_t i0 = (size_t)blockIdx.x * bd * U + threadIdx.x; i0 < n; i0 += span) {
+        T dv[U], pv[U], sval[U], tv[U], rhv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = i0 + u * bd;
+            const bool ok = i < n;
+            dv[u] = ok ? d[i] : T(0);
+            pv[u] = ok ? p[i] : T(0);
+            sval[u] = ok ? sv[i] : T(0);
+            tv[u] = ok ? t[i] : T(0);
+            rhv[u] = ok ? rh[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = i0 + u * bd;
+            if (i < n) {
+                const double si = sval[u];
+                d[i] = (T)((double)dv[u] + alpha * (double)pv[u] + omega * si);
+                const double rr = si - omega * (double)tv[u];
+                r[i] = (T)rr;
+                acc[0] += rhv[u] * rr;
+                acc[1] += rr * rr;
+            }
+        }
     }
     store_partials<2>(acc, P3, stride);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1343,12 +1393,12 @@ template <typename RT> struct RunTraceResidual {
                               hipStream_t s) {
             if (is_tiled(g))
                 hipLaunchKernelGGL((k_trace_residual<K, true, RT>), dim3(face_grid(g)),
-                                   dim3(256), 0, s, FragMats{G, Gh}, x, gv, gh, g, r, rin,
-                                   partials, stride, skip);
+                                   dim3(kFaceThreads), 0, s, FragMats{G, Gh}, x, gv, gh, g, r,
+                                   rin, partials, stride, skip);
             else
                 hipLaunchKernelGGL((k_trace_residual<K, false, RT>), dim3(face_grid(g)),
-                                   dim3(256), 0, s, FragMats{G, Gh}, x, gv, gh, g, r, rin,
-                                   partials, stride, skip);
+                                   dim3(kFaceThreads), 0, s, FragMats{G, Gh}, x, gv, gh, g, r,
+                                   rin, partials, stride, skip);
             return hipGetLastError();
         }
     };
@@ -1359,7 +1409,7 @@ template <typename T> struct RunK1 {
                               const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,
                               const KrylovBufs &kb, hipStream_t s) {
             const FragMatsT<T> A{Gh, nullptr};
-            const dim3 gr(face_grid(g)), bl(256);
+            const dim3 gr(face_grid(g)), bl(kFaceThreads);
             const int n3 = (int)elem_grid(g);
 #define IMEXHDG_K1(TL, SC)                                                                 \
     hipLaunchKernelGGL((k_bicg_k1<K, TL, T, SC>), gr, bl, 0, s, A, r, rh, pin, vin, pout, \
@@ -1379,7 +1429,7 @@ template <typename T> struct RunK2 {
         static hipError_t run(const Geom &g, const T *Gh, const T *r, const T *v, T *sv, T *t,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             const FragMatsT<T> A{Gh, nullptr};
-            const dim3 gr(face_grid(g)), bl(256);
+            const dim3 gr(face_grid(g)), bl(kFaceThreads);
             const int n1 = (int)face_grid(g), n3 = (int)elem_grid(g);
 #define IMEXHDG_K2(TL, SC)                                                                    \
     hipLaunchKernelGGL((k_bicg_k2<K, TL, T, SC>), gr, bl, 0, s, A, r, v, sv, t, g, ks, kb.P1, \
@@ -1412,13 +1462,13 @@ unsigned face_grid(const Geom &g) {
     // elements); a multiple of 8 blocks when there are enough tiles, so that
     // every XCD gets the same number of blocks
     const unsigned t = is_tiled(g) ? (unsigned)((g.nx / kTX) * (g.ny / kTY)) : grid1(g.nel, 64);
-    const unsigned n = std::min<unsigned>(t, kMaxGrid);
+    const unsigned n = std::min<unsigned>(t, (unsigned)std::min(g.fgrid, kMaxLaunchGrid));
     return n >= 8 ? n & ~7u : n;
 }
 
 unsigned elem_grid(const Geom &g) {
     const size_t n = (size_t)6 * g.K * g.nel;
-    return std::min<unsigned>(grid1(n, 256), kMaxGrid);
+    return std::min<unsigned>(grid1(n, 256), (unsigned)std::min(g.egrid, kMaxLaunchGrid));
 }
 
 unsigned diag_grid(const Geom &g) { return std::min<unsigned>(grid1(g.nel, 64), kMaxGrid); }

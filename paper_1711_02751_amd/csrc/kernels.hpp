@@ -18,7 +18,12 @@ struct Geom {
     double winv0, winvk;        // 1/w_0, 1/w_k
     double Dw[kMaxK * kMaxK];   // Dw[m*K + a] = w_m D[m][a] / w_a (weak derivative)
     double mass[kMaxK * kMaxK]; // (hx/2)(hy/2) w_i w_j at node j*K + i
+    int fgrid, egrid;           // grid caps of the face-tile and elementwise Krylov
+                                // launches (launch geometry, tuned per mesh)
 };
+
+// Largest grid of any launch that leaves per-block partial sums.
+constexpr int kMaxLaunchGrid = 4096;
 
 // out = self * X + sum_p coef[p] * in[p]   (X the kernel's own result)
 // and, if store != nullptr, store = X.  Volume device layout.

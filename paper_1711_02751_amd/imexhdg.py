@@ -28,7 +28,7 @@ EXPORTS = [
     "imexhdg_last_error", "imexhdg_state_device", "imexhdg_nl_residual",
     "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_profile",
     "imexhdg_profile_read", "imexhdg_kernel_name", "imexhdg_get_schedule",
-    "imexhdg_set_schedule",
+    "imexhdg_set_schedule", "imexhdg_set_launch_geometry", "imexhdg_autotune",
 ]
 KERNELS = ["nl_residual", "combine", "local_apply", "trace_rhs", "trace_residual", "bicg_init",
            "bicg_k1", "bicg_k2", "bicg_k3", "axpy", "recover", "diag", "linear_residual"]
@@ -104,6 +104,9 @@ def load():
         "imexhdg_kernel_name": (ctypes.c_char_p, [i32]),
         "imexhdg_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "imexhdg_set_schedule": (ctypes.c_int, [P, i32, ctypes.POINTER(i32)]),
+        "imexhdg_set_launch_geometry": (ctypes.c_int, [P, i32, i32]),
+        "imexhdg_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32),
+                                            ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -234,6 +237,17 @@ class Solver:
     def set_schedule(self, budgets):
         b = (ctypes.c_int32 * max(8, len(budgets)))(*[int(v) for v in budgets])
         _check(self.lib.imexhdg_set_schedule(self._ctx, len(budgets), b))
+
+    # ---- launch geometry
+    def set_launch_geometry(self, face_grid, elem_grid):
+        _check(self.lib.imexhdg_set_launch_geometry(self._ctx, int(face_grid), int(elem_grid)))
+
+    def autotune(self, cache_path=None):
+        """Tune the Krylov grid caps on the current state; returns them."""
+        f, e = ctypes.c_int32(), ctypes.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self.lib.imexhdg_autotune(self._ctx, path, ctypes.byref(f), ctypes.byref(e)))
+        return f.value, e.value
 
     # ---- operator-level calls on device tensors (volume / trace device layout)
     def state_device_ptr(self):

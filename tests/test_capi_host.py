@@ -67,4 +67,6 @@ def test_null_arguments_rejected():
     assert lib.imexhdg_sizes(None, None, None) == m.E_INVAL
     assert lib.imexhdg_get_schedule(None, None, None) == m.E_INVAL
     assert lib.imexhdg_set_schedule(None, 1, None) == m.E_INVAL
+    assert lib.imexhdg_set_launch_geometry(None, 1024, 1024) == m.E_INVAL
+    assert lib.imexhdg_autotune(None, None, None, None) == m.E_INVAL
     lib.imexhdg_destroy(None)

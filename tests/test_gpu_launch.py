@@ -91,3 +91,62 @@ def test_schedule_errors():
     with pytest.raises(m.ImexError) as e:
         H.set_schedule([5])
     assert e.value.code == m.E_STATE
+
+
+# ------------------------------------------------------ launch geometry
+@pytest.mark.parametrize("fg,eg", [(8, 8), (16, 4096), (4096, 24)])
+def test_launch_geometry_does_not_change_results(fg, eg):
+    """Grid caps only change how tiles are dealt to blocks and the order of
+    the partial sums; the steps agree with the default geometry."""
+    print(f"geometry fg={fg} eg={eg}", flush=True)
+    P, A = _solver(32, 16, 4, m.PREC_FP64, m.LAUNCH_GRAPH)
+    _, B = _solver(32, 16, 4, m.PREC_FP64, m.LAUNCH_GRAPH)
+    B.set_launch_geometry(fg, eg)
+    q0 = bump_state(P, seed=11, umax=0.2)
+    a = _run(A, q0, [6])
+    b = _run(B, q0, [6])
+    err = swe.rel_l2(P.mesh, a, b)
+    print("rel L2", err, flush=True)
+    assert np.all(err < 1e-12)
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    print("autotune", flush=True)
+    P, S = _solver(64, 64, 4, m.PREC_MIXED, m.LAUNCH_GRAPH, dt=0.004)
+    q0 = bump_state(P, seed=12, umax=0.2)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    S.step(3)
+    before = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
+    cache = tmp_path / "tune.txt"
+    f, e = S.autotune(str(cache))
+    print("tuned", f, e, open(cache).read(), flush=True)
+    assert 8 <= f <= 4096 and 8 <= e <= 4096
+    after = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
+    assert np.array_equal(before, after)
+    assert S.diag()["steps"] == 3
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(f"\t{f}\t{e}")
+    # a second context reads the cached choice
+    _, S2 = _solver(64, 64, 4, m.PREC_MIXED, m.LAUNCH_GRAPH, dt=0.004)
+    S2.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    assert S2.autotune(str(cache)) == (f, e)
+    assert len(open(cache).read().splitlines()) == 1
+    # stepping after tuning matches stepping on the default geometry
+    S.step(4)
+    _, R = _solver(64, 64, 4, m.PREC_MIXED, m.LAUNCH_GRAPH, dt=0.004)
+    R.set_state(*before.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    R.step(4)
+    err = swe.rel_l2(P.mesh, np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)).reshape(q0.shape),
+                     np.stack(R.get_state(vars=m.VARS_GEOPOTENTIAL)).reshape(q0.shape))
+    assert np.all(err < 1e-9)
+
+
+def test_launch_geometry_errors():
+    _, S = _solver(8, 8, 3, m.PREC_FP64, m.LAUNCH_GRAPH)
+    for fg, eg in [(4, 1024), (1024, 5000), (0, 0)]:
+        with pytest.raises(m.ImexError) as e:
+            S.set_launch_geometry(fg, eg)
+        assert e.value.code == m.E_INVAL
+    with pytest.raises(m.ImexError) as e:
+        S.autotune()
+    assert e.value.code == m.E_STATE
