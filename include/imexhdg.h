@@ -271,6 +271,42 @@ int imexhdg_set_launch_geometry(imexhdg_ctx *ctx, int32_t face_grid, int32_t ele
 int imexhdg_autotune(imexhdg_ctx *ctx, const char *cache_path, int32_t *face_grid,
                      int32_t *elem_grid);
 
+/* ---------------- ensembles
+ * An ensemble steps n independent members together: every kernel launch of
+ * a step covers all members (their arrays are concatenated, each member in
+ * the layout of a single context, with per-member reductions, convergence
+ * flags and element operators), and each step is one graph launch on the
+ * fixed schedule (IMEXHDG_LAUNCH_GRAPH is required).  Members may differ in
+ * nx, ny, Lx, Ly and dt only; every other field must equal member 0's
+ * (IMEXHDG_E_INVAL otherwise).  The first step after a set_state runs
+ * eagerly on a probe schedule of refine_max sweeps of up to 64 inner
+ * iterations; the schedule is then what the slowest member needed plus a
+ * margin, widened and the step redone whenever a member misses refine_rtol.
+ * Member m's state arrays follow the single-context conventions
+ * (imexhdg_ens_sizes gives its n_nodes); every member needs a state before
+ * the first step.  workspace, stream: as for imexhdg_create.             */
+typedef struct imexhdg_ens imexhdg_ens;
+
+int imexhdg_ens_workspace_bytes(const imexhdg_config *cfgs, int32_t n, size_t *bytes);
+int imexhdg_ens_create(const imexhdg_config *cfgs, int32_t n, void *stream,
+                       void *workspace, size_t ws_bytes, imexhdg_ens **out);
+void imexhdg_ens_destroy(imexhdg_ens *ens);
+int imexhdg_ens_members(const imexhdg_ens *ens, int32_t *n);
+int imexhdg_ens_sizes(const imexhdg_ens *ens, int32_t m, int64_t *n_nodes,
+                      int64_t *n_trace);
+int imexhdg_ens_get_nodes(const imexhdg_ens *ens, int32_t m, double *x, double *y);
+int imexhdg_ens_set_state(imexhdg_ens *ens, int32_t m, int vars, const double *a,
+                          const double *b, const double *c);
+int imexhdg_ens_get_state(imexhdg_ens *ens, int32_t m, int vars, double *a, double *b,
+                          double *c);
+/* Advance every member nsteps steps; returns when they are done.         */
+int imexhdg_ens_step(imexhdg_ens *ens, int32_t nsteps);
+/* Member m's mass and energy; the solver counters are the ensemble's.    */
+int imexhdg_ens_get_diag(imexhdg_ens *ens, int32_t m, imexhdg_diag *d);
+int imexhdg_ens_get_schedule(const imexhdg_ens *ens, int32_t *sweeps, int32_t *budget);
+int imexhdg_ens_set_launch_geometry(imexhdg_ens *ens, int32_t face_grid,
+                                    int32_t elem_grid);
+
 #ifdef __cplusplus
 }
 #endif

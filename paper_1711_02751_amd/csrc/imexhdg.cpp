@@ -1,4 +1,9 @@
 // C ABI of the IMEX HDG-DG step: context, workspace, stage orchestration.
+//
+// The engine runs a batch of members (independent periodic meshes sharing
+// the degree, the physical constants, the scheme and the solver settings):
+// a context is the batch of one member, an ensemble the batch of many.
+// Every launch covers all members; see kernels.hpp.
 #include "../../include/imexhdg.h"
 
 #include <hip/hip_runtime.h>
@@ -68,7 +73,9 @@ Tableau make_tableau(int scheme) {
 }
 
 // A linear combination over the step's vectors.  Vector ids:
-//   QN (q^n), NLV+j (NL_j), QV+j (Q_j), RV+j (Res0_j), SELF (kernel result).
+//   QN (q^n), NLV+j (dt NL_j), QV+j (Q_j), RV+j (Res0_j), SELF (kernel result).
+// The NL kernel returns dt NL (the member's dt), so no coefficient holds dt
+// and one plan serves members with different time steps.
 enum { QN = 0, NLV = 1, QV = 17, RV = 33, SELF = 49 };
 struct Term { int id; double coef; };
 using Plan = std::vector<Term>;
@@ -87,21 +94,43 @@ void cleanup(Plan &p) {
     p.swap(out);
 }
 
+// Element operators of one (hx, hy, dt) on the device.
+struct OpSet {
+    double hx = 0, hy = 0, dt = 0;
+    double *Ainv = nullptr, *W = nullptr, *G = nullptr, *Gh = nullptr, *Px = nullptr,
+           *Py = nullptr;
+    float *Ghf = nullptr;
+};
+
+struct MemberHost {
+    int nx = 0, ny = 0, nel = 0;
+    double Lx = 0, Ly = 0, dt = 0;
+    size_t N = 0, T = 0, vo = 0, to = 0;
+    int op = 0;
+};
+
 }  // namespace
 
 struct imexhdg_ctx {
-    imexhdg_config cfg{};
+    imexhdg_config cfg{};             // shared settings (the first member's config)
+    int nm = 1;
+    std::vector<MemberHost> mh;
+    std::vector<Member> mtab;         // host copy of the device member table
+    Member *dmem = nullptr;
+    Batch bt{};
+    int fgrid = 1024, egrid = 1024;   // launch-geometry caps
+    int pstride = 0;                  // stride of every partial-sum array
     hipStream_t stream = nullptr;
     int device = 0;
     bool own_ws = false;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     LGL ref;
-    StageOperators op;
     Geom geom{};
+    std::vector<OpSet> ops;
     Tableau tab;
     double aii = 0.0;
-    size_t N = 0, T = 0, nnodes = 0;
+    size_t N = 0, T = 0, nnodes = 0;  // over all members
     // device buffers; the state lives in a ring of three buffers, q is
     // qbuf[cur] and a step from qbuf[a] writes qbuf[(a + 1) % 3]
     double *qbuf[3] = {nullptr, nullptr, nullptr};
@@ -114,16 +143,14 @@ struct imexhdg_ctx {
     bool mixed = false;
     void *rin = nullptr, *kr = nullptr, *krh = nullptr, *kp[2] = {nullptr, nullptr},
          *kv[2] = {nullptr, nullptr}, *ks_ = nullptr, *kt = nullptr, *kd = nullptr;
-    float *dGhf = nullptr;   // FP32 packed Ghat fragments for the inner solve
-    double *dAinv = nullptr, *dW = nullptr, *dG = nullptr, *dGh = nullptr, *dPx = nullptr,
-           *dPy = nullptr;
-    KrylovState *ks = nullptr;
+    KrylovState *ks = nullptr;        // [nm]
     KrylovBufs kb{};
-    double *dpart = nullptr;          // [5][kPartStride] residual / diagnostics partials
+    double *dpart = nullptr;          // [5][pstride] residual / diagnostics partials
     // host mirrors
     KrylovState *hks = nullptr;
     double *hpart = nullptr;
     bool have_state = false;
+    std::vector<bool> member_set;
     // plans: after stage i the NL kernel writes plan_out[i]
     std::vector<Plan> plans;
     std::vector<bool> store_nl;
@@ -143,8 +170,8 @@ struct imexhdg_ctx {
     hipStream_t gstream = nullptr;    // capture stream
     hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
     hipEvent_t gev[3] = {nullptr, nullptr, nullptr};
-    StageStatus *dstat = nullptr;     // [3][s], device
-    StageStatus *hstat = nullptr;     // [3][s], pinned host mirror
+    StageStatus *dstat = nullptr;     // [3][s][nm], device
+    StageStatus *hstat = nullptr;     // [3][s][nm], pinned host mirror
     int64_t graph_steps = 0, redos = 0, captures = 0;
     // event profiler
     int prof_target = -2;
@@ -153,6 +180,10 @@ struct imexhdg_ctx {
     int ev_used = 0;
     double prof_ms[IMEXHDG_K_COUNT] = {};
     int64_t prof_n[IMEXHDG_K_COUNT] = {};
+};
+
+struct imexhdg_ens {
+    imexhdg_ctx *c = nullptr;
 };
 
 namespace {
@@ -166,7 +197,7 @@ size_t frag_count(int K) {
 }
 
 // Pack the 7-slot row blocks of G for x- and y-faces into the A-operand
-// order of v_mfma_f64_16x16x4f64: frag[dir][mb][kk][lane] holds row
+// order of the 16x16x4 matrix-core step: frag[dir][mb][kk][lane] holds row
 // 16 mb + lane % 16 (face row (c, j)) and column 4 (kk mod KS) + lane / 16
 // (c' K + j') of slot kk / KS, KS = ceil(3K / 4) k-steps per slot; rows and
 // columns past 3K are zero.
@@ -189,35 +220,61 @@ std::vector<double> pack_frags(const std::vector<double> &Gx, const std::vector<
     return f;
 }
 
-// stride of every partial-sum array; no launch has a larger grid
-constexpr int kPartStride = kMaxLaunchGrid;
+// Worst-case partial-sum stride of a batch: every class at its largest caps.
+int partial_stride(const std::vector<imexhdg_config> &cf) {
+    int64_t f = 0, e = 0, d = 0;
+    for (const imexhdg_config &c : cf) {
+        const int nel = c.nx * c.ny;
+        f += member_face_blocks(c.nx, c.ny, kMaxLaunchGrid);
+        e += member_elem_blocks(nel, c.degree + 1, kMaxLaunchGrid);
+        d += member_diag_blocks(nel);
+    }
+    const int64_t m = std::max<int64_t>(std::max(f, e), std::max<int64_t>(d, 1));
+    return (int)((m + 63) / 64 * 64);
+}
+
+// Distinct (hx, hy, dt) of a batch.
+int count_opsets(const std::vector<imexhdg_config> &cf) {
+    std::vector<std::vector<double>> seen;
+    for (const imexhdg_config &c : cf) {
+        const std::vector<double> key = {c.Lx / c.nx, c.Ly / c.ny, c.dt};
+        if (std::find(seen.begin(), seen.end(), key) == seen.end()) seen.push_back(key);
+    }
+    return (int)seen.size();
+}
 
 struct Layout {
-    size_t N, T, n_loc, n_tr, max_blocks, total;
-    int s;
+    size_t N = 0, T = 0, total = 0;
+    int s = 0, nops = 0, pstride = 0;
 };
 
-Layout layout_of(const imexhdg_config &c) {
+Layout layout_of(const std::vector<imexhdg_config> &cf) {
     Layout L{};
-    const size_t K = (size_t)c.degree + 1, nel = (size_t)c.nx * c.ny;
-    L.N = 3 * K * K * nel;
-    L.T = 6 * K * nel;
-    L.n_loc = 3 * K * K;
-    L.n_tr = 12 * K;
-    L.s = (c.scheme == IMEXHDG_SCHEME_ARS443) ? 5 : 3;
-    L.max_blocks = kPartStride;
+    const imexhdg_config &c0 = cf[0];
+    const size_t K = (size_t)c0.degree + 1;
+    for (const imexhdg_config &c : cf) {
+        const size_t nel = (size_t)c.nx * c.ny;
+        L.N += 3 * K * K * nel;
+        L.T += 6 * K * nel;
+    }
+    const size_t n_loc = 3 * K * K, n_tr = 12 * K;
+    L.s = (c0.scheme == IMEXHDG_SCHEME_ARS443) ? 5 : 3;
+    L.nops = count_opsets(cf);
+    L.pstride = partial_stride(cf);
+    const size_t nm = cf.size();
     size_t t = 0;
     t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
-    const size_t isz = (c.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
+    const size_t isz = (c0.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
     t += 4 * align256(L.T * 8);                        // FP64 trace vectors
     t += 10 * align256(L.T * isz);                     // inner-solve vectors
-    t += align256(L.n_loc * L.n_loc * 8) + align256(L.n_loc * L.n_tr * 8);
-    t += 2 * align256(frag_count((int)K) * 8) + 2 * align256(9 * K * K * 8);
-    t += align256(frag_count((int)K) * 4);             // FP32 Ghat fragments
-    t += 5 * align256(kPartStride * 8) + align256(5 * kPartStride * 8);
-    t += align256(sizeof(KrylovState));
-    t += align256(3 * (size_t)L.s * sizeof(StageStatus));
+    t += (size_t)L.nops * (align256(n_loc * n_loc * 8) + align256(n_loc * n_tr * 8) +
+                           2 * align256(frag_count((int)K) * 8) +
+                           align256(frag_count((int)K) * 4) + 2 * align256(9 * K * K * 8));
+    t += 5 * align256((size_t)L.pstride * 8) + align256(5 * (size_t)L.pstride * 8);
+    t += align256(nm * sizeof(KrylovState));
+    t += align256(nm * sizeof(Member));
+    t += align256(3 * (size_t)L.s * nm * sizeof(StageStatus));
     L.total = t;
     return L;
 }
@@ -228,6 +285,8 @@ int validate(const imexhdg_config *c) {
     if ((int64_t)c->nx * c->ny > (int64_t)1 << 28)
         return fail(IMEXHDG_E_INVAL, "too many elements");
     if (c->degree < 1 || c->degree > 8) return fail(IMEXHDG_E_INVAL, "degree must be in [1, 8]");
+    if ((int64_t)6 * (c->degree + 1) * c->nx * c->ny >= ((int64_t)1 << 31))
+        return fail(IMEXHDG_E_INVAL, "trace system too large (6 (k+1) nx ny >= 2^31)");
     if (!(c->Lx > 0) || !(c->Ly > 0) || !std::isfinite(c->Lx) || !std::isfinite(c->Ly))
         return fail(IMEXHDG_E_INVAL, "domain lengths must be positive and finite");
     if (!(c->g > 0) || !(c->H > 0) || !std::isfinite(c->g * c->H))
@@ -250,15 +309,37 @@ int validate(const imexhdg_config *c) {
     return IMEXHDG_OK;
 }
 
+// Members of one batch share everything but the mesh and the time step.
+int validate_batch(const imexhdg_config *cfgs, int n) {
+    if (!cfgs) return fail(IMEXHDG_E_INVAL, "configs are NULL");
+    if (n < 1) return fail(IMEXHDG_E_INVAL, "an ensemble needs at least one member");
+    for (int m = 0; m < n; ++m) {
+        int rc = validate(cfgs + m);
+        if (rc) return fail(rc, "member " + std::to_string(m) + ": " + g_last_error);
+        const imexhdg_config &a = cfgs[0], &b = cfgs[m];
+        if (a.degree != b.degree || a.g != b.g || a.H != b.H || a.scheme != b.scheme ||
+            a.physics != b.physics || a.precision != b.precision ||
+            a.krylov_rtol != b.krylov_rtol || a.krylov_max_iter != b.krylov_max_iter ||
+            a.check_every != b.check_every || a.refine_rtol != b.refine_rtol ||
+            a.refine_max != b.refine_max || a.launch != b.launch)
+            return fail(IMEXHDG_E_INVAL, "member " + std::to_string(m) +
+                                             " differs from member 0 in more than nx, ny, "
+                                             "Lx, Ly and dt");
+    }
+    if (n > 1 && cfgs[0].launch != IMEXHDG_LAUNCH_GRAPH)
+        return fail(IMEXHDG_E_INVAL, "an ensemble steps on the fixed launch schedule only");
+    return IMEXHDG_OK;
+}
+
 // Build the combination plans of Algorithm 1 for the configured tableau.
 // After stage i (0-based) the NL kernel (or a plain combination when the
 // physics is linearized) writes Res0_{i+1}, or q^{n+1} after the last stage.
 // The implicit residual of an implicit stage j is taken from its local
 // equation (eq. IMEXRKDiscretizedForm_localSolver):
 //   dt M^-1 L_j = (Q_j - Res0_j) / a~_jj.
+// NL terms carry no dt: the NL kernel's output is dt M^-1 NL.
 int build_plans(imexhdg_ctx *c) {
     const Tableau &t = c->tab;
-    const double dt = c->cfg.dt;
     const int s = t.s;
     for (int j = 0; j < s; ++j)
         if (t.at(j, j) == 0.0 && j != 0)
@@ -273,7 +354,7 @@ int build_plans(imexhdg_ctx *c) {
             const int m = i + 1;   // Res0_m
             add(p, QN, 1.0);
             for (int j = 0; j <= i; ++j) {
-                add(p, j == i ? SELF : NLV + j, dt * t.a(m, j));
+                add(p, j == i ? SELF : NLV + j, t.a(m, j));
                 if (j > 0) {
                     const double r = t.at(m, j) / t.at(j, j);
                     add(p, QV + j, r);
@@ -289,11 +370,11 @@ int build_plans(imexhdg_ctx *c) {
             if (stiff) {
                 add(p, QV + (s - 1), 1.0);
                 for (int j = 0; j < s; ++j)
-                    add(p, j == s - 1 ? SELF : NLV + j, dt * (t.b[j] - t.a(s - 1, j)));
+                    add(p, j == s - 1 ? SELF : NLV + j, t.b[j] - t.a(s - 1, j));
             } else {
                 add(p, QN, 1.0);
                 for (int j = 0; j < s; ++j) {
-                    add(p, j == s - 1 ? SELF : NLV + j, dt * t.b[j]);
+                    add(p, j == s - 1 ? SELF : NLV + j, t.b[j]);
                     if (j > 0) {
                         add(p, QV + j, t.bt[j] / t.at(j, j));
                         add(p, RV + j, -t.bt[j] / t.at(j, j));
@@ -308,6 +389,60 @@ int build_plans(imexhdg_ctx *c) {
     for (const Plan &p : c->plans)
         for (const Term &tm : p)
             if (tm.id >= NLV && tm.id < QV) c->store_nl[tm.id - NLV] = true;
+    return IMEXHDG_OK;
+}
+
+// Block ranges of every member for the current grid caps; uploads the
+// member table (not captured: call outside graph capture).
+int build_batch(imexhdg_ctx *c) {
+    const int K = c->geom.K;
+    int bv = 0, bf = 0, be = 0, bd = 0;
+    c->mtab.assign(c->nm, Member{});
+    for (int m = 0; m < c->nm; ++m) {
+        const MemberHost &h = c->mh[m];
+        const OpSet &o = c->ops[h.op];
+        Member &d = c->mtab[m];
+        d.nx = h.nx;
+        d.ny = h.ny;
+        d.nel = h.nel;
+        d.tiled = (h.nx % 16 == 0 && h.ny % 4 == 0) ? 1 : 0;
+        d.sx = 2.0 * h.nx / h.Lx;
+        d.sy = 2.0 * h.ny / h.Ly;
+        d.area = (h.Lx / h.nx / 2.0) * (h.Ly / h.ny / 2.0);
+        d.dt = h.dt;
+        d.vo = h.vo;
+        d.to = h.to;
+        d.bv = bv;
+        d.nbv = member_vol_blocks(h.nel);
+        d.bf = bf;
+        d.nbf = member_face_blocks(h.nx, h.ny, c->fgrid);
+        d.be = be;
+        d.nbe = member_elem_blocks(h.nel, K, c->egrid);
+        d.bd = bd;
+        d.nbd = member_diag_blocks(h.nel);
+        d.Ainv = o.Ainv;
+        d.W = o.W;
+        d.G = o.G;
+        d.Gh = o.Gh;
+        d.Px = o.Px;
+        d.Py = o.Py;
+        d.Ghf = o.Ghf;
+        bv += d.nbv;
+        bf += d.nbf;
+        be += d.nbe;
+        bd += d.nbd;
+    }
+    if (std::max(std::max(bf, be), bd) > c->pstride)
+        return fail(IMEXHDG_E_INVAL, "internal: partial-sum stride too small");
+    c->bt.m = c->dmem;
+    c->bt.nm = c->nm;
+    c->bt.nbv = bv;
+    c->bt.nbf = bf;
+    c->bt.nbe = be;
+    c->bt.nbd = bd;
+    HIP_TRY(hipMemcpyAsync(c->dmem, c->mtab.data(), c->nm * sizeof(Member),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return IMEXHDG_OK;
 }
 
@@ -374,18 +509,22 @@ int sync_read_ks(imexhdg_ctx *c) {
     return IMEXHDG_OK;
 }
 
-// Sum partials [nq][n] on the host in a fixed order (deterministic).
-int read_partials(imexhdg_ctx *c, int nq, unsigned n, double *out) {
-    HIP_TRY(hipMemcpy2DAsync(c->hpart, kPartStride * 8, c->dpart, kPartStride * 8, (size_t)n * 8,
-                             nq, hipMemcpyDeviceToHost, c->stream));
+// Sum partials [nq][first, first + n) on the host in a fixed order.
+int read_partials(imexhdg_ctx *c, int nq, int first, int n, double *out) {
+    HIP_TRY(hipMemcpy2DAsync(c->hpart, (size_t)c->pstride * 8, c->dpart + first,
+                             (size_t)c->pstride * 8, (size_t)n * 8, nq, hipMemcpyDeviceToHost,
+                             c->stream));
     HIP_TRY(stream_sync(c));
     for (int q = 0; q < nq; ++q) {
         double s = 0.0;
-        for (unsigned i = 0; i < n; ++i) s += c->hpart[(size_t)q * kPartStride + i];
+        for (int i = 0; i < n; ++i) s += c->hpart[(size_t)q * c->pstride + i];
         out[q] = s;
     }
     return IMEXHDG_OK;
 }
+
+// ------------------------------------------------ host-driven trace solve
+// (one member: the host reads the Krylov state of member 0)
 
 // Inner BiCGStab on Ghat d = rin in precision T, d0 = 0.  The operator is
 // the same for every stage and step, so the first sweep's iteration count
@@ -393,17 +532,19 @@ int read_partials(imexhdg_ctx *c, int nq, unsigned n, double *out) {
 // check, then check every two iterations (a converged solve turns the
 // remaining launches into no-ops, so few are wasted).
 template <typename T>
-int inner_solve(imexhdg_ctx *c, const T *Gh, double tol2, int sweep) {
+int inner_solve(imexhdg_ctx *c, double tol2, int sweep) {
     const imexhdg_config &cf = c->cfg;
     const Geom &g = c->geom;
+    const Batch &b = c->bt;
     T *rin = (T *)c->rin, *r = (T *)c->kr, *rh = (T *)c->krh, *sv = (T *)c->ks_,
       *t = (T *)c->kt, *d = (T *)c->kd;
     T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
     int rc;
     LAUNCH(IMEXHDG_K_BICG_INIT,
-           launch_bicg_init(g, (const T *)rin, r, rh, p[0], v[0], d, c->ks, tol2, c->kb, c->stream));
+           launch_bicg_init(g, b, (const T *)rin, r, rh, p[0], v[0], d, c->ks, tol2, c->kb,
+                            c->stream));
     int par = 0;     // p, v of the current iteration live in p[par], v[par]
-    LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par],
+    LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par],
                                              v[1 - par], c->ks, c->kb, c->stream));
     par = 1 - par;
     int done = 0;
@@ -413,10 +554,10 @@ int inner_solve(imexhdg_ctx *c, const T *Gh, double tol2, int sweep) {
         chunk = std::min(2, cf.check_every);
         for (int it = 0; it < n; ++it) {
             LAUNCH(IMEXHDG_K_BICG_K2,
-                   launch_bicg_k2(g, Gh, r, v[par], sv, t, c->ks, c->kb, c->stream));
+                   launch_bicg_k2(g, b, r, v[par], sv, t, c->ks, c->kb, c->stream));
             LAUNCH(IMEXHDG_K_BICG_K3,
-                   launch_bicg_k3(g, d, r, rh, p[par], sv, t, c->ks, c->kb, c->stream));
-            LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par],
+                   launch_bicg_k3(g, b, d, r, rh, p[par], sv, t, c->ks, c->kb, c->stream));
+            LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par],
                                                      v[1 - par], c->ks, c->kb, c->stream));
             par = 1 - par;
         }
@@ -436,19 +577,20 @@ int inner_solve(imexhdg_ctx *c, const T *Gh, double tol2, int sweep) {
 int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
     const imexhdg_config &cf = c->cfg;
     const Geom &g = c->geom;
+    const Batch &b = c->bt;
     int iters = 0;
     double relres = 0.0;
     for (int sweep = 0;; ++sweep) {
         int rc;
         LAUNCH(IMEXHDG_K_TRACE_RESID,
-               c->mixed ? launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
-                                                (float *)c->rin, c->dpart, kPartStride,
-                                                nullptr, c->stream)
-                        : launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
-                                                (double *)c->rin, c->dpart, kPartStride,
-                                                nullptr, c->stream));
+               c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64,
+                                                (float *)c->rin, c->dpart, c->pstride, nullptr,
+                                                c->stream)
+                        : launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64,
+                                                (double *)c->rin, c->dpart, c->pstride, nullptr,
+                                                c->stream));
         double nrm[4];
-        if ((rc = read_partials(c, 4, face_grid(g), nrm))) return rc;
+        if ((rc = read_partials(c, 4, 0, c->mtab[0].nbf, nrm))) return rc;
         const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
         if (!std::isfinite(gg) || !std::isfinite(rr) || !std::isfinite(rinrin)) {
             c->last_relres = NAN;
@@ -464,8 +606,7 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
         const double fl = 0.1 * cf.refine_rtol;
         const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
         const double tol2 = std::max(irt * irt * rinrin, fl * fl * ghh);
-        rc = c->mixed ? inner_solve<float>(c, c->dGhf, tol2, sweep)
-                      : inner_solve<double>(c, c->dGh, tol2, sweep);
+        rc = c->mixed ? inner_solve<float>(c, tol2, sweep) : inner_solve<double>(c, tol2, sweep);
         if (rc) return rc;
         iters += c->hks->iters;
         if (sweep < kMaxSweeps) {
@@ -486,12 +627,11 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
 
 // One implicit stage: Z = A^-1 R, g = C Z, solve G x = g, Q = Z - W x.
 int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres) {
-    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->dAinv, R, c->Z, c->stream));
-    LAUNCH(IMEXHDG_K_TRACE_RHS,
-           launch_trace_rhs(c->geom, c->Z, c->dPx, c->dPy, c->gv, c->gh, c->stream));
+    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->gh, c->stream));
     int rc = trace_solve(c, iters, relres);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
-    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->dW, c->Z, c->x, Q, c->stream));
+    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->bt, c->Z, c->x, Q, c->stream));
     return rc;
 }
 
@@ -511,17 +651,16 @@ int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
         cb.n += 1;
     }
     if (nonlinear) {
-        LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, Qi, cb, c->stream));
+        LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, Qi, cb, true, c->stream));
     } else {
-        LAUNCH(IMEXHDG_K_COMBINE, launch_combine(c->geom, cb, c->N, c->stream));
+        LAUNCH(IMEXHDG_K_COMBINE, launch_combine(cb, c->N, c->stream));
     }
     return IMEXHDG_OK;
 }
 
-
 // ------------------------------------------------ host-driven step
 // One step of Algorithm 1 from qin to qout; the trace solves are driven by
-// host reads of the residual and the Krylov state.
+// host reads of the residual and the Krylov state (one member).
 int step_host(imexhdg_ctx *c, const double *qin, double *qout, int *status) {
     const int s = c->tab.s;
     c->qin = qin;
@@ -542,74 +681,69 @@ int step_host(imexhdg_ctx *c, const double *qin, double *qout, int *status) {
 
 // ------------------------------------------------ fixed launch schedule
 // The same trace solve as trace_solve(), with every decision taken on the
-// device: per sweep the FP64 residual, the refinement check (which ends the
-// stage solve once refine_rtol is met and otherwise opens an inner solve),
-// K1 and `budget` rounds of K2, K3, K1, and x += d.  Launches after
-// convergence return at entry.
+// device, per member: per sweep the FP64 residual, the refinement check
+// (which ends the member's stage solve once refine_rtol is met and
+// otherwise opens an inner solve), K1 and `budget` rounds of K2, K3, K1,
+// and x += d.  Launches after convergence return at entry.
 template <typename T>
-int sched_sweep(imexhdg_ctx *c, const T *Gh, int budget, double inner_rtol) {
+int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     const Geom &g = c->geom;
+    const Batch &b = c->bt;
     T *rin = (T *)c->rin, *r = (T *)c->kr, *rh = (T *)c->krh, *sv = (T *)c->ks_,
       *t = (T *)c->kt, *d = (T *)c->kd;
     T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
     KrylovBufs kb = c->kb;
     kb.sched = 1;
-    const int32_t *done =
-        (const int32_t *)((const char *)c->ks + offsetof(KrylovState, stage_done));
-    HIP_TRY(launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64, rin, c->dpart,
-                                  kPartStride, done, c->stream));
-    HIP_TRY(launch_refine_check(g, (const T *)rin, r, rh, p[0], v[0], d, c->ks, c->dpart,
-                                kPartStride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
+    HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64, rin, c->dpart, c->pstride,
+                                  c->ks, c->stream));
+    HIP_TRY(launch_refine_check(g, b, (const T *)rin, r, rh, p[0], v[0], d, c->ks, c->dpart,
+                                c->pstride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
     int par = 0;
-    HIP_TRY(launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
+    HIP_TRY(launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
                            c->stream));
     par = 1 - par;
     for (int it = 0; it < budget; ++it) {
-        HIP_TRY(launch_bicg_k2(g, Gh, r, v[par], sv, t, c->ks, kb, c->stream));
-        HIP_TRY(launch_bicg_k3(g, d, r, rh, p[par], sv, t, c->ks, kb, c->stream));
-        HIP_TRY(launch_bicg_k1(g, Gh, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
+        HIP_TRY(launch_bicg_k2(g, b, r, v[par], sv, t, c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k3(g, b, d, r, rh, p[par], sv, t, c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
                                c->stream));
         par = 1 - par;
     }
-    HIP_TRY(launch_axpy_guarded(c->x, (const T *)d, c->T, c->ks, c->stream));
+    HIP_TRY(launch_axpy_guarded(g, b, c->x, (const T *)d, c->ks, c->stream));
     return IMEXHDG_OK;
 }
 
 int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *st) {
     const Geom &g = c->geom;
+    const Batch &b = c->bt;
     const imexhdg_config &cf = c->cfg;
-    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, c->dAinv, R, c->Z, c->stream));
-    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, c->Z, c->dPx, c->dPy, c->gv, c->gh, c->stream));
-    HIP_TRY(launch_stage_begin(c->ks, c->stream));
+    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->gh, c->stream));
+    HIP_TRY(launch_stage_begin(b, c->ks, c->stream));
     const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
     for (int sw = 0; sw < c->sched_sweeps; ++sw) {
-        const int b = c->sched_budget[sw];
-        int rc = c->mixed ? sched_sweep<float>(c, c->dGhf, b, irt)
-                          : sched_sweep<double>(c, c->dGh, b, irt);
+        const int bud = c->sched_budget[sw];
+        int rc = c->mixed ? sched_sweep<float>(c, bud, irt) : sched_sweep<double>(c, bud, irt);
         if (rc) return rc;
     }
-    const int32_t *done =
-        (const int32_t *)((const char *)c->ks + offsetof(KrylovState, stage_done));
-    HIP_TRY(c->mixed ? launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
-                                             (float *)c->rin, c->dpart, kPartStride, done,
-                                             c->stream)
-                     : launch_trace_residual(g, c->dG, c->dGh, c->x, c->gv, c->gh, c->r64,
-                                             (double *)c->rin, c->dpart, kPartStride, done,
-                                             c->stream));
-    HIP_TRY(launch_stage_finish(g, c->ks, c->dpart, kPartStride, st, c->stream));
-    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, c->dW, c->Z, c->x, Q, c->stream));
+    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64, (float *)c->rin,
+                                             c->dpart, c->pstride, c->ks, c->stream)
+                     : launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64, (double *)c->rin,
+                                             c->dpart, c->pstride, c->ks, c->stream));
+    HIP_TRY(launch_stage_finish(b, c->ks, c->dpart, c->pstride, st, c->stream));
+    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream));
     return IMEXHDG_OK;
 }
 
-// One step on the fixed schedule from qin to qout; stage i records its
-// outcome in st[i].  Nothing here reads from the device.
+// One step on the fixed schedule from qin to qout; stage i records the
+// outcome of member m in st[i nm + m].  Nothing here reads from the device.
 int step_sched(imexhdg_ctx *c, const double *qin, double *qout, StageStatus *st) {
     const int s = c->tab.s;
     c->qin = qin;
     for (int i = 0; i < s; ++i) {
         const double *Qi = qin;
         if (i > 0) {
-            int rc = stage_solve_sched(c, c->Rb[i], c->Qb[i], st + i);
+            int rc = stage_solve_sched(c, c->Rb[i], c->Qb[i], st + (size_t)i * c->nm);
             if (rc) return rc;
             Qi = c->Qb[i];
         }
@@ -640,10 +774,12 @@ void reset_window(imexhdg_ctx *c) {
     for (int &v : c->win_iters) v = 0;
 }
 
+int max_sweeps(const imexhdg_ctx *c) { return std::min((int)c->cfg.refine_max, kMaxSweeps); }
+
 // Schedule from observed sweeps / per-sweep iterations plus the margin.
 void schedule_from(imexhdg_ctx *c, int sweeps, const int *iters, bool widen_only) {
     const imexhdg_config &cf = c->cfg;
-    int ns = std::min(std::max(sweeps, 1), std::min((int)cf.refine_max, kMaxSweeps));
+    int ns = std::min(std::max(sweeps, 1), max_sweeps(c));
     int b[kMaxSweeps];
     for (int i = 0; i < kMaxSweeps; ++i)
         b[i] = std::min(iters[i] + c->margin, (int)cf.krylov_max_iter);
@@ -668,7 +804,8 @@ int capture(imexhdg_ctx *c) {
         HIP_TRY(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
         c->stream = c->gstream;
         c->prof_target = -2;
-        const int rc = step_sched(c, c->qbuf[a], c->qbuf[(a + 1) % 3], c->dstat + (size_t)a * s);
+        const int rc = step_sched(c, c->qbuf[a], c->qbuf[(a + 1) % 3],
+                                  c->dstat + (size_t)a * s * c->nm);
         c->stream = user;
         c->prof_target = prof;
         hipGraph_t graph = nullptr;
@@ -701,30 +838,128 @@ void advance(imexhdg_ctx *c) {
     c->steps += 1;
 }
 
-// Graph stepping.  After a cold start (fresh trace guess) one host-driven
-// step; then, once, a host-driven step that measures the schedule, and the
-// capture.  Graph steps are verified one step behind: before step m + 2 is
-// launched (it overwrites the input of step m), step m's stage outcomes are
-// read.  A failed step is redone host-driven from its input, and the
-// schedule is widened; after 64 verified steps a schedule that has become
-// loose by at least two iterations is tightened.
+// Stage outcomes of one step (st = [s][nm]): did every member meet
+// refine_rtol?  If so and `record`, adds them to the counters and window.
+bool check_step(imexhdg_ctx *c, const StageStatus *st, bool record) {
+    const imexhdg_config &cf = c->cfg;
+    const int s = c->tab.s;
+    bool ok = true;
+    for (int i = 0; i < s; ++i)
+        if (implicit_stage(c, i))
+            for (int m = 0; m < c->nm; ++m) {
+                const StageStatus &x = st[(size_t)i * c->nm + m];
+                ok = ok && std::isfinite(x.relres) && x.relres <= cf.refine_rtol;
+            }
+    if (!ok || !record) return ok;
+    for (int i = 0; i < s; ++i) {
+        if (!implicit_stage(c, i)) continue;
+        for (int m = 0; m < c->nm; ++m) {
+            const StageStatus &x = st[(size_t)i * c->nm + m];
+            c->kiters += x.iters_total;
+            c->sweeps += x.sweeps;
+            c->last_relres = x.relres;
+            c->max_relres = std::max(c->max_relres, x.relres);
+            c->win_sweeps = std::max(c->win_sweeps, (int)x.sweeps);
+            for (int w = 0; w < kMaxSweeps; ++w)
+                c->win_iters[w] = std::max(c->win_iters[w], (int)x.sweep_iters[w]);
+        }
+        c->solves += 1;
+    }
+    return true;
+}
+
+// Observations of a step that may have failed (all members, all stages).
+void observe(imexhdg_ctx *c, const StageStatus *st, int *sweeps, int *iters) {
+    *sweeps = 0;
+    for (int w = 0; w < kMaxSweeps; ++w) iters[w] = 0;
+    for (int i = 0; i < c->tab.s; ++i)
+        if (implicit_stage(c, i))
+            for (int m = 0; m < c->nm; ++m) {
+                const StageStatus &x = st[(size_t)i * c->nm + m];
+                *sweeps = std::max(*sweeps, (int)x.sweeps);
+                for (int w = 0; w < kMaxSweeps; ++w)
+                    iters[w] = std::max(iters[w], (int)x.sweep_iters[w]);
+            }
+}
+
+// Step on the fixed schedule, eagerly, from ring position a; widens the
+// schedule and repeats until every member meets refine_rtol or the schedule
+// is at refine_max sweeps of krylov_max_iter iterations.  Then sets the
+// schedule to what the step used plus the margin.
+int step_sched_eager(imexhdg_ctx *c, int a, int *status) {
+    const imexhdg_config &cf = c->cfg;
+    const int s = c->tab.s;
+    StageStatus *dst = c->dstat + (size_t)a * s * c->nm;
+    StageStatus *hst = c->hstat + (size_t)a * s * c->nm;
+    for (;;) {
+        int rc = step_sched(c, c->qbuf[a], c->qbuf[(a + 1) % 3], dst);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(hst, dst, (size_t)s * c->nm * sizeof(StageStatus),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(stream_sync(c));
+        for (int i = 0; i < s; ++i)
+            for (int m = 0; m < c->nm; ++m)
+                if (implicit_stage(c, i) && !std::isfinite(hst[(size_t)i * c->nm + m].relres))
+                    return fail(IMEXHDG_E_NONFINITE, "non-finite trace residual");
+        const bool full = c->sched_sweeps >= max_sweeps(c) &&
+                          c->sched_budget[c->sched_sweeps - 1] >= cf.krylov_max_iter;
+        const bool ok = check_step(c, hst, true);
+        if (ok || full) {
+            if (!ok) *status = IMEXHDG_E_NOCONV;
+            int sw, it[kMaxSweeps];
+            observe(c, hst, &sw, it);
+            schedule_from(c, sw, it, false);
+            return IMEXHDG_OK;
+        }
+        // widen: one more sweep and half again the budget of every sweep
+        c->redos += 1;
+        const int ns = std::min(c->sched_sweeps + 1, max_sweeps(c));
+        for (int w = 0; w < ns; ++w) {
+            const int b0 = w < c->sched_sweeps ? c->sched_budget[w] : c->sched_budget[0];
+            c->sched_budget[w] = std::min((int)cf.krylov_max_iter, std::max(b0 + 4, b0 * 3 / 2));
+        }
+        c->sched_sweeps = ns;
+    }
+}
+
+// Graph stepping.  One member: after a cold start (fresh trace guess) one
+// host-driven step; then, once, a host-driven step that measures the
+// schedule, and the capture.  Several members: cold and learning steps run
+// eagerly on a probe schedule (widened until every member converges).
+// Graph steps are verified one step behind: before step m + 2 is launched
+// (it overwrites the input of step m), step m's stage outcomes are read.
+// A failed step is redone (host-driven for one member, on a widened eager
+// schedule for several) and the schedule widened; after 64 verified steps a
+// schedule that has become loose by at least two iterations is tightened.
 int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
     const imexhdg_config &cf = c->cfg;
     const int s = c->tab.s;
+    const size_t slot = (size_t)s * c->nm;
     int done = 0;
     while (done < nsteps && (c->cold || !c->gready)) {
-        const bool learn = !c->cold;
-        if (learn) reset_learn(c);
         const int a = c->cur;
-        int rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], status);
-        if (rc) return rc;
+        const bool learn = !c->cold;
+        int rc;
+        if (c->nm == 1) {
+            if (learn) reset_learn(c);
+            rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], status);
+            if (rc) return rc;
+            if (learn) schedule_from(c, c->learn_sweeps, c->learn_iters, false);
+        } else {
+            if (c->sched_sweeps == 0) {
+                // probe schedule for the first step
+                c->sched_sweeps = max_sweeps(c);
+                for (int w = 0; w < kMaxSweeps; ++w)
+                    c->sched_budget[w] =
+                        w < c->sched_sweeps ? std::min((int)cf.krylov_max_iter, 64) : 0;
+            }
+            rc = step_sched_eager(c, a, status);
+            if (rc) return rc;
+        }
         advance(c);
         ++done;
         c->cold = false;
-        if (learn) {
-            schedule_from(c, c->learn_sweeps, c->learn_iters, false);
-            if ((rc = capture(c))) return rc;
-        }
+        if (learn && (rc = capture(c))) return rc;
     }
     int inflight[2] = {0, 0}, nin = 0, next = c->cur, launched = done;
     bool want = false;
@@ -738,8 +973,9 @@ int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
         if (!want && launched < nsteps && nin < 2) {
             const int a = next;
             HIP_TRY(hipGraphLaunch(c->gexec[a], c->stream));
-            HIP_TRY(hipMemcpyAsync(c->hstat + (size_t)a * s, c->dstat + (size_t)a * s,
-                                   s * sizeof(StageStatus), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->hstat + a * slot, c->dstat + a * slot,
+                                   slot * sizeof(StageStatus), hipMemcpyDeviceToHost,
+                                   c->stream));
             HIP_TRY(hipEventRecord(c->gev[a], c->stream));
             inflight[nin++] = a;
             next = (a + 1) % 3;
@@ -750,23 +986,7 @@ int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
         inflight[0] = inflight[1];
         --nin;
         HIP_TRY(hipEventSynchronize(c->gev[a]));
-        const StageStatus *st = c->hstat + (size_t)a * s;
-        bool ok = true;
-        for (int i = 0; i < s; ++i)
-            if (implicit_stage(c, i))
-                ok = ok && std::isfinite(st[i].relres) && st[i].relres <= cf.refine_rtol;
-        if (ok) {
-            for (int i = 0; i < s; ++i) {
-                if (!implicit_stage(c, i)) continue;
-                c->kiters += st[i].iters_total;
-                c->solves += 1;
-                c->sweeps += st[i].sweeps;
-                c->last_relres = st[i].relres;
-                c->max_relres = std::max(c->max_relres, st[i].relres);
-                c->win_sweeps = std::max(c->win_sweeps, (int)st[i].sweeps);
-                for (int w = 0; w < kMaxSweeps; ++w)
-                    c->win_iters[w] = std::max(c->win_iters[w], (int)st[i].sweep_iters[w]);
-            }
+        if (check_step(c, c->hstat + a * slot, true)) {
             c->graph_steps += 1;
             c->win_steps += 1;
             advance(c);
@@ -783,83 +1003,144 @@ int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
             }
             continue;
         }
-        // the step missed refine_rtol on the schedule: redo it host-driven
+        // the step missed refine_rtol on the schedule: redo it
         HIP_TRY(stream_sync(c));
         nin = 0;
         want = false;
         c->redos += 1;
-        reset_learn(c);
-        int rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], status);
-        if (rc) return rc;
+        c->margin = std::min(c->margin + 2, 16);
+        int rc;
+        if (c->nm == 1) {
+            reset_learn(c);
+            rc = step_host(c, c->qbuf[a], c->qbuf[(a + 1) % 3], status);
+            if (rc) return rc;
+            schedule_from(c, c->learn_sweeps, c->learn_iters, true);
+        } else {
+            rc = step_sched_eager(c, a, status);
+            if (rc) return rc;
+        }
         c->cur = a;
         advance(c);
         ++done;
         launched = done;
         next = c->cur;
-        c->margin = std::min(c->margin + 2, 16);
-        schedule_from(c, c->learn_sweeps, c->learn_iters, true);
         if ((rc = capture(c))) return rc;
     }
     return IMEXHDG_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int imexhdg_config_init(imexhdg_config *c) {
-    if (!c) return fail(IMEXHDG_E_INVAL, "config is NULL");
-    std::memset(c, 0, sizeof(*c));
-    c->nx = c->ny = 1;
-    c->Lx = c->Ly = 1.0;
-    c->degree = 2;
-    c->g = c->H = 1.0;
-    c->dt = 1e-3;
-    c->scheme = IMEXHDG_SCHEME_ARS232;
-    c->physics = IMEXHDG_PHYSICS_NONLINEAR;
-    c->precision = IMEXHDG_PREC_FP64;
-    c->krylov_rtol = 1e-14;
-    c->krylov_max_iter = 500;
-    c->check_every = 8;
-    c->refine_rtol = 1e-13;
-    c->refine_max = 4;
+// Convert a member's host state (user ordering [ey][ex][j][i]) to the device
+// layout in h (3 K^2 nel values).
+int state_to_device(const imexhdg_ctx *c, const MemberHost &m, int vars, const double *a,
+                    const double *b, const double *cc, std::vector<double> &h) {
+    const int K = c->geom.K, nel = m.nel;
+    const double g = c->cfg.g, H = c->cfg.H, phiB = g * H;
+    const size_t NN = (size_t)K * K * nel;
+    h.assign(3 * NN, 0.0);
+    for (int e = 0; e < nel; ++e)
+        for (int n = 0; n < K * K; ++n) {
+            const size_t src = (size_t)e * K * K + n, dst = (size_t)n * nel + e;
+            double p, U, V;
+            if (vars == IMEXHDG_VARS_DEPTH) {
+                p = g * (a[src] - H);
+                U = g * b[src];
+                V = g * cc[src];
+            } else {
+                p = a[src];
+                U = b[src];
+                V = cc[src];
+            }
+            const double phi = p + phiB;
+            if (!std::isfinite(p) || !std::isfinite(U) || !std::isfinite(V))
+                return fail(IMEXHDG_E_INVAL, "state holds NaN or Inf");
+            if (!(phi > 0)) return fail(IMEXHDG_E_INVAL, "total depth must be positive");
+            if (U * U + V * V >= phi * phi * phi)
+                return fail(IMEXHDG_E_INVAL, "supercritical state: |u| >= sqrt(phi)");
+            h[dst] = p;
+            h[NN + dst] = U;
+            h[2 * NN + dst] = V;
+        }
     return IMEXHDG_OK;
 }
 
-int imexhdg_validate(const imexhdg_config *cfg) { return validate(cfg); }
-
-int imexhdg_workspace_bytes(const imexhdg_config *cfg, size_t *bytes) {
-    int rc = validate(cfg);
-    if (rc) return rc;
-    if (!bytes) return fail(IMEXHDG_E_INVAL, "bytes is NULL");
-    *bytes = layout_of(*cfg).total;
-    return IMEXHDG_OK;
+void state_from_device(const imexhdg_ctx *c, const MemberHost &m, int vars,
+                       const std::vector<double> &h, double *a, double *b, double *cc) {
+    const int K = c->geom.K, nel = m.nel;
+    const double g = c->cfg.g, H = c->cfg.H;
+    const size_t NN = (size_t)K * K * nel;
+    for (int e = 0; e < nel; ++e)
+        for (int n = 0; n < K * K; ++n) {
+            const size_t dst = (size_t)e * K * K + n, src = (size_t)n * nel + e;
+            const double p = h[src], U = h[NN + src], V = h[2 * NN + src];
+            if (vars == IMEXHDG_VARS_DEPTH) {
+                a[dst] = H + p / g;
+                b[dst] = U / g;
+                cc[dst] = V / g;
+            } else {
+                a[dst] = p;
+                b[dst] = U;
+                cc[dst] = V;
+            }
+        }
 }
 
-const char *imexhdg_last_error(void) { return g_last_error.c_str(); }
+void get_nodes_of(const imexhdg_ctx *c, const MemberHost &m, double *x, double *y) {
+    const int K = c->geom.K;
+    const double hx = m.Lx / m.nx, hy = m.Ly / m.ny;
+    size_t o = 0;
+    for (int ey = 0; ey < m.ny; ++ey)
+        for (int ex = 0; ex < m.nx; ++ex)
+            for (int j = 0; j < K; ++j)
+                for (int i = 0; i < K; ++i, ++o) {
+                    x[o] = (ex + (c->ref.x[i] + 1.0) / 2.0) * hx;
+                    y[o] = (ey + (c->ref.x[j] + 1.0) / 2.0) * hy;
+                }
+}
 
-int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, size_t ws_bytes,
-                   imexhdg_ctx **out) {
-    int rc = validate(cfg);
-    if (rc) return rc;
-    if (!out) return fail(IMEXHDG_E_INVAL, "out is NULL");
+void destroy_ctx(imexhdg_ctx *c) {
+    if (!c) return;
+    if (c->ws || c->hks) (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < c->ev0.size(); ++i) {
+        (void)hipEventDestroy(c->ev0[i]);
+        (void)hipEventDestroy(c->ev1[i]);
+    }
+    drop_graphs(c);
+    for (hipEvent_t e : c->gev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->hstat) (void)hipHostFree(c->hstat);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->hks) (void)hipHostFree(c->hks);
+    if (c->hpart) (void)hipHostFree(c->hpart);
+    delete c;
+}
+
+// Create the engine for a batch of validated configs.
+int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
+               size_t ws_bytes, imexhdg_ctx **out) {
     *out = nullptr;
-    const Layout L = layout_of(*cfg);
+    const std::vector<imexhdg_config> cf(cfgs, cfgs + n);
+    const Layout L = layout_of(cf);
     if (workspace && ws_bytes < L.total)
-        return fail(IMEXHDG_E_INVAL, "workspace smaller than imexhdg_workspace_bytes()");
+        return fail(IMEXHDG_E_INVAL, "workspace smaller than the workspace_bytes() figure");
     if (workspace && ((uintptr_t)workspace & 255))
         return fail(IMEXHDG_E_INVAL, "workspace must be 256-byte aligned");
     imexhdg_ctx *c = new (std::nothrow) imexhdg_ctx();
     if (!c) return fail(IMEXHDG_E_NOMEM, "host allocation failed");
-    c->cfg = *cfg;
+    c->cfg = cf[0];
+    c->nm = n;
     c->stream = (hipStream_t)stream;
+    c->pstride = L.pstride;
+    c->member_set.assign(n, false);
     auto bail = [&](int code) {
-        imexhdg_destroy(c);
+        destroy_ctx(c);
         return code;
     };
+    const int K = cf[0].degree + 1;
+    std::vector<StageOperators> hops;
     try {
-        c->ref = make_lgl(cfg->degree);
-        c->tab = make_tableau(cfg->scheme);
+        c->ref = make_lgl(cf[0].degree);
+        c->tab = make_tableau(cf[0].scheme);
         double aii = 0.0;
         for (int i = 0; i < c->tab.s; ++i)
             if (c->tab.at(i, i) != 0.0) {
@@ -868,33 +1149,54 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
                 aii = c->tab.at(i, i);
             }
         c->aii = aii;
-        const double hx = cfg->Lx / cfg->nx, hy = cfg->Ly / cfg->ny;
-        c->op = make_stage_operators(c->ref, hx, hy, cfg->g * cfg->H, cfg->dt * aii);
+        size_t vo = 0, to = 0;
+        for (int m = 0; m < n; ++m) {
+            MemberHost h;
+            h.nx = cf[m].nx;
+            h.ny = cf[m].ny;
+            h.nel = h.nx * h.ny;
+            h.Lx = cf[m].Lx;
+            h.Ly = cf[m].Ly;
+            h.dt = cf[m].dt;
+            h.N = (size_t)3 * K * K * h.nel;
+            h.T = (size_t)6 * K * h.nel;
+            h.vo = vo;
+            h.to = to;
+            vo += h.N;
+            to += h.T;
+            const double hx = h.Lx / h.nx, hy = h.Ly / h.ny;
+            int found = -1;
+            for (size_t o = 0; o < c->ops.size(); ++o)
+                if (c->ops[o].hx == hx && c->ops[o].hy == hy && c->ops[o].dt == h.dt)
+                    found = (int)o;
+            if (found < 0) {
+                OpSet os;
+                os.hx = hx;
+                os.hy = hy;
+                os.dt = h.dt;
+                c->ops.push_back(os);
+                hops.push_back(make_stage_operators(c->ref, hx, hy, cf[0].g * cf[0].H,
+                                                    h.dt * c->aii));
+                found = (int)c->ops.size() - 1;
+            }
+            h.op = found;
+            c->mh.push_back(h);
+        }
     } catch (const std::exception &e) {
         return bail(fail(IMEXHDG_E_INVAL, std::string("precompute: ") + e.what()));
     }
+    int rc;
     if ((rc = build_plans(c))) return bail(rc);
-    const int K = cfg->degree + 1;
     Geom &g = c->geom;
-    g.nx = cfg->nx;
-    g.ny = cfg->ny;
-    g.nel = cfg->nx * cfg->ny;
     g.K = K;
-    g.sx = 2.0 * cfg->nx / cfg->Lx;
-    g.sy = 2.0 * cfg->ny / cfg->Ly;
-    g.phiB = cfg->g * cfg->H;
+    g.phiB = cf[0].g * cf[0].H;
     g.tau = std::sqrt(g.phiB);
     g.winv0 = 1.0 / c->ref.w[0];
     g.winvk = 1.0 / c->ref.w[K - 1];
+    for (int i = 0; i < K; ++i) g.w[i] = c->ref.w[i];
     for (int m = 0; m < K; ++m)
         for (int a = 0; a < K; ++a)
             g.Dw[m * K + a] = c->ref.w[m] * c->ref.D[m * K + a] / c->ref.w[a];
-    for (int j = 0; j < K; ++j)
-        for (int i = 0; i < K; ++i)
-            g.mass[j * K + i] = (cfg->Lx / cfg->nx / 2.0) * (cfg->Ly / cfg->ny / 2.0) *
-                                c->ref.w[i] * c->ref.w[j];
-    g.fgrid = 1024;
-    g.egrid = 1024;
     c->N = L.N;
     c->T = L.T;
     c->nnodes = L.N / 3;
@@ -925,31 +1227,36 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
     for (int i = 0; i < L.s; ++i) c->NLb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
-    c->mixed = cfg->precision == IMEXHDG_PREC_MIXED;
+    c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
     double **tv[4] = {&c->x, &c->gv, &c->gh, &c->r64};
     for (double **p : tv) *p = (double *)take(L.T * 8);
     void **iv[10] = {&c->rin, &c->kr, &c->krh, &c->kp[0], &c->kp[1],
                      &c->kv[0], &c->kv[1], &c->ks_, &c->kt, &c->kd};
     for (void **p : iv) *p = take(L.T * (c->mixed ? 4 : 8));
-    c->dAinv = (double *)take(L.n_loc * L.n_loc * 8);
-    c->dW = (double *)take(L.n_loc * L.n_tr * 8);
-    c->dG = (double *)take(frag_count(K) * 8);
-    c->dGh = (double *)take(frag_count(K) * 8);
-    c->dGhf = (float *)take(frag_count(K) * 4);
-    c->dPx = (double *)take(9 * K * K * 8);
-    c->dPy = (double *)take(9 * K * K * 8);
-    c->kb.P1 = (double *)take(kPartStride * 8);
-    c->kb.P2 = (double *)take(2 * kPartStride * 8);
-    c->kb.P3 = (double *)take(2 * kPartStride * 8);
-    c->kb.stride = kPartStride;
-    c->dpart = (double *)take(5 * kPartStride * 8);
-    c->ks = (KrylovState *)take(sizeof(KrylovState));
-    c->dstat = (StageStatus *)take(3 * (size_t)L.s * sizeof(StageStatus));
+    const size_t n_loc = 3 * K * K, n_tr = 12 * K;
+    for (OpSet &o : c->ops) {
+        o.Ainv = (double *)take(n_loc * n_loc * 8);
+        o.W = (double *)take(n_loc * n_tr * 8);
+        o.G = (double *)take(frag_count(K) * 8);
+        o.Gh = (double *)take(frag_count(K) * 8);
+        o.Ghf = (float *)take(frag_count(K) * 4);
+        o.Px = (double *)take(9 * K * K * 8);
+        o.Py = (double *)take(9 * K * K * 8);
+    }
+    c->kb.P1 = (double *)take((size_t)c->pstride * 8);
+    c->kb.P2 = (double *)take(2 * (size_t)c->pstride * 8);
+    c->kb.P3 = (double *)take(2 * (size_t)c->pstride * 8);
+    c->kb.stride = c->pstride;
+    c->dpart = (double *)take(5 * (size_t)c->pstride * 8);
+    c->ks = (KrylovState *)take(n * sizeof(KrylovState));
+    c->dmem = (Member *)take(n * sizeof(Member));
+    c->dstat = (StageStatus *)take(3 * (size_t)L.s * n * sizeof(StageStatus));
     if (off > c->ws_bytes) return bail(fail(IMEXHDG_E_INVAL, "internal: workspace overflow"));
 
     if (hipHostMalloc((void **)&c->hks, sizeof(KrylovState)) != hipSuccess ||
-        hipHostMalloc((void **)&c->hpart, 5 * kPartStride * 8) != hipSuccess ||
-        hipHostMalloc((void **)&c->hstat, 3 * (size_t)L.s * sizeof(StageStatus)) != hipSuccess)
+        hipHostMalloc((void **)&c->hpart, 5 * (size_t)c->pstride * 8) != hipSuccess ||
+        hipHostMalloc((void **)&c->hstat, 3 * (size_t)L.s * n * sizeof(StageStatus)) !=
+            hipSuccess)
         return bail(fail(IMEXHDG_E_NOMEM, "hipHostMalloc failed"));
     for (hipEvent_t &e : c->gev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
@@ -957,141 +1264,37 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, siz
             return bail(fail(IMEXHDG_E_DEVICE, "hipEventCreate failed"));
         }
 
-    const StageOperators &op = c->op;
-    const std::vector<double> G = pack_frags(op.Gx, op.Gy, K);
-    const std::vector<double> Gh = pack_frags(op.Gxh, op.Gyh, K);
-    const std::vector<float> Ghf(Gh.begin(), Gh.end());
-    auto up = [&](double *d, const std::vector<double> &h) {
-        return hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream);
-    };
-    if (up(c->dAinv, op.Ainv) || up(c->dW, op.W) || up(c->dG, G) || up(c->dGh, Gh) ||
-        hipMemcpyAsync(c->dGhf, Ghf.data(), Ghf.size() * 4, hipMemcpyHostToDevice, c->stream) ||
-        up(c->dPx, op.Pxinv) || up(c->dPy, op.Pyinv) ||
-        hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
+    for (size_t o = 0; o < c->ops.size(); ++o) {
+        const StageOperators &op = hops[o];
+        const std::vector<double> G = pack_frags(op.Gx, op.Gy, K);
+        const std::vector<double> Gh = pack_frags(op.Gxh, op.Gyh, K);
+        const std::vector<float> Ghf(Gh.begin(), Gh.end());
+        auto up = [&](double *d, const std::vector<double> &h) {
+            return hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream);
+        };
+        const OpSet &os = c->ops[o];
+        if (up(os.Ainv, op.Ainv) || up(os.W, op.W) || up(os.G, G) || up(os.Gh, Gh) ||
+            hipMemcpyAsync(os.Ghf, Ghf.data(), Ghf.size() * 4, hipMemcpyHostToDevice,
+                           c->stream) ||
+            up(os.Px, op.Pxinv) || up(os.Py, op.Pyinv) || hipStreamSynchronize(c->stream))
+            return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+    }
+    if (hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
         hipMemsetAsync(c->q, 0, L.N * 8, c->stream) ||
-        hipMemsetAsync(c->dstat, 0, 3 * (size_t)L.s * sizeof(StageStatus), c->stream) ||
+        hipMemsetAsync(c->dstat, 0, 3 * (size_t)L.s * n * sizeof(StageStatus), c->stream) ||
         hipStreamSynchronize(c->stream))
-        return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+        return bail(fail(IMEXHDG_E_DEVICE, "workspace initialisation failed"));
+    if ((rc = build_batch(c))) return bail(rc);
     *out = c;
     g_last_error.clear();
     return IMEXHDG_OK;
 }
 
-void imexhdg_destroy(imexhdg_ctx *c) {
-    if (!c) return;
-    if (c->ws || c->hks) (void)hipStreamSynchronize(c->stream);
-    for (size_t i = 0; i < c->ev0.size(); ++i) {
-        (void)hipEventDestroy(c->ev0[i]);
-        (void)hipEventDestroy(c->ev1[i]);
-    }
-    drop_graphs(c);
-    for (hipEvent_t e : c->gev)
-        if (e) (void)hipEventDestroy(e);
-    if (c->gstream) (void)hipStreamDestroy(c->gstream);
-    if (c->hstat) (void)hipHostFree(c->hstat);
-    if (c->own_ws && c->ws) (void)hipFree(c->ws);
-    if (c->hks) (void)hipHostFree(c->hks);
-    if (c->hpart) (void)hipHostFree(c->hpart);
-    delete c;
-}
-
-int imexhdg_sizes(const imexhdg_ctx *c, int64_t *n_nodes, int64_t *n_trace) {
-    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
-    if (n_nodes) *n_nodes = (int64_t)c->nnodes;
-    if (n_trace) *n_trace = (int64_t)c->T;
-    return IMEXHDG_OK;
-}
-
-int imexhdg_get_nodes(const imexhdg_ctx *c, double *x, double *y) {
-    if (!c || !x || !y) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    const int K = c->geom.K, nx = c->cfg.nx, ny = c->cfg.ny;
-    const double hx = c->cfg.Lx / nx, hy = c->cfg.Ly / ny;
-    size_t o = 0;
-    for (int ey = 0; ey < ny; ++ey)
-        for (int ex = 0; ex < nx; ++ex)
-            for (int j = 0; j < K; ++j)
-                for (int i = 0; i < K; ++i, ++o) {
-                    x[o] = (ex + (c->ref.x[i] + 1.0) / 2.0) * hx;
-                    y[o] = (ey + (c->ref.x[j] + 1.0) / 2.0) * hy;
-                }
-    return IMEXHDG_OK;
-}
-
-int imexhdg_set_state(imexhdg_ctx *c, int vars, const double *a, const double *b,
-                      const double *cc) {
-    if (!c || !a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
-        return fail(IMEXHDG_E_INVAL, "unknown vars");
-    const int K = c->geom.K, nel = c->geom.nel;
-    const double g = c->cfg.g, H = c->cfg.H, phiB = g * H;
-    std::vector<double> h(c->N);
-    const size_t NN = c->nnodes;
-    for (int e = 0; e < nel; ++e)
-        for (int n = 0; n < K * K; ++n) {
-            const size_t src = (size_t)e * K * K + n, dst = (size_t)n * nel + e;
-            double p, U, V;
-            if (vars == IMEXHDG_VARS_DEPTH) {
-                p = g * (a[src] - H);
-                U = g * b[src];
-                V = g * cc[src];
-            } else {
-                p = a[src];
-                U = b[src];
-                V = cc[src];
-            }
-            const double phi = p + phiB;
-            if (!std::isfinite(p) || !std::isfinite(U) || !std::isfinite(V))
-                return fail(IMEXHDG_E_INVAL, "state holds NaN or Inf");
-            if (!(phi > 0)) return fail(IMEXHDG_E_INVAL, "total depth must be positive");
-            if (U * U + V * V >= phi * phi * phi)
-                return fail(IMEXHDG_E_INVAL, "supercritical state: |u| >= sqrt(phi)");
-            h[dst] = p;
-            h[NN + dst] = U;
-            h[2 * NN + dst] = V;
-        }
-    HIP_TRY(hipMemcpyAsync(c->q, h.data(), c->N * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
-    HIP_TRY(stream_sync(c));
-    c->have_state = true;
-    c->cold = true;
-    c->steps = 0;
-    return IMEXHDG_OK;
-}
-
-int imexhdg_get_state(imexhdg_ctx *c, int vars, double *a, double *b, double *cc) {
-    if (!c || !a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
-        return fail(IMEXHDG_E_INVAL, "unknown vars");
-    if (!c->have_state) return fail(IMEXHDG_E_STATE, "no state set");
-    std::vector<double> h(c->N);
-    HIP_TRY(hipMemcpyAsync(h.data(), c->q, c->N * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(stream_sync(c));
-    const int K = c->geom.K, nel = c->geom.nel;
-    const double g = c->cfg.g, H = c->cfg.H;
-    const size_t NN = c->nnodes;
-    for (int e = 0; e < nel; ++e)
-        for (int n = 0; n < K * K; ++n) {
-            const size_t dst = (size_t)e * K * K + n, src = (size_t)n * nel + e;
-            const double p = h[src], U = h[NN + src], V = h[2 * NN + src];
-            if (vars == IMEXHDG_VARS_DEPTH) {
-                a[dst] = H + p / g;
-                b[dst] = U / g;
-                cc[dst] = V / g;
-            } else {
-                a[dst] = p;
-                b[dst] = U;
-                cc[dst] = V;
-            }
-        }
-    return IMEXHDG_OK;
-}
-
-int imexhdg_step(imexhdg_ctx *c, int32_t nsteps) {
-    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+int step_ctx(imexhdg_ctx *c, int nsteps) {
     if (nsteps < 0) return fail(IMEXHDG_E_INVAL, "nsteps must be >= 0");
     if (!c->have_state) return fail(IMEXHDG_E_STATE, "step before set_state");
     int status = IMEXHDG_OK;
-    if (c->cfg.launch == IMEXHDG_LAUNCH_GRAPH && c->prof_target == -2) {
+    if (c->cfg.launch == IMEXHDG_LAUNCH_GRAPH && (c->prof_target == -2 || c->nm > 1)) {
         int rc = step_graph(c, nsteps, &status);
         if (rc) return rc;
     } else {
@@ -1108,12 +1311,55 @@ int imexhdg_step(imexhdg_ctx *c, int32_t nsteps) {
     return IMEXHDG_OK;
 }
 
-int imexhdg_get_diag(imexhdg_ctx *c, imexhdg_diag *d) {
-    if (!c || !d) return fail(IMEXHDG_E_INVAL, "NULL argument");
+int set_member_state(imexhdg_ctx *c, int m, int vars, const double *a, const double *b,
+                     const double *cc) {
+    if (!a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (m < 0 || m >= c->nm) return fail(IMEXHDG_E_INVAL, "member index out of range");
+    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
+        return fail(IMEXHDG_E_INVAL, "unknown vars");
+    const MemberHost &mh = c->mh[m];
+    std::vector<double> h;
+    int rc = state_to_device(c, mh, vars, a, b, cc, h);
+    if (rc) return rc;
+    // the member's slice of each of the three variables
+    const size_t NN = mh.N / 3;
+    for (int v = 0; v < 3; ++v)
+        HIP_TRY(hipMemcpyAsync(c->q + mh.vo + v * NN, h.data() + v * NN, NN * 8,
+                               hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->x + mh.to, 0, mh.T * 8, c->stream));
+    HIP_TRY(stream_sync(c));
+    c->member_set[m] = true;
+    c->have_state = std::all_of(c->member_set.begin(), c->member_set.end(),
+                                [](bool v) { return v; });
+    c->cold = true;
+    c->steps = 0;
+    return IMEXHDG_OK;
+}
+
+int get_member_state(imexhdg_ctx *c, int m, int vars, double *a, double *b, double *cc) {
+    if (!a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (m < 0 || m >= c->nm) return fail(IMEXHDG_E_INVAL, "member index out of range");
+    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
+        return fail(IMEXHDG_E_INVAL, "unknown vars");
     if (!c->have_state) return fail(IMEXHDG_E_STATE, "no state set");
-    LAUNCH(IMEXHDG_K_DIAG, launch_diag(c->geom, c->q, c->dpart, kPartStride, c->stream));
+    const MemberHost &mh = c->mh[m];
+    std::vector<double> h(mh.N);
+    const size_t NN = mh.N / 3;
+    for (int v = 0; v < 3; ++v)
+        HIP_TRY(hipMemcpyAsync(h.data() + v * NN, c->q + mh.vo + v * NN, NN * 8,
+                               hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(stream_sync(c));
+    state_from_device(c, mh, vars, h, a, b, cc);
+    return IMEXHDG_OK;
+}
+
+int member_diag(imexhdg_ctx *c, int m, imexhdg_diag *d) {
+    if (!d) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (m < 0 || m >= c->nm) return fail(IMEXHDG_E_INVAL, "member index out of range");
+    if (!c->have_state) return fail(IMEXHDG_E_STATE, "no state set");
+    LAUNCH(IMEXHDG_K_DIAG, launch_diag(c->geom, c->bt, c->q, c->dpart, c->pstride, c->stream));
     double t[5];
-    int rc = read_partials(c, 5, diag_grid(c->geom), t);
+    int rc = read_partials(c, 5, c->mtab[m].bd, c->mtab[m].nbd, t);
     if (rc) return rc;
     std::memset(d, 0, sizeof(*d));
     for (int i = 0; i < 3; ++i) d->mass[i] = t[i];
@@ -1130,6 +1376,86 @@ int imexhdg_get_diag(imexhdg_ctx *c, imexhdg_diag *d) {
     return IMEXHDG_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int imexhdg_config_init(imexhdg_config *c) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "config is NULL");
+    std::memset(c, 0, sizeof(*c));
+    c->nx = c->ny = 1;
+    c->Lx = c->Ly = 1.0;
+    c->degree = 2;
+    c->g = c->H = 1.0;
+    c->dt = 1e-3;
+    c->scheme = IMEXHDG_SCHEME_ARS232;
+    c->physics = IMEXHDG_PHYSICS_NONLINEAR;
+    c->precision = IMEXHDG_PREC_FP64;
+    c->krylov_rtol = 1e-14;
+    c->krylov_max_iter = 500;
+    c->check_every = 8;
+    c->refine_rtol = 1e-13;
+    c->refine_max = 4;
+    c->launch = IMEXHDG_LAUNCH_GRAPH;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_validate(const imexhdg_config *cfg) { return validate(cfg); }
+
+int imexhdg_workspace_bytes(const imexhdg_config *cfg, size_t *bytes) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!bytes) return fail(IMEXHDG_E_INVAL, "bytes is NULL");
+    *bytes = layout_of(std::vector<imexhdg_config>(1, *cfg)).total;
+    return IMEXHDG_OK;
+}
+
+const char *imexhdg_last_error(void) { return g_last_error.c_str(); }
+
+int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace, size_t ws_bytes,
+                   imexhdg_ctx **out) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!out) return fail(IMEXHDG_E_INVAL, "out is NULL");
+    return create_ctx(cfg, 1, stream, workspace, ws_bytes, out);
+}
+
+void imexhdg_destroy(imexhdg_ctx *c) { destroy_ctx(c); }
+
+int imexhdg_sizes(const imexhdg_ctx *c, int64_t *n_nodes, int64_t *n_trace) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (n_nodes) *n_nodes = (int64_t)c->nnodes;
+    if (n_trace) *n_trace = (int64_t)c->T;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_get_nodes(const imexhdg_ctx *c, double *x, double *y) {
+    if (!c || !x || !y) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    get_nodes_of(c, c->mh[0], x, y);
+    return IMEXHDG_OK;
+}
+
+int imexhdg_set_state(imexhdg_ctx *c, int vars, const double *a, const double *b,
+                      const double *cc) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    return set_member_state(c, 0, vars, a, b, cc);
+}
+
+int imexhdg_get_state(imexhdg_ctx *c, int vars, double *a, double *b, double *cc) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    return get_member_state(c, 0, vars, a, b, cc);
+}
+
+int imexhdg_step(imexhdg_ctx *c, int32_t nsteps) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    return step_ctx(c, nsteps);
+}
+
+int imexhdg_get_diag(imexhdg_ctx *c, imexhdg_diag *d) {
+    if (!c || !d) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    return member_diag(c, 0, d);
+}
+
 int imexhdg_state_device(imexhdg_ctx *c, double **d_q) {
     if (!c || !d_q) return fail(IMEXHDG_E_INVAL, "NULL argument");
     *d_q = c->q;
@@ -1143,14 +1469,15 @@ int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
     cb.self = 1.0;
     cb.out = d_out;
     cb.store = nullptr;
-    LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, d_q, cb, c->stream));
+    LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, d_q, cb, false, c->stream));
     return IMEXHDG_OK;
 }
 
 int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_qhat,
                             double *d_out) {
     if (!c || !d_Q || !d_qhat || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    LAUNCH(IMEXHDG_K_LINRES, launch_linear_residual(c->geom, d_Q, d_qhat, d_out, c->stream));
+    LAUNCH(IMEXHDG_K_LINRES,
+           launch_linear_residual(c->geom, c->bt, d_Q, d_qhat, d_out, c->stream));
     return IMEXHDG_OK;
 }
 
@@ -1215,7 +1542,7 @@ int imexhdg_set_schedule(imexhdg_ctx *c, int32_t sweeps, const int32_t *budget) 
     if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
     if (c->cfg.launch != IMEXHDG_LAUNCH_GRAPH)
         return fail(IMEXHDG_E_STATE, "the context does not step on a fixed schedule");
-    if (sweeps < 0 || sweeps > std::min((int)c->cfg.refine_max, kMaxSweeps))
+    if (sweeps < 0 || sweeps > max_sweeps(c))
         return fail(IMEXHDG_E_INVAL, "sweeps must be in [0, min(refine_max, 8)]");
     if (sweeps > 0 && !budget) return fail(IMEXHDG_E_INVAL, "budget is NULL");
     for (int i = 0; i < sweeps; ++i)
@@ -1229,11 +1556,14 @@ int imexhdg_set_schedule(imexhdg_ctx *c, int32_t sweeps, const int32_t *budget) 
 
 int imexhdg_set_launch_geometry(imexhdg_ctx *c, int32_t face_grid, int32_t elem_grid) {
     if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
-    if (face_grid < 8 || face_grid > kMaxLaunchGrid || elem_grid < 8 || elem_grid > kMaxLaunchGrid)
+    if (face_grid < 8 || face_grid > kMaxLaunchGrid || elem_grid < 8 ||
+        elem_grid > kMaxLaunchGrid)
         return fail(IMEXHDG_E_INVAL, "grid caps must be in [8, 4096]");
     HIP_TRY(stream_sync(c));
-    c->geom.fgrid = face_grid;
-    c->geom.egrid = elem_grid;
+    c->fgrid = face_grid;
+    c->egrid = elem_grid;
+    int rc = build_batch(c);
+    if (rc) return rc;
     if (c->gready) return capture(c);
     return IMEXHDG_OK;
 }
@@ -1241,11 +1571,13 @@ int imexhdg_set_launch_geometry(imexhdg_ctx *c, int32_t face_grid, int32_t elem_
 // Two host-driven steps from the saved state with every kernel class
 // timed; per-class mean launch time (ms) and launch count.
 static int tune_trial(imexhdg_ctx *c, int fg, int eg, double *avg, int64_t *cnt) {
-    c->geom.fgrid = fg;
-    c->geom.egrid = eg;
+    c->fgrid = fg;
+    c->egrid = eg;
+    int rc = build_batch(c);
+    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
-    int rc = imexhdg_profile(c, -1);
+    rc = imexhdg_profile(c, -1);
     if (rc) return rc;
     int status = IMEXHDG_OK;
     for (int i = 0; i < 2; ++i) {
@@ -1300,8 +1632,13 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         const int face_k[3] = {IMEXHDG_K_TRACE_RESID, IMEXHDG_K_BICG_K1, IMEXHDG_K_BICG_K2};
         const int elem_k[2] = {IMEXHDG_K_BICG_INIT, IMEXHDG_K_BICG_K3};
         const int cand[5] = {256, 512, 1024, 2048, 4096};
-        const int f0 = c->geom.fgrid, e0 = c->geom.egrid;
+        const int f0 = c->fgrid, e0 = c->egrid;
+        const MemberHost &mh = c->mh[0];
+        const int K = c->geom.K;
+        // a discarded warm-up trial, then the incumbent; a candidate must beat
+        // the incumbent by 2% to replace it (two steps per trial are noisy)
         int rc = tune_trial(c, f0, e0, base_avg, w);
+        if (!rc) rc = tune_trial(c, f0, e0, base_avg, w);
         auto score = [&](const double *a, const int *ks_, int nk) {
             double s = 0.0;
             for (int i = 0; i < nk; ++i) s += a[ks_[i]] * (double)w[ks_[i]];
@@ -1310,28 +1647,24 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         best_f = f0;
         best_e = e0;
         double best = rc ? 0.0 : score(base_avg, face_k, 3);
-        Geom probe = c->geom;
         for (int i = 0; i < 5 && !rc; ++i) {
-            probe.fgrid = cand[i];
-            Geom cur = c->geom;
-            cur.fgrid = best_f;
-            if (imexhdg::face_grid(probe) == imexhdg::face_grid(cur)) continue;
+            if (member_face_blocks(mh.nx, mh.ny, cand[i]) ==
+                member_face_blocks(mh.nx, mh.ny, best_f))
+                continue;
             if ((rc = tune_trial(c, cand[i], e0, avg, cnt))) break;
             const double sc = score(avg, face_k, 3);
-            if (sc < best) {
+            if (sc < 0.98 * best) {
                 best = sc;
                 best_f = cand[i];
             }
         }
         if (!rc) best = score(base_avg, elem_k, 2);
         for (int i = 0; i < 5 && !rc; ++i) {
-            probe.egrid = cand[i];
-            Geom cur = c->geom;
-            cur.egrid = best_e;
-            if (imexhdg::elem_grid(probe) == imexhdg::elem_grid(cur)) continue;
+            if (member_elem_blocks(mh.nel, K, cand[i]) == member_elem_blocks(mh.nel, K, best_e))
+                continue;
             if ((rc = tune_trial(c, best_f, cand[i], avg, cnt))) break;
             const double sc = score(avg, elem_k, 2);
-            if (sc < best) {
+            if (sc < 0.98 * best) {
                 best = sc;
                 best_e = cand[i];
             }
@@ -1354,8 +1687,9 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         c->max_relres = keep_r[1];
         c->cold = true;
         if (rc) {
-            c->geom.fgrid = f0;
-            c->geom.egrid = e0;
+            c->fgrid = f0;
+            c->egrid = e0;
+            (void)build_batch(c);
             return rc;
         }
         if (cache_path) {
@@ -1366,6 +1700,91 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
     if (face_grid) *face_grid = best_f;
     if (elem_grid) *elem_grid = best_e;
     return imexhdg_set_launch_geometry(c, best_f, best_e);
+}
+
+// ------------------------------------------------------------- ensembles
+int imexhdg_ens_workspace_bytes(const imexhdg_config *cfgs, int32_t n, size_t *bytes) {
+    int rc = validate_batch(cfgs, n);
+    if (rc) return rc;
+    if (!bytes) return fail(IMEXHDG_E_INVAL, "bytes is NULL");
+    *bytes = layout_of(std::vector<imexhdg_config>(cfgs, cfgs + n)).total;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_ens_create(const imexhdg_config *cfgs, int32_t n, void *stream, void *workspace,
+                       size_t ws_bytes, imexhdg_ens **out) {
+    int rc = validate_batch(cfgs, n);
+    if (rc) return rc;
+    if (!out) return fail(IMEXHDG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    imexhdg_ens *e = new (std::nothrow) imexhdg_ens();
+    if (!e) return fail(IMEXHDG_E_NOMEM, "host allocation failed");
+    rc = create_ctx(cfgs, n, stream, workspace, ws_bytes, &e->c);
+    if (rc) {
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return IMEXHDG_OK;
+}
+
+void imexhdg_ens_destroy(imexhdg_ens *e) {
+    if (!e) return;
+    destroy_ctx(e->c);
+    delete e;
+}
+
+int imexhdg_ens_members(const imexhdg_ens *e, int32_t *n) {
+    if (!e || !n) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    *n = e->c->nm;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_ens_sizes(const imexhdg_ens *e, int32_t m, int64_t *n_nodes, int64_t *n_trace) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    if (m < 0 || m >= e->c->nm) return fail(IMEXHDG_E_INVAL, "member index out of range");
+    if (n_nodes) *n_nodes = (int64_t)e->c->mh[m].N / 3;
+    if (n_trace) *n_trace = (int64_t)e->c->mh[m].T;
+    return IMEXHDG_OK;
+}
+
+int imexhdg_ens_get_nodes(const imexhdg_ens *e, int32_t m, double *x, double *y) {
+    if (!e || !x || !y) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (m < 0 || m >= e->c->nm) return fail(IMEXHDG_E_INVAL, "member index out of range");
+    get_nodes_of(e->c, e->c->mh[m], x, y);
+    return IMEXHDG_OK;
+}
+
+int imexhdg_ens_set_state(imexhdg_ens *e, int32_t m, int vars, const double *a,
+                          const double *b, const double *c) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return set_member_state(e->c, m, vars, a, b, c);
+}
+
+int imexhdg_ens_get_state(imexhdg_ens *e, int32_t m, int vars, double *a, double *b,
+                          double *c) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return get_member_state(e->c, m, vars, a, b, c);
+}
+
+int imexhdg_ens_step(imexhdg_ens *e, int32_t nsteps) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return step_ctx(e->c, nsteps);
+}
+
+int imexhdg_ens_get_diag(imexhdg_ens *e, int32_t m, imexhdg_diag *d) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return member_diag(e->c, m, d);
+}
+
+int imexhdg_ens_get_schedule(const imexhdg_ens *e, int32_t *sweeps, int32_t *budget) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return imexhdg_get_schedule(e->c, sweeps, budget);
+}
+
+int imexhdg_ens_set_launch_geometry(imexhdg_ens *e, int32_t face_grid, int32_t elem_grid) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return imexhdg_set_launch_geometry(e->c, face_grid, elem_grid);
 }
 
 }  // extern "C"

@@ -7,7 +7,8 @@
 //                               d = 1 y-face e (south face of element e)
 // Workgroups are 64 lanes (elements or faces) x K "rows"; the row index is
 // wave-uniform, so every reference-element matrix entry a wave needs is the
-// same for all its lanes and is read through the scalar unit.
+// same for all its lanes and is read through the scalar unit.  Each member
+// of a batch has this layout within its slice of the concatenated arrays.
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -48,12 +49,51 @@ __device__ __forceinline__ Nbr neighbours(int e, int nx, int ny) {
     return n;
 }
 
+// Members are read through the constant address space: a block-uniform
+// member index compiles to scalar loads.
+typedef const __attribute__((address_space(4))) Member cmember;
+
+enum { CV = 0, CF = 1, CE = 2, CD = 3 };   // volume, face, elementwise, diagnostics
+
+template <int C> __device__ __forceinline__ int first_block(const cmember &m) {
+    return C == CV ? m.bv : C == CF ? m.bf : C == CE ? m.be : m.bd;
+}
+
+// Member holding block b of launch class C (binary search over the first
+// blocks), and b's index within the member.
+template <int C>
+__device__ __forceinline__ int member_of(const Batch &bt, int b, int &local) {
+    const cmember *m = (const cmember *)bt.m;
+    int lo = 0, hi = bt.nm - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first_block<C>(m[mid]) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    local = b - first_block<C>(m[lo]);
+    return lo;
+}
+
+__device__ __forceinline__ Member load_member(const Batch &bt, int i) {
+    const cmember &c = ((const cmember *)bt.m)[i];
+    Member r;
+    r.nx = c.nx; r.ny = c.ny; r.nel = c.nel; r.tiled = c.tiled;
+    r.sx = c.sx; r.sy = c.sy; r.area = c.area; r.dt = c.dt;
+    r.vo = c.vo; r.to = c.to;
+    r.bv = c.bv; r.nbv = c.nbv; r.bf = c.bf; r.nbf = c.nbf;
+    r.be = c.be; r.nbe = c.nbe; r.bd = c.bd; r.nbd = c.nbd;
+    r.Ainv = c.Ainv; r.W = c.W; r.G = c.G; r.Gh = c.Gh; r.Px = c.Px; r.Py = c.Py;
+    r.Ghf = c.Ghf;
+    return r;
+}
+
 // Deterministic reductions without fences or atomics.  A producer kernel
 // stores one partial sum per block with a plain store; the partials become
 // visible to the next kernel on the stream at the launch boundary, where
 // every block of the consumer reduces them again in the same fixed order
-// (consumer grids are capped, so this costs a few KB of L2 reads per block).
-constexpr int kMaxGrid = 1024;
+// (per-member grids are capped, so this costs a few KB of L2 reads per
+// block).  Partials are indexed by the global block; a member reduces its
+// own block range.
 
 // Block sum of NV values per thread; the result is returned to every thread.
 template <int NV>
@@ -148,14 +188,18 @@ __device__ __forceinline__ void rusanov_nl(const double qm[3], const double qp[3
 // face nodes.  The epilogue applies the stage combination `comb`.
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, const Geom g,
-                                               const Comb comb) {
+                                               const Batch bt, const Comb comb,
+                                               int scale_dt) {
     __shared__ double sFy[2][K][K][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
-    const int e = blockIdx.x * 64 + lane;
-    const bool active = e < g.nel;
-    const Nbr nb = neighbours(active ? e : 0, g.nx, g.ny);
-    const size_t nel = g.nel, NN = (size_t)K * K * nel;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    q += mb.vo;
+    const int e = lb * 64 + lane;
+    const bool active = e < mb.nel;
+    const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel;
     const double phiB = g.phiB;
 
     double p[K], U[K], V[K];
@@ -187,8 +231,8 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
             s2 += g.Dw[m * K + a] * fx2[m];
         }
         o0[a] = 0.0;
-        o1[a] = g.sx * s1;
-        o2[a] = g.sx * s2;
+        o1[a] = mb.sx * s1;
+        o2[a] = mb.sx * s2;
     }
     // east and west faces of row j
     {
@@ -197,13 +241,13 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         qm[0] = p[K - 1]; qm[1] = U[K - 1]; qm[2] = V[K - 1];
         qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
         rusanov_nl(qm, qp, 1.0, 0.0, phiB, g.tau, f);
-        const double se = g.sx * g.winvk;
+        const double se = mb.sx * g.winvk;
         o0[K - 1] -= se * f[0]; o1[K - 1] -= se * f[1]; o2[K - 1] -= se * f[2];
         o = (size_t)(j * K + K - 1) * nel + nb.west;
         qm[0] = p[0]; qm[1] = U[0]; qm[2] = V[0];
         qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
         rusanov_nl(qm, qp, -1.0, 0.0, phiB, g.tau, f);
-        const double sw = g.sx * g.winv0;
+        const double sw = mb.sx * g.winv0;
         o0[0] -= sw * f[0]; o1[0] -= sw * f[1]; o2[0] -= sw * f[2];
     }
     __syncthreads();
@@ -215,15 +259,15 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
             s1 += g.Dw[m * K + j] * sFy[0][m][i][lane];
             s2 += g.Dw[m * K + j] * sFy[1][m][i][lane];
         }
-        o1[i] += g.sy * s1;
-        o2[i] += g.sy * s2;
+        o1[i] += mb.sy * s1;
+        o2[i] += mb.sy * s2;
     }
     if (j == K - 1 || j == 0) {
         const bool north = (j == K - 1);
         const int other = north ? nb.north : nb.south;
         const int orow = north ? 0 : K - 1;
         const double ny = north ? 1.0 : -1.0;
-        const double sc = g.sy * (north ? g.winvk : g.winv0);
+        const double sc = mb.sy * (north ? g.winvk : g.winv0);
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             double qm[3] = {p[i], U[i], V[i]}, qp[3], f[3];
@@ -234,10 +278,12 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         }
     }
     if (!active) return;
+    // the step's combinations take dt NL (dt of the member)
+    const double sc = scale_dt ? mb.dt : 1.0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const size_t o = (size_t)(j * K + i) * nel + e;
-        const double val[3] = {o0[i], o1[i], o2[i]};
+        const size_t o = mb.vo + (size_t)(j * K + i) * nel + e;
+        const double val[3] = {sc * o0[i], sc * o1[i], sc * o2[i]};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const size_t oc = c * NN + o;
@@ -263,14 +309,20 @@ __global__ void k_combine(const Comb comb, size_t n) {
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
                                                    const double *__restrict__ qh,
-                                                   const Geom g, double *__restrict__ out) {
+                                                   const Geom g, const Batch bt,
+                                                   double *__restrict__ out) {
     __shared__ double sV[2][K][K][64];     // V and phi_B p, for d/dy
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
-    const int e = blockIdx.x * 64 + lane;
-    const bool active = e < g.nel;
-    const Nbr nb = neighbours(active ? e : 0, g.nx, g.ny);
-    const size_t nel = g.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    Q += mb.vo;
+    qh += mb.to;
+    out += mb.vo;
+    const int e = lb * 64 + lane;
+    const bool active = e < mb.nel;
+    const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
     const double phiB = g.phiB, tau = g.tau;
     double p[K], U[K], V[K];
 #pragma unroll
@@ -289,8 +341,8 @@ __global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
             s0 += g.Dw[m * K + a] * U[m];
             s1 += g.Dw[m * K + a] * p[m];
         }
-        o0[a] = g.sx * s0;
-        o1[a] = g.sx * phiB * s1;
+        o0[a] = mb.sx * s0;
+        o1[a] = mb.sx * phiB * s1;
         o2[a] = 0.0;
     }
     // west face = x-face e, east face = x-face east(e); node j
@@ -300,13 +352,13 @@ __global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
         double f0 = U[K - 1] + tau * (p[K - 1] - qh[oe]);
         double f1 = phiB * p[K - 1] + tau * (U[K - 1] - qh[nel * K + oe]);
         double f2 = tau * (V[K - 1] - qh[2 * nel * K + oe]);
-        const double se = g.sx * g.winvk;
+        const double se = mb.sx * g.winvk;
         o0[K - 1] -= se * f0; o1[K - 1] -= se * f1; o2[K - 1] -= se * f2;
         // west: n = (-1, 0)
         f0 = -U[0] + tau * (p[0] - qh[ow]);
         f1 = -phiB * p[0] + tau * (U[0] - qh[nel * K + ow]);
         f2 = tau * (V[0] - qh[2 * nel * K + ow]);
-        const double sw = g.sx * g.winv0;
+        const double sw = mb.sx * g.winv0;
         o0[0] -= sw * f0; o1[0] -= sw * f1; o2[0] -= sw * f2;
     }
     __syncthreads();
@@ -318,14 +370,14 @@ __global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
             s0 += g.Dw[m * K + j] * sV[0][m][i][lane];
             s2 += g.Dw[m * K + j] * sV[1][m][i][lane];
         }
-        o0[i] += g.sy * s0;
-        o2[i] += g.sy * s2;
+        o0[i] += mb.sy * s0;
+        o2[i] += mb.sy * s2;
     }
     if (j == K - 1 || j == 0) {
         const bool north = (j == K - 1);
         const int face = north ? nb.north : nb.e;      // y-face index
         const double ny = north ? 1.0 : -1.0;
-        const double sc = g.sy * (north ? g.winvk : g.winv0);
+        const double sc = mb.sy * (north ? g.winvk : g.winv0);
         const double *qy = qh + TT;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -350,16 +402,21 @@ __global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
 // Z = A^-1 R per element: the shared (3K^2)-square inverse applied to every
 // element.  Thread (element, row j) produces the 3K outputs of node row j.
 template <int K>
-__global__ __launch_bounds__(64 * K) void k_local_apply(const double *__restrict__ Ainv,
-                                                        const double *__restrict__ R,
-                                                        const Geom g, double *__restrict__ Z) {
+__global__ __launch_bounds__(64 * K) void k_local_apply(const double *__restrict__ R,
+                                                        const Batch bt,
+                                                        double *__restrict__ Z) {
     constexpr int NL = 3 * K * K;
     __shared__ double sR[NL][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
-    const int e = blockIdx.x * 64 + lane;
-    const bool active = e < g.nel;
-    const size_t nel = g.nel, NN = (size_t)K * K * nel;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    R += mb.vo;
+    Z += mb.vo;
+    const double *Ainv = mb.Ainv;
+    const int e = lb * 64 + lane;
+    const bool active = e < mb.nel;
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -391,18 +448,23 @@ __global__ __launch_bounds__(64 * K) void k_local_apply(const double *__restrict
 
 // Q = Z - W Qhat_dK per element, W = A^-1 B (eq. recover_volume_unknowns).
 template <int K>
-__global__ __launch_bounds__(64 * K) void k_recover(const double *__restrict__ W,
-                                                    const double *__restrict__ Z,
+__global__ __launch_bounds__(64 * K) void k_recover(const double *__restrict__ Z,
                                                     const double *__restrict__ qh,
-                                                    const Geom g, double *__restrict__ Q) {
+                                                    const Batch bt, double *__restrict__ Q) {
     constexpr int NT = 12 * K;
     __shared__ double sT[NT][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
-    const int e = blockIdx.x * 64 + lane;
-    const bool active = e < g.nel;
-    const Nbr nb = neighbours(active ? e : 0, g.nx, g.ny);
-    const size_t nel = g.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    Z += mb.vo;
+    qh += mb.to;
+    Q += mb.vo;
+    const double *W = mb.W;
+    const int e = lb * 64 + lane;
+    const bool active = e < mb.nel;
+    const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
     // local trace t(f, c, j) = (f*3 + c)*K + j, faces W, E, S, N
     const int face[4] = {nb.e, nb.east, nb.e, nb.north};
 #pragma unroll
@@ -486,17 +548,23 @@ __device__ __forceinline__ void slot_faces(const FaceIdx &fi, int nx, int ny, in
 // face node; ghat = P^-1 g with the block-Jacobi inverse of the face.
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__ Z,
-                                                      const double *__restrict__ Pxinv,
-                                                      const double *__restrict__ Pyinv,
-                                                      const Geom g, double *__restrict__ gv,
+                                                      const Geom g, const Batch bt,
+                                                      double *__restrict__ gv,
                                                       double *__restrict__ gh) {
     constexpr int B3 = 3 * K;
     __shared__ double sG[B3][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
-    const FaceIdx fi = face_of_tile(blockIdx.x, g.nel);
-    const Nbr n = neighbours(fi.f, g.nx, g.ny);
-    const size_t nel = g.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
+    // the member's blocks are [2 bv, 2 (bv + nbv)): x-face tiles, then y
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x >> 1, lb));
+    Z += mb.vo;
+    gv += mb.to;
+    gh += mb.to;
+    const double *Pxinv = mb.Px, *Pyinv = mb.Py;
+    const FaceIdx fi = face_of_tile(blockIdx.x - 2 * mb.bv, mb.nel);
+    const Nbr n = neighbours(fi.f, mb.nx, mb.ny);
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
     const double phiB = g.phiB, tau = g.tau;
     // plus side: element f (face is its west / south), minus side: west /
     // south neighbour (face is its east / north)
@@ -594,10 +662,11 @@ struct TileWalk {
     int first, step, end;
 };
 
-__device__ __forceinline__ TileWalk tile_walk(int ntiles) {
-    const int G = gridDim.x;
-    if (G % 8 != 0 || G < 8) return TileWalk{(int)blockIdx.x, G, ntiles};
-    const int xcd = blockIdx.x % 8, local = blockIdx.x / 8, per = G / 8;
+// Block `lb` of the G blocks of one member (G a multiple of 8 and the
+// member's first block a multiple of 8 keep lb mod 8 = the block's XCD).
+__device__ __forceinline__ TileWalk tile_walk(int lb, int G, int ntiles) {
+    if (G % 8 != 0 || G < 8) return TileWalk{lb, G, ntiles};
+    const int xcd = lb % 8, local = lb / 8, per = G / 8;
     const int chunk = (ntiles + 7) / 8;
     const int begin = xcd * chunk;
     const int end = min(ntiles, begin + chunk);
@@ -624,7 +693,7 @@ struct WaveFaces {
 };
 
 template <bool TILED>
-__device__ __forceinline__ WaveFaces wave_faces(int tile, const Geom &g) {
+__device__ __forceinline__ WaveFaces wave_faces(int tile, const Member &g) {
     WaveFaces wf;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -748,7 +817,7 @@ __device__ __forceinline__ int slot_lds(int set, int s, int lx, int ly, int NX, 
 // loads of a chunk of up to 8 values per thread are issued before any is
 // used.
 template <int K, typename T, int NA, typename Comb>
-__device__ __forceinline__ void stage_tile(int tile, const Geom &g, T *sB,
+__device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
                                            const T *__restrict__ const (&src)[NA], Comb comb) {
     using TL = Tile<K>;
     constexpr int NV = TL::B3 * TL::NF, PER = (NV + kFaceThreads - 1) / kFaceThreads;
@@ -831,7 +900,7 @@ __device__ __forceinline__ int own_lds(const WaveFaces &wf) {
 // operands of slot s + 1 are loaded while slot s is computed.  Slot 0 is
 // the face itself, whose combined value comb may store.
 template <int K, int NM, typename T, int NA, typename Comb>
-__device__ __forceinline__ void gather_rows(const T *__restrict__ const *frags, const Geom &g,
+__device__ __forceinline__ void gather_rows(const T *__restrict__ const *frags, const Member &g,
                                             const WaveFaces &wf,
                                             const T *__restrict__ const (&src)[NA], Comb comb,
                                             typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
@@ -903,7 +972,7 @@ __device__ __forceinline__ void gather_rows(const T *__restrict__ const *frags, 
 // Row blocks of this wave for one tile, staged (TILED) or gathered.
 template <int K, int NM, bool TILED, typename T, int NA, typename Comb>
 __device__ __forceinline__ void face_rows(const T *__restrict__ const *frags, int tile,
-                                          const Geom &g, const WaveFaces &wf, T *sB,
+                                          const Member &g, const WaveFaces &wf, T *sB,
                                           const T *__restrict__ const (&src)[NA], Comb comb,
                                           typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
     if constexpr (TILED) {
@@ -916,64 +985,83 @@ __device__ __forceinline__ void face_rows(const T *__restrict__ const *frags, in
     }
 }
 
-template <int K, bool TILED>
-__device__ __forceinline__ int face_tiles(const Geom &g) {
+template <bool TILED>
+__device__ __forceinline__ int face_tiles(const Member &g) {
     return TILED ? (g.nx / kTX) * (g.ny / kTY) : (g.nel + 63) / 64;
 }
 
 // LDS of a staged tile (unused without tiles).
-template <int K, bool TILED, typename T> struct TileLds {
-    static constexpr int n = TILED ? MF<K>::B3 * Tile<K>::NF : 1;
+template <int K, typename T> struct TileLds {
+    static constexpr int n = MF<K>::B3 * Tile<K>::NF;
 };
+
+template <bool B> struct Tiled {
+    static constexpr bool value = B;
+};
+
+// Run body(Tiled<...>{}) with the member's tiling as a compile-time value.
+template <typename Body>
+__device__ __forceinline__ void with_tiling(const Member &mb, Body body) {
+    if (mb.tiled) body(Tiled<true>{});
+    else body(Tiled<false>{});
+}
 
 // FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
 // partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
-template <int K, bool TILED, typename RT>
+template <int K, typename RT>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residual(
-    const FragMats A, const double *__restrict__ x, const double *__restrict__ gv,
-    const double *__restrict__ gh, const Geom g, double *__restrict__ r,
-    RT *__restrict__ rin, double *partials, int stride, const int32_t *skip) {
+    const Batch bt, const double *__restrict__ x, const double *__restrict__ gv,
+    const double *__restrict__ gh, double *__restrict__ r, RT *__restrict__ rin,
+    double *partials, int stride, const KrylovState *skip) {
     using T = double;
-    if (skip && *skip) return;
     constexpr int NMB = MF<K>::NMB;
-    __shared__ double sB[TileLds<K, TILED, T>::n];
-    const uint32_t nel = g.nel;
-    const double *fr[2] = {A.A0, A.A1};
+    int lb;
+    const int mi = member_of<CF>(bt, blockIdx.x, lb);
+    if (skip && skip[mi].stage_done) return;
+    const Member mb = load_member(bt, mi);
+    x += mb.to; gv += mb.to; gh += mb.to; r += mb.to; rin += mb.to;
+    __shared__ double sB[TileLds<K, T>::n];
+    const uint32_t nel = mb.nel;
+    const double *fr[2] = {mb.G, mb.Gh};
     const double *src[1] = {x};
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-    const TileWalk tw = tile_walk(face_tiles<K, TILED>(g));
-    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-        const WaveFaces wf = wave_faces<TILED>(tile, g);
-        // right-hand sides at the own rows, loaded ahead of the contraction
-        double gvv[NMB][4], ghv[NMB][4];
-        uint32_t o[NMB][4];
-        bool ok[NMB][4];
+    with_tiling(mb, [&](auto tl) {
+        constexpr bool TILED = decltype(tl)::value;
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles<TILED>(mb));
+        for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            const WaveFaces wf = wave_faces<TILED>(tile, mb);
+            // right-hand sides at the own rows, loaded ahead of the contraction
+            double gvv[NMB][4], ghv[NMB][4];
+            uint32_t o[NMB][4];
+            bool ok[NMB][4];
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
+            for (int m = 0; m < NMB; ++m)
 #pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                o[mb][e4] = own_off<K, T>(wf, mb, e4, nel, ok[mb][e4]);
-                gvv[mb][e4] = ok[mb][e4] ? gv[o[mb][e4]] : 0.0;
-                ghv[mb][e4] = ok[mb][e4] ? gh[o[mb][e4]] : 0.0;
-            }
-        v4d acc[2][NMB];
-        face_rows<K, 2, TILED>(fr, tile, g, wf, sB, src,
-                               [](const double (&a)[1], uint32_t, bool) { return a[0]; }, acc);
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4)
-                if (ok[mb][e4]) {
-                    const double rr = gvv[mb][e4] - acc[0][mb][e4];
-                    const double ri = ghv[mb][e4] - acc[1][mb][e4];
-                    r[o[mb][e4]] = rr;
-                    rin[o[mb][e4]] = (RT)ri;
-                    acc4[0] += rr * rr;
-                    acc4[1] += gvv[mb][e4] * gvv[mb][e4];
-                    acc4[2] += ghv[mb][e4] * ghv[mb][e4];
-                    acc4[3] += ri * ri;
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
+                    gvv[m][e4] = ok[m][e4] ? gv[o[m][e4]] : 0.0;
+                    ghv[m][e4] = ok[m][e4] ? gh[o[m][e4]] : 0.0;
                 }
-    }
+            v4d acc[2][NMB];
+            face_rows<K, 2, TILED>(fr, tile, mb, wf, sB, src,
+                                   [](const double (&a)[1], uint32_t, bool) { return a[0]; },
+                                   acc);
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4)
+                    if (ok[m][e4]) {
+                        const double rr = gvv[m][e4] - acc[0][m][e4];
+                        const double ri = ghv[m][e4] - acc[1][m][e4];
+                        r[o[m][e4]] = rr;
+                        rin[o[m][e4]] = (RT)ri;
+                        acc4[0] += rr * rr;
+                        acc4[1] += gvv[m][e4] * gvv[m][e4];
+                        acc4[2] += ghv[m][e4] * ghv[m][e4];
+                        acc4[3] += ri * ri;
+                    }
+        }
+    });
     store_partials<4>(acc4, partials, stride);
 }
 
@@ -990,21 +1078,49 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
 // p and v are double buffered because K1 reads the old values at
 // neighbouring faces while writing the new ones.  Convergence (r.r <= tol2)
 // is detected at the start of K1; every later kernel returns at entry.
+// Elementwise trace kernels: the member's nbe blocks run grid-stride loops
+// over its 6 K nel trace values, four values per thread and pass with all
+// loads issued before use.
+struct ElemRange {
+    size_t i0, span, n;
+};
+
+__device__ __forceinline__ ElemRange elem_range(const Member &mb, int lb, int K) {
+    const size_t bd = blockDim.x;
+    return ElemRange{(size_t)lb * bd * 4 + threadIdx.x, (size_t)mb.nbe * bd * 4,
+                     (size_t)6 * K * mb.nel};
+}
+
 template <typename T>
-__global__ void k_bicg_init(const T *__restrict__ rin, T *__restrict__ r,
-                            T *__restrict__ rh, T *__restrict__ p,
-                            T *__restrict__ v, T *__restrict__ d, size_t n,
-                            KrylovState *ks, double tol2, double *P3, int stride) {
+__global__ void k_bicg_init(const Batch bt, int K, const T *__restrict__ rin,
+                            T *__restrict__ r, T *__restrict__ rh, T *__restrict__ p,
+                            T *__restrict__ v, T *__restrict__ d, KrylovState *ks_all,
+                            double tol2, double *P3, int stride) {
+    int lb;
+    const int mi = member_of<CE>(bt, blockIdx.x, lb);
+    const Member mb = load_member(bt, mi);
+    rin += mb.to; r += mb.to; rh += mb.to; p += mb.to; v += mb.to; d += mb.to;
     double acc[2] = {0.0, 0.0};
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double x = rin[i];
-        r[i] = (T)x; rh[i] = (T)x; p[i] = T(0); v[i] = T(0); d[i] = T(0);
-        acc[0] += x * x;
-        acc[1] += x * x;
+    const ElemRange er = elem_range(mb, lb, K);
+    const size_t bd = blockDim.x;
+    for (size_t i0 = er.i0; i0 < er.n; i0 += er.span) {
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = (i0 + u * bd < er.n) ? rin[i0 + u * bd] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t i = i0 + u * bd;
+            if (i < er.n) {
+                r[i] = x[u]; rh[i] = x[u]; p[i] = T(0); v[i] = T(0); d[i] = T(0);
+                const double xd = x[u];
+                acc[0] += xd * xd;
+                acc[1] += xd * xd;
+            }
+        }
     }
     store_partials<2>(acc, P3, stride);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
+        KrylovState *ks = ks_all + mi;
         ks->rho = 1.0;
         ks->alpha = 1.0;
         ks->omega = 1.0;
@@ -1016,20 +1132,27 @@ __global__ void k_bicg_init(const T *__restrict__ rin, T *__restrict__ r,
     }
 }
 
-template <int K, bool TILED, typename T, bool SCHED>
+// Matrix-core fragments of Ghat in the inner solve's precision.
+__device__ __forceinline__ const double *ghat_frags(const Member &mb, double) { return mb.Gh; }
+__device__ __forceinline__ const float *ghat_frags(const Member &mb, float) { return mb.Ghf; }
+
+template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
-    const FragMatsT<T> A, const T *__restrict__ r, const T *__restrict__ rh,
+    const Batch bt, const T *__restrict__ r, const T *__restrict__ rh,
     const T *__restrict__ pin, const T *__restrict__ vin, T *__restrict__ pout,
-    T *__restrict__ vout, const Geom g, KrylovState *ks, const double *P3, int n3, double *P1,
-    int stride) {
+    T *__restrict__ vout, KrylovState *ks_all, const double *P3, double *P1, int stride) {
     constexpr int NMB = MF<K>::NMB;
+    int lb;
+    const int mi = member_of<CF>(bt, blockIdx.x, lb);
+    const Member mb = load_member(bt, mi);
+    KrylovState *ks = ks_all + mi;
     double red[2];
-    reduce_partials<2>(P3, stride, n3, red);
+    reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red);
     if (ks->conv) return;
     const double rho_new = red[0], rr = red[1];
     const double rho = ks->rho, alpha = ks->alpha, omega = ks->omega;
     if (rr <= ks->tol2 || rho_new == 0.0 || omega == 0.0 || !isfinite(rr)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lb == 0 && threadIdx.x == 0) {
             ks->rr = rr;
             ks->breakdown = (rr <= ks->tol2) ? 0 : 1;
             ks->conv = 1;
@@ -1037,59 +1160,67 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
         return;
     }
     const T beta = (T)((rho_new / rho) * (alpha / omega)), om = (T)omega;
-    __shared__ T sB[TileLds<K, TILED, T>::n];
-    const uint32_t nel = g.nel;
-    const T *fr[1] = {A.A0};
+    r += mb.to; rh += mb.to; pin += mb.to; vin += mb.to; pout += mb.to; vout += mb.to;
+    __shared__ T sB[TileLds<K, T>::n];
+    const uint32_t nel = mb.nel;
+    const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[3] = {r, pin, vin};
     double acc1[1] = {0.0};
-    const TileWalk tw = tile_walk(face_tiles<K, TILED>(g));
-    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-        const WaveFaces wf = wave_faces<TILED>(tile, g);
-        T rhv[NMB][4];
-        uint32_t o[NMB][4];
-        bool ok[NMB][4];
+    with_tiling(mb, [&](auto tl) {
+        constexpr bool TILED = decltype(tl)::value;
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles<TILED>(mb));
+        for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            const WaveFaces wf = wave_faces<TILED>(tile, mb);
+            T rhv[NMB][4];
+            uint32_t o[NMB][4];
+            bool ok[NMB][4];
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
+            for (int m = 0; m < NMB; ++m)
 #pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                o[mb][e4] = own_off<K, T>(wf, mb, e4, nel, ok[mb][e4]);
-                rhv[mb][e4] = ok[mb][e4] ? rh[o[mb][e4]] : T(0);
-            }
-        typename MfmaT<T>::v4 acc[1][NMB];
-        face_rows<K, 1, TILED>(fr, tile, g, wf, sB, src,
-                               [&](const T (&a)[3], uint32_t off, bool own) {
-                                   const T p = a[0] + beta * (a[1] - om * a[2]);
-                                   if (own) pout[off] = p;
-                                   return p;
-                               },
-                               acc);
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4)
-                if (ok[mb][e4]) {
-                    const double y = acc[0][mb][e4];
-                    vout[o[mb][e4]] = (T)y;
-                    acc1[0] += (double)rhv[mb][e4] * y;
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
+                    rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
                 }
-    }
+            typename MfmaT<T>::v4 acc[1][NMB];
+            face_rows<K, 1, TILED>(fr, tile, mb, wf, sB, src,
+                                   [&](const T (&a)[3], uint32_t off, bool own) {
+                                       const T p = a[0] + beta * (a[1] - om * a[2]);
+                                       if (own) pout[off] = p;
+                                       return p;
+                                   },
+                                   acc);
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4)
+                    if (ok[m][e4]) {
+                        const double y = acc[0][m][e4];
+                        vout[o[m][e4]] = (T)y;
+                        acc1[0] += (double)rhv[m][e4] * y;
+                    }
+        }
+    });
     store_partials<1>(acc1, P1, stride);
-    if (blockIdx.x == 0 && threadIdx.x == 0) ks->rr = rr;
+    if (lb == 0 && threadIdx.x == 0) ks->rr = rr;
 }
 
-template <int K, bool TILED, typename T, bool SCHED>
+template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
-    const FragMatsT<T> A, const T *__restrict__ r, const T *__restrict__ v,
-    T *__restrict__ sv, T *__restrict__ t, const Geom g, KrylovState *ks, const double *P1,
-    int n1, const double *P3, int n3, double *P2, int stride) {
+    const Batch bt, const T *__restrict__ r, const T *__restrict__ v, T *__restrict__ sv,
+    T *__restrict__ t, KrylovState *ks_all, const double *P1, const double *P3, double *P2,
+    int stride) {
     constexpr int NMB = MF<K>::NMB;
+    int lb;
+    const int mi = member_of<CF>(bt, blockIdx.x, lb);
+    const Member mb = load_member(bt, mi);
+    KrylovState *ks = ks_all + mi;
     double red1[1], red3[2];
-    reduce_partials<1>(P1, stride, n1, red1);
-    reduce_partials<2>(P3, stride, n3, red3);
+    reduce_partials<1>(P1 + mb.bf, stride, mb.nbf, red1);
+    reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red3);
     if (ks->conv) return;
     const double rv = red1[0], rho_new = red3[0];
     if (rv == 0.0 || !isfinite(rv)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lb == 0 && threadIdx.x == 0) {
             ks->breakdown = 1;
             ks->conv = 1;
         }
@@ -1097,82 +1228,91 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     }
     const double alpha = rho_new / rv;
     const T al = (T)alpha;
-    __shared__ T sB[TileLds<K, TILED, T>::n];
-    const uint32_t nel = g.nel;
-    const T *fr[1] = {A.A0};
+    r += mb.to; v += mb.to; sv += mb.to; t += mb.to;
+    __shared__ T sB[TileLds<K, T>::n];
+    const uint32_t nel = mb.nel;
+    const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[2] = {r, v};
     double acc2[2] = {0.0, 0.0};
-    const TileWalk tw = tile_walk(face_tiles<K, TILED>(g));
-    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-        const WaveFaces wf = wave_faces<TILED>(tile, g);
-        uint32_t o[NMB][4];
-        bool ok[NMB][4];
-        T sown[NMB][4];
+    with_tiling(mb, [&](auto tl) {
+        constexpr bool TILED = decltype(tl)::value;
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles<TILED>(mb));
+        for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            const WaveFaces wf = wave_faces<TILED>(tile, mb);
+            uint32_t o[NMB][4];
+            bool ok[NMB][4];
+            T sown[NMB][4];
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                o[mb][e4] = own_off<K, T>(wf, mb, e4, nel, ok[mb][e4]);
-                if constexpr (!TILED)
-                    sown[mb][e4] = ok[mb][e4] ? r[o[mb][e4]] - al * v[o[mb][e4]] : T(0);
-            }
-        typename MfmaT<T>::v4 acc[1][NMB];
-        face_rows<K, 1, TILED>(fr, tile, g, wf, sB, src,
-                               [&](const T (&a)[2], uint32_t off, bool own) {
-                                   const T s = a[0] - al * a[1];
-                                   if (own) sv[off] = s;
-                                   return s;
-                               },
-                               acc);
-        if constexpr (TILED) {
-            const int li = own_lds<K>(wf);
-#pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
+            for (int m = 0; m < NMB; ++m)
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4) {
-                    const int row = 16 * mb + MfmaT<T>::row(threadIdx.x & 63, e4);
-                    if (ok[mb][e4]) sown[mb][e4] = sB[row * Tile<K>::NF + li];
+                    o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
+                    if constexpr (!TILED)
+                        sown[m][e4] = ok[m][e4] ? r[o[m][e4]] - al * v[o[m][e4]] : T(0);
                 }
+            typename MfmaT<T>::v4 acc[1][NMB];
+            face_rows<K, 1, TILED>(fr, tile, mb, wf, sB, src,
+                                   [&](const T (&a)[2], uint32_t off, bool own) {
+                                       const T sval = a[0] - al * a[1];
+                                       if (own) sv[off] = sval;
+                                       return sval;
+                                   },
+                                   acc);
+            if constexpr (TILED) {
+                const int li = own_lds<K>(wf);
+#pragma unroll
+                for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        const int row = 16 * m + MfmaT<T>::row(threadIdx.x & 63, e4);
+                        if (ok[m][e4]) sown[m][e4] = sB[row * Tile<K>::NF + li];
+                    }
+            }
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4)
+                    if (ok[m][e4]) {
+                        const double y = acc[0][m][e4];
+                        const double sval = sown[m][e4];
+                        t[o[m][e4]] = (T)y;
+                        acc2[0] += y * sval;
+                        acc2[1] += y * y;
+                    }
         }
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4)
-                if (ok[mb][e4]) {
-                    const double y = acc[0][mb][e4];
-                    const double sval = sown[mb][e4];
-                    t[o[mb][e4]] = (T)y;
-                    acc2[0] += y * sval;
-                    acc2[1] += y * y;
-                }
-    }
+    });
     store_partials<2>(acc2, P2, stride);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         ks->rho = rho_new;
         ks->alpha = alpha;
     }
 }
 
 template <typename T>
-__global__ void k_bicg_k3(T *__restrict__ d, T *__restrict__ r,
+__global__ void k_bicg_k3(const Batch bt, int K, T *__restrict__ d, T *__restrict__ r,
                           const T *__restrict__ rh, const T *__restrict__ p,
-                          const T *__restrict__ sv, const T *__restrict__ t, size_t n,
-                          KrylovState *ks, const double *P2, int n2, double *P3, int stride) {
+                          const T *__restrict__ sv, const T *__restrict__ t,
+                          KrylovState *ks_all, const double *P2, double *P3, int stride) {
+    int lb;
+    const int mi = member_of<CE>(bt, blockIdx.x, lb);
+    const Member mb = load_member(bt, mi);
+    KrylovState *ks = ks_all + mi;
     double red[2];
-    reduce_partials<2>(P2, stride, n2, red);
+    reduce_partials<2>(P2 + mb.bf, stride, mb.nbf, red);
     if (ks->conv) return;
     const double omega = red[1] > 0.0 ? red[0] / red[1] : 0.0;
     const double alpha = ks->alpha;
+    d += mb.to; r += mb.to; rh += mb.to; p += mb.to; sv += mb.to; t += mb.to;
     double acc[2] = {0.0, 0.0};
-    // four elements per thread and pass, all loads issued before use
     constexpr int U = 4;
-    const size_t bd = blockDim.x, span = (size_t)gridDim.x * bd * U;
-    for (size_t i0 = (size_t)blockIdx.x * bd * U + threadIdx.x; i0 < n; i0 += span) {
+    const ElemRange er = elem_range(mb, lb, K);
+    const size_t bd = blockDim.x;
+    for (size_t i0 = er.i0; i0 < er.n; i0 += er.span) {
         T dv[U], pv[U], sval[U], tv[U], rhv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const size_t i = i0 + u * bd;
-            const bool ok = i < n;
+            const bool ok = i < er.n;
             dv[u] = ok ? d[i] : T(0);
             pv[u] = ok ? p[i] : T(0);
             sval[u] = ok ? sv[i] : T(0);
@@ -1182,7 +1322,7 @@ __global__ void k_bicg_k3(T *__restrict__ d, T *__restrict__ r,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const size_t i = i0 + u * bd;
-            if (i < n) {
+            if (i < er.n) {
                 const double si = sval[u];
                 d[i] = (T)((double)dv[u] + alpha * (double)pv[u] + omega * si);
                 const double rr = si - omega * (double)tv[u];
@@ -1193,7 +1333,7 @@ __global__ void k_bicg_k3(T *__restrict__ d, T *__restrict__ r,
         }
     }
     store_partials<2>(acc, P3, stride);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         ks->omega = omega;
         ks->iters += 1;
     }
@@ -1211,8 +1351,10 @@ __global__ void k_axpy(double *__restrict__ y, const T *__restrict__ x, double a
 // captured in a graph); the decisions the host-driven loop takes after a
 // read-back are taken here on the device, and launches past convergence
 // return at entry.
-__global__ void k_stage_begin(KrylovState *ks) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+// One block per member.
+__global__ void k_stage_begin(KrylovState *ks_all) {
+    KrylovState *ks = ks_all + blockIdx.x;
+    if (threadIdx.x == 0) {
         ks->stage_done = 0;
         ks->sweep = 0;
         ks->relres = 0.0;
@@ -1222,24 +1364,28 @@ __global__ void k_stage_begin(KrylovState *ks) {
     }
 }
 
-// Reduce the FP64 residual norms of the last trace_residual (partials
-// [4][n_res]); stop the stage solve if relres <= refine_rtol, else start an
-// inner solve on Ghat d = rin (as k_bicg_init) with tolerance
-// max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2).
+// Reduce the member's FP64 residual norms of the last trace_residual
+// (partials [4][face blocks]); stop its stage solve if relres <=
+// refine_rtol, else start an inner solve on Ghat d = rin (as k_bicg_init)
+// with tolerance max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2).
 template <typename T>
-__global__ void k_refine_check(const T *__restrict__ rin, T *__restrict__ r, T *__restrict__ rh,
-                               T *__restrict__ p, T *__restrict__ v, T *__restrict__ d,
-                               size_t n, KrylovState *ks, const double *res_partials,
-                               int stride, int n_res, double refine_rtol, double inner_rtol,
-                               double *P3, int p3_stride) {
+__global__ void k_refine_check(const Batch bt, int K, const T *__restrict__ rin,
+                               T *__restrict__ r, T *__restrict__ rh, T *__restrict__ p,
+                               T *__restrict__ v, T *__restrict__ d, KrylovState *ks_all,
+                               const double *res_partials, int stride, double refine_rtol,
+                               double inner_rtol, double *P3) {
+    int lb;
+    const int mi = member_of<CE>(bt, blockIdx.x, lb);
+    KrylovState *ks = ks_all + mi;
     if (ks->stage_done) return;
+    const Member mb = load_member(bt, mi);
     double nrm[4];
-    reduce_partials<4>(res_partials, stride, n_res, nrm);
+    reduce_partials<4>(res_partials + mb.bf, stride, mb.nbf, nrm);
     const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
     const double relres = gg > 0.0 ? sqrt(rr / gg) : sqrt(rr);
     const bool finite = isfinite(rr) && isfinite(gg) && isfinite(rinrin);
     if (!finite || relres <= refine_rtol) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lb == 0 && threadIdx.x == 0) {
             ks->relres = finite ? relres : NAN;
             ks->stage_done = 1;
             ks->conv = 1;
@@ -1248,16 +1394,27 @@ __global__ void k_refine_check(const T *__restrict__ rin, T *__restrict__ r, T *
     }
     const double fl = 0.1 * refine_rtol;
     const double tol2 = fmax(inner_rtol * inner_rtol * rinrin, fl * fl * ghh);
+    rin += mb.to; r += mb.to; rh += mb.to; p += mb.to; v += mb.to; d += mb.to;
     double acc[2] = {0.0, 0.0};
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double x = rin[i];
-        r[i] = (T)x; rh[i] = (T)x; p[i] = T(0); v[i] = T(0); d[i] = T(0);
-        acc[0] += x * x;
-        acc[1] += x * x;
+    const ElemRange er = elem_range(mb, lb, K);
+    const size_t bd = blockDim.x;
+    for (size_t i0 = er.i0; i0 < er.n; i0 += er.span) {
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = (i0 + u * bd < er.n) ? rin[i0 + u * bd] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t i = i0 + u * bd;
+            if (i < er.n) {
+                r[i] = x[u]; rh[i] = x[u]; p[i] = T(0); v[i] = T(0); d[i] = T(0);
+                const double xd = x[u];
+                acc[0] += xd * xd;
+                acc[1] += xd * xd;
+            }
+        }
     }
-    store_partials<2>(acc, P3, p3_stride);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store_partials<2>(acc, P3, stride);
+    if (lb == 0 && threadIdx.x == 0) {
         ks->relres = relres;
         ks->rho = 1.0;
         ks->alpha = 1.0;
@@ -1271,37 +1428,62 @@ __global__ void k_refine_check(const T *__restrict__ rin, T *__restrict__ r, T *
     }
 }
 
-// x += d after a sweep, unless the stage solve had already converged.
+// x += d after a sweep, unless the member's stage solve had already
+// converged.
 template <typename T>
-__global__ void k_axpy_guarded(double *__restrict__ y, const T *__restrict__ x, size_t n,
-                               KrylovState *ks) {
+__global__ void k_axpy_guarded(const Batch bt, int K, double *__restrict__ y,
+                               const T *__restrict__ x, KrylovState *ks_all) {
+    int lb;
+    const int mi = member_of<CE>(bt, blockIdx.x, lb);
+    KrylovState *ks = ks_all + mi;
     if (ks->stage_done) return;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] += (double)x[i];
-    if (i == 0) {
+    const Member mb = load_member(bt, mi);
+    y += mb.to;
+    x += mb.to;
+    const ElemRange er = elem_range(mb, lb, K);
+    const size_t bd = blockDim.x;
+    for (size_t i0 = er.i0; i0 < er.n; i0 += er.span) {
+        T xv[4];
+        double yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = i0 + u * bd < er.n;
+            xv[u] = ok ? x[i0 + u * bd] : T(0);
+            yv[u] = ok ? y[i0 + u * bd] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * bd < er.n) y[i0 + u * bd] = yv[u] + (double)xv[u];
+    }
+    if (lb == 0 && threadIdx.x == 0) {
         const int sw = ks->sweep - 1;
         if (sw >= 0 && sw < 8) ks->sweep_iters[sw] = ks->iters;
     }
 }
 
-// After the last sweep: if the solve never met refine_rtol, take the
-// residual of the final trace_residual; record the outcome.
-__global__ void k_stage_finish(KrylovState *ks, const double *res_partials, int stride,
-                               int n_res, double refine_rtol, StageStatus *out) {
+// After the last sweep, one block per member: if the solve never met
+// refine_rtol, take the residual of the final trace_residual; record the
+// outcome.
+__global__ void k_stage_finish(const Batch bt, KrylovState *ks_all, const double *res_partials,
+                               int stride, StageStatus *out_all) {
+    const int mi = blockIdx.x;
+    KrylovState *ks = ks_all + mi;
+    const Member mb = load_member(bt, mi);
     double relres = ks->relres;
     const int done = ks->stage_done;
     if (!done) {
         double nrm[2];
-        reduce_partials<2>(res_partials, stride, n_res, nrm);
+        reduce_partials<2>(res_partials + mb.bf, stride, mb.nbf, nrm);
         relres = nrm[1] > 0.0 ? sqrt(nrm[0] / nrm[1]) : sqrt(nrm[0]);
     }
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+        StageStatus *out = out_all + mi;
         out->relres = relres;
-        out->converged = (isfinite(relres) && relres <= refine_rtol) ? 1 : 0;
+        out->converged = done;
         out->sweeps = ks->sweep;
         int tot = 0;
         for (int i = 0; i < kMaxSweeps; ++i) {
-            out->sweep_iters[i] = i < 8 ? ks->sweep_iters[i] : 0;
+            out->sweep_iters[i] = ks->sweep_iters[i];
             tot += out->sweep_iters[i];
         }
         out->iters_total = tot;
@@ -1312,15 +1494,19 @@ __global__ void k_stage_finish(KrylovState *ks, const double *res_partials, int 
 // Partials of (mass phi_eta, mass U, mass V, energy, non-finite count).
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_diag(const double *__restrict__ q, const Geom g,
-                                                 double *partials, int stride) {
+                                                 const Batch bt, double *partials,
+                                                 int stride) {
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
-    const size_t nel = g.nel, NN = (size_t)K * K * nel;
+    int lb;
+    const Member mb = load_member(bt, member_of<CD>(bt, blockIdx.x, lb));
+    q += mb.vo;
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int e = blockIdx.x * 64 + lane; e < g.nel; e += gridDim.x * 64) {
+    for (int e = lb * 64 + lane; e < mb.nel; e += mb.nbd * 64) {
         for (int i = 0; i < K; ++i) {
             const size_t o = (size_t)(j * K + i) * nel + e;
-            const double m = g.mass[j * K + i];
+            const double m = mb.area * g.w[i] * g.w[j];
             const double p = q[o], U = q[NN + o], V = q[2 * NN + o];
             acc[0] += m * p;
             acc[1] += m * U;
@@ -1349,105 +1535,87 @@ hipError_t dispatch(int K, Args &&...args) {
     }
 }
 
-
 template <int K> struct RunNL {
-    static hipError_t run(const Geom &g, const double *q, const Comb &c, hipStream_t s) {
-        hipLaunchKernelGGL(k_nl<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, q, g, c);
+    static hipError_t run(const Geom &g, const Batch &b, const double *q, const Comb &c,
+                          bool scale_dt, hipStream_t s) {
+        hipLaunchKernelGGL(k_nl<K>, dim3(b.nbv), dim3(64 * K), 0, s, q, g, b, c,
+                           scale_dt ? 1 : 0);
         return hipGetLastError();
     }
 };
 template <int K> struct RunLinres {
-    static hipError_t run(const Geom &g, const double *Q, const double *qh, double *out,
-                          hipStream_t s) {
-        hipLaunchKernelGGL(k_linres<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, Q, qh, g, out);
+    static hipError_t run(const Geom &g, const Batch &b, const double *Q, const double *qh,
+                          double *out, hipStream_t s) {
+        hipLaunchKernelGGL(k_linres<K>, dim3(b.nbv), dim3(64 * K), 0, s, Q, qh, g, b, out);
         return hipGetLastError();
     }
 };
 template <int K> struct RunLocal {
-    static hipError_t run(const Geom &g, const double *A, const double *R, double *Z,
-                          hipStream_t s) {
-        hipLaunchKernelGGL(k_local_apply<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, A, R, g, Z);
+    static hipError_t run(const Batch &b, const double *R, double *Z, hipStream_t s) {
+        hipLaunchKernelGGL(k_local_apply<K>, dim3(b.nbv), dim3(64 * K), 0, s, R, b, Z);
         return hipGetLastError();
     }
 };
 template <int K> struct RunRecover {
-    static hipError_t run(const Geom &g, const double *W, const double *Z, const double *qh,
-                          double *Q, hipStream_t s) {
-        hipLaunchKernelGGL(k_recover<K>, dim3(grid1(g.nel, 64)), dim3(64 * K), 0, s, W, Z, qh, g, Q);
+    static hipError_t run(const Batch &b, const double *Z, const double *qh, double *Q,
+                          hipStream_t s) {
+        hipLaunchKernelGGL(k_recover<K>, dim3(b.nbv), dim3(64 * K), 0, s, Z, qh, b, Q);
         return hipGetLastError();
     }
 };
 template <int K> struct RunTraceRhs {
-    static hipError_t run(const Geom &g, const double *Z, const double *Px, const double *Py,
-                          double *gv, double *gh, hipStream_t s) {
-        hipLaunchKernelGGL(k_trace_rhs<K>, dim3(2 * grid1(g.nel, 64)), dim3(64 * K), 0, s, Z, Px,
-                           Py, g, gv, gh);
+    static hipError_t run(const Geom &g, const Batch &b, const double *Z, double *gv,
+                          double *gh, hipStream_t s) {
+        hipLaunchKernelGGL(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, gh);
         return hipGetLastError();
     }
 };
 template <typename RT> struct RunTraceResidual {
     template <int K> struct F {
-        static hipError_t run(const Geom &g, const double *G, const double *Gh,
-                              const double *x, const double *gv, const double *gh, double *r,
-                              RT *rin, double *partials, int stride, const int32_t *skip,
-                              hipStream_t s) {
-            if (is_tiled(g))
-                hipLaunchKernelGGL((k_trace_residual<K, true, RT>), dim3(face_grid(g)),
-                                   dim3(kFaceThreads), 0, s, FragMats{G, Gh}, x, gv, gh, g, r,
-                                   rin, partials, stride, skip);
-            else
-                hipLaunchKernelGGL((k_trace_residual<K, false, RT>), dim3(face_grid(g)),
-                                   dim3(kFaceThreads), 0, s, FragMats{G, Gh}, x, gv, gh, g, r,
-                                   rin, partials, stride, skip);
+        static hipError_t run(const Batch &b, const double *x, const double *gv,
+                              const double *gh, double *r, RT *rin, double *partials,
+                              int stride, const KrylovState *skip, hipStream_t s) {
+            hipLaunchKernelGGL((k_trace_residual<K, RT>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
+                               b, x, gv, gh, r, rin, partials, stride, skip);
             return hipGetLastError();
         }
     };
 };
 template <typename T> struct RunK1 {
     template <int K> struct F {
-        static hipError_t run(const Geom &g, const T *Gh, const T *r, const T *rh,
-                              const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,
+        static hipError_t run(const Batch &b, const T *r, const T *rh, const T *pin,
+                              const T *vin, T *pout, T *vout, KrylovState *ks,
                               const KrylovBufs &kb, hipStream_t s) {
-            const FragMatsT<T> A{Gh, nullptr};
-            const dim3 gr(face_grid(g)), bl(kFaceThreads);
-            const int n3 = (int)elem_grid(g);
-#define IMEXHDG_K1(TL, SC)                                                                 \
-    hipLaunchKernelGGL((k_bicg_k1<K, TL, T, SC>), gr, bl, 0, s, A, r, rh, pin, vin, pout, \
-                       vout, g, ks, kb.P3, n3, kb.P1, kb.stride)
-            if (is_tiled(g)) {
-                if (kb.sched) IMEXHDG_K1(true, true); else IMEXHDG_K1(true, false);
-            } else {
-                if (kb.sched) IMEXHDG_K1(false, true); else IMEXHDG_K1(false, false);
-            }
-#undef IMEXHDG_K1
+            if (kb.sched)
+                hipLaunchKernelGGL((k_bicg_k1<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                                   s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
+                                   kb.stride);
+            else
+                hipLaunchKernelGGL((k_bicg_k1<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                                   s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
+                                   kb.stride);
             return hipGetLastError();
         }
     };
 };
 template <typename T> struct RunK2 {
     template <int K> struct F {
-        static hipError_t run(const Geom &g, const T *Gh, const T *r, const T *v, T *sv, T *t,
+        static hipError_t run(const Batch &b, const T *r, const T *v, T *sv, T *t,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-            const FragMatsT<T> A{Gh, nullptr};
-            const dim3 gr(face_grid(g)), bl(kFaceThreads);
-            const int n1 = (int)face_grid(g), n3 = (int)elem_grid(g);
-#define IMEXHDG_K2(TL, SC)                                                                    \
-    hipLaunchKernelGGL((k_bicg_k2<K, TL, T, SC>), gr, bl, 0, s, A, r, v, sv, t, g, ks, kb.P1, \
-                       n1, kb.P3, n3, kb.P2, kb.stride)
-            if (is_tiled(g)) {
-                if (kb.sched) IMEXHDG_K2(true, true); else IMEXHDG_K2(true, false);
-            } else {
-                if (kb.sched) IMEXHDG_K2(false, true); else IMEXHDG_K2(false, false);
-            }
-#undef IMEXHDG_K2
+            if (kb.sched)
+                hipLaunchKernelGGL((k_bicg_k2<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                                   s, b, r, v, sv, t, ks, kb.P1, kb.P3, kb.P2, kb.stride);
+            else
+                hipLaunchKernelGGL((k_bicg_k2<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                                   s, b, r, v, sv, t, ks, kb.P1, kb.P3, kb.P2, kb.stride);
             return hipGetLastError();
         }
     };
 };
 template <int K> struct RunDiag {
-    static hipError_t run(const Geom &g, const double *q, double *partials, int stride,
-                          hipStream_t s) {
-        hipLaunchKernelGGL(k_diag<K>, dim3(diag_grid(g)), dim3(64 * K), 0, s, q, g, partials,
+    static hipError_t run(const Geom &g, const Batch &b, const double *q, double *partials,
+                          int stride, hipStream_t s) {
+        hipLaunchKernelGGL(k_diag<K>, dim3(b.nbd), dim3(64 * K), 0, s, q, g, b, partials,
                            stride);
         return hipGetLastError();
     }
@@ -1455,173 +1623,126 @@ template <int K> struct RunDiag {
 
 }  // namespace
 
-bool is_tiled(const Geom &g) { return g.nx % kTX == 0 && g.ny % kTY == 0; }
-
-unsigned face_grid(const Geom &g) {
-    // 64-element tiles (16 x 4 when the mesh is tiled, else 64 consecutive
-    // elements); a multiple of 8 blocks when there are enough tiles, so that
-    // every XCD gets the same number of blocks
-    const unsigned t = is_tiled(g) ? (unsigned)((g.nx / kTX) * (g.ny / kTY)) : grid1(g.nel, 64);
-    const unsigned n = std::min<unsigned>(t, (unsigned)std::min(g.fgrid, kMaxLaunchGrid));
-    return n >= 8 ? n & ~7u : n;
+int member_tiles(int nx, int ny) {
+    return (nx % kTX == 0 && ny % kTY == 0) ? (nx / kTX) * (ny / kTY)
+                                              : (int)grid1((size_t)nx * ny, 64);
 }
 
-unsigned elem_grid(const Geom &g) {
-    const size_t n = (size_t)6 * g.K * g.nel;
-    return std::min<unsigned>(grid1(n, 256), (unsigned)std::min(g.egrid, kMaxLaunchGrid));
+int member_face_blocks(int nx, int ny, int fgrid) {
+    // a multiple of 8 blocks when there are enough tiles, so that every XCD
+    // gets the same number of blocks
+    const int n = std::min(member_tiles(nx, ny), std::min(fgrid, kMaxLaunchGrid));
+    return n >= 8 ? n & ~7 : n;
 }
 
-unsigned diag_grid(const Geom &g) { return std::min<unsigned>(grid1(g.nel, 64), kMaxGrid); }
-
-hipError_t launch_nl(const Geom &g, const double *q, const Comb &comb, hipStream_t s) {
-    return dispatch<RunNL>(g.K, g, q, comb, s);
+int member_elem_blocks(int nel, int K, int egrid) {
+    const size_t n = (size_t)6 * K * nel;
+    return (int)std::min<size_t>(grid1(n, 256 * 4), (size_t)std::min(egrid, kMaxLaunchGrid));
 }
 
-hipError_t launch_combine(const Geom &g, const Comb &comb, size_t n, hipStream_t s) {
-    (void)g;
+int member_vol_blocks(int nel) { return (int)grid1(nel, 64); }
+
+int member_diag_blocks(int nel) { return (int)std::min<unsigned>(grid1(nel, 64), 1024u); }
+
+hipError_t launch_nl(const Geom &g, const Batch &b, const double *q, const Comb &comb,
+                     bool scale_dt, hipStream_t s) {
+    return dispatch<RunNL>(g.K, g, b, q, comb, scale_dt, s);
+}
+
+hipError_t launch_combine(const Comb &comb, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_combine, dim3(grid1(n, 256)), dim3(256), 0, s, comb, n);
     return hipGetLastError();
 }
 
-hipError_t launch_linear_residual(const Geom &g, const double *Q, const double *qhat,
-                                  double *out, hipStream_t s) {
-    return dispatch<RunLinres>(g.K, g, Q, qhat, out, s);
+hipError_t launch_linear_residual(const Geom &g, const Batch &b, const double *Q,
+                                  const double *qhat, double *out, hipStream_t s) {
+    return dispatch<RunLinres>(g.K, g, b, Q, qhat, out, s);
 }
 
-hipError_t launch_local_apply(const Geom &g, const double *Ainv, const double *R, double *Z,
+hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, double *Z,
                               hipStream_t s) {
-    return dispatch<RunLocal>(g.K, g, Ainv, R, Z, s);
+    return dispatch<RunLocal>(g.K, b, R, Z, s);
 }
 
-hipError_t launch_trace_rhs(const Geom &g, const double *Z, const double *Pxinv,
-                            const double *Pyinv, double *gvec, double *ghat, hipStream_t s) {
-    return dispatch<RunTraceRhs>(g.K, g, Z, Pxinv, Pyinv, gvec, ghat, s);
+hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
+                            double *ghat, hipStream_t s) {
+    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, ghat, s);
 }
 
-hipError_t launch_recover(const Geom &g, const double *W, const double *Z, const double *qhat,
+hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
                           double *Q, hipStream_t s) {
-    return dispatch<RunRecover>(g.K, g, W, Z, qhat, Q, s);
+    return dispatch<RunRecover>(g.K, b, Z, qhat, Q, s);
 }
-
-namespace {
-
-template <typename T>
-hipError_t trace_residual_impl(const Geom &g, const double *G, const double *Gh,
-                               const double *x, const double *gvec, const double *ghat,
-                               double *r, T *rin, double *partials, int stride,
-                               const int32_t *skip, hipStream_t s) {
-    return dispatch<RunTraceResidual<T>::template F>(g.K, g, G, Gh, x, gvec, ghat, r, rin,
-                                                      partials, stride, skip, s);
-}
-
-template <typename T>
-hipError_t refine_check_impl(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,
-                             KrylovState *ks, const double *partials, int stride,
-                             double refine_rtol, double inner_rtol, const KrylovBufs &kb,
-                             hipStream_t s) {
-    const size_t n = (size_t)6 * g.K * g.nel;
-    hipLaunchKernelGGL(k_refine_check<T>, dim3(elem_grid(g)), dim3(256), 0, s, rin, r, rh, p,
-                       v, d, n, ks, partials, stride, (int)face_grid(g), refine_rtol,
-                       inner_rtol, kb.P3, kb.stride);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t axpy_guarded_impl(double *y, const T *x, size_t n, KrylovState *ks, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy_guarded<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, n, ks);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t bicg_init_impl(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,
-                          KrylovState *ks, double tol2, const KrylovBufs &kb, hipStream_t s) {
-    const size_t n = (size_t)6 * g.K * g.nel;
-    hipLaunchKernelGGL(k_bicg_init<T>, dim3(elem_grid(g)), dim3(256), 0, s, rin, r, rh, p, v, d,
-                       n, ks, tol2, kb.P3, kb.stride);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t bicg_k3_impl(const Geom &g, T *d, T *r, const T *rh, const T *p, const T *sv,
-                        const T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-    const size_t n = (size_t)6 * g.K * g.nel;
-    hipLaunchKernelGGL(k_bicg_k3<T>, dim3(elem_grid(g)), dim3(256), 0, s, d, r, rh, p, sv, t, n,
-                       ks, kb.P2, (int)face_grid(g), kb.P3, kb.stride);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t axpy_impl(double *y, const T *x, double a, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);
-    return hipGetLastError();
-}
-
-}  // namespace
 
 #define IMEXHDG_KRYLOV_LAUNCHERS(T)                                                            \
-    hipError_t launch_trace_residual(const Geom &g, const double *G, const double *Gh,        \
-                                     const double *x, const double *gvec,                     \
-                                     const double *ghat, double *r, T *rin, double *partials, \
-                                     int stride, const int32_t *skip, hipStream_t s) {        \
-        return trace_residual_impl<T>(g, G, Gh, x, gvec, ghat, r, rin, partials, stride,      \
-                                      skip, s);                                               \
+    hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
+                                     const double *gvec, const double *ghat, double *r,       \
+                                     T *rin, double *partials, int stride,                    \
+                                     const KrylovState *skip, hipStream_t s) {                \
+        return dispatch<RunTraceResidual<T>::template F>(g.K, b, x, gvec, ghat, r, rin,       \
+                                                         partials, stride, skip, s);          \
     }                                                                                          \
-    hipError_t launch_refine_check(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v,      \
-                                   T *d, KrylovState *ks, const double *partials, int stride, \
-                                   double refine_rtol, double inner_rtol,                     \
-                                   const KrylovBufs &kb, hipStream_t s) {                     \
-        return refine_check_impl<T>(g, rin, r, rh, p, v, d, ks, partials, stride,             \
-                                    refine_rtol, inner_rtol, kb, s);                          \
+    hipError_t launch_bicg_init(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
+                                T *p, T *v, T *d, KrylovState *ks, double tol2,               \
+                                const KrylovBufs &kb, hipStream_t s) {                        \
+        hipLaunchKernelGGL(k_bicg_init<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r, rh, \
+                           p, v, d, ks, tol2, kb.P3, kb.stride);                              \
+        return hipGetLastError();                                                              \
     }                                                                                          \
-    hipError_t launch_axpy_guarded(double *y, const T *x, size_t n, KrylovState *ks,          \
-                                   hipStream_t s) {                                           \
-        return axpy_guarded_impl<T>(y, x, n, ks, s);                                          \
-    }                                                                                          \
-    hipError_t launch_bicg_init(const Geom &g, const T *rin, T *r, T *rh, T *p, T *v, T *d,  \
-                                KrylovState *ks, double tol2, const KrylovBufs &kb,           \
-                                hipStream_t s) {                                              \
-        return bicg_init_impl<T>(g, rin, r, rh, p, v, d, ks, tol2, kb, s);                    \
-    }                                                                                          \
-    hipError_t launch_bicg_k1(const Geom &g, const T *Gh, const T *r, const T *rh,            \
+    hipError_t launch_bicg_k1(const Geom &g, const Batch &b, const T *r, const T *rh,         \
                               const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,  \
                               const KrylovBufs &kb, hipStream_t s) {                          \
-        return dispatch<RunK1<T>::template F>(g.K, g, Gh, r, rh, pin, vin, pout, vout, ks, kb,  \
+        return dispatch<RunK1<T>::template F>(g.K, b, r, rh, pin, vin, pout, vout, ks, kb,    \
                                               s);                                             \
     }                                                                                          \
-    hipError_t launch_bicg_k2(const Geom &g, const T *Gh, const T *r, const T *v, T *sv,      \
+    hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v, T *sv,   \
                               T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {   \
-        return dispatch<RunK2<T>::template F>(g.K, g, Gh, r, v, sv, t, ks, kb, s);            \
+        return dispatch<RunK2<T>::template F>(g.K, b, r, v, sv, t, ks, kb, s);                \
     }                                                                                          \
-    hipError_t launch_bicg_k3(const Geom &g, T *d, T *r, const T *rh, const T *p,             \
-                              const T *sv, const T *t, KrylovState *ks, const KrylovBufs &kb, \
-                              hipStream_t s) {                                                \
-        return bicg_k3_impl<T>(g, d, r, rh, p, sv, t, ks, kb, s);                             \
+    hipError_t launch_bicg_k3(const Geom &g, const Batch &b, T *d, T *r, const T *rh,         \
+                              const T *p, const T *sv, const T *t, KrylovState *ks,           \
+                              const KrylovBufs &kb, hipStream_t s) {                          \
+        hipLaunchKernelGGL(k_bicg_k3<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, d, r, rh, p,   \
+                           sv, t, ks, kb.P2, kb.P3, kb.stride);                               \
+        return hipGetLastError();                                                              \
     }                                                                                          \
     hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s) {        \
-        return axpy_impl<T>(y, x, a, n, s);                                                   \
+        hipLaunchKernelGGL(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);     \
+        return hipGetLastError();                                                              \
+    }                                                                                          \
+    hipError_t launch_refine_check(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,  \
+                                   T *p, T *v, T *d, KrylovState *ks, const double *partials, \
+                                   int stride, double refine_rtol, double inner_rtol,         \
+                                   const KrylovBufs &kb, hipStream_t s) {                     \
+        hipLaunchKernelGGL(k_refine_check<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r,   \
+                           rh, p, v, d, ks, partials, stride, refine_rtol, inner_rtol, kb.P3); \
+        return hipGetLastError();                                                              \
+    }                                                                                          \
+    hipError_t launch_axpy_guarded(const Geom &g, const Batch &b, double *y, const T *x,      \
+                                   KrylovState *ks, hipStream_t s) {                          \
+        hipLaunchKernelGGL(k_axpy_guarded<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, y, x, ks); \
+        return hipGetLastError();                                                              \
     }
 
 IMEXHDG_KRYLOV_LAUNCHERS(double)
 IMEXHDG_KRYLOV_LAUNCHERS(float)
 #undef IMEXHDG_KRYLOV_LAUNCHERS
 
-hipError_t launch_stage_begin(KrylovState *ks, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(64), 0, s, ks);
+hipError_t launch_stage_begin(const Batch &b, KrylovState *ks, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_begin, dim3(b.nm), dim3(64), 0, s, ks);
     return hipGetLastError();
 }
 
-hipError_t launch_stage_finish(const Geom &g, KrylovState *ks, const double *partials,
+hipError_t launch_stage_finish(const Batch &b, KrylovState *ks, const double *partials,
                                int stride, StageStatus *out, hipStream_t s) {
-    // refine_rtol is not known here; the host compares relres itself, so pass
-    // +inf and keep `converged` as "residual finite"
-    hipLaunchKernelGGL(k_stage_finish, dim3(1), dim3(256), 0, s, ks, partials, stride,
-                       (int)face_grid(g), INFINITY, out);
+    hipLaunchKernelGGL(k_stage_finish, dim3(b.nm), dim3(256), 0, s, b, ks, partials, stride,
+                       out);
     return hipGetLastError();
 }
 
-hipError_t launch_diag(const Geom &g, const double *q, double *partials, int stride,
-                       hipStream_t s) {
-    return dispatch<RunDiag>(g.K, g, q, partials, stride, s);
+hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
+                       int stride, hipStream_t s) {
+    return dispatch<RunDiag>(g.K, g, b, q, partials, stride, s);
 }
 
 }  // namespace imexhdg

@@ -29,6 +29,10 @@ EXPORTS = [
     "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_profile",
     "imexhdg_profile_read", "imexhdg_kernel_name", "imexhdg_get_schedule",
     "imexhdg_set_schedule", "imexhdg_set_launch_geometry", "imexhdg_autotune",
+    "imexhdg_ens_workspace_bytes", "imexhdg_ens_create", "imexhdg_ens_destroy",
+    "imexhdg_ens_members", "imexhdg_ens_sizes", "imexhdg_ens_get_nodes",
+    "imexhdg_ens_set_state", "imexhdg_ens_get_state", "imexhdg_ens_step",
+    "imexhdg_ens_get_diag", "imexhdg_ens_get_schedule", "imexhdg_ens_set_launch_geometry",
 ]
 KERNELS = ["nl_residual", "combine", "local_apply", "trace_rhs", "trace_residual", "bicg_init",
            "bicg_k1", "bicg_k2", "bicg_k3", "axpy", "recover", "diag", "linear_residual"]
@@ -105,6 +109,19 @@ def load():
         "imexhdg_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "imexhdg_set_schedule": (ctypes.c_int, [P, i32, ctypes.POINTER(i32)]),
         "imexhdg_set_launch_geometry": (ctypes.c_int, [P, i32, i32]),
+        "imexhdg_ens_workspace_bytes": (ctypes.c_int, [cfgp, i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "imexhdg_ens_create": (ctypes.c_int, [cfgp, i32, P, P, ctypes.c_size_t,
+                                              ctypes.POINTER(P)]),
+        "imexhdg_ens_destroy": (None, [P]),
+        "imexhdg_ens_members": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
+        "imexhdg_ens_sizes": (ctypes.c_int, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "imexhdg_ens_get_nodes": (ctypes.c_int, [P, i32, P, P]),
+        "imexhdg_ens_set_state": (ctypes.c_int, [P, i32, ctypes.c_int, P, P, P]),
+        "imexhdg_ens_get_state": (ctypes.c_int, [P, i32, ctypes.c_int, P, P, P]),
+        "imexhdg_ens_step": (ctypes.c_int, [P, i32]),
+        "imexhdg_ens_get_diag": (ctypes.c_int, [P, i32, ctypes.POINTER(Diag)]),
+        "imexhdg_ens_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "imexhdg_ens_set_launch_geometry": (ctypes.c_int, [P, i32, i32]),
         "imexhdg_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32),
                                             ctypes.POINTER(i32)]),
     }
@@ -291,3 +308,81 @@ def volume_to_device_layout(q, nel, K):
 def volume_from_device_layout(v, nel, K):
     v = np.asarray(v).reshape(3, K * K, nel)
     return np.ascontiguousarray(v.transpose(0, 2, 1)).reshape(3, nel * K * K)
+
+
+class Ensemble:
+    """Members stepped together: every launch covers all members, one graph
+    launch per step.  cfgs: list of Config that differ in nx, ny, Lx, Ly, dt
+    only (LAUNCH_GRAPH)."""
+
+    def __init__(self, cfgs, device="cuda"):
+        self.lib = load()
+        self.cfgs = list(cfgs)
+        n = len(self.cfgs)
+        self._arr = (Config * n)(*self.cfgs)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        nb = ctypes.c_size_t(0)
+        _check(self.lib.imexhdg_ens_workspace_bytes(self._arr, n, ctypes.byref(nb)))
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self._ens = ctypes.c_void_p()
+        _check(self.lib.imexhdg_ens_create(self._arr, n, ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.c_void_p(aligned), nb.value,
+                                           ctypes.byref(self._ens)))
+        self.n = n
+        self.n_nodes, self.n_trace = [], []
+        for m in range(n):
+            nn, nt = ctypes.c_int64(), ctypes.c_int64()
+            _check(self.lib.imexhdg_ens_sizes(self._ens, m, ctypes.byref(nn), ctypes.byref(nt)))
+            self.n_nodes.append(nn.value)
+            self.n_trace.append(nt.value)
+
+    def close(self):
+        if getattr(self, "_ens", None) and self._ens.value:
+            self.lib.imexhdg_ens_destroy(self._ens)
+            self._ens = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self, m):
+        x = np.empty(self.n_nodes[m])
+        y = np.empty(self.n_nodes[m])
+        _check(self.lib.imexhdg_ens_get_nodes(self._ens, m, _ptr(x), _ptr(y)))
+        return x, y
+
+    def set_state(self, m, a, b, c, vars=VARS_DEPTH):
+        arrs = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).ravel()) for v in (a, b, c)]
+        for v in arrs:
+            if v.size != self.n_nodes[m]:
+                raise ValueError("state arrays must hold the member's n_nodes values")
+        _check(self.lib.imexhdg_ens_set_state(self._ens, m, vars, *[_ptr(v) for v in arrs]))
+
+    def get_state(self, m, vars=VARS_DEPTH):
+        out = [np.empty(self.n_nodes[m]) for _ in range(3)]
+        _check(self.lib.imexhdg_ens_get_state(self._ens, m, vars, *[_ptr(v) for v in out]))
+        return out
+
+    def step(self, n=1, allow_noconv=False):
+        return _check(self.lib.imexhdg_ens_step(self._ens, int(n)),
+                      allow=(E_NOCONV,) if allow_noconv else ())
+
+    def diag(self, m):
+        d = Diag()
+        _check(self.lib.imexhdg_ens_get_diag(self._ens, m, ctypes.byref(d)))
+        return {f: (list(getattr(d, f)) if f == "mass" else getattr(d, f))
+                for f, _ in Diag._fields_}
+
+    def schedule(self):
+        n = ctypes.c_int32()
+        b = (ctypes.c_int32 * 8)()
+        _check(self.lib.imexhdg_ens_get_schedule(self._ens, ctypes.byref(n), b))
+        return n.value, list(b)[:n.value]
+
+    def set_launch_geometry(self, face_grid, elem_grid):
+        _check(self.lib.imexhdg_ens_set_launch_geometry(self._ens, int(face_grid),
+                                                        int(elem_grid)))
