@@ -52,12 +52,12 @@ def algorithmic_cost(name, wl, n_dof, isz=8):
     nfaces = 2 * nel
     b3 = 3 * K
     table = {
-        # read r, p, v, rh; write p, v
+        # first K1 of a solve: read r, p, v, rh; write p, v
         "bicg_k1": (6 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
-        # read r, v; write s, t
-        "bicg_k2": (4 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
-        # read d, p, s, t, rh; write d, r
-        "bicg_k3": (7 * T * isz, 8.0 * T),
+        # read r, v, rh; write s, t
+        "bicg_k2": (5 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
+        # fused K1: read s, t, p, v, rh, d; write r, p, v, d
+        "bicg_k1f": (10 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
         # read x, g, ghat (FP64); write r (FP64), rin (inner)
         "trace_residual": (4 * T * 8 + T * isz, 4.0 * 7 * b3 * b3 * nfaces),
         "local_apply": (2 * N * 8, 2.0 * (3 * K * K) ** 2 * nel),
@@ -73,7 +73,7 @@ def algorithmic_cost(name, wl, n_dof, isz=8):
 KERNEL_SYMBOL = {"nl_residual": "k_nl", "combine": "k_combine", "local_apply": "k_local_apply",
                  "trace_rhs": "k_trace_rhs", "trace_residual": "k_trace_residual",
                  "bicg_init": "k_bicg_init", "bicg_k1": "k_bicg_k1", "bicg_k2": "k_bicg_k2",
-                 "bicg_k3": "k_bicg_k3", "axpy": "k_axpy", "recover": "k_recover"}
+                 "bicg_k1f": "k_bicg_k1f", "axpy": "k_axpy", "recover": "k_recover"}
 
 
 def measured_traffic(kernel_class, wl_name, precision="fp64"):
@@ -199,7 +199,7 @@ def run_path(m, wl, precision, steps, warmup):
     isz = 4 if mixed else 8
     avg_s = ms / 1000.0 / nl
     nbytes, nflops = algorithmic_cost(dominant, wl, n_dof, isz)
-    matrix = dominant in ("bicg_k1", "bicg_k2", "trace_residual")
+    matrix = dominant in ("bicg_k1", "bicg_k2", "bicg_k1f", "trace_residual")
     fpeak = (FP32_MFMA_PEAK_TFLOPS if mixed and dominant != "trace_residual"
              else FP64_PEAK_TFLOPS)
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
@@ -232,6 +232,56 @@ def run_path(m, wl, precision, steps, warmup):
     return res, state
 
 
+def run_ensemble(m, steps, warmup, mixed=True):
+    """The 64-member ensemble (meshes 32^2 ... 128^2, k = 3, dt_m = 2 dx_min):
+    every launch covers all members, one graph launch per step."""
+    import torch
+    from paper_1711_02751_amd import workloads as W
+    members = W.ensemble_members()
+    cfgs = []
+    for w in members:
+        cfg = m.default_config(nx=w.n, ny=w.n, Lx=w.L, Ly=w.L, degree=w.k, g=w.g, H=w.H,
+                               dt=w.dt, physics=m.PHYSICS_NONLINEAR,
+                               precision=m.PREC_MIXED if mixed else m.PREC_FP64,
+                               launch=m.LAUNCH_GRAPH)
+        if mixed:
+            cfg.krylov_rtol = MIXED_KRYLOV_RTOL
+            cfg.refine_rtol = MIXED_REFINE_RTOL
+            cfg.refine_max = 8
+        cfgs.append(cfg)
+    E = m.Ensemble(cfgs)
+    for i, w in enumerate(members):
+        x, y = E.nodes(i)
+        E.set_state(i, *w.initial_state(x, y))
+    n_dof = 3 * sum(E.n_nodes)
+    log(f"[bench] ensemble: {len(members)} members, {n_dof} DOFs; warmup {max(warmup, 3)}")
+    E.step(max(warmup, 3))
+    fg = E.autotune()
+    log(f"[bench] ensemble: autotuned face grid cap per member: {fg}")
+    E.step(1)
+    d0 = E.diag(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d1 = E.diag(0)
+    value = n_dof * steps / el
+    log(f"[bench] ensemble: {steps} graph steps in {el:.3f} s -> {value:.4g} DOF-updates/s "
+        f"(schedule {E.schedule()})")
+    res = {"workload": "ensemble_64_members_k3", "members": len(members),
+           "mesh_sizes": f"{min(w.n for w in members)}^2..{max(w.n for w in members)}^2",
+           "n_dof": n_dof, "value": value, "unit": "DOF-updates/s",
+           "ms_per_step": 1000.0 * el / steps, "steps": steps,
+           "precision": "mixed" if mixed else "fp64",
+           "schedule": {"sweeps": E.schedule()[0], "inner_budget": E.schedule()[1]},
+           "face_grid_cap_per_member": fg,
+           "graph_steps": d1["graph_steps"] - d0["graph_steps"],
+           "redone_steps": d1["redo_steps"] - d0["redo_steps"]}
+    E.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +291,8 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed",
                     help="headline path; the FP64 path is always measured too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the 64-member ensemble measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB (counter calibration)")
@@ -302,6 +354,9 @@ def main():
                        "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
         out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]
         out["mixed_rel_l2_vs_fp64"] = [float(e) for e in err]
+    if not args.no_ensemble:
+        out["ensemble"] = run_ensemble(m, args.steps, args.warmup,
+                                       mixed=args.precision == "mixed")
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(wl.name, args.cpu_seconds)

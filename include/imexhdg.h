@@ -215,9 +215,9 @@ int imexhdg_stage_solve(imexhdg_ctx *ctx, const double *d_res0, double *d_Q,
 #define IMEXHDG_K_TRACE_RHS    3  /* g = sum C Z, ghat = P^-1 g            */
 #define IMEXHDG_K_TRACE_RESID  4  /* FP64 r = g - G x, rin = ghat - Ghat x  */
 #define IMEXHDG_K_BICG_INIT    5
-#define IMEXHDG_K_BICG_K1      6  /* p update + v = Ghat p, rh . v         */
-#define IMEXHDG_K_BICG_K2      7  /* s update + t = Ghat s, t . s, t . t   */
-#define IMEXHDG_K_BICG_K3      8  /* d, r update, rh . r, r . r            */
+#define IMEXHDG_K_BICG_K1      6  /* first p + v = Ghat p of an inner solve */
+#define IMEXHDG_K_BICG_K2      7  /* s update + t = Ghat s, t.s, t.t, rh.t  */
+#define IMEXHDG_K_BICG_K1F     8  /* d, r update + next p, v = Ghat p      */
 #define IMEXHDG_K_AXPY         9  /* x += d after a refinement sweep       */
 #define IMEXHDG_K_RECOVER     10  /* Q = Z - A^-1 B Qhat per element       */
 #define IMEXHDG_K_DIAG        11
@@ -306,6 +306,14 @@ int imexhdg_ens_get_diag(imexhdg_ens *ens, int32_t m, imexhdg_diag *d);
 int imexhdg_ens_get_schedule(const imexhdg_ens *ens, int32_t *sweeps, int32_t *budget);
 int imexhdg_ens_set_launch_geometry(imexhdg_ens *ens, int32_t face_grid,
                                     int32_t elem_grid);
+/* Tune the face-class grid cap per member (16 ... 1024 blocks) by timing
+ * graph steps from the current state, which is restored afterwards with its
+ * trace guess (solver counters kept).  Launches of members that have
+ * converged still run their blocks as no-ops, so the best cap balances
+ * parallelism against that overhead.  cache_path: as for imexhdg_autotune
+ * (one line per device, degree, member count, element count and
+ * precision).  The choice is returned in *face_grid when not NULL.       */
+int imexhdg_ens_autotune(imexhdg_ens *ens, const char *cache_path, int32_t *face_grid);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -139,6 +140,7 @@ struct imexhdg_ctx {
     const double *qin = nullptr;      // q^n of the step being enqueued
     std::vector<double *> NLb, Qb, Rb;
     double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr;
+    double *xsave = nullptr;          // autotuner's copy of the trace guess
     // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
     bool mixed = false;
     void *rin = nullptr, *kr = nullptr, *krh = nullptr, *kp[2] = {nullptr, nullptr},
@@ -220,6 +222,25 @@ std::vector<double> pack_frags(const std::vector<double> &Gx, const std::vector<
     return f;
 }
 
+// Local matrix-core operand of an nr x nc row-major matrix M:
+// frag[mb][kk][lane] = M[16 mb + lane % 16][4 kk + lane / 16], zero past M.
+size_t local_frag_count(int nr, int nc) {
+    return (size_t)((nr + 15) / 16) * ((nc + 3) / 4) * 64;
+}
+
+std::vector<double> pack_local(const std::vector<double> &M, int nr, int nc) {
+    const int NMB = (nr + 15) / 16, KS = (nc + 3) / 4;
+    std::vector<double> f(local_frag_count(nr, nc), 0.0);
+    for (int mb = 0; mb < NMB; ++mb)
+        for (int kk = 0; kk < KS; ++kk)
+            for (int l = 0; l < 64; ++l) {
+                const int row = 16 * mb + l % 16, col = 4 * kk + l / 16;
+                if (row < nr && col < nc)
+                    f[((size_t)mb * KS + kk) * 64 + l] = M[(size_t)row * nc + col];
+            }
+    return f;
+}
+
 // Worst-case partial-sum stride of a batch: every class at its largest caps.
 int partial_stride(const std::vector<imexhdg_config> &cf) {
     int64_t f = 0, e = 0, d = 0;
@@ -266,12 +287,13 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     const size_t isz = (c0.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
-    t += 4 * align256(L.T * 8);                        // FP64 trace vectors
+    t += 5 * align256(L.T * 8);                        // FP64 trace vectors
     t += 10 * align256(L.T * isz);                     // inner-solve vectors
-    t += (size_t)L.nops * (align256(n_loc * n_loc * 8) + align256(n_loc * n_tr * 8) +
+    t += (size_t)L.nops * (align256(local_frag_count((int)n_loc, (int)n_loc) * 8) +
+                           align256(local_frag_count((int)n_loc, (int)n_tr) * 8) +
                            2 * align256(frag_count((int)K) * 8) +
                            align256(frag_count((int)K) * 4) + 2 * align256(9 * K * K * 8));
-    t += 5 * align256((size_t)L.pstride * 8) + align256(5 * (size_t)L.pstride * 8);
+    t += 8 * align256((size_t)L.pstride * 8) + align256(5 * (size_t)L.pstride * 8);
     t += align256(nm * sizeof(KrylovState));
     t += align256(nm * sizeof(Member));
     t += align256(3 * (size_t)L.s * nm * sizeof(StageStatus));
@@ -405,7 +427,6 @@ int build_batch(imexhdg_ctx *c) {
         d.nx = h.nx;
         d.ny = h.ny;
         d.nel = h.nel;
-        d.tiled = (h.nx % 16 == 0 && h.ny % 4 == 0) ? 1 : 0;
         d.sx = 2.0 * h.nx / h.Lx;
         d.sy = 2.0 * h.ny / h.Ly;
         d.area = (h.Lx / h.nx / 2.0) * (h.Ly / h.ny / 2.0);
@@ -530,7 +551,8 @@ int read_partials(imexhdg_ctx *c, int nq, int first, int n, double *out) {
 // the same for every stage and step, so the first sweep's iteration count
 // is predictable: run one less than last time before the first convergence
 // check, then check every two iterations (a converged solve turns the
-// remaining launches into no-ops, so few are wasted).
+// remaining launches into no-ops, so few are wasted).  One iteration is K2
+// then K1f (the next K1 fused with this iteration's d and r updates).
 template <typename T>
 int inner_solve(imexhdg_ctx *c, double tol2, int sweep) {
     const imexhdg_config &cf = c->cfg;
@@ -554,11 +576,10 @@ int inner_solve(imexhdg_ctx *c, double tol2, int sweep) {
         chunk = std::min(2, cf.check_every);
         for (int it = 0; it < n; ++it) {
             LAUNCH(IMEXHDG_K_BICG_K2,
-                   launch_bicg_k2(g, b, r, v[par], sv, t, c->ks, c->kb, c->stream));
-            LAUNCH(IMEXHDG_K_BICG_K3,
-                   launch_bicg_k3(g, b, d, r, rh, p[par], sv, t, c->ks, c->kb, c->stream));
-            LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par],
-                                                     v[1 - par], c->ks, c->kb, c->stream));
+                   launch_bicg_k2(g, b, r, v[par], rh, sv, t, c->ks, c->kb, c->stream));
+            LAUNCH(IMEXHDG_K_BICG_K1F,
+                   launch_bicg_k1f(g, b, sv, t, rh, p[par], v[par], p[1 - par], v[1 - par], r,
+                                   d, c->ks, c->kb, c->stream));
             par = 1 - par;
         }
         done += n;
@@ -703,10 +724,9 @@ int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
                            c->stream));
     par = 1 - par;
     for (int it = 0; it < budget; ++it) {
-        HIP_TRY(launch_bicg_k2(g, b, r, v[par], sv, t, c->ks, kb, c->stream));
-        HIP_TRY(launch_bicg_k3(g, b, d, r, rh, p[par], sv, t, c->ks, kb, c->stream));
-        HIP_TRY(launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
-                               c->stream));
+        HIP_TRY(launch_bicg_k2(g, b, r, v[par], rh, sv, t, c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k1f(g, b, sv, t, rh, p[par], v[par], p[1 - par], v[1 - par], r, d,
+                                c->ks, kb, c->stream));
         par = 1 - par;
     }
     HIP_TRY(launch_axpy_guarded(g, b, c->x, (const T *)d, c->ks, c->stream));
@@ -1228,23 +1248,23 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
     c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
-    double **tv[4] = {&c->x, &c->gv, &c->gh, &c->r64};
+    double **tv[5] = {&c->x, &c->gv, &c->gh, &c->r64, &c->xsave};
     for (double **p : tv) *p = (double *)take(L.T * 8);
     void **iv[10] = {&c->rin, &c->kr, &c->krh, &c->kp[0], &c->kp[1],
                      &c->kv[0], &c->kv[1], &c->ks_, &c->kt, &c->kd};
     for (void **p : iv) *p = take(L.T * (c->mixed ? 4 : 8));
     const size_t n_loc = 3 * K * K, n_tr = 12 * K;
     for (OpSet &o : c->ops) {
-        o.Ainv = (double *)take(n_loc * n_loc * 8);
-        o.W = (double *)take(n_loc * n_tr * 8);
+        o.Ainv = (double *)take(local_frag_count((int)n_loc, (int)n_loc) * 8);
+        o.W = (double *)take(local_frag_count((int)n_loc, (int)n_tr) * 8);
         o.G = (double *)take(frag_count(K) * 8);
         o.Gh = (double *)take(frag_count(K) * 8);
         o.Ghf = (float *)take(frag_count(K) * 4);
         o.Px = (double *)take(9 * K * K * 8);
         o.Py = (double *)take(9 * K * K * 8);
     }
-    c->kb.P1 = (double *)take((size_t)c->pstride * 8);
-    c->kb.P2 = (double *)take(2 * (size_t)c->pstride * 8);
+    c->kb.P1 = (double *)take(3 * (size_t)c->pstride * 8);
+    c->kb.P2 = (double *)take(3 * (size_t)c->pstride * 8);
     c->kb.P3 = (double *)take(2 * (size_t)c->pstride * 8);
     c->kb.stride = c->pstride;
     c->dpart = (double *)take(5 * (size_t)c->pstride * 8);
@@ -1273,7 +1293,9 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
             return hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream);
         };
         const OpSet &os = c->ops[o];
-        if (up(os.Ainv, op.Ainv) || up(os.W, op.W) || up(os.G, G) || up(os.Gh, Gh) ||
+        const int nl = 3 * K * K, nt = 12 * K;
+        if (up(os.Ainv, pack_local(op.Ainv, nl, nl)) || up(os.W, pack_local(op.W, nl, nt)) ||
+            up(os.G, G) || up(os.Gh, Gh) ||
             hipMemcpyAsync(os.Ghf, Ghf.data(), Ghf.size() * 4, hipMemcpyHostToDevice,
                            c->stream) ||
             up(os.Px, op.Pxinv) || up(os.Py, op.Pyinv) || hipStreamSynchronize(c->stream))
@@ -1494,7 +1516,7 @@ int imexhdg_stage_solve(imexhdg_ctx *c, const double *d_res0, double *d_Q, doubl
 
 static const char *kKernelNames[IMEXHDG_K_COUNT] = {
     "nl_residual", "combine", "local_apply", "trace_rhs", "trace_residual", "bicg_init",
-    "bicg_k1", "bicg_k2", "bicg_k3", "axpy", "recover", "diag", "linear_residual"};
+    "bicg_k1", "bicg_k2", "bicg_k1f", "axpy", "recover", "diag", "linear_residual"};
 
 const char *imexhdg_kernel_name(int32_t k) {
     return (k >= 0 && k < IMEXHDG_K_COUNT) ? kKernelNames[k] : nullptr;
@@ -1629,8 +1651,9 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         const double keep_r[2] = {c->last_relres, c->max_relres};
         double avg[IMEXHDG_K_COUNT], base_avg[IMEXHDG_K_COUNT];
         int64_t cnt[IMEXHDG_K_COUNT], w[IMEXHDG_K_COUNT];
-        const int face_k[3] = {IMEXHDG_K_TRACE_RESID, IMEXHDG_K_BICG_K1, IMEXHDG_K_BICG_K2};
-        const int elem_k[2] = {IMEXHDG_K_BICG_INIT, IMEXHDG_K_BICG_K3};
+        const int face_k[4] = {IMEXHDG_K_TRACE_RESID, IMEXHDG_K_BICG_K1, IMEXHDG_K_BICG_K2,
+                               IMEXHDG_K_BICG_K1F};
+        const int elem_k[1] = {IMEXHDG_K_BICG_INIT};
         const int cand[5] = {256, 512, 1024, 2048, 4096};
         const int f0 = c->fgrid, e0 = c->egrid;
         const MemberHost &mh = c->mh[0];
@@ -1646,24 +1669,24 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         };
         best_f = f0;
         best_e = e0;
-        double best = rc ? 0.0 : score(base_avg, face_k, 3);
+        double best = rc ? 0.0 : score(base_avg, face_k, 4);
         for (int i = 0; i < 5 && !rc; ++i) {
             if (member_face_blocks(mh.nx, mh.ny, cand[i]) ==
                 member_face_blocks(mh.nx, mh.ny, best_f))
                 continue;
             if ((rc = tune_trial(c, cand[i], e0, avg, cnt))) break;
-            const double sc = score(avg, face_k, 3);
+            const double sc = score(avg, face_k, 4);
             if (sc < 0.98 * best) {
                 best = sc;
                 best_f = cand[i];
             }
         }
-        if (!rc) best = score(base_avg, elem_k, 2);
+        if (!rc) best = score(base_avg, elem_k, 1);
         for (int i = 0; i < 5 && !rc; ++i) {
             if (member_elem_blocks(mh.nel, K, cand[i]) == member_elem_blocks(mh.nel, K, best_e))
                 continue;
             if ((rc = tune_trial(c, best_f, cand[i], avg, cnt))) break;
-            const double sc = score(avg, elem_k, 2);
+            const double sc = score(avg, elem_k, 1);
             if (sc < 0.98 * best) {
                 best = sc;
                 best_e = cand[i];
@@ -1703,6 +1726,101 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
 }
 
 // ------------------------------------------------------------- ensembles
+// Ensemble autotuner: the face-class grid cap per member sets how many
+// blocks every face launch has; members that have converged still launch
+// theirs (as no-ops), so fewer blocks per member can win.  Times graph
+// steps (one warm step, then two) from a saved state for each candidate.
+static int ens_trial(imexhdg_ctx *c, int fg, double *ms) {
+    int rc = imexhdg_set_launch_geometry(c, fg, c->egrid);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->x, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(stream_sync(c));
+    if ((rc = step_ctx(c, 1))) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((rc = step_ctx(c, 2))) return rc;
+    HIP_TRY(stream_sync(c));
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return IMEXHDG_OK;
+}
+
+int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_grid) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    imexhdg_ctx *c = e->c;
+    if (!c->have_state) return fail(IMEXHDG_E_STATE, "autotune needs a state");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+    int64_t nel = 0;
+    for (const MemberHost &h : c->mh) nel += h.nel;
+    std::ostringstream ks;
+    ks << prop.gcnArchName << "/" << prop.multiProcessorCount << "cu ensemble k="
+       << c->cfg.degree << " members=" << c->nm << " elements=" << nel
+       << " prec=" << c->cfg.precision;
+    const std::string key = ks.str();
+    int best_f = -1;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (in && std::getline(in, line)) {
+            const size_t t1 = line.find('\t');
+            if (t1 == std::string::npos || t1 != key.size() || line.compare(0, t1, key) != 0)
+                continue;
+            std::istringstream rest(line.substr(t1 + 1));
+            int f = 0;
+            if (!(rest >> f) || f < 8 || f > kMaxLaunchGrid)
+                return fail(IMEXHDG_E_INVAL, "malformed autotune cache line: " + line);
+            best_f = f;
+        }
+    }
+    if (best_f < 0) {
+        if (c->cold || !c->gready) {
+            int rc = step_ctx(c, 2);   // learn the schedule first
+            if (rc) return rc;
+        }
+        HIP_TRY(stream_sync(c));
+        HIP_TRY(hipMemcpyAsync(c->save, c->q, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->xsave, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+        const int64_t keep[6] = {c->steps, c->kiters, c->solves, c->sweeps, c->graph_steps,
+                                 c->redos};
+        const double keep_r[2] = {c->last_relres, c->max_relres};
+        const int cand[7] = {16, 32, 48, 64, 96, 128, 1024};
+        const int f0 = c->fgrid;
+        double best = 0.0, ms = 0.0;
+        int rc = ens_trial(c, f0, &ms);          // warm-up
+        if (!rc) rc = ens_trial(c, f0, &best);
+        best_f = f0;
+        for (int i = 0; i < 7 && !rc; ++i) {
+            if (cand[i] == best_f) continue;
+            if ((rc = ens_trial(c, cand[i], &ms))) break;
+            if (ms < 0.98 * best) {
+                best = ms;
+                best_f = cand[i];
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->x, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(stream_sync(c));
+        c->steps = keep[0];
+        c->kiters = keep[1];
+        c->solves = keep[2];
+        c->sweeps = keep[3];
+        c->graph_steps = keep[4];
+        c->redos = keep[5];
+        c->last_relres = keep_r[0];
+        c->max_relres = keep_r[1];
+        if (rc) {
+            (void)imexhdg_set_launch_geometry(c, f0, c->egrid);
+            return rc;
+        }
+        if (cache_path) {
+            std::ofstream out(cache_path, std::ios::app);
+            if (out) out << key << '\t' << best_f << '\n';
+        }
+    }
+    if (face_grid) *face_grid = best_f;
+    return imexhdg_set_launch_geometry(c, best_f, c->egrid);
+}
+
 int imexhdg_ens_workspace_bytes(const imexhdg_config *cfgs, int32_t n, size_t *bytes) {
     int rc = validate_batch(cfgs, n);
     if (rc) return rc;

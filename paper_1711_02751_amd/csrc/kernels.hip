@@ -77,7 +77,7 @@ __device__ __forceinline__ int member_of(const Batch &bt, int b, int &local) {
 __device__ __forceinline__ Member load_member(const Batch &bt, int i) {
     const cmember &c = ((const cmember *)bt.m)[i];
     Member r;
-    r.nx = c.nx; r.ny = c.ny; r.nel = c.nel; r.tiled = c.tiled;
+    r.nx = c.nx; r.ny = c.ny; r.nel = c.nel;
     r.sx = c.sx; r.sy = c.sy; r.area = c.area; r.dt = c.dt;
     r.vo = c.vo; r.to = c.to;
     r.bv = c.bv; r.nbv = c.nbv; r.bf = c.bf; r.nbf = c.nbf;
@@ -398,107 +398,6 @@ __global__ __launch_bounds__(64 * K) void k_linres(const double *__restrict__ Q,
     }
 }
 
-// ------------------------------------------------- local solver kernels
-// Z = A^-1 R per element: the shared (3K^2)-square inverse applied to every
-// element.  Thread (element, row j) produces the 3K outputs of node row j.
-template <int K>
-__global__ __launch_bounds__(64 * K) void k_local_apply(const double *__restrict__ R,
-                                                        const Batch bt,
-                                                        double *__restrict__ Z) {
-    constexpr int NL = 3 * K * K;
-    __shared__ double sR[NL][64];
-    const int lane = threadIdx.x & 63;
-    const int j = wave_id();
-    int lb;
-    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
-    R += mb.vo;
-    Z += mb.vo;
-    const double *Ainv = mb.Ainv;
-    const int e = lb * 64 + lane;
-    const bool active = e < mb.nel;
-    const size_t nel = mb.nel, NN = (size_t)K * K * nel;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-            sR[c * K * K + j * K + i][lane] =
-                active ? R[c * NN + (size_t)(j * K + i) * nel + e] : 0.0;
-    __syncthreads();
-    double acc[3][K];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < K; ++i) acc[c][i] = 0.0;
-    const cdouble *A = as_const(Ainv) + (size_t)(j * K) * NL;
-#pragma unroll 3
-    for (int col = 0; col < NL; ++col) {
-        const double r = sR[col][lane];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int i = 0; i < K; ++i)
-                acc[c][i] += A[(size_t)(c * K * K + i) * NL + col] * r;
-    }
-    if (!active) return;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < K; ++i) Z[c * NN + (size_t)(j * K + i) * nel + e] = acc[c][i];
-}
-
-// Q = Z - W Qhat_dK per element, W = A^-1 B (eq. recover_volume_unknowns).
-template <int K>
-__global__ __launch_bounds__(64 * K) void k_recover(const double *__restrict__ Z,
-                                                    const double *__restrict__ qh,
-                                                    const Batch bt, double *__restrict__ Q) {
-    constexpr int NT = 12 * K;
-    __shared__ double sT[NT][64];
-    const int lane = threadIdx.x & 63;
-    const int j = wave_id();
-    int lb;
-    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
-    Z += mb.vo;
-    qh += mb.to;
-    Q += mb.vo;
-    const double *W = mb.W;
-    const int e = lb * 64 + lane;
-    const bool active = e < mb.nel;
-    const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
-    const size_t nel = mb.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
-    // local trace t(f, c, j) = (f*3 + c)*K + j, faces W, E, S, N
-    const int face[4] = {nb.e, nb.east, nb.e, nb.north};
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            sT[(f * 3 + c) * K + j][lane] =
-                qh[(f >= 2 ? TT : 0) + (size_t)(c * K + j) * nel + face[f]];
-    __syncthreads();
-    double acc[3][K];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < K; ++i) acc[c][i] = 0.0;
-    const cdouble *Wr = as_const(W) + (size_t)(j * K) * NT;
-#pragma unroll 3
-    for (int col = 0; col < NT; ++col) {
-        const double t = sT[col][lane];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int i = 0; i < K; ++i)
-                acc[c][i] += Wr[(size_t)(c * K * K + i) * NT + col] * t;
-    }
-    if (!active) return;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const size_t o = c * NN + (size_t)(j * K + i) * nel + e;
-            Q[o] = Z[o] - acc[c][i];
-        }
-}
-
 // ---------------------------------------------------- trace kernels
 // Face tiles: tiles [0, nb) hold x-faces, [nb, 2 nb) y-faces, 64 faces
 // each; thread (face lane, node j).  Krylov kernels loop over tiles with a
@@ -517,31 +416,6 @@ __device__ __forceinline__ FaceIdx face_of_tile(int tile, int nel) {
     fi.active = fi.f < nel;
     if (!fi.active) fi.f = 0;
     return fi;
-}
-
-// Neighbour faces of the 7 slots of a face row block (see element.hpp).
-__device__ __forceinline__ void slot_faces(const FaceIdx &fi, int nx, int ny, int dir[7],
-                                           int idx[7]) {
-    const Nbr n = neighbours(fi.f, nx, ny);
-    if (fi.d == 0) {
-        const Nbr w = neighbours(n.west, nx, ny);
-        dir[0] = 0; idx[0] = n.e;
-        dir[1] = 0; idx[1] = n.east;
-        dir[2] = 1; idx[2] = n.e;
-        dir[3] = 1; idx[3] = n.north;
-        dir[4] = 0; idx[4] = n.west;
-        dir[5] = 1; idx[5] = n.west;
-        dir[6] = 1; idx[6] = w.north;
-    } else {
-        const Nbr s = neighbours(n.south, nx, ny);
-        dir[0] = 1; idx[0] = n.e;
-        dir[1] = 0; idx[1] = n.e;
-        dir[2] = 0; idx[2] = n.east;
-        dir[3] = 1; idx[3] = n.north;
-        dir[4] = 1; idx[4] = n.south;
-        dir[5] = 0; idx[5] = n.south;
-        dir[6] = 0; idx[6] = s.east;
-    }
 }
 
 // g = sum over the two elements of C_K Z_K = F_L(Z) . n_K + tau Z at the
@@ -643,6 +517,130 @@ template <int K> struct MF {
     static constexpr int NMB = (B3 + 15) / 16;     // 16-row blocks
 };
 
+// ------------------------------------------------- local solver kernels
+// Z = A^-1 R and Q = Z - W Qhat_dK (eq. recover_volume_unknowns) for every
+// element as matrix-core contractions: the shared matrix (A^-1, 3K^2 x 3K^2;
+// W = A^-1 B, 3K^2 x 12K) is the A operand, host-packed per lane as
+// frag[mb][kk][lane] = M[16 mb + lane % 16][4 kk + lane / 16] (zero past the
+// matrix); the B operand holds one element per column, 16 elements per wave,
+// 64 per block; k steps of 4 run over the matrix columns.
+template <int NR, int NC> struct LocalMF {
+    static constexpr int NMB = (NR + 15) / 16, KS = (NC + 3) / 4;
+};
+
+template <int K>
+__global__ __launch_bounds__(256) void k_local_apply(const double *__restrict__ R,
+                                                     const Batch bt, double *__restrict__ Z) {
+    constexpr int NL = 3 * K * K;
+    using LM = LocalMF<NL, NL>;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    R += mb.vo;
+    Z += mb.vo;
+    const double *__restrict__ A = mb.Ainv;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+    const int e = lb * 64 + w * 16 + (lane & 15);
+    const bool active = e < mb.nel;
+    const size_t nel = mb.nel, ec = active ? e : 0;
+    v4d acc[LM::NMB];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m) acc[m] = v4d{0, 0, 0, 0};
+    // B of k step kk: row 4 kk + q of R at this lane's element; the next
+    // step's B and A operands are loaded before this step's products
+    double b = q < NL ? R[(size_t)q * nel + ec] : 0.0;
+    double a[LM::NMB];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m) a[m] = A[(size_t)m * LM::KS * 64 + lane];
+#pragma unroll 2
+    for (int kk = 0; kk < LM::KS; ++kk) {
+        const int rn = 4 * (kk + 1) + q;
+        const bool more = kk + 1 < LM::KS;
+        const double bn = (more && rn < NL) ? R[(size_t)rn * nel + ec] : 0.0;
+        double an[LM::NMB];
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m)
+            an[m] = more ? A[((size_t)m * LM::KS + kk + 1) * 64 + lane] : 0.0;
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b, acc[m], 0, 0, 0);
+        b = bn;
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m) a[m] = an[m];
+    }
+    if (!active) return;
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * r + q;
+            if (row < NL) Z[(size_t)row * nel + e] = acc[m][r];
+        }
+}
+
+// Local trace t = (f 3 + c) K + j of the element's faces f = W (x-face e),
+// E (x-face east(e)), S (y-face e), N (y-face north(e)).
+template <int K>
+__device__ __forceinline__ double local_trace(const double *__restrict__ qh, const Nbr &nb,
+                                              int t, size_t nel) {
+    constexpr int NT = 12 * K;
+    if (t >= NT) return 0.0;
+    const int f = t / (3 * K), cj = t - f * 3 * K;
+    const int face = f == 1 ? nb.east : f == 3 ? nb.north : nb.e;
+    return qh[(f >= 2 ? (size_t)3 * K * nel : 0) + (size_t)cj * nel + face];
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_recover(const double *__restrict__ Z,
+                                                 const double *__restrict__ qh,
+                                                 const Batch bt, double *__restrict__ Q) {
+    constexpr int NL = 3 * K * K, NT = 12 * K;
+    using LM = LocalMF<NL, NT>;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    Z += mb.vo;
+    qh += mb.to;
+    Q += mb.vo;
+    const double *__restrict__ Wf = mb.W;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+    const int e = lb * 64 + w * 16 + (lane & 15);
+    const bool active = e < mb.nel;
+    const size_t nel = mb.nel;
+    const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
+    v4d acc[LM::NMB];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m) acc[m] = v4d{0, 0, 0, 0};
+    double b = local_trace<K>(qh, nb, q, nel);
+    double a[LM::NMB];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m) a[m] = Wf[(size_t)m * LM::KS * 64 + lane];
+#pragma unroll 2
+    for (int kk = 0; kk < LM::KS; ++kk) {
+        const bool more = kk + 1 < LM::KS;
+        const double bn = more ? local_trace<K>(qh, nb, 4 * (kk + 1) + q, nel) : 0.0;
+        double an[LM::NMB];
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m)
+            an[m] = more ? Wf[((size_t)m * LM::KS + kk + 1) * 64 + lane] : 0.0;
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b, acc[m], 0, 0, 0);
+        b = bn;
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m) a[m] = an[m];
+    }
+    if (!active) return;
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * r + q;
+            if (row < NL) {
+                const size_t o = (size_t)row * nel + e;
+                Q[o] = Z[o] - acc[m][r];
+            }
+        }
+}
+
 // Workgroups per CU the matrix-core kernels are compiled for (8 waves
 // each): the register budget that keeps them free of scratch spills.
 template <int K> struct MFOcc {
@@ -684,7 +682,7 @@ typedef FragMatsT<double> FragMats;
 // elements in row w % 4 of the tile, so every wave runs one accumulation
 // chain and the two sets proceed in parallel.
 constexpr int kFaceThreads = 512;
-constexpr int kTX = 16, kTY = 4;     // element tile of a tiled mesh (below)
+constexpr int kTX = 16, kTY = 4;     // element tile (below)
 
 struct WaveFaces {
     int set, sub;            // face set (wave-uniform), tile row
@@ -692,22 +690,20 @@ struct WaveFaces {
     bool active;             // e < nel
 };
 
-template <bool TILED>
+// Tiles of 16 x 4 elements cover the mesh (partial tiles at the high
+// edges, their lanes past the mesh inactive).
+__device__ __forceinline__ int tiles_per_row(const Member &g) { return (g.nx + kTX - 1) / kTX; }
+
 __device__ __forceinline__ WaveFaces wave_faces(int tile, const Member &g) {
     WaveFaces wf;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     wf.set = w >> 2;
     wf.sub = w & 3;
-    if constexpr (TILED) {
-        const int tpr = g.nx / kTX;
-        wf.e = ((tile / tpr) * kTY + wf.sub) * g.nx + (tile % tpr) * kTX + (lane & 15);
-        wf.active = true;
-    } else {
-        const int e = tile * 64 + wf.sub * 16 + (lane & 15);
-        wf.active = e < g.nel;
-        wf.e = wf.active ? e : 0;
-    }
+    const int tpr = tiles_per_row(g);
+    const int ex = (tile % tpr) * kTX + (lane & 15), ey = (tile / tpr) * kTY + wf.sub;
+    wf.active = ex < g.nx && ey < g.ny;
+    wf.e = wf.active ? ey * g.nx + ex : 0;
     return wf;
 }
 
@@ -755,12 +751,13 @@ __device__ __forceinline__ void zero_acc(typename MfmaT<T>::v4 (&acc)[NM][MF<K>:
 }
 
 // ------------------------------------- LDS-staged tiles of 16 x 4 elements
-// When the mesh is a whole number of 16 x 4 element tiles, a workgroup
-// stages once into LDS every trace face its tile's row blocks read (the
-// union over the 7 slots of the x- and y-faces of its 64 elements: 18 x 5
-// x-faces and 17 x 6 y-faces), with coalesced loads of whole face rows, and
-// the matrix cores read their B operands from LDS.  Each trace value then
-// crosses L2 about 1.5 times per launch instead of 7.
+// A workgroup stages once into LDS every trace face its tile's row blocks
+// read (the union over the 7 slots of the x- and y-faces of its 64
+// elements: 18 x 5 x-faces and 17 x 6 y-faces), with coalesced loads of
+// whole face rows, and the matrix cores read their B operands from LDS.
+// Each trace value then crosses L2 about 1.5 times per launch instead of 7.
+// Tiles past the mesh edge are partial: their positions wrap periodically
+// and their lanes outside the mesh store nothing.
 
 template <int K> struct Tile {
     static constexpr int B3 = 3 * K;
@@ -777,9 +774,15 @@ __device__ __forceinline__ void staged_face(int f, int ex0, int ey0, int nx, int
     int r, c;
     if (f < NX) { dir = 0; r = f / XC; c = f % XC; }
     else { dir = 1; r = (f - NX) / YC; c = (f - NX) % YC; }
-    const int ex = (ex0 - 1 + c + nx) % nx, ey = (ey0 - 1 + r + ny) % ny;
+    // positions past the mesh wrap periodically (a tile wider than the mesh
+    // stages a face more than once); only positions of the tile's own
+    // elements inside the mesh own their face
+    const int gx = ex0 - 1 + c, gy = ey0 - 1 + r;
+    int ex = gx < 0 ? gx + nx : gx, ey = gy < 0 ? gy + ny : gy;
+    if (ex >= nx) ex = ex - nx < nx ? ex - nx : ex % nx;   // the modulo only on meshes
+    if (ey >= ny) ey = ey - ny < ny ? ey - ny : ey % ny;   // narrower than a tile
     elem = ey * nx + ex;
-    own = r >= 1 && r <= kTY && c >= 1 && c <= kTX;
+    own = r >= 1 && r <= kTY && c >= 1 && c <= kTX && gx < nx && gy < ny;
 }
 
 // LDS face index of slot `s` of face set `set` for tile element (lx, ly).
@@ -822,7 +825,7 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
     using TL = Tile<K>;
     constexpr int NV = TL::B3 * TL::NF, PER = (NV + kFaceThreads - 1) / kFaceThreads;
     constexpr int CH = PER < 8 ? PER : 8;
-    const int tpr = g.nx / kTX;
+    const int tpr = tiles_per_row(g);
     const int ex0 = (tile % tpr) * kTX, ey0 = (tile / tpr) * kTY;
     const uint32_t nel = g.nel, TT = TL::B3 * nel;
 #pragma unroll
@@ -895,116 +898,26 @@ __device__ __forceinline__ int own_lds(const WaveFaces &wf) {
                        : TL::NX + (wf.sub + 1) * TL::YC + (lx + 1);
 }
 
-// Without tiles: this wave's row blocks with B operands gathered from
-// global memory, slot by slot; the raw values of slot s + 1 and the A
-// operands of slot s + 1 are loaded while slot s is computed.  Slot 0 is
-// the face itself, whose combined value comb may store.
+// Row blocks of this wave for one tile: stage, then contract from LDS.
 template <int K, int NM, typename T, int NA, typename Comb>
-__device__ __forceinline__ void gather_rows(const T *__restrict__ const *frags, const Member &g,
-                                            const WaveFaces &wf,
-                                            const T *__restrict__ const (&src)[NA], Comb comb,
-                                            typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
-    constexpr int B3 = MF<K>::B3, KS = MF<K>::KS, NMB = MF<K>::NMB;
-    constexpr bool PF = FragPrefetch<K, NM, T>::value;
-    const int lane = threadIdx.x & 63, q = lane >> 4;
-    const uint32_t nel = g.nel, TT = (uint32_t)B3 * nel;
-    FaceIdx fi;
-    fi.d = wf.set;
-    fi.f = wf.e;
-    fi.active = wf.active;
-    int dirs[7], idx[7];
-    slot_faces(fi, g.nx, g.ny, dirs, idx);
-    zero_acc<K, NM, T>(acc);
-    // slot s is uniform over the wave: the switch selects its neighbour face
-    // with scalar branches (no indexed register arrays)
-    auto fetch = [&](int s, T (&raw)[KS][NA], uint32_t (&off)[KS]) {
-        int dd = dirs[0], ii = idx[0];
-        switch (s) {
-            case 1: dd = dirs[1]; ii = idx[1]; break;
-            case 2: dd = dirs[2]; ii = idx[2]; break;
-            case 3: dd = dirs[3]; ii = idx[3]; break;
-            case 4: dd = dirs[4]; ii = idx[4]; break;
-            case 5: dd = dirs[5]; ii = idx[5]; break;
-            case 6: dd = dirs[6]; ii = idx[6]; break;
-            default: break;
-        }
-        const uint32_t base = (uint32_t)dd * TT + (uint32_t)ii;
-#pragma unroll
-        for (int u = 0; u < KS; ++u) {
-            const int cj = 4 * u + q;
-            off[u] = base + (uint32_t)cj * nel;
-#pragma unroll
-            for (int a = 0; a < NA; ++a) raw[u][a] = (cj < B3) ? src[a][off[u]] : T(0);
-        }
-    };
-    T raw[KS][NA], rawn[KS][NA];
-    uint32_t off[KS], offn[KS];
-    FragSlot<K, NM, T> cur, nxt;
-    fetch(0, raw, off);
-    if (PF) load_frags<K, NM, T>(frags, wf.set, 0, cur);
-#pragma unroll 1
-    for (int s = 0; s < 7; ++s) {
-        if (s + 1 < 7) {
-            fetch(s + 1, rawn, offn);
-            if (PF) load_frags<K, NM, T>(frags, wf.set, s + 1, nxt);
-        }
-        if (!PF) load_frags<K, NM, T>(frags, wf.set, s, cur);
-#pragma unroll
-        for (int u = 0; u < KS; ++u) {
-            const int cj = 4 * u + q;
-            const T b = (cj < B3) ? comb(raw[u], off[u], s == 0 && wf.active) : T(0);
-#pragma unroll
-            for (int m = 0; m < NM; ++m)
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb)
-                    acc[m][mb] = MfmaT<T>::mma(cur.v[m][mb][u], b, acc[m][mb]);
-        }
-#pragma unroll
-        for (int u = 0; u < KS; ++u) {
-            off[u] = offn[u];
-#pragma unroll
-            for (int a = 0; a < NA; ++a) raw[u][a] = rawn[u][a];
-        }
-        if (PF) cur = nxt;
-    }
-}
-
-// Row blocks of this wave for one tile, staged (TILED) or gathered.
-template <int K, int NM, bool TILED, typename T, int NA, typename Comb>
 __device__ __forceinline__ void face_rows(const T *__restrict__ const *frags, int tile,
                                           const Member &g, const WaveFaces &wf, T *sB,
                                           const T *__restrict__ const (&src)[NA], Comb comb,
                                           typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
-    if constexpr (TILED) {
-        __syncthreads();   // the previous tile's LDS reads are done
-        stage_tile<K, T, NA>(tile, g, sB, src, comb);
-        __syncthreads();
-        tile_rows<K, NM, T>(frags, sB, wf, acc);
-    } else {
-        gather_rows<K, NM, T, NA>(frags, g, wf, src, comb, acc);
-    }
+    __syncthreads();   // the previous tile's LDS reads are done
+    stage_tile<K, T, NA>(tile, g, sB, src, comb);
+    __syncthreads();
+    tile_rows<K, NM, T>(frags, sB, wf, acc);
 }
 
-template <bool TILED>
 __device__ __forceinline__ int face_tiles(const Member &g) {
-    return TILED ? (g.nx / kTX) * (g.ny / kTY) : (g.nel + 63) / 64;
+    return tiles_per_row(g) * ((g.ny + kTY - 1) / kTY);
 }
 
-// LDS of a staged tile (unused without tiles).
+// LDS of a staged tile.
 template <int K, typename T> struct TileLds {
     static constexpr int n = MF<K>::B3 * Tile<K>::NF;
 };
-
-template <bool B> struct Tiled {
-    static constexpr bool value = B;
-};
-
-// Run body(Tiled<...>{}) with the member's tiling as a compile-time value.
-template <typename Body>
-__device__ __forceinline__ void with_tiling(const Member &mb, Body body) {
-    if (mb.tiled) body(Tiled<true>{});
-    else body(Tiled<false>{});
-}
 
 // FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
 // partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
@@ -1025,11 +938,10 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
     const double *fr[2] = {mb.G, mb.Gh};
     const double *src[1] = {x};
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-    with_tiling(mb, [&](auto tl) {
-        constexpr bool TILED = decltype(tl)::value;
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles<TILED>(mb));
+    {
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            const WaveFaces wf = wave_faces<TILED>(tile, mb);
+            const WaveFaces wf = wave_faces(tile, mb);
             // right-hand sides at the own rows, loaded ahead of the contraction
             double gvv[NMB][4], ghv[NMB][4];
             uint32_t o[NMB][4];
@@ -1043,7 +955,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
                     ghv[m][e4] = ok[m][e4] ? gh[o[m][e4]] : 0.0;
                 }
             v4d acc[2][NMB];
-            face_rows<K, 2, TILED>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 2>(fr, tile, mb, wf, sB, src,
                                    [](const double (&a)[1], uint32_t, bool) { return a[0]; },
                                    acc);
 #pragma unroll
@@ -1061,7 +973,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
                         acc4[3] += ri * ri;
                     }
         }
-    });
+    }
     store_partials<4>(acc4, partials, stride);
 }
 
@@ -1125,6 +1037,7 @@ __global__ void k_bicg_init(const Batch bt, int K, const T *__restrict__ rin,
         ks->alpha = 1.0;
         ks->omega = 1.0;
         ks->rr = 0.0;
+        ks->rv = 0.0;
         ks->tol2 = tol2;
         ks->conv = 0;
         ks->breakdown = 0;
@@ -1136,6 +1049,10 @@ __global__ void k_bicg_init(const Batch bt, int K, const T *__restrict__ rin,
 __device__ __forceinline__ const double *ghat_frags(const Member &mb, double) { return mb.Gh; }
 __device__ __forceinline__ const float *ghat_frags(const Member &mb, float) { return mb.Ghf; }
 
+// First K1 of an inner solve (after init or a refinement check): beta
+// from rh.r and r.r [partials P3 of the elementwise class]; p <- r + beta
+// (p - omega v) at the seven faces of each row block (p = v = 0 here), v =
+// Ghat p; partials P1 = (rh.v, rh.r, r.r) over the own faces.
 template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const Batch bt, const T *__restrict__ r, const T *__restrict__ rh,
@@ -1146,9 +1063,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
+    if (ks->conv) return;
     double red[2];
     reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red);
-    if (ks->conv) return;
     const double rho_new = red[0], rr = red[1];
     const double rho = ks->rho, alpha = ks->alpha, omega = ks->omega;
     if (rr <= ks->tol2 || rho_new == 0.0 || omega == 0.0 || !isfinite(rr)) {
@@ -1165,13 +1082,12 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const uint32_t nel = mb.nel;
     const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[3] = {r, pin, vin};
-    double acc1[1] = {0.0};
-    with_tiling(mb, [&](auto tl) {
-        constexpr bool TILED = decltype(tl)::value;
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles<TILED>(mb));
+    double acc1[3] = {0.0, 0.0, 0.0};
+    {
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            const WaveFaces wf = wave_faces<TILED>(tile, mb);
-            T rhv[NMB][4];
+            const WaveFaces wf = wave_faces(tile, mb);
+            T rhv[NMB][4], rv[NMB][4];
             uint32_t o[NMB][4];
             bool ok[NMB][4];
 #pragma unroll
@@ -1180,9 +1096,10 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
                     rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
+                    rv[m][e4] = ok[m][e4] ? r[o[m][e4]] : T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            face_rows<K, 1, TILED>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 1>(fr, tile, mb, wf, sB, src,
                                    [&](const T (&a)[3], uint32_t off, bool own) {
                                        const T p = a[0] + beta * (a[1] - om * a[2]);
                                        if (own) pout[off] = p;
@@ -1195,70 +1112,76 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                 for (int e4 = 0; e4 < 4; ++e4)
                     if (ok[m][e4]) {
                         const double y = acc[0][m][e4];
+                        const double rhd = rhv[m][e4], rd = rv[m][e4];
                         vout[o[m][e4]] = (T)y;
-                        acc1[0] += (double)rhv[m][e4] * y;
+                        acc1[0] += rhd * y;
+                        acc1[1] += rhd * rd;
+                        acc1[2] += rd * rd;
                     }
         }
-    });
-    store_partials<1>(acc1, P1, stride);
+    }
+    store_partials<3>(acc1, P1, stride);
     if (lb == 0 && threadIdx.x == 0) ks->rr = rr;
 }
 
+// K2: rho = rh.r, rr = r.r and rv = rh.v from partials P1 (exact dot
+// products of the last K1); stop when rr <= tol2; alpha = rho / rv;
+// s = r - alpha v at the seven faces, t = Ghat s; partials P2 = (t.s, t.t,
+// rh.t) over the own faces.
 template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
-    const Batch bt, const T *__restrict__ r, const T *__restrict__ v, T *__restrict__ sv,
-    T *__restrict__ t, KrylovState *ks_all, const double *P1, const double *P3, double *P2,
-    int stride) {
+    const Batch bt, const T *__restrict__ r, const T *__restrict__ v,
+    const T *__restrict__ rh, T *__restrict__ sv, T *__restrict__ t, KrylovState *ks_all,
+    const double *P1, double *P2, int stride) {
     constexpr int NMB = MF<K>::NMB;
     int lb;
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
-    double red1[1], red3[2];
-    reduce_partials<1>(P1 + mb.bf, stride, mb.nbf, red1);
-    reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red3);
     if (ks->conv) return;
-    const double rv = red1[0], rho_new = red3[0];
-    if (rv == 0.0 || !isfinite(rv)) {
+    double red1[3];
+    reduce_partials<3>(P1 + mb.bf, stride, mb.nbf, red1);
+    const double rv = red1[0], rho = red1[1], rr = red1[2];
+    if (rr <= ks->tol2 || !isfinite(rr) || rv == 0.0 || !isfinite(rv)) {
         if (lb == 0 && threadIdx.x == 0) {
-            ks->breakdown = 1;
+            ks->rr = rr;
+            ks->breakdown = (rr <= ks->tol2) ? 0 : 1;
             ks->conv = 1;
         }
         return;
     }
-    const double alpha = rho_new / rv;
+    const double alpha = rho / rv;
     const T al = (T)alpha;
-    r += mb.to; v += mb.to; sv += mb.to; t += mb.to;
+    r += mb.to; v += mb.to; rh += mb.to; sv += mb.to; t += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
     const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[2] = {r, v};
-    double acc2[2] = {0.0, 0.0};
-    with_tiling(mb, [&](auto tl) {
-        constexpr bool TILED = decltype(tl)::value;
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles<TILED>(mb));
+    double acc2[3] = {0.0, 0.0, 0.0};
+    {
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            const WaveFaces wf = wave_faces<TILED>(tile, mb);
+            const WaveFaces wf = wave_faces(tile, mb);
             uint32_t o[NMB][4];
             bool ok[NMB][4];
-            T sown[NMB][4];
+            T sown[NMB][4], rhv[NMB][4];
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
-                    if constexpr (!TILED)
-                        sown[m][e4] = ok[m][e4] ? r[o[m][e4]] - al * v[o[m][e4]] : T(0);
+                    rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
+                    sown[m][e4] = T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            face_rows<K, 1, TILED>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 1>(fr, tile, mb, wf, sB, src,
                                    [&](const T (&a)[2], uint32_t off, bool own) {
                                        const T sval = a[0] - al * a[1];
                                        if (own) sv[off] = sval;
                                        return sval;
                                    },
                                    acc);
-            if constexpr (TILED) {
+            {
                 const int li = own_lds<K>(wf);
 #pragma unroll
                 for (int m = 0; m < NMB; ++m)
@@ -1278,64 +1201,122 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                         t[o[m][e4]] = (T)y;
                         acc2[0] += y * sval;
                         acc2[1] += y * y;
+                        acc2[2] += (double)rhv[m][e4] * y;
                     }
         }
-    });
-    store_partials<2>(acc2, P2, stride);
+    }
+    store_partials<3>(acc2, P2, stride);
     if (lb == 0 && threadIdx.x == 0) {
-        ks->rho = rho_new;
+        ks->rho = rho;
         ks->alpha = alpha;
+        ks->rv = rv;
+        ks->rr = rr;
     }
 }
 
-template <typename T>
-__global__ void k_bicg_k3(const Batch bt, int K, T *__restrict__ d, T *__restrict__ r,
-                          const T *__restrict__ rh, const T *__restrict__ p,
-                          const T *__restrict__ sv, const T *__restrict__ t,
-                          KrylovState *ks_all, const double *P2, double *P3, int stride) {
+// K1 of the next iteration fused with the d and r updates of this one:
+//   omega = (t.s)/(t.t) and rh.t from partials P2 of K2;
+//   rho' = rh.(s - omega t) = (rho - alpha rv) - omega rh.t;
+//   beta = (rho'/rho)(alpha/omega);
+//   r' = s - omega t, p' = r' + beta (p - omega v) at the seven faces of
+//   each row block, v' = Ghat p';  d += alpha p + omega s, r', p', v' stored
+//   at the own faces;  partials P1 = (rh.v', rh.r', r'.r').
+// On breakdown (omega or rho' zero or not finite) the d and r updates still
+// complete the iteration, and the solve stops.
+template <int K, typename T, bool SCHED>
+__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
+    const Batch bt, const T *__restrict__ sv, const T *__restrict__ t,
+    const T *__restrict__ rh, const T *__restrict__ pin, const T *__restrict__ vin,
+    T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ r, T *__restrict__ d,
+    KrylovState *ks_all, const double *P2, double *P1, int stride) {
+    constexpr int NMB = MF<K>::NMB;
     int lb;
-    const int mi = member_of<CE>(bt, blockIdx.x, lb);
+    const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
-    double red[2];
-    reduce_partials<2>(P2 + mb.bf, stride, mb.nbf, red);
     if (ks->conv) return;
-    const double omega = red[1] > 0.0 ? red[0] / red[1] : 0.0;
-    const double alpha = ks->alpha;
-    d += mb.to; r += mb.to; rh += mb.to; p += mb.to; sv += mb.to; t += mb.to;
-    double acc[2] = {0.0, 0.0};
-    constexpr int U = 4;
-    const ElemRange er = elem_range(mb, lb, K);
-    const size_t bd = blockDim.x;
-    for (size_t i0 = er.i0; i0 < er.n; i0 += er.span) {
-        T dv[U], pv[U], sval[U], tv[U], rhv[U];
+    double red[3];
+    reduce_partials<3>(P2 + mb.bf, stride, mb.nbf, red);
+    const double ts = red[0], tt = red[1], rht = red[2];
+    const double omega = tt > 0.0 ? ts / tt : 0.0;
+    const double rho = ks->rho, alpha = ks->alpha, rvv = ks->rv;
+    const double rho_new = (rho - alpha * rvv) - omega * rht;
+    const bool brk = !(omega != 0.0) || !isfinite(omega) || !(rho_new != 0.0) ||
+                     !isfinite(rho_new);
+    const double beta = brk ? 0.0 : (rho_new / rho) * (alpha / omega);
+    const T be = (T)beta, om = (T)omega;
+    sv += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
+    pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
+    __shared__ T sB[TileLds<K, T>::n];
+    const uint32_t nel = mb.nel;
+    const T *fr[1] = {ghat_frags(mb, T(0))};
+    const T *src[4] = {sv, t, pin, vin};
+    auto rnew = [&](T s_, T t_) { return (T)((double)s_ - omega * (double)t_); };
+    auto pnew = [&](T r_, T p_, T v_) { return r_ + be * (p_ - om * v_); };
+    double acc1[3] = {0.0, 0.0, 0.0};
+    {
+        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+        for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            const WaveFaces wf = wave_faces(tile, mb);
+            T rhv[NMB][4];
+            uint32_t o[NMB][4];
+            bool ok[NMB][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t i = i0 + u * bd;
-            const bool ok = i < er.n;
-            dv[u] = ok ? d[i] : T(0);
-            pv[u] = ok ? p[i] : T(0);
-            sval[u] = ok ? sv[i] : T(0);
-            tv[u] = ok ? t[i] : T(0);
-            rhv[u] = ok ? rh[i] : T(0);
-        }
+            for (int m = 0; m < NMB; ++m)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t i = i0 + u * bd;
-            if (i < er.n) {
-                const double si = sval[u];
-                d[i] = (T)((double)dv[u] + alpha * (double)pv[u] + omega * si);
-                const double rr = si - omega * (double)tv[u];
-                r[i] = (T)rr;
-                acc[0] += rhv[u] * rr;
-                acc[1] += rr * rr;
-            }
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
+                    rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
+                }
+            typename MfmaT<T>::v4 acc[1][NMB];
+            face_rows<K, 1>(fr, tile, mb, wf, sB, src,
+                                   [&](const T (&a)[4], uint32_t, bool) {
+                                       return pnew(rnew(a[0], a[1]), a[2], a[3]);
+                                   },
+                                   acc);
+            // own faces: all loads first, then the updates
+            T sv_[NMB][4], tv_[NMB][4], pv_[NMB][4], vv_[NMB][4], dv_[NMB][4];
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    const bool k_ = ok[m][e4];
+                    const uint32_t oo = o[m][e4];
+                    sv_[m][e4] = k_ ? sv[oo] : T(0);
+                    tv_[m][e4] = k_ ? t[oo] : T(0);
+                    pv_[m][e4] = k_ ? pin[oo] : T(0);
+                    vv_[m][e4] = k_ ? vin[oo] : T(0);
+                    dv_[m][e4] = k_ ? d[oo] : T(0);
+                }
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4)
+                    if (ok[m][e4]) {
+                        const uint32_t oo = o[m][e4];
+                        const T rn = rnew(sv_[m][e4], tv_[m][e4]);
+                        const T pn = pnew(rn, pv_[m][e4], vv_[m][e4]);
+                        d[oo] = (T)((double)dv_[m][e4] + alpha * (double)pv_[m][e4] +
+                                    omega * (double)sv_[m][e4]);
+                        r[oo] = rn;
+                        pout[oo] = pn;
+                        const double y = acc[0][m][e4];
+                        const double rhd = rhv[m][e4], rd = rn;
+                        vout[oo] = (T)y;
+                        acc1[0] += rhd * y;
+                        acc1[1] += rhd * rd;
+                        acc1[2] += rd * rd;
+                    }
         }
     }
-    store_partials<2>(acc, P3, stride);
+    store_partials<3>(acc1, P1, stride);
     if (lb == 0 && threadIdx.x == 0) {
         ks->omega = omega;
         ks->iters += 1;
+        if (brk) {
+            ks->breakdown = 1;
+            ks->conv = 1;
+        }
     }
 }
 
@@ -1420,6 +1401,7 @@ __global__ void k_refine_check(const Batch bt, int K, const T *__restrict__ rin,
         ks->alpha = 1.0;
         ks->omega = 1.0;
         ks->rr = 0.0;
+        ks->rv = 0.0;
         ks->tol2 = tol2;
         ks->conv = 0;
         ks->breakdown = 0;
@@ -1552,14 +1534,14 @@ template <int K> struct RunLinres {
 };
 template <int K> struct RunLocal {
     static hipError_t run(const Batch &b, const double *R, double *Z, hipStream_t s) {
-        hipLaunchKernelGGL(k_local_apply<K>, dim3(b.nbv), dim3(64 * K), 0, s, R, b, Z);
+        hipLaunchKernelGGL(k_local_apply<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
         return hipGetLastError();
     }
 };
 template <int K> struct RunRecover {
     static hipError_t run(const Batch &b, const double *Z, const double *qh, double *Q,
                           hipStream_t s) {
-        hipLaunchKernelGGL(k_recover<K>, dim3(b.nbv), dim3(64 * K), 0, s, Z, qh, b, Q);
+        hipLaunchKernelGGL(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q);
         return hipGetLastError();
     }
 };
@@ -1600,14 +1582,31 @@ template <typename T> struct RunK1 {
 };
 template <typename T> struct RunK2 {
     template <int K> struct F {
-        static hipError_t run(const Batch &b, const T *r, const T *v, T *sv, T *t,
-                              KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+        static hipError_t run(const Batch &b, const T *r, const T *v, const T *rh, T *sv,
+                              T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             if (kb.sched)
                 hipLaunchKernelGGL((k_bicg_k2<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, v, sv, t, ks, kb.P1, kb.P3, kb.P2, kb.stride);
+                                   s, b, r, v, rh, sv, t, ks, kb.P1, kb.P2, kb.stride);
             else
                 hipLaunchKernelGGL((k_bicg_k2<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, v, sv, t, ks, kb.P1, kb.P3, kb.P2, kb.stride);
+                                   s, b, r, v, rh, sv, t, ks, kb.P1, kb.P2, kb.stride);
+            return hipGetLastError();
+        }
+    };
+};
+template <typename T> struct RunK1F {
+    template <int K> struct F {
+        static hipError_t run(const Batch &b, const T *sv, const T *t, const T *rh,
+                              const T *pin, const T *vin, T *pout, T *vout, T *r, T *d,
+                              KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+            if (kb.sched)
+                hipLaunchKernelGGL((k_bicg_k1f<K, T, true>), dim3(b.nbf), dim3(kFaceThreads),
+                                   0, s, b, sv, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
+                                   kb.P1, kb.stride);
+            else
+                hipLaunchKernelGGL((k_bicg_k1f<K, T, false>), dim3(b.nbf), dim3(kFaceThreads),
+                                   0, s, b, sv, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
+                                   kb.P1, kb.stride);
             return hipGetLastError();
         }
     };
@@ -1623,10 +1622,7 @@ template <int K> struct RunDiag {
 
 }  // namespace
 
-int member_tiles(int nx, int ny) {
-    return (nx % kTX == 0 && ny % kTY == 0) ? (nx / kTX) * (ny / kTY)
-                                              : (int)grid1((size_t)nx * ny, 64);
-}
+int member_tiles(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
 
 int member_face_blocks(int nx, int ny, int fgrid) {
     // a multiple of 8 blocks when there are enough tiles, so that every XCD
@@ -1695,16 +1691,17 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
         return dispatch<RunK1<T>::template F>(g.K, b, r, rh, pin, vin, pout, vout, ks, kb,    \
                                               s);                                             \
     }                                                                                          \
-    hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v, T *sv,   \
-                              T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {   \
-        return dispatch<RunK2<T>::template F>(g.K, b, r, v, sv, t, ks, kb, s);                \
-    }                                                                                          \
-    hipError_t launch_bicg_k3(const Geom &g, const Batch &b, T *d, T *r, const T *rh,         \
-                              const T *p, const T *sv, const T *t, KrylovState *ks,           \
+    hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v,          \
+                              const T *rh, T *sv, T *t, KrylovState *ks,                      \
                               const KrylovBufs &kb, hipStream_t s) {                          \
-        hipLaunchKernelGGL(k_bicg_k3<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, d, r, rh, p,   \
-                           sv, t, ks, kb.P2, kb.P3, kb.stride);                               \
-        return hipGetLastError();                                                              \
+        return dispatch<RunK2<T>::template F>(g.K, b, r, v, rh, sv, t, ks, kb, s);            \
+    }                                                                                          \
+    hipError_t launch_bicg_k1f(const Geom &g, const Batch &b, const T *sv, const T *t,        \
+                               const T *rh, const T *pin, const T *vin, T *pout, T *vout,     \
+                               T *r, T *d, KrylovState *ks, const KrylovBufs &kb,             \
+                               hipStream_t s) {                                               \
+        return dispatch<RunK1F<T>::template F>(g.K, b, sv, t, rh, pin, vin, pout, vout, r, d, \
+                                               ks, kb, s);                                    \
     }                                                                                          \
     hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s) {        \
         hipLaunchKernelGGL(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);     \

@@ -29,7 +29,7 @@ struct Geom {
 // One member: its mesh, its slices of the concatenated arrays, its element
 // operators and its block ranges in the four launch classes.
 struct Member {
-    int nx, ny, nel, tiled;     // tiled: nx % 16 == 0 and ny % 4 == 0
+    int nx, ny, nel;
     double sx, sy;              // 2/hx, 2/hy
     double area;                // hx hy / 4: the mass of node (i, j) is area w_i w_j
     double dt;                  // time step (scales the NL residual of a step)
@@ -38,7 +38,9 @@ struct Member {
     int bf, nbf;                // face class: blocks walking 64-element tiles
     int be, nbe;                // elementwise trace class: grid-stride blocks
     int bd, nbd;                // diagnostics class
-    const double *Ainv, *W, *G, *Gh, *Px, *Py;   // element operators (packed fragments)
+    // element operators: A^-1 and W as local matrix-core fragments, G and
+    // Ghat as face row-block fragments, the block-Jacobi inverses dense
+    const double *Ainv, *W, *G, *Gh, *Px, *Py;
     const float *Ghf;                            // FP32 Ghat fragments
 };
 
@@ -68,7 +70,8 @@ struct Comb {
 // only by later kernels.
 struct KrylovState {
     double rho, alpha, omega;   // rho = rh.r of the last K2, alpha, omega
-    double rr;                  // last ||r||^2 seen by K1
+    double rv;                  // rh.v of the last K2
+    double rr;                  // last ||r||^2 seen by K1 or K2
     double tol2;                // stop when ||r||^2 <= tol2
     int32_t conv, breakdown, iters, pad;
     // device-driven refinement of one stage solve (fixed launch schedule)
@@ -86,7 +89,9 @@ struct StageStatus {
     int32_t sweep_iters[kMaxSweeps];
 };
 
-// Per-block partial sums of the three BiCGStab reductions, [quantity][block].
+// Per-block partial sums of the BiCGStab reductions, [quantity][block]:
+// P1 (rh.v, rh.r, r.r) of K1 / K1f, P2 (t.s, t.t, rh.t) of K2, P3 (rh.r,
+// r.r) of init / refinement check.
 struct KrylovBufs {
     double *P1, *P2, *P3;
     int stride;                 // >= blocks of any partial-producing class
@@ -95,7 +100,7 @@ struct KrylovBufs {
 };
 
 // Block counts of one member (host side), for grid caps fgrid / egrid.
-int member_tiles(int nx, int ny);                     // 64-element tiles
+int member_tiles(int nx, int ny);                     // 16 x 4 element tiles
 int member_face_blocks(int nx, int ny, int fgrid);    // min(tiles, fgrid), multiple of 8
 int member_elem_blocks(int nel, int K, int egrid);
 int member_vol_blocks(int nel);
@@ -118,9 +123,10 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 // FP64 r = g - G x and rin = ghat - Ghat x (stored in the inner solve's
 // precision); partials [4][face blocks] of ||r||^2, ||g||^2, ||ghat||^2,
 // ||rin||^2.  With `skip`, members whose stage solve is done return.
-// BiCGStab on Ghat d = rin with d0 = 0: init, then per iteration K1, K2,
-// K3; x += d after the sweep.  Each exists for an FP64 and an FP32 inner
-// solve (matrix-core fragments in the same precision).
+// BiCGStab on Ghat d = rin with d0 = 0: init and K1, then per iteration
+// K2 and K1f (the next K1 fused with this iteration's d and r updates);
+// x += d after the sweep.  Each exists for an FP64 and an FP32 inner solve
+// (matrix-core fragments in the same precision).
 #define IMEXHDG_KRYLOV_DECLS(T)                                                                \
     hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
                                      const double *gvec, const double *ghat, double *r,       \
@@ -132,11 +138,13 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
     hipError_t launch_bicg_k1(const Geom &g, const Batch &b, const T *r, const T *rh,         \
                               const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,  \
                               const KrylovBufs &kb, hipStream_t s);                           \
-    hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v, T *sv,   \
-                              T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s);    \
-    hipError_t launch_bicg_k3(const Geom &g, const Batch &b, T *d, T *r, const T *rh,         \
-                              const T *p, const T *sv, const T *t, KrylovState *ks,           \
+    hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v,          \
+                              const T *rh, T *sv, T *t, KrylovState *ks,                      \
                               const KrylovBufs &kb, hipStream_t s);                           \
+    hipError_t launch_bicg_k1f(const Geom &g, const Batch &b, const T *sv, const T *t,        \
+                               const T *rh, const T *pin, const T *vin, T *pout, T *vout,     \
+                               T *r, T *d, KrylovState *ks, const KrylovBufs &kb,             \
+                               hipStream_t s);                                                \
     hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s);
 IMEXHDG_KRYLOV_DECLS(double)
 IMEXHDG_KRYLOV_DECLS(float)

@@ -33,9 +33,10 @@ EXPORTS = [
     "imexhdg_ens_members", "imexhdg_ens_sizes", "imexhdg_ens_get_nodes",
     "imexhdg_ens_set_state", "imexhdg_ens_get_state", "imexhdg_ens_step",
     "imexhdg_ens_get_diag", "imexhdg_ens_get_schedule", "imexhdg_ens_set_launch_geometry",
+    "imexhdg_ens_autotune",
 ]
 KERNELS = ["nl_residual", "combine", "local_apply", "trace_rhs", "trace_residual", "bicg_init",
-           "bicg_k1", "bicg_k2", "bicg_k3", "axpy", "recover", "diag", "linear_residual"]
+           "bicg_k1", "bicg_k2", "bicg_k1f", "axpy", "recover", "diag", "linear_residual"]
 
 
 class Config(ctypes.Structure):
@@ -122,6 +123,7 @@ def load():
         "imexhdg_ens_get_diag": (ctypes.c_int, [P, i32, ctypes.POINTER(Diag)]),
         "imexhdg_ens_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "imexhdg_ens_set_launch_geometry": (ctypes.c_int, [P, i32, i32]),
+        "imexhdg_ens_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32)]),
         "imexhdg_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32),
                                             ctypes.POINTER(i32)]),
     }
@@ -386,3 +388,10 @@ class Ensemble:
     def set_launch_geometry(self, face_grid, elem_grid):
         _check(self.lib.imexhdg_ens_set_launch_geometry(self._ens, int(face_grid),
                                                         int(elem_grid)))
+
+    def autotune(self, cache_path=None):
+        """Tune the per-member face grid cap on the current state; returns it."""
+        f = ctypes.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self.lib.imexhdg_ens_autotune(self._ens, path, ctypes.byref(f)))
+        return f.value

@@ -155,3 +155,25 @@ def test_ensemble_64_members_sampled():
         err = swe.rel_l2(mesh, a, b)
         print(f"member {i} n={w.n}: {err}", flush=True)
         assert np.all(err < 1e-12)
+
+
+def test_ensemble_autotune_restores_state(tmp_path):
+    k = 3
+    cfgs = [_cfg(nx, ny, k, m.PREC_MIXED) for nx, ny in MESHES]
+    E = m.Ensemble(cfgs)
+    for i, (nx, ny) in enumerate(MESHES):
+        _, q0 = _ic(nx, ny, k, seed=400 + i)
+        E.set_state(i, *q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    E.step(3)
+    before = [np.stack(E.get_state(i, vars=m.VARS_GEOPOTENTIAL)) for i in range(len(MESHES))]
+    cache = tmp_path / "ens_tune.txt"
+    f = E.autotune(str(cache))
+    print("ensemble face grid cap", f, open(cache).read(), flush=True)
+    assert f in (16, 32, 48, 64, 96, 128, 1024)
+    for i in range(len(MESHES)):
+        assert np.array_equal(before[i], np.stack(E.get_state(i, vars=m.VARS_GEOPOTENTIAL)))
+    assert E.diag(0)["steps"] == 3
+    assert E.autotune(str(cache)) == f
+    assert len(open(cache).read().splitlines()) == 1
+    E.step(2)
+    assert E.diag(0)["steps"] == 5
