@@ -58,8 +58,8 @@ def algorithmic_cost(name, wl, n_dof, isz=8):
         "bicg_k2": (5 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
         # fused K1: read s, t, p, v, rh, d; write r, p, v, d
         "bicg_k1f": (10 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
-        # read x, g, ghat (FP64); write r (FP64), rin (inner)
-        "trace_residual": (4 * T * 8 + T * isz, 4.0 * 7 * b3 * b3 * nfaces),
+        # read x, g, ghat (FP64); write rin (inner)
+        "trace_residual": (3 * T * 8 + T * isz, 4.0 * 7 * b3 * b3 * nfaces),
         "local_apply": (2 * N * 8, 2.0 * (3 * K * K) ** 2 * nel),
         "recover": ((2 * N + T) * 8, 2.0 * (3 * K * K) * 12 * K * nel),
         "trace_rhs": (4 * T * 8, 2.0 * b3 * b3 * nfaces),
@@ -70,18 +70,30 @@ def algorithmic_cost(name, wl, n_dof, isz=8):
     return table.get(name)
 
 
-KERNEL_SYMBOL = {"nl_residual": "k_nl", "combine": "k_combine", "local_apply": "k_local_apply",
-                 "trace_rhs": "k_trace_rhs", "trace_residual": "k_trace_residual",
-                 "bicg_init": "k_bicg_init", "bicg_k1": "k_bicg_k1", "bicg_k2": "k_bicg_k2",
-                 "bicg_k1f": "k_bicg_k1f", "axpy": "k_axpy", "recover": "k_recover"}
+def kernel_symbol(kernel_class, K, mixed):
+    """Demangled symbol (as a kernel trace names it) of a kernel class's
+    host-driven launches."""
+    T = "float" if mixed else "double"
+    face = {"bicg_k1": "k_bicg_k1", "bicg_k2": "k_bicg_k2", "bicg_k1f": "k_bicg_k1f"}
+    if kernel_class in face:
+        return f"{face[kernel_class]}<{K}, {T}, false>"
+    if kernel_class == "trace_residual":
+        return f"k_trace_residual<{K}, {T}>"
+    if kernel_class in ("bicg_init", "axpy"):
+        return f"k_{kernel_class}<{T}>"
+    base = {"nl_residual": "k_nl", "local_apply": "k_local_apply", "recover": "k_recover",
+            "trace_rhs": "k_trace_rhs", "diag": "k_diag", "linear_residual": "k_linres"}
+    if kernel_class in base:
+        return f"{base[kernel_class]}<{K}>"
+    return "k_" + kernel_class
 
 
-def measured_traffic(kernel_class, wl_name, precision="fp64"):
+def measured_traffic(kernel_class, wl, precision="fp64"):
     """HBM bytes per dispatch from the committed FETCH_SIZE / WRITE_SIZE
     profile of this workload, or None when the kernel source has changed
     since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{wl_name}_{precision}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{precision}.json")
     src = os.path.join(ROOT, "paper_1711_02751_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
@@ -91,7 +103,7 @@ def measured_traffic(kernel_class, wl_name, precision="fp64"):
         sha = hashlib.sha256(f.read()).hexdigest()
     if d.get("kernels_hip_sha256") != sha:
         return None
-    rec = d["per_dispatch"].get(KERNEL_SYMBOL.get(kernel_class, ""))
+    rec = d["per_dispatch"].get(kernel_symbol(kernel_class, wl.k + 1, precision == "mixed"))
     return None if rec is None else rec["hbm_bytes"]
 
 
@@ -124,7 +136,10 @@ def cpu_baseline(wl_name, seconds=15.0):
             "seconds": el}
 
 
-def run_path(m, wl, precision, steps, warmup):
+TUNE_CACHE = os.path.join(ROOT, "paper_1711_02751_amd", "tuning_cache.txt")
+
+
+def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     """Run one precision path; returns (result dict, final state).
 
     Timed region: `steps` steps on the fixed launch schedule, one graph
@@ -153,7 +168,7 @@ def run_path(m, wl, precision, steps, warmup):
     n_dof = 3 * S.n_nodes
     log(f"[bench] {precision}: {n_dof} DOFs, {S.n_trace} trace unknowns; warmup {warmup}")
     S.step(max(warmup, 3))
-    fg, eg = S.autotune()
+    fg, eg = S.autotune(tune_cache)
     log(f"[bench] {precision}: autotuned grid caps: face {fg}, elementwise {eg}")
     S.step(2)
     torch.cuda.synchronize()
@@ -185,15 +200,12 @@ def run_path(m, wl, precision, steps, warmup):
     value = n_dof * steps / el
     log(f"[bench] {precision}: {steps} graph steps in {el:.3f} s -> {value:.4g} DOF-updates/s "
         f"(schedule {sched}, redone steps {d1['redo_steps'] - d0['redo_steps']})")
-    # roofline run: same steps host-driven, dominant class timed by events
+    # roofline run: same steps host-driven, each launch of the dominant class
+    # timed by start / stop events on its own dispatch
     S.set_state(h, hu, hv)
     S.step(1)
     S.profile(dominant)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     S.step(steps)
-    torch.cuda.synchronize()
-    el_host = time.perf_counter() - t0
     nl, ms = S.profile_read(dominant)
     S.profile(-2)
     isz = 4 if mixed else 8
@@ -211,17 +223,18 @@ def run_path(m, wl, precision, steps, warmup):
         roof = {"bound": "mfma" if matrix else "alu", "achieved": nflops / avg_s / 1e12,
                 "peak": fpeak, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dominant, wl.name, precision)
+    roof["traffic"] = measured_traffic(dominant, wl, precision)
+    roof["symbol"] = kernel_symbol(dominant, wl.k + 1, mixed)
     roof["kernel"] = dominant
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = nl
-    roof["timed_in"] = "host-driven run of the same steps (HIP events per launch)"
+    roof["timed_in"] = ("host-driven run of the same steps; HIP start/stop events on each "
+                        "launch's dispatch")
     roof["algorithmic_bytes_per_launch"] = nbytes
     roof["algorithmic_flops_per_launch"] = nflops
     iters = ((d1["krylov_iters"] - d0["krylov_iters"])
              / max(1, d1["stage_solves"] - d0["stage_solves"]))
     res = {"value": value, "ms_per_step": 1000.0 * el / steps, "roofline": roof,
-           "host_driven_ms_per_step": 1000.0 * el_host / steps,
            "schedule": {"sweeps": sched[0], "inner_budget": sched[1]},
            "grid_caps": {"face": fg, "elementwise": eg},
            "graph_steps": d1["graph_steps"] - d0["graph_steps"],
@@ -232,7 +245,7 @@ def run_path(m, wl, precision, steps, warmup):
     return res, state
 
 
-def run_ensemble(m, steps, warmup, mixed=True):
+def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
     """The 64-member ensemble (meshes 32^2 ... 128^2, k = 3, dt_m = 2 dx_min):
     every launch covers all members, one graph launch per step."""
     import torch
@@ -256,7 +269,7 @@ def run_ensemble(m, steps, warmup, mixed=True):
     n_dof = 3 * sum(E.n_nodes)
     log(f"[bench] ensemble: {len(members)} members, {n_dof} DOFs; warmup {max(warmup, 3)}")
     E.step(max(warmup, 3))
-    fg = E.autotune()
+    fg = E.autotune(tune_cache)
     log(f"[bench] ensemble: autotuned face grid cap per member: {fg}")
     E.step(1)
     d0 = E.diag(0)
@@ -293,6 +306,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-member ensemble measurement")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="launch-geometry cache: a line for this device and workload is "
+                         "used as is, else the autotuner times the candidates and appends one")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB (counter calibration)")
@@ -309,12 +325,22 @@ def main():
 
     wl = W.WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.calib_copy_mib > 0:
+        # one plain elementwise pass over a known size: its FETCH_SIZE and
+        # WRITE_SIZE counters scale the others to bytes
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)     # reads and writes calib_copy_mib MiB once
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+        del src, dst
     log(f"[bench] workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
-    fp64, s64 = run_path(m, wl, "fp64", args.steps, args.warmup)
+    fp64, s64 = run_path(m, wl, "fp64", args.steps, args.warmup, args.tune_cache)
     if args.precision == "fp64":
         head, smx = fp64, None
     else:
-        head, smx = run_path(m, wl, "mixed", args.steps, args.warmup)
+        head, smx = run_path(m, wl, "mixed", args.steps, args.warmup, args.tune_cache)
     from oracle import swe   # only for the mass-weighted norm of the comparison
     out = {
         "metric": METRIC,
@@ -340,7 +366,7 @@ def main():
         "krylov_iters_per_stage": head["krylov_iters_per_stage"],
         "max_trace_relres": head["max_trace_relres"],
         "launch": {k: head[k] for k in ("schedule", "grid_caps", "graph_steps",
-                                        "redone_steps", "host_driven_ms_per_step")},
+                                        "redone_steps")},
         "kernels": head["kernels"],
     }
     if smx is not None:
@@ -349,14 +375,14 @@ def main():
         out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                        "roofline": fp64["roofline"],
                        "launch": {k: fp64[k] for k in ("schedule", "grid_caps",
-                                                       "graph_steps", "redone_steps",
-                                                       "host_driven_ms_per_step")},
+                                                       "graph_steps", "redone_steps")},
                        "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
         out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]
         out["mixed_rel_l2_vs_fp64"] = [float(e) for e in err]
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(m, args.steps, args.warmup,
-                                       mixed=args.precision == "mixed")
+                                       mixed=args.precision == "mixed",
+                                       tune_cache=args.tune_cache)
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(wl.name, args.cpu_seconds)

@@ -225,7 +225,8 @@ int imexhdg_stage_solve(imexhdg_ctx *ctx, const double *d_res0, double *d_Q,
 #define IMEXHDG_K_COUNT       13
 
 /* Select the class to time (0..IMEXHDG_K_COUNT-1), -1 for all classes or
- * -2 to switch timing off; clears the accumulated times.                 */
+ * -2 to switch timing off; clears the accumulated times.  Each timed launch
+ * carries start / stop events on its own dispatch.                       */
 int imexhdg_profile(imexhdg_ctx *ctx, int32_t kernel);
 
 /* Launch count and summed device time (ms) of a class since the last

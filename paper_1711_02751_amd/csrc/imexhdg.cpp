@@ -139,7 +139,7 @@ struct imexhdg_ctx {
     double *q = nullptr, *Z = nullptr, *save = nullptr;   // save: autotuner's copy of q
     const double *qin = nullptr;      // q^n of the step being enqueued
     std::vector<double *> NLb, Qb, Rb;
-    double *x = nullptr, *gv = nullptr, *gh = nullptr, *r64 = nullptr;
+    double *x = nullptr, *gv = nullptr, *gh = nullptr;
     double *xsave = nullptr;          // autotuner's copy of the trace guess
     // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
     bool mixed = false;
@@ -287,7 +287,7 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     const size_t isz = (c0.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
-    t += 5 * align256(L.T * 8);                        // FP64 trace vectors
+    t += 4 * align256(L.T * 8);                        // FP64 trace vectors
     t += 10 * align256(L.T * isz);                     // inner-solve vectors
     t += (size_t)L.nops * (align256(local_frag_count((int)n_loc, (int)n_loc) * 8) +
                            align256(local_frag_count((int)n_loc, (int)n_tr) * 8) +
@@ -486,6 +486,8 @@ bool prof_on(const imexhdg_ctx *c, int id) {
     return c->prof_target == -1 || c->prof_target == id;
 }
 
+// The events go with the launch itself (set_launch_events), so they time
+// the kernel's execution, not the event packets around it.
 hipError_t prof_begin(imexhdg_ctx *c, int id) {
     if (!prof_on(c, id)) return hipSuccess;
     if (c->ev_used == kEventPool) {
@@ -493,15 +495,16 @@ hipError_t prof_begin(imexhdg_ctx *c, int id) {
         if (e != hipSuccess) return e;
         prof_harvest(c);
     }
-    return hipEventRecord(c->ev0[c->ev_used], c->stream);
+    set_launch_events(c->ev0[c->ev_used], c->ev1[c->ev_used]);
+    return hipSuccess;
 }
 
 hipError_t prof_end(imexhdg_ctx *c, int id) {
     if (!prof_on(c, id)) return hipSuccess;
-    hipError_t e = hipEventRecord(c->ev1[c->ev_used], c->stream);
+    set_launch_events(nullptr, nullptr);
     c->ev_id[c->ev_used] = id;
     c->ev_used += 1;
-    return e;
+    return hipSuccess;
 }
 
 hipError_t stream_sync(imexhdg_ctx *c) {
@@ -604,10 +607,10 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
     for (int sweep = 0;; ++sweep) {
         int rc;
         LAUNCH(IMEXHDG_K_TRACE_RESID,
-               c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64,
+               c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh,
                                                 (float *)c->rin, c->dpart, c->pstride, nullptr,
                                                 c->stream)
-                        : launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64,
+                        : launch_trace_residual(g, b, c->x, c->gv, c->gh,
                                                 (double *)c->rin, c->dpart, c->pstride, nullptr,
                                                 c->stream));
         double nrm[4];
@@ -715,7 +718,7 @@ int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
     KrylovBufs kb = c->kb;
     kb.sched = 1;
-    HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64, rin, c->dpart, c->pstride,
+    HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, c->gh, rin, c->dpart, c->pstride,
                                   c->ks, c->stream));
     HIP_TRY(launch_refine_check(g, b, (const T *)rin, r, rh, p[0], v[0], d, c->ks, c->dpart,
                                 c->pstride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
@@ -746,9 +749,9 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
         int rc = c->mixed ? sched_sweep<float>(c, bud, irt) : sched_sweep<double>(c, bud, irt);
         if (rc) return rc;
     }
-    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64, (float *)c->rin,
+    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh, (float *)c->rin,
                                              c->dpart, c->pstride, c->ks, c->stream)
-                     : launch_trace_residual(g, b, c->x, c->gv, c->gh, c->r64, (double *)c->rin,
+                     : launch_trace_residual(g, b, c->x, c->gv, c->gh, (double *)c->rin,
                                              c->dpart, c->pstride, c->ks, c->stream));
     HIP_TRY(launch_stage_finish(b, c->ks, c->dpart, c->pstride, st, c->stream));
     LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream));
@@ -1248,7 +1251,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
     c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
-    double **tv[5] = {&c->x, &c->gv, &c->gh, &c->r64, &c->xsave};
+    double **tv[4] = {&c->x, &c->gv, &c->gh, &c->xsave};
     for (double **p : tv) *p = (double *)take(L.T * 8);
     void **iv[10] = {&c->rin, &c->kr, &c->krh, &c->kp[0], &c->kp[1],
                      &c->kv[0], &c->kv[1], &c->ks_, &c->kt, &c->kd};

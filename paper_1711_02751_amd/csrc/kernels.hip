@@ -11,9 +11,31 @@
 // of a batch has this layout within its slice of the concatenated arrays.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 namespace imexhdg {
+
+// Events for the next launch on this thread (kernel profiler): attached to
+// the dispatch itself, so they time the same interval a kernel trace does.
+thread_local hipEvent_t t_launch_ev[2] = {nullptr, nullptr};
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_launch_ev[0] = start;
+    t_launch_ev[1] = stop;
+}
+
+#define KLAUNCH(kernel, grid, block, shm, stream, ...)                                 \
+    do {                                                                               \
+        if (t_launch_ev[0]) {                                                          \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, t_launch_ev[0],    \
+                                  t_launch_ev[1], 0, __VA_ARGS__);                     \
+            t_launch_ev[0] = t_launch_ev[1] = nullptr;                                 \
+        } else {                                                                       \
+            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);         \
+        }                                                                              \
+    } while (0)
 
 namespace {
 
@@ -278,20 +300,52 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         }
     }
     if (!active) return;
-    // the step's combinations take dt NL (dt of the member)
+    // the step's combinations take dt NL (dt of the member); input by
+    // input, the 3 K values of this row are loaded together
     const double sc = scale_dt ? mb.dt : 1.0;
+    const size_t o = mb.vo + (size_t)(j * K) * nel + e;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const size_t o = mb.vo + (size_t)(j * K + i) * nel + e;
-        const double val[3] = {sc * o0[i], sc * o1[i], sc * o2[i]};
+        o0[i] *= sc;
+        o1[i] *= sc;
+        o2[i] *= sc;
+    }
+    if (comb.store) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const size_t oc = c * NN + o;
-            if (comb.store) comb.store[oc] = val[c];
-            double acc = comb.self * val[c];
-            for (int t = 0; t < comb.n; ++t) acc += comb.coef[t] * comb.in[t][oc];
-            comb.out[oc] = acc;
+        for (int i = 0; i < K; ++i) {
+            comb.store[o + (size_t)i * nel] = o0[i];
+            comb.store[NN + o + (size_t)i * nel] = o1[i];
+            comb.store[2 * NN + o + (size_t)i * nel] = o2[i];
         }
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        o0[i] *= comb.self;
+        o1[i] *= comb.self;
+        o2[i] *= comb.self;
+    }
+    for (int t = 0; t < comb.n; ++t) {
+        const double *in = comb.in[t] + o;
+        const double cf = comb.coef[t];
+        double v0[K], v1[K], v2[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            v0[i] = in[(size_t)i * nel];
+            v1[i] = in[NN + (size_t)i * nel];
+            v2[i] = in[2 * NN + (size_t)i * nel];
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            o0[i] += cf * v0[i];
+            o1[i] += cf * v1[i];
+            o2[i] += cf * v2[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        comb.out[o + (size_t)i * nel] = o0[i];
+        comb.out[NN + o + (size_t)i * nel] = o1[i];
+        comb.out[2 * NN + o + (size_t)i * nel] = o2[i];
     }
 }
 
@@ -919,12 +973,13 @@ template <int K, typename T> struct TileLds {
     static constexpr int n = MF<K>::B3 * Tile<K>::NF;
 };
 
-// FP64 residuals of the trace system: r = g - G x, rin = ghat - Ghat x;
-// partials of ||r||^2, ||g||^2, ||ghat||^2, ||rin||^2.
+// FP64 residuals of the trace system: r = g - G x (only its norm is
+// needed) and rin = ghat - Ghat x (stored); partials of ||r||^2, ||g||^2,
+// ||ghat||^2, ||rin||^2.
 template <int K, typename RT>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residual(
     const Batch bt, const double *__restrict__ x, const double *__restrict__ gv,
-    const double *__restrict__ gh, double *__restrict__ r, RT *__restrict__ rin,
+    const double *__restrict__ gh, RT *__restrict__ rin,
     double *partials, int stride, const KrylovState *skip) {
     using T = double;
     constexpr int NMB = MF<K>::NMB;
@@ -932,7 +987,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     if (skip && skip[mi].stage_done) return;
     const Member mb = load_member(bt, mi);
-    x += mb.to; gv += mb.to; gh += mb.to; r += mb.to; rin += mb.to;
+    x += mb.to; gv += mb.to; gh += mb.to; rin += mb.to;
     __shared__ double sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
     const double *fr[2] = {mb.G, mb.Gh};
@@ -965,7 +1020,6 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
                     if (ok[m][e4]) {
                         const double rr = gvv[m][e4] - acc[0][m][e4];
                         const double ri = ghv[m][e4] - acc[1][m][e4];
-                        r[o[m][e4]] = rr;
                         rin[o[m][e4]] = (RT)ri;
                         acc4[0] += rr * rr;
                         acc4[1] += gvv[m][e4] * gvv[m][e4];
@@ -1520,7 +1574,7 @@ hipError_t dispatch(int K, Args &&...args) {
 template <int K> struct RunNL {
     static hipError_t run(const Geom &g, const Batch &b, const double *q, const Comb &c,
                           bool scale_dt, hipStream_t s) {
-        hipLaunchKernelGGL(k_nl<K>, dim3(b.nbv), dim3(64 * K), 0, s, q, g, b, c,
+        KLAUNCH(k_nl<K>, dim3(b.nbv), dim3(64 * K), 0, s, q, g, b, c,
                            scale_dt ? 1 : 0);
         return hipGetLastError();
     }
@@ -1528,37 +1582,37 @@ template <int K> struct RunNL {
 template <int K> struct RunLinres {
     static hipError_t run(const Geom &g, const Batch &b, const double *Q, const double *qh,
                           double *out, hipStream_t s) {
-        hipLaunchKernelGGL(k_linres<K>, dim3(b.nbv), dim3(64 * K), 0, s, Q, qh, g, b, out);
+        KLAUNCH(k_linres<K>, dim3(b.nbv), dim3(64 * K), 0, s, Q, qh, g, b, out);
         return hipGetLastError();
     }
 };
 template <int K> struct RunLocal {
     static hipError_t run(const Batch &b, const double *R, double *Z, hipStream_t s) {
-        hipLaunchKernelGGL(k_local_apply<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
+        KLAUNCH(k_local_apply<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
         return hipGetLastError();
     }
 };
 template <int K> struct RunRecover {
     static hipError_t run(const Batch &b, const double *Z, const double *qh, double *Q,
                           hipStream_t s) {
-        hipLaunchKernelGGL(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q);
+        KLAUNCH(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q);
         return hipGetLastError();
     }
 };
 template <int K> struct RunTraceRhs {
     static hipError_t run(const Geom &g, const Batch &b, const double *Z, double *gv,
                           double *gh, hipStream_t s) {
-        hipLaunchKernelGGL(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, gh);
+        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, gh);
         return hipGetLastError();
     }
 };
 template <typename RT> struct RunTraceResidual {
     template <int K> struct F {
         static hipError_t run(const Batch &b, const double *x, const double *gv,
-                              const double *gh, double *r, RT *rin, double *partials,
-                              int stride, const KrylovState *skip, hipStream_t s) {
-            hipLaunchKernelGGL((k_trace_residual<K, RT>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
-                               b, x, gv, gh, r, rin, partials, stride, skip);
+                              const double *gh, RT *rin, double *partials, int stride,
+                              const KrylovState *skip, hipStream_t s) {
+            KLAUNCH((k_trace_residual<K, RT>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
+                               b, x, gv, gh, rin, partials, stride, skip);
             return hipGetLastError();
         }
     };
@@ -1569,11 +1623,11 @@ template <typename T> struct RunK1 {
                               const T *vin, T *pout, T *vout, KrylovState *ks,
                               const KrylovBufs &kb, hipStream_t s) {
             if (kb.sched)
-                hipLaunchKernelGGL((k_bicg_k1<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                KLAUNCH((k_bicg_k1<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
                                    s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
                                    kb.stride);
             else
-                hipLaunchKernelGGL((k_bicg_k1<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                KLAUNCH((k_bicg_k1<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
                                    s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
                                    kb.stride);
             return hipGetLastError();
@@ -1585,10 +1639,10 @@ template <typename T> struct RunK2 {
         static hipError_t run(const Batch &b, const T *r, const T *v, const T *rh, T *sv,
                               T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             if (kb.sched)
-                hipLaunchKernelGGL((k_bicg_k2<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                KLAUNCH((k_bicg_k2<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
                                    s, b, r, v, rh, sv, t, ks, kb.P1, kb.P2, kb.stride);
             else
-                hipLaunchKernelGGL((k_bicg_k2<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
+                KLAUNCH((k_bicg_k2<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
                                    s, b, r, v, rh, sv, t, ks, kb.P1, kb.P2, kb.stride);
             return hipGetLastError();
         }
@@ -1600,11 +1654,11 @@ template <typename T> struct RunK1F {
                               const T *pin, const T *vin, T *pout, T *vout, T *r, T *d,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             if (kb.sched)
-                hipLaunchKernelGGL((k_bicg_k1f<K, T, true>), dim3(b.nbf), dim3(kFaceThreads),
+                KLAUNCH((k_bicg_k1f<K, T, true>), dim3(b.nbf), dim3(kFaceThreads),
                                    0, s, b, sv, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
                                    kb.P1, kb.stride);
             else
-                hipLaunchKernelGGL((k_bicg_k1f<K, T, false>), dim3(b.nbf), dim3(kFaceThreads),
+                KLAUNCH((k_bicg_k1f<K, T, false>), dim3(b.nbf), dim3(kFaceThreads),
                                    0, s, b, sv, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
                                    kb.P1, kb.stride);
             return hipGetLastError();
@@ -1614,7 +1668,7 @@ template <typename T> struct RunK1F {
 template <int K> struct RunDiag {
     static hipError_t run(const Geom &g, const Batch &b, const double *q, double *partials,
                           int stride, hipStream_t s) {
-        hipLaunchKernelGGL(k_diag<K>, dim3(b.nbd), dim3(64 * K), 0, s, q, g, b, partials,
+        KLAUNCH(k_diag<K>, dim3(b.nbd), dim3(64 * K), 0, s, q, g, b, partials,
                            stride);
         return hipGetLastError();
     }
@@ -1646,7 +1700,7 @@ hipError_t launch_nl(const Geom &g, const Batch &b, const double *q, const Comb 
 }
 
 hipError_t launch_combine(const Comb &comb, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_combine, dim3(grid1(n, 256)), dim3(256), 0, s, comb, n);
+    KLAUNCH(k_combine, dim3(grid1(n, 256)), dim3(256), 0, s, comb, n);
     return hipGetLastError();
 }
 
@@ -1672,16 +1726,16 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 
 #define IMEXHDG_KRYLOV_LAUNCHERS(T)                                                            \
     hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
-                                     const double *gvec, const double *ghat, double *r,       \
-                                     T *rin, double *partials, int stride,                    \
-                                     const KrylovState *skip, hipStream_t s) {                \
-        return dispatch<RunTraceResidual<T>::template F>(g.K, b, x, gvec, ghat, r, rin,       \
+                                     const double *gvec, const double *ghat, T *rin,          \
+                                     double *partials, int stride, const KrylovState *skip,   \
+                                     hipStream_t s) {                                         \
+        return dispatch<RunTraceResidual<T>::template F>(g.K, b, x, gvec, ghat, rin,          \
                                                          partials, stride, skip, s);          \
     }                                                                                          \
     hipError_t launch_bicg_init(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
                                 T *p, T *v, T *d, KrylovState *ks, double tol2,               \
                                 const KrylovBufs &kb, hipStream_t s) {                        \
-        hipLaunchKernelGGL(k_bicg_init<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r, rh, \
+        KLAUNCH(k_bicg_init<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r, rh, \
                            p, v, d, ks, tol2, kb.P3, kb.stride);                              \
         return hipGetLastError();                                                              \
     }                                                                                          \
@@ -1704,20 +1758,20 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
                                                ks, kb, s);                                    \
     }                                                                                          \
     hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s) {        \
-        hipLaunchKernelGGL(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);     \
+        KLAUNCH(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);     \
         return hipGetLastError();                                                              \
     }                                                                                          \
     hipError_t launch_refine_check(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,  \
                                    T *p, T *v, T *d, KrylovState *ks, const double *partials, \
                                    int stride, double refine_rtol, double inner_rtol,         \
                                    const KrylovBufs &kb, hipStream_t s) {                     \
-        hipLaunchKernelGGL(k_refine_check<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r,   \
+        KLAUNCH(k_refine_check<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r,   \
                            rh, p, v, d, ks, partials, stride, refine_rtol, inner_rtol, kb.P3); \
         return hipGetLastError();                                                              \
     }                                                                                          \
     hipError_t launch_axpy_guarded(const Geom &g, const Batch &b, double *y, const T *x,      \
                                    KrylovState *ks, hipStream_t s) {                          \
-        hipLaunchKernelGGL(k_axpy_guarded<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, y, x, ks); \
+        KLAUNCH(k_axpy_guarded<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, y, x, ks); \
         return hipGetLastError();                                                              \
     }
 
@@ -1726,13 +1780,13 @@ IMEXHDG_KRYLOV_LAUNCHERS(float)
 #undef IMEXHDG_KRYLOV_LAUNCHERS
 
 hipError_t launch_stage_begin(const Batch &b, KrylovState *ks, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_begin, dim3(b.nm), dim3(64), 0, s, ks);
+    KLAUNCH(k_stage_begin, dim3(b.nm), dim3(64), 0, s, ks);
     return hipGetLastError();
 }
 
 hipError_t launch_stage_finish(const Batch &b, KrylovState *ks, const double *partials,
                                int stride, StageStatus *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_finish, dim3(b.nm), dim3(256), 0, s, b, ks, partials, stride,
+    KLAUNCH(k_stage_finish, dim3(b.nm), dim3(256), 0, s, b, ks, partials, stride,
                        out);
     return hipGetLastError();
 }

@@ -106,8 +106,12 @@ int member_elem_blocks(int nel, int K, int egrid);
 int member_vol_blocks(int nel);
 int member_diag_blocks(int nel);
 
+// Start / stop events for the next kernel launch of the calling thread
+// (kernel profiler); cleared by that launch.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // ---------------------------------------------------------------- launchers
-// All return hipError_t of the launch.  Pointers are the base pointers of
+// All return hipError_t of the launch; each launches one kernel.  Pointers are the base pointers of
 // the concatenated arrays.
 hipError_t launch_nl(const Geom &g, const Batch &b, const double *q, const Comb &comb,
                      bool scale_dt, hipStream_t s);
@@ -120,18 +124,18 @@ hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, doub
                             double *ghat, hipStream_t s);
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
                           double *Q, hipStream_t s);
-// FP64 r = g - G x and rin = ghat - Ghat x (stored in the inner solve's
-// precision); partials [4][face blocks] of ||r||^2, ||g||^2, ||ghat||^2,
-// ||rin||^2.  With `skip`, members whose stage solve is done return.
+// FP64 r = g - G x (its norm only) and rin = ghat - Ghat x (stored in the
+// inner solve's precision); partials [4][face blocks] of ||r||^2, ||g||^2,
+// ||ghat||^2, ||rin||^2.  With `skip`, members whose stage solve is done return.
 // BiCGStab on Ghat d = rin with d0 = 0: init and K1, then per iteration
 // K2 and K1f (the next K1 fused with this iteration's d and r updates);
 // x += d after the sweep.  Each exists for an FP64 and an FP32 inner solve
 // (matrix-core fragments in the same precision).
 #define IMEXHDG_KRYLOV_DECLS(T)                                                                \
     hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
-                                     const double *gvec, const double *ghat, double *r,       \
-                                     T *rin, double *partials, int stride,                    \
-                                     const KrylovState *skip, hipStream_t s);                 \
+                                     const double *gvec, const double *ghat, T *rin,          \
+                                     double *partials, int stride, const KrylovState *skip,   \
+                                     hipStream_t s);                                          \
     hipError_t launch_bicg_init(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
                                 T *p, T *v, T *d, KrylovState *ks, double tol2,               \
                                 const KrylovBufs &kb, hipStream_t s);                         \
