@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6          # FP64 vector and matrix-core peak
 FP32_MFMA_PEAK_TFLOPS = 157.3    # dense FP32 matrix-core peak
 MIXED_KRYLOV_RTOL = 1e-6
-MIXED_REFINE_RTOL = 1e-10
+MIXED_REFINE_RTOL = 1e-9     # 500 steps at 256^2: 1.9e-8 from the FP64 path (bound 1e-6)
 
 
 def log(*a):

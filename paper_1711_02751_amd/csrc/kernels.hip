@@ -1103,6 +1103,36 @@ __global__ void k_bicg_init(const Batch bt, int K, const T *__restrict__ rin,
 __device__ __forceinline__ const double *ghat_frags(const Member &mb, double) { return mb.Gh; }
 __device__ __forceinline__ const float *ghat_frags(const Member &mb, float) { return mb.Ghf; }
 
+// The Ghat fragments of both face sets are copied into LDS once per block
+// when both fit in 64 KB (K <= 5), so the matrix-core loop
+// reads its A operands from LDS instead of L2.
+template <int K, typename T> struct FragLds {
+    static constexpr int n = 2 * MF<K>::NMB * MF<K>::NKK * 64;
+    static constexpr bool value = (TileLds<K, T>::n + n) * (int)sizeof(T) <= 64 * 1024;
+    static constexpr int alloc = value ? n : 1;
+};
+
+template <int K, typename T>
+__device__ __forceinline__ const T *stage_frags(const T *__restrict__ g, T *sA) {
+    if constexpr (FragLds<K, T>::value) {
+        constexpr int n = FragLds<K, T>::n, PER = (n + kFaceThreads - 1) / kFaceThreads;
+        T v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + kFaceThreads * u;
+            v[u] = i < n ? g[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + kFaceThreads * u;
+            if (i < n) sA[i] = v[u];
+        }
+        return sA;   // read after the staging barrier of the first tile
+    } else {
+        return g;
+    }
+}
+
 // First K1 of an inner solve (after init or a refinement check): beta
 // from rh.r and r.r [partials P3 of the elementwise class]; p <- r + beta
 // (p - omega v) at the seven faces of each row block (p = v = 0 here), v =
@@ -1118,6 +1148,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
     if (ks->conv) return;
+    // the A operands go to LDS while the partial sums are reduced
+    __shared__ T sA[FragLds<K, T>::alloc];
+    const T *fr[1] = {stage_frags<K, T>(ghat_frags(mb, T(0)), sA)};
     double red[2];
     reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red);
     const double rho_new = red[0], rr = red[1];
@@ -1134,7 +1167,6 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     r += mb.to; rh += mb.to; pin += mb.to; vin += mb.to; pout += mb.to; vout += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
-    const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[3] = {r, pin, vin};
     double acc1[3] = {0.0, 0.0, 0.0};
     {
@@ -1193,6 +1225,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
     if (ks->conv) return;
+    // the A operands go to LDS while the partial sums are reduced
+    __shared__ T sA[FragLds<K, T>::alloc];
+    const T *fr[1] = {stage_frags<K, T>(ghat_frags(mb, T(0)), sA)};
     double red1[3];
     reduce_partials<3>(P1 + mb.bf, stride, mb.nbf, red1);
     const double rv = red1[0], rho = red1[1], rr = red1[2];
@@ -1209,7 +1244,6 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     r += mb.to; v += mb.to; rh += mb.to; sv += mb.to; t += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
-    const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[2] = {r, v};
     double acc2[3] = {0.0, 0.0, 0.0};
     {
@@ -1289,6 +1323,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
     if (ks->conv) return;
+    // the A operands go to LDS while the partial sums are reduced
+    __shared__ T sA[FragLds<K, T>::alloc];
+    const T *fr[1] = {stage_frags<K, T>(ghat_frags(mb, T(0)), sA)};
     double red[3];
     reduce_partials<3>(P2 + mb.bf, stride, mb.nbf, red);
     const double ts = red[0], tt = red[1], rht = red[2];
@@ -1303,7 +1340,6 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
-    const T *fr[1] = {ghat_frags(mb, T(0))};
     const T *src[4] = {sv, t, pin, vin};
     auto rnew = [&](T s_, T t_) { return (T)((double)s_ - omega * (double)t_); };
     auto pnew = [&](T r_, T p_, T v_) { return r_ + be * (p_ - om * v_); };

@@ -87,6 +87,30 @@ def test_config3_500_steps_sampled():
     assert abs(d["energy"] - ref["energy"]) <= 1e-11 * ref["energy"]
 
 
+def test_config3_mixed_500_steps_within_bound():
+    """Mixed path (FP32 inner solve, krylov_rtol 1e-6, FP64 refinement to
+    1e-9) after the full 500 steps: within 1e-7 of the FP64 oracle at the
+    sampled nodes (the mixed bound is 1e-6)."""
+    wl = W.WORKLOADS["bump_256x256_k4"]
+    ref = _ref(wl.name)
+    cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
+                           dt=wl.dt, physics=m.PHYSICS_NONLINEAR, precision=m.PREC_MIXED,
+                           krylov_rtol=1e-6, refine_rtol=1e-9, refine_max=8)
+    S = m.Solver(cfg)
+    q0 = _initial(wl, S)
+    S.set_state(*q0, vars=m.VARS_GEOPOTENTIAL)
+    S.step(wl.steps)
+    got = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
+    idx, val = ref["sample_idx"], ref["sample_val"]
+    mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
+    mm = mesh.mass().ravel()
+    for c in range(3):
+        num = np.sqrt(np.sum(mm[idx] * (got[c, idx] - val[c]) ** 2))
+        den = np.sqrt(np.sum(mm[idx] * val[c] ** 2))
+        print(f"config3 mixed sampled rel L2 c={c}: {num / den:.3e}", flush=True)
+        assert num / den < 1e-7
+
+
 # ---------------------------------------------------------- 1024 x 1024
 def _patch(q_host, wl, e_list):
     """3x3 element patches (periodic wrap) around elements e, in the
