@@ -973,6 +973,43 @@ template <int K, typename T> struct TileLds {
     static constexpr int n = MF<K>::B3 * Tile<K>::NF;
 };
 
+// The matrix-core fragments (both face sets, NM matrices) are copied into
+// LDS once per block when they fit beside the staged tile in 80 KB (K <= 5:
+// two blocks of 8 waves per CU, the register limit, still fit), so the
+// matrix-core loop reads its A operands from LDS instead of L2.
+template <int K, typename T, int NM = 1> struct FragLds {
+    static constexpr int n = 2 * MF<K>::NMB * MF<K>::NKK * 64;
+    static constexpr bool value =
+        (TileLds<K, T>::n + NM * n) * (int)sizeof(T) <= 80 * 1024;
+    static constexpr int alloc = value ? NM * n : 1;
+};
+
+template <int K, typename T, int NM = 1>
+__device__ __forceinline__ void stage_frags(const T *__restrict__ const *g, T *sA,
+                                            const T **out) {
+    if constexpr (FragLds<K, T, NM>::value) {
+        constexpr int n = FragLds<K, T, NM>::n, PER = (n + kFaceThreads - 1) / kFaceThreads;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            T v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int i = threadIdx.x + kFaceThreads * u;
+                v[u] = i < n ? g[m][i] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int i = threadIdx.x + kFaceThreads * u;
+                if (i < n) sA[m * n + i] = v[u];
+            }
+            out[m] = sA + m * n;   // read after the staging barrier of the first tile
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) out[m] = g[m];
+    }
+}
+
 // FP64 residuals of the trace system: r = g - G x (only its norm is
 // needed) and rin = ghat - Ghat x (stored); partials of ||r||^2, ||g||^2,
 // ||ghat||^2, ||rin||^2.
@@ -989,8 +1026,11 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
     const Member mb = load_member(bt, mi);
     x += mb.to; gv += mb.to; gh += mb.to; rin += mb.to;
     __shared__ double sB[TileLds<K, T>::n];
+    __shared__ double sA[FragLds<K, T, 2>::alloc];
     const uint32_t nel = mb.nel;
-    const double *fr[2] = {mb.G, mb.Gh};
+    const double *gfr[2] = {mb.G, mb.Gh};
+    const double *fr[2];
+    stage_frags<K, T, 2>(gfr, sA, fr);
     const double *src[1] = {x};
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
     {
@@ -1103,35 +1143,6 @@ __global__ void k_bicg_init(const Batch bt, int K, const T *__restrict__ rin,
 __device__ __forceinline__ const double *ghat_frags(const Member &mb, double) { return mb.Gh; }
 __device__ __forceinline__ const float *ghat_frags(const Member &mb, float) { return mb.Ghf; }
 
-// The Ghat fragments of both face sets are copied into LDS once per block
-// when both fit in 64 KB (K <= 5), so the matrix-core loop
-// reads its A operands from LDS instead of L2.
-template <int K, typename T> struct FragLds {
-    static constexpr int n = 2 * MF<K>::NMB * MF<K>::NKK * 64;
-    static constexpr bool value = (TileLds<K, T>::n + n) * (int)sizeof(T) <= 64 * 1024;
-    static constexpr int alloc = value ? n : 1;
-};
-
-template <int K, typename T>
-__device__ __forceinline__ const T *stage_frags(const T *__restrict__ g, T *sA) {
-    if constexpr (FragLds<K, T>::value) {
-        constexpr int n = FragLds<K, T>::n, PER = (n + kFaceThreads - 1) / kFaceThreads;
-        T v[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + kFaceThreads * u;
-            v[u] = i < n ? g[i] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + kFaceThreads * u;
-            if (i < n) sA[i] = v[u];
-        }
-        return sA;   // read after the staging barrier of the first tile
-    } else {
-        return g;
-    }
-}
 
 // First K1 of an inner solve (after init or a refinement check): beta
 // from rh.r and r.r [partials P3 of the elementwise class]; p <- r + beta
@@ -1150,7 +1161,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     if (ks->conv) return;
     // the A operands go to LDS while the partial sums are reduced
     __shared__ T sA[FragLds<K, T>::alloc];
-    const T *fr[1] = {stage_frags<K, T>(ghat_frags(mb, T(0)), sA)};
+    const T *gfr[1] = {ghat_frags(mb, T(0))};
+    const T *fr[1];
+    stage_frags<K, T>(gfr, sA, fr);
     double red[2];
     reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red);
     const double rho_new = red[0], rr = red[1];
@@ -1227,7 +1240,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     if (ks->conv) return;
     // the A operands go to LDS while the partial sums are reduced
     __shared__ T sA[FragLds<K, T>::alloc];
-    const T *fr[1] = {stage_frags<K, T>(ghat_frags(mb, T(0)), sA)};
+    const T *gfr[1] = {ghat_frags(mb, T(0))};
+    const T *fr[1];
+    stage_frags<K, T>(gfr, sA, fr);
     double red1[3];
     reduce_partials<3>(P1 + mb.bf, stride, mb.nbf, red1);
     const double rv = red1[0], rho = red1[1], rr = red1[2];
@@ -1325,7 +1340,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     if (ks->conv) return;
     // the A operands go to LDS while the partial sums are reduced
     __shared__ T sA[FragLds<K, T>::alloc];
-    const T *fr[1] = {stage_frags<K, T>(ghat_frags(mb, T(0)), sA)};
+    const T *gfr[1] = {ghat_frags(mb, T(0))};
+    const T *fr[1];
+    stage_frags<K, T>(gfr, sA, fr);
     double red[3];
     reduce_partials<3>(P2 + mb.bf, stride, mb.nbf, red);
     const double ts = red[0], tt = red[1], rht = red[2];
