@@ -907,6 +907,61 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
     }
 }
 
+// A tile's staging split in two: load() issues the loads of every value
+// this thread stages (held in registers when there are at most 8 per
+// thread), commit() combines them and writes LDS.  The FP32 Krylov kernels
+// issue the first tile's loads before their partial-sum reduction, so the
+// two memory round trips overlap (FP64 keeps the registers for occupancy).
+// With more than 8 values per thread, commit() stages in chunks
+// (stage_tile) and load() only records the tile.
+template <int K, typename T, int NA> struct StagedTile {
+    using TL = Tile<K>;
+    static constexpr int NV = TL::B3 * TL::NF;
+    static constexpr int PER = (NV + kFaceThreads - 1) / kFaceThreads;
+    static constexpr bool kHold = PER <= 8;
+    static constexpr int H = kHold ? PER : 1;
+    T raw[H][NA];
+    uint32_t off[H];
+    bool own[H], ok[H];
+    int tile;
+
+    __device__ __forceinline__ void load(int t, const Member &g,
+                                         const T *__restrict__ const (&src)[NA]) {
+        tile = t;
+        if constexpr (kHold) {
+            const int tpr = tiles_per_row(g);
+            const int ex0 = (t % tpr) * kTX, ey0 = (t / tpr) * kTY;
+            const uint32_t nel = g.nel, TT = TL::B3 * nel;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int v = threadIdx.x + kFaceThreads * u;
+                ok[u] = v < NV;
+                const int vv = ok[u] ? v : 0;
+                const int cj = vv / TL::NF, fc = vv - cj * TL::NF;
+                int dir, elem;
+                staged_face(fc, ex0, ey0, g.nx, g.ny, TL::NX, TL::XC, TL::YC, dir, elem, own[u]);
+                off[u] = (uint32_t)dir * TT + (uint32_t)cj * nel + (uint32_t)elem;
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u)
+#pragma unroll
+                for (int a = 0; a < NA; ++a) raw[u][a] = ok[u] ? src[a][off[u]] : T(0);
+        }
+    }
+
+    template <typename Comb>
+    __device__ __forceinline__ void commit(const Member &g, const T *__restrict__ const (&src)[NA],
+                                           T *sB, Comb comb) {
+        if constexpr (kHold) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u)
+                if (ok[u]) sB[threadIdx.x + kFaceThreads * u] = comb(raw[u], off[u], own[u]);
+        } else {
+            stage_tile<K, T, NA>(tile, g, sB, src, comb);
+        }
+    }
+};
+
 // This wave's row blocks from the staged tile: the matrix cores read the B
 // operands from LDS, slot by slot; the A operands of slot s + 1 are loaded
 // while slot s is computed.
@@ -952,14 +1007,16 @@ __device__ __forceinline__ int own_lds(const WaveFaces &wf) {
                        : TL::NX + (wf.sub + 1) * TL::YC + (lx + 1);
 }
 
-// Row blocks of this wave for one tile: stage, then contract from LDS.
+// Row blocks of this wave for one tile whose staging loads are in flight
+// in st: commit the staging, then contract from LDS.
 template <int K, int NM, typename T, int NA, typename Comb>
-__device__ __forceinline__ void face_rows(const T *__restrict__ const *frags, int tile,
-                                          const Member &g, const WaveFaces &wf, T *sB,
+__device__ __forceinline__ void face_rows(const T *__restrict__ const *frags,
+                                          StagedTile<K, T, NA> &st, const Member &g,
+                                          const WaveFaces &wf, T *sB,
                                           const T *__restrict__ const (&src)[NA], Comb comb,
                                           typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
     __syncthreads();   // the previous tile's LDS reads are done
-    stage_tile<K, T, NA>(tile, g, sB, src, comb);
+    st.commit(g, src, sB, comb);
     __syncthreads();
     tile_rows<K, NM, T>(frags, sB, wf, acc);
 }
@@ -1035,7 +1092,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
     {
         const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+        StagedTile<K, T, 1> st;
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            st.load(tile, mb, src);
             const WaveFaces wf = wave_faces(tile, mb);
             // right-hand sides at the own rows, loaded ahead of the contraction
             double gvv[NMB][4], ghv[NMB][4];
@@ -1050,7 +1109,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
                     ghv[m][e4] = ok[m][e4] ? gh[o[m][e4]] : 0.0;
                 }
             v4d acc[2][NMB];
-            face_rows<K, 2>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 2>(fr, st, mb, wf, sB, src,
                                    [](const double (&a)[1], uint32_t, bool) { return a[0]; },
                                    acc);
 #pragma unroll
@@ -1164,6 +1223,12 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const T *gfr[1] = {ghat_frags(mb, T(0))};
     const T *fr[1];
     stage_frags<K, T>(gfr, sA, fr);
+    r += mb.to; rh += mb.to; pin += mb.to; vin += mb.to; pout += mb.to; vout += mb.to;
+    const T *src[3] = {r, pin, vin};
+    const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+    StagedTile<K, T, 3> st;
+    constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
+    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src);
     double red[2];
     reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red);
     const double rho_new = red[0], rr = red[1];
@@ -1177,14 +1242,12 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
         return;
     }
     const T beta = (T)((rho_new / rho) * (alpha / omega)), om = (T)omega;
-    r += mb.to; rh += mb.to; pin += mb.to; vin += mb.to; pout += mb.to; vout += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
-    const T *src[3] = {r, pin, vin};
     double acc1[3] = {0.0, 0.0, 0.0};
     {
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            if (!kEarly || tile != tw.first) st.load(tile, mb, src);
             const WaveFaces wf = wave_faces(tile, mb);
             T rhv[NMB][4], rv[NMB][4];
             uint32_t o[NMB][4];
@@ -1198,7 +1261,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                     rv[m][e4] = ok[m][e4] ? r[o[m][e4]] : T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            face_rows<K, 1>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                    [&](const T (&a)[3], uint32_t off, bool own) {
                                        const T p = a[0] + beta * (a[1] - om * a[2]);
                                        if (own) pout[off] = p;
@@ -1243,6 +1306,12 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const T *gfr[1] = {ghat_frags(mb, T(0))};
     const T *fr[1];
     stage_frags<K, T>(gfr, sA, fr);
+    r += mb.to; v += mb.to; rh += mb.to; sv += mb.to; t += mb.to;
+    const T *src[2] = {r, v};
+    const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+    StagedTile<K, T, 2> st;
+    constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
+    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src);
     double red1[3];
     reduce_partials<3>(P1 + mb.bf, stride, mb.nbf, red1);
     const double rv = red1[0], rho = red1[1], rr = red1[2];
@@ -1256,14 +1325,12 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     }
     const double alpha = rho / rv;
     const T al = (T)alpha;
-    r += mb.to; v += mb.to; rh += mb.to; sv += mb.to; t += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
-    const T *src[2] = {r, v};
     double acc2[3] = {0.0, 0.0, 0.0};
     {
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            if (!kEarly || tile != tw.first) st.load(tile, mb, src);
             const WaveFaces wf = wave_faces(tile, mb);
             uint32_t o[NMB][4];
             bool ok[NMB][4];
@@ -1277,7 +1344,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                     sown[m][e4] = T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            face_rows<K, 1>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                    [&](const T (&a)[2], uint32_t off, bool own) {
                                        const T sval = a[0] - al * a[1];
                                        if (own) sv[off] = sval;
@@ -1343,6 +1410,13 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const T *gfr[1] = {ghat_frags(mb, T(0))};
     const T *fr[1];
     stage_frags<K, T>(gfr, sA, fr);
+    sv += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
+    pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
+    const T *src[4] = {sv, t, pin, vin};
+    const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+    StagedTile<K, T, 4> st;
+    constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
+    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src);
     double red[3];
     reduce_partials<3>(P2 + mb.bf, stride, mb.nbf, red);
     const double ts = red[0], tt = red[1], rht = red[2];
@@ -1353,17 +1427,14 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                      !isfinite(rho_new);
     const double beta = brk ? 0.0 : (rho_new / rho) * (alpha / omega);
     const T be = (T)beta, om = (T)omega;
-    sv += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
-    pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
-    const T *src[4] = {sv, t, pin, vin};
     auto rnew = [&](T s_, T t_) { return (T)((double)s_ - omega * (double)t_); };
     auto pnew = [&](T r_, T p_, T v_) { return r_ + be * (p_ - om * v_); };
     double acc1[3] = {0.0, 0.0, 0.0};
     {
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+            if (!kEarly || tile != tw.first) st.load(tile, mb, src);
             const WaveFaces wf = wave_faces(tile, mb);
             T rhv[NMB][4];
             uint32_t o[NMB][4];
@@ -1376,7 +1447,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            face_rows<K, 1>(fr, tile, mb, wf, sB, src,
+            face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                    [&](const T (&a)[4], uint32_t, bool) {
                                        return pnew(rnew(a[0], a[1]), a[2], a[3]);
                                    },
