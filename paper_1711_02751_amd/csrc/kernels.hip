@@ -868,14 +868,24 @@ __device__ __forceinline__ int slot_lds(int set, int s, int lx, int ly, int NX, 
                   : NX + (ly + dy + 1) * YC + (lx + dx + 1);
 }
 
+// comb(raw, off, own), or comb(raw, oraw, off, own) with NO own-face sources.
+template <int NO, typename T, int NA, typename Comb>
+__device__ __forceinline__ T apply_comb(Comb &comb, const T (&a)[NA], const T (&o)[NO > 0 ? NO : 1],
+                                        uint32_t off, bool own) {
+    if constexpr (NO == 0) return comb(a, off, own);
+    else return comb(a, o, off, own);
+}
+
 // Stage the tile: sB[cj NF + f] = comb(raw, o, own) for every staged face
 // f and row cj (c' K + j'), where raw holds the NA source arrays at trace
-// offset o; comb may store the value at o when the tile owns the face.  All
-// loads of a chunk of up to 8 values per thread are issued before any is
-// used.
-template <int K, typename T, int NA, typename Comb>
+// offset o; comb may store the value at o when the tile owns the face.
+// With NO > 0, the NO arrays osrc are also loaded at the faces the tile
+// owns (zero elsewhere) and handed to comb.  All loads of a chunk of up to
+// 8 values per thread are issued before any is used.
+template <int K, typename T, int NA, int NO, typename Comb>
 __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
-                                           const T *__restrict__ const (&src)[NA], Comb comb) {
+                                           const T *__restrict__ const (&src)[NA],
+                                           const T *const *osrc, Comb comb) {
     using TL = Tile<K>;
     constexpr int NV = TL::B3 * TL::NF, PER = (NV + kFaceThreads - 1) / kFaceThreads;
     constexpr int CH = PER < 8 ? PER : 8;
@@ -886,7 +896,7 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
     for (int i0 = 0; i0 < PER; i0 += CH) {
         uint32_t off[CH];
         bool own[CH], ok[CH];
-        T raw[CH][NA];
+        T raw[CH][NA], oraw[CH][NO > 0 ? NO : 1];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int v = threadIdx.x + kFaceThreads * (i0 + u);
@@ -903,7 +913,13 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
             for (int a = 0; a < NA; ++a) raw[u][a] = ok[u] ? src[a][off[u]] : T(0);
 #pragma unroll
         for (int u = 0; u < CH; ++u)
-            if (ok[u]) sB[threadIdx.x + kFaceThreads * (i0 + u)] = comb(raw[u], off[u], own[u]);
+#pragma unroll
+            for (int b = 0; b < NO; ++b) oraw[u][b] = ok[u] && own[u] ? osrc[b][off[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (ok[u])
+                sB[threadIdx.x + kFaceThreads * (i0 + u)] =
+                    apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u]);
     }
 }
 
@@ -913,21 +929,25 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
 // issue the first tile's loads before their partial-sum reduction, so the
 // two memory round trips overlap (FP64 keeps the registers for occupancy).
 // With more than 8 values per thread, commit() stages in chunks
-// (stage_tile) and load() only records the tile.
-template <int K, typename T, int NA> struct StagedTile {
+// (stage_tile) and load() only records the tile.  NO > 0: own-face sources
+// as in stage_tile.
+template <int K, typename T, int NA, int NO = 0> struct StagedTile {
     using TL = Tile<K>;
     static constexpr int NV = TL::B3 * TL::NF;
     static constexpr int PER = (NV + kFaceThreads - 1) / kFaceThreads;
     static constexpr bool kHold = PER <= 8;
     static constexpr int H = kHold ? PER : 1;
-    T raw[H][NA];
+    T raw[H][NA], oraw[H][NO > 0 ? NO : 1];
     uint32_t off[H];
     bool own[H], ok[H];
     int tile;
+    const T *const *os;
 
     __device__ __forceinline__ void load(int t, const Member &g,
-                                         const T *__restrict__ const (&src)[NA]) {
+                                         const T *__restrict__ const (&src)[NA],
+                                         const T *const *osrc = nullptr) {
         tile = t;
+        os = osrc;
         if constexpr (kHold) {
             const int tpr = tiles_per_row(g);
             const int ex0 = (t % tpr) * kTX, ey0 = (t / tpr) * kTY;
@@ -946,6 +966,11 @@ template <int K, typename T, int NA> struct StagedTile {
             for (int u = 0; u < PER; ++u)
 #pragma unroll
                 for (int a = 0; a < NA; ++a) raw[u][a] = ok[u] ? src[a][off[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < PER; ++u)
+#pragma unroll
+                for (int b = 0; b < NO; ++b)
+                    oraw[u][b] = ok[u] && own[u] ? osrc[b][off[u]] : T(0);
         }
     }
 
@@ -955,9 +980,11 @@ template <int K, typename T, int NA> struct StagedTile {
         if constexpr (kHold) {
 #pragma unroll
             for (int u = 0; u < PER; ++u)
-                if (ok[u]) sB[threadIdx.x + kFaceThreads * u] = comb(raw[u], off[u], own[u]);
+                if (ok[u])
+                    sB[threadIdx.x + kFaceThreads * u] =
+                        apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u]);
         } else {
-            stage_tile<K, T, NA>(tile, g, sB, src, comb);
+            stage_tile<K, T, NA, NO>(tile, g, sB, src, os, comb);
         }
     }
 };
@@ -1009,9 +1036,9 @@ __device__ __forceinline__ int own_lds(const WaveFaces &wf) {
 
 // Row blocks of this wave for one tile whose staging loads are in flight
 // in st: commit the staging, then contract from LDS.
-template <int K, int NM, typename T, int NA, typename Comb>
+template <int K, int NM, typename T, int NA, int NO, typename Comb>
 __device__ __forceinline__ void face_rows(const T *__restrict__ const *frags,
-                                          StagedTile<K, T, NA> &st, const Member &g,
+                                          StagedTile<K, T, NA, NO> &st, const Member &g,
                                           const WaveFaces &wf, T *sB,
                                           const T *__restrict__ const (&src)[NA], Comb comb,
                                           typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
@@ -1413,10 +1440,16 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     sv += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
     pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
     const T *src[4] = {sv, t, pin, vin};
+    // FP32 with the tile held in registers (K <= 7): the staging thread of
+    // an own face also reads d and rh there and updates r, p and d.  FP64
+    // keeps its registers for occupancy and updates the own faces after the
+    // contraction.
+    constexpr bool kOwnStage = sizeof(T) == 4 && StagedTile<K, T, 4>::kHold;
+    const T *osrc[2] = {d, rh};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
-    StagedTile<K, T, 4> st;
+    StagedTile<K, T, 4, kOwnStage ? 2 : 0> st;
     constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
-    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src);
+    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src, osrc);
     double red[3];
     reduce_partials<3>(P2 + mb.bf, stride, mb.nbf, red);
     const double ts = red[0], tt = red[1], rht = red[2];
@@ -1434,7 +1467,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     double acc1[3] = {0.0, 0.0, 0.0};
     {
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            if (!kEarly || tile != tw.first) st.load(tile, mb, src);
+            if (!kEarly || tile != tw.first) st.load(tile, mb, src, osrc);
             const WaveFaces wf = wave_faces(tile, mb);
             T rhv[NMB][4];
             uint32_t o[NMB][4];
@@ -1447,43 +1480,59 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            face_rows<K, 1>(fr, st, mb, wf, sB, src,
-                                   [&](const T (&a)[4], uint32_t, bool) {
-                                       return pnew(rnew(a[0], a[1]), a[2], a[3]);
-                                   },
-                                   acc);
-            // own faces: all loads first, then the updates
-            T sv_[NMB][4], tv_[NMB][4], pv_[NMB][4], vv_[NMB][4], dv_[NMB][4];
+            auto own_update = [&](T s_, T t_, T p_, T v_, T d_, T rh_, uint32_t oo) {
+                const T rn = rnew(s_, t_);
+                r[oo] = rn;
+                pout[oo] = pnew(rn, p_, v_);
+                d[oo] = (T)((double)d_ + alpha * (double)p_ + omega * (double)s_);
+                const double rd = rn;
+                acc1[1] += (double)rh_ * rd;
+                acc1[2] += rd * rd;
+            };
+            if constexpr (kOwnStage) {
+                face_rows<K, 1>(fr, st, mb, wf, sB, src,
+                                [&](const T (&a)[4], const T (&ov)[2], uint32_t off, bool own) {
+                                    if (own) own_update(a[0], a[1], a[2], a[3], ov[0], ov[1], off);
+                                    return pnew(rnew(a[0], a[1]), a[2], a[3]);
+                                },
+                                acc);
+            } else {
+                face_rows<K, 1>(fr, st, mb, wf, sB, src,
+                                [&](const T (&a)[4], uint32_t, bool) {
+                                    return pnew(rnew(a[0], a[1]), a[2], a[3]);
+                                },
+                                acc);
+                // own faces: all loads first, then the updates
+                T sv_[NMB][4], tv_[NMB][4], pv_[NMB][4], vv_[NMB][4], dv_[NMB][4];
 #pragma unroll
-            for (int m = 0; m < NMB; ++m)
+                for (int m = 0; m < NMB; ++m)
 #pragma unroll
-                for (int e4 = 0; e4 < 4; ++e4) {
-                    const bool k_ = ok[m][e4];
-                    const uint32_t oo = o[m][e4];
-                    sv_[m][e4] = k_ ? sv[oo] : T(0);
-                    tv_[m][e4] = k_ ? t[oo] : T(0);
-                    pv_[m][e4] = k_ ? pin[oo] : T(0);
-                    vv_[m][e4] = k_ ? vin[oo] : T(0);
-                    dv_[m][e4] = k_ ? d[oo] : T(0);
-                }
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        const bool k_ = ok[m][e4];
+                        const uint32_t oo = o[m][e4];
+                        sv_[m][e4] = k_ ? sv[oo] : T(0);
+                        tv_[m][e4] = k_ ? t[oo] : T(0);
+                        pv_[m][e4] = k_ ? pin[oo] : T(0);
+                        vv_[m][e4] = k_ ? vin[oo] : T(0);
+                        dv_[m][e4] = k_ ? d[oo] : T(0);
+                    }
+#pragma unroll
+                for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4)
+                        if (ok[m][e4])
+                            own_update(sv_[m][e4], tv_[m][e4], pv_[m][e4], vv_[m][e4],
+                                       dv_[m][e4], rhv[m][e4], o[m][e4]);
+            }
+            // the matrix-core lanes store v' = Ghat p' and sum rh.v'
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4)
                     if (ok[m][e4]) {
-                        const uint32_t oo = o[m][e4];
-                        const T rn = rnew(sv_[m][e4], tv_[m][e4]);
-                        const T pn = pnew(rn, pv_[m][e4], vv_[m][e4]);
-                        d[oo] = (T)((double)dv_[m][e4] + alpha * (double)pv_[m][e4] +
-                                    omega * (double)sv_[m][e4]);
-                        r[oo] = rn;
-                        pout[oo] = pn;
                         const double y = acc[0][m][e4];
-                        const double rhd = rhv[m][e4], rd = rn;
-                        vout[oo] = (T)y;
-                        acc1[0] += rhd * y;
-                        acc1[1] += rhd * rd;
-                        acc1[2] += rd * rd;
+                        vout[o[m][e4]] = (T)y;
+                        acc1[0] += (double)rhv[m][e4] * y;
                     }
         }
     }
