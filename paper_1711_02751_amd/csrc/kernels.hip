@@ -117,24 +117,34 @@ __device__ __forceinline__ Member load_member(const Batch &bt, int i) {
 // block).  Partials are indexed by the global block; a member reduces its
 // own block range.
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also orders
+// global memory, which on this target waits for every vector memory
+// operation in flight, loads included; a barrier that only hands LDS data
+// between waves need not wait for the global loads issued ahead of it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Block sum of NV values per thread; the result is returned to every thread.
 template <int NV>
 __device__ void block_sum(double (&v)[NV]) {
     __shared__ double sred[16][NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
+    lds_barrier();
     for (int q = 0; q < NV; ++q) {
         double s = wave_sum(v[q]);
         if (lane == 0) sred[w][q] = s;
     }
-    __syncthreads();
+    lds_barrier();
     for (int q = 0; q < NV; ++q) {
         double s = 0.0;
         for (int i = 0; i < nw; ++i) s += sred[i][q];
         v[q] = s;
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // partials[q * stride + blockIdx.x] = block sum of v[q]
@@ -171,6 +181,37 @@ __device__ void reduce_partials(const double *__restrict__ partials, int stride,
     }
     block_sum<NV>(out);
 }
+
+// reduce_partials split in two, so that its loads can be issued ahead of
+// other loads of the kernel: load() sums this thread's values (one per
+// quantity unless the member has more blocks than threads) in a fixed
+// order, finish() sums over the block.  Identical in every block.  Any
+// loop over further values stays in load(), ahead of the loads issued
+// between the two calls, so finish() waits for the partial sums only.
+// Loads whose result is not needed read a valid address and are discarded
+// rather than skipped: a load under a branch leaves the compiler unsure
+// how many loads follow an earlier one, and it then waits for all of them.
+template <int NV> struct EarlyPartials {
+    double a[NV], b[NV];   // this thread's first value, the sum of the others
+    bool has;
+    __device__ __forceinline__ void load(const double *__restrict__ partials, int stride, int n) {
+        const int i = threadIdx.x;
+        has = i < n;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            a[q] = partials[q * stride + (has ? i : 0)];
+            b[q] = 0.0;
+        }
+        for (int j = i + (int)blockDim.x; j < n; j += blockDim.x)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) b[q] += partials[q * stride + j];
+    }
+    __device__ __forceinline__ void finish(double (&out)[NV]) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q] = has ? a[q] + b[q] : 0.0;
+        block_sum<NV>(out);
+    }
+};
 
 // ------------------------------------------------------------- physics
 // Nonlinear remainder of the flux, F_NL = F - F_L (Sec. 4.3), in closed form:
@@ -700,6 +741,11 @@ __global__ __launch_bounds__(256) void k_recover(const double *__restrict__ Z,
 template <int K> struct MFOcc {
     static constexpr int value = K <= 5 ? 2 : 1;
 };
+// The residual kernel at K <= 5 must keep two 512-thread blocks per CU
+// (at most 128 VGPRs: four waves per SIMD).
+template <int K> struct ResidOcc {
+    static constexpr int value = K <= 5 ? 4 : 1;
+};
 
 // Packed A fragments: frag[dir][mb][kk][lane] (see element-side packing).
 __device__ __forceinline__ size_t frag_off(int d, int mb, int kk, int lane, int NMB, int NKK) {
@@ -763,6 +809,10 @@ __device__ __forceinline__ WaveFaces wave_faces(int tile, const Member &g) {
 
 // Trace offset of accumulator element (mb, r) of this lane: row 16 mb +
 // row(lane, r) of the row block of face (set, e); valid if that row < 3K.
+// Callers load x[valid ? off : 0] and use the value only where valid: a
+// load under a divergent branch would be followed by a write of the
+// default value to the same register, which waits for every load in
+// flight.
 template <int K, typename T>
 __device__ __forceinline__ uint32_t own_off(const WaveFaces &wf, int mb, int r, uint32_t nel,
                                             bool &valid) {
@@ -943,9 +993,11 @@ template <int K, typename T, int NA, int NO = 0> struct StagedTile {
     int tile;
     const T *const *os;
 
+    // dummy: every lane reads the member's first values instead (a load
+    // that is issued but never committed costs one cache line per wave)
     __device__ __forceinline__ void load(int t, const Member &g,
                                          const T *__restrict__ const (&src)[NA],
-                                         const T *const *osrc = nullptr) {
+                                         const T *const *osrc = nullptr, bool dummy = false) {
         tile = t;
         os = osrc;
         if constexpr (kHold) {
@@ -960,17 +1012,21 @@ template <int K, typename T, int NA, int NO = 0> struct StagedTile {
                 const int cj = vv / TL::NF, fc = vv - cj * TL::NF;
                 int dir, elem;
                 staged_face(fc, ex0, ey0, g.nx, g.ny, TL::NX, TL::XC, TL::YC, dir, elem, own[u]);
-                off[u] = (uint32_t)dir * TT + (uint32_t)cj * nel + (uint32_t)elem;
+                off[u] = dummy ? 0u : (uint32_t)dir * TT + (uint32_t)cj * nel + (uint32_t)elem;
             }
+            // every load is issued and nothing is selected here, so that no
+            // wait lands in load() (see EarlyPartials): off[u] is a valid
+            // face for every slot (commit() skips the slots past the tile),
+            // and the own-face sources of other faces read the member's
+            // first value (one cache line per wave; comb ignores them)
 #pragma unroll
             for (int u = 0; u < PER; ++u)
 #pragma unroll
-                for (int a = 0; a < NA; ++a) raw[u][a] = ok[u] ? src[a][off[u]] : T(0);
+                for (int a = 0; a < NA; ++a) raw[u][a] = src[a][off[u]];
 #pragma unroll
             for (int u = 0; u < PER; ++u)
 #pragma unroll
-                for (int b = 0; b < NO; ++b)
-                    oraw[u][b] = ok[u] && own[u] ? osrc[b][off[u]] : T(0);
+                for (int b = 0; b < NO; ++b) oraw[u][b] = osrc[b][ok[u] && own[u] ? off[u] : 0u];
         }
     }
 
@@ -1036,15 +1092,22 @@ __device__ __forceinline__ int own_lds(const WaveFaces &wf) {
 
 // Row blocks of this wave for one tile whose staging loads are in flight
 // in st: commit the staging, then contract from LDS.
-template <int K, int NM, typename T, int NA, int NO, typename Comb>
+// `next` runs between the staging and the contraction: the FP32 kernels
+// issue the next tile's loads there, into the registers commit() freed.
+struct NoNext {
+    __device__ __forceinline__ void operator()() const {}
+};
+template <int K, int NM, typename T, int NA, int NO, typename Comb, typename Next = NoNext>
 __device__ __forceinline__ void face_rows(const T *__restrict__ const *frags,
                                           StagedTile<K, T, NA, NO> &st, const Member &g,
                                           const WaveFaces &wf, T *sB,
                                           const T *__restrict__ const (&src)[NA], Comb comb,
-                                          typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
-    __syncthreads();   // the previous tile's LDS reads are done
+                                          typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB],
+                                          Next next = Next()) {
+    lds_barrier();   // the previous tile's LDS reads are done
     st.commit(g, src, sB, comb);
-    __syncthreads();
+    lds_barrier();
+    next();
     tile_rows<K, NM, T>(frags, sB, wf, acc);
 }
 
@@ -1066,6 +1129,44 @@ template <int K, typename T, int NM = 1> struct FragLds {
     static constexpr bool value =
         (TileLds<K, T>::n + NM * n) * (int)sizeof(T) <= 80 * 1024;
     static constexpr int alloc = value ? NM * n : 1;
+};
+
+// stage_frags split in two: load() issues the fragment loads, store()
+// writes LDS and returns the operand pointers.
+template <int K, typename T, int NM = 1> struct FragStage {
+    static constexpr int n = FragLds<K, T, NM>::n;
+    static constexpr int PER = FragLds<K, T, NM>::value ? (n + kFaceThreads - 1) / kFaceThreads : 1;
+    T v[NM][PER];
+    const T *src[NM];
+    __device__ __forceinline__ void load(const T *__restrict__ const *g) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            src[m] = g[m];
+            if constexpr (FragLds<K, T, NM>::value) {
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int i = threadIdx.x + kFaceThreads * u;
+                    const T x = g[m][i < n ? i : 0];   // unconditional (see EarlyPartials)
+                    v[m][u] = i < n ? x : T(0);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T *sA, const T **out) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            if constexpr (FragLds<K, T, NM>::value) {
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int i = threadIdx.x + kFaceThreads * u;
+                    if (i < n) sA[m * n + i] = v[m][u];
+                }
+                out[m] = sA + m * n;   // read after the staging barrier of the first tile
+            } else {
+                out[m] = src[m];
+            }
+        }
+    }
 };
 
 template <int K, typename T, int NM = 1>
@@ -1098,7 +1199,7 @@ __device__ __forceinline__ void stage_frags(const T *__restrict__ const *g, T *s
 // needed) and rin = ghat - Ghat x (stored); partials of ||r||^2, ||g||^2,
 // ||ghat||^2, ||rin||^2.
 template <int K, typename RT>
-__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residual(
+__global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_residual(
     const Batch bt, const double *__restrict__ x, const double *__restrict__ gv,
     const double *__restrict__ gh, RT *__restrict__ rin,
     double *partials, int stride, const KrylovState *skip) {
@@ -1114,14 +1215,19 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
     const uint32_t nel = mb.nel;
     const double *gfr[2] = {mb.G, mb.Gh};
     const double *fr[2];
-    stage_frags<K, T, 2>(gfr, sA, fr);
+    // the first tile's loads are issued with the operand loads (a block
+    // without tiles loads tile 0 and never commits it)
+    FragStage<K, T, 2> fs;
+    fs.load(gfr);
     const double *src[1] = {x};
+    const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+    StagedTile<K, T, 1> st;
+    st.load(tw.first < tw.end ? tw.first : 0, mb, src);
+    fs.store(sA, fr);
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
     {
-        const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
-        StagedTile<K, T, 1> st;
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            st.load(tile, mb, src);
+            if (tile != tw.first) st.load(tile, mb, src);
             const WaveFaces wf = wave_faces(tile, mb);
             // right-hand sides at the own rows, loaded ahead of the contraction
             double gvv[NMB][4], ghv[NMB][4];
@@ -1132,8 +1238,8 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_trace_residua
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
-                    gvv[m][e4] = ok[m][e4] ? gv[o[m][e4]] : 0.0;
-                    ghv[m][e4] = ok[m][e4] ? gh[o[m][e4]] : 0.0;
+                    gvv[m][e4] = gv[ok[m][e4] ? o[m][e4] : 0u];
+                    ghv[m][e4] = gh[ok[m][e4] ? o[m][e4] : 0u];
                 }
             v4d acc[2][NMB];
             face_rows<K, 2>(fr, st, mb, wf, sB, src,
@@ -1245,25 +1351,31 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
     if (ks->conv) return;
-    // the A operands go to LDS while the partial sums are reduced
+    const double rho = ks->rho, alpha = ks->alpha, omega = ks->omega, tol2 = ks->tol2;
+    // issue order: the partial sums, the A operands, the first tile; the
+    // partial sums are reduced while the rest is in flight
+    EarlyPartials<2> ep;
+    ep.load(P3 + mb.be, stride, mb.nbe);
     __shared__ T sA[FragLds<K, T>::alloc];
     const T *gfr[1] = {ghat_frags(mb, T(0))};
     const T *fr[1];
-    stage_frags<K, T>(gfr, sA, fr);
+    FragStage<K, T> fs;
+    fs.load(gfr);
     r += mb.to; rh += mb.to; pin += mb.to; vin += mb.to; pout += mb.to; vout += mb.to;
     const T *src[3] = {r, pin, vin};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
     StagedTile<K, T, 3> st;
     constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
-    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src);
+    // unconditional: a block without tiles loads tile 0 and never commits it
+    if (kEarly) st.load(tw.first < tw.end ? tw.first : 0, mb, src);
     double red[2];
-    reduce_partials<2>(P3 + mb.be, stride, mb.nbe, red);
+    ep.finish(red);
+    fs.store(sA, fr);
     const double rho_new = red[0], rr = red[1];
-    const double rho = ks->rho, alpha = ks->alpha, omega = ks->omega;
-    if (rr <= ks->tol2 || rho_new == 0.0 || omega == 0.0 || !isfinite(rr)) {
+    if (rr <= tol2 || rho_new == 0.0 || omega == 0.0 || !isfinite(rr)) {
         if (lb == 0 && threadIdx.x == 0) {
             ks->rr = rr;
-            ks->breakdown = (rr <= ks->tol2) ? 0 : 1;
+            ks->breakdown = (rr <= tol2) ? 0 : 1;
             ks->conv = 1;
         }
         return;
@@ -1274,7 +1386,15 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     double acc1[3] = {0.0, 0.0, 0.0};
     {
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            if (!kEarly || tile != tw.first) st.load(tile, mb, src);
+            // FP32: this tile's loads were issued in the prologue or during
+            // the previous tile's contraction
+            if (!kEarly) st.load(tile, mb, src);
+            auto prefetch = [&] {
+                if constexpr (kEarly) {
+                    const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
+                    st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
+                }
+            };
             const WaveFaces wf = wave_faces(tile, mb);
             T rhv[NMB][4], rv[NMB][4];
             uint32_t o[NMB][4];
@@ -1284,8 +1404,8 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
-                    rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
-                    rv[m][e4] = ok[m][e4] ? r[o[m][e4]] : T(0);
+                    rhv[m][e4] = rh[ok[m][e4] ? o[m][e4] : 0u];
+                    rv[m][e4] = r[ok[m][e4] ? o[m][e4] : 0u];
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
             face_rows<K, 1>(fr, st, mb, wf, sB, src,
@@ -1294,7 +1414,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                                        if (own) pout[off] = p;
                                        return p;
                                    },
-                                   acc);
+                                   acc, prefetch);
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
@@ -1328,24 +1448,31 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
     if (ks->conv) return;
-    // the A operands go to LDS while the partial sums are reduced
+    const double tol2 = ks->tol2;
+    // issue order: the partial sums, the A operands, the first tile; the
+    // partial sums are reduced while the rest is in flight
+    EarlyPartials<3> ep;
+    ep.load(P1 + mb.bf, stride, mb.nbf);
     __shared__ T sA[FragLds<K, T>::alloc];
     const T *gfr[1] = {ghat_frags(mb, T(0))};
     const T *fr[1];
-    stage_frags<K, T>(gfr, sA, fr);
+    FragStage<K, T> fs;
+    fs.load(gfr);
     r += mb.to; v += mb.to; rh += mb.to; sv += mb.to; t += mb.to;
     const T *src[2] = {r, v};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
     StagedTile<K, T, 2> st;
     constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
-    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src);
+    // unconditional: a block without tiles loads tile 0 and never commits it
+    if (kEarly) st.load(tw.first < tw.end ? tw.first : 0, mb, src);
     double red1[3];
-    reduce_partials<3>(P1 + mb.bf, stride, mb.nbf, red1);
+    ep.finish(red1);
+    fs.store(sA, fr);
     const double rv = red1[0], rho = red1[1], rr = red1[2];
-    if (rr <= ks->tol2 || !isfinite(rr) || rv == 0.0 || !isfinite(rv)) {
+    if (rr <= tol2 || !isfinite(rr) || rv == 0.0 || !isfinite(rv)) {
         if (lb == 0 && threadIdx.x == 0) {
             ks->rr = rr;
-            ks->breakdown = (rr <= ks->tol2) ? 0 : 1;
+            ks->breakdown = (rr <= tol2) ? 0 : 1;
             ks->conv = 1;
         }
         return;
@@ -1357,7 +1484,15 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     double acc2[3] = {0.0, 0.0, 0.0};
     {
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            if (!kEarly || tile != tw.first) st.load(tile, mb, src);
+            // FP32: this tile's loads were issued in the prologue or during
+            // the previous tile's contraction
+            if (!kEarly) st.load(tile, mb, src);
+            auto prefetch = [&] {
+                if constexpr (kEarly) {
+                    const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
+                    st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
+                }
+            };
             const WaveFaces wf = wave_faces(tile, mb);
             uint32_t o[NMB][4];
             bool ok[NMB][4];
@@ -1367,7 +1502,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
-                    rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
+                    rhv[m][e4] = rh[ok[m][e4] ? o[m][e4] : 0u];
                     sown[m][e4] = T(0);
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
@@ -1377,7 +1512,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                                        if (own) sv[off] = sval;
                                        return sval;
                                    },
-                                   acc);
+                                   acc, prefetch);
             {
                 const int li = own_lds<K>(wf);
 #pragma unroll
@@ -1432,11 +1567,16 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
     if (ks->conv) return;
-    // the A operands go to LDS while the partial sums are reduced
+    const double rho = ks->rho, alpha = ks->alpha, rvv = ks->rv;
+    // issue order: the partial sums, the A operands, the first tile; the
+    // partial sums are reduced while the rest is in flight
+    EarlyPartials<3> ep;
+    ep.load(P2 + mb.bf, stride, mb.nbf);
     __shared__ T sA[FragLds<K, T>::alloc];
     const T *gfr[1] = {ghat_frags(mb, T(0))};
     const T *fr[1];
-    stage_frags<K, T>(gfr, sA, fr);
+    FragStage<K, T> fs;
+    fs.load(gfr);
     sv += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
     pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
     const T *src[4] = {sv, t, pin, vin};
@@ -1449,12 +1589,13 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
     StagedTile<K, T, 4, kOwnStage ? 2 : 0> st;
     constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
-    if (kEarly && tw.first < tw.end) st.load(tw.first, mb, src, osrc);
+    // unconditional: a block without tiles loads tile 0 and never commits it
+    if (kEarly) st.load(tw.first < tw.end ? tw.first : 0, mb, src, osrc);
     double red[3];
-    reduce_partials<3>(P2 + mb.bf, stride, mb.nbf, red);
+    ep.finish(red);
+    fs.store(sA, fr);
     const double ts = red[0], tt = red[1], rht = red[2];
     const double omega = tt > 0.0 ? ts / tt : 0.0;
-    const double rho = ks->rho, alpha = ks->alpha, rvv = ks->rv;
     const double rho_new = (rho - alpha * rvv) - omega * rht;
     const bool brk = !(omega != 0.0) || !isfinite(omega) || !(rho_new != 0.0) ||
                      !isfinite(rho_new);
@@ -1467,7 +1608,15 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     double acc1[3] = {0.0, 0.0, 0.0};
     {
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            if (!kEarly || tile != tw.first) st.load(tile, mb, src, osrc);
+            // FP32: this tile's loads were issued in the prologue or during
+            // the previous tile's contraction
+            if (!kEarly) st.load(tile, mb, src, osrc);
+            auto prefetch = [&] {
+                if constexpr (kEarly) {
+                    const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
+                    st.load(nt < tw.end ? nt : tile, mb, src, osrc, nt >= tw.end);
+                }
+            };
             const WaveFaces wf = wave_faces(tile, mb);
             T rhv[NMB][4];
             uint32_t o[NMB][4];
@@ -1477,7 +1626,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
-                    rhv[m][e4] = ok[m][e4] ? rh[o[m][e4]] : T(0);
+                    rhv[m][e4] = rh[ok[m][e4] ? o[m][e4] : 0u];
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
             auto own_update = [&](T s_, T t_, T p_, T v_, T d_, T rh_, uint32_t oo) {
@@ -1495,13 +1644,13 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                                     if (own) own_update(a[0], a[1], a[2], a[3], ov[0], ov[1], off);
                                     return pnew(rnew(a[0], a[1]), a[2], a[3]);
                                 },
-                                acc);
+                                acc, prefetch);
             } else {
                 face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                 [&](const T (&a)[4], uint32_t, bool) {
                                     return pnew(rnew(a[0], a[1]), a[2], a[3]);
                                 },
-                                acc);
+                                acc, prefetch);
                 // own faces: all loads first, then the updates
                 T sv_[NMB][4], tv_[NMB][4], pv_[NMB][4], vv_[NMB][4], dv_[NMB][4];
 #pragma unroll
@@ -1510,11 +1659,11 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     for (int e4 = 0; e4 < 4; ++e4) {
                         const bool k_ = ok[m][e4];
                         const uint32_t oo = o[m][e4];
-                        sv_[m][e4] = k_ ? sv[oo] : T(0);
-                        tv_[m][e4] = k_ ? t[oo] : T(0);
-                        pv_[m][e4] = k_ ? pin[oo] : T(0);
-                        vv_[m][e4] = k_ ? vin[oo] : T(0);
-                        dv_[m][e4] = k_ ? d[oo] : T(0);
+                        sv_[m][e4] = sv[k_ ? oo : 0u];
+                        tv_[m][e4] = t[k_ ? oo : 0u];
+                        pv_[m][e4] = pin[k_ ? oo : 0u];
+                        vv_[m][e4] = vin[k_ ? oo : 0u];
+                        dv_[m][e4] = d[k_ ? oo : 0u];
                     }
 #pragma unroll
                 for (int m = 0; m < NMB; ++m)
