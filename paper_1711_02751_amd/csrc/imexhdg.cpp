@@ -706,9 +706,9 @@ int step_host(imexhdg_ctx *c, const double *qin, double *qout, int *status) {
 // ------------------------------------------------ fixed launch schedule
 // The same trace solve as trace_solve(), with every decision taken on the
 // device, per member: per sweep the FP64 residual, the refinement check
-// (which ends the member's stage solve once refine_rtol is met and
-// otherwise opens an inner solve), K1 and `budget` rounds of K2, K3, K1,
-// and x += d.  Launches after convergence return at entry.
+// fused with the first K1 (it ends the member's stage solve once
+// refine_rtol is met and otherwise opens an inner solve), `budget` rounds
+// of K2 and K1f, and x += d.  Launches after convergence return at entry.
 template <typename T>
 int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     const Geom &g = c->geom;
@@ -720,12 +720,10 @@ int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     kb.sched = 1;
     HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, c->gh, rin, c->dpart, c->pstride,
                                   c->ks, c->stream));
-    HIP_TRY(launch_refine_check(g, b, (const T *)rin, r, rh, p[0], v[0], d, c->ks, c->dpart,
-                                c->pstride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
-    int par = 0;
-    HIP_TRY(launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par], v[1 - par], c->ks, kb,
-                           c->stream));
-    par = 1 - par;
+    // the refinement check and the first K1 of the inner solve in one launch
+    HIP_TRY(launch_refine_k1(g, b, (const T *)rin, r, rh, p[1], v[1], d, c->ks, c->dpart,
+                             c->pstride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
+    int par = 1;
     for (int it = 0; it < budget; ++it) {
         HIP_TRY(launch_bicg_k2(g, b, r, v[par], rh, sv, t, c->ks, kb, c->stream));
         HIP_TRY(launch_bicg_k1f(g, b, sv, t, rh, p[par], v[par], p[1 - par], v[1 - par], r, d,
@@ -741,8 +739,8 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
     const Batch &b = c->bt;
     const imexhdg_config &cf = c->cfg;
     LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
-    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->gh, c->stream));
-    HIP_TRY(launch_stage_begin(b, c->ks, c->stream));
+    // trace_rhs also resets each member's stage-solve state
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->gh, c->stream, c->ks));
     const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
     for (int sw = 0; sw < c->sched_sweeps; ++sw) {
         const int bud = c->sched_budget[sw];
@@ -753,8 +751,9 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
                                              c->dpart, c->pstride, c->ks, c->stream)
                      : launch_trace_residual(g, b, c->x, c->gv, c->gh, (double *)c->rin,
                                              c->dpart, c->pstride, c->ks, c->stream));
-    HIP_TRY(launch_stage_finish(b, c->ks, c->dpart, c->pstride, st, c->stream));
-    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream));
+    // recover also records each member's stage-solve outcome
+    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream, c->ks, c->dpart,
+                                             c->pstride, st));
     return IMEXHDG_OK;
 }
 

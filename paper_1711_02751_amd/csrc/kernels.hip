@@ -515,18 +515,62 @@ __device__ __forceinline__ FaceIdx face_of_tile(int tile, int nel) {
 
 // g = sum over the two elements of C_K Z_K = F_L(Z) . n_K + tau Z at the
 // face node; ghat = P^-1 g with the block-Jacobi inverse of the face.
+// Stage-solve state of one member on the fixed launch schedule.  At the
+// start of a stage solve (run by trace_rhs): no sweep yet, no inner solve
+// active until the first refinement check opens one.
+__device__ __forceinline__ void stage_begin_state(KrylovState *ks) {
+    ks->stage_done = 0;
+    ks->sweep = 0;
+    ks->relres = 0.0;
+    ks->conv = 1;
+    ks->iters = 0;
+    for (int i = 0; i < kMaxSweeps; ++i) ks->sweep_iters[i] = 0;
+}
+
+// After the last sweep (run by one block of the member in recover): if the
+// solve never met refine_rtol, take the residual of the final
+// trace_residual [partials [4][face blocks]]; record the outcome.  Called
+// by every thread of the block.
+__device__ void stage_finish_block(const Member &mb, const KrylovState *ks,
+                                   const double *res_partials, int stride, StageStatus *out) {
+    double relres = ks->relres;
+    const int done = ks->stage_done;
+    if (!done) {
+        double nrm[2];
+        reduce_partials<2>(res_partials + mb.bf, stride, mb.nbf, nrm);
+        relres = nrm[1] > 0.0 ? sqrt(nrm[0] / nrm[1]) : sqrt(nrm[0]);
+    }
+    if (threadIdx.x == 0) {
+        out->relres = relres;
+        out->converged = done;
+        out->sweeps = ks->sweep;
+        int tot = 0;
+        for (int i = 0; i < kMaxSweeps; ++i) {
+            out->sweep_iters[i] = ks->sweep_iters[i];
+            tot += out->sweep_iters[i];
+        }
+        out->iters_total = tot;
+    }
+}
+
+// `begin` (fixed schedule only): the member's first block also resets its
+// stage-solve state (stage_begin_state).
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__ Z,
                                                       const Geom g, const Batch bt,
                                                       double *__restrict__ gv,
-                                                      double *__restrict__ gh) {
+                                                      double *__restrict__ gh,
+                                                      KrylovState *begin) {
     constexpr int B3 = 3 * K;
     __shared__ double sG[B3][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
     // the member's blocks are [2 bv, 2 (bv + nbv)): x-face tiles, then y
     int lb;
-    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x >> 1, lb));
+    const int mi = member_of<CV>(bt, blockIdx.x >> 1, lb);
+    const Member mb = load_member(bt, mi);
+    if (begin != nullptr && lb == 0 && (blockIdx.x & 1) == 0 && threadIdx.x == 0)
+        stage_begin_state(begin + mi);
     Z += mb.vo;
     gv += mb.to;
     gh += mb.to;
@@ -684,14 +728,20 @@ __device__ __forceinline__ double local_trace(const double *__restrict__ qh, con
     return qh[(f >= 2 ? (size_t)3 * K * nel : 0) + (size_t)cj * nel + face];
 }
 
+// `fout` (fixed schedule only): the member's first block also records the
+// outcome of its stage solve (stage_finish_block).
 template <int K>
 __global__ __launch_bounds__(256) void k_recover(const double *__restrict__ Z,
                                                  const double *__restrict__ qh,
-                                                 const Batch bt, double *__restrict__ Q) {
+                                                 const Batch bt, double *__restrict__ Q,
+                                                 const KrylovState *fks, const double *fpart,
+                                                 int fstride, StageStatus *fout) {
     constexpr int NL = 3 * K * K, NT = 12 * K;
     using LM = LocalMF<NL, NT>;
     int lb;
-    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    const int mi = member_of<CV>(bt, blockIdx.x, lb);
+    const Member mb = load_member(bt, mi);
+    if (fout != nullptr && lb == 0) stage_finish_block(mb, fks + mi, fpart, fstride, fout + mi);
     Z += mb.vo;
     qh += mb.to;
     Q += mb.vo;
@@ -1227,7 +1277,12 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
     {
         for (int tile = tw.first; tile < tw.end; tile += tw.step) {
-            if (tile != tw.first) st.load(tile, mb, src);
+            // this tile's loads were issued above or during the previous
+            // tile's contraction
+            auto prefetch = [&] {
+                const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
+                st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
+            };
             const WaveFaces wf = wave_faces(tile, mb);
             // right-hand sides at the own rows, loaded ahead of the contraction
             double gvv[NMB][4], ghv[NMB][4];
@@ -1244,7 +1299,7 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
             v4d acc[2][NMB];
             face_rows<K, 2>(fr, st, mb, wf, sB, src,
                                    [](const double (&a)[1], uint32_t, bool) { return a[0]; },
-                                   acc);
+                                   acc, prefetch);
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
@@ -1431,6 +1486,118 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     }
     store_partials<3>(acc1, P1, stride);
     if (lb == 0 && threadIdx.x == 0) ks->rr = rr;
+}
+
+// A refinement check fused with the first K1 of the sweep's inner solve
+// (fixed launch schedule; it replaces refine_check + K1 there).  Every
+// block reduces the member's FP64 residual norms of the last
+// trace_residual (partials [4][face blocks]: ||r||^2, ||g||^2, ||ghat||^2,
+// ||rin||^2).  Once relres = ||r|| / ||g|| <= refine_rtol the member's
+// stage solve is done and the launch returns.  Otherwise the inner solve on
+// Ghat d = rin starts from d = 0, so r = rh = p = rin, and v = Ghat rin; the
+// own faces receive r, rh, p, v and d = 0, P1 = (rh.v, rh.r, r.r), and the
+// tolerance is max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2)
+// (an inner solve that starts below it is converged at once).
+template <int K, typename T>
+__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
+    const Batch bt, const T *__restrict__ rin, T *__restrict__ r, T *__restrict__ rh,
+    T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ d, KrylovState *ks_all,
+    const double *res_partials, int rstride, double refine_rtol, double inner_rtol,
+    double *P1, int stride) {
+    constexpr int NMB = MF<K>::NMB;
+    int lb;
+    const int mi = member_of<CF>(bt, blockIdx.x, lb);
+    KrylovState *ks = ks_all + mi;
+    if (ks->stage_done) return;
+    const Member mb = load_member(bt, mi);
+    // issue order: the residual norms, the A operands, the first tile
+    EarlyPartials<4> ep;
+    ep.load(res_partials + mb.bf, rstride, mb.nbf);
+    __shared__ T sA[FragLds<K, T>::alloc];
+    const T *gfr[1] = {ghat_frags(mb, T(0))};
+    const T *fr[1];
+    FragStage<K, T> fs;
+    fs.load(gfr);
+    rin += mb.to; r += mb.to; rh += mb.to; pout += mb.to; vout += mb.to; d += mb.to;
+    const T *src[1] = {rin};
+    const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
+    StagedTile<K, T, 1> st;
+    // unconditional: a block without tiles loads tile 0 and never commits it
+    st.load(tw.first < tw.end ? tw.first : 0, mb, src);
+    double nrm[4];
+    ep.finish(nrm);
+    fs.store(sA, fr);
+    const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
+    const double relres = gg > 0.0 ? sqrt(rr / gg) : sqrt(rr);
+    const bool finite = isfinite(rr) && isfinite(gg) && isfinite(rinrin);
+    if (!finite || relres <= refine_rtol) {
+        if (lb == 0 && threadIdx.x == 0) {
+            ks->relres = finite ? relres : NAN;
+            ks->stage_done = 1;
+            ks->conv = 1;
+        }
+        return;
+    }
+    const double fl = 0.1 * refine_rtol;
+    const double tol2 = fmax(inner_rtol * inner_rtol * rinrin, fl * fl * ghh);
+    __shared__ T sB[TileLds<K, T>::n];
+    const uint32_t nel = mb.nel;
+    double acc1[3] = {0.0, 0.0, 0.0};
+    for (int tile = tw.first; tile < tw.end; tile += tw.step) {
+        auto prefetch = [&] {
+            const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
+            st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
+        };
+        const WaveFaces wf = wave_faces(tile, mb);
+        T rv[NMB][4];
+        uint32_t o[NMB][4];
+        bool ok[NMB][4];
+#pragma unroll
+        for (int m = 0; m < NMB; ++m)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
+                rv[m][e4] = rin[ok[m][e4] ? o[m][e4] : 0u];
+            }
+        typename MfmaT<T>::v4 acc[1][NMB];
+        face_rows<K, 1>(fr, st, mb, wf, sB, src,
+                        [&](const T (&a)[1], uint32_t off, bool own) {
+                            if (own) {
+                                r[off] = a[0];
+                                rh[off] = a[0];
+                                pout[off] = a[0];
+                                d[off] = T(0);
+                            }
+                            return a[0];
+                        },
+                        acc, prefetch);
+#pragma unroll
+        for (int m = 0; m < NMB; ++m)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4)
+                if (ok[m][e4]) {
+                    const double y = acc[0][m][e4], rd = rv[m][e4];
+                    vout[o[m][e4]] = (T)y;
+                    acc1[0] += rd * y;
+                    acc1[1] += rd * rd;
+                    acc1[2] += rd * rd;
+                }
+    }
+    store_partials<3>(acc1, P1, stride);
+    if (lb == 0 && threadIdx.x == 0) {
+        const bool done = rinrin <= tol2;
+        ks->relres = relres;
+        ks->rho = 1.0;
+        ks->alpha = 1.0;
+        ks->omega = 1.0;
+        ks->rr = rinrin;
+        ks->rv = 0.0;
+        ks->tol2 = tol2;
+        ks->conv = done ? 1 : 0;
+        ks->breakdown = 0;
+        ks->iters = 0;
+        ks->sweep += 1;
+    }
 }
 
 // K2: rho = rh.r, rr = r.r and rv = rh.v from partials P1 (exact dot
@@ -1708,84 +1875,6 @@ __global__ void k_axpy(double *__restrict__ y, const T *__restrict__ x, double a
 // captured in a graph); the decisions the host-driven loop takes after a
 // read-back are taken here on the device, and launches past convergence
 // return at entry.
-// One block per member.
-__global__ void k_stage_begin(KrylovState *ks_all) {
-    KrylovState *ks = ks_all + blockIdx.x;
-    if (threadIdx.x == 0) {
-        ks->stage_done = 0;
-        ks->sweep = 0;
-        ks->relres = 0.0;
-        ks->conv = 1;          // no inner solve active until refine_check opens one
-        ks->iters = 0;
-        for (int i = 0; i < 8; ++i) ks->sweep_iters[i] = 0;
-    }
-}
-
-// Reduce the member's FP64 residual norms of the last trace_residual
-// (partials [4][face blocks]); stop its stage solve if relres <=
-// refine_rtol, else start an inner solve on Ghat d = rin (as k_bicg_init)
-// with tolerance max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2).
-template <typename T>
-__global__ void k_refine_check(const Batch bt, int K, const T *__restrict__ rin,
-                               T *__restrict__ r, T *__restrict__ rh, T *__restrict__ p,
-                               T *__restrict__ v, T *__restrict__ d, KrylovState *ks_all,
-                               const double *res_partials, int stride, double refine_rtol,
-                               double inner_rtol, double *P3) {
-    int lb;
-    const int mi = member_of<CE>(bt, blockIdx.x, lb);
-    KrylovState *ks = ks_all + mi;
-    if (ks->stage_done) return;
-    const Member mb = load_member(bt, mi);
-    double nrm[4];
-    reduce_partials<4>(res_partials + mb.bf, stride, mb.nbf, nrm);
-    const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
-    const double relres = gg > 0.0 ? sqrt(rr / gg) : sqrt(rr);
-    const bool finite = isfinite(rr) && isfinite(gg) && isfinite(rinrin);
-    if (!finite || relres <= refine_rtol) {
-        if (lb == 0 && threadIdx.x == 0) {
-            ks->relres = finite ? relres : NAN;
-            ks->stage_done = 1;
-            ks->conv = 1;
-        }
-        return;
-    }
-    const double fl = 0.1 * refine_rtol;
-    const double tol2 = fmax(inner_rtol * inner_rtol * rinrin, fl * fl * ghh);
-    rin += mb.to; r += mb.to; rh += mb.to; p += mb.to; v += mb.to; d += mb.to;
-    double acc[2] = {0.0, 0.0};
-    const ElemRange er = elem_range(mb, lb, K);
-    const size_t bd = blockDim.x;
-    for (size_t i0 = er.i0; i0 < er.n; i0 += er.span) {
-        T x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = (i0 + u * bd < er.n) ? rin[i0 + u * bd] : T(0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const size_t i = i0 + u * bd;
-            if (i < er.n) {
-                r[i] = x[u]; rh[i] = x[u]; p[i] = T(0); v[i] = T(0); d[i] = T(0);
-                const double xd = x[u];
-                acc[0] += xd * xd;
-                acc[1] += xd * xd;
-            }
-        }
-    }
-    store_partials<2>(acc, P3, stride);
-    if (lb == 0 && threadIdx.x == 0) {
-        ks->relres = relres;
-        ks->rho = 1.0;
-        ks->alpha = 1.0;
-        ks->omega = 1.0;
-        ks->rr = 0.0;
-        ks->rv = 0.0;
-        ks->tol2 = tol2;
-        ks->conv = 0;
-        ks->breakdown = 0;
-        ks->iters = 0;
-        ks->sweep += 1;
-    }
-}
-
 // x += d after a sweep, unless the member's stage solve had already
 // converged.
 template <typename T>
@@ -1819,34 +1908,6 @@ __global__ void k_axpy_guarded(const Batch bt, int K, double *__restrict__ y,
     }
 }
 
-// After the last sweep, one block per member: if the solve never met
-// refine_rtol, take the residual of the final trace_residual; record the
-// outcome.
-__global__ void k_stage_finish(const Batch bt, KrylovState *ks_all, const double *res_partials,
-                               int stride, StageStatus *out_all) {
-    const int mi = blockIdx.x;
-    KrylovState *ks = ks_all + mi;
-    const Member mb = load_member(bt, mi);
-    double relres = ks->relres;
-    const int done = ks->stage_done;
-    if (!done) {
-        double nrm[2];
-        reduce_partials<2>(res_partials + mb.bf, stride, mb.nbf, nrm);
-        relres = nrm[1] > 0.0 ? sqrt(nrm[0] / nrm[1]) : sqrt(nrm[0]);
-    }
-    if (threadIdx.x == 0) {
-        StageStatus *out = out_all + mi;
-        out->relres = relres;
-        out->converged = done;
-        out->sweeps = ks->sweep;
-        int tot = 0;
-        for (int i = 0; i < kMaxSweeps; ++i) {
-            out->sweep_iters[i] = ks->sweep_iters[i];
-            tot += out->sweep_iters[i];
-        }
-        out->iters_total = tot;
-    }
-}
 
 // --------------------------------------------------------- diagnostics
 // Partials of (mass phi_eta, mass U, mass V, energy, non-finite count).
@@ -1916,15 +1977,17 @@ template <int K> struct RunLocal {
 };
 template <int K> struct RunRecover {
     static hipError_t run(const Batch &b, const double *Z, const double *qh, double *Q,
-                          hipStream_t s) {
-        KLAUNCH(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q);
+                          const KrylovState *ks, const double *part, int stride,
+                          StageStatus *status, hipStream_t s) {
+        KLAUNCH(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q, ks, part, stride,
+                status);
         return hipGetLastError();
     }
 };
 template <int K> struct RunTraceRhs {
     static hipError_t run(const Geom &g, const Batch &b, const double *Z, double *gv,
-                          double *gh, hipStream_t s) {
-        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, gh);
+                          double *gh, KrylovState *begin, hipStream_t s) {
+        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, gh, begin);
         return hipGetLastError();
     }
 };
@@ -1952,6 +2015,18 @@ template <typename T> struct RunK1 {
                 KLAUNCH((k_bicg_k1<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
                                    s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
                                    kb.stride);
+            return hipGetLastError();
+        }
+    };
+};
+template <typename T> struct RunRefineK1 {
+    template <int K> struct F {
+        static hipError_t run(const Batch &b, const T *rin, T *r, T *rh, T *p, T *v, T *d,
+                              KrylovState *ks, const double *partials, int pstride,
+                              double refine_rtol, double inner_rtol, const KrylovBufs &kb,
+                              hipStream_t s) {
+            KLAUNCH((k_refine_k1<K, T>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b, rin, r, rh,
+                    p, v, d, ks, partials, pstride, refine_rtol, inner_rtol, kb.P1, kb.stride);
             return hipGetLastError();
         }
     };
@@ -2037,13 +2112,14 @@ hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, do
 }
 
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
-                            double *ghat, hipStream_t s) {
-    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, ghat, s);
+                            double *ghat, hipStream_t s, KrylovState *begin) {
+    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, ghat, begin, s);
 }
 
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
-                          double *Q, hipStream_t s) {
-    return dispatch<RunRecover>(g.K, b, Z, qhat, Q, s);
+                          double *Q, hipStream_t s, const KrylovState *ks,
+                          const double *partials, int stride, StageStatus *status) {
+    return dispatch<RunRecover>(g.K, b, Z, qhat, Q, ks, partials, stride, status, s);
 }
 
 #define IMEXHDG_KRYLOV_LAUNCHERS(T)                                                            \
@@ -2083,13 +2159,12 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
         KLAUNCH(k_axpy<T>, dim3(grid1(n, 256)), dim3(256), 0, s, y, x, a, n);     \
         return hipGetLastError();                                                              \
     }                                                                                          \
-    hipError_t launch_refine_check(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,  \
-                                   T *p, T *v, T *d, KrylovState *ks, const double *partials, \
-                                   int stride, double refine_rtol, double inner_rtol,         \
-                                   const KrylovBufs &kb, hipStream_t s) {                     \
-        KLAUNCH(k_refine_check<T>, dim3(b.nbe), dim3(256), 0, s, b, g.K, rin, r,   \
-                           rh, p, v, d, ks, partials, stride, refine_rtol, inner_rtol, kb.P3); \
-        return hipGetLastError();                                                              \
+    hipError_t launch_refine_k1(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
+                                T *p, T *v, T *d, KrylovState *ks, const double *partials,    \
+                                int stride, double refine_rtol, double inner_rtol,            \
+                                const KrylovBufs &kb, hipStream_t s) {                        \
+        return dispatch<RunRefineK1<T>::template F>(g.K, b, rin, r, rh, p, v, d, ks, partials, \
+                                                    stride, refine_rtol, inner_rtol, kb, s);  \
     }                                                                                          \
     hipError_t launch_axpy_guarded(const Geom &g, const Batch &b, double *y, const T *x,      \
                                    KrylovState *ks, hipStream_t s) {                          \
@@ -2100,18 +2175,6 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 IMEXHDG_KRYLOV_LAUNCHERS(double)
 IMEXHDG_KRYLOV_LAUNCHERS(float)
 #undef IMEXHDG_KRYLOV_LAUNCHERS
-
-hipError_t launch_stage_begin(const Batch &b, KrylovState *ks, hipStream_t s) {
-    KLAUNCH(k_stage_begin, dim3(b.nm), dim3(64), 0, s, ks);
-    return hipGetLastError();
-}
-
-hipError_t launch_stage_finish(const Batch &b, KrylovState *ks, const double *partials,
-                               int stride, StageStatus *out, hipStream_t s) {
-    KLAUNCH(k_stage_finish, dim3(b.nm), dim3(256), 0, s, b, ks, partials, stride,
-                       out);
-    return hipGetLastError();
-}
 
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
                        int stride, hipStream_t s) {

@@ -120,10 +120,15 @@ hipError_t launch_linear_residual(const Geom &g, const Batch &b, const double *Q
                                   const double *qhat, double *out, hipStream_t s);
 hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, double *Z,
                               hipStream_t s);
+// begin (fixed schedule): also reset each member's stage-solve state.
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
-                            double *ghat, hipStream_t s);
+                            double *ghat, hipStream_t s, KrylovState *begin = nullptr);
+// status (fixed schedule): also record each member's stage-solve outcome
+// from ks and the final trace_residual's partials [4][stride].
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
-                          double *Q, hipStream_t s);
+                          double *Q, hipStream_t s, const KrylovState *ks = nullptr,
+                          const double *partials = nullptr, int stride = 0,
+                          StageStatus *status = nullptr);
 // FP64 r = g - G x (its norm only) and rin = ghat - Ghat x (stored in the
 // inner solve's precision); partials [4][face blocks] of ||r||^2, ||g||^2,
 // ||ghat||^2, ||rin||^2.  With `skip`, members whose stage solve is done return.
@@ -153,25 +158,23 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 IMEXHDG_KRYLOV_DECLS(double)
 IMEXHDG_KRYLOV_DECLS(float)
 #undef IMEXHDG_KRYLOV_DECLS
-// Device-driven refinement (no host reads inside a stage solve):
-//   stage_begin; then per sweep: trace_residual(skip = ks),
-//   refine_check (reduces the residual norms, stops the member's stage
-//   solve when relres <= refine_rtol, else initialises its inner solve with
-//   its tolerance), inner iterations, axpy_guarded; finally trace_residual
-//   and stage_finish, which records a StageStatus per member.
-hipError_t launch_stage_begin(const Batch &b, KrylovState *ks, hipStream_t s);
+// Device-driven refinement (no host reads inside a stage solve), per
+// stage: trace_rhs(begin = ks); per sweep trace_residual(skip = ks),
+// refine_k1 (reduces the residual norms, ends the member's stage solve
+// when relres <= refine_rtol, else starts its inner solve with its
+// tolerance and runs the first K1), the inner iterations and
+// axpy_guarded; finally trace_residual and recover(status), which records
+// a StageStatus per member.
 #define IMEXHDG_REFINE_DECLS(T)                                                                \
-    hipError_t launch_refine_check(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,  \
-                                   T *p, T *v, T *d, KrylovState *ks, const double *partials, \
-                                   int stride, double refine_rtol, double inner_rtol,         \
-                                   const KrylovBufs &kb, hipStream_t s);                      \
+    hipError_t launch_refine_k1(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
+                                T *p, T *v, T *d, KrylovState *ks, const double *partials,    \
+                                int stride, double refine_rtol, double inner_rtol,            \
+                                const KrylovBufs &kb, hipStream_t s);                         \
     hipError_t launch_axpy_guarded(const Geom &g, const Batch &b, double *y, const T *x,      \
                                    KrylovState *ks, hipStream_t s);
 IMEXHDG_REFINE_DECLS(double)
 IMEXHDG_REFINE_DECLS(float)
 #undef IMEXHDG_REFINE_DECLS
-hipError_t launch_stage_finish(const Batch &b, KrylovState *ks, const double *partials,
-                               int stride, StageStatus *out, hipStream_t s);
 
 // partials [5][diag blocks]: mass of phi_eta, U, V; energy; non-finite count
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
