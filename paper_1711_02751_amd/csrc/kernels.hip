@@ -786,6 +786,150 @@ __global__ __launch_bounds__(256) void k_recover(const double *__restrict__ Z,
         }
 }
 
+// The same two contractions with the shared matrix staged in LDS once per
+// block (its fragments are otherwise read from L2 by every wave) and every
+// global load issued up front: the matrix fragments, this lane's B column
+// for all k steps, and (recover) the Z values of its epilogue.  For the
+// degrees whose matrix fits in 64 KB.
+template <int NR, int NC> struct LocalLds {
+    using LM = LocalMF<NR, NC>;
+    static constexpr int NA = LM::NMB * LM::KS * 64;   // doubles of packed fragments
+    static constexpr bool value = NA * 8 <= 64 * 1024;
+    static constexpr int PER = (NA + 255) / 256;       // per thread of a 256-thread block
+};
+
+// Fragment loads of the packed matrix (A operand), to LDS after the caller
+// has issued its other loads.
+template <int NA, int PER> struct MatStage {
+    double v[PER];
+    __device__ __forceinline__ void load(const double *__restrict__ A) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            v[u] = A[i < NA ? i : 0];   // unconditional (see EarlyPartials)
+        }
+    }
+    __device__ __forceinline__ void store(double *sA) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            if (i < NA) sA[i] = v[u];
+        }
+    }
+};
+
+template <int K>
+__global__ __launch_bounds__(256, 3) void k_local_apply_lds(const double *__restrict__ R,
+                                                         const Batch bt, double *__restrict__ Z) {
+    constexpr int NL = 3 * K * K;
+    using LL = LocalLds<NL, NL>;
+    using LM = typename LL::LM;
+    __shared__ double sA[LL::NA];
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    R += mb.vo;
+    Z += mb.vo;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+    const int e = lb * 64 + w * 16 + (lane & 15);
+    const bool active = e < mb.nel;
+    const size_t nel = mb.nel, ec = active ? e : 0;
+    MatStage<LL::NA, LL::PER> ms;
+    ms.load(mb.Ainv);
+    // B of k step kk: row 4 kk + q of R at this lane's element
+    double b[LM::KS];
+#pragma unroll
+    for (int kk = 0; kk < LM::KS; ++kk) {
+        const int row = 4 * kk + q;
+        b[kk] = R[(size_t)(row < NL ? row : 0) * nel + ec];
+    }
+    ms.store(sA);
+    lds_barrier();
+    v4d acc[LM::NMB];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m) acc[m] = v4d{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < LM::KS; ++kk) {
+        const double bk = 4 * kk + q < NL ? b[kk] : 0.0;
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(m * LM::KS + kk) * 64 + lane], bk,
+                                                          acc[m], 0, 0, 0);
+    }
+    if (!active) return;
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * r + q;
+            if (row < NL) Z[(size_t)row * nel + e] = acc[m][r];
+        }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_recover_lds(const double *__restrict__ Z,
+                                                     const double *__restrict__ qh,
+                                                     const Batch bt, double *__restrict__ Q,
+                                                     const KrylovState *fks, const double *fpart,
+                                                     int fstride, StageStatus *fout) {
+    constexpr int NL = 3 * K * K, NT = 12 * K;
+    using LL = LocalLds<NL, NT>;
+    using LM = typename LL::LM;
+    __shared__ double sA[LL::NA];
+    int lb;
+    const int mi = member_of<CV>(bt, blockIdx.x, lb);
+    const Member mb = load_member(bt, mi);
+    if (fout != nullptr && lb == 0) stage_finish_block(mb, fks + mi, fpart, fstride, fout + mi);
+    Z += mb.vo;
+    qh += mb.to;
+    Q += mb.vo;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+    const int e = lb * 64 + w * 16 + (lane & 15);
+    const bool active = e < mb.nel;
+    const size_t nel = mb.nel, ec = active ? e : 0;
+    const Nbr nb = neighbours((int)ec, mb.nx, mb.ny);
+    MatStage<LL::NA, LL::PER> ms;
+    ms.load(mb.W);
+    // B of k step kk: local trace 4 kk + q of this lane's element
+    double b[LM::KS];
+#pragma unroll
+    for (int kk = 0; kk < LM::KS; ++kk) {
+        const int t = 4 * kk + q < NT ? 4 * kk + q : 0;
+        const int f = t / (3 * K), cj = t - f * 3 * K;
+        const int face = f == 1 ? nb.east : f == 3 ? nb.north : nb.e;
+        b[kk] = qh[(f >= 2 ? (size_t)3 * K * nel : 0) + (size_t)cj * nel + face];
+    }
+    ms.store(sA);
+    // the epilogue's Z values, in flight during the contraction
+    double z[LM::NMB][4];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * r + q;
+            z[m][r] = Z[(size_t)(row < NL ? row : 0) * nel + ec];
+        }
+    lds_barrier();
+    v4d acc[LM::NMB];
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m) acc[m] = v4d{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < LM::KS; ++kk) {
+        const double bk = 4 * kk + q < NT ? b[kk] : 0.0;
+#pragma unroll
+        for (int m = 0; m < LM::NMB; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(m * LM::KS + kk) * 64 + lane], bk,
+                                                          acc[m], 0, 0, 0);
+    }
+    if (!active) return;
+#pragma unroll
+    for (int m = 0; m < LM::NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * r + q;
+            if (row < NL) Q[(size_t)row * nel + e] = z[m][r] - acc[m][r];
+        }
+}
+
 // Workgroups per CU the matrix-core kernels are compiled for (8 waves
 // each): the register budget that keeps them free of scratch spills.
 template <int K> struct MFOcc {
@@ -1971,7 +2115,10 @@ template <int K> struct RunLinres {
 };
 template <int K> struct RunLocal {
     static hipError_t run(const Batch &b, const double *R, double *Z, hipStream_t s) {
-        KLAUNCH(k_local_apply<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
+        if constexpr (LocalLds<3 * K * K, 3 * K * K>::value)
+            KLAUNCH(k_local_apply_lds<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
+        else
+            KLAUNCH(k_local_apply<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
         return hipGetLastError();
     }
 };
@@ -1979,8 +2126,12 @@ template <int K> struct RunRecover {
     static hipError_t run(const Batch &b, const double *Z, const double *qh, double *Q,
                           const KrylovState *ks, const double *part, int stride,
                           StageStatus *status, hipStream_t s) {
-        KLAUNCH(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q, ks, part, stride,
-                status);
+        if constexpr (LocalLds<3 * K * K, 12 * K>::value)
+            KLAUNCH(k_recover_lds<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q, ks, part,
+                    stride, status);
+        else
+            KLAUNCH(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q, ks, part, stride,
+                    status);
         return hipGetLastError();
     }
 };
