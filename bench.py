@@ -54,9 +54,9 @@ def algorithmic_cost(name, wl, n_dof, isz=8):
     table = {
         # first K1 of a solve: read r, p, v, rh; write p, v
         "bicg_k1": (6 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
-        # read r, v, rh; write s, t
-        "bicg_k2": (5 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
-        # fused K1: read s, t, p, v, rh, d; write r, p, v, d
+        # read r, v, rh; write t (s = r - alpha v is formed, not stored)
+        "bicg_k2": (4 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
+        # fused K1: read r, t, p, v, rh, d; write r, p, v, d
         "bicg_k1f": (10 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
         # read x, g, ghat (FP64); write rin (inner)
         "trace_residual": (3 * T * 8 + T * isz, 4.0 * 7 * b3 * b3 * nfaces),
@@ -269,8 +269,9 @@ def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
     n_dof = 3 * sum(E.n_nodes)
     log(f"[bench] ensemble: {len(members)} members, {n_dof} DOFs; warmup {max(warmup, 3)}")
     E.step(max(warmup, 3))
-    fg = E.autotune(tune_cache)
-    log(f"[bench] ensemble: autotuned face grid cap per member: {fg}")
+    fg, tpb = E.autotune(tune_cache)
+    log(f"[bench] ensemble: autotuned face blocks per member: "
+        + (f"{tpb} tiles per block" if tpb else f"cap {fg}"))
     E.step(1)
     d0 = E.diag(0)
     torch.cuda.synchronize()
@@ -289,6 +290,7 @@ def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
            "precision": "mixed" if mixed else "fp64",
            "schedule": {"sweeps": E.schedule()[0], "inner_budget": E.schedule()[1]},
            "face_grid_cap_per_member": fg,
+           "face_tiles_per_block": tpb,
            "graph_steps": d1["graph_steps"] - d0["graph_steps"],
            "redone_steps": d1["redo_steps"] - d0["redo_steps"]}
     E.close()

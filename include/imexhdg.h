@@ -305,16 +305,23 @@ int imexhdg_ens_step(imexhdg_ens *ens, int32_t nsteps);
 /* Member m's mass and energy; the solver counters are the ensemble's.    */
 int imexhdg_ens_get_diag(imexhdg_ens *ens, int32_t m, imexhdg_diag *d);
 int imexhdg_ens_get_schedule(const imexhdg_ens *ens, int32_t *sweeps, int32_t *budget);
+/* Caps every member's face-class blocks at face_grid (and drops a
+ * tiles-per-block sizing chosen by imexhdg_ens_autotune).                 */
 int imexhdg_ens_set_launch_geometry(imexhdg_ens *ens, int32_t face_grid,
                                     int32_t elem_grid);
-/* Tune the face-class grid cap per member (16 ... 1024 blocks) by timing
- * graph steps from the current state, which is restored afterwards with its
- * trace guess (solver counters kept).  Launches of members that have
- * converged still run their blocks as no-ops, so the best cap balances
- * parallelism against that overhead.  cache_path: as for imexhdg_autotune
- * (one line per device, degree, member count, element count and
- * precision).  The choice is returned in *face_grid when not NULL.       */
-int imexhdg_ens_autotune(imexhdg_ens *ens, const char *cache_path, int32_t *face_grid);
+/* Tune the face-class blocks per member by timing graph steps from the
+ * current state, which is restored afterwards with its trace guess (solver
+ * counters kept).  Candidates: a cap per member (16 ... 1024 blocks), or a
+ * number of 16 x 4-element tiles per block (2 ... 8: every block of every
+ * member has the same work, so a large member's blocks do not form the
+ * tail of a launch).  Launches of members that have converged still run
+ * their blocks as no-ops, so the choice balances parallelism against that
+ * overhead.  cache_path: as for imexhdg_autotune (one line per device,
+ * degree, member count, element count and precision).  The cap is returned
+ * in *face_grid (4096 when the blocks are sized by tiles) and the tiles per
+ * block in *tiles_per_block (0: capped), each when not NULL.              */
+int imexhdg_ens_autotune(imexhdg_ens *ens, const char *cache_path, int32_t *face_grid,
+                         int32_t *tiles_per_block);
 
 #ifdef __cplusplus
 }

@@ -120,6 +120,7 @@ struct imexhdg_ctx {
     Member *dmem = nullptr;
     Batch bt{};
     int fgrid = 1024, egrid = 1024;   // launch-geometry caps
+    int ftpb = 0;                     // > 0: face blocks per member = tiles / ftpb (ensembles)
     int pstride = 0;                  // stride of every partial-sum array
     hipStream_t stream = nullptr;
     int device = 0;
@@ -143,8 +144,9 @@ struct imexhdg_ctx {
     double *xsave = nullptr;          // autotuner's copy of the trace guess
     // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
     bool mixed = false;
-    void *rin = nullptr, *kr = nullptr, *krh = nullptr, *kp[2] = {nullptr, nullptr},
-         *kv[2] = {nullptr, nullptr}, *ks_ = nullptr, *kt = nullptr, *kd = nullptr;
+    void *rin = nullptr, *kr[2] = {nullptr, nullptr}, *krh = nullptr,
+         *kp[2] = {nullptr, nullptr}, *kv[2] = {nullptr, nullptr}, *kt = nullptr,
+         *kd = nullptr;
     KrylovState *ks = nullptr;        // [nm]
     KrylovBufs kb{};
     double *dpart = nullptr;          // [5][pstride] residual / diagnostics partials
@@ -436,7 +438,7 @@ int build_batch(imexhdg_ctx *c) {
         d.bv = bv;
         d.nbv = member_vol_blocks(h.nel);
         d.bf = bf;
-        d.nbf = member_face_blocks(h.nx, h.ny, c->fgrid);
+        d.nbf = member_face_blocks(h.nx, h.ny, c->fgrid, c->ftpb);
         d.be = be;
         d.nbe = member_elem_blocks(h.nel, K, c->egrid);
         d.bd = bd;
@@ -561,15 +563,16 @@ int inner_solve(imexhdg_ctx *c, double tol2, int sweep) {
     const imexhdg_config &cf = c->cfg;
     const Geom &g = c->geom;
     const Batch &b = c->bt;
-    T *rin = (T *)c->rin, *r = (T *)c->kr, *rh = (T *)c->krh, *sv = (T *)c->ks_,
-      *t = (T *)c->kt, *d = (T *)c->kd;
+    T *rin = (T *)c->rin, *rh = (T *)c->krh, *t = (T *)c->kt, *d = (T *)c->kd;
     T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
+    T *r[2] = {(T *)c->kr[0], (T *)c->kr[1]};
     int rc;
     LAUNCH(IMEXHDG_K_BICG_INIT,
-           launch_bicg_init(g, b, (const T *)rin, r, rh, p[0], v[0], d, c->ks, tol2, c->kb,
+           launch_bicg_init(g, b, (const T *)rin, r[0], rh, p[0], v[0], d, c->ks, tol2, c->kb,
                             c->stream));
     int par = 0;     // p, v of the current iteration live in p[par], v[par]
-    LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, b, r, rh, p[par], v[par], p[1 - par],
+    int rp = 0;      // r in r[rp]
+    LAUNCH(IMEXHDG_K_BICG_K1, launch_bicg_k1(g, b, r[rp], rh, p[par], v[par], p[1 - par],
                                              v[1 - par], c->ks, c->kb, c->stream));
     par = 1 - par;
     int done = 0;
@@ -579,11 +582,12 @@ int inner_solve(imexhdg_ctx *c, double tol2, int sweep) {
         chunk = std::min(2, cf.check_every);
         for (int it = 0; it < n; ++it) {
             LAUNCH(IMEXHDG_K_BICG_K2,
-                   launch_bicg_k2(g, b, r, v[par], rh, sv, t, c->ks, c->kb, c->stream));
+                   launch_bicg_k2(g, b, r[rp], v[par], rh, t, c->ks, c->kb, c->stream));
             LAUNCH(IMEXHDG_K_BICG_K1F,
-                   launch_bicg_k1f(g, b, sv, t, rh, p[par], v[par], p[1 - par], v[1 - par], r,
-                                   d, c->ks, c->kb, c->stream));
+                   launch_bicg_k1f(g, b, r[rp], t, rh, p[par], v[par], p[1 - par], v[1 - par],
+                                   r[1 - rp], d, c->ks, c->kb, c->stream));
             par = 1 - par;
+            rp = 1 - rp;
         }
         done += n;
         if ((rc = sync_read_ks(c))) return rc;
@@ -713,22 +717,23 @@ template <typename T>
 int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     const Geom &g = c->geom;
     const Batch &b = c->bt;
-    T *rin = (T *)c->rin, *r = (T *)c->kr, *rh = (T *)c->krh, *sv = (T *)c->ks_,
-      *t = (T *)c->kt, *d = (T *)c->kd;
+    T *rin = (T *)c->rin, *rh = (T *)c->krh, *t = (T *)c->kt, *d = (T *)c->kd;
     T *p[2] = {(T *)c->kp[0], (T *)c->kp[1]}, *v[2] = {(T *)c->kv[0], (T *)c->kv[1]};
+    T *r[2] = {(T *)c->kr[0], (T *)c->kr[1]};
     KrylovBufs kb = c->kb;
     kb.sched = 1;
     HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, c->gh, rin, c->dpart, c->pstride,
                                   c->ks, c->stream));
     // the refinement check and the first K1 of the inner solve in one launch
-    HIP_TRY(launch_refine_k1(g, b, (const T *)rin, r, rh, p[1], v[1], d, c->ks, c->dpart,
+    HIP_TRY(launch_refine_k1(g, b, (const T *)rin, r[0], rh, p[1], v[1], d, c->ks, c->dpart,
                              c->pstride, c->cfg.refine_rtol, inner_rtol, kb, c->stream));
-    int par = 1;
+    int par = 1, rp = 0;
     for (int it = 0; it < budget; ++it) {
-        HIP_TRY(launch_bicg_k2(g, b, r, v[par], rh, sv, t, c->ks, kb, c->stream));
-        HIP_TRY(launch_bicg_k1f(g, b, sv, t, rh, p[par], v[par], p[1 - par], v[1 - par], r, d,
-                                c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k2(g, b, r[rp], v[par], rh, t, c->ks, kb, c->stream));
+        HIP_TRY(launch_bicg_k1f(g, b, r[rp], t, rh, p[par], v[par], p[1 - par], v[1 - par],
+                                r[1 - rp], d, c->ks, kb, c->stream));
         par = 1 - par;
+        rp = 1 - rp;
     }
     HIP_TRY(launch_axpy_guarded(g, b, c->x, (const T *)d, c->ks, c->stream));
     return IMEXHDG_OK;
@@ -1252,8 +1257,8 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
     double **tv[4] = {&c->x, &c->gv, &c->gh, &c->xsave};
     for (double **p : tv) *p = (double *)take(L.T * 8);
-    void **iv[10] = {&c->rin, &c->kr, &c->krh, &c->kp[0], &c->kp[1],
-                     &c->kv[0], &c->kv[1], &c->ks_, &c->kt, &c->kd};
+    void **iv[10] = {&c->rin, &c->kr[0], &c->krh, &c->kp[0], &c->kp[1],
+                     &c->kv[0], &c->kv[1], &c->kr[1], &c->kt, &c->kd};
     for (void **p : iv) *p = take(L.T * (c->mixed ? 4 : 8));
     const size_t n_loc = 3 * K * K, n_tr = 12 * K;
     for (OpSet &o : c->ops) {
@@ -1728,11 +1733,14 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
 }
 
 // ------------------------------------------------------------- ensembles
-// Ensemble autotuner: the face-class grid cap per member sets how many
-// blocks every face launch has; members that have converged still launch
-// theirs (as no-ops), so fewer blocks per member can win.  Times graph
+// Ensemble autotuner: the face blocks of each member are either capped
+// (fg) or sized to a number of tiles per block (tpb > 0, the same work per
+// block whatever the member's size, so that no large member's blocks form
+// the tail of a launch); members that have converged still launch their
+// blocks (as no-ops), so fewer blocks per member can win.  Times graph
 // steps (one warm step, then two) from a saved state for each candidate.
-static int ens_trial(imexhdg_ctx *c, int fg, double *ms) {
+static int ens_trial(imexhdg_ctx *c, int fg, int tpb, double *ms) {
+    c->ftpb = tpb;
     int rc = imexhdg_set_launch_geometry(c, fg, c->egrid);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1746,7 +1754,8 @@ static int ens_trial(imexhdg_ctx *c, int fg, double *ms) {
     return IMEXHDG_OK;
 }
 
-int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_grid) {
+int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_grid,
+                         int32_t *tiles_per_block) {
     if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
     imexhdg_ctx *c = e->c;
     if (!c->have_state) return fail(IMEXHDG_E_STATE, "autotune needs a state");
@@ -1759,7 +1768,7 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
        << c->cfg.degree << " members=" << c->nm << " elements=" << nel
        << " prec=" << c->cfg.precision;
     const std::string key = ks.str();
-    int best_f = -1;
+    int best_f = -1, best_t = 0;
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
@@ -1768,10 +1777,14 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
             if (t1 == std::string::npos || t1 != key.size() || line.compare(0, t1, key) != 0)
                 continue;
             std::istringstream rest(line.substr(t1 + 1));
-            int f = 0;
+            int f = 0, t = 0;
             if (!(rest >> f) || f < 8 || f > kMaxLaunchGrid)
                 return fail(IMEXHDG_E_INVAL, "malformed autotune cache line: " + line);
+            if (!(rest >> t)) t = 0;   // tiles per block: optional
+            if (t < 0 || t > 64)
+                return fail(IMEXHDG_E_INVAL, "malformed autotune cache line: " + line);
             best_f = f;
+            best_t = t;
         }
     }
     if (best_f < 0) {
@@ -1785,18 +1798,24 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
         const int64_t keep[6] = {c->steps, c->kiters, c->solves, c->sweeps, c->graph_steps,
                                  c->redos};
         const double keep_r[2] = {c->last_relres, c->max_relres};
-        const int cand[7] = {16, 32, 48, 64, 96, 128, 1024};
-        const int f0 = c->fgrid;
+        // (cap, tiles per block): caps alone, then uniform tiles per block
+        const int cand[12][2] = {{16, 0},   {32, 0},   {48, 0},   {64, 0},
+                                 {96, 0},   {128, 0},  {1024, 0}, {kMaxLaunchGrid, 2},
+                                 {kMaxLaunchGrid, 3}, {kMaxLaunchGrid, 4},
+                                 {kMaxLaunchGrid, 6}, {kMaxLaunchGrid, 8}};
+        const int f0 = c->fgrid, t0 = c->ftpb;
         double best = 0.0, ms = 0.0;
-        int rc = ens_trial(c, f0, &ms);          // warm-up
-        if (!rc) rc = ens_trial(c, f0, &best);
+        int rc = ens_trial(c, f0, t0, &ms);          // warm-up
+        if (!rc) rc = ens_trial(c, f0, t0, &best);
         best_f = f0;
-        for (int i = 0; i < 7 && !rc; ++i) {
-            if (cand[i] == best_f) continue;
-            if ((rc = ens_trial(c, cand[i], &ms))) break;
+        best_t = t0;
+        for (int i = 0; i < 12 && !rc; ++i) {
+            if (cand[i][0] == best_f && cand[i][1] == best_t) continue;
+            if ((rc = ens_trial(c, cand[i][0], cand[i][1], &ms))) break;
             if (ms < 0.98 * best) {
                 best = ms;
-                best_f = cand[i];
+                best_f = cand[i][0];
+                best_t = cand[i][1];
             }
         }
         HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1811,15 +1830,18 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
         c->last_relres = keep_r[0];
         c->max_relres = keep_r[1];
         if (rc) {
+            c->ftpb = t0;
             (void)imexhdg_set_launch_geometry(c, f0, c->egrid);
             return rc;
         }
         if (cache_path) {
             std::ofstream out(cache_path, std::ios::app);
-            if (out) out << key << '\t' << best_f << '\n';
+            if (out) out << key << '\t' << best_f << '\t' << best_t << '\n';
         }
     }
     if (face_grid) *face_grid = best_f;
+    if (tiles_per_block) *tiles_per_block = best_t;
+    c->ftpb = best_t;
     return imexhdg_set_launch_geometry(c, best_f, c->egrid);
 }
 
@@ -1904,6 +1926,7 @@ int imexhdg_ens_get_schedule(const imexhdg_ens *e, int32_t *sweeps, int32_t *bud
 
 int imexhdg_ens_set_launch_geometry(imexhdg_ens *e, int32_t face_grid, int32_t elem_grid) {
     if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    e->c->ftpb = 0;
     return imexhdg_set_launch_geometry(e->c, face_grid, elem_grid);
 }
 

@@ -1464,17 +1464,17 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
 
 // ------------------------------------------------------------ BiCGStab
 // Left-preconditioned BiCGStab (van der Vorst 1992) on Ghat d = rin, d0 = 0,
-// with the block-Jacobi preconditioner folded into Ghat.  One iteration is
-// three launches:
-//   K1: beta from (rh.r) [partials P3];  p <- r + beta (p - omega v) at the
-//       seven faces each row block reads, v = Ghat p;  partials P1 = rh.v
-//   K2: alpha = rho / (rh.v);  s = r - alpha v on the fly, t = Ghat s;
-//       partials P2 = (t.s, t.t)
-//   K3: omega = (t.s)/(t.t);  d += alpha p + omega s;  r = s - omega t;
-//       partials P3 = (rh.r, r.r)
-// p and v are double buffered because K1 reads the old values at
+// with the block-Jacobi preconditioner folded into Ghat.  A solve is init
+// (or, on the fixed schedule, refine_k1) and a first K1, then two launches
+// per iteration:
+//   K2:  alpha = rho / (rh.v);  s = r - alpha v on the fly, t = Ghat s;
+//        partials P2 = (t.s, t.t, rh.t)
+//   K1f: omega = (t.s)/(t.t);  d += alpha p + omega s;  r' = s - omega t;
+//        p' = r' + beta (p - omega v), v' = Ghat p';
+//        partials P1 = (rh.v', rh.r', r'.r')
+// r, p and v are double buffered because K1f reads the old values at
 // neighbouring faces while writing the new ones.  Convergence (r.r <= tol2)
-// is detected at the start of K1; every later kernel returns at entry.
+// is detected at the start of K2; every later kernel returns at entry.
 // Elementwise trace kernels: the member's nbe blocks run grid-stride loops
 // over its 6 K nel trace values, four values per thread and pass with all
 // loads issued before use.
@@ -1633,7 +1633,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
 }
 
 // A refinement check fused with the first K1 of the sweep's inner solve
-// (fixed launch schedule; it replaces refine_check + K1 there).  Every
+// (fixed launch schedule, where it replaces a separate check kernel and K1).  Every
 // block reduces the member's FP64 residual norms of the last
 // trace_residual (partials [4][face blocks]: ||r||^2, ||g||^2, ||ghat||^2,
 // ||rin||^2).  Once relres = ||r|| / ||g|| <= refine_rtol the member's
@@ -1744,6 +1744,16 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
     }
 }
 
+// s = r - alpha v, formed identically (one fused multiply-add) by K2, which
+// applies Ghat to it, and by K1f, which recomputes it instead of K2 storing
+// it.
+__device__ __forceinline__ float s_of(float r, float al, float v) {
+    return __builtin_fmaf(-al, v, r);
+}
+__device__ __forceinline__ double s_of(double r, double al, double v) {
+    return __builtin_fma(-al, v, r);
+}
+
 // K2: rho = rh.r, rr = r.r and rv = rh.v from partials P1 (exact dot
 // products of the last K1); stop when rr <= tol2; alpha = rho / rv;
 // s = r - alpha v at the seven faces, t = Ghat s; partials P2 = (t.s, t.t,
@@ -1751,7 +1761,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
 template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const Batch bt, const T *__restrict__ r, const T *__restrict__ v,
-    const T *__restrict__ rh, T *__restrict__ sv, T *__restrict__ t, KrylovState *ks_all,
+    const T *__restrict__ rh, T *__restrict__ t, KrylovState *ks_all,
     const double *P1, double *P2, int stride) {
     constexpr int NMB = MF<K>::NMB;
     int lb;
@@ -1769,7 +1779,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const T *fr[1];
     FragStage<K, T> fs;
     fs.load(gfr);
-    r += mb.to; v += mb.to; rh += mb.to; sv += mb.to; t += mb.to;
+    r += mb.to; v += mb.to; rh += mb.to; t += mb.to;
     const T *src[2] = {r, v};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
     StagedTile<K, T, 2> st;
@@ -1818,10 +1828,8 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
             face_rows<K, 1>(fr, st, mb, wf, sB, src,
-                                   [&](const T (&a)[2], uint32_t off, bool own) {
-                                       const T sval = a[0] - al * a[1];
-                                       if (own) sv[off] = sval;
-                                       return sval;
+                                   [&](const T (&a)[2], uint32_t, bool) {
+                                       return s_of(a[0], al, a[1]);
                                    },
                                    acc, prefetch);
             {
@@ -1861,14 +1869,16 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
 //   omega = (t.s)/(t.t) and rh.t from partials P2 of K2;
 //   rho' = rh.(s - omega t) = (rho - alpha rv) - omega rh.t;
 //   beta = (rho'/rho)(alpha/omega);
-//   r' = s - omega t, p' = r' + beta (p - omega v) at the seven faces of
-//   each row block, v' = Ghat p';  d += alpha p + omega s, r', p', v' stored
-//   at the own faces;  partials P1 = (rh.v', rh.r', r'.r').
+//   s = r - alpha v (recomputed as in K2), r' = s - omega t,
+//   p' = r' + beta (p - omega v) at the seven faces of each row block,
+//   v' = Ghat p';  d += alpha p + omega s, r', p', v' stored at the own
+//   faces (r', p' and v' into the other buffer of each pair: neighbouring
+//   blocks still read r, p and v);  partials P1 = (rh.v', rh.r', r'.r').
 // On breakdown (omega or rho' zero or not finite) the d and r updates still
 // complete the iteration, and the solve stops.
 template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
-    const Batch bt, const T *__restrict__ sv, const T *__restrict__ t,
+    const Batch bt, const T *__restrict__ rin, const T *__restrict__ t,
     const T *__restrict__ rh, const T *__restrict__ pin, const T *__restrict__ vin,
     T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ r, T *__restrict__ d,
     KrylovState *ks_all, const double *P2, double *P1, int stride) {
@@ -1888,9 +1898,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const T *fr[1];
     FragStage<K, T> fs;
     fs.load(gfr);
-    sv += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
+    rin += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
     pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
-    const T *src[4] = {sv, t, pin, vin};
+    const T *src[4] = {rin, t, pin, vin};
     // FP32 with the tile held in registers (K <= 7): the staging thread of
     // an own face also reads d and rh there and updates r, p and d.  FP64
     // keeps its registers for occupancy and updates the own faces after the
@@ -1911,7 +1921,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const bool brk = !(omega != 0.0) || !isfinite(omega) || !(rho_new != 0.0) ||
                      !isfinite(rho_new);
     const double beta = brk ? 0.0 : (rho_new / rho) * (alpha / omega);
-    const T be = (T)beta, om = (T)omega;
+    const T be = (T)beta, om = (T)omega, al = (T)alpha;
     __shared__ T sB[TileLds<K, T>::n];
     const uint32_t nel = mb.nel;
     auto rnew = [&](T s_, T t_) { return (T)((double)s_ - omega * (double)t_); };
@@ -1940,7 +1950,9 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     rhv[m][e4] = rh[ok[m][e4] ? o[m][e4] : 0u];
                 }
             typename MfmaT<T>::v4 acc[1][NMB];
-            auto own_update = [&](T s_, T t_, T p_, T v_, T d_, T rh_, uint32_t oo) {
+            // r_ is r at the face; s = r - alpha v as in K2
+            auto own_update = [&](T r_, T t_, T p_, T v_, T d_, T rh_, uint32_t oo) {
+                const T s_ = s_of(r_, al, v_);
                 const T rn = rnew(s_, t_);
                 r[oo] = rn;
                 pout[oo] = pnew(rn, p_, v_);
@@ -1953,13 +1965,13 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                 face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                 [&](const T (&a)[4], const T (&ov)[2], uint32_t off, bool own) {
                                     if (own) own_update(a[0], a[1], a[2], a[3], ov[0], ov[1], off);
-                                    return pnew(rnew(a[0], a[1]), a[2], a[3]);
+                                    return pnew(rnew(s_of(a[0], al, a[3]), a[1]), a[2], a[3]);
                                 },
                                 acc, prefetch);
             } else {
                 face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                 [&](const T (&a)[4], uint32_t, bool) {
-                                    return pnew(rnew(a[0], a[1]), a[2], a[3]);
+                                    return pnew(rnew(s_of(a[0], al, a[3]), a[1]), a[2], a[3]);
                                 },
                                 acc, prefetch);
                 // own faces: all loads first, then the updates
@@ -1970,7 +1982,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     for (int e4 = 0; e4 < 4; ++e4) {
                         const bool k_ = ok[m][e4];
                         const uint32_t oo = o[m][e4];
-                        sv_[m][e4] = sv[k_ ? oo : 0u];
+                        sv_[m][e4] = rin[k_ ? oo : 0u];
                         tv_[m][e4] = t[k_ ? oo : 0u];
                         pv_[m][e4] = pin[k_ ? oo : 0u];
                         vv_[m][e4] = vin[k_ ? oo : 0u];
@@ -2115,7 +2127,9 @@ template <int K> struct RunLinres {
 };
 template <int K> struct RunLocal {
     static hipError_t run(const Batch &b, const double *R, double *Z, hipStream_t s) {
-        if constexpr (LocalLds<3 * K * K, 3 * K * K>::value)
+        // measured: the LDS variant wins at K <= 4; at K = 5 the streamed
+        // one is faster (its 48 KB matrix costs the LDS variant occupancy)
+        if constexpr (K <= 4 && LocalLds<3 * K * K, 3 * K * K>::value)
             KLAUNCH(k_local_apply_lds<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
         else
             KLAUNCH(k_local_apply<K>, dim3(b.nbv), dim3(256), 0, s, R, b, Z);
@@ -2184,30 +2198,30 @@ template <typename T> struct RunRefineK1 {
 };
 template <typename T> struct RunK2 {
     template <int K> struct F {
-        static hipError_t run(const Batch &b, const T *r, const T *v, const T *rh, T *sv,
-                              T *t, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+        static hipError_t run(const Batch &b, const T *r, const T *v, const T *rh, T *t,
+                              KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             if (kb.sched)
                 KLAUNCH((k_bicg_k2<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, v, rh, sv, t, ks, kb.P1, kb.P2, kb.stride);
+                                   s, b, r, v, rh, t, ks, kb.P1, kb.P2, kb.stride);
             else
                 KLAUNCH((k_bicg_k2<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, v, rh, sv, t, ks, kb.P1, kb.P2, kb.stride);
+                                   s, b, r, v, rh, t, ks, kb.P1, kb.P2, kb.stride);
             return hipGetLastError();
         }
     };
 };
 template <typename T> struct RunK1F {
     template <int K> struct F {
-        static hipError_t run(const Batch &b, const T *sv, const T *t, const T *rh,
+        static hipError_t run(const Batch &b, const T *rin, const T *t, const T *rh,
                               const T *pin, const T *vin, T *pout, T *vout, T *r, T *d,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
             if (kb.sched)
                 KLAUNCH((k_bicg_k1f<K, T, true>), dim3(b.nbf), dim3(kFaceThreads),
-                                   0, s, b, sv, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
+                                   0, s, b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
                                    kb.P1, kb.stride);
             else
                 KLAUNCH((k_bicg_k1f<K, T, false>), dim3(b.nbf), dim3(kFaceThreads),
-                                   0, s, b, sv, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
+                                   0, s, b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
                                    kb.P1, kb.stride);
             return hipGetLastError();
         }
@@ -2226,10 +2240,12 @@ template <int K> struct RunDiag {
 
 int member_tiles(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
 
-int member_face_blocks(int nx, int ny, int fgrid) {
+int member_face_blocks(int nx, int ny, int fgrid, int tpb) {
     // a multiple of 8 blocks when there are enough tiles, so that every XCD
     // gets the same number of blocks
-    const int n = std::min(member_tiles(nx, ny), std::min(fgrid, kMaxLaunchGrid));
+    const int tiles = member_tiles(nx, ny);
+    const int want = tpb > 0 ? (tiles + tpb - 1) / tpb : tiles;
+    const int n = std::min(want, std::min(fgrid, kMaxLaunchGrid));
     return n >= 8 ? n & ~7 : n;
 }
 
@@ -2295,15 +2311,15 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
                                               s);                                             \
     }                                                                                          \
     hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v,          \
-                              const T *rh, T *sv, T *t, KrylovState *ks,                      \
-                              const KrylovBufs &kb, hipStream_t s) {                          \
-        return dispatch<RunK2<T>::template F>(g.K, b, r, v, rh, sv, t, ks, kb, s);            \
+                              const T *rh, T *t, KrylovState *ks, const KrylovBufs &kb,       \
+                              hipStream_t s) {                                                \
+        return dispatch<RunK2<T>::template F>(g.K, b, r, v, rh, t, ks, kb, s);                \
     }                                                                                          \
-    hipError_t launch_bicg_k1f(const Geom &g, const Batch &b, const T *sv, const T *t,        \
+    hipError_t launch_bicg_k1f(const Geom &g, const Batch &b, const T *rin, const T *t,       \
                                const T *rh, const T *pin, const T *vin, T *pout, T *vout,     \
                                T *r, T *d, KrylovState *ks, const KrylovBufs &kb,             \
                                hipStream_t s) {                                               \
-        return dispatch<RunK1F<T>::template F>(g.K, b, sv, t, rh, pin, vin, pout, vout, r, d, \
+        return dispatch<RunK1F<T>::template F>(g.K, b, rin, t, rh, pin, vin, pout, vout, r, d,\
                                                ks, kb, s);                                    \
     }                                                                                          \
     hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s) {        \

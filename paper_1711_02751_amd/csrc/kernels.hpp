@@ -101,7 +101,8 @@ struct KrylovBufs {
 
 // Block counts of one member (host side), for grid caps fgrid / egrid.
 int member_tiles(int nx, int ny);                     // 16 x 4 element tiles
-int member_face_blocks(int nx, int ny, int fgrid);    // min(tiles, fgrid), multiple of 8
+// min(tiles, fgrid), multiple of 8; with tpb > 0, min(ceil(tiles / tpb), fgrid)
+int member_face_blocks(int nx, int ny, int fgrid, int tpb = 0);
 int member_elem_blocks(int nel, int K, int egrid);
 int member_vol_blocks(int nel);
 int member_diag_blocks(int nel);
@@ -133,8 +134,10 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 // inner solve's precision); partials [4][face blocks] of ||r||^2, ||g||^2,
 // ||ghat||^2, ||rin||^2.  With `skip`, members whose stage solve is done return.
 // BiCGStab on Ghat d = rin with d0 = 0: init and K1, then per iteration
-// K2 and K1f (the next K1 fused with this iteration's d and r updates);
-// x += d after the sweep.  Each exists for an FP64 and an FP32 inner solve
+// K2 and K1f (the next K1 fused with this iteration's d and r updates;
+// s = r - alpha v is formed by both, never stored, so r is double buffered
+// like p and v: K1f reads r and writes r' to the other buffer); x += d
+// after the sweep.  Each exists for an FP64 and an FP32 inner solve
 // (matrix-core fragments in the same precision).
 #define IMEXHDG_KRYLOV_DECLS(T)                                                                \
     hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
@@ -148,11 +151,11 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
                               const T *pin, const T *vin, T *pout, T *vout, KrylovState *ks,  \
                               const KrylovBufs &kb, hipStream_t s);                           \
     hipError_t launch_bicg_k2(const Geom &g, const Batch &b, const T *r, const T *v,          \
-                              const T *rh, T *sv, T *t, KrylovState *ks,                      \
-                              const KrylovBufs &kb, hipStream_t s);                           \
-    hipError_t launch_bicg_k1f(const Geom &g, const Batch &b, const T *sv, const T *t,        \
+                              const T *rh, T *t, KrylovState *ks, const KrylovBufs &kb,       \
+                              hipStream_t s);                                                 \
+    hipError_t launch_bicg_k1f(const Geom &g, const Batch &b, const T *rin, const T *t,       \
                                const T *rh, const T *pin, const T *vin, T *pout, T *vout,     \
-                               T *r, T *d, KrylovState *ks, const KrylovBufs &kb,             \
+                               T *rout, T *d, KrylovState *ks, const KrylovBufs &kb,          \
                                hipStream_t s);                                                \
     hipError_t launch_axpy(double *y, const T *x, double a, size_t n, hipStream_t s);
 IMEXHDG_KRYLOV_DECLS(double)

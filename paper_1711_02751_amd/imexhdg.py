@@ -123,7 +123,8 @@ def load():
         "imexhdg_ens_get_diag": (ctypes.c_int, [P, i32, ctypes.POINTER(Diag)]),
         "imexhdg_ens_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "imexhdg_ens_set_launch_geometry": (ctypes.c_int, [P, i32, i32]),
-        "imexhdg_ens_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32)]),
+        "imexhdg_ens_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32),
+                                                ctypes.POINTER(i32)]),
         "imexhdg_autotune": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i32),
                                             ctypes.POINTER(i32)]),
     }
@@ -390,8 +391,9 @@ class Ensemble:
                                                         int(elem_grid)))
 
     def autotune(self, cache_path=None):
-        """Tune the per-member face grid cap on the current state; returns it."""
-        f = ctypes.c_int32()
+        """Tune the per-member face blocks on the current state; returns
+        (cap, tiles per block), the latter 0 when the blocks are capped."""
+        f, t = ctypes.c_int32(), ctypes.c_int32()
         path = None if cache_path is None else os.fsencode(cache_path)
-        _check(self.lib.imexhdg_ens_autotune(self._ens, path, ctypes.byref(f)))
-        return f.value
+        _check(self.lib.imexhdg_ens_autotune(self._ens, path, ctypes.byref(f), ctypes.byref(t)))
+        return f.value, t.value

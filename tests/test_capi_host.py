@@ -71,6 +71,6 @@ def test_null_arguments_rejected():
     assert lib.imexhdg_autotune(None, None, None, None) == m.E_INVAL
     assert lib.imexhdg_ens_create(None, 0, None, None, 0, None) == m.E_INVAL
     assert lib.imexhdg_ens_step(None, 1) == m.E_INVAL
-    assert lib.imexhdg_ens_autotune(None, None, None) == m.E_INVAL
+    assert lib.imexhdg_ens_autotune(None, None, None, None) == m.E_INVAL
     lib.imexhdg_ens_destroy(None)
     lib.imexhdg_destroy(None)

@@ -167,13 +167,13 @@ def test_ensemble_autotune_restores_state(tmp_path):
     E.step(3)
     before = [np.stack(E.get_state(i, vars=m.VARS_GEOPOTENTIAL)) for i in range(len(MESHES))]
     cache = tmp_path / "ens_tune.txt"
-    f = E.autotune(str(cache))
-    print("ensemble face grid cap", f, open(cache).read(), flush=True)
-    assert f in (16, 32, 48, 64, 96, 128, 1024)
+    f, tpb = E.autotune(str(cache))
+    print("ensemble face blocks", f, tpb, open(cache).read(), flush=True)
+    assert (tpb == 0 and f in (16, 32, 48, 64, 96, 128, 1024)) or (f == 4096 and tpb in (2, 3, 4, 6, 8))
     for i in range(len(MESHES)):
         assert np.array_equal(before[i], np.stack(E.get_state(i, vars=m.VARS_GEOPOTENTIAL)))
     assert E.diag(0)["steps"] == 3
-    assert E.autotune(str(cache)) == f
+    assert E.autotune(str(cache)) == (f, tpb)
     assert len(open(cache).read().splitlines()) == 1
     E.step(2)
     assert E.diag(0)["steps"] == 5
