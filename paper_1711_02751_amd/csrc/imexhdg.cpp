@@ -140,7 +140,7 @@ struct imexhdg_ctx {
     double *q = nullptr, *Z = nullptr, *save = nullptr;   // save: autotuner's copy of q
     const double *qin = nullptr;      // q^n of the step being enqueued
     std::vector<double *> NLb, Qb, Rb;
-    double *x = nullptr, *gv = nullptr, *gh = nullptr;
+    double *x = nullptr, *gv = nullptr;
     double *xsave = nullptr;          // autotuner's copy of the trace guess
     // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
     bool mixed = false;
@@ -289,7 +289,7 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     const size_t isz = (c0.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
-    t += 4 * align256(L.T * 8);                        // FP64 trace vectors
+    t += 3 * align256(L.T * 8);                        // FP64 trace vectors
     t += 10 * align256(L.T * isz);                     // inner-solve vectors
     t += (size_t)L.nops * (align256(local_frag_count((int)n_loc, (int)n_loc) * 8) +
                            align256(local_frag_count((int)n_loc, (int)n_tr) * 8) +
@@ -611,12 +611,10 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
     for (int sweep = 0;; ++sweep) {
         int rc;
         LAUNCH(IMEXHDG_K_TRACE_RESID,
-               c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh,
-                                                (float *)c->rin, c->dpart, c->pstride, nullptr,
-                                                c->stream)
-                        : launch_trace_residual(g, b, c->x, c->gv, c->gh,
-                                                (double *)c->rin, c->dpart, c->pstride, nullptr,
-                                                c->stream));
+               c->mixed ? launch_trace_residual(g, b, c->x, c->gv, (float *)c->rin, c->dpart,
+                                                c->pstride, nullptr, c->stream)
+                        : launch_trace_residual(g, b, c->x, c->gv, (double *)c->rin, c->dpart,
+                                                c->pstride, nullptr, c->stream));
         double nrm[4];
         if ((rc = read_partials(c, 4, 0, c->mtab[0].nbf, nrm))) return rc;
         const double rr = nrm[0], gg = nrm[1], ghh = nrm[2], rinrin = nrm[3];
@@ -656,7 +654,7 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
 // One implicit stage: Z = A^-1 R, g = C Z, solve G x = g, Q = Z - W x.
 int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres) {
     LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
-    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->gh, c->stream));
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->stream));
     int rc = trace_solve(c, iters, relres);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
     LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->bt, c->Z, c->x, Q, c->stream));
@@ -722,7 +720,7 @@ int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     T *r[2] = {(T *)c->kr[0], (T *)c->kr[1]};
     KrylovBufs kb = c->kb;
     kb.sched = 1;
-    HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, c->gh, rin, c->dpart, c->pstride,
+    HIP_TRY(launch_trace_residual(g, b, c->x, c->gv, rin, c->dpart, c->pstride,
                                   c->ks, c->stream));
     // the refinement check and the first K1 of the inner solve in one launch
     HIP_TRY(launch_refine_k1(g, b, (const T *)rin, r[0], rh, p[1], v[1], d, c->ks, c->dpart,
@@ -745,16 +743,16 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
     const imexhdg_config &cf = c->cfg;
     LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
     // trace_rhs also resets each member's stage-solve state
-    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->gh, c->stream, c->ks));
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->stream, c->ks));
     const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
     for (int sw = 0; sw < c->sched_sweeps; ++sw) {
         const int bud = c->sched_budget[sw];
         int rc = c->mixed ? sched_sweep<float>(c, bud, irt) : sched_sweep<double>(c, bud, irt);
         if (rc) return rc;
     }
-    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, c->gh, (float *)c->rin,
+    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, (float *)c->rin,
                                              c->dpart, c->pstride, c->ks, c->stream)
-                     : launch_trace_residual(g, b, c->x, c->gv, c->gh, (double *)c->rin,
+                     : launch_trace_residual(g, b, c->x, c->gv, (double *)c->rin,
                                              c->dpart, c->pstride, c->ks, c->stream));
     // recover also records each member's stage-solve outcome
     LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream, c->ks, c->dpart,
@@ -1255,7 +1253,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
     c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
-    double **tv[4] = {&c->x, &c->gv, &c->gh, &c->xsave};
+    double **tv[3] = {&c->x, &c->gv, &c->xsave};
     for (double **p : tv) *p = (double *)take(L.T * 8);
     void **iv[10] = {&c->rin, &c->kr[0], &c->krh, &c->kp[0], &c->kp[1],
                      &c->kv[0], &c->kv[1], &c->kr[1], &c->kt, &c->kd};

@@ -559,10 +559,7 @@ template <int K>
 __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__ Z,
                                                       const Geom g, const Batch bt,
                                                       double *__restrict__ gv,
-                                                      double *__restrict__ gh,
                                                       KrylovState *begin) {
-    constexpr int B3 = 3 * K;
-    __shared__ double sG[B3][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
     // the member's blocks are [2 bv, 2 (bv + nbv)): x-face tiles, then y
@@ -573,8 +570,6 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
         stage_begin_state(begin + mi);
     Z += mb.vo;
     gv += mb.to;
-    gh += mb.to;
-    const double *Pxinv = mb.Px, *Pyinv = mb.Py;
     const FaceIdx fi = face_of_tile(blockIdx.x - 2 * mb.bv, mb.nel);
     const Nbr n = neighbours(fi.f, mb.nx, mb.ny);
     const size_t nel = mb.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
@@ -593,28 +588,11 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
     const double g0 = (Um * nx + Vm * ny + tau * pm) + (-(Up * nx + Vp * ny) + tau * pp);
     const double g1 = (nx * phiB * pm + tau * Um) + (-nx * phiB * pp + tau * Up);
     const double g2 = (ny * phiB * pm + tau * Vm) + (-ny * phiB * pp + tau * Vp);
-    sG[0 * K + j][lane] = g0;
-    sG[1 * K + j][lane] = g1;
-    sG[2 * K + j][lane] = g2;
     const size_t base = fi.d * TT + (size_t)j * nel + fi.f;
     if (fi.active) {
         gv[base] = g0;
         gv[base + nel * K] = g1;
         gv[base + 2 * nel * K] = g2;
-    }
-    __syncthreads();
-    const cdouble *P = as_const(fi.d == 0 ? Pxinv : Pyinv) + j * B3;
-    double h[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int col = 0; col < B3; ++col) {
-        const double x = sG[col][lane];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) h[c] += P[c * K * B3 + col] * x;
-    }
-    if (fi.active) {
-        gh[base] = h[0];
-        gh[base + nel * K] = h[1];
-        gh[base + 2 * nel * K] = h[2];
     }
 }
 
@@ -1389,34 +1367,52 @@ __device__ __forceinline__ void stage_frags(const T *__restrict__ const *g, T *s
     }
 }
 
-// FP64 residuals of the trace system: r = g - G x (only its norm is
-// needed) and rin = ghat - Ghat x (stored); partials of ||r||^2, ||g||^2,
-// ||ghat||^2, ||rin||^2.
+// FP64 residuals of the trace system: r = g - G x and rin = P^-1 r (the
+// face's block-Jacobi inverse applied to r: ghat - Ghat x, with ghat =
+// P^-1 g never stored), rin stored in the inner solve's precision;
+// partials of ||r||^2, ||g||^2, ||P^-1 g||^2, ||rin||^2.  The accumulator of
+// the G contraction already holds r in the B-operand layout of a further
+// matrix-core step (FP64 element e4 of row block mb of lane l is row
+// 16 mb + 4 e4 + l/16 of face l % 16: the B operand of k step 4 mb + e4), so
+// P^-1 r and P^-1 g are two short contractions on the registers.
 template <int K, typename RT>
 __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_residual(
     const Batch bt, const double *__restrict__ x, const double *__restrict__ gv,
-    const double *__restrict__ gh, RT *__restrict__ rin,
-    double *partials, int stride, const KrylovState *skip) {
+    RT *__restrict__ rin, double *partials, int stride, const KrylovState *skip) {
     using T = double;
-    constexpr int NMB = MF<K>::NMB;
+    constexpr int NMB = MF<K>::NMB, B3 = 3 * K;
     int lb;
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     if (skip && skip[mi].stage_done) return;
     const Member mb = load_member(bt, mi);
-    x += mb.to; gv += mb.to; gh += mb.to; rin += mb.to;
+    x += mb.to; gv += mb.to; rin += mb.to;
     __shared__ double sB[TileLds<K, T>::n];
-    __shared__ double sA[FragLds<K, T, 2>::alloc];
+    __shared__ double sA[FragLds<K, T, 1>::alloc];
     const uint32_t nel = mb.nel;
-    const double *gfr[2] = {mb.G, mb.Gh};
-    const double *fr[2];
+    const double *gfr[1] = {mb.G};
+    const double *fr[1];
     // the first tile's loads are issued with the operand loads (a block
     // without tiles loads tile 0 and never commits it)
-    FragStage<K, T, 2> fs;
+    FragStage<K, T, 1> fs;
     fs.load(gfr);
     const double *src[1] = {x};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
     StagedTile<K, T, 1> st;
     st.load(tw.first < tw.end ? tw.first : 0, mb, src);
+    // P^-1 of this wave's face set as A fragments: pf[mo][kk] = P[16 mo +
+    // l % 16][4 kk + l / 16], zero past 3K (P row-major, 3K x 3K)
+    const int lane = threadIdx.x & 63;
+    const double *P = ((threadIdx.x >> 6) >> 2) == 0 ? mb.Px : mb.Py;
+    double pf[NMB][4 * NMB];
+#pragma unroll
+    for (int mo = 0; mo < NMB; ++mo)
+#pragma unroll
+        for (int kk = 0; kk < 4 * NMB; ++kk) {
+            const int row = 16 * mo + (lane & 15), col = 4 * kk + (lane >> 4);
+            const bool in = row < B3 && col < B3;
+            const double pv = P[in ? row * B3 + col : 0];
+            pf[mo][kk] = in ? pv : 0.0;
+        }
     fs.store(sA, fr);
     double acc4[4] = {0.0, 0.0, 0.0, 0.0};
     {
@@ -1428,8 +1424,8 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
                 st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
             };
             const WaveFaces wf = wave_faces(tile, mb);
-            // right-hand sides at the own rows, loaded ahead of the contraction
-            double gvv[NMB][4], ghv[NMB][4];
+            // g at the own rows, loaded ahead of the contraction
+            double gvv[NMB][4];
             uint32_t o[NMB][4];
             bool ok[NMB][4];
 #pragma unroll
@@ -1438,23 +1434,41 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
                 for (int e4 = 0; e4 < 4; ++e4) {
                     o[m][e4] = own_off<K, T>(wf, m, e4, nel, ok[m][e4]);
                     gvv[m][e4] = gv[ok[m][e4] ? o[m][e4] : 0u];
-                    ghv[m][e4] = gh[ok[m][e4] ? o[m][e4] : 0u];
                 }
-            v4d acc[2][NMB];
-            face_rows<K, 2>(fr, st, mb, wf, sB, src,
-                                   [](const double (&a)[1], uint32_t, bool) { return a[0]; },
-                                   acc, prefetch);
+            v4d acc[1][NMB];
+            face_rows<K, 1>(fr, st, mb, wf, sB, src,
+                            [](const double (&a)[1], uint32_t, bool) { return a[0]; },
+                            acc, prefetch);
+            // r and g as B operands (zero past row 3K and off the mesh)
+            double rb[NMB][4], gb[NMB][4];
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    gb[m][e4] = ok[m][e4] ? gvv[m][e4] : 0.0;
+                    rb[m][e4] = ok[m][e4] ? gvv[m][e4] - acc[0][m][e4] : 0.0;
+                }
+            v4d ar[NMB], ag[NMB];
+#pragma unroll
+            for (int mo = 0; mo < NMB; ++mo) {
+                ar[mo] = v4d{0, 0, 0, 0};
+                ag[mo] = v4d{0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < 4 * NMB; ++kk) {
+                    ar[mo] = MfmaT<double>::mma(pf[mo][kk], rb[kk / 4][kk % 4], ar[mo]);
+                    ag[mo] = MfmaT<double>::mma(pf[mo][kk], gb[kk / 4][kk % 4], ag[mo]);
+                }
+            }
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
                 for (int e4 = 0; e4 < 4; ++e4)
                     if (ok[m][e4]) {
-                        const double rr = gvv[m][e4] - acc[0][m][e4];
-                        const double ri = ghv[m][e4] - acc[1][m][e4];
+                        const double ri = ar[m][e4];
                         rin[o[m][e4]] = (RT)ri;
-                        acc4[0] += rr * rr;
-                        acc4[1] += gvv[m][e4] * gvv[m][e4];
-                        acc4[2] += ghv[m][e4] * ghv[m][e4];
+                        acc4[0] += rb[m][e4] * rb[m][e4];
+                        acc4[1] += gb[m][e4] * gb[m][e4];
+                        acc4[2] += ag[m][e4] * ag[m][e4];
                         acc4[3] += ri * ri;
                     }
         }
@@ -2151,18 +2165,18 @@ template <int K> struct RunRecover {
 };
 template <int K> struct RunTraceRhs {
     static hipError_t run(const Geom &g, const Batch &b, const double *Z, double *gv,
-                          double *gh, KrylovState *begin, hipStream_t s) {
-        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, gh, begin);
+                          KrylovState *begin, hipStream_t s) {
+        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, begin);
         return hipGetLastError();
     }
 };
 template <typename RT> struct RunTraceResidual {
     template <int K> struct F {
-        static hipError_t run(const Batch &b, const double *x, const double *gv,
-                              const double *gh, RT *rin, double *partials, int stride,
-                              const KrylovState *skip, hipStream_t s) {
+        static hipError_t run(const Batch &b, const double *x, const double *gv, RT *rin,
+                              double *partials, int stride, const KrylovState *skip,
+                              hipStream_t s) {
             KLAUNCH((k_trace_residual<K, RT>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
-                               b, x, gv, gh, rin, partials, stride, skip);
+                               b, x, gv, rin, partials, stride, skip);
             return hipGetLastError();
         }
     };
@@ -2279,8 +2293,8 @@ hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, do
 }
 
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
-                            double *ghat, hipStream_t s, KrylovState *begin) {
-    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, ghat, begin, s);
+                            hipStream_t s, KrylovState *begin) {
+    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, begin, s);
 }
 
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
@@ -2291,11 +2305,10 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 
 #define IMEXHDG_KRYLOV_LAUNCHERS(T)                                                            \
     hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
-                                     const double *gvec, const double *ghat, T *rin,          \
-                                     double *partials, int stride, const KrylovState *skip,   \
-                                     hipStream_t s) {                                         \
-        return dispatch<RunTraceResidual<T>::template F>(g.K, b, x, gvec, ghat, rin,          \
-                                                         partials, stride, skip, s);          \
+                                     const double *gvec, T *rin, double *partials,            \
+                                     int stride, const KrylovState *skip, hipStream_t s) {    \
+        return dispatch<RunTraceResidual<T>::template F>(g.K, b, x, gvec, rin, partials,      \
+                                                         stride, skip, s);                    \
     }                                                                                          \
     hipError_t launch_bicg_init(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
                                 T *p, T *v, T *d, KrylovState *ks, double tol2,               \

@@ -121,18 +121,20 @@ hipError_t launch_linear_residual(const Geom &g, const Batch &b, const double *Q
                                   const double *qhat, double *out, hipStream_t s);
 hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, double *Z,
                               hipStream_t s);
-// begin (fixed schedule): also reset each member's stage-solve state.
+// g = sum C Z per face (the trace system's right-hand side); begin (fixed
+// schedule): also reset each member's stage-solve state.
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
-                            double *ghat, hipStream_t s, KrylovState *begin = nullptr);
+                            hipStream_t s, KrylovState *begin = nullptr);
 // status (fixed schedule): also record each member's stage-solve outcome
 // from ks and the final trace_residual's partials [4][stride].
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
                           double *Q, hipStream_t s, const KrylovState *ks = nullptr,
                           const double *partials = nullptr, int stride = 0,
                           StageStatus *status = nullptr);
-// FP64 r = g - G x (its norm only) and rin = ghat - Ghat x (stored in the
-// inner solve's precision); partials [4][face blocks] of ||r||^2, ||g||^2,
-// ||ghat||^2, ||rin||^2.  With `skip`, members whose stage solve is done return.
+// FP64 r = g - G x (its norm only) and rin = P^-1 r = ghat - Ghat x (stored
+// in the inner solve's precision); partials [4][face blocks] of ||r||^2,
+// ||g||^2, ||ghat||^2, ||rin||^2.  With `skip`, members whose stage solve is
+// done return.
 // BiCGStab on Ghat d = rin with d0 = 0: init and K1, then per iteration
 // K2 and K1f (the next K1 fused with this iteration's d and r updates;
 // s = r - alpha v is formed by both, never stored, so r is double buffered
@@ -141,9 +143,8 @@ hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const 
 // (matrix-core fragments in the same precision).
 #define IMEXHDG_KRYLOV_DECLS(T)                                                                \
     hipError_t launch_trace_residual(const Geom &g, const Batch &b, const double *x,          \
-                                     const double *gvec, const double *ghat, T *rin,          \
-                                     double *partials, int stride, const KrylovState *skip,   \
-                                     hipStream_t s);                                          \
+                                     const double *gvec, T *rin, double *partials,            \
+                                     int stride, const KrylovState *skip, hipStream_t s);     \
     hipError_t launch_bicg_init(const Geom &g, const Batch &b, const T *rin, T *r, T *rh,     \
                                 T *p, T *v, T *d, KrylovState *ks, double tol2,               \
                                 const KrylovBufs &kb, hipStream_t s);                         \
