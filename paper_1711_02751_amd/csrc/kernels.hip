@@ -1090,12 +1090,13 @@ __device__ __forceinline__ int slot_lds(int set, int s, int lx, int ly, int NX, 
                   : NX + (ly + dy + 1) * YC + (lx + dx + 1);
 }
 
-// comb(raw, off, own), or comb(raw, oraw, off, own) with NO own-face sources.
+// comb(raw, off, own), or comb(raw, oraw, off, own, li) with NO own-face
+// sources (li: the value's LDS index in the staged tile).
 template <int NO, typename T, int NA, typename Comb>
 __device__ __forceinline__ T apply_comb(Comb &comb, const T (&a)[NA], const T (&o)[NO > 0 ? NO : 1],
-                                        uint32_t off, bool own) {
+                                        uint32_t off, bool own, int li) {
     if constexpr (NO == 0) return comb(a, off, own);
-    else return comb(a, o, off, own);
+    else return comb(a, o, off, own, li);
 }
 
 // Stage the tile: sB[cj NF + f] = comb(raw, o, own) for every staged face
@@ -1139,9 +1140,10 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
             for (int b = 0; b < NO; ++b) oraw[u][b] = ok[u] && own[u] ? osrc[b][off[u]] : T(0);
 #pragma unroll
         for (int u = 0; u < CH; ++u)
-            if (ok[u])
-                sB[threadIdx.x + kFaceThreads * (i0 + u)] =
-                    apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u]);
+            if (ok[u]) {
+                const int li = threadIdx.x + kFaceThreads * (i0 + u);
+                sB[li] = apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u], li);
+            }
     }
 }
 
@@ -1208,9 +1210,10 @@ template <int K, typename T, int NA, int NO = 0> struct StagedTile {
         if constexpr (kHold) {
 #pragma unroll
             for (int u = 0; u < PER; ++u)
-                if (ok[u])
-                    sB[threadIdx.x + kFaceThreads * u] =
-                        apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u]);
+                if (ok[u]) {
+                    const int li = threadIdx.x + kFaceThreads * u;
+                    sB[li] = apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u], li);
+                }
         } else {
             stage_tile<K, T, NA, NO>(tile, g, sB, src, os, comb);
         }
@@ -1916,13 +1919,14 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
     const T *src[4] = {rin, t, pin, vin};
     // FP32 with the tile held in registers (K <= 7): the staging thread of
-    // an own face also reads d and rh there and updates r, p and d.  FP64
-    // keeps its registers for occupancy and updates the own faces after the
-    // contraction.
+    // an own face also reads d there and updates r, p and d, and leaves r'
+    // in LDS for the matrix-core lanes (which hold rh) to sum rh.r' and
+    // r'.r'.  FP64 keeps its registers for occupancy and updates the own
+    // faces after the contraction.
     constexpr bool kOwnStage = sizeof(T) == 4 && StagedTile<K, T, 4>::kHold;
-    const T *osrc[2] = {d, rh};
+    const T *osrc[1] = {d};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
-    StagedTile<K, T, 4, kOwnStage ? 2 : 0> st;
+    StagedTile<K, T, 4, kOwnStage ? 1 : 0> st;
     constexpr bool kEarly = sizeof(T) == 4;   // registers allow it for FP32
     // unconditional: a block without tiles loads tile 0 and never commits it
     if (kEarly) st.load(tw.first < tw.end ? tw.first : 0, mb, src, osrc);
@@ -1937,6 +1941,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const double beta = brk ? 0.0 : (rho_new / rho) * (alpha / omega);
     const T be = (T)beta, om = (T)omega, al = (T)alpha;
     __shared__ T sB[TileLds<K, T>::n];
+    __shared__ T sR[kOwnStage ? TileLds<K, T>::n : 1];   // r' at the own faces
     const uint32_t nel = mb.nel;
     auto rnew = [&](T s_, T t_) { return (T)((double)s_ - omega * (double)t_); };
     auto pnew = [&](T r_, T p_, T v_) { return r_ + be * (p_ - om * v_); };
@@ -1977,11 +1982,32 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
             };
             if constexpr (kOwnStage) {
                 face_rows<K, 1>(fr, st, mb, wf, sB, src,
-                                [&](const T (&a)[4], const T (&ov)[2], uint32_t off, bool own) {
-                                    if (own) own_update(a[0], a[1], a[2], a[3], ov[0], ov[1], off);
-                                    return pnew(rnew(s_of(a[0], al, a[3]), a[1]), a[2], a[3]);
+                                [&](const T (&a)[4], const T (&ov)[1], uint32_t off, bool own,
+                                    int li) {
+                                    const T s_ = s_of(a[0], al, a[3]);
+                                    const T rn = rnew(s_, a[1]);
+                                    const T pn = pnew(rn, a[2], a[3]);
+                                    if (own) {
+                                        r[off] = rn;
+                                        pout[off] = pn;
+                                        d[off] = (T)((double)ov[0] + alpha * (double)a[2] +
+                                                     omega * (double)s_);
+                                        sR[li] = rn;
+                                    }
+                                    return pn;
                                 },
                                 acc, prefetch);
+                const int li = own_lds<K>(wf);
+#pragma unroll
+                for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4)
+                        if (ok[m][e4]) {
+                            const int row = 16 * m + MfmaT<T>::row(threadIdx.x & 63, e4);
+                            const double rd = sR[row * Tile<K>::NF + li];
+                            acc1[1] += (double)rhv[m][e4] * rd;
+                            acc1[2] += rd * rd;
+                        }
             } else {
                 face_rows<K, 1>(fr, st, mb, wf, sB, src,
                                 [&](const T (&a)[4], uint32_t, bool) {
