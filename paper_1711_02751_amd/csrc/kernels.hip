@@ -249,6 +249,14 @@ __device__ __forceinline__ void rusanov_nl(const double qm[3], const double qp[3
 //                                + (2/hy) sum_m Dw[m][b] F_y(a, m),
 // with F_y exchanged through LDS; surface term -(2/h) Phi / w_end at the
 // face nodes.  The epilogue applies the stage combination `comb`.
+// Every load that does not depend on arithmetic is issued at the start (the
+// row, its east and west neighbours and, for K <= 6, the neighbour row
+// across the south or north face), so a block (one per CU at this register
+// count) waits for memory once instead of once per face; the waves of the
+// middle rows, which have no north or south face, load their own row
+// instead of a neighbour's so that the loads stay unconditional (see
+// EarlyPartials), and for K <= 6 the combination inputs are loaded one
+// input ahead.  (Larger K would spill registers.)
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, const Geom g,
                                                const Batch bt, const Comb comb,
@@ -272,6 +280,28 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         p[i] = q[o];
         U[i] = q[NN + o];
         V[i] = q[2 * NN + o];
+    }
+    // east neighbour's first node and west neighbour's last node of row j
+    double qe[3], qw[3];
+    {
+        const size_t oe = (size_t)(j * K + 0) * nel + nb.east;
+        const size_t ow = (size_t)(j * K + K - 1) * nel + nb.west;
+        qe[0] = q[oe]; qe[1] = q[NN + oe]; qe[2] = q[2 * NN + oe];
+        qw[0] = q[ow]; qw[1] = q[NN + ow]; qw[2] = q[2 * NN + ow];
+    }
+    // across the north face (j = K - 1) or the south face (j = 0): the
+    // neighbour's first or last row; the middle rows read their own row
+    constexpr bool kHoist = K <= 6;
+    const bool north = (j == K - 1), edge = (j == K - 1 || j == 0);
+    double qs[kHoist ? K : 1][3];
+    if constexpr (kHoist) {
+        const int other = north ? nb.north : j == 0 ? nb.south : nb.e;
+        const int orow = north ? 0 : j == 0 ? K - 1 : j;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const size_t o = (size_t)(orow * K + i) * nel + other;
+            qs[i][0] = q[o]; qs[i][1] = q[NN + o]; qs[i][2] = q[2 * NN + o];
+        }
     }
     double fx1[K], fx2[K];
 #pragma unroll
@@ -299,21 +329,17 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
     }
     // east and west faces of row j
     {
-        double qm[3], qp[3], f[3];
-        size_t o = (size_t)(j * K + 0) * nel + nb.east;
+        double qm[3], f[3];
         qm[0] = p[K - 1]; qm[1] = U[K - 1]; qm[2] = V[K - 1];
-        qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
-        rusanov_nl(qm, qp, 1.0, 0.0, phiB, g.tau, f);
+        rusanov_nl(qm, qe, 1.0, 0.0, phiB, g.tau, f);
         const double se = mb.sx * g.winvk;
         o0[K - 1] -= se * f[0]; o1[K - 1] -= se * f[1]; o2[K - 1] -= se * f[2];
-        o = (size_t)(j * K + K - 1) * nel + nb.west;
         qm[0] = p[0]; qm[1] = U[0]; qm[2] = V[0];
-        qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
-        rusanov_nl(qm, qp, -1.0, 0.0, phiB, g.tau, f);
+        rusanov_nl(qm, qw, -1.0, 0.0, phiB, g.tau, f);
         const double sw = mb.sx * g.winv0;
         o0[0] -= sw * f[0]; o1[0] -= sw * f[1]; o2[0] -= sw * f[2];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         double s1 = 0.0, s2 = 0.0;
@@ -325,17 +351,20 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         o1[i] += mb.sy * s1;
         o2[i] += mb.sy * s2;
     }
-    if (j == K - 1 || j == 0) {
-        const bool north = (j == K - 1);
-        const int other = north ? nb.north : nb.south;
-        const int orow = north ? 0 : K - 1;
+    if (edge) {
         const double ny = north ? 1.0 : -1.0;
         const double sc = mb.sy * (north ? g.winvk : g.winv0);
+        const int other = north ? nb.north : nb.south;
+        const int orow = north ? 0 : K - 1;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             double qm[3] = {p[i], U[i], V[i]}, qp[3], f[3];
-            const size_t o = (size_t)(orow * K + i) * nel + other;
-            qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
+            if constexpr (kHoist) {
+                qp[0] = qs[i][0]; qp[1] = qs[i][1]; qp[2] = qs[i][2];
+            } else {
+                const size_t o = (size_t)(orow * K + i) * nel + other;
+                qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
+            }
             rusanov_nl(qm, qp, 0.0, ny, phiB, g.tau, f);
             o0[i] -= sc * f[0]; o1[i] -= sc * f[1]; o2[i] -= sc * f[2];
         }
@@ -365,21 +394,49 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         o1[i] *= comb.self;
         o2[i] *= comb.self;
     }
-    for (int t = 0; t < comb.n; ++t) {
-        const double *in = comb.in[t] + o;
-        const double cf = comb.coef[t];
-        double v0[K], v1[K], v2[K];
+    // input t + 1 is loaded while input t is added (the last round reloads
+    // input n - 1 and discards it: unconditional, see EarlyPartials)
+    double v0[K], v1[K], v2[K];
+    if (kHoist && comb.n > 0) {
+        const double *in = comb.in[0] + o;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             v0[i] = in[(size_t)i * nel];
             v1[i] = in[NN + (size_t)i * nel];
             v2[i] = in[2 * NN + (size_t)i * nel];
         }
+    }
+    for (int t = 0; t < comb.n; ++t) {
+        if constexpr (!kHoist) {   // one input at a time
+            const double *in = comb.in[t] + o;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                v0[i] = in[(size_t)i * nel];
+                v1[i] = in[NN + (size_t)i * nel];
+                v2[i] = in[2 * NN + (size_t)i * nel];
+            }
+        }
+        const double *in = comb.in[kHoist && t + 1 < comb.n ? t + 1 : t] + o;
+        const double cf = comb.coef[t];
+        double w0[K], w1[K], w2[K];
+        if constexpr (kHoist) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                w0[i] = in[(size_t)i * nel];
+                w1[i] = in[NN + (size_t)i * nel];
+                w2[i] = in[2 * NN + (size_t)i * nel];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             o0[i] += cf * v0[i];
             o1[i] += cf * v1[i];
             o2[i] += cf * v2[i];
+            if constexpr (kHoist) {
+                v0[i] = w0[i];
+                v1[i] = w1[i];
+                v2[i] = w2[i];
+            }
         }
     }
 #pragma unroll
