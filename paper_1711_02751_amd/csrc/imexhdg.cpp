@@ -141,6 +141,8 @@ struct imexhdg_ctx {
     const double *qin = nullptr;      // q^n of the step being enqueued
     std::vector<double *> NLb, Qb, Rb;
     double *x = nullptr, *gv = nullptr;
+    double *xp = nullptr;             // trace of the stage solve before the last
+    std::vector<double> xcoef;        // per stage: trace-guess extrapolation coefficient
     double *xsave = nullptr;          // autotuner's copy of the trace guess
     // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
     bool mixed = false;
@@ -289,7 +291,7 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
     const size_t isz = (c0.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
-    t += 3 * align256(L.T * 8);                        // FP64 trace vectors
+    t += 4 * align256(L.T * 8);                        // FP64 trace vectors
     t += 10 * align256(L.T * isz);                     // inner-solve vectors
     t += (size_t)L.nops * (align256(local_frag_count((int)n_loc, (int)n_loc) * 8) +
                            align256(local_frag_count((int)n_loc, (int)n_tr) * 8) +
@@ -362,6 +364,36 @@ int validate_batch(const imexhdg_config *cfgs, int n) {
 // equation (eq. IMEXRKDiscretizedForm_localSolver):
 //   dt M^-1 L_j = (Q_j - Res0_j) / a~_jj.
 // NL terms carry no dt: the NL kernel's output is dt M^-1 NL.
+// Trace-guess extrapolation per implicit stage i: the guess is the last
+// stage solution x_b plus (tau_i - tau_b) / (tau_b - tau_a) (x_b - x_a), a
+// straight line in time through the last two solutions (tau = c~ of the
+// stage, one step earlier for the previous step's stages).  Used only where
+// tau_a < tau_b < tau_i (ARS(2,3,2): 2.414 for its second stage, 0.414 for
+// its first; ARS(4,4,3) has non-monotone stage times, where the guess stays
+// the last solution, coefficient 0).
+std::vector<double> guess_coefficients(const Tableau &t) {
+    std::vector<int> imp;
+    for (int i = 0; i < t.s; ++i)
+        if (t.at(i, i) != 0.0) imp.push_back(i);
+    std::vector<double> ct(t.s, 0.0), coef(t.s, 0.0);
+    for (int i = 0; i < t.s; ++i)
+        for (int j = 0; j < t.s; ++j) ct[i] += t.at(i, j);
+    const int n = (int)imp.size();
+    // time (in steps, from the current step's start) of the solve m places
+    // before implicit stage k in the sequence of solves
+    auto tau = [&](int k, int m) {
+        const int p = k - m;
+        const int q = ((p % n) + n) % n;
+        const int step = (p - q) / n;   // 0, -1, -2, ...
+        return ct[imp[q]] + step;
+    };
+    for (int k = 0; k < n; ++k) {
+        const double ti = tau(k, 0), tb = tau(k, 1), ta = tau(k, 2);
+        if (ta < tb && tb < ti) coef[imp[k]] = (ti - tb) / (tb - ta);
+    }
+    return coef;
+}
+
 int build_plans(imexhdg_ctx *c) {
     const Tableau &t = c->tab;
     const int s = t.s;
@@ -652,9 +684,15 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
 }
 
 // One implicit stage: Z = A^-1 R, g = C Z, solve G x = g, Q = Z - W x.
-int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres) {
+// stage >= 0 (a step's stage i): the trace guess is extrapolated from the
+// last two solutions; stage < 0: x is the guess as it is.
+int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres,
+                int stage) {
     LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
-    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->stream));
+    LAUNCH(IMEXHDG_K_TRACE_RHS,
+           launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->stream, nullptr,
+                            stage >= 0 ? c->x : nullptr, c->xp,
+                            stage >= 0 ? c->xcoef[stage] : 0.0));
     int rc = trace_solve(c, iters, relres);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
     LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->bt, c->Z, c->x, Q, c->stream));
@@ -693,7 +731,7 @@ int step_host(imexhdg_ctx *c, const double *qin, double *qout, int *status) {
     for (int i = 0; i < s; ++i) {
         const double *Qi = qin;
         if (i > 0) {
-            int rc = stage_solve(c, c->Rb[i], c->Qb[i], nullptr, nullptr);
+            int rc = stage_solve(c, c->Rb[i], c->Qb[i], nullptr, nullptr, i);
             if (rc == IMEXHDG_E_NOCONV) *status = rc;
             else if (rc) return rc;
             Qi = c->Qb[i];
@@ -737,13 +775,15 @@ int sched_sweep(imexhdg_ctx *c, int budget, double inner_rtol) {
     return IMEXHDG_OK;
 }
 
-int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *st) {
+int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *st, int stage) {
     const Geom &g = c->geom;
     const Batch &b = c->bt;
     const imexhdg_config &cf = c->cfg;
     LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
-    // trace_rhs also resets each member's stage-solve state
-    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->stream, c->ks));
+    // trace_rhs also resets each member's stage-solve state and extrapolates
+    // the trace guess
+    LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->stream, c->ks, c->x,
+                                                 c->xp, c->xcoef[stage]));
     const double irt = c->mixed ? std::max(cf.krylov_rtol, 1e-6) : cf.krylov_rtol;
     for (int sw = 0; sw < c->sched_sweeps; ++sw) {
         const int bud = c->sched_budget[sw];
@@ -768,7 +808,7 @@ int step_sched(imexhdg_ctx *c, const double *qin, double *qout, StageStatus *st)
     for (int i = 0; i < s; ++i) {
         const double *Qi = qin;
         if (i > 0) {
-            int rc = stage_solve_sched(c, c->Rb[i], c->Qb[i], st + (size_t)i * c->nm);
+            int rc = stage_solve_sched(c, c->Rb[i], c->Qb[i], st + (size_t)i * c->nm, i);
             if (rc) return rc;
             Qi = c->Qb[i];
         }
@@ -1212,6 +1252,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     }
     int rc;
     if ((rc = build_plans(c))) return bail(rc);
+    c->xcoef = guess_coefficients(c->tab);
     Geom &g = c->geom;
     g.K = K;
     g.phiB = cf[0].g * cf[0].H;
@@ -1253,7 +1294,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
     c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
-    double **tv[3] = {&c->x, &c->gv, &c->xsave};
+    double **tv[4] = {&c->x, &c->gv, &c->xsave, &c->xp};
     for (double **p : tv) *p = (double *)take(L.T * 8);
     void **iv[10] = {&c->rin, &c->kr[0], &c->krh, &c->kp[0], &c->kp[1],
                      &c->kv[0], &c->kv[1], &c->kr[1], &c->kt, &c->kd};
@@ -1307,6 +1348,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
             return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
     }
     if (hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
+        hipMemsetAsync(c->xp, 0, L.T * 8, c->stream) ||
         hipMemsetAsync(c->q, 0, L.N * 8, c->stream) ||
         hipMemsetAsync(c->dstat, 0, 3 * (size_t)L.s * n * sizeof(StageStatus), c->stream) ||
         hipStreamSynchronize(c->stream))
@@ -1354,6 +1396,7 @@ int set_member_state(imexhdg_ctx *c, int m, int vars, const double *a, const dou
         HIP_TRY(hipMemcpyAsync(c->q + mh.vo + v * NN, h.data() + v * NN, NN * 8,
                                hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->x + mh.to, 0, mh.T * 8, c->stream));
+    HIP_TRY(hipMemsetAsync(c->xp + mh.to, 0, mh.T * 8, c->stream));
     HIP_TRY(stream_sync(c));
     c->member_set[m] = true;
     c->have_state = std::all_of(c->member_set.begin(), c->member_set.end(),
@@ -1512,7 +1555,7 @@ int imexhdg_stage_solve(imexhdg_ctx *c, const double *d_res0, double *d_Q, doubl
                         int32_t *iters, double *relres) {
     if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
     HIP_TRY(hipMemcpyAsync(c->x, d_qhat, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
-    int rc = stage_solve(c, d_res0, d_Q, iters, relres);
+    int rc = stage_solve(c, d_res0, d_Q, iters, relres, -1);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
     HIP_TRY(hipMemcpyAsync(d_qhat, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(stream_sync(c));
@@ -1604,6 +1647,7 @@ static int tune_trial(imexhdg_ctx *c, int fg, int eg, double *avg, int64_t *cnt)
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
+    HIP_TRY(hipMemsetAsync(c->xp, 0, c->T * 8, c->stream));
     rc = imexhdg_profile(c, -1);
     if (rc) return rc;
     int status = IMEXHDG_OK;
@@ -1706,6 +1750,7 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         }
         HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
+        HIP_TRY(hipMemsetAsync(c->xp, 0, c->T * 8, c->stream));
         HIP_TRY(stream_sync(c));
         c->steps = keep[0];
         c->kiters = keep[1];
@@ -1743,6 +1788,7 @@ static int ens_trial(imexhdg_ctx *c, int fg, int tpb, double *ms) {
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->x, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->xp, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(stream_sync(c));
     if ((rc = step_ctx(c, 1))) return rc;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1818,6 +1864,7 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
         }
         HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->x, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->xp, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(stream_sync(c));
         c->steps = keep[0];
         c->kiters = keep[1];

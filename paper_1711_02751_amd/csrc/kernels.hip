@@ -570,8 +570,6 @@ __device__ __forceinline__ FaceIdx face_of_tile(int tile, int nel) {
     return fi;
 }
 
-// g = sum over the two elements of C_K Z_K = F_L(Z) . n_K + tau Z at the
-// face node; ghat = P^-1 g with the block-Jacobi inverse of the face.
 // Stage-solve state of one member on the fixed launch schedule.  At the
 // start of a stage solve (run by trace_rhs): no sweep yet, no inner solve
 // active until the first refinement check opens one.
@@ -610,13 +608,21 @@ __device__ void stage_finish_block(const Member &mb, const KrylovState *ks,
     }
 }
 
-// `begin` (fixed schedule only): the member's first block also resets its
-// stage-solve state (stage_begin_state).
+// g = sum over the two elements of C_K Z_K = F_L(Z) . n_K + tau Z at the
+// face node.  `begin` (fixed schedule only): the member's first block also
+// resets its stage-solve state (stage_begin_state).  `x` (steps only): the
+// trace guess of this stage solve by linear extrapolation in time from the
+// last two solutions, x <- x + xc (x - xp), xp <- x (x holds the last
+// stage's solution, xp the one before; elementwise, each value has one
+// thread).  The guess is the solver's heuristic, not the method: it
+// changes the iterations, not the converged result.
 template <int K>
 __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__ Z,
                                                       const Geom g, const Batch bt,
                                                       double *__restrict__ gv,
-                                                      KrylovState *begin) {
+                                                      KrylovState *begin,
+                                                      double *__restrict__ x,
+                                                      double *__restrict__ xp, double xc) {
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
     // the member's blocks are [2 bv, 2 (bv + nbv)): x-face tiles, then y
@@ -650,6 +656,20 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
         gv[base] = g0;
         gv[base + nel * K] = g1;
         gv[base + 2 * nel * K] = g2;
+    }
+    if (x != nullptr && fi.active) {
+        double xv[3], pv[3];
+        const size_t ob = mb.to + base;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xv[c] = x[ob + c * nel * K];
+            pv[c] = xp[ob + c * nel * K];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[ob + c * nel * K] = xv[c] + xc * (xv[c] - pv[c]);
+            xp[ob + c * nel * K] = xv[c];
+        }
     }
 }
 
@@ -2248,8 +2268,10 @@ template <int K> struct RunRecover {
 };
 template <int K> struct RunTraceRhs {
     static hipError_t run(const Geom &g, const Batch &b, const double *Z, double *gv,
-                          KrylovState *begin, hipStream_t s) {
-        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, begin);
+                          KrylovState *begin, double *x, double *xp, double xc,
+                          hipStream_t s) {
+        KLAUNCH(k_trace_rhs<K>, dim3(2 * b.nbv), dim3(64 * K), 0, s, Z, g, b, gv, begin, x,
+                xp, xc);
         return hipGetLastError();
     }
 };
@@ -2376,8 +2398,9 @@ hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, do
 }
 
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
-                            hipStream_t s, KrylovState *begin) {
-    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, begin, s);
+                            hipStream_t s, KrylovState *begin, double *x, double *xprev,
+                            double xcoef) {
+    return dispatch<RunTraceRhs>(g.K, g, b, Z, gvec, begin, x, xprev, xcoef, s);
 }
 
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,

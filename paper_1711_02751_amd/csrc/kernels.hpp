@@ -122,9 +122,12 @@ hipError_t launch_linear_residual(const Geom &g, const Batch &b, const double *Q
 hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, double *Z,
                               hipStream_t s);
 // g = sum C Z per face (the trace system's right-hand side); begin (fixed
-// schedule): also reset each member's stage-solve state.
+// schedule): also reset each member's stage-solve state; x (steps): the
+// trace guess by linear extrapolation, x <- x + xcoef (x - xprev) and
+// xprev <- x (x: last stage's solution, xprev: the one before).
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,
-                            hipStream_t s, KrylovState *begin = nullptr);
+                            hipStream_t s, KrylovState *begin = nullptr, double *x = nullptr,
+                            double *xprev = nullptr, double xcoef = 0.0);
 // status (fixed schedule): also record each member's stage-solve outcome
 // from ks and the final trace_residual's partials [4][stride].
 hipError_t launch_recover(const Geom &g, const Batch &b, const double *Z, const double *qhat,
