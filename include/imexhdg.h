@@ -234,6 +234,11 @@ int imexhdg_profile(imexhdg_ctx *ctx, int32_t kernel);
 int imexhdg_profile_read(imexhdg_ctx *ctx, int32_t kernel, int64_t *launches,
                          double *total_ms);
 
+/* The same over the launches that took at least min_ms, e.g. to leave out
+ * the launches of a converged solve that return at entry.                */
+int imexhdg_profile_read_min(imexhdg_ctx *ctx, int32_t kernel, double min_ms,
+                             int64_t *launches, double *total_ms);
+
 /* Static name of a kernel class, or NULL for an unknown id.              */
 const char *imexhdg_kernel_name(int32_t kernel);
 

@@ -185,6 +185,7 @@ struct imexhdg_ctx {
     std::vector<int> ev_id;
     int ev_used = 0;
     double prof_ms[IMEXHDG_K_COUNT] = {};
+    std::vector<float> prof_dur[IMEXHDG_K_COUNT];   // per-launch times (ms) of the timed classes
     int64_t prof_n[IMEXHDG_K_COUNT] = {};
 };
 
@@ -511,6 +512,7 @@ void prof_harvest(imexhdg_ctx *c) {
         if (hipEventElapsedTime(&ms, c->ev0[i], c->ev1[i]) == hipSuccess) {
             c->prof_ms[c->ev_id[i]] += ms;
             c->prof_n[c->ev_id[i]] += 1;
+            c->prof_dur[c->ev_id[i]].push_back(ms);
         }
     }
     c->ev_used = 0;
@@ -1588,6 +1590,7 @@ int imexhdg_profile(imexhdg_ctx *c, int32_t kernel) {
     for (int i = 0; i < IMEXHDG_K_COUNT; ++i) {
         c->prof_ms[i] = 0.0;
         c->prof_n[i] = 0;
+        c->prof_dur[i].clear();
     }
     return IMEXHDG_OK;
 }
@@ -1598,6 +1601,24 @@ int imexhdg_profile_read(imexhdg_ctx *c, int32_t kernel, int64_t *launches, doub
     HIP_TRY(stream_sync(c));
     if (launches) *launches = c->prof_n[kernel];
     if (total_ms) *total_ms = c->prof_ms[kernel];
+    return IMEXHDG_OK;
+}
+
+int imexhdg_profile_read_min(imexhdg_ctx *c, int32_t kernel, double min_ms, int64_t *launches,
+                             double *total_ms) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "ctx is NULL");
+    if (kernel < 0 || kernel >= IMEXHDG_K_COUNT) return fail(IMEXHDG_E_INVAL, "bad kernel id");
+    HIP_TRY(stream_sync(c));
+    prof_harvest(c);
+    int64_t n = 0;
+    double ms = 0.0;
+    for (float d : c->prof_dur[kernel])
+        if (d >= min_ms) {
+            n += 1;
+            ms += d;
+        }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
     return IMEXHDG_OK;
 }
 

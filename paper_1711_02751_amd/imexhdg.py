@@ -27,7 +27,8 @@ EXPORTS = [
     "imexhdg_set_state", "imexhdg_get_state", "imexhdg_step", "imexhdg_get_diag",
     "imexhdg_last_error", "imexhdg_state_device", "imexhdg_nl_residual",
     "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_profile",
-    "imexhdg_profile_read", "imexhdg_kernel_name", "imexhdg_get_schedule",
+    "imexhdg_profile_read", "imexhdg_profile_read_min", "imexhdg_kernel_name",
+    "imexhdg_get_schedule",
     "imexhdg_set_schedule", "imexhdg_set_launch_geometry", "imexhdg_autotune",
     "imexhdg_ens_workspace_bytes", "imexhdg_ens_create", "imexhdg_ens_destroy",
     "imexhdg_ens_members", "imexhdg_ens_sizes", "imexhdg_ens_get_nodes",
@@ -106,6 +107,8 @@ def load():
         "imexhdg_stage_solve": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "imexhdg_profile": (ctypes.c_int, [P, i32]),
         "imexhdg_profile_read": (ctypes.c_int, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]),
+        "imexhdg_profile_read_min": (ctypes.c_int, [P, i32, dbl, ctypes.POINTER(i64),
+                                                    ctypes.POINTER(dbl)]),
         "imexhdg_kernel_name": (ctypes.c_char_p, [i32]),
         "imexhdg_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "imexhdg_set_schedule": (ctypes.c_int, [P, i32, ctypes.POINTER(i32)]),
@@ -239,11 +242,18 @@ class Solver:
             kernel = KERNELS.index(kernel)
         _check(self.lib.imexhdg_profile(self._ctx, int(kernel)))
 
-    def profile_read(self, kernel):
+    def profile_read(self, kernel, min_us=0.0):
+        """(launches, total ms) of a class since profile(); with min_us > 0,
+        over the launches that took at least min_us only."""
         if isinstance(kernel, str):
             kernel = KERNELS.index(kernel)
         n, ms = ctypes.c_int64(), ctypes.c_double()
-        _check(self.lib.imexhdg_profile_read(self._ctx, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
+        if min_us > 0.0:
+            _check(self.lib.imexhdg_profile_read_min(self._ctx, int(kernel), min_us / 1000.0,
+                                                     ctypes.byref(n), ctypes.byref(ms)))
+        else:
+            _check(self.lib.imexhdg_profile_read(self._ctx, int(kernel), ctypes.byref(n),
+                                                 ctypes.byref(ms)))
         return n.value, ms.value
 
     # ---- fixed launch schedule (LAUNCH_GRAPH)
