@@ -167,7 +167,7 @@ struct imexhdg_ctx {
     // fixed-schedule stepping: sweeps and inner-iteration budget per sweep,
     // what the last host-driven solves needed, one graph per ring position
     int sched_sweeps = 0, sched_budget[kMaxSweeps] = {};
-    int margin = 2;
+    int margin = 2;                   // schedule slack: +2 per redone step, -1 per clean window
     int learn_sweeps = 0, learn_iters[kMaxSweeps] = {};
     int win_sweeps = 0, win_iters[kMaxSweeps] = {};   // graph steps since capture
     int64_t win_steps = 0;
@@ -996,7 +996,8 @@ int step_sched_eager(imexhdg_ctx *c, int a, int *status) {
 // Graph steps are verified one step behind: before step m + 2 is launched
 // (it overwrites the input of step m), step m's stage outcomes are read.
 // A failed step is redone (host-driven for one member, on a widened eager
-// schedule for several) and the schedule widened; after 64 verified steps a
+// schedule for several) and the schedule widened (the margin grows by 2);
+// after 64 verified steps the margin shrinks by 1 (down to 2) and a
 // schedule that has become loose by at least two iterations is tightened.
 int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
     const imexhdg_config &cf = c->cfg;
@@ -1059,6 +1060,9 @@ int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
             advance(c);
             ++done;
             if (c->win_steps >= 64 && !want) {
+                // 64 verified steps without a redo: give back one iteration
+                // of the slack a redo added (never below the initial 2)
+                if (c->margin > 2) c->margin -= 1;
                 int loose = 0;
                 for (int w = 0; w < c->sched_sweeps; ++w)
                     loose += c->sched_budget[w] -
