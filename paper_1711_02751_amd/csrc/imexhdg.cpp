@@ -792,10 +792,11 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
         int rc = c->mixed ? sched_sweep<float>(c, bud, irt) : sched_sweep<double>(c, bud, irt);
         if (rc) return rc;
     }
-    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, (float *)c->rin,
-                                             c->dpart, c->pstride, c->ks, c->stream)
-                     : launch_trace_residual(g, b, c->x, c->gv, (double *)c->rin,
-                                             c->dpart, c->pstride, c->ks, c->stream));
+    // the final check needs ||r|| and ||g|| only (no rin)
+    HIP_TRY(c->mixed ? launch_trace_residual(g, b, c->x, c->gv, (float *)nullptr, c->dpart,
+                                             c->pstride, c->ks, c->stream)
+                     : launch_trace_residual(g, b, c->x, c->gv, (double *)nullptr, c->dpart,
+                                             c->pstride, c->ks, c->stream));
     // recover also records each member's stage-solve outcome
     LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream, c->ks, c->dpart,
                                              c->pstride, st));

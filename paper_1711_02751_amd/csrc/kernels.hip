@@ -1454,7 +1454,9 @@ __device__ __forceinline__ void stage_frags(const T *__restrict__ const *g, T *s
 // the G contraction already holds r in the B-operand layout of a further
 // matrix-core step (FP64 element e4 of row block mb of lane l is row
 // 16 mb + 4 e4 + l/16 of face l % 16: the B operand of k step 4 mb + e4), so
-// P^-1 r and P^-1 g are two short contractions on the registers.
+// P^-1 r and P^-1 g are two short contractions on the registers.  With rin
+// == nullptr (a check of a finished solve) only ||r||^2 and ||g||^2 are
+// formed.
 template <int K, typename RT>
 __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_residual(
     const Batch bt, const double *__restrict__ x, const double *__restrict__ gv,
@@ -1465,7 +1467,9 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     if (skip && skip[mi].stage_done) return;
     const Member mb = load_member(bt, mi);
-    x += mb.to; gv += mb.to; rin += mb.to;
+    const bool want_rin = rin != nullptr;
+    x += mb.to; gv += mb.to;
+    if (want_rin) rin += mb.to;
     __shared__ double sB[TileLds<K, T>::n];
     __shared__ double sA[FragLds<K, T, 1>::alloc];
     const uint32_t nel = mb.nel;
@@ -1528,6 +1532,16 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
                     gb[m][e4] = ok[m][e4] ? gvv[m][e4] : 0.0;
                     rb[m][e4] = ok[m][e4] ? gvv[m][e4] - acc[0][m][e4] : 0.0;
                 }
+            if (!want_rin) {
+#pragma unroll
+                for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        acc4[0] += rb[m][e4] * rb[m][e4];
+                        acc4[1] += gb[m][e4] * gb[m][e4];
+                    }
+                continue;
+            }
             v4d ar[NMB], ag[NMB];
 #pragma unroll
             for (int mo = 0; mo < NMB; ++mo) {
