@@ -77,6 +77,13 @@ extern "C" {
 #define IMEXHDG_LAUNCH_HOST  1  /* host reads the residual between sweeps and
                                    the Krylov state every few iterations     */
 
+/* initial trace guess of a step's stage solves (a heuristic of the solver:
+ * it changes the iteration count, not the converged trace)               */
+#define IMEXHDG_GUESS_EXTRAPOLATE 0  /* straight line in time through the last
+                                        two stage solutions (where the stage
+                                        times increase), else the last one   */
+#define IMEXHDG_GUESS_LAST        1  /* the last stage solution             */
+
 /* variables of host state arrays */
 #define IMEXHDG_VARS_DEPTH       0  /* (h, hu, hv): depth and momenta        */
 #define IMEXHDG_VARS_GEOPOTENTIAL 1 /* (phi_eta, U, V) = (g(h-H), g hu, g hv) */
@@ -97,6 +104,7 @@ typedef struct imexhdg_config {
     double  refine_rtol;     /* FP64 true-residual tolerance ||g-Gx||/||g|| */
     int32_t refine_max;      /* max refinement sweeps per stage solve      */
     int32_t launch;          /* IMEXHDG_LAUNCH_*                           */
+    int32_t trace_guess;     /* IMEXHDG_GUESS_*                            */
 } imexhdg_config;
 
 typedef struct imexhdg_diag {

@@ -333,6 +333,8 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "iteration budgets must be >= 1");
     if (c->launch != IMEXHDG_LAUNCH_GRAPH && c->launch != IMEXHDG_LAUNCH_HOST)
         return fail(IMEXHDG_E_INVAL, "unknown launch mode");
+    if (c->trace_guess != IMEXHDG_GUESS_EXTRAPOLATE && c->trace_guess != IMEXHDG_GUESS_LAST)
+        return fail(IMEXHDG_E_INVAL, "unknown trace guess");
     return IMEXHDG_OK;
 }
 
@@ -348,7 +350,8 @@ int validate_batch(const imexhdg_config *cfgs, int n) {
             a.physics != b.physics || a.precision != b.precision ||
             a.krylov_rtol != b.krylov_rtol || a.krylov_max_iter != b.krylov_max_iter ||
             a.check_every != b.check_every || a.refine_rtol != b.refine_rtol ||
-            a.refine_max != b.refine_max || a.launch != b.launch)
+            a.refine_max != b.refine_max || a.launch != b.launch ||
+            a.trace_guess != b.trace_guess)
             return fail(IMEXHDG_E_INVAL, "member " + std::to_string(m) +
                                              " differs from member 0 in more than nx, ny, "
                                              "Lx, Ly and dt");
@@ -1260,6 +1263,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     int rc;
     if ((rc = build_plans(c))) return bail(rc);
     c->xcoef = guess_coefficients(c->tab);
+    if (cf[0].trace_guess == IMEXHDG_GUESS_LAST) std::fill(c->xcoef.begin(), c->xcoef.end(), 0.0);
     Geom &g = c->geom;
     g.K = K;
     g.phiB = cf[0].g * cf[0].H;
@@ -1474,6 +1478,7 @@ int imexhdg_config_init(imexhdg_config *c) {
     c->refine_rtol = 1e-13;
     c->refine_max = 4;
     c->launch = IMEXHDG_LAUNCH_GRAPH;
+    c->trace_guess = IMEXHDG_GUESS_EXTRAPOLATE;
     return IMEXHDG_OK;
 }
 

@@ -19,6 +19,7 @@ SCHEME_ARS232, SCHEME_ARS443 = 0, 1
 PHYSICS_LINEARIZED, PHYSICS_NONLINEAR = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 LAUNCH_GRAPH, LAUNCH_HOST = 0, 1
+GUESS_EXTRAPOLATE, GUESS_LAST = 0, 1
 VARS_DEPTH, VARS_GEOPOTENTIAL = 0, 1
 
 EXPORTS = [
@@ -52,7 +53,7 @@ class Config(ctypes.Structure):
         ("krylov_rtol", ctypes.c_double),
         ("krylov_max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("refine_rtol", ctypes.c_double), ("refine_max", ctypes.c_int32),
-        ("launch", ctypes.c_int32),
+        ("launch", ctypes.c_int32), ("trace_guess", ctypes.c_int32),
     ]
 
 

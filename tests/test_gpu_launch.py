@@ -150,3 +150,38 @@ def test_launch_geometry_errors():
     with pytest.raises(m.ImexError) as e:
         S.autotune()
     assert e.value.code == m.E_STATE
+
+
+@pytest.mark.parametrize("prec", [m.PREC_FP64, m.PREC_MIXED])
+def test_trace_guess_same_state_fewer_iterations(prec):
+    """The extrapolated trace guess is a heuristic of the solver: against the
+    last stage solution as the guess, the states agree to the solve
+    tolerance and the stage solves take fewer inner iterations.  64^2, k = 4,
+    the bump recipe at its time step, 12 graph steps."""
+    from paper_1711_02751_amd import workloads as W
+    wl = W.WORKLOADS["bump_64x64_k4"]
+    print(f"trace guess prec={prec}", flush=True)
+    out = {}
+    for guess in (m.GUESS_LAST, m.GUESS_EXTRAPOLATE):
+        cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
+                               dt=wl.dt, precision=prec, launch=m.LAUNCH_GRAPH,
+                               trace_guess=guess)
+        if prec == m.PREC_MIXED:
+            cfg.krylov_rtol, cfg.refine_rtol, cfg.refine_max = 1e-6, 1e-9, 8
+        S = m.Solver(cfg)
+        x, y = S.nodes()
+        S.set_state(*wl.initial_state(x, y))
+        S.step(12)
+        d = S.diag()
+        out[guess] = (np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)), d)
+        print(f"  guess {guess}: {d['krylov_iters']} inner iterations over "
+              f"{d['stage_solves']} solves, schedule {S.schedule()}", flush=True)
+        S.close()
+    mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
+    a = out[m.GUESS_LAST][0].reshape(mesh.shape)
+    b = out[m.GUESS_EXTRAPOLATE][0].reshape(mesh.shape)
+    err = swe.rel_l2(mesh, a, b)
+    print("  state difference", err, flush=True)
+    assert np.all(err < (1e-11 if prec == m.PREC_FP64 else 1e-7))
+    assert (out[m.GUESS_EXTRAPOLATE][1]["krylov_iters"]
+            < out[m.GUESS_LAST][1]["krylov_iters"])
