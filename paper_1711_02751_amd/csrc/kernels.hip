@@ -1311,7 +1311,7 @@ __device__ __forceinline__ void tile_rows(const T *__restrict__ const *frags, co
     zero_acc<K, NM, T>(acc);
     FragSlot<K, NM, T> cur, nxt;
     if (PF) load_frags<K, NM, T>(frags, wf.set, 0, cur);
-#pragma unroll 1
+#pragma unroll
     for (int s = 0; s < 7; ++s) {
         if (PF) {
             if (s + 1 < 7) load_frags<K, NM, T>(frags, wf.set, s + 1, nxt);
