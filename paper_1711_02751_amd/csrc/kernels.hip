@@ -1321,8 +1321,10 @@ __device__ __forceinline__ void tile_rows(const T *__restrict__ const *frags, co
         const int li = slot_lds(wf.set, s, lx, wf.sub, TL::NX, TL::XC, TL::YC);
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
+            // rows past 3K meet zero columns of A: any finite staged value
+            // serves, so the read is clamped instead of branched around
             const int cj = 4 * u + q;
-            const T b = cj < B3 ? sB[cj * NF + li] : T(0);
+            const T b = sB[(cj < B3 ? cj : B3 - 1) * NF + li];
 #pragma unroll
             for (int m = 0; m < NM; ++m)
 #pragma unroll
