@@ -43,9 +43,35 @@ __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// v from lane l ^ m within groups of lanes (data-parallel primitives: a
+// quad permutation or a row mirror), in two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave, the same value in every lane: within each row of 16
+// lanes by exchanges between lanes (quad xor 1, quad xor 2, half-row
+// mirror, row mirror; both partners of an exchange add the same two values,
+// so every lane of a row holds the same sum), then the four row sums in a
+// fixed order.  Every lane of the wave must be active (callers: whole
+// blocks of multiples of 64 threads in uniform control flow).
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);   // row_half_mirror
+    v += dpp_d<0x140>(v);   // row_mirror
+    return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 // Matrices shared by all lanes of a wave are read through the constant
