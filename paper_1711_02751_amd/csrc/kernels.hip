@@ -147,6 +147,11 @@ __device__ __forceinline__ Member load_member(const Batch &bt, int i) {
 // global memory, which on this target waits for every vector memory
 // operation in flight, loads included; a barrier that only hands LDS data
 // between waves need not wait for the global loads issued ahead of it.
+// Materialise a kernel argument in scalar registers here: the compiler
+// otherwise loads arguments where they are first used, one dependent
+// round trip each, on the path to the first global loads.
+template <typename P> __device__ __forceinline__ void arg_now(P p) { asm volatile("" ::"s"(p)); }
+
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -154,11 +159,12 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Block sum of NV values per thread; the result is returned to every thread.
-template <int NV>
+// BD > 0: the block size, known at compile time (no argument load).
+template <int NV, int BD = 0>
 __device__ void block_sum(double (&v)[NV]) {
     __shared__ double sred[16][NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nw = (blockDim.x + 63) >> 6;
+    const int nw = BD > 0 ? BD / 64 : (blockDim.x + 63) >> 6;
     lds_barrier();
     for (int q = 0; q < NV; ++q) {
         double s = wave_sum(v[q]);
@@ -174,9 +180,9 @@ __device__ void block_sum(double (&v)[NV]) {
 }
 
 // partials[q * stride + blockIdx.x] = block sum of v[q]
-template <int NV>
+template <int NV, int BD = 0>
 __device__ void store_partials(double (&v)[NV], double *partials, int stride) {
-    block_sum<NV>(v);
+    block_sum<NV, BD>(v);
     if (threadIdx.x == 0)
         for (int q = 0; q < NV; ++q) partials[q * stride + blockIdx.x] = v[q];
 }
@@ -217,7 +223,7 @@ __device__ void reduce_partials(const double *__restrict__ partials, int stride,
 // Loads whose result is not needed read a valid address and are discarded
 // rather than skipped: a load under a branch leaves the compiler unsure
 // how many loads follow an earlier one, and it then waits for all of them.
-template <int NV> struct EarlyPartials {
+template <int NV, int BD = 0> struct EarlyPartials {
     double a[NV], b[NV];   // this thread's first value, the sum of the others
     bool has;
     __device__ __forceinline__ void load(const double *__restrict__ partials, int stride, int n) {
@@ -228,14 +234,15 @@ template <int NV> struct EarlyPartials {
             a[q] = partials[q * stride + (has ? i : 0)];
             b[q] = 0.0;
         }
-        for (int j = i + (int)blockDim.x; j < n; j += blockDim.x)
+        const int bd = BD > 0 ? BD : (int)blockDim.x;
+        for (int j = i + bd; j < n; j += bd)
 #pragma unroll
             for (int q = 0; q < NV; ++q) b[q] += partials[q * stride + j];
     }
     __device__ __forceinline__ void finish(double (&out)[NV]) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) out[q] = has ? a[q] + b[q] : 0.0;
-        block_sum<NV>(out);
+        block_sum<NV, BD>(out);
     }
 };
 
@@ -1900,15 +1907,21 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const T *__restrict__ rh, T *__restrict__ t, KrylovState *ks_all,
     const double *P1, double *P2, int stride) {
     constexpr int NMB = MF<K>::NMB;
+    arg_now(stride);
+    arg_now(ks_all);
     int lb;
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
-    if (ks->conv) return;
+    // the member's fields and the flag in one round trip
+    const int conv = ks->conv;
+    arg_now(mb.to);
+    arg_now(mb.bf);
+    if (conv) return;
     const double tol2 = ks->tol2;
     // issue order: the partial sums, the A operands, the first tile; the
     // partial sums are reduced while the rest is in flight
-    EarlyPartials<3> ep;
+    EarlyPartials<3, kFaceThreads> ep;
     ep.load(P1 + mb.bf, stride, mb.nbf);
     __shared__ T sA[FragLds<K, T>::alloc];
     const T *gfr[1] = {ghat_frags(mb, T(0))};
@@ -1992,7 +2005,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                     }
         }
     }
-    store_partials<3>(acc2, P2, stride);
+    store_partials<3, kFaceThreads>(acc2, P2, stride);
     if (lb == 0 && threadIdx.x == 0) {
         ks->rho = rho;
         ks->alpha = alpha;
@@ -2019,15 +2032,21 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ r, T *__restrict__ d,
     KrylovState *ks_all, const double *P2, double *P1, int stride) {
     constexpr int NMB = MF<K>::NMB;
+    arg_now(stride);
+    arg_now(ks_all);
     int lb;
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
-    if (ks->conv) return;
+    // the member's fields and the flag in one round trip
+    const int conv = ks->conv;
+    arg_now(mb.to);
+    arg_now(mb.bf);
+    if (conv) return;
     const double rho = ks->rho, alpha = ks->alpha, rvv = ks->rv;
     // issue order: the partial sums, the A operands, the first tile; the
     // partial sums are reduced while the rest is in flight
-    EarlyPartials<3> ep;
+    EarlyPartials<3, kFaceThreads> ep;
     ep.load(P2 + mb.bf, stride, mb.nbf);
     __shared__ T sA[FragLds<K, T>::alloc];
     const T *gfr[1] = {ghat_frags(mb, T(0))};
@@ -2167,7 +2186,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     }
         }
     }
-    store_partials<3>(acc1, P1, stride);
+    store_partials<3, kFaceThreads>(acc1, P1, stride);
     if (lb == 0 && threadIdx.x == 0) {
         ks->omega = omega;
         ks->iters += 1;
