@@ -1498,10 +1498,17 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
     RT *__restrict__ rin, double *partials, int stride, const KrylovState *skip) {
     using T = double;
     constexpr int NMB = MF<K>::NMB, B3 = 3 * K;
+    arg_now(stride);
+    arg_now(skip);
     int lb;
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
-    if (skip && skip[mi].stage_done) return;
     const Member mb = load_member(bt, mi);
+    // the member's fields and the flag in one round trip
+    const int done = skip ? skip[mi].stage_done : 0;
+    arg_now(mb.to);
+    arg_now(mb.bf);
+    arg_now(mb.G);
+    if (done) return;
     const bool want_rin = rin != nullptr;
     x += mb.to; gv += mb.to;
     if (want_rin) rin += mb.to;
@@ -1602,7 +1609,7 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
                     }
         }
     }
-    store_partials<4>(acc4, partials, stride);
+    store_partials<4, kFaceThreads>(acc4, partials, stride);
 }
 
 // ------------------------------------------------------------ BiCGStab
@@ -1792,11 +1799,18 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
     const double *res_partials, int rstride, double refine_rtol, double inner_rtol,
     double *P1, int stride) {
     constexpr int NMB = MF<K>::NMB;
+    arg_now(ks_all);
+    arg_now(rstride);
+    arg_now(stride);
     int lb;
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     KrylovState *ks = ks_all + mi;
-    if (ks->stage_done) return;
     const Member mb = load_member(bt, mi);
+    // the member's fields and the flag in one round trip
+    const int done = ks->stage_done;
+    arg_now(mb.to);
+    arg_now(mb.bf);
+    if (done) return;
     // issue order: the residual norms, the A operands, the first tile
     EarlyPartials<4> ep;
     ep.load(res_partials + mb.bf, rstride, mb.nbf);
