@@ -656,7 +656,6 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
                                                       KrylovState *begin,
                                                       double *__restrict__ x,
                                                       double *__restrict__ xp, double xc) {
-    const int lane = threadIdx.x & 63;
     const int j = wave_id();
     // the member's blocks are [2 bv, 2 (bv + nbv)): x-face tiles, then y
     int lb;
