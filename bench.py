@@ -90,9 +90,10 @@ def kernel_symbol(kernel_class, K, mixed):
 
 
 def measured_traffic(kernel_class, wl, precision="fp64"):
-    """HBM bytes per dispatch from the committed FETCH_SIZE / WRITE_SIZE
-    profile of this workload, or None when the kernel source has changed
-    since the counters were taken."""
+    """HBM bytes per working dispatch (the launches that did work, as for
+    `achieved`) from the committed FETCH_SIZE / WRITE_SIZE profile of this
+    workload, or None when the kernel source has changed since the counters
+    were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{precision}.json")
     src = os.path.join(ROOT, "paper_1711_02751_amd", "csrc", "kernels.hip")
@@ -105,7 +106,9 @@ def measured_traffic(kernel_class, wl, precision="fp64"):
     if d.get("kernels_hip_sha256") != sha:
         return None
     rec = d["per_dispatch"].get(kernel_symbol(kernel_class, wl.k + 1, precision == "mixed"))
-    return None if rec is None else rec["hbm_bytes"]
+    if rec is None:
+        return None
+    return rec.get("working_hbm_bytes", rec["hbm_bytes"])
 
 
 def cpu_baseline(wl_name, seconds=15.0):
