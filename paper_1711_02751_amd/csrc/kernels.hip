@@ -1151,6 +1151,17 @@ template <int K> struct Tile {
     static constexpr int NX = XR * XC, NY = YR * YC, NF = NX + NY;
 };
 
+// LDS row stride of a staged tile of T values.  FP32: 16 words past a
+// multiple of the 64 banks, so the four rows that one matrix-core B read
+// spans (lane groups l / 16) fall into disjoint banks.  FP64 keeps the
+// dense stride (the padded one costs its Krylov kernels their occupancy).
+template <int K, typename T> struct TileRow {
+    static constexpr int NF = Tile<K>::NF;
+    static constexpr int stride = sizeof(T) == 4 ? NF + (80 - NF % 64) % 64 : NF;
+    // LDS index of staged value v = cj NF + f
+    static __device__ __forceinline__ int lds(int v) { return v + (v / NF) * (stride - NF); }
+};
+
 // Staged face f of the tile with corner (ex0, ey0) -> direction, global face
 // (element) index, and whether the tile owns it (it is a face of one of the
 // tile's own elements).
@@ -1208,7 +1219,7 @@ __device__ __forceinline__ T apply_comb(Comb &comb, const T (&a)[NA], const T (&
     else return comb(a, o, off, own, li);
 }
 
-// Stage the tile: sB[cj NF + f] = comb(raw, o, own) for every staged face
+// Stage the tile: sB[cj stride + f] = comb(raw, o, own) for every staged face
 // f and row cj (c' K + j'), where raw holds the NA source arrays at trace
 // offset o; comb may store the value at o when the tile owns the face.
 // With NO > 0, the NO arrays osrc are also loaded at the faces the tile
@@ -1250,7 +1261,7 @@ __device__ __forceinline__ void stage_tile(int tile, const Member &g, T *sB,
 #pragma unroll
         for (int u = 0; u < CH; ++u)
             if (ok[u]) {
-                const int li = threadIdx.x + kFaceThreads * (i0 + u);
+                const int li = TileRow<K, T>::lds(threadIdx.x + kFaceThreads * (i0 + u));
                 sB[li] = apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u], li);
             }
     }
@@ -1320,7 +1331,7 @@ template <int K, typename T, int NA, int NO = 0> struct StagedTile {
 #pragma unroll
             for (int u = 0; u < PER; ++u)
                 if (ok[u]) {
-                    const int li = threadIdx.x + kFaceThreads * u;
+                    const int li = TileRow<K, T>::lds(threadIdx.x + kFaceThreads * u);
                     sB[li] = apply_comb<NO>(comb, raw[u], oraw[u], off[u], own[u], li);
                 }
         } else {
@@ -1337,7 +1348,7 @@ __device__ __forceinline__ void tile_rows(const T *__restrict__ const *frags, co
                                           const WaveFaces &wf,
                                           typename MfmaT<T>::v4 (&acc)[NM][MF<K>::NMB]) {
     using TL = Tile<K>;
-    constexpr int B3 = TL::B3, NF = TL::NF, KS = MF<K>::KS, NMB = MF<K>::NMB;
+    constexpr int B3 = TL::B3, NF = TileRow<K, T>::stride, KS = MF<K>::KS, NMB = MF<K>::NMB;
     constexpr bool PF = FragPrefetch<K, NM, T>::value;
     const int lane = threadIdx.x & 63, q = lane >> 4, lx = lane & 15;
     zero_acc<K, NM, T>(acc);
@@ -1403,7 +1414,7 @@ __device__ __forceinline__ int face_tiles(const Member &g) {
 
 // LDS of a staged tile.
 template <int K, typename T> struct TileLds {
-    static constexpr int n = MF<K>::B3 * Tile<K>::NF;
+    static constexpr int n = MF<K>::B3 * TileRow<K, T>::stride;
 };
 
 // The matrix-core fragments (both face sets, NM matrices) are copied into
@@ -2001,7 +2012,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
 #pragma unroll
                     for (int e4 = 0; e4 < 4; ++e4) {
                         const int row = 16 * m + MfmaT<T>::row(threadIdx.x & 63, e4);
-                        if (ok[m][e4]) sown[m][e4] = sB[row * Tile<K>::NF + li];
+                        if (ok[m][e4]) sown[m][e4] = sB[row * TileRow<K, T>::stride + li];
                     }
             }
 #pragma unroll
@@ -2155,7 +2166,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     for (int e4 = 0; e4 < 4; ++e4)
                         if (ok[m][e4]) {
                             const int row = 16 * m + MfmaT<T>::row(threadIdx.x & 63, e4);
-                            const double rd = sR[row * Tile<K>::NF + li];
+                            const double rd = sR[row * TileRow<K, T>::stride + li];
                             acc1[1] += (double)rhv[m][e4] * rd;
                             acc1[2] += rd * rd;
                         }
