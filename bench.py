@@ -59,11 +59,12 @@ def algorithmic_cost(name, wl, n_dof, isz=8):
         "bicg_k2": (4 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
         # fused K1: read r, t, p, v, rh, d; write r, p, v, d
         "bicg_k1f": (10 * T * isz, 2.0 * 7 * b3 * b3 * nfaces),
-        # read x, g, ghat (FP64); write rin (inner)
-        "trace_residual": (3 * T * 8 + T * isz, 4.0 * 7 * b3 * b3 * nfaces),
+        # read x, g (FP64); write rin (inner); G x over 7 slots, P^-1 g and P^-1 r
+        "trace_residual": (2 * T * 8 + T * isz, 2.0 * 9 * b3 * b3 * nfaces),
         "local_apply": (2 * N * 8, 2.0 * (3 * K * K) ** 2 * nel),
         "recover": ((2 * N + T) * 8, 2.0 * (3 * K * K) * 12 * K * nel),
-        "trace_rhs": (4 * T * 8, 2.0 * b3 * b3 * nfaces),
+        # read Z at the face nodes, x, x_prev; write g, x, x_prev
+        "trace_rhs": (6 * T * 8, 2.0 * b3 * b3 * nfaces),
         "axpy": (2 * T * 8 + T * isz, 2.0 * T),
         # read Q, write NL and the combination, read about 2.5 inputs on average
         "nl_residual": (5.5 * N * 8, 60.0 * N),
