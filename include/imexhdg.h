@@ -221,7 +221,7 @@ int imexhdg_stage_solve(imexhdg_ctx *ctx, const double *d_res0, double *d_Q,
 #define IMEXHDG_K_COMBINE      1  /* stage combination (linearized)        */
 #define IMEXHDG_K_LOCAL_APPLY  2  /* Z = A^-1 Res0 per element             */
 #define IMEXHDG_K_TRACE_RHS    3  /* g = sum C Z; extrapolated trace guess */
-#define IMEXHDG_K_TRACE_RESID  4  /* FP64 r = g - G x, rin = P^-1 r          */
+#define IMEXHDG_K_TRACE_RESID  4  /* FP64 r = g - G x, rin = P^-1 r         */
 #define IMEXHDG_K_BICG_INIT    5
 #define IMEXHDG_K_BICG_K1      6  /* first p + v = Ghat p of an inner solve */
 #define IMEXHDG_K_BICG_K2      7  /* s update + t = Ghat s, t.s, t.t, rh.t  */
