@@ -179,12 +179,25 @@ __device__ void block_sum(double (&v)[NV]) {
     lds_barrier();
 }
 
-// partials[q * stride + blockIdx.x] = block sum of v[q]
+// partials[q * stride + blockIdx.x] = block sum of v[q], the same sum in
+// the same order as block_sum, formed by thread 0 only.  Called once, at
+// the end of a kernel (its LDS is not reused, so no barrier precedes it).
 template <int NV, int BD = 0>
 __device__ void store_partials(double (&v)[NV], double *partials, int stride) {
-    block_sum<NV, BD>(v);
+    __shared__ double sred[16][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = BD > 0 ? BD / 64 : (blockDim.x + 63) >> 6;
+    for (int q = 0; q < NV; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) sred[w][q] = s;
+    }
+    lds_barrier();
     if (threadIdx.x == 0)
-        for (int q = 0; q < NV; ++q) partials[q * stride + blockIdx.x] = v[q];
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int i = 0; i < nw; ++i) s += sred[i][q];
+            partials[q * stride + blockIdx.x] = s;
+        }
 }
 
 // out[q] = sum_{b < n} partials[q * stride + b], identical in every block
