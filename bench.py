@@ -112,33 +112,73 @@ def measured_traffic(kernel_class, wl, precision="fp64"):
     return rec.get("working_hbm_bytes", rec["hbm_bytes"])
 
 
-def cpu_baseline(wl_name, seconds=15.0):
-    """FP64 oracle on a bounded sample: the same recipe (physics, degree,
-    dt = 5 dx_min, seed) on a 64 x 64 mesh, single-threaded, timed after its
-    one-off factorisation."""
+def cpu_model():
+    """CPU model string of the host (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def _oracle_rate(wl, n, threads, seconds):
+    """Steps of the FP64 oracle on an n x n sample of the workload's recipe
+    (same physics, degree, seed and Courant number: dt scaled with the mesh)
+    with at most `threads` BLAS / FFT threads, timed after its one-off
+    factorisation and one warm step.  Returns (DOF-updates/s, steps,
+    wall s, effective cores = process CPU time / wall time)."""
     from threadpoolctl import threadpool_limits
     from oracle import imex, swe
     from paper_1711_02751_amd import workloads as W
-    wl = W.WORKLOADS[wl_name]
-    n = min(wl.n, 64)
     dt = wl.dt * wl.n / n
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         P = imex.Problem(n, n, wl.L, wl.L, wl.k, wl.g, wl.H, dt, nonlinear=wl.nonlinear,
                          solver="circulant")
         x, y = P.mesh.coords()
         h, hu, hv = W.bump_flow(x, y, wl.seed, H=wl.H, n_bumps=wl.n_bumps, Lx=wl.L, Ly=wl.L)
         q = swe.from_user(h, hu, hv, wl.g, wl.H)
         q = P.step(q)  # first step outside the clock
-        steps, t0 = 0, time.perf_counter()
+        steps, t0, c0 = 0, time.perf_counter(), time.process_time()
         while time.perf_counter() - t0 < seconds:
             q = P.step(q)
             steps += 1
-        el = time.perf_counter() - t0
+        el, cpu = time.perf_counter() - t0, time.process_time() - c0
     ndof = 3 * n * n * (wl.k + 1) ** 2
-    return {"value": ndof * steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n}x{n} mesh, k={wl.k}, same recipe and CFL, {steps} ARS2 steps "
-                      f"after one warm step (block-circulant direct stage solve)",
-            "seconds": el}
+    return ndof * steps / el, steps, el, cpu / el
+
+
+def cpu_baseline(wl_name, seconds=15.0):
+    """FP64 oracle on a bounded sample: the same recipe (physics, degree,
+    dt = 2 dx_min, seed) on a 64 x 64 mesh, with all host cores' worth of
+    BLAS / FFT threads and with one thread, each timed for `seconds` / 2
+    after its one-off factorisation.  The oracle is plain NumPy / SciPy:
+    most of its work runs on one thread whatever the limit, which the
+    effective core count (CPU time / wall time) shows."""
+    from paper_1711_02751_amd import workloads as W
+    wl = W.WORKLOADS[wl_name]
+    n = min(wl.n, 64)
+    nproc = os.cpu_count() or 1
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    many = _oracle_rate(wl, n, nproc, seconds / 2)
+    one = _oracle_rate(wl, n, 1, seconds / 2)
+    best, threads = (many, nproc) if many[0] >= one[0] else (one, 1)
+    return {"value": best[0], "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n}x{n} mesh, k={wl.k}, same recipe and Courant number, "
+                      f"{best[1]} ARS2 steps after one warm step (block-circulant direct "
+                      f"stage solve), best of {nproc} threads and 1 thread",
+            "seconds": best[2], "effective_cores": best[3],
+            "threads_nproc": {"threads": nproc, "value": many[0], "steps": many[1],
+                              "effective_cores": many[3]},
+            "threads_1": {"threads": 1, "value": one[0], "steps": one[1],
+                          "effective_cores": one[3]},
+            "cpu_model": cpu_model()}
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_1711_02751_amd", "tuning_cache.txt")
@@ -257,6 +297,28 @@ def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     return res, state
 
 
+def run_large(m, wl, steps, warmup, tune_cache=TUNE_CACHE):
+    """The large single-mesh workload (1024^2, k = 6): both paths, each
+    with its own roofline object, and the mixed-vs-FP64 error of the final
+    states."""
+    from oracle import swe   # only for the mass-weighted norm of the comparison
+    log(f"[bench] large workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
+    f64, s64 = run_path(m, wl, "fp64", steps, warmup, tune_cache)
+    mix, smx = run_path(m, wl, "mixed", steps, warmup, tune_cache)
+    mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
+    err = swe.rel_l2(mesh, smx.reshape(mesh.shape), s64.reshape(mesh.shape))
+    del s64, smx
+    keep = ("value", "ms_per_step", "roofline", "krylov_iters_per_stage", "max_trace_relres",
+            "schedule", "grid_caps", "graph_steps", "redone_steps", "kernels")
+    return {"workload": wl.name, "mesh": f"{wl.n}x{wl.n}", "degree": wl.k,
+            "n_dof": mix["n_dof"], "n_trace": mix["n_trace"], "dt": wl.dt, "steps": steps,
+            "unit": "DOF-updates/s",
+            "mixed": {k: mix[k] for k in keep}, "fp64": {k: f64[k] for k in keep},
+            "speedup_mixed_vs_fp64": mix["value"] / f64["value"],
+            "mixed_rel_l2_vs_fp64": [float(e) for e in err],
+            "note": f"mixed vs FP64 after the same {steps} + 1 steps from the initial state"}
+
+
 def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
     """The 64-member ensemble (meshes 32^2 ... 128^2, k = 3, dt_m = 2 dx_min):
     every launch covers all members, one graph launch per step."""
@@ -323,7 +385,11 @@ def main():
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="launch-geometry cache: a line for this device and workload is "
                          "used as is, else the autotuner times the candidates and appends one")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--large-workload", default="bump_1024x1024_k6",
+                    help="second workload measured beside the headline one (both paths)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large-workload measurement")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -393,6 +459,9 @@ def main():
                        "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
         out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]
         out["mixed_rel_l2_vs_fp64"] = [float(e) for e in err]
+    if not args.no_large and args.large_workload != wl.name:
+        out["large"] = run_large(m, W.WORKLOADS[args.large_workload], args.steps, args.warmup,
+                                 args.tune_cache)
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(m, args.steps, args.warmup,
                                        mixed=args.precision == "mixed",

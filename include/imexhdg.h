@@ -88,6 +88,10 @@ extern "C" {
 #define IMEXHDG_VARS_DEPTH       0  /* (h, hu, hv): depth and momenta        */
 #define IMEXHDG_VARS_GEOPOTENTIAL 1 /* (phi_eta, U, V) = (g(h-H), g hu, g hv) */
 
+/* element type of device state arrays (imexhdg_set_state_device)          */
+#define IMEXHDG_DTYPE_F64 0
+#define IMEXHDG_DTYPE_F32 1
+
 typedef struct imexhdg_config {
     int32_t nx, ny;          /* elements per direction, >= 1               */
     double  Lx, Ly;          /* periodic domain [0,Lx) x [0,Ly), > 0       */
@@ -119,7 +123,29 @@ typedef struct imexhdg_diag {
     int32_t nonfinite;       /* 1 if the state holds NaN/Inf               */
     int64_t graph_steps;     /* steps run as one graph launch, cumulative  */
     int64_t redo_steps;      /* graph steps redone host-driven, cumulative */
+    double  step_ms;         /* host wall time inside imexhdg_step since the
+                                last set_state, stream synchronised (ms)   */
+    /* Device time per phase of the step (ms), summed over the launches the
+     * kernel event profiler timed since the last imexhdg_profile() call
+     * (all zero while it is off; with imexhdg_profile(ctx, -1) every class
+     * is timed).  Phases, by IMEXHDG_PHASE_*:
+     *   EXPLICIT   DG residual M^-1 NL of the nonlinear part with the stage
+     *              combinations (Sec. 4.3; eq. IMEXRKDiscretizedForm);
+     *   CONDENSE   static condensation: Z = A^-1 Res0 per element and the
+     *              trace right-hand side (eq. linearizedHDGsystem_schur);
+     *   TRACE      the global trace solve: FP64 residuals, the inner
+     *              Krylov iterations and the refinement updates;
+     *   RECOVER    local recovery Q = A^-1 (R1 - B Qhat)
+     *              (eq. recover_volume_unknowns);
+     *   OTHER      diagnostics and operator-level calls.                   */
+    double  phase_ms[5];
 } imexhdg_diag;
+
+#define IMEXHDG_PHASE_EXPLICIT 0
+#define IMEXHDG_PHASE_CONDENSE 1
+#define IMEXHDG_PHASE_TRACE    2
+#define IMEXHDG_PHASE_RECOVER  3
+#define IMEXHDG_PHASE_OTHER    4
 
 typedef struct imexhdg_ctx imexhdg_ctx;
 
@@ -135,8 +161,11 @@ int imexhdg_validate(const imexhdg_config *cfg);
 int imexhdg_workspace_bytes(const imexhdg_config *cfg, size_t *bytes);
 
 /* Create a context: validate, precompute the element operators in FP64 on
- * the host (local solver A^-1, A^-1 B, Schur blocks of the trace system and
- * their block-Jacobi inverses) and upload them.
+ * the host (local solver A^-1, A^-1 B of eq. recover_volume_unknowns, the
+ * row blocks of the condensed trace system of eq.
+ * linearizedHDGsystem_schur and their block-Jacobi inverses; one SDIRK
+ * coefficient dt a~_ii serves every implicit stage, Sec. 5) and upload
+ * them.
  *   stream      hipStream_t the context enqueues on (NULL = null stream);
  *               caller owned, must outlive the context.
  *   workspace   device buffer of >= imexhdg_workspace_bytes() bytes,
@@ -149,18 +178,41 @@ int imexhdg_create(const imexhdg_config *cfg, void *stream, void *workspace,
 /* NULL-safe; synchronises the context's stream first.                    */
 void imexhdg_destroy(imexhdg_ctx *ctx);
 
+/* Sizes of the discrete spaces (Sec. 4.1): n_nodes = nx ny (k+1)^2 nodes
+ * of the tensor-product space Q_k per variable, n_trace = 6 (k+1) nx ny
+ * trace unknowns (three variables at the k+1 edge nodes of the 2 nx ny
+ * faces of the periodic grid).  Either pointer may be NULL.              */
 int imexhdg_sizes(const imexhdg_ctx *ctx, int64_t *n_nodes, int64_t *n_trace);
 
-/* Node coordinates (host, n_nodes each, host state ordering).            */
+/* Coordinates of the nodes of the nodal basis (Sec. 4.1; LGL nodes mapped
+ * affinely onto each element), for evaluating initial states: caller-owned
+ * host arrays of n_nodes doubles each, host state ordering.              */
 int imexhdg_get_nodes(const imexhdg_ctx *ctx, double *x, double *y);
 
-/* Copy a state in (host arrays of n_nodes doubles, host state ordering);
- * `vars` is IMEXHDG_VARS_*.  Rejects non-finite values, h <= 0 and
- * supercritical nodes |u| >= sqrt(g h) with IMEXHDG_E_INVAL.              */
+/* Set q^n, the state at the nodes (Sec. 3.1 variables; Algorithm 1 takes
+ * it as its input): host arrays of n_nodes doubles, host state ordering,
+ * copied during the call; `vars` is IMEXHDG_VARS_*.  Rejects non-finite
+ * values, h <= 0 and supercritical nodes |u| >= sqrt(g h) (the regime of
+ * Sec. 3) with IMEXHDG_E_INVAL, leaving the state unchanged.  Resets the
+ * trace guess and the step count.                                        */
 int imexhdg_set_state(imexhdg_ctx *ctx, int vars, const double *a,
                       const double *b, const double *c);
 
-/* Copy the state out; synchronises the stream.                           */
+/* The same from device memory without a host copy, e.g. from a torch
+ * tensor: d_state holds 3 * n_nodes values of type `dtype`
+ * (IMEXHDG_DTYPE_*), the three variables one after the other, each in the
+ * host state ordering (a contiguous (3, n_nodes) array).  The conversion
+ * and the checks of imexhdg_set_state run on the device, ordered on the
+ * context's stream after the work already enqueued there (so a producer on
+ * that stream needs no synchronisation); the call then synchronises the
+ * stream to read the outcome of the checks.  d_state is borrowed for the
+ * call only.  IMEXHDG_E_INVAL for a rejected state (the state is left
+ * unchanged) or an unknown vars / dtype.                                 */
+int imexhdg_set_state_device(imexhdg_ctx *ctx, int vars, int dtype,
+                             const void *d_state);
+
+/* Copy q^n out (Sec. 3.1 variables, `vars` as for set_state) into
+ * caller-owned host arrays of n_nodes doubles; synchronises the stream.  */
 int imexhdg_get_state(imexhdg_ctx *ctx, int vars, double *a, double *b,
                       double *c);
 
@@ -180,8 +232,10 @@ int imexhdg_get_state(imexhdg_ctx *ctx, int vars, double *a, double *b,
  * refine_max sweeps (the state is still advanced). */
 int imexhdg_step(imexhdg_ctx *ctx, int32_t nsteps);
 
-/* FP64 mass and energy of the current state plus solver counters;
- * synchronises the stream.                                               */
+/* FP64 diagnostics of the current state: the discrete mass of each
+ * variable (exactly conserved by the scheme, Sec. 5) and the energy E^h of
+ * Lemma sdStability (Sec. 4.2), with the solver counters and the step and
+ * phase times; synchronises the stream.                                  */
 int imexhdg_get_diag(imexhdg_ctx *ctx, imexhdg_diag *d);
 
 /* Thread-local text of the last error ("" if none).                      */
@@ -311,6 +365,9 @@ int imexhdg_ens_sizes(const imexhdg_ens *ens, int32_t m, int64_t *n_nodes,
 int imexhdg_ens_get_nodes(const imexhdg_ens *ens, int32_t m, double *x, double *y);
 int imexhdg_ens_set_state(imexhdg_ens *ens, int32_t m, int vars, const double *a,
                           const double *b, const double *c);
+/* Member m's state from device memory, as imexhdg_set_state_device.      */
+int imexhdg_ens_set_state_device(imexhdg_ens *ens, int32_t m, int vars, int dtype,
+                                 const void *d_state);
 int imexhdg_ens_get_state(imexhdg_ens *ens, int32_t m, int vars, double *a, double *b,
                           double *c);
 /* Advance every member nsteps steps; returns when they are done.         */

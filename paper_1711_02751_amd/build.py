@@ -21,7 +21,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-munsafe-fp-atomics"]
+          "-packed-fp32-ops"]
 SOURCES = ["element.cpp", "imexhdg.cpp", "kernels.hip"]
 
 

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <fstream>
@@ -162,8 +163,11 @@ struct imexhdg_ctx {
     std::vector<bool> store_nl;
     // counters
     int64_t steps = 0, kiters = 0, solves = 0, sweeps = 0;
+    double step_ms = 0.0;             // host wall time inside step calls since set_state
     double last_relres = 0.0, max_relres = 0.0;
     int iter_pred = 0;      // inner iterations of the last first sweep
+    int dbg_brk = 0;        // debug (IMEXHDG_DEBUG_BREAKDOWN_AT): host-driven inner solves
+                            // take the breakdown branch in this K1f iteration (1-based)
     // fixed-schedule stepping: sweeps and inner-iteration budget per sweep,
     // what the last host-driven solves needed, one graph per ring position
     int sched_sweeps = 0, sched_budget[kMaxSweeps] = {};
@@ -620,9 +624,16 @@ int inner_solve(imexhdg_ctx *c, double tol2, int sweep) {
         for (int it = 0; it < n; ++it) {
             LAUNCH(IMEXHDG_K_BICG_K2,
                    launch_bicg_k2(g, b, r[rp], v[par], rh, t, c->ks, c->kb, c->stream));
+            // debug knob: force the breakdown branch of this K1f (the flag is
+            // set and cleared between launches, so every block sees one value)
+            const bool force = c->dbg_brk > 0 && done + it + 1 == c->dbg_brk;
+            if (force)
+                HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&c->ks->force_brk, 1, 1, c->stream));
             LAUNCH(IMEXHDG_K_BICG_K1F,
                    launch_bicg_k1f(g, b, r[rp], t, rh, p[par], v[par], p[1 - par], v[1 - par],
                                    r[1 - rp], d, c->ks, c->kb, c->stream));
+            if (force)
+                HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&c->ks->force_brk, 0, 1, c->stream));
             par = 1 - par;
             rp = 1 - rp;
         }
@@ -1358,7 +1369,9 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
             up(os.Px, op.Pxinv) || up(os.Py, op.Pyinv) || hipStreamSynchronize(c->stream))
             return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
     }
+    if (const char *db = std::getenv("IMEXHDG_DEBUG_BREAKDOWN_AT")) c->dbg_brk = std::atoi(db);
     if (hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
+        hipMemsetAsync(c->ks, 0, n * sizeof(KrylovState), c->stream) ||
         hipMemsetAsync(c->xp, 0, L.T * 8, c->stream) ||
         hipMemsetAsync(c->q, 0, L.N * 8, c->stream) ||
         hipMemsetAsync(c->dstat, 0, 3 * (size_t)L.s * n * sizeof(StageStatus), c->stream) ||
@@ -1370,9 +1383,21 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     return IMEXHDG_OK;
 }
 
+int step_ctx_run(imexhdg_ctx *c, int nsteps);
+
+// Steps with their host wall time (every path returns with the stream
+// synchronised, so the time covers the device work).
 int step_ctx(imexhdg_ctx *c, int nsteps) {
     if (nsteps < 0) return fail(IMEXHDG_E_INVAL, "nsteps must be >= 0");
     if (!c->have_state) return fail(IMEXHDG_E_STATE, "step before set_state");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = step_ctx_run(c, nsteps);
+    c->step_ms +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int step_ctx_run(imexhdg_ctx *c, int nsteps) {
     int status = IMEXHDG_OK;
     if (c->cfg.launch == IMEXHDG_LAUNCH_GRAPH && (c->prof_target == -2 || c->nm > 1)) {
         int rc = step_graph(c, nsteps, &status);
@@ -1391,6 +1416,8 @@ int step_ctx(imexhdg_ctx *c, int nsteps) {
     return IMEXHDG_OK;
 }
 
+int state_was_set(imexhdg_ctx *c, int m);
+
 int set_member_state(imexhdg_ctx *c, int m, int vars, const double *a, const double *b,
                      const double *cc) {
     if (!a || !b || !cc) return fail(IMEXHDG_E_INVAL, "NULL argument");
@@ -1406,6 +1433,13 @@ int set_member_state(imexhdg_ctx *c, int m, int vars, const double *a, const dou
     for (int v = 0; v < 3; ++v)
         HIP_TRY(hipMemcpyAsync(c->q + mh.vo + v * NN, h.data() + v * NN, NN * 8,
                                hipMemcpyHostToDevice, c->stream));
+    return state_was_set(c, m);
+}
+
+// After member m's state has been written (enqueued): reset its trace guess
+// and the step bookkeeping.
+int state_was_set(imexhdg_ctx *c, int m) {
+    const MemberHost &mh = c->mh[m];
     HIP_TRY(hipMemsetAsync(c->x + mh.to, 0, mh.T * 8, c->stream));
     HIP_TRY(hipMemsetAsync(c->xp + mh.to, 0, mh.T * 8, c->stream));
     HIP_TRY(stream_sync(c));
@@ -1414,7 +1448,36 @@ int set_member_state(imexhdg_ctx *c, int m, int vars, const double *a, const dou
                                 [](bool v) { return v; });
     c->cold = true;
     c->steps = 0;
+    c->step_ms = 0.0;
     return IMEXHDG_OK;
+}
+
+// Member m's state from a caller's device array (3 n_nodes values,
+// variable-major, host state ordering): converted and checked on the device
+// into the member's slice of Z (free between steps), then copied into q only
+// if every node passed, so a rejected state leaves q unchanged.
+int set_member_state_device(imexhdg_ctx *c, int m, int vars, int dtype, const void *src) {
+    if (!src) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (m < 0 || m >= c->nm) return fail(IMEXHDG_E_INVAL, "member index out of range");
+    if (vars != IMEXHDG_VARS_DEPTH && vars != IMEXHDG_VARS_GEOPOTENTIAL)
+        return fail(IMEXHDG_E_INVAL, "unknown vars");
+    if (dtype != IMEXHDG_DTYPE_F64 && dtype != IMEXHDG_DTYPE_F32)
+        return fail(IMEXHDG_E_INVAL, "unknown dtype");
+    const MemberHost &mh = c->mh[m];
+    const int K = c->geom.K;
+    const int blocks = state_in_blocks(mh.nel, K, c->pstride);
+    HIP_TRY(launch_state_in(src, dtype == IMEXHDG_DTYPE_F32, vars == IMEXHDG_VARS_DEPTH,
+                            c->cfg.g, c->cfg.H, mh.nel, K, c->Z + mh.vo, c->dpart, blocks,
+                            c->stream));
+    double bad = 0.0;
+    int rc = read_partials(c, 1, 0, blocks, &bad);
+    if (rc) return rc;
+    if (bad != 0.0)
+        return fail(IMEXHDG_E_INVAL, "state rejected at " + std::to_string((int64_t)bad) +
+                                         " nodes: NaN or Inf, h <= 0 or |u| >= sqrt(phi)");
+    HIP_TRY(hipMemcpyAsync(c->q + mh.vo, c->Z + mh.vo, mh.N * 8, hipMemcpyDeviceToDevice,
+                           c->stream));
+    return state_was_set(c, m);
 }
 
 int get_member_state(imexhdg_ctx *c, int m, int vars, double *a, double *b, double *cc) {
@@ -1432,6 +1495,24 @@ int get_member_state(imexhdg_ctx *c, int m, int vars, double *a, double *b, doub
     HIP_TRY(stream_sync(c));
     state_from_device(c, mh, vars, h, a, b, cc);
     return IMEXHDG_OK;
+}
+
+// Phase of the step a kernel class belongs to (IMEXHDG_PHASE_*).
+int phase_of(int k) {
+    switch (k) {
+        case IMEXHDG_K_NL:
+        case IMEXHDG_K_COMBINE: return IMEXHDG_PHASE_EXPLICIT;
+        case IMEXHDG_K_LOCAL_APPLY:
+        case IMEXHDG_K_TRACE_RHS: return IMEXHDG_PHASE_CONDENSE;
+        case IMEXHDG_K_TRACE_RESID:
+        case IMEXHDG_K_BICG_INIT:
+        case IMEXHDG_K_BICG_K1:
+        case IMEXHDG_K_BICG_K2:
+        case IMEXHDG_K_BICG_K1F:
+        case IMEXHDG_K_AXPY: return IMEXHDG_PHASE_TRACE;
+        case IMEXHDG_K_RECOVER: return IMEXHDG_PHASE_RECOVER;
+        default: return IMEXHDG_PHASE_OTHER;
+    }
 }
 
 int member_diag(imexhdg_ctx *c, int m, imexhdg_diag *d) {
@@ -1454,6 +1535,8 @@ int member_diag(imexhdg_ctx *c, int m, imexhdg_diag *d) {
     d->max_relres = c->max_relres;
     d->graph_steps = c->graph_steps;
     d->redo_steps = c->redos;
+    d->step_ms = c->step_ms;
+    for (int k = 0; k < IMEXHDG_K_COUNT; ++k) d->phase_ms[phase_of(k)] += c->prof_ms[k];
     return IMEXHDG_OK;
 }
 
@@ -1521,6 +1604,11 @@ int imexhdg_set_state(imexhdg_ctx *c, int vars, const double *a, const double *b
                       const double *cc) {
     if (!c) return fail(IMEXHDG_E_INVAL, "NULL argument");
     return set_member_state(c, 0, vars, a, b, cc);
+}
+
+int imexhdg_set_state_device(imexhdg_ctx *c, int vars, int dtype, const void *d_state) {
+    if (!c) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    return set_member_state_device(c, 0, vars, dtype, d_state);
 }
 
 int imexhdg_get_state(imexhdg_ctx *c, int vars, double *a, double *b, double *cc) {
@@ -1872,7 +1960,7 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
         HIP_TRY(hipMemcpyAsync(c->xsave, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
         const int64_t keep[6] = {c->steps, c->kiters, c->solves, c->sweeps, c->graph_steps,
                                  c->redos};
-        const double keep_r[2] = {c->last_relres, c->max_relres};
+        const double keep_r[3] = {c->last_relres, c->max_relres, c->step_ms};
         // (cap, tiles per block): caps alone, then uniform tiles per block
         const int cand[12][2] = {{16, 0},   {32, 0},   {48, 0},   {64, 0},
                                  {96, 0},   {128, 0},  {1024, 0}, {kMaxLaunchGrid, 2},
@@ -1905,6 +1993,7 @@ int imexhdg_ens_autotune(imexhdg_ens *e, const char *cache_path, int32_t *face_g
         c->redos = keep[5];
         c->last_relres = keep_r[0];
         c->max_relres = keep_r[1];
+        c->step_ms = keep_r[2];
         if (rc) {
             c->ftpb = t0;
             (void)imexhdg_set_launch_geometry(c, f0, c->egrid);
@@ -1977,6 +2066,12 @@ int imexhdg_ens_set_state(imexhdg_ens *e, int32_t m, int vars, const double *a,
                           const double *b, const double *c) {
     if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
     return set_member_state(e->c, m, vars, a, b, c);
+}
+
+int imexhdg_ens_set_state_device(imexhdg_ens *e, int32_t m, int vars, int dtype,
+                                 const void *d_state) {
+    if (!e) return fail(IMEXHDG_E_INVAL, "ens is NULL");
+    return set_member_state_device(e->c, m, vars, dtype, d_state);
 }
 
 int imexhdg_ens_get_state(imexhdg_ens *e, int32_t m, int vars, double *a, double *b,

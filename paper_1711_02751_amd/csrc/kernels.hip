@@ -1950,11 +1950,18 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
-    // the member's fields and the flag in one round trip
-    const int conv = ks->conv;
+    // the member's fields and the flags in one round trip
+    const int conv = ks->conv, brk = ks->breakdown;
     arg_now(mb.to);
     arg_now(mb.bf);
     if (conv) return;
+    // a breakdown in the last K1f (which completed its iteration) ends the
+    // solve here: the flag was written by an earlier launch, so every block
+    // of this one decides alike
+    if (brk) {
+        if (lb == 0 && threadIdx.x == 0) ks->conv = 1;
+        return;
+    }
     const double tol2 = ks->tol2;
     // issue order: the partial sums, the A operands, the first tile; the
     // partial sums are reduced while the rest is in flight
@@ -2061,7 +2068,10 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
 //   faces (r', p' and v' into the other buffer of each pair: neighbouring
 //   blocks still read r, p and v);  partials P1 = (rh.v', rh.r', r'.r').
 // On breakdown (omega or rho' zero or not finite) the d and r updates still
-// complete the iteration, and the solve stops.
+// complete the iteration in every block, and the solve stops at the next K2:
+// this launch only flags it (a flag read at entry and written in the same
+// launch would let a block that starts after block 0 has finished skip its
+// updates).
 template <int K, typename T, bool SCHED>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const Batch bt, const T *__restrict__ rin, const T *__restrict__ t,
@@ -2075,8 +2085,8 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const int mi = member_of<CF>(bt, blockIdx.x, lb);
     const Member mb = load_member(bt, mi);
     KrylovState *ks = ks_all + mi;
-    // the member's fields and the flag in one round trip
-    const int conv = ks->conv;
+    // the member's fields and the flags in one round trip
+    const int conv = ks->conv, fbrk = ks->force_brk;
     arg_now(mb.to);
     arg_now(mb.bf);
     if (conv) return;
@@ -2112,7 +2122,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const double omega = tt > 0.0 ? ts / tt : 0.0;
     const double rho_new = (rho - alpha * rvv) - omega * rht;
     const bool brk = !(omega != 0.0) || !isfinite(omega) || !(rho_new != 0.0) ||
-                     !isfinite(rho_new);
+                     !isfinite(rho_new) || fbrk != 0;
     const double beta = brk ? 0.0 : (rho_new / rho) * (alpha / omega);
     const T be = (T)beta, om = (T)omega, al = (T)alpha;
     __shared__ T sB[TileLds<K, T>::n];
@@ -2227,10 +2237,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     if (lb == 0 && threadIdx.x == 0) {
         ks->omega = omega;
         ks->iters += 1;
-        if (brk) {
-            ks->breakdown = 1;
-            ks->conv = 1;
-        }
+        if (brk) ks->breakdown = 1;
     }
 }
 
@@ -2306,6 +2313,33 @@ __global__ __launch_bounds__(64 * K) void k_diag(const double *__restrict__ q, c
         }
     }
     store_partials<5>(acc, partials, stride);
+}
+
+// State in from a caller's device array (see launch_state_in).  Each thread
+// reads consecutive host-ordered values (coalesced) and scatters them to the
+// element-fastest device layout; the checks are those of the host path.
+template <typename T>
+__global__ void k_state_in(const T *__restrict__ src, int depth, double g, double H,
+                           double phiB, int nel, int KK, double *__restrict__ dst,
+                           double *partials, int stride) {
+    const size_t nn = (size_t)nel * KK;
+    double bad[1] = {0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double a = (double)src[i], b = (double)src[nn + i], c = (double)src[2 * nn + i];
+        const double p = depth ? g * (a - H) : a;
+        const double U = depth ? g * b : b;
+        const double V = depth ? g * c : c;
+        const double phi = p + phiB;
+        const bool ok = isfinite(p) && isfinite(U) && isfinite(V) && phi > 0.0 &&
+                        U * U + V * V < phi * phi * phi;
+        if (!ok) bad[0] += 1.0;
+        const size_t e = i / KK, n = i - e * KK, o = n * nel + e;
+        dst[o] = p;
+        dst[nn + o] = U;
+        dst[2 * nn + o] = V;
+    }
+    store_partials<1>(bad, partials, stride);
 }
 
 inline unsigned grid1(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
@@ -2563,6 +2597,24 @@ IMEXHDG_KRYLOV_LAUNCHERS(float)
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
                        int stride, hipStream_t s) {
     return dispatch<RunDiag>(g.K, g, b, q, partials, stride, s);
+}
+
+int state_in_blocks(int nel, int K, int cap) {
+    return (int)std::max<unsigned>(1u, std::min<unsigned>(grid1((size_t)nel * K * K, 256),
+                                                          (unsigned)cap));
+}
+
+hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, double H,
+                           int nel, int K, double *dst, double *partials, int blocks,
+                           hipStream_t s) {
+    const double phiB = g * H;
+    if (f32)
+        KLAUNCH(k_state_in<float>, dim3(blocks), dim3(256), 0, s, (const float *)src,
+                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks);
+    else
+        KLAUNCH(k_state_in<double>, dim3(blocks), dim3(256), 0, s, (const double *)src,
+                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks);
+    return hipGetLastError();
 }
 
 }  // namespace imexhdg

@@ -73,7 +73,9 @@ struct KrylovState {
     double rv;                  // rh.v of the last K2
     double rr;                  // last ||r||^2 seen by K1 or K2
     double tol2;                // stop when ||r||^2 <= tol2
-    int32_t conv, breakdown, iters, pad;
+    int32_t conv, breakdown, iters;
+    int32_t force_brk;          // debug: the next K1f takes its breakdown branch (set by the
+                                // host between launches, never written by a kernel)
     // device-driven refinement of one stage solve (fixed launch schedule)
     double relres;              // FP64 true relative residual at the last check
     int32_t stage_done;         // refine_rtol reached: later launches are no-ops
@@ -186,5 +188,17 @@ IMEXHDG_REFINE_DECLS(float)
 // partials [5][diag blocks]: mass of phi_eta, U, V; energy; non-finite count
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
                        int stride, hipStream_t s);
+
+// One member's state from a caller's device array `src` (3 nel K^2 values,
+// FP64 or, with f32, FP32; variable-major, each variable in the host state
+// ordering [e][j K + i]) into the volume device layout at dst, converting
+// depth variables (h, hu, hv) to (phi_eta, U, V) when `depth` is set.
+// partials [1][blocks]: per block, the count of nodes that are not finite,
+// not of positive depth or supercritical (|u| >= sqrt(phi)).
+hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, double H,
+                           int nel, int K, double *dst, double *partials, int blocks,
+                           hipStream_t s);
+// Blocks launch_state_in uses for nel elements of degree K - 1 (at most cap).
+int state_in_blocks(int nel, int K, int cap);
 
 }  // namespace imexhdg

@@ -21,11 +21,14 @@ PREC_FP64, PREC_MIXED = 0, 1
 LAUNCH_GRAPH, LAUNCH_HOST = 0, 1
 GUESS_EXTRAPOLATE, GUESS_LAST = 0, 1
 VARS_DEPTH, VARS_GEOPOTENTIAL = 0, 1
+DTYPE_F64, DTYPE_F32 = 0, 1
+PHASES = ["explicit", "condense", "trace", "recover", "other"]
 
 EXPORTS = [
     "imexhdg_config_init", "imexhdg_validate", "imexhdg_workspace_bytes",
     "imexhdg_create", "imexhdg_destroy", "imexhdg_sizes", "imexhdg_get_nodes",
-    "imexhdg_set_state", "imexhdg_get_state", "imexhdg_step", "imexhdg_get_diag",
+    "imexhdg_set_state", "imexhdg_set_state_device", "imexhdg_get_state", "imexhdg_step",
+    "imexhdg_get_diag",
     "imexhdg_last_error", "imexhdg_state_device", "imexhdg_nl_residual",
     "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_profile",
     "imexhdg_profile_read", "imexhdg_profile_read_min", "imexhdg_kernel_name",
@@ -33,7 +36,8 @@ EXPORTS = [
     "imexhdg_set_schedule", "imexhdg_set_launch_geometry", "imexhdg_autotune",
     "imexhdg_ens_workspace_bytes", "imexhdg_ens_create", "imexhdg_ens_destroy",
     "imexhdg_ens_members", "imexhdg_ens_sizes", "imexhdg_ens_get_nodes",
-    "imexhdg_ens_set_state", "imexhdg_ens_get_state", "imexhdg_ens_step",
+    "imexhdg_ens_set_state", "imexhdg_ens_set_state_device", "imexhdg_ens_get_state",
+    "imexhdg_ens_step",
     "imexhdg_ens_get_diag", "imexhdg_ens_get_schedule", "imexhdg_ens_set_launch_geometry",
     "imexhdg_ens_autotune",
 ]
@@ -65,7 +69,28 @@ class Diag(ctypes.Structure):
         ("last_relres", ctypes.c_double), ("max_relres", ctypes.c_double),
         ("nonfinite", ctypes.c_int32),
         ("graph_steps", ctypes.c_int64), ("redo_steps", ctypes.c_int64),
+        ("step_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 5),
     ]
+
+
+def _diag_dict(d):
+    out = {f: (list(getattr(d, f)) if f in ("mass", "phase_ms") else getattr(d, f))
+           for f, _ in Diag._fields_}
+    out["phase_ms"] = dict(zip(PHASES, out["phase_ms"]))
+    return out
+
+
+def _device_state(t, n_nodes, device):
+    """(pointer, dtype code) of a contiguous (3, n_nodes) FP64 / FP32 tensor
+    on the context's device; the tensor must stay alive for the call."""
+    want = device.index if device.index is not None else torch.cuda.current_device()
+    if not isinstance(t, torch.Tensor) or t.device.type != device.type or t.device.index != want:
+        raise ValueError("device state must be a tensor on the context's device")
+    if t.dtype not in (torch.float64, torch.float32):
+        raise ValueError("device state must be float64 or float32")
+    if not t.is_contiguous() or t.numel() != 3 * n_nodes:
+        raise ValueError("device state must be a contiguous (3, n_nodes) tensor")
+    return ctypes.c_void_p(t.data_ptr()), (DTYPE_F64 if t.dtype == torch.float64 else DTYPE_F32)
 
 
 class ImexError(RuntimeError):
@@ -99,6 +124,7 @@ def load():
         "imexhdg_get_nodes": (ctypes.c_int, [P, P, P]),
         "imexhdg_set_state": (ctypes.c_int, [P, ctypes.c_int, P, P, P]),
         "imexhdg_get_state": (ctypes.c_int, [P, ctypes.c_int, P, P, P]),
+        "imexhdg_set_state_device": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P]),
         "imexhdg_step": (ctypes.c_int, [P, i32]),
         "imexhdg_get_diag": (ctypes.c_int, [P, ctypes.POINTER(Diag)]),
         "imexhdg_last_error": (ctypes.c_char_p, []),
@@ -123,6 +149,7 @@ def load():
         "imexhdg_ens_get_nodes": (ctypes.c_int, [P, i32, P, P]),
         "imexhdg_ens_set_state": (ctypes.c_int, [P, i32, ctypes.c_int, P, P, P]),
         "imexhdg_ens_get_state": (ctypes.c_int, [P, i32, ctypes.c_int, P, P, P]),
+        "imexhdg_ens_set_state_device": (ctypes.c_int, [P, i32, ctypes.c_int, ctypes.c_int, P]),
         "imexhdg_ens_step": (ctypes.c_int, [P, i32]),
         "imexhdg_ens_get_diag": (ctypes.c_int, [P, i32, ctypes.POINTER(Diag)]),
         "imexhdg_ens_get_schedule": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -221,6 +248,12 @@ class Solver:
                 raise ValueError("state arrays must hold n_nodes values")
         _check(self.lib.imexhdg_set_state(self._ctx, vars, *[_ptr(v) for v in arrs]))
 
+    def set_state_device(self, t, vars=VARS_DEPTH):
+        """State from a device tensor of shape (3, n_nodes) (host state
+        ordering per variable), float64 or float32, without a host copy."""
+        p, dt = _device_state(t, self.n_nodes, self.device)
+        _check(self.lib.imexhdg_set_state_device(self._ctx, vars, dt, p))
+
     def get_state(self, vars=VARS_DEPTH):
         out = [np.empty(self.n_nodes) for _ in range(3)]
         _check(self.lib.imexhdg_get_state(self._ctx, vars, *[_ptr(v) for v in out]))
@@ -233,8 +266,7 @@ class Solver:
     def diag(self):
         d = Diag()
         _check(self.lib.imexhdg_get_diag(self._ctx, ctypes.byref(d)))
-        return {f: (list(getattr(d, f)) if f == "mass" else getattr(d, f))
-                for f, _ in Diag._fields_}
+        return _diag_dict(d)
 
     # ---- event profiler
     def profile(self, kernel=-1):
@@ -311,7 +343,6 @@ class Solver:
                allow=(E_NOCONV,) if allow_noconv else ())
         return Q, qh, it.value, rr.value
 
-
 # ---- layout helpers (host numpy <-> device layout of the C ABI)
 def volume_to_device_layout(q, nel, K):
     """q: (3, n_nodes) in host ordering [e][j*K+i] -> flat [c][node][e]."""
@@ -376,6 +407,10 @@ class Ensemble:
                 raise ValueError("state arrays must hold the member's n_nodes values")
         _check(self.lib.imexhdg_ens_set_state(self._ens, m, vars, *[_ptr(v) for v in arrs]))
 
+    def set_state_device(self, m, t, vars=VARS_DEPTH):
+        p, dt = _device_state(t, self.n_nodes[m], self.device)
+        _check(self.lib.imexhdg_ens_set_state_device(self._ens, m, vars, dt, p))
+
     def get_state(self, m, vars=VARS_DEPTH):
         out = [np.empty(self.n_nodes[m]) for _ in range(3)]
         _check(self.lib.imexhdg_ens_get_state(self._ens, m, vars, *[_ptr(v) for v in out]))
@@ -388,8 +423,7 @@ class Ensemble:
     def diag(self, m):
         d = Diag()
         _check(self.lib.imexhdg_ens_get_diag(self._ens, m, ctypes.byref(d)))
-        return {f: (list(getattr(d, f)) if f == "mass" else getattr(d, f))
-                for f, _ in Diag._fields_}
+        return _diag_dict(d)
 
     def schedule(self):
         n = ctypes.c_int32()

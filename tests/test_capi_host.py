@@ -73,5 +73,9 @@ def test_null_arguments_rejected():
     assert lib.imexhdg_ens_create(None, 0, None, None, 0, None) == m.E_INVAL
     assert lib.imexhdg_ens_step(None, 1) == m.E_INVAL
     assert lib.imexhdg_ens_autotune(None, None, None, None) == m.E_INVAL
+    assert lib.imexhdg_set_state_device(None, m.VARS_DEPTH, m.DTYPE_F64, None) == m.E_INVAL
+    assert lib.imexhdg_ens_set_state_device(None, 0, m.VARS_DEPTH, m.DTYPE_F64, None) == m.E_INVAL
+    d = m.Diag()
+    assert lib.imexhdg_get_diag(None, ctypes.byref(d)) == m.E_INVAL
     lib.imexhdg_ens_destroy(None)
     lib.imexhdg_destroy(None)

@@ -1,0 +1,163 @@
+"""C-ABI calls around the step: device-side state input, per-phase times,
+and the Krylov breakdown branch.
+
+  * imexhdg_set_state_device from a torch tensor (FP64 and FP32, both
+    variable sets) gives the bits that imexhdg_set_state gives from host
+    arrays, rejects what set_state rejects and then leaves the state as it
+    was; the ensemble variant sets one member;
+  * the per-phase device times of imexhdg_diag add up to the event
+    profiler's per-class totals;
+  * a BiCGStab breakdown forced in a K1f launch (debug knob
+    IMEXHDG_DEBUG_BREAKDOWN_AT) completes that iteration in every block, so
+    the solve is bitwise repeatable and the refinement still reaches the
+    oracle's stage solution.
+"""
+import numpy as np
+import pytest
+
+from oracle import swe
+from paper_1711_02751_amd import imexhdg as m
+from gpu_helpers import make_pair, bump_state, to_dev, from_dev, traces_from_dev, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _pair(nx=10, ny=7, k=3, **kw):
+    return make_pair(nx, ny, k, 9.81, 1.0, 0.006, **kw)
+
+
+def _host_vars(P, q, vars):
+    """(3, n_nodes) host-ordered arrays of q in the requested variables."""
+    a = q.reshape(3, -1)
+    if vars == m.VARS_GEOPOTENTIAL:
+        return a.copy()
+    return np.stack([P.H + a[0] / P.g, a[1] / P.g, a[2] / P.g])
+
+
+@pytest.mark.parametrize("vars", [m.VARS_GEOPOTENTIAL, m.VARS_DEPTH])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_set_state_device_equals_host(vars, dtype):
+    print(f"set_state_device vars={vars} dtype={dtype}", flush=True)
+    P, A = _pair()
+    _, B = _pair()
+    q0 = bump_state(P, seed=3, umax=0.2)
+    host = _host_vars(P, q0, vars)
+    if dtype == torch.float32:
+        host = host.astype(np.float32).astype(np.float64)   # what the device reads
+    A.set_state(*host, vars=vars)
+    B.set_state_device(torch.from_numpy(host).to(dtype).to(B.device).contiguous(), vars=vars)
+    a0 = np.stack(A.get_state(vars=m.VARS_GEOPOTENTIAL))
+    b0 = np.stack(B.get_state(vars=m.VARS_GEOPOTENTIAL))
+    assert np.array_equal(a0, b0)
+    A.step(4)
+    B.step(4)
+    assert np.array_equal(np.stack(A.get_state()), np.stack(B.get_state()))
+    assert A.diag()["steps"] == B.diag()["steps"] == 4
+
+
+def test_set_state_device_rejects_and_keeps_state():
+    P, S = _pair()
+    q0 = bump_state(P, seed=4, umax=0.2)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    keep = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
+    good = torch.from_numpy(_host_vars(P, q0, m.VARS_DEPTH)).to(S.device)
+    bads = []
+    t = good.clone()
+    t[0, 5] = float("nan")
+    bads.append(t)
+    t = good.clone()
+    t[0, 17] = -0.5                     # h <= 0
+    bads.append(t)
+    t = good.clone()
+    t[1, 3] = 10.0                      # |u| = 10 / h >> sqrt(g h)
+    bads.append(t)
+    for t in bads:
+        with pytest.raises(m.ImexError) as ei:
+            S.set_state_device(t, vars=m.VARS_DEPTH)
+        assert ei.value.code == m.E_INVAL
+        assert np.array_equal(np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)), keep)
+    lib = m.load()
+    rc = lib.imexhdg_set_state_device(S._ctx, m.VARS_DEPTH, 7, m._ptr(good))
+    assert rc == m.E_INVAL
+    rc = lib.imexhdg_set_state_device(S._ctx, 5, m.DTYPE_F64, m._ptr(good))
+    assert rc == m.E_INVAL
+    assert lib.imexhdg_set_state_device(S._ctx, m.VARS_DEPTH, m.DTYPE_F64, None) == m.E_INVAL
+    with pytest.raises(ValueError):
+        S.set_state_device(good[:, :-1].contiguous(), vars=m.VARS_DEPTH)
+    S.set_state_device(good, vars=m.VARS_DEPTH)
+    assert np.array_equal(np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)), keep)
+
+
+def test_ensemble_set_state_device():
+    cfgs = [m.default_config(nx=n, ny=n, degree=3, g=9.81, H=1.0, dt=0.006 * 12 / n)
+            for n in (12, 9)]
+    E = m.Ensemble(cfgs)
+    F = m.Ensemble(cfgs)
+    for i, n in enumerate((12, 9)):
+        P, _ = _pair(n, n, 3)
+        q = bump_state(P, seed=10 + i, umax=0.2).reshape(3, -1)
+        E.set_state(i, *q, vars=m.VARS_GEOPOTENTIAL)
+        F.set_state_device(i, torch.from_numpy(q.copy()).to(F.device),
+                           vars=m.VARS_GEOPOTENTIAL)
+    E.step(3)
+    F.step(3)
+    for i in range(2):
+        assert np.array_equal(np.stack(E.get_state(i)), np.stack(F.get_state(i)))
+
+
+def test_diag_phase_times_match_profiler():
+    P, S = _pair(16, 8, 4)
+    S.set_state(*bump_state(P, seed=5, umax=0.2).reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    S.step(2)
+    d = S.diag()
+    assert d["step_ms"] > 0.0
+    assert all(v == 0.0 for v in d["phase_ms"].values())
+    S.profile(-1)
+    S.step(2)
+    d = S.diag()
+    ph = d["phase_ms"]
+    print("phase ms", ph, "step ms", d["step_ms"], flush=True)
+    for name in ("explicit", "condense", "trace", "recover"):
+        assert ph[name] > 0.0, name
+    total = sum(S.profile_read(k)[1] for k in m.KERNELS)
+    assert abs(sum(ph.values()) - total) <= 1e-9 * max(total, 1.0)
+    assert ph["trace"] >= S.profile_read("bicg_k1f")[1]
+    S.profile(-2)
+    assert all(v == 0.0 for v in S.diag()["phase_ms"].values())
+
+
+def test_forced_breakdown_is_bitwise_repeatable(monkeypatch):
+    """Force the breakdown branch in the fourth K1f of every host-driven
+    inner solve: the iteration still completes in every block (the solve
+    stops at the next launch), the refinement restarts the inner solve, and
+    the stage solution is bitwise repeatable and matches the oracle."""
+    monkeypatch.setenv("IMEXHDG_DEBUG_BREAKDOWN_AT", "4")
+    nx, ny, k = 16, 8, 4
+    P, S = make_pair(nx, ny, k, 9.81, 1.0, 0.006, launch=m.LAUNCH_HOST, refine_max=40)
+    monkeypatch.delenv("IMEXHDG_DEBUG_BREAKDOWN_AT")
+    _, R = make_pair(nx, ny, k, 9.81, 1.0, 0.006, launch=m.LAUNCH_HOST, refine_max=40)
+    res0 = bump_state(P, seed=6, umax=0.2)
+    d = to_dev(res0, S)
+    Q1, qh1, it1, rr1 = S.stage_solve(d)
+    Q2, qh2, it2, rr2 = S.stage_solve(d)
+    Qr, qhr, itr, rrr = R.stage_solve(to_dev(res0, R))
+    print("iterations forced / free", it1, it2, itr, "relres", rr1, rrr, flush=True)
+    assert torch.equal(Q1, Q2) and torch.equal(qh1, qh2) and it1 == it2
+    assert it1 != itr
+    assert rr1 <= S.cfg.refine_rtol
+    Qo = P.stage_solve(res0)
+    assert rel_err(from_dev(Q1, S, P.mesh), Qo) < 1e-11
+    qx, qy = swe.hdg_trace(P.mesh, Qo, P.phi_B)
+    gx, gy = traces_from_dev(qh1, S, P.mesh)
+    assert rel_err(gx, qx) < 1e-10 and rel_err(gy, qy) < 1e-10
+    # whole steps on the host-driven path with the knob on: repeatable
+    q0 = bump_state(P, seed=7, umax=0.2)
+    outs = []
+    for _ in range(2):
+        S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+        S.step(3)
+        outs.append(np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)))
+    assert np.array_equal(outs[0], outs[1])
+    ref = P.run(q0, 3)
+    assert np.all(swe.rel_l2(P.mesh, outs[0].reshape(P.mesh.shape), ref) < 1e-11)

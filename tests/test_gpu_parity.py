@@ -108,7 +108,7 @@ def test_nonlinear_steps(nx, ny, k, scheme):
 
 
 def test_config2_short_run_live_oracle():
-    """64x64, k=4, g=9.81, dt = 5 dx_min: 10 steps against the oracle."""
+    """64x64, k=4, g=9.81, dt = 2 dx_min (the workload's step): 10 steps against the oracle."""
     wl = W.WORKLOADS["bump_64x64_k4"]
     P, S = make_pair(wl.n, wl.n, wl.k, wl.g, wl.H, wl.dt, solver="circulant")
     x, y = P.mesh.coords()
