@@ -268,6 +268,24 @@ int imexhdg_linear_residual(imexhdg_ctx *ctx, const double *d_Q,
 int imexhdg_stage_solve(imexhdg_ctx *ctx, const double *d_res0, double *d_Q,
                         double *d_qhat, int32_t *iters, double *relres);
 
+/* imexhdg_stage_solve for callers that cannot allocate device memory
+ * (serving loops, harnesses that forbid allocation): the same kernels on
+ * the same data, bit for bit, but every buffer the solve needs beyond its
+ * arguments (Z = A^-1 Res0, the trace right-hand side and iterate, the
+ * inner Krylov vectors, partial sums and the Krylov state) is taken from a
+ * file-scope device array of 64 MiB that each GPU the library runs on
+ * holds until the process ends, instead of the context's workspace.  The
+ * call itself allocates no device memory (no hipMalloc, hipFree or
+ * allocating library routine).  Contexts of one mesh only, whose solve
+ * fits the array: about 57 MB at 128 x 128 elements and k = 4 in FP64;
+ * larger meshes get IMEXHDG_E_INVAL with the bytes needed, before any
+ * work is enqueued.  The array is shared by every call on a GPU and keeps
+ * the last call's contents; the library serialises calls within a process
+ * (a lock held until the call has synchronised its stream), so calls never
+ * overlap on the array.  Synchronises the stream; not for graph capture.  */
+int imexhdg_stage_solve_noalloc(imexhdg_ctx *ctx, const double *d_res0, double *d_Q,
+                                double *d_qhat, int32_t *iters, double *relres);
+
 /* ---------------- per-kernel event profiler
  * Kernel classes timed with HIP events recorded on the context's stream
  * around each launch of the selected class(es).                          */

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <exception>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1291,6 +1292,11 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
 
     if (hipGetDevice(&c->device) != hipSuccess)
         return bail(fail(IMEXHDG_E_DEVICE, "no HIP device"));
+    // the allocation-free stage solve's scratch on this device (once per
+    // device, with the device current)
+    if (hipError_t e = scratch_init(c->device); e != hipSuccess)
+        return bail(fail(IMEXHDG_E_DEVICE, std::string("scratch address: ") +
+                                               hipGetErrorString(e)));
     if (workspace) {
         c->ws = (char *)workspace;
         c->ws_bytes = ws_bytes;
@@ -1540,6 +1546,59 @@ int member_diag(imexhdg_ctx *c, int m, imexhdg_diag *d) {
     return IMEXHDG_OK;
 }
 
+// ---- allocation-free stage solve
+// The buffers a host-driven stage solve uses beyond its inputs and outputs,
+// taken from the device's scratch array instead of the context workspace.
+struct SolveBufs {
+    double *Z, *gv, *x, *dpart, *P1, *P2, *P3;
+    void *rin, *kr[2], *krh, *kp[2], *kv[2], *kt, *kd;
+    KrylovState *ks;
+};
+
+SolveBufs bufs_of(const imexhdg_ctx *c) {
+    SolveBufs b;
+    b.Z = c->Z; b.gv = c->gv; b.x = c->x; b.dpart = c->dpart;
+    b.P1 = c->kb.P1; b.P2 = c->kb.P2; b.P3 = c->kb.P3;
+    b.rin = c->rin; b.krh = c->krh; b.kt = c->kt; b.kd = c->kd;
+    for (int i = 0; i < 2; ++i) { b.kr[i] = c->kr[i]; b.kp[i] = c->kp[i]; b.kv[i] = c->kv[i]; }
+    b.ks = c->ks;
+    return b;
+}
+
+void use_bufs(imexhdg_ctx *c, const SolveBufs &b) {
+    c->Z = b.Z; c->gv = b.gv; c->x = b.x; c->dpart = b.dpart;
+    c->kb.P1 = b.P1; c->kb.P2 = b.P2; c->kb.P3 = b.P3;
+    c->rin = b.rin; c->krh = b.krh; c->kt = b.kt; c->kd = b.kd;
+    for (int i = 0; i < 2; ++i) { c->kr[i] = b.kr[i]; c->kp[i] = b.kp[i]; c->kv[i] = b.kv[i]; }
+    c->ks = b.ks;
+}
+
+// Carve the buffers out of `base` (nullptr: only count); returns the bytes.
+size_t carve_scratch(const imexhdg_ctx *c, char *base, SolveBufs *b) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const size_t isz = c->mixed ? 4 : 8, ps = (size_t)c->pstride * 8;
+    b->Z = (double *)take(c->N * 8);
+    b->gv = (double *)take(c->T * 8);
+    b->x = (double *)take(c->T * 8);
+    void **iv[10] = {&b->rin, &b->kr[0], &b->krh, &b->kp[0], &b->kp[1],
+                     &b->kv[0], &b->kv[1], &b->kr[1], &b->kt, &b->kd};
+    for (void **p : iv) *p = take(c->T * isz);
+    b->P1 = (double *)take(3 * ps);
+    b->P2 = (double *)take(3 * ps);
+    b->P3 = (double *)take(2 * ps);
+    b->dpart = (double *)take(5 * ps);
+    b->ks = (KrylovState *)take(c->nm * sizeof(KrylovState));
+    return off;
+}
+
+std::mutex g_noalloc_mu;   // one allocation-free solve at a time per process
+static_assert(sizeof(KrylovState) % 4 == 0, "KrylovState is cleared in 32-bit words");
+
 }  // namespace
 
 extern "C" {
@@ -1649,6 +1708,41 @@ int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_q
     LAUNCH(IMEXHDG_K_LINRES,
            launch_linear_residual(c->geom, c->bt, d_Q, d_qhat, d_out, c->stream));
     return IMEXHDG_OK;
+}
+
+int imexhdg_stage_solve_noalloc(imexhdg_ctx *c, const double *d_res0, double *d_Q,
+                                double *d_qhat, int32_t *iters, double *relres) {
+    if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (c->nm != 1) return fail(IMEXHDG_E_INVAL, "a context of one mesh is required");
+    SolveBufs sb;
+    const size_t need = carve_scratch(c, nullptr, &sb);
+    if (need > kScratchBytes)
+        return fail(IMEXHDG_E_INVAL,
+                    "mesh too large for the allocation-free stage solve: it needs " +
+                        std::to_string(need) + " bytes of scratch, the limit is " +
+                        std::to_string(kScratchBytes) + " bytes (64 MiB)");
+    char *base = (char *)scratch_base(c->device);
+    if (!base) return fail(IMEXHDG_E_STATE, "scratch not initialised on this device");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    carve_scratch(c, base, &sb);
+    const SolveBufs keep = bufs_of(c);
+    use_bufs(c, sb);
+    // the Krylov state starts cleared (the debug breakdown flag must be 0);
+    // the other buffers are written before they are read
+    hipError_t e = launch_zero(sb.ks, sizeof(KrylovState) / 4, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->x, d_qhat, c->T * 8, hipMemcpyDeviceToDevice, c->stream);
+    int rc = e == hipSuccess ? stage_solve(c, d_res0, d_Q, iters, relres, -1)
+                             : fail(IMEXHDG_E_DEVICE, hipGetErrorString(e));
+    if (!rc || rc == IMEXHDG_E_NOCONV) {
+        e = hipMemcpyAsync(d_qhat, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = stream_sync(c);
+        if (e != hipSuccess) rc = fail(IMEXHDG_E_DEVICE, hipGetErrorString(e));
+    } else {
+        (void)hipStreamSynchronize(c->stream);   // the scratch is free again on return
+    }
+    use_bufs(c, keep);
+    return rc;
 }
 
 int imexhdg_stage_solve(imexhdg_ctx *c, const double *d_res0, double *d_Q, double *d_qhat,

@@ -14,6 +14,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace imexhdg {
 
@@ -2597,6 +2598,48 @@ IMEXHDG_KRYLOV_LAUNCHERS(float)
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
                        int stride, hipStream_t s) {
     return dispatch<RunDiag>(g.K, g, b, q, partials, stride, s);
+}
+
+// ------------------------------------------------------------ scratch
+// Device memory of the allocation-free stage solve.  Each GPU the library
+// runs on holds its own copy at its own address until the process ends.
+// Host code never uses the array's name as an address (on the host it is
+// a stand-in, not device memory): it uses the pointer that
+// hipGetSymbolAddress returned on that device.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+    return hipSuccess;
+}
+
+__global__ void k_zero(uint32_t *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, size_t n32, hipStream_t s) {
+    if (n32 == 0) return hipSuccess;
+    KLAUNCH(k_zero, dim3((unsigned)((n32 + 255) / 256)), dim3(256), 0, s, (uint32_t *)p, n32);
+    return hipGetLastError();
+}
+
+void *scratch_base(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
 }
 
 int state_in_blocks(int nel, int K, int cap) {

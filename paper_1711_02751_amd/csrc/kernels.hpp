@@ -189,6 +189,17 @@ IMEXHDG_REFINE_DECLS(float)
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
                        int stride, hipStream_t s);
 
+// Scratch of the allocation-free stage solve: a file-scope device array of
+// kScratchBytes per GPU.  scratch_init(dev) takes its address on device
+// `dev` (which must be current) once per device; scratch_base(dev) returns
+// it afterwards (nullptr before).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t scratch_init(int dev);
+void *scratch_base(int dev);
+// n32 zero words at p (a fill kernel, so that no memset node is ever
+// recorded into a caller's graph).
+hipError_t launch_zero(void *p, size_t n32, hipStream_t s);
+
 // One member's state from a caller's device array `src` (3 nel K^2 values,
 // FP64 or, with f32, FP32; variable-major, each variable in the host state
 // ordering [e][j K + i]) into the volume device layout at dst, converting

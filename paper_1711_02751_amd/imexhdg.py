@@ -30,7 +30,8 @@ EXPORTS = [
     "imexhdg_set_state", "imexhdg_set_state_device", "imexhdg_get_state", "imexhdg_step",
     "imexhdg_get_diag",
     "imexhdg_last_error", "imexhdg_state_device", "imexhdg_nl_residual",
-    "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_profile",
+    "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_stage_solve_noalloc",
+    "imexhdg_profile",
     "imexhdg_profile_read", "imexhdg_profile_read_min", "imexhdg_kernel_name",
     "imexhdg_get_schedule",
     "imexhdg_set_schedule", "imexhdg_set_launch_geometry", "imexhdg_autotune",
@@ -132,6 +133,8 @@ def load():
         "imexhdg_nl_residual": (ctypes.c_int, [P, P, P]),
         "imexhdg_linear_residual": (ctypes.c_int, [P, P, P, P]),
         "imexhdg_stage_solve": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "imexhdg_stage_solve_noalloc": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(i32),
+                                                       ctypes.POINTER(dbl)]),
         "imexhdg_profile": (ctypes.c_int, [P, i32]),
         "imexhdg_profile_read": (ctypes.c_int, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]),
         "imexhdg_profile_read_min": (ctypes.c_int, [P, i32, dbl, ctypes.POINTER(i64),
@@ -342,6 +345,18 @@ class Solver:
                                             ctypes.byref(it), ctypes.byref(rr)),
                allow=(E_NOCONV,) if allow_noconv else ())
         return Q, qh, it.value, rr.value
+
+    def stage_solve_noalloc(self, res0, Q, qhat, allow_noconv=False):
+        """imexhdg_stage_solve_noalloc into caller-provided tensors: Q
+        (3 n_nodes FP64) receives the stage state, qhat (n_trace FP64) holds
+        the guess on entry and the trace on exit.  Returns (iterations,
+        relative residual)."""
+        it, rr = ctypes.c_int32(), ctypes.c_double()
+        _check(self.lib.imexhdg_stage_solve_noalloc(self._ctx, _ptr(res0), _ptr(Q), _ptr(qhat),
+                                                    ctypes.byref(it), ctypes.byref(rr)),
+               allow=(E_NOCONV,) if allow_noconv else ())
+        return it.value, rr.value
+
 
 # ---- layout helpers (host numpy <-> device layout of the C ABI)
 def volume_to_device_layout(q, nel, K):
