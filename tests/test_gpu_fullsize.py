@@ -195,3 +195,46 @@ def test_config5_mass_conservation(big):
     print("config5 mass drift", [d1["mass"][c] - d0["mass"][c] for c in range(3)], flush=True)
     assert abs(d1["mass"][0] - d0["mass"][0]) <= 1e-12 * scale
     assert d1["max_relres"] <= 1e-13
+
+
+def test_config5_200_steps_mixed_vs_fp64(big):
+    """The whole 1024^2, k = 6 run (200 steps) on both paths: finite, mass
+    conserved to round-off on the FP64 path (and to the refinement tolerance
+    on the mixed path), every stage solve at its tolerance, and the mixed
+    state within 1e-6 (relative L2 per variable) of the FP64 state.  The
+    FP64 path itself matches the oracle to 1e-11 on the other workloads."""
+    wl, S, q0, els = big
+    out, diags = {}, {}
+    for prec in ("fp64", "mixed"):
+        if prec == "fp64":
+            R = S
+        else:
+            cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g,
+                                   H=wl.H, dt=wl.dt, physics=m.PHYSICS_NONLINEAR,
+                                   precision=m.PREC_MIXED, krylov_rtol=1e-6, refine_rtol=1e-9,
+                                   refine_max=8)
+            R = m.Solver(cfg)
+        R.set_state(*q0, vars=m.VARS_GEOPOTENTIAL)
+        d0 = R.diag()
+        R.step(wl.steps)
+        d1 = R.diag()
+        out[prec] = np.stack(R.get_state(vars=m.VARS_GEOPOTENTIAL))
+        diags[prec] = (d0, d1)
+        print(f"config5 {prec}: {wl.steps} steps, {d1['step_ms'] / wl.steps:.2f} ms/step, "
+              f"redone {d1['redo_steps']}, max relres {d1['max_relres']:.2e}, mass drift "
+              f"{[d1['mass'][c] - d0['mass'][c] for c in range(3)]}", flush=True)
+        assert d1["nonfinite"] == 0 and d1["steps"] == wl.steps
+        if R is not S:
+            R.close()
+    scale = float(np.sum(np.abs(q0[0]))) * (wl.L / wl.n) ** 2
+    d0, d1 = diags["fp64"]
+    assert d1["max_relres"] <= 1e-13
+    assert abs(d1["mass"][0] - d0["mass"][0]) <= 1e-12 * scale
+    d0, d1 = diags["mixed"]
+    assert d1["max_relres"] <= 1e-9
+    assert abs(d1["mass"][0] - d0["mass"][0]) <= 1e-9 * scale
+    mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
+    err = swe.rel_l2(mesh, out["mixed"].reshape(mesh.shape), out["fp64"].reshape(mesh.shape))
+    print("config5 mixed vs fp64 after 200 steps, rel L2:", err, flush=True)
+    assert np.all(err < 1e-6)
+
