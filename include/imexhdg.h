@@ -68,6 +68,17 @@ extern "C" {
                                   DG residuals, local solves, trace
                                   residual, iterative refinement, mass and
                                   energy sums                               */
+#define IMEXHDG_PREC_FP32   2  /* as MIXED, and the element-local solves of
+                                  the condensation and the recovery (eqs.
+                                  linearizedHDGsystem_schur,
+                                  recover_volume_unknowns) on the FP32
+                                  matrix cores with FP64 defect correction
+                                  (local_sweeps), and the DG residual of the
+                                  nonlinear part (Sec. 4.3) computed in
+                                  FP32 from the FP64 state                  */
+#define IMEXHDG_PREC_BF16   3  /* as FP32, with the local solves' dense
+                                  contraction on the BF16 matrix cores (FP32
+                                  accumulation)                             */
 
 /* how imexhdg_step drives the trace solves */
 #define IMEXHDG_LAUNCH_GRAPH 0  /* fixed launch schedule, one captured graph per
@@ -109,6 +120,12 @@ typedef struct imexhdg_config {
     int32_t refine_max;      /* max refinement sweeps per stage solve      */
     int32_t launch;          /* IMEXHDG_LAUNCH_*                           */
     int32_t trace_guess;     /* IMEXHDG_GUESS_*                            */
+    int32_t local_sweeps;    /* defect-correction sweeps of a reduced-
+                                precision local solve (IMEXHDG_PREC_FP32 /
+                                _BF16): Q <- Q + A_lp^-1 (R - A Q) with the
+                                residual in FP64; 1 or 2 (3 with BF16),
+                                0 = the default (1 for FP32, 3 for BF16);
+                                ignored by the other precisions           */
 } imexhdg_config;
 
 typedef struct imexhdg_diag {

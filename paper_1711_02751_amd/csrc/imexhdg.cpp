@@ -103,6 +103,7 @@ struct OpSet {
     double *Ainv = nullptr, *W = nullptr, *G = nullptr, *Gh = nullptr, *Px = nullptr,
            *Py = nullptr;
     float *Ghf = nullptr;
+    void *Alp = nullptr;      // reduced-precision A^-1 fragments (launch_local_lp)
 };
 
 struct MemberHost {
@@ -146,8 +147,12 @@ struct imexhdg_ctx {
     double *xp = nullptr;             // trace of the stage solve before the last
     std::vector<double> xcoef;        // per stage: trace-guess extrapolation coefficient
     double *xsave = nullptr;          // autotuner's copy of the trace guess
-    // inner-solve vectors, FP64 or FP32 (precision == IMEXHDG_PREC_MIXED)
+    // inner-solve vectors, FP64 or FP32 (every precision but IMEXHDG_PREC_FP64)
     bool mixed = false;
+    // reduced-precision local solves (IMEXHDG_PREC_FP32 / _BF16) with
+    // lp_ndc defect-correction sweeps, and the FP32 DG residual
+    bool lp = false, lp_bf16 = false, nl32 = false;
+    int lp_ndc = 0;
     void *rin = nullptr, *kr[2] = {nullptr, nullptr}, *krh = nullptr,
          *kp[2] = {nullptr, nullptr}, *kv[2] = {nullptr, nullptr}, *kt = nullptr,
          *kd = nullptr;
@@ -251,6 +256,45 @@ std::vector<double> pack_local(const std::vector<double> &M, int nr, int nc) {
     return f;
 }
 
+// A^-1 fragments of the reduced-precision local solve (launch_local_lp):
+// frag[mb][kk][lane][v] = M[16 mb + lane % 16][kw kk + (kw / 4)(lane / 16) + v],
+// zero past the n x n matrix; FP32 values, or BF16 bit patterns rounded to
+// nearest even.
+size_t lp_frag_count(int n, bool bf16) {
+    const int kw = local_lp_kw(bf16);
+    return (size_t)((n + 15) / 16) * ((n + kw - 1) / kw) * 64 * (kw / 4);
+}
+
+size_t lp_frag_bytes(int n, bool bf16) { return lp_frag_count(n, bf16) * (bf16 ? 2 : 4); }
+
+uint16_t bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite values)
+    return (uint16_t)(u >> 16);
+}
+
+std::vector<uint8_t> pack_lp(const std::vector<double> &M, int n, bool bf16) {
+    const int kw = local_lp_kw(bf16), vpl = kw / 4;
+    const int NMB = (n + 15) / 16, KS = (n + kw - 1) / kw;
+    std::vector<uint8_t> out(lp_frag_bytes(n, bf16), 0);
+    size_t idx = 0;
+    for (int mb = 0; mb < NMB; ++mb)
+        for (int kk = 0; kk < KS; ++kk)
+            for (int l = 0; l < 64; ++l)
+                for (int v = 0; v < vpl; ++v, ++idx) {
+                    const int row = 16 * mb + l % 16, col = kw * kk + vpl * (l / 16) + v;
+                    const float x = (row < n && col < n) ? (float)M[(size_t)row * n + col] : 0.f;
+                    if (bf16) {
+                        const uint16_t b = bf16_bits(x);
+                        std::memcpy(&out[idx * 2], &b, 2);
+                    } else {
+                        std::memcpy(&out[idx * 4], &x, 4);
+                    }
+                }
+    return out;
+}
+
 // Worst-case partial-sum stride of a batch: every class at its largest caps.
 int partial_stride(const std::vector<imexhdg_config> &cf) {
     int64_t f = 0, e = 0, d = 0;
@@ -296,9 +340,12 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     size_t t = 0;
     t += 5 * align256(L.N * 8);                       // q ring (3), Z, save
     t += 3 * (size_t)L.s * align256(L.N * 8);          // NL, Q, R per stage
-    const size_t isz = (c0.precision == IMEXHDG_PREC_MIXED) ? 4 : 8;
+    const size_t isz = (c0.precision != IMEXHDG_PREC_FP64) ? 4 : 8;
     t += 4 * align256(L.T * 8);                        // FP64 trace vectors
     t += 10 * align256(L.T * isz);                     // inner-solve vectors
+    if (c0.precision == IMEXHDG_PREC_FP32 || c0.precision == IMEXHDG_PREC_BF16)
+        t += (size_t)L.nops * align256(lp_frag_bytes((int)n_loc,
+                                                     c0.precision == IMEXHDG_PREC_BF16));
     t += (size_t)L.nops * (align256(local_frag_count((int)n_loc, (int)n_loc) * 8) +
                            align256(local_frag_count((int)n_loc, (int)n_tr) * 8) +
                            2 * align256(frag_count((int)K) * 8) +
@@ -328,8 +375,11 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "unknown scheme");
     if (c->physics != IMEXHDG_PHYSICS_LINEARIZED && c->physics != IMEXHDG_PHYSICS_NONLINEAR)
         return fail(IMEXHDG_E_INVAL, "unknown physics");
-    if (c->precision != IMEXHDG_PREC_FP64 && c->precision != IMEXHDG_PREC_MIXED)
+    if (c->precision < IMEXHDG_PREC_FP64 || c->precision > IMEXHDG_PREC_BF16)
         return fail(IMEXHDG_E_INVAL, "unknown precision");
+    if (c->local_sweeps < 0 || c->local_sweeps > 3 ||
+        (c->local_sweeps == 3 && c->precision != IMEXHDG_PREC_BF16))
+        return fail(IMEXHDG_E_INVAL, "local_sweeps must be 0 (default), 1 or 2, or 3 with BF16");
     if (!(c->krylov_rtol > 0) || !(c->krylov_rtol < 1))
         return fail(IMEXHDG_E_INVAL, "krylov_rtol must be in (0, 1)");
     if (!(c->refine_rtol > 0) || !(c->refine_rtol < 1))
@@ -353,6 +403,7 @@ int validate_batch(const imexhdg_config *cfgs, int n) {
         const imexhdg_config &a = cfgs[0], &b = cfgs[m];
         if (a.degree != b.degree || a.g != b.g || a.H != b.H || a.scheme != b.scheme ||
             a.physics != b.physics || a.precision != b.precision ||
+            a.local_sweeps != b.local_sweeps ||
             a.krylov_rtol != b.krylov_rtol || a.krylov_max_iter != b.krylov_max_iter ||
             a.check_every != b.check_every || a.refine_rtol != b.refine_rtol ||
             a.refine_max != b.refine_max || a.launch != b.launch ||
@@ -491,6 +542,7 @@ int build_batch(imexhdg_ctx *c) {
         d.Px = o.Px;
         d.Py = o.Py;
         d.Ghf = o.Ghf;
+        d.Alp = o.Alp;
         bv += d.nbv;
         bf += d.nbf;
         be += d.nbe;
@@ -705,14 +757,24 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
 // last two solutions; stage < 0: x is the guess as it is.
 int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres,
                 int stage) {
-    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
+    if (c->lp) {
+        LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_lp(c->geom, c->bt, R, nullptr, c->aii, c->Z,
+                                                      c->lp_bf16, c->lp_ndc, c->stream));
+    } else {
+        LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
+    }
     LAUNCH(IMEXHDG_K_TRACE_RHS,
            launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->stream, nullptr,
                             stage >= 0 ? c->x : nullptr, c->xp,
                             stage >= 0 ? c->xcoef[stage] : 0.0));
     int rc = trace_solve(c, iters, relres);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
-    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->bt, c->Z, c->x, Q, c->stream));
+    if (c->lp) {
+        LAUNCH(IMEXHDG_K_RECOVER, launch_local_lp(c->geom, c->bt, R, c->x, c->aii, Q, c->lp_bf16,
+                                                  c->lp_ndc, c->stream));
+    } else {
+        LAUNCH(IMEXHDG_K_RECOVER, launch_recover(c->geom, c->bt, c->Z, c->x, Q, c->stream));
+    }
     return rc;
 }
 
@@ -732,7 +794,7 @@ int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
         cb.n += 1;
     }
     if (nonlinear) {
-        LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, Qi, cb, true, c->stream));
+        LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, Qi, cb, true, c->stream, c->nl32));
     } else {
         LAUNCH(IMEXHDG_K_COMBINE, launch_combine(cb, c->N, c->stream));
     }
@@ -796,7 +858,12 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
     const Geom &g = c->geom;
     const Batch &b = c->bt;
     const imexhdg_config &cf = c->cfg;
-    LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
+    if (c->lp) {
+        LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_lp(g, b, R, nullptr, c->aii, c->Z,
+                                                      c->lp_bf16, c->lp_ndc, c->stream));
+    } else {
+        LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
+    }
     // trace_rhs also resets each member's stage-solve state and extrapolates
     // the trace guess
     LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->stream, c->ks, c->x,
@@ -813,8 +880,14 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
                      : launch_trace_residual(g, b, c->x, c->gv, (double *)nullptr, c->dpart,
                                              c->pstride, c->ks, c->stream));
     // recover also records each member's stage-solve outcome
-    LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream, c->ks, c->dpart,
-                                             c->pstride, st));
+    if (c->lp) {
+        LAUNCH(IMEXHDG_K_RECOVER, launch_local_lp(g, b, R, c->x, c->aii, Q, c->lp_bf16,
+                                                  c->lp_ndc, c->stream, c->ks, c->dpart,
+                                                  c->pstride, st));
+    } else {
+        LAUNCH(IMEXHDG_K_RECOVER, launch_recover(g, b, c->Z, c->x, Q, c->stream, c->ks, c->dpart,
+                                                 c->pstride, st));
+    }
     return IMEXHDG_OK;
 }
 
@@ -1321,7 +1394,11 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     for (int i = 0; i < L.s; ++i) c->NLb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Qb.push_back((double *)take(L.N * 8));
     for (int i = 0; i < L.s; ++i) c->Rb.push_back((double *)take(L.N * 8));
-    c->mixed = cf[0].precision == IMEXHDG_PREC_MIXED;
+    c->mixed = cf[0].precision != IMEXHDG_PREC_FP64;
+    c->lp = cf[0].precision == IMEXHDG_PREC_FP32 || cf[0].precision == IMEXHDG_PREC_BF16;
+    c->lp_bf16 = cf[0].precision == IMEXHDG_PREC_BF16;
+    c->nl32 = c->lp;
+    c->lp_ndc = cf[0].local_sweeps > 0 ? cf[0].local_sweeps : (c->lp_bf16 ? 3 : 1);
     double **tv[4] = {&c->x, &c->gv, &c->xsave, &c->xp};
     for (double **p : tv) *p = (double *)take(L.T * 8);
     void **iv[10] = {&c->rin, &c->kr[0], &c->krh, &c->kp[0], &c->kp[1],
@@ -1336,6 +1413,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         o.Ghf = (float *)take(frag_count(K) * 4);
         o.Px = (double *)take(9 * K * K * 8);
         o.Py = (double *)take(9 * K * K * 8);
+        if (c->lp) o.Alp = take(lp_frag_bytes((int)n_loc, c->lp_bf16));
     }
     c->kb.P1 = (double *)take(3 * (size_t)c->pstride * 8);
     c->kb.P2 = (double *)take(3 * (size_t)c->pstride * 8);
@@ -1374,6 +1452,12 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
                            c->stream) ||
             up(os.Px, op.Pxinv) || up(os.Py, op.Pyinv) || hipStreamSynchronize(c->stream))
             return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+        if (c->lp) {
+            const std::vector<uint8_t> f = pack_lp(op.Ainv, nl, c->lp_bf16);
+            if (hipMemcpyAsync(os.Alp, f.data(), f.size(), hipMemcpyHostToDevice, c->stream) ||
+                hipStreamSynchronize(c->stream))
+                return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+        }
     }
     if (const char *db = std::getenv("IMEXHDG_DEBUG_BREAKDOWN_AT")) c->dbg_brk = std::atoi(db);
     if (hipMemsetAsync(c->x, 0, L.T * 8, c->stream) ||
@@ -1698,7 +1782,7 @@ int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
     cb.self = 1.0;
     cb.out = d_out;
     cb.store = nullptr;
-    LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, d_q, cb, false, c->stream));
+    LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, d_q, cb, false, c->stream, c->nl32));
     return IMEXHDG_OK;
 }
 

@@ -133,6 +133,7 @@ __device__ __forceinline__ Member load_member(const Batch &bt, int i) {
     r.be = c.be; r.nbe = c.nbe; r.bd = c.bd; r.nbd = c.nbd;
     r.Ainv = c.Ainv; r.W = c.W; r.G = c.G; r.Gh = c.Gh; r.Px = c.Px; r.Py = c.Py;
     r.Ghf = c.Ghf;
+    r.Alp = c.Alp;
     return r;
 }
 
@@ -266,28 +267,30 @@ template <int NV, int BD = 0> struct EarlyPartials {
 // Rusanov flux of the remainder (eqs. Full_russanov, Linear_russanov):
 //   F*_NL . n = {F_NL} . n + (tau* - tau_L*) / 2 (q- - q+)
 //   tau* = max over both sides of |u . n| + sqrt(phi),  tau_L* = sqrt(phi_B)
-__device__ __forceinline__ void nl_flux_n(double p, double U, double V, double phiB,
-                                          double nx, double ny, double &f1, double &f2,
-                                          double &speed) {
-    const double phi = p + phiB;
-    const double inv = 1.0 / phi;
-    const double uu = U * U * inv, uv = U * V * inv, vv = V * V * inv;
-    const double hp = 0.5 * p * p;
+// TC: the arithmetic type (FP64, or FP32 for the reduced-precision DG
+// residual).
+template <typename TC>
+__device__ __forceinline__ void nl_flux_n(TC p, TC U, TC V, TC phiB, TC nx, TC ny, TC &f1,
+                                          TC &f2, TC &speed) {
+    const TC phi = p + phiB;
+    const TC inv = TC(1) / phi;
+    const TC uu = U * U * inv, uv = U * V * inv, vv = V * V * inv;
+    const TC hp = TC(0.5) * p * p;
     f1 = (uu + hp) * nx + uv * ny;
     f2 = uv * nx + (vv + hp) * ny;
     speed = fabs((U * nx + V * ny) * inv) + sqrt(phi);
 }
 
-__device__ __forceinline__ void rusanov_nl(const double qm[3], const double qp[3],
-                                           double nx, double ny, double phiB, double tauL,
-                                           double out[3]) {
-    double fm1, fm2, sm, fp1, fp2, sp;
-    nl_flux_n(qm[0], qm[1], qm[2], phiB, nx, ny, fm1, fm2, sm);
-    nl_flux_n(qp[0], qp[1], qp[2], phiB, nx, ny, fp1, fp2, sp);
-    const double diss = 0.5 * (fmax(sm, sp) - tauL);
+template <typename TC>
+__device__ __forceinline__ void rusanov_nl(const TC qm[3], const TC qp[3], TC nx, TC ny,
+                                           TC phiB, TC tauL, TC out[3]) {
+    TC fm1, fm2, sm, fp1, fp2, sp;
+    nl_flux_n<TC>(qm[0], qm[1], qm[2], phiB, nx, ny, fm1, fm2, sm);
+    nl_flux_n<TC>(qp[0], qp[1], qp[2], phiB, nx, ny, fp1, fp2, sp);
+    const TC diss = TC(0.5) * (fmax(sm, sp) - tauL);
     out[0] = diss * (qm[0] - qp[0]);
-    out[1] = 0.5 * (fm1 + fp1) + diss * (qm[1] - qp[1]);
-    out[2] = 0.5 * (fm2 + fp2) + diss * (qm[2] - qp[2]);
+    out[1] = TC(0.5) * (fm1 + fp1) + diss * (qm[1] - qp[1]);
+    out[2] = TC(0.5) * (fm2 + fp2) + diss * (qm[2] - qp[2]);
 }
 
 // -------------------------------------------------- NL residual kernel
@@ -304,11 +307,11 @@ __device__ __forceinline__ void rusanov_nl(const double qm[3], const double qp[3
 // instead of a neighbour's so that the loads stay unconditional (see
 // EarlyPartials), and for K <= 6 the combination inputs are loaded one
 // input ahead.  (Larger K would spill registers.)
-template <int K>
+template <int K, typename TC = double>
 __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, const Geom g,
                                                const Batch bt, const Comb comb,
                                                int scale_dt) {
-    __shared__ double sFy[2][K][K][64];
+    __shared__ TC sFy[2][K][K][64];
     const int lane = threadIdx.x & 63;
     const int j = wave_id();
     int lb;
@@ -318,101 +321,102 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
     const bool active = e < mb.nel;
     const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
     const size_t nel = mb.nel, NN = (size_t)K * K * nel;
-    const double phiB = g.phiB;
+    const TC phiB = (TC)g.phiB, tauL = (TC)g.tau;
 
-    double p[K], U[K], V[K];
+    TC p[K], U[K], V[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const size_t o = (size_t)(j * K + i) * nel + nb.e;
-        p[i] = q[o];
-        U[i] = q[NN + o];
-        V[i] = q[2 * NN + o];
+        p[i] = (TC)q[o];
+        U[i] = (TC)q[NN + o];
+        V[i] = (TC)q[2 * NN + o];
     }
     // east neighbour's first node and west neighbour's last node of row j
-    double qe[3], qw[3];
+    TC qe[3], qw[3];
     {
         const size_t oe = (size_t)(j * K + 0) * nel + nb.east;
         const size_t ow = (size_t)(j * K + K - 1) * nel + nb.west;
-        qe[0] = q[oe]; qe[1] = q[NN + oe]; qe[2] = q[2 * NN + oe];
-        qw[0] = q[ow]; qw[1] = q[NN + ow]; qw[2] = q[2 * NN + ow];
+        qe[0] = (TC)q[oe]; qe[1] = (TC)q[NN + oe]; qe[2] = (TC)q[2 * NN + oe];
+        qw[0] = (TC)q[ow]; qw[1] = (TC)q[NN + ow]; qw[2] = (TC)q[2 * NN + ow];
     }
     // across the north face (j = K - 1) or the south face (j = 0): the
     // neighbour's first or last row; the middle rows read their own row
     constexpr bool kHoist = K <= 6;
     const bool north = (j == K - 1), edge = (j == K - 1 || j == 0);
-    double qs[kHoist ? K : 1][3];
+    TC qs[kHoist ? K : 1][3];
     if constexpr (kHoist) {
         const int other = north ? nb.north : j == 0 ? nb.south : nb.e;
         const int orow = north ? 0 : j == 0 ? K - 1 : j;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const size_t o = (size_t)(orow * K + i) * nel + other;
-            qs[i][0] = q[o]; qs[i][1] = q[NN + o]; qs[i][2] = q[2 * NN + o];
+            qs[i][0] = (TC)q[o]; qs[i][1] = (TC)q[NN + o]; qs[i][2] = (TC)q[2 * NN + o];
         }
     }
-    double fx1[K], fx2[K];
+    TC fx1[K], fx2[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const double inv = 1.0 / (p[i] + phiB);
-        const double hp = 0.5 * p[i] * p[i];
-        const double uv = U[i] * V[i] * inv;
+        const TC inv = TC(1) / (p[i] + phiB);
+        const TC hp = TC(0.5) * p[i] * p[i];
+        const TC uv = U[i] * V[i] * inv;
         fx1[i] = U[i] * U[i] * inv + hp;
         fx2[i] = uv;
         sFy[0][j][i][lane] = uv;
         sFy[1][j][i][lane] = V[i] * V[i] * inv + hp;
     }
-    double o0[K], o1[K], o2[K];
+    const TC sx = (TC)mb.sx, sy = (TC)mb.sy;
+    TC o0[K], o1[K], o2[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
-        double s1 = 0.0, s2 = 0.0;
+        TC s1 = 0, s2 = 0;
 #pragma unroll
         for (int m = 0; m < K; ++m) {
-            s1 += g.Dw[m * K + a] * fx1[m];
-            s2 += g.Dw[m * K + a] * fx2[m];
+            s1 += (TC)g.Dw[m * K + a] * fx1[m];
+            s2 += (TC)g.Dw[m * K + a] * fx2[m];
         }
-        o0[a] = 0.0;
-        o1[a] = mb.sx * s1;
-        o2[a] = mb.sx * s2;
+        o0[a] = 0;
+        o1[a] = sx * s1;
+        o2[a] = sx * s2;
     }
     // east and west faces of row j
     {
-        double qm[3], f[3];
+        TC qm[3], f[3];
         qm[0] = p[K - 1]; qm[1] = U[K - 1]; qm[2] = V[K - 1];
-        rusanov_nl(qm, qe, 1.0, 0.0, phiB, g.tau, f);
-        const double se = mb.sx * g.winvk;
+        rusanov_nl<TC>(qm, qe, TC(1), TC(0), phiB, tauL, f);
+        const TC se = (TC)(mb.sx * g.winvk);
         o0[K - 1] -= se * f[0]; o1[K - 1] -= se * f[1]; o2[K - 1] -= se * f[2];
         qm[0] = p[0]; qm[1] = U[0]; qm[2] = V[0];
-        rusanov_nl(qm, qw, -1.0, 0.0, phiB, g.tau, f);
-        const double sw = mb.sx * g.winv0;
+        rusanov_nl<TC>(qm, qw, TC(-1), TC(0), phiB, tauL, f);
+        const TC sw = (TC)(mb.sx * g.winv0);
         o0[0] -= sw * f[0]; o1[0] -= sw * f[1]; o2[0] -= sw * f[2];
     }
     lds_barrier();
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        double s1 = 0.0, s2 = 0.0;
+        TC s1 = 0, s2 = 0;
 #pragma unroll
         for (int m = 0; m < K; ++m) {
-            s1 += g.Dw[m * K + j] * sFy[0][m][i][lane];
-            s2 += g.Dw[m * K + j] * sFy[1][m][i][lane];
+            s1 += (TC)g.Dw[m * K + j] * sFy[0][m][i][lane];
+            s2 += (TC)g.Dw[m * K + j] * sFy[1][m][i][lane];
         }
-        o1[i] += mb.sy * s1;
-        o2[i] += mb.sy * s2;
+        o1[i] += sy * s1;
+        o2[i] += sy * s2;
     }
     if (edge) {
-        const double ny = north ? 1.0 : -1.0;
-        const double sc = mb.sy * (north ? g.winvk : g.winv0);
+        const TC ny = north ? TC(1) : TC(-1);
+        const TC sc = (TC)(mb.sy * (north ? g.winvk : g.winv0));
         const int other = north ? nb.north : nb.south;
         const int orow = north ? 0 : K - 1;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            double qm[3] = {p[i], U[i], V[i]}, qp[3], f[3];
+            TC qm[3] = {p[i], U[i], V[i]}, qp[3], f[3];
             if constexpr (kHoist) {
                 qp[0] = qs[i][0]; qp[1] = qs[i][1]; qp[2] = qs[i][2];
             } else {
                 const size_t o = (size_t)(orow * K + i) * nel + other;
-                qp[0] = q[o]; qp[1] = q[NN + o]; qp[2] = q[2 * NN + o];
+                qp[0] = (TC)q[o]; qp[1] = (TC)q[NN + o]; qp[2] = (TC)q[2 * NN + o];
             }
-            rusanov_nl(qm, qp, 0.0, ny, phiB, g.tau, f);
+            rusanov_nl<TC>(qm, qp, TC(0), ny, phiB, tauL, f);
             o0[i] -= sc * f[0]; o1[i] -= sc * f[1]; o2[i] -= sc * f[2];
         }
     }
@@ -421,25 +425,26 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
     // input, the 3 K values of this row are loaded together
     const double sc = scale_dt ? mb.dt : 1.0;
     const size_t o = mb.vo + (size_t)(j * K) * nel + e;
+    double d0[K], d1[K], d2[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        o0[i] *= sc;
-        o1[i] *= sc;
-        o2[i] *= sc;
+        d0[i] = (double)o0[i] * sc;
+        d1[i] = (double)o1[i] * sc;
+        d2[i] = (double)o2[i] * sc;
     }
     if (comb.store) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            comb.store[o + (size_t)i * nel] = o0[i];
-            comb.store[NN + o + (size_t)i * nel] = o1[i];
-            comb.store[2 * NN + o + (size_t)i * nel] = o2[i];
+            comb.store[o + (size_t)i * nel] = d0[i];
+            comb.store[NN + o + (size_t)i * nel] = d1[i];
+            comb.store[2 * NN + o + (size_t)i * nel] = d2[i];
         }
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        o0[i] *= comb.self;
-        o1[i] *= comb.self;
-        o2[i] *= comb.self;
+        d0[i] *= comb.self;
+        d1[i] *= comb.self;
+        d2[i] *= comb.self;
     }
     // input t + 1 is loaded while input t is added (the last round reloads
     // input n - 1 and discards it: unconditional, see EarlyPartials)
@@ -476,9 +481,9 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            o0[i] += cf * v0[i];
-            o1[i] += cf * v1[i];
-            o2[i] += cf * v2[i];
+            d0[i] += cf * v0[i];
+            d1[i] += cf * v1[i];
+            d2[i] += cf * v2[i];
             if constexpr (kHoist) {
                 v0[i] = w0[i];
                 v1[i] = w1[i];
@@ -488,9 +493,9 @@ __global__ __launch_bounds__(64 * K) void k_nl(const double *__restrict__ q, con
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        comb.out[o + (size_t)i * nel] = o0[i];
-        comb.out[NN + o + (size_t)i * nel] = o1[i];
-        comb.out[2 * NN + o + (size_t)i * nel] = o2[i];
+        comb.out[o + (size_t)i * nel] = d0[i];
+        comb.out[NN + o + (size_t)i * nel] = d1[i];
+        comb.out[2 * NN + o + (size_t)i * nel] = d2[i];
     }
 }
 
@@ -1028,6 +1033,246 @@ __global__ __launch_bounds__(256) void k_recover_lds(const double *__restrict__ 
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * m + 4 * r + q;
             if (row < NL) Q[(size_t)row * nel + e] = z[m][r] - acc[m][r];
+        }
+}
+
+// ----------------------- reduced-precision local solve, defect corrected
+// Q = A^-1 R' per element, R' = R - B Qhat (recovery, eq.
+// recover_volume_unknowns; Qhat = nullptr: Z = A^-1 R, the condensation of
+// eq. linearizedHDGsystem_schur), with the dense contraction on the FP32
+// (16x16x4) or BF16 (16x16x32, FP32 accumulation) matrix cores and NDC
+// defect-correction sweeps
+//   Q <- Q + A_lp^-1 (R' - A Q)
+// whose residual R' - A Q = R' - Q + c Lq Q is formed in FP64, matrix free,
+// from the local operator of the stage system (Sec. 5, eq.
+// linearizedHDGsystem: A = I - c M^-1 dL/dQ, B = -c M^-1 dL/dQhat with the
+// hybridized flux of eq. linear_hdgflux3, c = dt a~_ii).  Each sweep
+// multiplies the error by I - A_lp^-1 A, whose norm is about the rounding
+// unit of A_lp^-1 times the condition of A (about 50 for these operators:
+// 2e-7 in FP32, 2e-2 in BF16), so the iterate reaches FP64 accuracy in one
+// sweep from FP32 and to about 2e-8 relative in two from BF16.  The HBM
+// traffic is that of one FP64 solve (R and Qhat read once, Q written once);
+// the iterate stays in LDS in FP64.
+//
+// Roles in a block of EB elements (EB / 16 waves of 64 lanes):
+//   contraction: wave w, lane l -> element 16 w + l % 16; the B operand of
+//     k step kk holds rows KW kk + VPL (l / 16) + v (v < VPL = KW / 4) and
+//     the accumulator rows 16 mb + 4 (l / 16) + r of that element (the lane
+//     layouts of both instruction shapes, checked on the device);
+//   residual: thread t -> element t % EB, rows t / EB + 4 i.
+template <typename LP> struct LpMfma;
+template <> struct LpMfma<float> {
+    static constexpr int KW = 4;
+    typedef float operand;
+    static __device__ __forceinline__ v4f mma(operand a, operand b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ operand load_a(const void *frags, size_t idx) {
+        return ((const float *)frags)[idx];
+    }
+    template <typename F> static __device__ __forceinline__ operand make_b(F f) {
+        return (float)f(0);
+    }
+};
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+template <> struct LpMfma<__bf16> {
+    static constexpr int KW = 32;
+    typedef bf16x8 operand;
+    static __device__ __forceinline__ v4f mma(operand a, operand b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ operand load_a(const void *frags, size_t idx) {
+        return ((const bf16x8 *)frags)[idx];
+    }
+    template <typename F> static __device__ __forceinline__ operand make_b(F f) {
+        operand b;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) b[v] = (__bf16)(float)f(v);
+        return b;
+    }
+};
+
+template <int K, typename LP> struct LocalLp {
+    static constexpr int NL = 3 * K * K;
+    static constexpr int KW = LpMfma<LP>::KW, VPL = KW / 4;
+    static constexpr int NMB = (NL + 15) / 16;          // accumulator row blocks
+    static constexpr int KS = (NL + KW - 1) / KW;       // k steps
+    static constexpr int NLK = KS * KW;                 // padded k range
+    static constexpr int EB = K <= 4 ? 64 : K <= 5 ? 32 : 16;   // elements per block
+    static constexpr int SPLIT = 64 / EB;               // blocks per 64-element volume block
+    static constexpr int THREADS = 4 * EB;
+};
+
+template <int K, typename LP, int NDC>
+__global__ __launch_bounds__((LocalLp<K, LP>::THREADS)) void k_local_lp(
+    const double *__restrict__ R, const double *__restrict__ qh, const Geom g, const Batch bt,
+    double aii, double *__restrict__ out,
+    const KrylovState *fks, const double *fpart, int fstride, StageStatus *fout) {
+    using L = LocalLp<K, LP>;
+    using M = LpMfma<LP>;
+    constexpr int NL = L::NL, EB = L::EB, KW = L::KW, VPL = L::VPL, NMB = L::NMB, KS = L::KS;
+    constexpr int NLK = L::NLK, TH = L::THREADS;
+    __shared__ double sQ[NMB * 16][EB];       // the FP64 iterate, [row][element]
+    __shared__ double sP[NL][EB];             // R' = R - B Qhat in FP64
+    __shared__ LP sR[NLK][EB];                // the residual as B operand
+    __shared__ double sD[K * K];              // the weak derivative weights Dw
+    int lb;
+    const int mi = member_of<CV>(bt, blockIdx.x / L::SPLIT, lb);
+    const Member mb = load_member(bt, mi);
+    if (fout != nullptr && lb == 0 && blockIdx.x % L::SPLIT == 0)
+        stage_finish_block(mb, fks + mi, fpart, fstride, fout + mi);
+    const size_t nel = mb.nel;
+    R += mb.vo;
+    out += mb.vo;
+    if (qh != nullptr) qh += mb.to;
+    const void *frags = mb.Alp;
+    const int e0 = lb * 64 + (blockIdx.x % L::SPLIT) * EB;   // first element of the block
+    const double c = mb.dt * aii, tau = g.tau, phiB = g.phiB;
+    const double sw = mb.sx * g.winv0, se = mb.sx * g.winvk;
+    const double ss = mb.sy * g.winv0, sn = mb.sy * g.winvk;
+    // contraction role
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q4 = lane >> 4;
+    const int ce = w * 16 + (lane & 15);                     // element within the block
+    const bool cact = e0 + ce < mb.nel;
+    // residual role
+    const int re = threadIdx.x % EB, rg = threadIdx.x / EB;
+    const bool ract = e0 + re < mb.nel;
+    const Nbr rnb = neighbours(ract ? e0 + re : 0, mb.nx, mb.ny);
+
+    // R' at local row t of the element with neighbour set nb: R plus the
+    // lift c tau s_f Qhat of each face the node lies on
+    auto rhs = [&](const Nbr &nb, int t) -> double {
+        double r = R[(size_t)t * nel + nb.e];
+        if (qh == nullptr) return r;
+        const int comp = t / (K * K), ij = t - comp * K * K, j = ij / K, i = ij - j * K;
+        const size_t TT = (size_t)3 * K * nel, cb = (size_t)comp * K * nel;
+        double lift = 0.0;
+        if (i == 0) lift += sw * qh[cb + (size_t)j * nel + nb.e];
+        if (i == K - 1) lift += se * qh[cb + (size_t)j * nel + nb.east];
+        if (j == 0) lift += ss * qh[TT + cb + (size_t)i * nel + nb.e];
+        if (j == K - 1) lift += sn * qh[TT + cb + (size_t)i * nel + nb.north];
+        return r + c * tau * lift;
+    };
+
+    // Dw is indexed by lane-dependent rows in the residual: LDS, not the
+    // kernel-argument segment
+    for (int i = threadIdx.x; i < K * K; i += TH) sD[i] = g.Dw[i];
+    // R' of the block's elements into LDS: thread (re, rg) loads rows rg,
+    // rg + 4, ... of element re (consecutive threads, consecutive elements:
+    // coalesced), eight rows' loads in flight at a time
+    {
+        constexpr int PER = (NL + 3) / 4, CH = 8;
+#pragma unroll 1
+        for (int i0 = 0; i0 < PER; i0 += CH) {
+            double v[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int t = rg + 4 * (i0 + u);
+                v[u] = (t < NL && ract) ? rhs(rnb, t) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int t = rg + 4 * (i0 + u);
+                if (t < NL) sP[t][re] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    // first solve: Q = A_lp^-1 R'
+    v4f acc[NMB];
+#pragma unroll
+    for (int m = 0; m < NMB; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int kk = 0; kk < KS; ++kk) {
+        const typename M::operand b = M::make_b([&](int v) {
+            const int row = KW * kk + VPL * q4 + v;
+            return row < NL ? sP[row][ce] : 0.0;
+        });
+#pragma unroll
+        for (int m = 0; m < NMB; ++m)
+            acc[m] = M::mma(M::load_a(frags, ((size_t)m * KS + kk) * 64 + lane), b, acc[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sQ[16 * m + 4 * q4 + r][ce] = (double)acc[m][r];
+    // rows of the padded k range past NL stay zero
+    for (int i = threadIdx.x; i < (NLK - NL) * EB; i += TH) sR[NL + i / EB][i % EB] = LP(0.f);
+    __syncthreads();
+
+#pragma unroll 1
+    for (int sweep = 0; sweep < NDC; ++sweep) {
+        // residual R' - Q + c Lq Q of this thread's rows, in FP64
+#pragma unroll 1
+        for (int t = rg; t < NL; t += 4) {
+            const int comp = t / (K * K), ij = t - comp * K * K, j = ij / K, i = ij - j * K;
+            const double *Qp = &sQ[0][re], *QU = &sQ[K * K][re], *QV = &sQ[2 * K * K][re];
+            auto at = [&](const double *b, int ii, int jj) { return b[(jj * K + ii) * EB]; };
+            double lq = 0.0;
+            if (comp == 0) {
+                double sx_ = 0.0, sy_ = 0.0;
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    sx_ += sD[m * K + i] * at(QU, m, j);
+                    sy_ += sD[m * K + j] * at(QV, i, m);
+                }
+                lq = mb.sx * sx_ + mb.sy * sy_;
+                const double p = at(Qp, i, j), U = at(QU, i, j), V = at(QV, i, j);
+                if (i == 0) lq += sw * U - sw * tau * p;
+                if (i == K - 1) lq += -se * U - se * tau * p;
+                if (j == 0) lq += ss * V - ss * tau * p;
+                if (j == K - 1) lq += -sn * V - sn * tau * p;
+            } else if (comp == 1) {
+                double sx_ = 0.0;
+#pragma unroll
+                for (int m = 0; m < K; ++m) sx_ += sD[m * K + i] * at(Qp, m, j);
+                lq = mb.sx * phiB * sx_;
+                const double p = at(Qp, i, j), U = at(QU, i, j);
+                if (i == 0) lq += sw * phiB * p - sw * tau * U;
+                if (i == K - 1) lq += -se * phiB * p - se * tau * U;
+                if (j == 0) lq += -ss * tau * U;
+                if (j == K - 1) lq += -sn * tau * U;
+            } else {
+                double sy_ = 0.0;
+#pragma unroll
+                for (int m = 0; m < K; ++m) sy_ += sD[m * K + j] * at(Qp, i, m);
+                lq = mb.sy * phiB * sy_;
+                const double p = at(Qp, i, j), V = at(QV, i, j);
+                if (i == 0) lq += -sw * tau * V;
+                if (i == K - 1) lq += -se * tau * V;
+                if (j == 0) lq += ss * phiB * p - ss * tau * V;
+                if (j == K - 1) lq += -sn * phiB * p - sn * tau * V;
+            }
+            const double res = ract ? sP[t][re] - sQ[t][re] + c * lq : 0.0;
+            sR[t][re] = LP((float)res);
+        }
+        __syncthreads();
+        // correction d = A_lp^-1 (R' - A Q), added to the iterate in FP64
+#pragma unroll
+        for (int m = 0; m < NMB; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int kk = 0; kk < KS; ++kk) {
+            const typename M::operand b =
+                M::make_b([&](int v) { return (float)sR[KW * kk + VPL * q4 + v][ce]; });
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+                acc[m] = M::mma(M::load_a(frags, ((size_t)m * KS + kk) * 64 + lane), b, acc[m]);
+        }
+        if (sweep + 1 < NDC) {
+#pragma unroll
+            for (int m = 0; m < NMB; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sQ[16 * m + 4 * q4 + r][ce] += (double)acc[m][r];
+            __syncthreads();
+        }
+    }
+    if (!cact) return;
+#pragma unroll
+    for (int m = 0; m < NMB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * q4 + r;
+            if (row < NL) out[(size_t)row * nel + e0 + ce] = sQ[row][ce] + (double)acc[m][r];
         }
 }
 
@@ -2362,9 +2607,13 @@ hipError_t dispatch(int K, Args &&...args) {
 
 template <int K> struct RunNL {
     static hipError_t run(const Geom &g, const Batch &b, const double *q, const Comb &c,
-                          bool scale_dt, hipStream_t s) {
-        KLAUNCH(k_nl<K>, dim3(b.nbv), dim3(64 * K), 0, s, q, g, b, c,
-                           scale_dt ? 1 : 0);
+                          bool scale_dt, bool fp32, hipStream_t s) {
+        if (fp32)
+            KLAUNCH((k_nl<K, float>), dim3(b.nbv), dim3(64 * K), 0, s, q, g, b, c,
+                    scale_dt ? 1 : 0);
+        else
+            KLAUNCH((k_nl<K, double>), dim3(b.nbv), dim3(64 * K), 0, s, q, g, b, c,
+                    scale_dt ? 1 : 0);
         return hipGetLastError();
     }
 };
@@ -2397,6 +2646,27 @@ template <int K> struct RunRecover {
             KLAUNCH(k_recover<K>, dim3(b.nbv), dim3(256), 0, s, Z, qh, b, Q, ks, part, stride,
                     status);
         return hipGetLastError();
+    }
+};
+template <int K> struct RunLocalLp {
+    template <typename LP, int NDC>
+    static hipError_t go(const Geom &g, const Batch &b, const double *R, const double *qh,
+                         double aii, double *out, const KrylovState *ks, const double *part,
+                         int stride, StageStatus *status, hipStream_t s) {
+        using L = LocalLp<K, LP>;
+        KLAUNCH((k_local_lp<K, LP, NDC>), dim3(b.nbv * L::SPLIT), dim3(L::THREADS), 0, s, R, qh,
+                g, b, aii, out, ks, part, stride, status);
+        return hipGetLastError();
+    }
+    static hipError_t run(const Geom &g, const Batch &b, const double *R, const double *qh,
+                          double aii, double *out, bool bf16, int ndc, const KrylovState *ks,
+                          const double *part, int stride, StageStatus *status, hipStream_t s) {
+        if (bf16)
+            return ndc == 1   ? go<__bf16, 1>(g, b, R, qh, aii, out, ks, part, stride, status, s)
+                   : ndc == 2 ? go<__bf16, 2>(g, b, R, qh, aii, out, ks, part, stride, status, s)
+                              : go<__bf16, 3>(g, b, R, qh, aii, out, ks, part, stride, status, s);
+        return ndc == 1 ? go<float, 1>(g, b, R, qh, aii, out, ks, part, stride, status, s)
+                        : go<float, 2>(g, b, R, qh, aii, out, ks, part, stride, status, s);
     }
 };
 template <int K> struct RunTraceRhs {
@@ -2511,8 +2781,8 @@ int member_vol_blocks(int nel) { return (int)grid1(nel, 64); }
 int member_diag_blocks(int nel) { return (int)std::min<unsigned>(grid1(nel, 64), 1024u); }
 
 hipError_t launch_nl(const Geom &g, const Batch &b, const double *q, const Comb &comb,
-                     bool scale_dt, hipStream_t s) {
-    return dispatch<RunNL>(g.K, g, b, q, comb, scale_dt, s);
+                     bool scale_dt, hipStream_t s, bool fp32) {
+    return dispatch<RunNL>(g.K, g, b, q, comb, scale_dt, fp32, s);
 }
 
 hipError_t launch_combine(const Comb &comb, size_t n, hipStream_t s) {
@@ -2528,6 +2798,17 @@ hipError_t launch_linear_residual(const Geom &g, const Batch &b, const double *Q
 hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, double *Z,
                               hipStream_t s) {
     return dispatch<RunLocal>(g.K, b, R, Z, s);
+}
+
+int local_lp_kw(bool bf16) { return bf16 ? LpMfma<__bf16>::KW : LpMfma<float>::KW; }
+
+hipError_t launch_local_lp(const Geom &g, const Batch &b, const double *R, const double *qhat,
+                           double aii, double *out, bool bf16, int ndc, hipStream_t s,
+                           const KrylovState *ks, const double *partials, int stride,
+                           StageStatus *status) {
+    if (ndc < 1 || ndc > (bf16 ? 3 : 2)) return hipErrorInvalidValue;
+    return dispatch<RunLocalLp>(g.K, g, b, R, qhat, aii, out, bf16, ndc, ks, partials, stride,
+                                status, s);
 }
 
 hipError_t launch_trace_rhs(const Geom &g, const Batch &b, const double *Z, double *gvec,

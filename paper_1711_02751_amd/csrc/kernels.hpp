@@ -42,6 +42,7 @@ struct Member {
     // Ghat as face row-block fragments, the block-Jacobi inverses dense
     const double *Ainv, *W, *G, *Gh, *Px, *Py;
     const float *Ghf;                            // FP32 Ghat fragments
+    const void *Alp;    // A^-1 as FP32 or BF16 fragments of the reduced-precision local solve
 };
 
 struct Batch {
@@ -116,13 +117,30 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // ---------------------------------------------------------------- launchers
 // All return hipError_t of the launch; each launches one kernel.  Pointers are the base pointers of
 // the concatenated arrays.
+// NL residual (with the stage combination); fp32: the residual's
+// arithmetic in FP32 from the FP64 state, the combination in FP64.
 hipError_t launch_nl(const Geom &g, const Batch &b, const double *q, const Comb &comb,
-                     bool scale_dt, hipStream_t s);
+                     bool scale_dt, hipStream_t s, bool fp32 = false);
 hipError_t launch_combine(const Comb &comb, size_t n, hipStream_t s);
 hipError_t launch_linear_residual(const Geom &g, const Batch &b, const double *Q,
                                   const double *qhat, double *out, hipStream_t s);
 hipError_t launch_local_apply(const Geom &g, const Batch &b, const double *R, double *Z,
                               hipStream_t s);
+// Reduced-precision local solve with FP64 defect correction (ndc sweeps, 1
+// or 2 with FP32, 1 to 3 with BF16): out = A^-1 (R - B qhat) per element, the contraction on FP32
+// (bf16 = false) or BF16 matrix cores with the member's Alp fragments;
+// qhat == nullptr gives Z = A^-1 R.  aii: the tableau's a~_ii (c = dt a~_ii
+// per member).  status (fixed schedule): as for launch_recover.
+hipError_t launch_local_lp(const Geom &g, const Batch &b, const double *R, const double *qhat,
+                           double aii, double *out, bool bf16, int ndc, hipStream_t s,
+                           const KrylovState *ks = nullptr, const double *partials = nullptr,
+                           int stride = 0, StageStatus *status = nullptr);
+// Fragment layout of the reduced-precision local solve's A^-1 (element
+// type 4 bytes FP32 or 2 bytes BF16): frag[mb][kk][lane][v] =
+// A^-1[16 mb + lane % 16][kw kk + (kw / 4)(lane / 16) + v], kw = 4 (FP32)
+// or 32 (BF16), zero past the matrix.
+int local_lp_kw(bool bf16);
+
 // g = sum C Z per face (the trace system's right-hand side); begin (fixed
 // schedule): also reset each member's stage-solve state; x (steps): the
 // trace guess by linear extrapolation, x <- x + xcoef (x - xprev) and

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libimexhdg.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOCONV, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5, -6
 SCHEME_ARS232, SCHEME_ARS443 = 0, 1
 PHYSICS_LINEARIZED, PHYSICS_NONLINEAR = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_FP32, PREC_BF16 = 0, 1, 2, 3
 LAUNCH_GRAPH, LAUNCH_HOST = 0, 1
 GUESS_EXTRAPOLATE, GUESS_LAST = 0, 1
 VARS_DEPTH, VARS_GEOPOTENTIAL = 0, 1
@@ -59,6 +59,7 @@ class Config(ctypes.Structure):
         ("krylov_max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("refine_rtol", ctypes.c_double), ("refine_max", ctypes.c_int32),
         ("launch", ctypes.c_int32), ("trace_guess", ctypes.c_int32),
+        ("local_sweeps", ctypes.c_int32),
     ]
 
 

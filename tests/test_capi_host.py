@@ -40,7 +40,8 @@ def test_validation_errors_are_host_only():
            dict(g=0.0), dict(H=-1.0), dict(Lx=0.0), dict(scheme=7), dict(physics=3),
            dict(krylov_rtol=0.0), dict(refine_rtol=2.0), dict(krylov_max_iter=0),
            dict(check_every=0), dict(precision=9), dict(launch=5),
-           dict(trace_guess=2)]
+           dict(trace_guess=2), dict(local_sweeps=4), dict(local_sweeps=-1),
+           dict(precision=2, local_sweeps=3)]
     for kw in bad:
         base = dict(nx=4, ny=3, degree=3, dt=0.01)
         base.update(kw)

@@ -87,14 +87,19 @@ def test_config3_500_steps_sampled():
     assert abs(d["energy"] - ref["energy"]) <= 1e-11 * ref["energy"]
 
 
-def test_config3_mixed_500_steps_within_bound():
-    """Mixed path (FP32 inner solve, krylov_rtol 1e-6, FP64 refinement to
-    1e-9) after the full 500 steps: within 1e-7 of the FP64 oracle at the
-    sampled nodes (the mixed bound is 1e-6)."""
+@pytest.mark.parametrize("prec,bound", [(m.PREC_MIXED, 1e-7), (m.PREC_FP32, 1e-6),
+                                        (m.PREC_BF16, 1e-6)])
+def test_config3_mixed_500_steps_within_bound(prec, bound):
+    """Reduced-precision paths after the full 500 steps, at the sampled nodes
+    against the FP64 oracle.  MIXED (FP32 inner solve, krylov_rtol 1e-6,
+    FP64 refinement to 1e-9): measured 3.2e-8, bound 1e-7.  FP32 (also the
+    FP32 DG residual and FP32-matrix-core local solves with one FP64
+    correction sweep) and BF16 (BF16-matrix-core local solves, three
+    sweeps): measured 1.0e-7 over the whole state, bound 1e-6."""
     wl = W.WORKLOADS["bump_256x256_k4"]
     ref = _ref(wl.name)
     cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
-                           dt=wl.dt, physics=m.PHYSICS_NONLINEAR, precision=m.PREC_MIXED,
+                           dt=wl.dt, physics=m.PHYSICS_NONLINEAR, precision=prec,
                            krylov_rtol=1e-6, refine_rtol=1e-9, refine_max=8)
     S = m.Solver(cfg)
     q0 = _initial(wl, S)
@@ -107,8 +112,8 @@ def test_config3_mixed_500_steps_within_bound():
     for c in range(3):
         num = np.sqrt(np.sum(mm[idx] * (got[c, idx] - val[c]) ** 2))
         den = np.sqrt(np.sum(mm[idx] * val[c] ** 2))
-        print(f"config3 mixed sampled rel L2 c={c}: {num / den:.3e}", flush=True)
-        assert num / den < 1e-7
+        print(f"config3 precision {prec} sampled rel L2 c={c}: {num / den:.3e}", flush=True)
+        assert num / den < bound
 
 
 # ---------------------------------------------------------- 1024 x 1024
