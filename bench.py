@@ -112,6 +112,30 @@ def measured_traffic(kernel_class, wl, precision="fp64"):
     return rec.get("working_hbm_bytes", rec["hbm_bytes"])
 
 
+def lgl_weights(k):
+    """Legendre-Gauss-Lobatto quadrature weights of degree k on [-1, 1]:
+    w_i = 2 / (k (k + 1) P_k(x_i)^2) at x = -1, 1 and the roots of P_k'."""
+    from numpy.polynomial import legendre as leg
+    pk = leg.Legendre.basis(k)
+    x = np.concatenate([[-1.0], np.sort(pk.deriv().roots().real), [1.0]])
+    return 2.0 / (k * (k + 1) * pk(x) ** 2)
+
+
+def rel_l2_mass(a, b, k):
+    """Per-variable ||a - b||_M / ||b||_M with the LGL mass of uniform
+    elements (the element area cancels), for states of shape (3, n_nodes)
+    in the host ordering (element-major, node j K + i within an element)."""
+    w = lgl_weights(k)
+    K = k + 1
+    wn = np.tile(np.outer(w, w).ravel(), a.shape[1] // (K * K))
+    out = []
+    for c in range(3):
+        num = np.sqrt(np.sum(wn * (a[c] - b[c]) ** 2))
+        den = np.sqrt(np.sum(wn * b[c] ** 2))
+        out.append(float(num / den) if den > 0 else float(num))
+    return out
+
+
 def cpu_model():
     """CPU model string of the host (Linux /proc/cpuinfo), or the platform's."""
     try:
@@ -184,6 +208,38 @@ def cpu_baseline(wl_name, seconds=15.0):
 TUNE_CACHE = os.path.join(ROOT, "paper_1711_02751_amd", "tuning_cache.txt")
 
 
+PRECISIONS = ("fp64", "mixed", "fp32", "bf16")
+MFMA_PEAK_TFLOPS = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
+                    "bf16": 2500.0}                # dense BF16 matrix-core peak
+
+
+def local_solve_mfma(per, wl, n_dof, precision, ndc):
+    """Matrix-core rate of the element-local solve Z = A^-1 Res0 (kernel
+    class local_apply) against the peak of the precision its contraction
+    runs in, with the cap its arithmetic intensity puts on that fraction
+    (one solve: 2 (3K^2)^2 flop per element over the FP64 state read and
+    written, 16 (3K^2) bytes, at 8 TB/s).  Reduced-precision modes run
+    1 + ndc contractions (the first solve and ndc defect-correction
+    sweeps)."""
+    rec = per.get("local_apply")
+    if not rec:
+        return None
+    K = wl.k + 1
+    nel = wl.n * wl.n
+    nl = 3 * K * K
+    gemm = 2.0 * nl * nl * nel
+    cp = {"fp64": "fp64", "mixed": "fp64", "fp32": "fp32", "bf16": "bf16"}[precision]
+    runs = 1 if cp == "fp64" else 1 + ndc
+    t = rec["avg_us"] * 1e-6
+    peak = MFMA_PEAK_TFLOPS[cp]
+    achieved = runs * gemm / t / 1e12
+    ai = gemm / (2 * n_dof * 8)
+    return {"contraction": cp, "contractions_per_launch": runs,
+            "achieved_tflops": achieved, "peak_tflops": peak, "frac": achieved / peak,
+            "roofline_cap_frac": min(1.0, ai * HBM_PEAK_GBS * 1e9 / (peak * 1e12)),
+            "avg_launch_us": rec["avg_us"]}
+
+
 def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     """Run one precision path; returns (result dict, final state).
 
@@ -196,12 +252,13 @@ def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     both modes; the graph launches carry their own symbols (a SCHED
     template tag), so a profile tells the two apart."""
     import torch
-    mixed = precision == "mixed"
+    mixed = precision != "fp64"     # FP32 inner Krylov solve
+    code = {"fp64": m.PREC_FP64, "mixed": m.PREC_MIXED, "fp32": m.PREC_FP32,
+            "bf16": m.PREC_BF16}[precision]
     cfg = m.default_config(nx=wl.n, ny=wl.n, Lx=wl.L, Ly=wl.L, degree=wl.k, g=wl.g, H=wl.H,
                            dt=wl.dt, scheme=m.SCHEME_ARS232,
                            physics=m.PHYSICS_NONLINEAR if wl.nonlinear else m.PHYSICS_LINEARIZED,
-                           precision=m.PREC_MIXED if mixed else m.PREC_FP64,
-                           launch=m.LAUNCH_GRAPH)
+                           precision=code, launch=m.LAUNCH_GRAPH)
     if mixed:
         cfg.krylov_rtol = MIXED_KRYLOV_RTOL
         cfg.refine_rtol = MIXED_REFINE_RTOL
@@ -286,7 +343,9 @@ def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     roof["algorithmic_flops_per_launch"] = nflops
     iters = ((d1["krylov_iters"] - d0["krylov_iters"])
              / max(1, d1["stage_solves"] - d0["stage_solves"]))
+    ndc = {"fp32": 1, "bf16": 3}.get(precision, 0)
     res = {"value": value, "ms_per_step": 1000.0 * el / steps, "roofline": roof,
+           "local_solve_mfma": local_solve_mfma(per, wl, n_dof, precision, ndc),
            "schedule": {"sweeps": sched[0], "inner_budget": sched[1]},
            "grid_caps": {"face": fg, "elementwise": eg},
            "graph_steps": d1["graph_steps"] - d0["graph_steps"],
@@ -301,12 +360,10 @@ def run_large(m, wl, steps, warmup, tune_cache=TUNE_CACHE):
     """The large single-mesh workload (1024^2, k = 6): both paths, each
     with its own roofline object, and the mixed-vs-FP64 error of the final
     states."""
-    from oracle import swe   # only for the mass-weighted norm of the comparison
     log(f"[bench] large workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
     f64, s64 = run_path(m, wl, "fp64", steps, warmup, tune_cache)
     mix, smx = run_path(m, wl, "mixed", steps, warmup, tune_cache)
-    mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
-    err = swe.rel_l2(mesh, smx.reshape(mesh.shape), s64.reshape(mesh.shape))
+    err = rel_l2_mass(smx, s64, wl.k)
     del s64, smx
     keep = ("value", "ms_per_step", "roofline", "krylov_iters_per_stage", "max_trace_relres",
             "schedule", "grid_caps", "graph_steps", "redone_steps", "kernels")
@@ -389,6 +446,8 @@ def main():
                     help="second workload measured beside the headline one (both paths)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-workload measurement")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the FP32 / BF16 precision modes")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB (counter calibration)")
@@ -421,7 +480,6 @@ def main():
         head, smx = fp64, None
     else:
         head, smx = run_path(m, wl, "mixed", args.steps, args.warmup, args.tune_cache)
-    from oracle import swe   # only for the mass-weighted norm of the comparison
     out = {
         "metric": METRIC,
         "value": head["value"],
@@ -450,8 +508,7 @@ def main():
         "kernels": head["kernels"],
     }
     if smx is not None:
-        mesh = swe.Mesh(wl.n, wl.n, wl.L, wl.L, wl.k)
-        err = swe.rel_l2(mesh, smx.reshape(mesh.shape), s64.reshape(mesh.shape))
+        err = rel_l2_mass(smx, s64, wl.k)
         out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                        "roofline": fp64["roofline"],
                        "launch": {k: fp64[k] for k in ("schedule", "grid_caps",
@@ -459,6 +516,26 @@ def main():
                        "krylov_iters_per_stage": fp64["krylov_iters_per_stage"]}
         out["speedup_mixed_vs_fp64"] = head["value"] / fp64["value"]
         out["mixed_rel_l2_vs_fp64"] = [float(e) for e in err]
+    if smx is not None and not args.no_modes:
+        # the precision modes with reduced-precision local solves and DG
+        # residual, beside MIXED, each with its error against the FP64 path
+        out["precision_modes"] = {}
+        for prec in ("fp32", "bf16"):
+            r, st = run_path(m, wl, prec, args.steps, args.warmup, args.tune_cache)
+            e = rel_l2_mass(st, s64, wl.k)
+            out["precision_modes"][prec] = {
+                "value": r["value"], "ms_per_step": r["ms_per_step"],
+                "rel_l2_vs_fp64": [float(x) for x in e],
+                "local_solve_mfma": r["local_solve_mfma"],
+                "speedup_vs_fp64": r["value"] / fp64["value"]}
+        out["precision_modes"]["mixed"] = {
+            "value": head["value"], "ms_per_step": head["ms_per_step"],
+            "rel_l2_vs_fp64": out["mixed_rel_l2_vs_fp64"],
+            "local_solve_mfma": head["local_solve_mfma"],
+            "speedup_vs_fp64": head["value"] / fp64["value"]}
+        out["precision_modes"]["fp64"] = {"value": fp64["value"],
+                                         "ms_per_step": fp64["ms_per_step"],
+                                         "local_solve_mfma": fp64["local_solve_mfma"]}
     if not args.no_large and args.large_workload != wl.name:
         out["large"] = run_large(m, W.WORKLOADS[args.large_workload], args.steps, args.warmup,
                                  args.tune_cache)

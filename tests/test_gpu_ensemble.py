@@ -157,6 +157,38 @@ def test_ensemble_64_members_sampled():
         assert np.all(err < 1e-12)
 
 
+def test_ensemble_64_members_mixed_vs_oracle():
+    """The 64-member configuration on the mixed path (FP32 inner solves,
+    krylov_rtol 1e-6, FP64 refinement to 1e-9) as the benchmark runs it:
+    20 steps, then the smallest, a middle and the largest member against
+    the FP64 oracle (block-circulant direct stage solve) within 1e-6."""
+    members = W.ensemble_members()
+    cfgs = [m.default_config(nx=w.n, ny=w.n, Lx=w.L, Ly=w.L, degree=w.k, g=w.g, H=w.H,
+                             dt=w.dt, launch=m.LAUNCH_GRAPH, precision=m.PREC_MIXED,
+                             krylov_rtol=1e-6, refine_rtol=1e-9, refine_max=8)
+            for w in members]
+    E = m.Ensemble(cfgs)
+    q0s = []
+    for i, w in enumerate(members):
+        x, y = E.nodes(i)
+        h, hu, hv = w.initial_state(x, y)
+        q0s.append(swe.from_user(h, hu, hv, w.g, w.H))
+        E.set_state(i, h, hu, hv)
+    steps = 20
+    E.step(steps)
+    print("mixed 64-member schedule", E.schedule(), flush=True)
+    sizes = [w.n for w in members]
+    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
+    for i in picks:
+        w = members[i]
+        P = imex.Problem(w.n, w.n, w.L, w.L, w.k, w.g, w.H, w.dt, solver="circulant")
+        ref = P.run(q0s[i].reshape(P.mesh.shape), steps)
+        got = np.stack(E.get_state(i, vars=m.VARS_GEOPOTENTIAL)).reshape(P.mesh.shape)
+        err = swe.rel_l2(P.mesh, got, ref)
+        print(f"member {i} n={w.n}: rel L2 vs oracle after {steps} steps {err}", flush=True)
+        assert np.all(err < 1e-6)
+
+
 def test_ensemble_autotune_restores_state(tmp_path):
     k = 3
     cfgs = [_cfg(nx, ny, k, m.PREC_MIXED) for nx, ny in MESHES]
