@@ -365,7 +365,8 @@ def run_large(m, wl, steps, warmup, tune_cache=TUNE_CACHE):
     mix, smx = run_path(m, wl, "mixed", steps, warmup, tune_cache)
     err = rel_l2_mass(smx, s64, wl.k)
     del s64, smx
-    keep = ("value", "ms_per_step", "roofline", "krylov_iters_per_stage", "max_trace_relres",
+    keep = ("value", "ms_per_step", "roofline", "local_solve_mfma", "krylov_iters_per_stage",
+            "max_trace_relres",
             "schedule", "grid_caps", "graph_steps", "redone_steps", "kernels")
     return {"workload": wl.name, "mesh": f"{wl.n}x{wl.n}", "degree": wl.k,
             "n_dof": mix["n_dof"], "n_trace": mix["n_trace"], "dt": wl.dt, "steps": steps,
