@@ -83,8 +83,13 @@ def kernel_symbol(kernel_class, K, mixed):
         return f"k_trace_residual<{K}, {T}>"
     if kernel_class in ("bicg_init", "axpy"):
         return f"k_{kernel_class}<{T}>"
-    base = {"nl_residual": "k_nl", "local_apply": "k_local_apply", "recover": "k_recover",
-            "trace_rhs": "k_trace_rhs", "diag": "k_diag", "linear_residual": "k_linres"}
+    if kernel_class == "nl_residual":
+        return f"k_nl<{K}, double>"
+    if kernel_class == "local_apply":
+        return f"k_local_apply_lds<{K}>" if K <= 4 else f"k_local_apply<{K}>"
+    if kernel_class == "recover":
+        return f"k_recover_lds<{K}>" if K <= 6 else f"k_recover<{K}>"
+    base = {"trace_rhs": "k_trace_rhs", "diag": "k_diag", "linear_residual": "k_linres"}
     if kernel_class in base:
         return f"{base[kernel_class]}<{K}>"
     return "k_" + kernel_class
