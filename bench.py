@@ -245,6 +245,29 @@ def local_solve_mfma(per, wl, n_dof, precision, ndc):
             "avg_launch_us": rec["avg_us"]}
 
 
+def measure_copy_bandwidth(gib=2, reps=5):
+    """Achieved HBM bandwidth of a plain device-to-device copy (torch's copy
+    kernel) of `gib` GiB, bytes read plus written per second, best of
+    `reps`: the practical ceiling of a streaming kernel beside the nominal
+    8 TB/s."""
+    import torch
+    n = gib * (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1000.0)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / best / 1e9
+
+
 def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     """Run one precision path; returns (result dict, final state).
 
@@ -480,6 +503,8 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del src, dst
+    hbm_copy = measure_copy_bandwidth()
+    log(f"[bench] device copy bandwidth (torch copy of 2 GiB): {hbm_copy:.0f} GB/s")
     log(f"[bench] workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
     fp64, s64 = run_path(m, wl, "fp64", args.steps, args.warmup, args.tune_cache)
     if args.precision == "fp64":
@@ -507,6 +532,7 @@ def main():
                    f"{MIXED_REFINE_RTOL:g})",
                    "parallelism": "single GPU"},
         "roofline": head["roofline"],
+        "hbm_copy_gbs": hbm_copy,
         "krylov_iters_per_stage": head["krylov_iters_per_stage"],
         "max_trace_relres": head["max_trace_relres"],
         "launch": {k: head[k] for k in ("schedule", "grid_caps", "graph_steps",
