@@ -15,7 +15,11 @@
  *
  * Discretisation choices (the paper leaves them open): LGL nodes with
  * collocated LGL quadrature on elements and edges, trace nodes = LGL edge
- * nodes, flat bottom phi_B = g H, periodic boundaries.
+ * nodes, flat bottom phi_B = g H.  Boundaries: periodic, or a bounded
+ * rectangle whose boundary faces take the state of an imaginary neighbour
+ * in the numerical fluxes and the conservation condition (the principle of
+ * Sec. 4.3's wall condition) set from the exact translating vortex of
+ * Sec. 6.1 (eq. tc_vortex_ic), as in the paper's vortex test.
  *
  * Conventions
  *   - Every call returns an int status: IMEXHDG_OK (0) or a negative code.
@@ -99,13 +103,32 @@ extern "C" {
 #define IMEXHDG_VARS_DEPTH       0  /* (h, hu, hv): depth and momenta        */
 #define IMEXHDG_VARS_GEOPOTENTIAL 1 /* (phi_eta, U, V) = (g(h-H), g hu, g hv) */
 
+/* boundary of the domain [0,Lx] x [0,Ly] (config.boundary)
+ *   PERIODIC  every face has two elements.
+ *   VORTEX    bounded rectangle; a boundary face takes as its exterior state
+ *             the exact translating vortex of Sec. 6.1 (eq. tc_vortex_ic)
+ *             at the stage time, with H_inf = H, g = g and
+ *             (u_inf, v_inf, beta, xc, yc) = vortex[0..4] (centre at t = 0
+ *             in the domain's coordinates), in the explicit Rusanov flux and
+ *             in the conservation condition of the boundary face (an
+ *             imaginary neighbour, as Sec. 4.3 does for the wall; eqs.
+ *             reflection, reflectionBC).  Time is counted from the last
+ *             set_state (t = 0 there), t = steps dt.  Device arrays of the
+ *             operator-level calls and imexhdg_state_device use a mesh
+ *             padded by two ghost columns and rows ((nx + 2) x (ny + 2)
+ *             elements; the ghosts hold boundary states, faces between
+ *             ghosts hold zero); those calls, ensembles and the
+ *             allocation-free stage solve take periodic meshes only.     */
+#define IMEXHDG_BOUNDARY_PERIODIC 0
+#define IMEXHDG_BOUNDARY_VORTEX   1
+
 /* element type of device state arrays (imexhdg_set_state_device)          */
 #define IMEXHDG_DTYPE_F64 0
 #define IMEXHDG_DTYPE_F32 1
 
 typedef struct imexhdg_config {
     int32_t nx, ny;          /* elements per direction, >= 1               */
-    double  Lx, Ly;          /* periodic domain [0,Lx) x [0,Ly), > 0       */
+    double  Lx, Ly;          /* domain [0,Lx) x [0,Ly), > 0                */
     int32_t degree;          /* polynomial degree k, 1 <= k <= 8           */
     double  g, H;            /* gravity and mean depth: phi_B = g H > 0    */
     double  dt;              /* time step, > 0                             */
@@ -126,6 +149,9 @@ typedef struct imexhdg_config {
                                 residual in FP64; 1 or 2 (3 with BF16),
                                 0 = the default (1 for FP32, 3 for BF16);
                                 ignored by the other precisions           */
+    int32_t boundary;        /* IMEXHDG_BOUNDARY_*                         */
+    double  vortex[5];       /* u_inf, v_inf, beta, xc, yc of
+                                IMEXHDG_BOUNDARY_VORTEX (finite)           */
 } imexhdg_config;
 
 typedef struct imexhdg_diag {
@@ -170,8 +196,8 @@ typedef struct imexhdg_ctx imexhdg_ctx;
  * k = 2, g = H = 1, dt = 1e-3, krylov_rtol = 1e-14, refine_rtol = 1e-13). */
 int imexhdg_config_init(imexhdg_config *cfg);
 
-/* Validate cfg without touching a device.  Subcritical flow (|u| < sqrt(phi),
- * Sec. 3) is a property of the state and is checked by set_state.          */
+/* Validate cfg without touching a device (the state is checked by
+ * set_state).                                                             */
 int imexhdg_validate(const imexhdg_config *cfg);
 
 /* Device workspace the context needs for cfg, in bytes (host only).       */
@@ -198,7 +224,9 @@ void imexhdg_destroy(imexhdg_ctx *ctx);
 /* Sizes of the discrete spaces (Sec. 4.1): n_nodes = nx ny (k+1)^2 nodes
  * of the tensor-product space Q_k per variable, n_trace = 6 (k+1) nx ny
  * trace unknowns (three variables at the k+1 edge nodes of the 2 nx ny
- * faces of the periodic grid).  Either pointer may be NULL.              */
+ * faces of the periodic grid).  A bounded mesh reports the length of its
+ * padded device trace array, 6 (k+1) (nx+2) (ny+2).  Either pointer may
+ * be NULL.                                                               */
 int imexhdg_sizes(const imexhdg_ctx *ctx, int64_t *n_nodes, int64_t *n_trace);
 
 /* Coordinates of the nodes of the nodal basis (Sec. 4.1; LGL nodes mapped
@@ -209,9 +237,11 @@ int imexhdg_get_nodes(const imexhdg_ctx *ctx, double *x, double *y);
 /* Set q^n, the state at the nodes (Sec. 3.1 variables; Algorithm 1 takes
  * it as its input): host arrays of n_nodes doubles, host state ordering,
  * copied during the call; `vars` is IMEXHDG_VARS_*.  Rejects non-finite
- * values, h <= 0 and supercritical nodes |u| >= sqrt(g h) (the regime of
- * Sec. 3) with IMEXHDG_E_INVAL, leaving the state unchanged.  Resets the
- * trace guess and the step count.                                        */
+ * values and h <= 0 (the wave speed of the Rusanov flux needs phi > 0)
+ * with IMEXHDG_E_INVAL, leaving the state unchanged.  The subcritical
+ * regime of Sec. 3 (|u| < sqrt(phi)) is where the splitting pays, not a
+ * condition of the scheme: the moving vortex of Sec. 6.1 has |u| above
+ * sqrt(g h) at its centre.  Resets the trace guess and the step count.  */
 int imexhdg_set_state(imexhdg_ctx *ctx, int vars, const double *a,
                       const double *b, const double *c);
 

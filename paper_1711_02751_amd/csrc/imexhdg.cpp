@@ -104,10 +104,17 @@ struct OpSet {
            *Py = nullptr;
     float *Ghf = nullptr;
     void *Alp = nullptr;      // reduced-precision A^-1 fragments (launch_local_lp)
+    // boundary-row corrections of G and Ghat (bounded meshes), see Member
+    double *dG = nullptr, *dGh = nullptr;
+    float *dGhf = nullptr;
 };
 
+// nx, ny, nel: the device mesh (a bounded one padded by two ghost columns
+// and rows); bx, by: the bounded mesh's own elements (0: periodic).
 struct MemberHost {
     int nx = 0, ny = 0, nel = 0;
+    int bx = 0, by = 0;
+    double hx = 0, hy = 0;
     double Lx = 0, Ly = 0, dt = 0;
     size_t N = 0, T = 0, vo = 0, to = 0;
     int op = 0;
@@ -158,6 +165,15 @@ struct imexhdg_ctx {
          *kd = nullptr;
     KrylovState *ks = nullptr;        // [nm]
     KrylovBufs kb{};
+    // bounded mesh: boundary states of the exact vortex at the stage times;
+    // tstep[a] is the step count of the state in qbuf[a] (device, so that
+    // captured steps read it), tcur the ring position of the step being
+    // enqueued, cst[i] the abscissa of stage i
+    bool box = false;
+    Vortex vx{};
+    double *tstep = nullptr;
+    int tcur = 0;
+    std::vector<double> cst;
     double *dpart = nullptr;          // [5][pstride] residual / diagnostics partials
     // host mirrors
     KrylovState *hks = nullptr;
@@ -206,6 +222,68 @@ struct imexhdg_ens {
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device mesh of a config: a bounded rectangle is padded by two ghost
+// columns and rows.
+void device_dims(const imexhdg_config &c, int &nx, int &ny) {
+    const int pad = c.boundary == IMEXHDG_BOUNDARY_VORTEX ? 2 : 0;
+    nx = c.nx + pad;
+    ny = c.ny + pad;
+}
+
+// Boundary-row corrections (bounded meshes), one slot of fragments per side
+// [W, E, S, N]: frag[side][mb][kk][lane] = D_side[16 mb + lane % 16][4 kk +
+// lane / 16], KS = ceil(3K / 4) k steps, zero past 3K.
+size_t side_frag_count(int K) {
+    const int B3 = 3 * K, KS = (B3 + 3) / 4, NMB = (B3 + 15) / 16;
+    return (size_t)4 * NMB * KS * 64;
+}
+
+std::vector<double> pack_sides(const std::vector<double> (&D)[4], int K) {
+    const int B3 = 3 * K, KS = (B3 + 3) / 4, NMB = (B3 + 15) / 16;
+    std::vector<double> f(side_frag_count(K), 0.0);
+    for (int sd = 0; sd < 4; ++sd)
+        for (int mb = 0; mb < NMB; ++mb)
+            for (int u = 0; u < KS; ++u)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * mb + l % 16, col = 4 * u + l / 16;
+                    if (row < B3 && col < B3)
+                        f[(((size_t)sd * NMB + mb) * KS + u) * 64 + l] =
+                            D[sd][(size_t)row * B3 + col];
+                }
+    return f;
+}
+
+// A boundary face has one element and the imaginary neighbour (Sec. 4.3,
+// eqs. reflection / reflectionBC; the exact-solution data of Sec. 6.1 enter
+// the same way): its conservation condition keeps 2 tau I and the element's
+// C W, while the neighbour's part, C Z at its face nodes, is data (the
+// ghost element holds the exterior state there).  So the self block of a
+// boundary row is the interior one without the ghost side's C_K W_K at that
+// face: dG_side = -S(f, f), f the ghost's local face (W: the ghost lies
+// west, its east face 1; E: its west face 0; S: its north face 3; N: its
+// south face 2).  With the interior block-Jacobi inverse P^-1 kept as the
+// boundary rows' preconditioner, dGh_side = P^-1 dG_side.
+void boundary_deltas(const StageOperators &op, int K, std::vector<double> (&dG)[4],
+                     std::vector<double> (&dGh)[4]) {
+    const int B3 = 3 * K, NT = 12 * K;
+    const int ghost_face[4] = {1, 0, 3, 2};
+    for (int sd = 0; sd < 4; ++sd) {
+        const int f = ghost_face[sd];
+        dG[sd].assign((size_t)B3 * B3, 0.0);
+        for (int r = 0; r < B3; ++r)
+            for (int cc = 0; cc < B3; ++cc)
+                dG[sd][(size_t)r * B3 + cc] = -op.S[(size_t)(f * B3 + r) * NT + f * B3 + cc];
+        const std::vector<double> &P = sd < 2 ? op.Pxinv : op.Pyinv;
+        dGh[sd].assign((size_t)B3 * B3, 0.0);
+        for (int r = 0; r < B3; ++r)
+            for (int m = 0; m < B3; ++m) {
+                const double a = P[(size_t)r * B3 + m];
+                for (int cc = 0; cc < B3; ++cc)
+                    dGh[sd][(size_t)r * B3 + cc] += a * dG[sd][(size_t)m * B3 + cc];
+            }
+    }
+}
 
 // Sizes of the packed matrix-core operands of the trace row blocks.
 size_t frag_count(int K) {
@@ -299,8 +377,10 @@ std::vector<uint8_t> pack_lp(const std::vector<double> &M, int n, bool bf16) {
 int partial_stride(const std::vector<imexhdg_config> &cf) {
     int64_t f = 0, e = 0, d = 0;
     for (const imexhdg_config &c : cf) {
-        const int nel = c.nx * c.ny;
-        f += member_face_blocks(c.nx, c.ny, kMaxLaunchGrid);
+        int nx, ny;
+        device_dims(c, nx, ny);
+        const int nel = nx * ny;
+        f += member_face_blocks(nx, ny, kMaxLaunchGrid);
         e += member_elem_blocks(nel, c.degree + 1, kMaxLaunchGrid);
         d += member_diag_blocks(nel);
     }
@@ -328,7 +408,9 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     const imexhdg_config &c0 = cf[0];
     const size_t K = (size_t)c0.degree + 1;
     for (const imexhdg_config &c : cf) {
-        const size_t nel = (size_t)c.nx * c.ny;
+        int nx, ny;
+        device_dims(c, nx, ny);
+        const size_t nel = (size_t)nx * ny;
         L.N += 3 * K * K * nel;
         L.T += 6 * K * nel;
     }
@@ -349,7 +431,10 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
     t += (size_t)L.nops * (align256(local_frag_count((int)n_loc, (int)n_loc) * 8) +
                            align256(local_frag_count((int)n_loc, (int)n_tr) * 8) +
                            2 * align256(frag_count((int)K) * 8) +
-                           align256(frag_count((int)K) * 4) + 2 * align256(9 * K * K * 8));
+                           align256(frag_count((int)K) * 4) + 2 * align256(9 * K * K * 8) +
+                           2 * align256(side_frag_count((int)K) * 8) +
+                           align256(side_frag_count((int)K) * 4));
+    t += align256(3 * 8);                              // step counts of the state ring
     t += 8 * align256((size_t)L.pstride * 8) + align256(5 * (size_t)L.pstride * 8);
     t += align256(nm * sizeof(KrylovState));
     t += align256(nm * sizeof(Member));
@@ -390,6 +475,15 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "unknown launch mode");
     if (c->trace_guess != IMEXHDG_GUESS_EXTRAPOLATE && c->trace_guess != IMEXHDG_GUESS_LAST)
         return fail(IMEXHDG_E_INVAL, "unknown trace guess");
+    if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC && c->boundary != IMEXHDG_BOUNDARY_VORTEX)
+        return fail(IMEXHDG_E_INVAL, "unknown boundary");
+    if (c->boundary == IMEXHDG_BOUNDARY_VORTEX) {
+        for (double v : c->vortex)
+            if (!std::isfinite(v)) return fail(IMEXHDG_E_INVAL, "vortex parameters must be finite");
+        if ((int64_t)(c->nx + 2) * (c->ny + 2) > (int64_t)1 << 28 ||
+            (int64_t)6 * (c->degree + 1) * (c->nx + 2) * (c->ny + 2) >= ((int64_t)1 << 31))
+            return fail(IMEXHDG_E_INVAL, "bounded mesh too large");
+    }
     return IMEXHDG_OK;
 }
 
@@ -407,13 +501,15 @@ int validate_batch(const imexhdg_config *cfgs, int n) {
             a.krylov_rtol != b.krylov_rtol || a.krylov_max_iter != b.krylov_max_iter ||
             a.check_every != b.check_every || a.refine_rtol != b.refine_rtol ||
             a.refine_max != b.refine_max || a.launch != b.launch ||
-            a.trace_guess != b.trace_guess)
+            a.trace_guess != b.trace_guess || a.boundary != b.boundary)
             return fail(IMEXHDG_E_INVAL, "member " + std::to_string(m) +
                                              " differs from member 0 in more than nx, ny, "
                                              "Lx, Ly and dt");
     }
     if (n > 1 && cfgs[0].launch != IMEXHDG_LAUNCH_GRAPH)
         return fail(IMEXHDG_E_INVAL, "an ensemble steps on the fixed launch schedule only");
+    if (n > 1 && cfgs[0].boundary != IMEXHDG_BOUNDARY_PERIODIC)
+        return fail(IMEXHDG_E_INVAL, "ensemble members must be periodic");
     return IMEXHDG_OK;
 }
 
@@ -521,9 +617,15 @@ int build_batch(imexhdg_ctx *c) {
         d.nx = h.nx;
         d.ny = h.ny;
         d.nel = h.nel;
-        d.sx = 2.0 * h.nx / h.Lx;
-        d.sy = 2.0 * h.ny / h.Ly;
-        d.area = (h.Lx / h.nx / 2.0) * (h.Ly / h.ny / 2.0);
+        const int rx = h.bx > 0 ? h.bx : h.nx, ry = h.by > 0 ? h.by : h.ny;
+        d.sx = 2.0 * rx / h.Lx;
+        d.sy = 2.0 * ry / h.Ly;
+        d.area = (h.Lx / rx / 2.0) * (h.Ly / ry / 2.0);
+        d.bx = h.bx;
+        d.by = h.by;
+        d.dG = o.dG;
+        d.dGh = o.dGh;
+        d.dGhf = o.dGhf;
         d.dt = h.dt;
         d.vo = h.vo;
         d.to = h.to;
@@ -556,6 +658,7 @@ int build_batch(imexhdg_ctx *c) {
     c->bt.nbf = bf;
     c->bt.nbe = be;
     c->bt.nbd = bd;
+    c->bt.box = c->box ? 1 : 0;
     HIP_TRY(hipMemcpyAsync(c->dmem, c->mtab.data(), c->nm * sizeof(Member),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -752,6 +855,25 @@ int trace_solve(imexhdg_ctx *c, int32_t *iters_out, double *relres_out) {
     return IMEXHDG_OK;
 }
 
+// Bounded mesh: boundary states at stage i's time into the ghost elements of
+// v (the state ring position of the step being enqueued gives its step
+// count); `last`: also advance the step count of the output position.
+int fill_ghosts(imexhdg_ctx *c, double *v, int i, bool last) {
+    if (!c->box) return IMEXHDG_OK;
+    const int a = c->tcur;
+    HIP_TRY(launch_bc_fill(c->geom, c->bt, v, c->tstep + a, c->cst[i] * c->mh[0].dt,
+                           last ? c->tstep + (a + 1) % 3 : nullptr, c->vx, c->stream));
+    return IMEXHDG_OK;
+}
+
+// Ring position of a step's input state (bounded meshes step from the ring only).
+void begin_step(imexhdg_ctx *c, const double *qin) {
+    c->qin = qin;
+    c->tcur = 0;
+    for (int a = 0; a < 3; ++a)
+        if (c->qbuf[a] == qin) c->tcur = a;
+}
+
 // One implicit stage: Z = A^-1 R, g = C Z, solve G x = g, Q = Z - W x.
 // stage >= 0 (a step's stage i): the trace guess is extrapolated from the
 // last two solutions; stage < 0: x is the guess as it is.
@@ -762,6 +884,10 @@ int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, doub
                                                       c->lp_bf16, c->lp_ndc, c->stream));
     } else {
         LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
+    }
+    if (stage >= 0) {
+        int rf = fill_ghosts(c, c->Z, stage, false);
+        if (rf) return rf;
     }
     LAUNCH(IMEXHDG_K_TRACE_RHS,
            launch_trace_rhs(c->geom, c->bt, c->Z, c->gv, c->stream, nullptr,
@@ -793,6 +919,9 @@ int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
         cb.coef[cb.n] = t.coef;
         cb.n += 1;
     }
+    // bounded mesh: the explicit flux reads the boundary states from the
+    // ghosts of Q_i (Qi is the step's input or a stage buffer, both workspace)
+    if (int rf = fill_ghosts(c, const_cast<double *>(Qi), i, i + 1 == c->tab.s)) return rf;
     if (nonlinear) {
         LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, Qi, cb, true, c->stream, c->nl32));
     } else {
@@ -806,7 +935,7 @@ int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
 // host reads of the residual and the Krylov state (one member).
 int step_host(imexhdg_ctx *c, const double *qin, double *qout, int *status) {
     const int s = c->tab.s;
-    c->qin = qin;
+    begin_step(c, qin);
     for (int i = 0; i < s; ++i) {
         const double *Qi = qin;
         if (i > 0) {
@@ -864,6 +993,7 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
     } else {
         LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(g, b, R, c->Z, c->stream));
     }
+    if (int rf = fill_ghosts(c, c->Z, stage, false)) return rf;
     // trace_rhs also resets each member's stage-solve state and extrapolates
     // the trace guess
     LAUNCH(IMEXHDG_K_TRACE_RHS, launch_trace_rhs(g, b, c->Z, c->gv, c->stream, c->ks, c->x,
@@ -895,7 +1025,7 @@ int stage_solve_sched(imexhdg_ctx *c, const double *R, double *Q, StageStatus *s
 // outcome of member m in st[i nm + m].  Nothing here reads from the device.
 int step_sched(imexhdg_ctx *c, const double *qin, double *qout, StageStatus *st) {
     const int s = c->tab.s;
-    c->qin = qin;
+    begin_step(c, qin);
     for (int i = 0; i < s; ++i) {
         const double *Qi = qin;
         if (i > 0) {
@@ -1191,15 +1321,24 @@ int step_graph(imexhdg_ctx *c, int nsteps, int *status) {
 
 // Convert a member's host state (user ordering [ey][ex][j][i]) to the device
 // layout in h (3 K^2 nel values).
+// Element e of the host ordering (over the mesh's own elements) in the
+// device layout: a bounded mesh's element (ex, ey) sits at ey (bx + 2) + ex.
+int device_elem(const MemberHost &m, int e) {
+    return m.bx > 0 ? (e / m.bx) * m.nx + e % m.bx : e;
+}
+
+int host_elems(const MemberHost &m) { return m.bx > 0 ? m.bx * m.by : m.nel; }
+
 int state_to_device(const imexhdg_ctx *c, const MemberHost &m, int vars, const double *a,
                     const double *b, const double *cc, std::vector<double> &h) {
     const int K = c->geom.K, nel = m.nel;
     const double g = c->cfg.g, H = c->cfg.H, phiB = g * H;
     const size_t NN = (size_t)K * K * nel;
     h.assign(3 * NN, 0.0);
-    for (int e = 0; e < nel; ++e)
+    for (int e = 0; e < host_elems(m); ++e)
         for (int n = 0; n < K * K; ++n) {
-            const size_t src = (size_t)e * K * K + n, dst = (size_t)n * nel + e;
+            const size_t src = (size_t)e * K * K + n,
+                         dst = (size_t)n * nel + device_elem(m, e);
             double p, U, V;
             if (vars == IMEXHDG_VARS_DEPTH) {
                 p = g * (a[src] - H);
@@ -1214,8 +1353,6 @@ int state_to_device(const imexhdg_ctx *c, const MemberHost &m, int vars, const d
             if (!std::isfinite(p) || !std::isfinite(U) || !std::isfinite(V))
                 return fail(IMEXHDG_E_INVAL, "state holds NaN or Inf");
             if (!(phi > 0)) return fail(IMEXHDG_E_INVAL, "total depth must be positive");
-            if (U * U + V * V >= phi * phi * phi)
-                return fail(IMEXHDG_E_INVAL, "supercritical state: |u| >= sqrt(phi)");
             h[dst] = p;
             h[NN + dst] = U;
             h[2 * NN + dst] = V;
@@ -1228,9 +1365,10 @@ void state_from_device(const imexhdg_ctx *c, const MemberHost &m, int vars,
     const int K = c->geom.K, nel = m.nel;
     const double g = c->cfg.g, H = c->cfg.H;
     const size_t NN = (size_t)K * K * nel;
-    for (int e = 0; e < nel; ++e)
+    for (int e = 0; e < host_elems(m); ++e)
         for (int n = 0; n < K * K; ++n) {
-            const size_t dst = (size_t)e * K * K + n, src = (size_t)n * nel + e;
+            const size_t dst = (size_t)e * K * K + n,
+                         src = (size_t)n * nel + device_elem(m, e);
             const double p = h[src], U = h[NN + src], V = h[2 * NN + src];
             if (vars == IMEXHDG_VARS_DEPTH) {
                 a[dst] = H + p / g;
@@ -1246,10 +1384,11 @@ void state_from_device(const imexhdg_ctx *c, const MemberHost &m, int vars,
 
 void get_nodes_of(const imexhdg_ctx *c, const MemberHost &m, double *x, double *y) {
     const int K = c->geom.K;
-    const double hx = m.Lx / m.nx, hy = m.Ly / m.ny;
+    const double hx = m.hx, hy = m.hy;
+    const int nx = m.bx > 0 ? m.bx : m.nx, ny = m.by > 0 ? m.by : m.ny;
     size_t o = 0;
-    for (int ey = 0; ey < m.ny; ++ey)
-        for (int ex = 0; ex < m.nx; ++ex)
+    for (int ey = 0; ey < ny; ++ey)
+        for (int ex = 0; ex < nx; ++ex)
             for (int j = 0; j < K; ++j)
                 for (int i = 0; i < K; ++i, ++o) {
                     x[o] = (ex + (c->ref.x[i] + 1.0) / 2.0) * hx;
@@ -1312,9 +1451,14 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         size_t vo = 0, to = 0;
         for (int m = 0; m < n; ++m) {
             MemberHost h;
-            h.nx = cf[m].nx;
-            h.ny = cf[m].ny;
+            device_dims(cf[m], h.nx, h.ny);
             h.nel = h.nx * h.ny;
+            if (cf[m].boundary != IMEXHDG_BOUNDARY_PERIODIC) {
+                h.bx = cf[m].nx;
+                h.by = cf[m].ny;
+            }
+            h.hx = cf[m].Lx / cf[m].nx;
+            h.hy = cf[m].Ly / cf[m].ny;
             h.Lx = cf[m].Lx;
             h.Ly = cf[m].Ly;
             h.dt = cf[m].dt;
@@ -1324,7 +1468,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
             h.to = to;
             vo += h.N;
             to += h.T;
-            const double hx = h.Lx / h.nx, hy = h.Ly / h.ny;
+            const double hx = h.hx, hy = h.hy;
             int found = -1;
             for (size_t o = 0; o < c->ops.size(); ++o)
                 if (c->ops[o].hx == hx && c->ops[o].hy == hy && c->ops[o].dt == h.dt)
@@ -1349,6 +1493,22 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     if ((rc = build_plans(c))) return bail(rc);
     c->xcoef = guess_coefficients(c->tab);
     if (cf[0].trace_guess == IMEXHDG_GUESS_LAST) std::fill(c->xcoef.begin(), c->xcoef.end(), 0.0);
+    // stage abscissae c_i (row sums of the explicit tableau); boundary
+    // data at the stage times need c = c~ (true of the ARS schemes)
+    c->cst.assign(c->tab.s, 0.0);
+    for (int i = 0; i < c->tab.s; ++i) {
+        double ce = 0.0, ci = 0.0;
+        for (int j = 0; j < c->tab.s; ++j) {
+            ce += c->tab.a(i, j);
+            ci += c->tab.at(i, j);
+        }
+        c->cst[i] = ce;
+        if (cf[0].boundary != IMEXHDG_BOUNDARY_PERIODIC && std::fabs(ce - ci) > 1e-14)
+            return bail(fail(IMEXHDG_E_INVAL, "boundary data need equal stage abscissae"));
+    }
+    c->box = cf[0].boundary == IMEXHDG_BOUNDARY_VORTEX;
+    c->vx = Vortex{cf[0].H, cf[0].g, cf[0].vortex[0], cf[0].vortex[1], cf[0].vortex[2],
+                   cf[0].vortex[3], cf[0].vortex[4]};
     Geom &g = c->geom;
     g.K = K;
     g.phiB = cf[0].g * cf[0].H;
@@ -1356,12 +1516,14 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     g.winv0 = 1.0 / c->ref.w[0];
     g.winvk = 1.0 / c->ref.w[K - 1];
     for (int i = 0; i < K; ++i) g.w[i] = c->ref.w[i];
+    for (int i = 0; i < K; ++i) g.xi[i] = c->ref.x[i];
     for (int m = 0; m < K; ++m)
         for (int a = 0; a < K; ++a)
             g.Dw[m * K + a] = c->ref.w[m] * c->ref.D[m * K + a] / c->ref.w[a];
     c->N = L.N;
     c->T = L.T;
-    c->nnodes = L.N / 3;
+    c->nnodes = 0;
+    for (const imexhdg_config &m : cf) c->nnodes += (size_t)m.nx * m.ny * K * K;
 
     if (hipGetDevice(&c->device) != hipSuccess)
         return bail(fail(IMEXHDG_E_DEVICE, "no HIP device"));
@@ -1414,7 +1576,11 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         o.Px = (double *)take(9 * K * K * 8);
         o.Py = (double *)take(9 * K * K * 8);
         if (c->lp) o.Alp = take(lp_frag_bytes((int)n_loc, c->lp_bf16));
+        o.dG = (double *)take(side_frag_count(K) * 8);
+        o.dGh = (double *)take(side_frag_count(K) * 8);
+        o.dGhf = (float *)take(side_frag_count(K) * 4);
     }
+    c->tstep = (double *)take(3 * 8);
     c->kb.P1 = (double *)take(3 * (size_t)c->pstride * 8);
     c->kb.P2 = (double *)take(3 * (size_t)c->pstride * 8);
     c->kb.P3 = (double *)take(2 * (size_t)c->pstride * 8);
@@ -1424,6 +1590,11 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     c->dmem = (Member *)take(n * sizeof(Member));
     c->dstat = (StageStatus *)take(3 * (size_t)L.s * n * sizeof(StageStatus));
     if (off > c->ws_bytes) return bail(fail(IMEXHDG_E_INVAL, "internal: workspace overflow"));
+    // a bounded mesh's faces between ghosts must read zero in every trace
+    // vector, and nothing ever writes them: clear the whole workspace once
+    if (c->box && (hipMemsetAsync(c->ws, 0, off, c->stream) ||
+                   hipStreamSynchronize(c->stream)))
+        return bail(fail(IMEXHDG_E_DEVICE, "workspace initialisation failed"));
 
     if (hipHostMalloc((void **)&c->hks, sizeof(KrylovState)) != hipSuccess ||
         hipHostMalloc((void **)&c->hpart, 5 * (size_t)c->pstride * 8) != hipSuccess ||
@@ -1452,6 +1623,17 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
                            c->stream) ||
             up(os.Px, op.Pxinv) || up(os.Py, op.Pyinv) || hipStreamSynchronize(c->stream))
             return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+        if (c->box) {
+            std::vector<double> dG[4], dGh[4];
+            boundary_deltas(op, K, dG, dGh);
+            const std::vector<double> fG = pack_sides(dG, K), fGh = pack_sides(dGh, K);
+            const std::vector<float> fGhf(fGh.begin(), fGh.end());
+            if (up(os.dG, fG) || up(os.dGh, fGh) ||
+                hipMemcpyAsync(os.dGhf, fGhf.data(), fGhf.size() * 4, hipMemcpyHostToDevice,
+                               c->stream) ||
+                hipStreamSynchronize(c->stream))
+                return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
+        }
         if (c->lp) {
             const std::vector<uint8_t> f = pack_lp(op.Ainv, nl, c->lp_bf16);
             if (hipMemcpyAsync(os.Alp, f.data(), f.size(), hipMemcpyHostToDevice, c->stream) ||
@@ -1532,6 +1714,7 @@ int state_was_set(imexhdg_ctx *c, int m) {
     const MemberHost &mh = c->mh[m];
     HIP_TRY(hipMemsetAsync(c->x + mh.to, 0, mh.T * 8, c->stream));
     HIP_TRY(hipMemsetAsync(c->xp + mh.to, 0, mh.T * 8, c->stream));
+    if (c->box) HIP_TRY(launch_put(c->tstep + c->cur, 0.0, c->stream));
     HIP_TRY(stream_sync(c));
     c->member_set[m] = true;
     c->have_state = std::all_of(c->member_set.begin(), c->member_set.end(),
@@ -1555,16 +1738,16 @@ int set_member_state_device(imexhdg_ctx *c, int m, int vars, int dtype, const vo
         return fail(IMEXHDG_E_INVAL, "unknown dtype");
     const MemberHost &mh = c->mh[m];
     const int K = c->geom.K;
-    const int blocks = state_in_blocks(mh.nel, K, c->pstride);
+    const int blocks = state_in_blocks(host_elems(mh), K, c->pstride);
     HIP_TRY(launch_state_in(src, dtype == IMEXHDG_DTYPE_F32, vars == IMEXHDG_VARS_DEPTH,
-                            c->cfg.g, c->cfg.H, mh.nel, K, c->Z + mh.vo, c->dpart, blocks,
-                            c->stream));
+                            c->cfg.g, c->cfg.H, host_elems(mh), K, c->Z + mh.vo, c->dpart,
+                            blocks, c->stream, mh.bx, mh.nx));
     double bad = 0.0;
     int rc = read_partials(c, 1, 0, blocks, &bad);
     if (rc) return rc;
     if (bad != 0.0)
         return fail(IMEXHDG_E_INVAL, "state rejected at " + std::to_string((int64_t)bad) +
-                                         " nodes: NaN or Inf, h <= 0 or |u| >= sqrt(phi)");
+                                         " nodes: NaN or Inf or h <= 0");
     HIP_TRY(hipMemcpyAsync(c->q + mh.vo, c->Z + mh.vo, mh.N * 8, hipMemcpyDeviceToDevice,
                            c->stream));
     return state_was_set(c, m);
@@ -1705,6 +1888,10 @@ int imexhdg_config_init(imexhdg_config *c) {
     c->refine_max = 4;
     c->launch = IMEXHDG_LAUNCH_GRAPH;
     c->trace_guess = IMEXHDG_GUESS_EXTRAPOLATE;
+    c->boundary = IMEXHDG_BOUNDARY_PERIODIC;
+    c->vortex[0] = 1.0;   // u_inf, v_inf, beta, xc, yc of Sec. 6.1
+    c->vortex[1] = 0.0;
+    c->vortex[2] = 5.0;
     return IMEXHDG_OK;
 }
 
@@ -1777,6 +1964,7 @@ int imexhdg_state_device(imexhdg_ctx *c, double **d_q) {
 
 int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
     if (!c || !d_q || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
     Comb cb{};
     cb.n = 0;
     cb.self = 1.0;
@@ -1789,6 +1977,7 @@ int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
 int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_qhat,
                             double *d_out) {
     if (!c || !d_Q || !d_qhat || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
     LAUNCH(IMEXHDG_K_LINRES,
            launch_linear_residual(c->geom, c->bt, d_Q, d_qhat, d_out, c->stream));
     return IMEXHDG_OK;
@@ -1797,6 +1986,7 @@ int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_q
 int imexhdg_stage_solve_noalloc(imexhdg_ctx *c, const double *d_res0, double *d_Q,
                                 double *d_qhat, int32_t *iters, double *relres) {
     if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
     if (c->nm != 1) return fail(IMEXHDG_E_INVAL, "a context of one mesh is required");
     SolveBufs sb;
     const size_t need = carve_scratch(c, nullptr, &sb);
@@ -1832,6 +2022,7 @@ int imexhdg_stage_solve_noalloc(imexhdg_ctx *c, const double *d_res0, double *d_
 int imexhdg_stage_solve(imexhdg_ctx *c, const double *d_res0, double *d_Q, double *d_qhat,
                         int32_t *iters, double *relres) {
     if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
     HIP_TRY(hipMemcpyAsync(c->x, d_qhat, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
     int rc = stage_solve(c, d_res0, d_Q, iters, relres, -1);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
@@ -1945,6 +2136,7 @@ static int tune_trial(imexhdg_ctx *c, int fg, int eg, double *avg, int64_t *cnt)
     HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
     HIP_TRY(hipMemsetAsync(c->xp, 0, c->T * 8, c->stream));
+    if (c->box) HIP_TRY(launch_put(c->tstep + c->cur, (double)c->steps, c->stream));
     rc = imexhdg_profile(c, -1);
     if (rc) return rc;
     int status = IMEXHDG_OK;
@@ -2048,6 +2240,7 @@ int imexhdg_autotune(imexhdg_ctx *c, const char *cache_path, int32_t *face_grid,
         HIP_TRY(hipMemcpyAsync(c->q, c->save, c->N * 8, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
         HIP_TRY(hipMemsetAsync(c->xp, 0, c->T * 8, c->stream));
+        if (c->box) HIP_TRY(launch_put(c->tstep + c->cur, (double)keep[0], c->stream));
         HIP_TRY(stream_sync(c));
         c->steps = keep[0];
         c->kiters = keep[1];

@@ -134,7 +134,21 @@ __device__ __forceinline__ Member load_member(const Batch &bt, int i) {
     r.Ainv = c.Ainv; r.W = c.W; r.G = c.G; r.Gh = c.Gh; r.Px = c.Px; r.Py = c.Py;
     r.Ghf = c.Ghf;
     r.Alp = c.Alp;
+    r.bx = c.bx; r.by = c.by;
+    r.dG = c.dG; r.dGh = c.dGh; r.dGhf = c.dGhf;
     return r;
+}
+
+// Bounded member (bx > 0): faces between ghost elements are not unknowns.
+__device__ __forceinline__ bool dummy_face(int d, int ex, int ey, const Member &g) {
+    return g.bx > 0 && (d == 0 ? (ey >= g.by || ex == g.bx + 1) : (ex >= g.bx || ey == g.by + 1));
+}
+
+// Side of a boundary face of a bounded member: 0 W, 1 E, 2 S, 3 N, -1 none.
+__device__ __forceinline__ int boundary_side(int d, int ex, int ey, const Member &g) {
+    if (g.bx == 0) return -1;
+    if (d == 0) return ey < g.by ? (ex == 0 ? 0 : ex == g.bx ? 1 : -1) : -1;
+    return ex < g.bx ? (ey == 0 ? 2 : ey == g.by ? 3 : -1) : -1;
 }
 
 // Deterministic reductions without fences or atomics.  A producer kernel
@@ -684,7 +698,9 @@ __global__ __launch_bounds__(64 * K) void k_trace_rhs(const double *__restrict__
         stage_begin_state(begin + mi);
     Z += mb.vo;
     gv += mb.to;
-    const FaceIdx fi = face_of_tile(blockIdx.x - 2 * mb.bv, mb.nel);
+    FaceIdx fi = face_of_tile(blockIdx.x - 2 * mb.bv, mb.nel);
+    // faces between the ghost elements of a bounded member stay zero
+    if (dummy_face(fi.d, fi.f % mb.nx, fi.f / mb.nx, mb)) fi.active = false;
     const Nbr n = neighbours(fi.f, mb.nx, mb.ny);
     const size_t nel = mb.nel, NN = (size_t)K * K * nel, TT = (size_t)3 * K * nel;
     const double phiB = g.phiB, tau = g.tau;
@@ -1327,14 +1343,31 @@ constexpr int kTX = 16, kTY = 4;     // element tile (below)
 struct WaveFaces {
     int set, sub;            // face set (wave-uniform), tile row
     int e;                   // element (= face index) of this lane
-    bool active;             // e < nel
+    bool active;             // e < nel, and an unknown of a bounded mesh
+    int bt;                  // boundary side of this lane's face (bounded mesh): 0 W, 1 E,
+                             // 2 S, 3 N, -1 none
+    const void *dfr;         // boundary-row corrections of the wave's operator, or nullptr
 };
+
+
+// Boundary-row corrections of the preconditioned row blocks in precision T.
+template <typename T> __device__ __forceinline__ const void *delta_hat(const Member &g);
+template <> __device__ __forceinline__ const void *delta_hat<double>(const Member &g) {
+    return g.dGh;
+}
+template <> __device__ __forceinline__ const void *delta_hat<float>(const Member &g) {
+    return g.dGhf;
+}
 
 // Tiles of 16 x 4 elements cover the mesh (partial tiles at the high
 // edges, their lanes past the mesh inactive).
 __device__ __forceinline__ int tiles_per_row(const Member &g) { return (g.nx + kTX - 1) / kTX; }
 
-__device__ __forceinline__ WaveFaces wave_faces(int tile, const Member &g) {
+// BND: the batch has a bounded member (mask its faces between ghosts, mark
+// its boundary faces); false compiles the periodic mapping alone.
+template <bool BND>
+__device__ __forceinline__ WaveFaces wave_faces(int tile, const Member &g,
+                                                const void *dfr = nullptr) {
     WaveFaces wf;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1343,6 +1376,13 @@ __device__ __forceinline__ WaveFaces wave_faces(int tile, const Member &g) {
     const int tpr = tiles_per_row(g);
     const int ex = (tile % tpr) * kTX + (lane & 15), ey = (tile / tpr) * kTY + wf.sub;
     wf.active = ex < g.nx && ey < g.ny;
+    wf.bt = -1;
+    wf.dfr = nullptr;
+    if constexpr (BND) {
+        wf.active = wf.active && !dummy_face(wf.set, ex, ey, g);
+        wf.bt = wf.active ? boundary_side(wf.set, ex, ey, g) : -1;
+        wf.dfr = g.bx > 0 ? dfr : nullptr;
+    }
     wf.e = wf.active ? ey * g.nx + ex : 0;
     return wf;
 }
@@ -1637,6 +1677,35 @@ __device__ __forceinline__ void tile_rows(const T *__restrict__ const *frags, co
     }
 }
 
+// Bounded mesh: a boundary row adds its side's correction of the self
+// block, applied to the lane's own face (slot 0 of the staged tile) where
+// the lane's face is on that side (the B operand is zero elsewhere).
+template <int K, typename T>
+__device__ __forceinline__ void boundary_rows(const WaveFaces &wf, const T *sB,
+                                              typename MfmaT<T>::v4 (&acc)[1][MF<K>::NMB]) {
+    using TL = Tile<K>;
+    constexpr int B3 = TL::B3, NF = TileRow<K, T>::stride, KS = MF<K>::KS, NMB = MF<K>::NMB;
+    if (wf.dfr == nullptr) return;
+    const int lane = threadIdx.x & 63, q = lane >> 4, lx = lane & 15;
+    const T *dfr = (const T *)wf.dfr;
+    const int li = slot_lds(wf.set, 0, lx, wf.sub, TL::NX, TL::XC, TL::YC);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int side = 2 * wf.set + h;
+        if (!__any(wf.bt == side)) continue;
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int cj = 4 * u + q;
+            const T bv = sB[(cj < B3 ? cj : B3 - 1) * NF + li];
+            const T b = wf.bt == side ? bv : T(0);
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+                acc[0][mb] = MfmaT<T>::mma(dfr[frag_off(side, mb, u, lane, NMB, KS)], b,
+                                           acc[0][mb]);
+        }
+    }
+}
+
 // LDS index of this lane's own face of its wave's set.
 template <int K>
 __device__ __forceinline__ int own_lds(const WaveFaces &wf) {
@@ -1761,7 +1830,7 @@ __device__ __forceinline__ void stage_frags(const T *__restrict__ const *g, T *s
 // P^-1 r and P^-1 g are two short contractions on the registers.  With rin
 // == nullptr (a check of a finished solve) only ||r||^2 and ||g||^2 are
 // formed.
-template <int K, typename RT>
+template <int K, typename RT, bool BND>
 __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_residual(
     const Batch bt, const double *__restrict__ x, const double *__restrict__ gv,
     RT *__restrict__ rin, double *partials, int stride, const KrylovState *skip) {
@@ -1818,7 +1887,7 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
                 const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
                 st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
             };
-            const WaveFaces wf = wave_faces(tile, mb);
+            const WaveFaces wf = wave_faces<BND>(tile, mb, mb.dG);
             // g at the own rows, loaded ahead of the contraction
             double gvv[NMB][4];
             uint32_t o[NMB][4];
@@ -1834,6 +1903,7 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
             face_rows<K, 1>(fr, st, mb, wf, sB, src,
                             [](const double (&a)[1], uint32_t, bool) { return a[0]; },
                             acc, prefetch);
+            if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
             // r and g as B operands (zero past row 3K and off the mesh)
             double rb[NMB][4], gb[NMB][4];
 #pragma unroll
@@ -1958,7 +2028,7 @@ __device__ __forceinline__ const float *ghat_frags(const Member &mb, float) { re
 // from rh.r and r.r [partials P3 of the elementwise class]; p <- r + beta
 // (p - omega v) at the seven faces of each row block (p = v = 0 here), v =
 // Ghat p; partials P1 = (rh.v, rh.r, r.r) over the own faces.
-template <int K, typename T, bool SCHED>
+template <int K, typename T, bool SCHED, bool BND>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
     const Batch bt, const T *__restrict__ r, const T *__restrict__ rh,
     const T *__restrict__ pin, const T *__restrict__ vin, T *__restrict__ pout,
@@ -2013,7 +2083,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                     st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
                 }
             };
-            const WaveFaces wf = wave_faces(tile, mb);
+            const WaveFaces wf = wave_faces<BND>(tile, mb, delta_hat<T>(mb));
             T rhv[NMB][4], rv[NMB][4];
             uint32_t o[NMB][4];
             bool ok[NMB][4];
@@ -2033,6 +2103,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                                        return p;
                                    },
                                    acc, prefetch);
+            if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
@@ -2061,7 +2132,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
 // own faces receive r, rh, p, v and d = 0, P1 = (rh.v, rh.r, r.r), and the
 // tolerance is max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2)
 // (an inner solve that starts below it is converged at once).
-template <int K, typename T>
+template <int K, typename T, bool BND>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
     const Batch bt, const T *__restrict__ rin, T *__restrict__ r, T *__restrict__ rh,
     T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ d, KrylovState *ks_all,
@@ -2118,7 +2189,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
             const int nt = tile + tw.step;   // unconditional (see EarlyPartials)
             st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
         };
-        const WaveFaces wf = wave_faces(tile, mb);
+        const WaveFaces wf = wave_faces<BND>(tile, mb, delta_hat<T>(mb));
         T rv[NMB][4];
         uint32_t o[NMB][4];
         bool ok[NMB][4];
@@ -2141,6 +2212,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
                             return a[0];
                         },
                         acc, prefetch);
+        if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
 #pragma unroll
         for (int m = 0; m < NMB; ++m)
 #pragma unroll
@@ -2184,7 +2256,7 @@ __device__ __forceinline__ double s_of(double r, double al, double v) {
 // products of the last K1); stop when rr <= tol2; alpha = rho / rv;
 // s = r - alpha v at the seven faces, t = Ghat s; partials P2 = (t.s, t.t,
 // rh.t) over the own faces.
-template <int K, typename T, bool SCHED>
+template <int K, typename T, bool SCHED, bool BND>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
     const Batch bt, const T *__restrict__ r, const T *__restrict__ v,
     const T *__restrict__ rh, T *__restrict__ t, KrylovState *ks_all,
@@ -2253,7 +2325,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                     st.load(nt < tw.end ? nt : tile, mb, src, nullptr, nt >= tw.end);
                 }
             };
-            const WaveFaces wf = wave_faces(tile, mb);
+            const WaveFaces wf = wave_faces<BND>(tile, mb, delta_hat<T>(mb));
             uint32_t o[NMB][4];
             bool ok[NMB][4];
             T sown[NMB][4], rhv[NMB][4];
@@ -2271,6 +2343,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                                        return s_of(a[0], al, a[1]);
                                    },
                                    acc, prefetch);
+            if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
             {
                 const int li = own_lds<K>(wf);
 #pragma unroll
@@ -2318,7 +2391,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
 // this launch only flags it (a flag read at entry and written in the same
 // launch would let a block that starts after block 0 has finished skip its
 // updates).
-template <int K, typename T, bool SCHED>
+template <int K, typename T, bool SCHED, bool BND>
 __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     const Batch bt, const T *__restrict__ rin, const T *__restrict__ t,
     const T *__restrict__ rh, const T *__restrict__ pin, const T *__restrict__ vin,
@@ -2388,7 +2461,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                     st.load(nt < tw.end ? nt : tile, mb, src, osrc, nt >= tw.end);
                 }
             };
-            const WaveFaces wf = wave_faces(tile, mb);
+            const WaveFaces wf = wave_faces<BND>(tile, mb, delta_hat<T>(mb));
             T rhv[NMB][4];
             uint32_t o[NMB][4];
             bool ok[NMB][4];
@@ -2428,6 +2501,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                                     return pn;
                                 },
                                 acc, prefetch);
+                if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
                 const int li = own_lds<K>(wf);
 #pragma unroll
                 for (int m = 0; m < NMB; ++m)
@@ -2445,6 +2519,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                                     return pnew(rnew(s_of(a[0], al, a[3]), a[1]), a[2], a[3]);
                                 },
                                 acc, prefetch);
+                if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
                 // own faces: all loads first, then the updates
                 T sv_[NMB][4], tv_[NMB][4], pv_[NMB][4], vv_[NMB][4], dv_[NMB][4];
 #pragma unroll
@@ -2533,6 +2608,72 @@ __global__ void k_axpy_guarded(const Batch bt, int K, double *__restrict__ y,
 }
 
 
+// ------------------------------------------------ boundary states
+// The exact translating vortex of Sec. 6.1 (eq. tc_vortex_ic) at (x, y, t)
+// in the geopotential variables: depth h = H - beta^2 / (32 pi^2)
+// exp(-2 (r^2 - 1)), velocity (u_inf - beta / (2 pi) exp(-(r^2 - 1)) y_t,
+// v_inf + beta / (2 pi) exp(-(r^2 - 1)) x_t), x_t = x - xc - u_inf t,
+// y_t = y - yc - v_inf t; (phi_eta, U, V) = (g (h - H), g h u, g h v).
+__device__ __forceinline__ void vortex_state(const Vortex &v, double x, double y, double t,
+                                             double &p, double &U, double &V) {
+    const double xt = x - v.xc - v.uinf * t, yt = y - v.yc - v.vinf * t;
+    const double r2 = xt * xt + yt * yt;
+    const double e = exp(-(r2 - 1.0));
+    const double pi = 3.141592653589793;
+    const double h = v.H - v.beta * v.beta / (32.0 * (pi * pi)) * e * e;
+    const double u = v.uinf - v.beta / (2.0 * pi) * e * yt;
+    const double w = v.vinf + v.beta / (2.0 * pi) * e * xt;
+    p = v.g * (h - v.H);
+    U = v.g * (h * u);
+    V = v.g * (h * w);
+}
+
+// Ghost elements of a bounded member (see Member): every node of a ghost
+// takes the boundary state at the point of the domain boundary it faces
+// (only the nodes on the shared face are read: by the explicit flux, and
+// by the trace right-hand side from Z).  One thread per (element, node
+// row j, node i): block = 64 elements x K rows.
+__global__ __launch_bounds__(64 * kMaxK) void k_bc_fill(double *__restrict__ q, const Geom g,
+                                                        const Batch bt, const double *tstep,
+                                                        double toff, double *tnext,
+                                                        const Vortex vx) {
+    const int K = g.K;
+    const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    if (mb.bx == 0) return;
+    if (tnext != nullptr && lb == 0 && threadIdx.x == 0) tnext[0] = tstep[0] + 1.0;
+    const int e = lb * 64 + lane;
+    if (e >= mb.nel) return;
+    const int ex = e % mb.nx, ey = e / mb.nx;
+    const bool gx = ex >= mb.bx, gy = ey >= mb.by;
+    if (!gx && !gy) return;
+    q += mb.vo;
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel;
+    const double t = tstep[0] * mb.dt + toff;
+    const double hx = 2.0 / mb.sx, hy = 2.0 / mb.sy;
+    for (int i = 0; i < K; ++i) {
+        double p = 0.0, U = 0.0, V = 0.0;
+        if (gx != gy) {
+            double x, y;
+            if (gx) {   // east (bx) or west (bx + 1) ghost: boundary x, the node's y
+                x = ex == mb.bx ? mb.bx * hx : 0.0;
+                y = (ey + (g.xi[j] + 1.0) * 0.5) * hy;
+            } else {    // north (by) or south (by + 1) ghost: the node's x, boundary y
+                x = (ex + (g.xi[i] + 1.0) * 0.5) * hx;
+                y = ey == mb.by ? mb.by * hy : 0.0;
+            }
+            vortex_state(vx, x, y, t, p, U, V);
+        }
+        const size_t o = (size_t)(j * K + i) * nel + e;
+        q[o] = p;
+        q[NN + o] = U;
+        q[2 * NN + o] = V;
+    }
+}
+
+__global__ void k_put_f64(double *p, double v) { p[0] = v; }
+
 // --------------------------------------------------------- diagnostics
 // Partials of (mass phi_eta, mass U, mass V, energy, non-finite count).
 template <int K>
@@ -2547,6 +2688,7 @@ __global__ __launch_bounds__(64 * K) void k_diag(const double *__restrict__ q, c
     const size_t nel = mb.nel, NN = (size_t)K * K * nel;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int e = lb * 64 + lane; e < mb.nel; e += mb.nbd * 64) {
+        if (mb.bx > 0 && (e % mb.nx >= mb.bx || e / mb.nx >= mb.by)) continue;   // ghost
         for (int i = 0; i < K; ++i) {
             const size_t o = (size_t)(j * K + i) * nel + e;
             const double m = mb.area * g.w[i] * g.w[j];
@@ -2567,8 +2709,11 @@ __global__ __launch_bounds__(64 * K) void k_diag(const double *__restrict__ q, c
 template <typename T>
 __global__ void k_state_in(const T *__restrict__ src, int depth, double g, double H,
                            double phiB, int nel, int KK, double *__restrict__ dst,
-                           double *partials, int stride) {
+                           double *partials, int stride, int bx, int nxp) {
     const size_t nn = (size_t)nel * KK;
+    // bounded member: real element e = ey bx + ex sits at ey nxp + ex of the
+    // padded layout of nxp (nel / bx + 2) elements
+    const size_t nd = bx > 0 ? (size_t)nxp * (nel / bx + 2) : (size_t)nel;
     double bad[1] = {0.0};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
          i += (size_t)gridDim.x * blockDim.x) {
@@ -2577,13 +2722,14 @@ __global__ void k_state_in(const T *__restrict__ src, int depth, double g, doubl
         const double U = depth ? g * b : b;
         const double V = depth ? g * c : c;
         const double phi = p + phiB;
-        const bool ok = isfinite(p) && isfinite(U) && isfinite(V) && phi > 0.0 &&
-                        U * U + V * V < phi * phi * phi;
+        const bool ok = isfinite(p) && isfinite(U) && isfinite(V) && phi > 0.0;
         if (!ok) bad[0] += 1.0;
-        const size_t e = i / KK, n = i - e * KK, o = n * nel + e;
+        const size_t e = i / KK, n = i - e * KK;
+        const size_t ed = bx > 0 ? (e / bx) * nxp + e % bx : e;
+        const size_t o = n * nd + ed, nnd = nd * KK;
         dst[o] = p;
-        dst[nn + o] = U;
-        dst[2 * nn + o] = V;
+        dst[nnd + o] = U;
+        dst[2 * nnd + o] = V;
     }
     store_partials<1>(bad, partials, stride);
 }
@@ -2678,30 +2824,38 @@ template <int K> struct RunTraceRhs {
         return hipGetLastError();
     }
 };
+// The face kernels exist in a periodic (BND = false) and a bounded-mesh
+// variant; the batch's box flag picks one.
 template <typename RT> struct RunTraceResidual {
     template <int K> struct F {
         static hipError_t run(const Batch &b, const double *x, const double *gv, RT *rin,
                               double *partials, int stride, const KrylovState *skip,
                               hipStream_t s) {
-            KLAUNCH((k_trace_residual<K, RT>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
-                               b, x, gv, rin, partials, stride, skip);
+            if (b.box)
+                KLAUNCH((k_trace_residual<K, RT, true>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
+                        b, x, gv, rin, partials, stride, skip);
+            else
+                KLAUNCH((k_trace_residual<K, RT, false>), dim3(b.nbf), dim3(kFaceThreads), 0, s,
+                        b, x, gv, rin, partials, stride, skip);
             return hipGetLastError();
         }
     };
 };
 template <typename T> struct RunK1 {
+    template <int K, bool SCHED, bool BND>
+    static void go(const Batch &b, const T *r, const T *rh, const T *pin, const T *vin, T *pout,
+                   T *vout, KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
+        KLAUNCH((k_bicg_k1<K, T, SCHED, BND>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b, r, rh,
+                pin, vin, pout, vout, ks, kb.P3, kb.P1, kb.stride);
+    }
     template <int K> struct F {
         static hipError_t run(const Batch &b, const T *r, const T *rh, const T *pin,
                               const T *vin, T *pout, T *vout, KrylovState *ks,
                               const KrylovBufs &kb, hipStream_t s) {
-            if (kb.sched)
-                KLAUNCH((k_bicg_k1<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
-                                   kb.stride);
-            else
-                KLAUNCH((k_bicg_k1<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, rh, pin, vin, pout, vout, ks, kb.P3, kb.P1,
-                                   kb.stride);
+            if (kb.sched && b.box) go<K, true, true>(b, r, rh, pin, vin, pout, vout, ks, kb, s);
+            else if (kb.sched) go<K, true, false>(b, r, rh, pin, vin, pout, vout, ks, kb, s);
+            else if (b.box) go<K, false, true>(b, r, rh, pin, vin, pout, vout, ks, kb, s);
+            else go<K, false, false>(b, r, rh, pin, vin, pout, vout, ks, kb, s);
             return hipGetLastError();
         }
     };
@@ -2712,39 +2866,56 @@ template <typename T> struct RunRefineK1 {
                               KrylovState *ks, const double *partials, int pstride,
                               double refine_rtol, double inner_rtol, const KrylovBufs &kb,
                               hipStream_t s) {
-            KLAUNCH((k_refine_k1<K, T>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b, rin, r, rh,
-                    p, v, d, ks, partials, pstride, refine_rtol, inner_rtol, kb.P1, kb.stride);
+            if (b.box)
+                KLAUNCH((k_refine_k1<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b, rin,
+                        r, rh, p, v, d, ks, partials, pstride, refine_rtol, inner_rtol, kb.P1,
+                        kb.stride);
+            else
+                KLAUNCH((k_refine_k1<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b,
+                        rin, r, rh, p, v, d, ks, partials, pstride, refine_rtol, inner_rtol,
+                        kb.P1, kb.stride);
             return hipGetLastError();
         }
     };
 };
 template <typename T> struct RunK2 {
+    template <int K, bool SCHED, bool BND>
+    static void go(const Batch &b, const T *r, const T *v, const T *rh, T *t, KrylovState *ks,
+                   const KrylovBufs &kb, hipStream_t s) {
+        KLAUNCH((k_bicg_k2<K, T, SCHED, BND>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b, r, v,
+                rh, t, ks, kb.P1, kb.P2, kb.stride);
+    }
     template <int K> struct F {
         static hipError_t run(const Batch &b, const T *r, const T *v, const T *rh, T *t,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-            if (kb.sched)
-                KLAUNCH((k_bicg_k2<K, T, true>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, v, rh, t, ks, kb.P1, kb.P2, kb.stride);
-            else
-                KLAUNCH((k_bicg_k2<K, T, false>), dim3(b.nbf), dim3(kFaceThreads), 0,
-                                   s, b, r, v, rh, t, ks, kb.P1, kb.P2, kb.stride);
+            if (kb.sched && b.box) go<K, true, true>(b, r, v, rh, t, ks, kb, s);
+            else if (kb.sched) go<K, true, false>(b, r, v, rh, t, ks, kb, s);
+            else if (b.box) go<K, false, true>(b, r, v, rh, t, ks, kb, s);
+            else go<K, false, false>(b, r, v, rh, t, ks, kb, s);
             return hipGetLastError();
         }
     };
 };
 template <typename T> struct RunK1F {
+    template <int K, bool SCHED, bool BND>
+    static void go(const Batch &b, const T *rin, const T *t, const T *rh, const T *pin,
+                   const T *vin, T *pout, T *vout, T *r, T *d, KrylovState *ks,
+                   const KrylovBufs &kb, hipStream_t s) {
+        KLAUNCH((k_bicg_k1f<K, T, SCHED, BND>), dim3(b.nbf), dim3(kFaceThreads), 0, s, b, rin,
+                t, rh, pin, vin, pout, vout, r, d, ks, kb.P2, kb.P1, kb.stride);
+    }
     template <int K> struct F {
         static hipError_t run(const Batch &b, const T *rin, const T *t, const T *rh,
                               const T *pin, const T *vin, T *pout, T *vout, T *r, T *d,
                               KrylovState *ks, const KrylovBufs &kb, hipStream_t s) {
-            if (kb.sched)
-                KLAUNCH((k_bicg_k1f<K, T, true>), dim3(b.nbf), dim3(kFaceThreads),
-                                   0, s, b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
-                                   kb.P1, kb.stride);
+            if (kb.sched && b.box)
+                go<K, true, true>(b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb, s);
+            else if (kb.sched)
+                go<K, true, false>(b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb, s);
+            else if (b.box)
+                go<K, false, true>(b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb, s);
             else
-                KLAUNCH((k_bicg_k1f<K, T, false>), dim3(b.nbf), dim3(kFaceThreads),
-                                   0, s, b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb.P2,
-                                   kb.P1, kb.stride);
+                go<K, false, false>(b, rin, t, rh, pin, vin, pout, vout, r, d, ks, kb, s);
             return hipGetLastError();
         }
     };
@@ -2930,14 +3101,25 @@ int state_in_blocks(int nel, int K, int cap) {
 
 hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, double H,
                            int nel, int K, double *dst, double *partials, int blocks,
-                           hipStream_t s) {
+                           hipStream_t s, int bx, int nxp) {
     const double phiB = g * H;
     if (f32)
         KLAUNCH(k_state_in<float>, dim3(blocks), dim3(256), 0, s, (const float *)src,
-                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks);
+                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks, bx, nxp);
     else
         KLAUNCH(k_state_in<double>, dim3(blocks), dim3(256), 0, s, (const double *)src,
-                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks);
+                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks, bx, nxp);
+    return hipGetLastError();
+}
+
+hipError_t launch_put(double *p, double v, hipStream_t s) {
+    KLAUNCH(k_put_f64, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_bc_fill(const Geom &g, const Batch &b, double *q, const double *tstep,
+                          double toff, double *tnext, const Vortex &vx, hipStream_t s) {
+    KLAUNCH(k_bc_fill, dim3(b.nbv), dim3(64 * g.K), 0, s, q, g, b, tstep, toff, tnext, vx);
     return hipGetLastError();
 }
 

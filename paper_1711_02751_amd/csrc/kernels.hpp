@@ -23,6 +23,7 @@ struct Geom {
     double phiB, tau;           // phi_B, sqrt(phi_B)
     double winv0, winvk;        // 1/w_0, 1/w_k
     double w[kMaxK];            // LGL weights
+    double xi[kMaxK];           // LGL nodes on [-1, 1]
     double Dw[kMaxK * kMaxK];   // Dw[m*K + a] = w_m D[m][a] / w_a (weak derivative)
 };
 
@@ -43,12 +44,27 @@ struct Member {
     const double *Ainv, *W, *G, *Gh, *Px, *Py;
     const float *Ghf;                            // FP32 Ghat fragments
     const void *Alp;    // A^-1 as FP32 or BF16 fragments of the reduced-precision local solve
+    // Bounded rectangle (bx > 0): bx x by elements padded by two ghost
+    // columns and rows (nx = bx + 2, ny = by + 2).  Ghost column bx lies east
+    // of the domain, bx + 1 west of it (the periodic wrap of the padded grid
+    // makes it column 0's west neighbour); ghost rows by (north) and by + 1
+    // (south) likewise.  x-face (i, j) is the west face of element (i, j):
+    // a boundary face at i = 0 (W) and i = bx (E) for j < by; y-faces (i, 0)
+    // (S) and (i, by) (N) for i < bx; the faces between ghosts are not
+    // unknowns and hold zero.  A boundary row of the trace system has one
+    // element and the imaginary neighbour: its self block lacks the ghost
+    // side's C A^-1 B term, and dG / dGh / dGhf hold that difference for the
+    // four sides [W, E, S, N] as one slot of G / Ghat fragments each.
+    int bx, by;
+    const double *dG, *dGh;
+    const float *dGhf;
 };
 
 struct Batch {
     const Member *m;            // device array of nm members
     int nm;
     int nbv, nbf, nbe, nbd;     // blocks per class over all members
+    int box;                    // 1: a bounded member (the face kernels' bounded variant)
 };
 
 // Largest face or elementwise grid of one member, and the default caps.
@@ -203,7 +219,24 @@ IMEXHDG_REFINE_DECLS(double)
 IMEXHDG_REFINE_DECLS(float)
 #undef IMEXHDG_REFINE_DECLS
 
+// Boundary states of a bounded member (bx > 0) into its ghost elements of
+// the volume array q: the exact translating vortex of eq. tc_vortex_ic
+// (Sec. 6.1) at time tstep[0] dt + toff, evaluated at the boundary point
+// each ghost node faces (ghost column bx: x = Lx at the node's y; column
+// bx + 1: x = 0; row by: y = Ly; row by + 1: y = 0; corner ghosts zero).
+// tstep[0] is the step count of the state (an integer held as a double);
+// with tnext != nullptr the kernel also writes tnext[0] = tstep[0] + 1.
+struct Vortex {
+    double H, g, uinf, vinf, beta, xc, yc;
+};
+hipError_t launch_bc_fill(const Geom &g, const Batch &b, double *q, const double *tstep,
+                          double toff, double *tnext, const Vortex &vx, hipStream_t s);
+// p[0] = v (one thread; stream ordered, so a host value can be placed
+// between kernels without a copy from host memory).
+hipError_t launch_put(double *p, double v, hipStream_t s);
+
 // partials [5][diag blocks]: mass of phi_eta, U, V; energy; non-finite count
+// (bounded members: over the real elements only)
 hipError_t launch_diag(const Geom &g, const Batch &b, const double *q, double *partials,
                        int stride, hipStream_t s);
 
@@ -222,11 +255,13 @@ hipError_t launch_zero(void *p, size_t n32, hipStream_t s);
 // FP64 or, with f32, FP32; variable-major, each variable in the host state
 // ordering [e][j K + i]) into the volume device layout at dst, converting
 // depth variables (h, hu, hv) to (phi_eta, U, V) when `depth` is set.
-// partials [1][blocks]: per block, the count of nodes that are not finite,
-// not of positive depth or supercritical (|u| >= sqrt(phi)).
+// partials [1][blocks]: per block, the count of nodes that are not finite
+// or not of positive depth.
+// bx > 0 (bounded member): src holds the bx x (nel / bx) real elements and
+// dst is the padded layout with nxp = bx + 2 elements per row.
 hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, double H,
                            int nel, int K, double *dst, double *partials, int blocks,
-                           hipStream_t s);
+                           hipStream_t s, int bx = 0, int nxp = 0);
 // Blocks launch_state_in uses for nel elements of degree K - 1 (at most cap).
 int state_in_blocks(int nel, int K, int cap);
 

@@ -22,6 +22,7 @@ LAUNCH_GRAPH, LAUNCH_HOST = 0, 1
 GUESS_EXTRAPOLATE, GUESS_LAST = 0, 1
 VARS_DEPTH, VARS_GEOPOTENTIAL = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
+BOUNDARY_PERIODIC, BOUNDARY_VORTEX = 0, 1
 PHASES = ["explicit", "condense", "trace", "recover", "other"]
 
 EXPORTS = [
@@ -60,6 +61,8 @@ class Config(ctypes.Structure):
         ("refine_rtol", ctypes.c_double), ("refine_max", ctypes.c_int32),
         ("launch", ctypes.c_int32), ("trace_guess", ctypes.c_int32),
         ("local_sweeps", ctypes.c_int32),
+        ("boundary", ctypes.c_int32),
+        ("vortex", ctypes.c_double * 5),
     ]
 
 
@@ -183,6 +186,8 @@ def default_config(**kw):
     for k, v in kw.items():
         if not hasattr(cfg, k):
             raise TypeError(f"unknown config field {k}")
+        if k == "vortex":
+            v = (ctypes.c_double * 5)(*[float(a) for a in v])
         setattr(cfg, k, v)
     return cfg
 
@@ -225,7 +230,9 @@ class Solver:
         _check(self.lib.imexhdg_sizes(self._ctx, ctypes.byref(nn), ctypes.byref(nt)))
         self.n_nodes, self.n_trace = nn.value, nt.value
         self.K = self.cfg.degree + 1
-        self.nel = self.cfg.nx * self.cfg.ny
+        # elements of the device layout (a bounded mesh is padded by two ghost
+        # columns and rows)
+        self.nel = self.n_trace // (6 * self.K)
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:

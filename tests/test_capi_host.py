@@ -41,13 +41,31 @@ def test_validation_errors_are_host_only():
            dict(krylov_rtol=0.0), dict(refine_rtol=2.0), dict(krylov_max_iter=0),
            dict(check_every=0), dict(precision=9), dict(launch=5),
            dict(trace_guess=2), dict(local_sweeps=4), dict(local_sweeps=-1),
-           dict(precision=2, local_sweeps=3)]
+           dict(precision=2, local_sweeps=3), dict(boundary=2), dict(boundary=-1),
+           dict(boundary=1, vortex=(1.0, 0.0, float("nan"), 0.0, 0.0))]
     for kw in bad:
         base = dict(nx=4, ny=3, degree=3, dt=0.01)
         base.update(kw)
         cfg = m.default_config(**base)
         assert m.validate(cfg) == m.E_INVAL, kw
         assert m.load().imexhdg_last_error().decode() != ""
+
+
+def test_bounded_mesh_sizes_and_ensembles():
+    """A bounded mesh's device arrays hold two ghost columns and rows;
+    ensembles take periodic members only."""
+    import ctypes
+    from paper_1711_02751_amd import imexhdg as m
+    per = m.default_config(nx=30, ny=30, degree=3)
+    bnd = m.default_config(nx=28, ny=28, degree=3, boundary=m.BOUNDARY_VORTEX)
+    assert m.validate(bnd) == m.OK
+    a, b = m.workspace_bytes(per), m.workspace_bytes(bnd)
+    assert abs(a - b) < 0.01 * a
+    cfgs = (m.Config * 2)(bnd, bnd)
+    n = ctypes.c_size_t(0)
+    assert m.load().imexhdg_ens_workspace_bytes(cfgs, 2, ctypes.byref(n)) == m.E_INVAL
+    cfgs = (m.Config * 2)(per, per)
+    assert m.load().imexhdg_ens_workspace_bytes(cfgs, 2, ctypes.byref(n)) == m.OK
 
 
 def test_workspace_bytes_scales_with_mesh():

@@ -143,7 +143,7 @@ def test_error_paths():
     assert e.value.code == m.E_STATE
     n = S.n_nodes
     with pytest.raises(m.ImexError) as e:
-        S.set_state(np.full(n, 1.0), np.full(n, 5.0), np.zeros(n))   # |u| = 5 > sqrt(g h)
+        S.set_state(np.full(n, -0.5), np.zeros(n), np.zeros(n))     # h <= 0
     assert e.value.code == m.E_INVAL
     with pytest.raises(m.ImexError) as e:
         S.set_state(np.full(n, np.nan), np.zeros(n), np.zeros(n))

@@ -1,0 +1,133 @@
+"""Bounded rectangle with the exact translating vortex as boundary data
+(IMEXHDG_BOUNDARY_VORTEX; Sec. 6.1, eq. tc_vortex_ic; boundary faces with an
+imaginary neighbour as in Sec. 4.3), through the C ABI, against the oracle
+(oracle/box.py):
+
+  * whole ARS3 steps on square, non-square, ragged-tile and one-element-wide
+    meshes, host-driven and on the captured schedule, every node within
+    1e-11 of the oracle (FP64) and 1e-8 (MIXED: FP32 inner Krylov solve);
+  * the state and node round trip over the mesh's own elements;
+  * the moving-vortex errors of Tables 1 and 2 at T = 2 on every mesh and
+    degree the paper prints (4x4 ... 32x32, p = 2 ... 5), against the
+    printed digits and against the oracle's stored values;
+  * the calls that take periodic meshes only reject a bounded one.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import box
+from paper_1711_02751_amd import imexhdg as m
+from test_oracle_box import DT, G, H_INF, read_tables, vortex_state
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def make_box(nx, ny, k, dt, Ly=4.0, **kw):
+    cfg = m.default_config(nx=nx, ny=ny, Lx=4.0, Ly=Ly, degree=k, g=G, H=H_INF, dt=dt,
+                           scheme=m.SCHEME_ARS443, physics=m.PHYSICS_NONLINEAR,
+                           boundary=m.BOUNDARY_VORTEX, vortex=(1.0, 0.0, 5.0, 2.0, 2.0), **kw)
+    S = m.Solver(cfg)
+    P = box.BoxProblem(nx, ny, 4.0, Ly, k, G, H_INF, dt, vortex_state)
+    return P, S
+
+
+def start(P, S):
+    x, y = P.mesh.coords()
+    q0 = vortex_state(x, y, 0.0)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    return q0
+
+
+def state(S, P):
+    return np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)).reshape(P.mesh.shape)
+
+
+def rel_max(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("nx,ny,k,Ly,launch,steps", [
+    (8, 8, 3, 4.0, m.LAUNCH_HOST, 4),
+    (8, 8, 3, 4.0, m.LAUNCH_GRAPH, 12),
+    (21, 6, 2, 2.5, m.LAUNCH_GRAPH, 8),     # ragged 16 x 4 tiles, non-square elements
+    (5, 17, 4, 4.0, m.LAUNCH_HOST, 3),
+    (1, 3, 2, 3.0, m.LAUNCH_HOST, 3),       # one element wide
+    (4, 4, 5, 4.0, m.LAUNCH_GRAPH, 6),
+])
+def test_vortex_steps_match_oracle(nx, ny, k, Ly, launch, steps):
+    print(f"vortex steps {nx}x{ny} k={k} launch={launch} steps={steps}", flush=True)
+    P, S = make_box(nx, ny, k, DT.get(k, 0.005), Ly=Ly, launch=launch)
+    q0 = start(P, S)
+    got0 = state(S, P)
+    assert np.array_equal(got0, q0)
+    S.step(steps)
+    ref = P.run(q0, steps)
+    err = rel_max(state(S, P), ref)
+    print("  rel max err", err, "diag", S.diag()["graph_steps"], flush=True)
+    assert err < 1e-11
+    d = S.diag()
+    assert d["steps"] == steps and d["nonfinite"] == 0
+
+
+def test_vortex_mixed_precision_matches_oracle():
+    P, S = make_box(8, 8, 3, DT[3], precision=m.PREC_MIXED, krylov_rtol=1e-6,
+                    refine_rtol=1e-9, refine_max=8)
+    q0 = start(P, S)
+    S.step(12)
+    err = rel_max(state(S, P), P.run(q0, 12))
+    print("mixed rel max err", err, flush=True)
+    assert err < 1e-8
+
+
+def test_vortex_nodes_are_the_oracle_nodes():
+    P, S = make_box(6, 3, 3, DT[3], Ly=2.0)
+    x, y = S.nodes()
+    xo, yo = P.mesh.coords()
+    assert np.abs(x - xo.ravel()).max() < 1e-14 and np.abs(y - yo.ravel()).max() < 1e-14
+
+
+def test_operator_level_calls_reject_a_bounded_mesh():
+    P, S = make_box(4, 4, 2, DT[2])
+    start(P, S)
+    lib = m.load()
+    d = torch.zeros(3 * (S.nel * S.K * S.K), dtype=torch.float64, device=S.device)
+    assert lib.imexhdg_nl_residual(S._ctx, m._ptr(d), m._ptr(d)) == m.E_INVAL
+
+
+def _oracle_tables():
+    path = os.path.join(HERE, "golden", "vortex_oracle_tables.txt")
+    return read_tables("vortex_oracle_tables.txt") if os.path.exists(path) else None
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_vortex_tables_on_the_gpu(p):
+    """Every mesh of Tables 1 and 2 for degree p, T = 2 on the captured
+    schedule in FP64: the oracle's stored errors to 1e-6 and the printed
+    errors to 1% (L_inf of eta aside, as in the oracle's test; which meshes
+    agree with the print to its four digits is pinned on the oracle)."""
+    paper = read_tables("vortex_tables.txt")
+    mine = _oracle_tables()
+    for n in (4, 8, 16, 32):
+        print(f"vortex table p={p} n={n}", flush=True)
+        P, S = make_box(n, n, p, DT[p])
+        start(P, S)
+        steps = int(round(2.0 / DT[p]))
+        S.step(steps)
+        x, y = P.mesh.coords()
+        e = box.error_norms(P.mesh, state(S, P), vortex_state(x, y, steps * DT[p]), G, H_INF)
+        d = S.diag()
+        print("  ", {c: f"{e[c]:.4e}" for c in e}, "graph steps", d["graph_steps"],
+              "redone", d["redo_steps"], flush=True)
+        for c in ("eta_L1", "eta_L2", "u_L2", "v_L2", "sqrtE"):
+            assert abs(e[c] - paper[(p, n)][c]) <= 1e-2 * paper[(p, n)][c], (n, c)
+            if mine is not None:
+                assert abs(e[c] - mine[(p, n)][c]) <= 1e-6 * mine[(p, n)][c], (n, c)
+        if mine is not None:
+            assert abs(e["eta_Linf_nodes"] - mine[(p, n)]["eta_Linf"]) <= \
+                1e-6 * mine[(p, n)]["eta_Linf"]
+        S.close()
