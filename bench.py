@@ -405,6 +405,98 @@ def run_large(m, wl, steps, warmup, tune_cache=TUNE_CACHE):
             "note": f"mixed vs FP64 after the same {steps} + 1 steps from the initial state"}
 
 
+# Moving vortex of Sec. 6.1 (eq. tc_vortex_ic) on [0, 4]^2 (the paper's
+# [-2, 2]^2 translated, centre (2, 2)): H_inf = 1, (u_inf, v_inf) = (1, 0),
+# beta = 5, g = 2, exact solution as boundary data, ARS3, dt per degree,
+# errors at T = 2.  Printed errors (Tables 1 and 2): L1 and L2 of eta, L2 of
+# u and v, sqrt(E).
+VORTEX_DT = {2: 0.005, 3: 0.0025, 4: 0.00125, 5: 0.000625}
+VORTEX_PAPER = {
+    (2, 4): (2.036e-01, 8.189e-02, 1.654e-01, 2.277e-01, 2.072e-01),
+    (2, 8): (4.455e-02, 1.693e-02, 4.993e-02, 4.260e-02, 4.793e-02),
+    (2, 16): (6.561e-03, 2.793e-03, 1.196e-02, 5.513e-03, 9.517e-03),
+    (2, 32): (1.057e-03, 5.412e-04, 2.534e-03, 9.236e-04, 1.945e-03),
+    (3, 4): (8.991e-02, 3.645e-02, 1.665e-01, 8.503e-02, 1.347e-01),
+    (3, 8): (1.001e-02, 4.226e-03, 9.142e-03, 5.988e-03, 8.285e-03),
+    (3, 16): (1.139e-03, 5.864e-04, 9.278e-04, 7.128e-04, 9.254e-04),
+    (3, 32): (6.117e-05, 3.228e-05, 5.166e-05, 4.479e-05, 5.347e-05),
+    (4, 4): (1.999e-02, 8.123e-03, 1.734e-02, 1.707e-02, 1.814e-02),
+    (4, 8): (1.287e-03, 5.723e-04, 1.199e-03, 1.092e-03, 1.216e-03),
+    (4, 16): (5.053e-05, 2.705e-05, 5.942e-05, 3.699e-05, 5.306e-05),
+    (4, 32): (2.244e-06, 1.467e-06, 3.593e-06, 1.660e-06, 2.985e-06),
+    (5, 4): (7.790e-03, 3.015e-03, 1.403e-02, 6.759e-03, 1.121e-02),
+    (5, 8): (2.856e-04, 1.408e-04, 2.666e-04, 1.623e-04, 2.421e-04),
+    (5, 16): (6.040e-06, 3.378e-06, 5.734e-06, 3.357e-06, 5.270e-06),
+    (5, 32): (6.822e-08, 4.193e-08, 6.808e-08, 4.744e-08, 6.574e-08),
+}
+VORTEX_ERR = ("eta_L1", "eta_L2", "u_L2", "v_L2", "sqrtE")
+
+
+def vortex_state(x, y, t):
+    from paper_1711_02751_amd import workloads as W
+    h, hu, hv = W.moving_vortex(x, y, t, xc=2.0, yc=2.0, g=2.0)
+    return np.stack([2.0 * (h - 1.0), 2.0 * hu, 2.0 * hv])
+
+
+def vortex_errors(q, qe, n, k):
+    """The error norms of Sec. 6.1 with LGL quadrature: L1, L2 of eta =
+    phi_eta / g, L2 of u = U / phi and v, sqrt((||eta||^2 + ||u||^2) / 2)."""
+    w = lgl_weights(k)
+    K = k + 1
+    area = (4.0 / n) ** 2 / 4.0
+    wn = np.tile(np.outer(w, w).ravel(), q.shape[1] // (K * K)) * area
+    g, phiB = 2.0, 2.0
+    de = (q[0] - qe[0]) / g
+    du = q[1] / (q[0] + phiB) - qe[1] / (qe[0] + phiB)
+    dv = q[2] / (q[0] + phiB) - qe[2] / (qe[0] + phiB)
+    l2 = math.sqrt(np.sum(wn * de * de))
+    eu, ev = math.sqrt(np.sum(wn * du * du)), math.sqrt(np.sum(wn * dv * dv))
+    return (float(np.sum(wn * np.abs(de))), l2, eu, ev,
+            math.sqrt(0.5 * (l2 * l2 + eu * eu + ev * ev)))
+
+
+def run_vortex(m, warm=20):
+    """Every mesh and degree of Tables 1 and 2 to T = 2 on one GPU (FP64,
+    captured schedule): the errors beside the printed ones, and the step
+    rate after `warm` steps (schedule learning and capture)."""
+    import torch
+    rows = []
+    for (p, n) in sorted(VORTEX_PAPER):
+        dt = VORTEX_DT[p]
+        steps = int(round(2.0 / dt))
+        cfg = m.default_config(nx=n, ny=n, Lx=4.0, Ly=4.0, degree=p, g=2.0, H=1.0, dt=dt,
+                               scheme=m.SCHEME_ARS443, physics=m.PHYSICS_NONLINEAR,
+                               boundary=m.BOUNDARY_VORTEX, vortex=(1.0, 0.0, 5.0, 2.0, 2.0))
+        S = m.Solver(cfg)
+        x, y = S.nodes()
+        S.set_state(*vortex_state(x, y, 0.0), vars=m.VARS_GEOPOTENTIAL)
+        S.step(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(steps - warm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        q = np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL))
+        e = vortex_errors(q, vortex_state(x, y, steps * dt), n, p)
+        d = S.diag()
+        ndof = 3 * n * n * (p + 1) ** 2
+        rows.append({"p": p, "mesh": f"{n}x{n}", "steps": steps, "dt": dt,
+                     "ms_per_step": 1e3 * el / (steps - warm),
+                     "dof_updates_per_s": ndof * (steps - warm) / el,
+                     "errors": dict(zip(VORTEX_ERR, e)),
+                     "paper": dict(zip(VORTEX_ERR, VORTEX_PAPER[(p, n)])),
+                     "max_rel_dev_from_paper": max(abs(a - b) / b for a, b in
+                                                   zip(e, VORTEX_PAPER[(p, n)])),
+                     "krylov_iters_per_stage": d["krylov_iters"] / max(d["stage_solves"], 1),
+                     "graph_steps": d["graph_steps"], "redone_steps": d["redo_steps"]})
+        log(f"[bench] vortex p={p} {n}x{n}: {rows[-1]['ms_per_step']:.3f} ms/step, "
+            f"L2(eta) {e[1]:.4e} (paper {VORTEX_PAPER[(p, n)][1]:.4e})")
+        S.close()
+        del S
+    return {"workload": "moving vortex, Sec. 6.1 (Tables 1-2), ARS3, FP64, exact-solution "
+                        "boundary data", "T": 2.0, "cases": rows}
+
+
 def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
     """The 64-member ensemble (meshes 32^2 ... 128^2, k = 3, dt_m = 2 dx_min):
     every launch covers all members, one graph launch per step."""
@@ -475,6 +567,10 @@ def main():
                     help="second workload measured beside the headline one (both paths)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-workload measurement")
+    ap.add_argument("--vortex-only", action="store_true",
+                    help="run only the moving-vortex tables and print their JSON")
+    ap.add_argument("--no-vortex", action="store_true",
+                    help="skip the moving-vortex tables (bounded mesh, Sec. 6.1)")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the FP32 / BF16 precision modes")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -493,6 +589,9 @@ def main():
 
     wl = W.WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.vortex_only:
+        print(json.dumps({"vortex": run_vortex(m)}))
+        return
     if args.calib_copy_mib > 0:
         # one plain elementwise pass over a known size: its FETCH_SIZE and
         # WRITE_SIZE counters scale the others to bytes
@@ -571,6 +670,8 @@ def main():
     if not args.no_large and args.large_workload != wl.name:
         out["large"] = run_large(m, W.WORKLOADS[args.large_workload], args.steps, args.warmup,
                                  args.tune_cache)
+    if not args.no_vortex:
+        out["vortex"] = run_vortex(m)
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(m, args.steps, args.warmup,
                                        mixed=args.precision == "mixed",
