@@ -50,6 +50,22 @@ def exterior_states(mesh, state_fn, t):
             for s, (px, py) in boundary_points(mesh).items()}
 
 
+def reflect_exterior(mesh, q):
+    """The imaginary neighbour of a wall (Sec. 4.3, eq. reflection): at every
+    boundary face node phi+ = phi- and U+ = U- - 2 (U- . n) n, i.e. the
+    normal momentum changes sign.  Shaped like ext."""
+    k = mesh.k
+    e = q[:, :, -1, :, k].copy()
+    w = q[:, :, 0, :, 0].copy()
+    n = q[:, -1, :, k, :].copy()
+    s = q[:, 0, :, 0, :].copy()
+    e[1] *= -1.0
+    w[1] *= -1.0
+    n[2] *= -1.0
+    s[2] *= -1.0
+    return {'W': w, 'E': e, 'S': s, 'N': n}
+
+
 def zero_exterior(mesh):
     K = mesh.K
     return {'W': np.zeros((3, mesh.ny, K)), 'E': np.zeros((3, mesh.ny, K)),
@@ -130,6 +146,30 @@ def assemble_linear(mesh, phi_B):
     return L.tocsr()
 
 
+def assemble_wall(mesh, phi_B):
+    """Sparse matrix of q -> M^-1 L_DG(q) with walls on all four sides: the
+    open-grid operator plus q -> L_DG(0; reflect_exterior(q)).  The latter
+    maps an element's own face nodes to its own residual, so it is block
+    diagonal; its blocks are read off by applying it to one local unit
+    vector in every element at once."""
+    K = mesh.K
+    nloc = 3 * K * K
+    nel = mesh.nx * mesh.ny
+    rows, cols, vals = [], [], []
+    for d in range(nloc):
+        e = np.zeros((mesh.ny, mesh.nx, nloc))
+        e[:, :, d] = 1.0
+        q = e.reshape(mesh.ny, mesh.nx, 3, K, K).transpose(2, 0, 1, 3, 4)
+        out = linear_residual(mesh, np.zeros(mesh.shape), phi_B, reflect_exterior(mesh, q))
+        o = out.transpose(1, 2, 0, 3, 4).reshape(nel, nloc)
+        r, c = np.nonzero(o)
+        rows.extend(r * nloc + c)
+        cols.extend(r * nloc + d)
+        vals.extend(o[r, c])
+    B = sp.csr_matrix((vals, (rows, cols)), shape=(nel * nloc, nel * nloc))
+    return (assemble_linear(mesh, phi_B) + B).tocsr()
+
+
 def hdg_trace(mesh, q, phi_B, ext):
     """HDG trace on every face of the bounded grid (closed form of the
     conservation condition, with the imaginary neighbour's state on the
@@ -153,10 +193,14 @@ def hdg_trace(mesh, q, phi_B, ext):
 class BoxProblem:
     """Planar SWE with flat bottom phi_B = g H on the bounded rectangle
     [0, Lx] x [0, Ly], boundary states from `state_fn(x, y, t)` (in
-    (phi_eta, U, V)) at the stage times.  The step is Algorithm 1 with
-    the implicit stage system of `imex.Problem`, now affine in Q:
+    (phi_eta, U, V)) at the stage times, or walls on all four sides with
+    state_fn = "wall".  The step is Algorithm 1 with the implicit stage
+    system of `imex.Problem`, now affine in Q:
         (I - dt a~_ii L) Q_i = Res0_i + dt a~_ii L_DG(0; ext(t_i)),
-    t_i = t_n + c~_i dt (c = c~ for the ARS schemes); NL_i uses ext(t_i)."""
+    t_i = t_n + c~_i dt (c = c~ for the ARS schemes); NL_i uses ext(t_i).
+    With walls the imaginary neighbour reflects the element's own state, so
+    L is linear (the reflection is part of the matrix, no data term) and
+    NL_i takes the reflection of Q_i."""
 
     def __init__(self, nx, ny, Lx, Ly, k, g, H, dt, state_fn, tableau=None,
                  nonlinear=True):
@@ -169,7 +213,9 @@ class BoxProblem:
         if not np.allclose(self.tab.c, self.tab.ct):
             raise ValueError("boundary data at the stage times needs c = c~")
         self.nonlinear = bool(nonlinear)
-        self.Lmat = assemble_linear(self.mesh, self.phi_B)
+        self.wall = isinstance(state_fn, str) and state_fn == "wall"
+        self.Lmat = (assemble_wall(self.mesh, self.phi_B) if self.wall
+                     else assemble_linear(self.mesh, self.phi_B))
         diag = np.unique(np.diag(self.tab.At)[np.diag(self.tab.At) != 0])
         if len(diag) != 1:
             raise ValueError("oracle stage solve expects an SDIRK tableau")
@@ -179,7 +225,14 @@ class BoxProblem:
         self.lu = spla.splu(stage.tocsc())
 
     def ext(self, t):
+        """Boundary data at time t (None with walls: no data)."""
+        if self.wall:
+            return None
         return exterior_states(self.mesh, self.state_fn, t)
+
+    def exterior(self, q, t):
+        """The imaginary neighbours' states for the state q at time t."""
+        return reflect_exterior(self.mesh, q) if self.wall else self.ext(t)
 
     def NL(self, q, ext):
         if not self.nonlinear:
@@ -188,6 +241,8 @@ class BoxProblem:
 
     def data(self, ext):
         """L_DG(0; ext): the boundary data's part of the linear residual."""
+        if ext is None:
+            return np.zeros(self.mesh.shape)
         return linear_residual(self.mesh, np.zeros(self.mesh.shape), self.phi_B, ext)
 
     def L(self, q, ext):
@@ -201,7 +256,8 @@ class BoxProblem:
         tab, dt = self.tab, self.dt
         NLs, Ls = [], []
         for i in range(tab.s):
-            ext = self.ext(t + tab.c[i] * dt)
+            ti = t + tab.c[i] * dt
+            ext = self.ext(ti)
             if tab.At[i, i] == 0.0:
                 if i != 0:
                     raise ValueError("explicit-only stage after the first")
@@ -212,9 +268,9 @@ class BoxProblem:
                     res0 += dt * (tab.A[i, j] * NLs[j] + tab.At[i, j] * Ls[j])
                 Q = self.stage_solve(res0, ext)
             Ls.append(self.L(Q, ext))
-            NLs.append(self.NL(Q, ext))
+            NLs.append(self.NL(Q, self.exterior(Q, ti)))
             if record is not None:
-                qx, qy = hdg_trace(self.mesh, Q, self.phi_B, ext)
+                qx, qy = hdg_trace(self.mesh, Q, self.phi_B, self.exterior(Q, ti))
                 record.append(dict(Q=Q, qhat_x=qx, qhat_y=qy, NL=NLs[-1], L=Ls[-1]))
         qn1 = qn.copy()
         for i in range(tab.s):
@@ -260,6 +316,8 @@ class DenseHDGBox:
     the DG-LF stage solve on tiny meshes."""
 
     def __init__(self, mesh, phi_B, dt_aii, ext):
+        """ext: boundary data, or "wall" (the neighbour reflects the
+        element's own face values, eq. reflection)."""
         self.mesh, self.phi_B, self.c, self.ext = mesh, phi_B, float(dt_aii), ext
         ny, nx, K = mesh.ny, mesh.nx, mesh.K
         self.nQ = 3 * ny * nx * K * K
@@ -267,7 +325,7 @@ class DenseHDGBox:
         self.nY = 3 * (ny + 1) * nx * K
         n = self.nQ + self.nX + self.nY
         self.b0 = self._apply(np.zeros(n), ext)
-        zero = zero_exterior(mesh)
+        zero = ext if isinstance(ext, str) else zero_exterior(mesh)
         M = np.zeros((n, n))
         for col in range(n):
             x = np.zeros(n)
@@ -304,6 +362,8 @@ class DenseHDGBox:
     def _apply(self, x, ext):
         m, phi_B, k = self.mesh, self.phi_B, self.mesh.k
         Q, qx, qy = self.split(x)
+        if isinstance(ext, str):
+            ext = reflect_exterior(m, Q)
         r1 = Q - self.c * self._L(Q, qx, qy)
         # x-faces: the element on the right sees the face as its W edge
         # (n = (-1, 0)), the one on the left as its E edge (n = (1, 0));

@@ -169,3 +169,15 @@ def moving_vortex(x, y, t, H_inf=1.0, u_inf=1.0, v_inf=0.0, beta=5.0,
     u = u_inf - beta / (2.0 * math.pi) * e * yt
     v = v_inf + beta / (2.0 * math.pi) * e * xt
     return h, h * u, h * v
+
+
+def water_drop(x, y, H_inf=100.0, sigma=0.1, xc=1.0, yc=1.0):
+    """Water-height perturbation of Sec. 6.2 on [0, 2]^2 (the paper's
+    [-1, 1]^2 translated, centre (1, 1)): depth H_inf + exp(-r^2 / (2
+    sigma^2)), r the distance to the centre, at rest.  The paper does not
+    print sigma; 0.1 is the reading taken (a bump resolved by the 20 x 20,
+    degree-8 mesh: about 9 nodes across one sigma).  Returns (h, hu, hv)."""
+    r2 = (x - xc) ** 2 + (y - yc) ** 2
+    h = H_inf + np.exp(-r2 / (2.0 * sigma * sigma))
+    z = np.zeros_like(h)
+    return h, z, z.copy()
