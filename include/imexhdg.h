@@ -118,9 +118,16 @@ extern "C" {
  *             padded by two ghost columns and rows ((nx + 2) x (ny + 2)
  *             elements; the ghosts hold boundary states, faces between
  *             ghosts hold zero); those calls, ensembles and the
- *             allocation-free stage solve take periodic meshes only.     */
+ *             allocation-free stage solve take periodic meshes only.
+ *   WALL      bounded rectangle with reflecting walls on all four sides
+ *             (Sec. 4.3): the imaginary neighbour of a boundary face holds
+ *             the element's own state with the normal momentum reversed
+ *             (eq. reflection), in the explicit flux and in the
+ *             conservation condition, which yields eq. reflectionBC for
+ *             the trace.  Padded layout and restrictions as for VORTEX.  */
 #define IMEXHDG_BOUNDARY_PERIODIC 0
 #define IMEXHDG_BOUNDARY_VORTEX   1
+#define IMEXHDG_BOUNDARY_WALL     2
 
 /* element type of device state arrays (imexhdg_set_state_device)          */
 #define IMEXHDG_DTYPE_F64 0

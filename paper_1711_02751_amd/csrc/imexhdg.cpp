@@ -169,7 +169,7 @@ struct imexhdg_ctx {
     // tstep[a] is the step count of the state in qbuf[a] (device, so that
     // captured steps read it), tcur the ring position of the step being
     // enqueued, cst[i] the abscissa of stage i
-    bool box = false;
+    bool box = false, wall = false;
     Vortex vx{};
     double *tstep = nullptr;
     int tcur = 0;
@@ -226,62 +226,114 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Device mesh of a config: a bounded rectangle is padded by two ghost
 // columns and rows.
 void device_dims(const imexhdg_config &c, int &nx, int &ny) {
-    const int pad = c.boundary == IMEXHDG_BOUNDARY_VORTEX ? 2 : 0;
+    const int pad = c.boundary != IMEXHDG_BOUNDARY_PERIODIC ? 2 : 0;
     nx = c.nx + pad;
     ny = c.ny + pad;
 }
 
-// Boundary-row corrections (bounded meshes), one slot of fragments per side
-// [W, E, S, N]: frag[side][mb][kk][lane] = D_side[16 mb + lane % 16][4 kk +
-// lane / 16], KS = ceil(3K / 4) k steps, zero past 3K.
+// Boundary-row corrections (bounded meshes): per side [W, E, S, N] four
+// entries, one per local face of the side's real element (entry 0 its
+// boundary face, the self slot of the row), each a 3K x 3K matrix packed
+// like one slot of G: frag[4 side + e][mb][kk][lane] = D[16 mb + lane % 16]
+// [4 kk + lane / 16], KS = ceil(3K / 4) k steps, zero past 3K.
+constexpr int kSideEntries = 4;
 size_t side_frag_count(int K) {
     const int B3 = 3 * K, KS = (B3 + 3) / 4, NMB = (B3 + 15) / 16;
-    return (size_t)4 * NMB * KS * 64;
+    return (size_t)4 * kSideEntries * NMB * KS * 64;
 }
 
-std::vector<double> pack_sides(const std::vector<double> (&D)[4], int K) {
+std::vector<double> pack_sides(const std::vector<double> (&D)[4][kSideEntries], int K) {
     const int B3 = 3 * K, KS = (B3 + 3) / 4, NMB = (B3 + 15) / 16;
     std::vector<double> f(side_frag_count(K), 0.0);
     for (int sd = 0; sd < 4; ++sd)
-        for (int mb = 0; mb < NMB; ++mb)
-            for (int u = 0; u < KS; ++u)
-                for (int l = 0; l < 64; ++l) {
-                    const int row = 16 * mb + l % 16, col = 4 * u + l / 16;
-                    if (row < B3 && col < B3)
-                        f[(((size_t)sd * NMB + mb) * KS + u) * 64 + l] =
-                            D[sd][(size_t)row * B3 + col];
-                }
+        for (int e = 0; e < kSideEntries; ++e)
+            for (int mb = 0; mb < NMB; ++mb)
+                for (int u = 0; u < KS; ++u)
+                    for (int l = 0; l < 64; ++l) {
+                        const int row = 16 * mb + l % 16, col = 4 * u + l / 16;
+                        if (row < B3 && col < B3)
+                            f[((((size_t)sd * kSideEntries + e) * NMB + mb) * KS + u) * 64 + l] =
+                                D[sd][e][(size_t)row * B3 + col];
+                    }
     return f;
 }
 
 // A boundary face has one element and the imaginary neighbour (Sec. 4.3,
 // eqs. reflection / reflectionBC; the exact-solution data of Sec. 6.1 enter
-// the same way): its conservation condition keeps 2 tau I and the element's
-// C W, while the neighbour's part, C Z at its face nodes, is data (the
-// ghost element holds the exterior state there).  So the self block of a
-// boundary row is the interior one without the ghost side's C_K W_K at that
-// face: dG_side = -S(f, f), f the ghost's local face (W: the ghost lies
-// west, its east face 1; E: its west face 0; S: its north face 3; N: its
-// south face 2).  With the interior block-Jacobi inverse P^-1 kept as the
-// boundary rows' preconditioner, dGh_side = P^-1 dG_side.
-void boundary_deltas(const StageOperators &op, int K, std::vector<double> (&dG)[4],
-                     std::vector<double> (&dGh)[4]) {
-    const int B3 = 3 * K, NT = 12 * K;
+// the same way).  Its conservation condition keeps 2 tau I and the real
+// element's C W; the neighbour adds C_g Q_g at the face nodes, C_g Q =
+// F_L(Q) . n_g + tau Q with n_g = -n the neighbour's outward normal.
+//   * Exact-solution data: Q_g is data (the ghost element holds it there,
+//     so the right-hand side kernel adds C_g Q_g as for an interior face).
+//   * Wall: Q_g = R E Q, the reflection R of the real element's face values
+//     E Q, Q = Z - W qhat: the right-hand side gains C_g R E Z (the ghost
+//     holds R E Z) and the row gains + C_g R E W over the real element's
+//     four faces.
+// The interior row the face kernels apply has instead C_g' W_g' of the ghost
+// element at the face (its other faces hold zero), so every side's entry 0
+// (the self slot) removes it, -S(f_g, f_g) with f_g the ghost's local face
+// (W: the ghost lies west, its east face 1; E: 0; S: 3; N: 2), and with a
+// wall entries 0..3 add C_g R E W for the real element's faces in the order
+// side_faces below.  With the interior block-Jacobi inverse P^-1 kept as
+// the boundary rows' preconditioner, dGh = P^-1 dG.
+void boundary_deltas(const StageOperators &op, int K, bool wall,
+                     std::vector<double> (&dG)[4][kSideEntries],
+                     std::vector<double> (&dGh)[4][kSideEntries]) {
+    const int B3 = 3 * K, NT = 12 * K, k = K - 1;
     const int ghost_face[4] = {1, 0, 3, 2};
+    const int real_face[4] = {0, 1, 2, 3};   // the boundary face as a face of the real element
+    const double nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};   // its outward normal
+    // the real element's faces in entry order (entry 0: the boundary face)
+    const int side_faces[4][4] = {{0, 1, 2, 3}, {1, 0, 2, 3}, {2, 0, 1, 3}, {3, 0, 1, 2}};
+    auto face_node = [k](int f, int j, int &a, int &b) {
+        if (f == 0) { a = 0; b = j; }
+        else if (f == 1) { a = k; b = j; }
+        else if (f == 2) { a = j; b = 0; }
+        else { a = j; b = k; }
+    };
     for (int sd = 0; sd < 4; ++sd) {
-        const int f = ghost_face[sd];
-        dG[sd].assign((size_t)B3 * B3, 0.0);
+        for (int e = 0; e < kSideEntries; ++e) dG[sd][e].assign((size_t)B3 * B3, 0.0);
+        const int fg = ghost_face[sd];
         for (int r = 0; r < B3; ++r)
             for (int cc = 0; cc < B3; ++cc)
-                dG[sd][(size_t)r * B3 + cc] = -op.S[(size_t)(f * B3 + r) * NT + f * B3 + cc];
-        const std::vector<double> &P = sd < 2 ? op.Pxinv : op.Pyinv;
-        dGh[sd].assign((size_t)B3 * B3, 0.0);
-        for (int r = 0; r < B3; ++r)
-            for (int m = 0; m < B3; ++m) {
-                const double a = P[(size_t)r * B3 + m];
-                for (int cc = 0; cc < B3; ++cc)
-                    dGh[sd][(size_t)r * B3 + cc] += a * dG[sd][(size_t)m * B3 + cc];
+                dG[sd][0][(size_t)r * B3 + cc] = -op.S[(size_t)(fg * B3 + r) * NT + fg * B3 + cc];
+        if (wall) {
+            const double gx = -nrm[sd][0], gy = -nrm[sd][1];   // the neighbour's normal
+            const int refl = sd < 2 ? 1 : 2;                    // the normal momentum
+            for (int e = 0; e < kSideEntries; ++e) {
+                const int f = side_faces[sd][e];
+                for (int j = 0; j < K; ++j) {
+                    int a, b;
+                    face_node(real_face[sd], j, a, b);
+                    // R E W restricted to face f's traces: rows (c, j), cols (c', j')
+                    double rew[3][3 * kMaxK];
+                    for (int c = 0; c < 3; ++c)
+                        for (int col = 0; col < B3; ++col) {
+                            const int v = c * K * K + b * K + a;
+                            const double w = op.W[(size_t)v * NT + f * B3 + col];
+                            rew[c][col] = c == refl ? -w : w;
+                        }
+                    for (int col = 0; col < B3; ++col) {
+                        const double p = rew[0][col], U = rew[1][col], V = rew[2][col];
+                        const double cg[3] = {op.tau * p + gx * U + gy * V,
+                                              op.phiB * gx * p + op.tau * U,
+                                              op.phiB * gy * p + op.tau * V};
+                        for (int c = 0; c < 3; ++c)
+                            dG[sd][e][(size_t)(c * K + j) * B3 + col] += cg[c];
+                    }
+                }
             }
+        }
+        const std::vector<double> &P = sd < 2 ? op.Pxinv : op.Pyinv;
+        for (int e = 0; e < kSideEntries; ++e) {
+            dGh[sd][e].assign((size_t)B3 * B3, 0.0);
+            for (int r = 0; r < B3; ++r)
+                for (int m = 0; m < B3; ++m) {
+                    const double pv = P[(size_t)r * B3 + m];
+                    for (int cc = 0; cc < B3; ++cc)
+                        dGh[sd][e][(size_t)r * B3 + cc] += pv * dG[sd][e][(size_t)m * B3 + cc];
+                }
+        }
     }
 }
 
@@ -475,11 +527,14 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "unknown launch mode");
     if (c->trace_guess != IMEXHDG_GUESS_EXTRAPOLATE && c->trace_guess != IMEXHDG_GUESS_LAST)
         return fail(IMEXHDG_E_INVAL, "unknown trace guess");
-    if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC && c->boundary != IMEXHDG_BOUNDARY_VORTEX)
+    if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC && c->boundary != IMEXHDG_BOUNDARY_VORTEX &&
+        c->boundary != IMEXHDG_BOUNDARY_WALL)
         return fail(IMEXHDG_E_INVAL, "unknown boundary");
-    if (c->boundary == IMEXHDG_BOUNDARY_VORTEX) {
-        for (double v : c->vortex)
-            if (!std::isfinite(v)) return fail(IMEXHDG_E_INVAL, "vortex parameters must be finite");
+    if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC) {
+        if (c->boundary == IMEXHDG_BOUNDARY_VORTEX)
+            for (double v : c->vortex)
+                if (!std::isfinite(v))
+                    return fail(IMEXHDG_E_INVAL, "vortex parameters must be finite");
         if ((int64_t)(c->nx + 2) * (c->ny + 2) > (int64_t)1 << 28 ||
             (int64_t)6 * (c->degree + 1) * (c->nx + 2) * (c->ny + 2) >= ((int64_t)1 << 31))
             return fail(IMEXHDG_E_INVAL, "bounded mesh too large");
@@ -623,6 +678,7 @@ int build_batch(imexhdg_ctx *c) {
         d.area = (h.Lx / rx / 2.0) * (h.Ly / ry / 2.0);
         d.bx = h.bx;
         d.by = h.by;
+        d.bwall = c->wall ? 1 : 0;
         d.dG = o.dG;
         d.dGh = o.dGh;
         d.dGhf = o.dGhf;
@@ -1506,7 +1562,8 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         if (cf[0].boundary != IMEXHDG_BOUNDARY_PERIODIC && std::fabs(ce - ci) > 1e-14)
             return bail(fail(IMEXHDG_E_INVAL, "boundary data need equal stage abscissae"));
     }
-    c->box = cf[0].boundary == IMEXHDG_BOUNDARY_VORTEX;
+    c->box = cf[0].boundary != IMEXHDG_BOUNDARY_PERIODIC;
+    c->wall = cf[0].boundary == IMEXHDG_BOUNDARY_WALL;
     c->vx = Vortex{cf[0].H, cf[0].g, cf[0].vortex[0], cf[0].vortex[1], cf[0].vortex[2],
                    cf[0].vortex[3], cf[0].vortex[4]};
     Geom &g = c->geom;
@@ -1624,8 +1681,8 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
             up(os.Px, op.Pxinv) || up(os.Py, op.Pyinv) || hipStreamSynchronize(c->stream))
             return bail(fail(IMEXHDG_E_DEVICE, "upload of the element operators failed"));
         if (c->box) {
-            std::vector<double> dG[4], dGh[4];
-            boundary_deltas(op, K, dG, dGh);
+            std::vector<double> dG[4][kSideEntries], dGh[4][kSideEntries];
+            boundary_deltas(op, K, c->wall, dG, dGh);
             const std::vector<double> fG = pack_sides(dG, K), fGh = pack_sides(dGh, K);
             const std::vector<float> fGhf(fGh.begin(), fGh.end());
             if (up(os.dG, fG) || up(os.dGh, fGh) ||

@@ -134,7 +134,7 @@ __device__ __forceinline__ Member load_member(const Batch &bt, int i) {
     r.Ainv = c.Ainv; r.W = c.W; r.G = c.G; r.Gh = c.Gh; r.Px = c.Px; r.Py = c.Py;
     r.Ghf = c.Ghf;
     r.Alp = c.Alp;
-    r.bx = c.bx; r.by = c.by;
+    r.bx = c.bx; r.by = c.by; r.bwall = c.bwall;
     r.dG = c.dG; r.dGh = c.dGh; r.dGhf = c.dGhf;
     return r;
 }
@@ -1677,31 +1677,47 @@ __device__ __forceinline__ void tile_rows(const T *__restrict__ const *frags, co
     }
 }
 
-// Bounded mesh: a boundary row adds its side's correction of the self
-// block, applied to the lane's own face (slot 0 of the staged tile) where
-// the lane's face is on that side (the B operand is zero elsewhere).
+// Row-block slot of entry e of a boundary side's corrections (the real
+// element's faces, the boundary face first; see Member): W and S sides, the
+// real element is the face's plus element (slots of its west, east, south,
+// north faces); E and N, its minus element.
+__device__ __forceinline__ int side_slot(int side, int e) {
+    switch (side) {
+        case 0: return e;                       // W: x-face plus element
+        case 1: return e == 0 ? 0 : 3 + e;      // E: 0, 4, 5, 6
+        case 2: return e;                       // S: y-face plus element
+        default: return e == 0 ? 0 : e == 3 ? 4 : 4 + e;   // N: 0, 5, 6, 4
+    }
+}
+
+// Bounded mesh: a boundary row adds its side's corrections, each applied to
+// the staged face of its slot for the lanes whose face is on that side (the
+// B operand is zero for the other lanes): the self slot only with
+// exact-solution data, the real element's four faces with walls.
 template <int K, typename T>
-__device__ __forceinline__ void boundary_rows(const WaveFaces &wf, const T *sB,
+__device__ __forceinline__ void boundary_rows(const WaveFaces &wf, const T *sB, int nent,
                                               typename MfmaT<T>::v4 (&acc)[1][MF<K>::NMB]) {
     using TL = Tile<K>;
     constexpr int B3 = TL::B3, NF = TileRow<K, T>::stride, KS = MF<K>::KS, NMB = MF<K>::NMB;
     if (wf.dfr == nullptr) return;
     const int lane = threadIdx.x & 63, q = lane >> 4, lx = lane & 15;
     const T *dfr = (const T *)wf.dfr;
-    const int li = slot_lds(wf.set, 0, lx, wf.sub, TL::NX, TL::XC, TL::YC);
-#pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int side = 2 * wf.set + h;
         if (!__any(wf.bt == side)) continue;
+        for (int e = 0; e < nent; ++e) {
+            const int li = slot_lds(wf.set, side_slot(side, e), lx, wf.sub, TL::NX, TL::XC,
+                                    TL::YC);
 #pragma unroll
-        for (int u = 0; u < KS; ++u) {
-            const int cj = 4 * u + q;
-            const T bv = sB[(cj < B3 ? cj : B3 - 1) * NF + li];
-            const T b = wf.bt == side ? bv : T(0);
+            for (int u = 0; u < KS; ++u) {
+                const int cj = 4 * u + q;
+                const T bv = sB[(cj < B3 ? cj : B3 - 1) * NF + li];
+                const T b = wf.bt == side ? bv : T(0);
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
-                acc[0][mb] = MfmaT<T>::mma(dfr[frag_off(side, mb, u, lane, NMB, KS)], b,
-                                           acc[0][mb]);
+                for (int mb = 0; mb < NMB; ++mb)
+                    acc[0][mb] = MfmaT<T>::mma(dfr[frag_off(4 * side + e, mb, u, lane, NMB, KS)],
+                                               b, acc[0][mb]);
+            }
         }
     }
 }
@@ -1903,7 +1919,7 @@ __global__ __launch_bounds__(kFaceThreads, ResidOcc<K>::value) void k_trace_resi
             face_rows<K, 1>(fr, st, mb, wf, sB, src,
                             [](const double (&a)[1], uint32_t, bool) { return a[0]; },
                             acc, prefetch);
-            if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
+            if constexpr (BND) boundary_rows<K, T>(wf, sB, mb.bwall ? 4 : 1, acc);
             // r and g as B operands (zero past row 3K and off the mesh)
             double rb[NMB][4], gb[NMB][4];
 #pragma unroll
@@ -2103,7 +2119,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
                                        return p;
                                    },
                                    acc, prefetch);
-            if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
+            if constexpr (BND) boundary_rows<K, T>(wf, sB, mb.bwall ? 4 : 1, acc);
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
 #pragma unroll
@@ -2212,7 +2228,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
                             return a[0];
                         },
                         acc, prefetch);
-        if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
+        if constexpr (BND) boundary_rows<K, T>(wf, sB, mb.bwall ? 4 : 1, acc);
 #pragma unroll
         for (int m = 0; m < NMB; ++m)
 #pragma unroll
@@ -2343,7 +2359,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
                                        return s_of(a[0], al, a[1]);
                                    },
                                    acc, prefetch);
-            if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
+            if constexpr (BND) boundary_rows<K, T>(wf, sB, mb.bwall ? 4 : 1, acc);
             {
                 const int li = own_lds<K>(wf);
 #pragma unroll
@@ -2501,7 +2517,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                                     return pn;
                                 },
                                 acc, prefetch);
-                if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
+                if constexpr (BND) boundary_rows<K, T>(wf, sB, mb.bwall ? 4 : 1, acc);
                 const int li = own_lds<K>(wf);
 #pragma unroll
                 for (int m = 0; m < NMB; ++m)
@@ -2519,7 +2535,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
                                     return pnew(rnew(s_of(a[0], al, a[3]), a[1]), a[2], a[3]);
                                 },
                                 acc, prefetch);
-                if constexpr (BND) boundary_rows<K, T>(wf, sB, acc);
+                if constexpr (BND) boundary_rows<K, T>(wf, sB, mb.bwall ? 4 : 1, acc);
                 // own faces: all loads first, then the updates
                 T sv_[NMB][4], tv_[NMB][4], pv_[NMB][4], vv_[NMB][4], dv_[NMB][4];
 #pragma unroll
@@ -2650,6 +2666,33 @@ __global__ __launch_bounds__(64 * kMaxK) void k_bc_fill(double *__restrict__ q, 
     if (!gx && !gy) return;
     q += mb.vo;
     const size_t nel = mb.nel, NN = (size_t)K * K * nel;
+    if (mb.bwall) {
+        // the real element across the boundary face and its node on that
+        // face; the normal momentum (U across x-walls, V across y-walls)
+        // changes sign
+        for (int i = 0; i < K; ++i) {
+            double p = 0.0, U = 0.0, V = 0.0;
+            if (gx != gy) {
+                int se, sn;
+                if (gx) {
+                    se = ey * mb.nx + (ex == mb.bx ? mb.bx - 1 : 0);
+                    sn = j * K + (ex == mb.bx ? K - 1 : 0);
+                } else {
+                    se = (ey == mb.by ? mb.by - 1 : 0) * mb.nx + ex;
+                    sn = (ey == mb.by ? K - 1 : 0) * K + i;
+                }
+                const size_t so = (size_t)sn * nel + se;
+                p = q[so];
+                U = gx ? -q[NN + so] : q[NN + so];
+                V = gx ? q[2 * NN + so] : -q[2 * NN + so];
+            }
+            const size_t o = (size_t)(j * K + i) * nel + e;
+            q[o] = p;
+            q[NN + o] = U;
+            q[2 * NN + o] = V;
+        }
+        return;
+    }
     const double t = tstep[0] * mb.dt + toff;
     const double hx = 2.0 / mb.sx, hy = 2.0 / mb.sy;
     for (int i = 0; i < K; ++i) {

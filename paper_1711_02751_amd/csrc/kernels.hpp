@@ -53,9 +53,12 @@ struct Member {
     // (S) and (i, by) (N) for i < bx; the faces between ghosts are not
     // unknowns and hold zero.  A boundary row of the trace system has one
     // element and the imaginary neighbour: its self block lacks the ghost
-    // side's C A^-1 B term, and dG / dGh / dGhf hold that difference for the
-    // four sides [W, E, S, N] as one slot of G / Ghat fragments each.
-    int bx, by;
+    // side's C A^-1 B term and, with walls (bwall), gains the reflected
+    // real element's coupling over that element's four faces.  dG / dGh /
+    // dGhf hold, per side [W, E, S, N], four entries packed like one slot of
+    // G / Ghat: the real element's faces, the boundary face (the self slot)
+    // first (see side_slot).
+    int bx, by, bwall;
     const double *dG, *dGh;
     const float *dGhf;
 };
@@ -220,10 +223,13 @@ IMEXHDG_REFINE_DECLS(float)
 #undef IMEXHDG_REFINE_DECLS
 
 // Boundary states of a bounded member (bx > 0) into its ghost elements of
-// the volume array q: the exact translating vortex of eq. tc_vortex_ic
-// (Sec. 6.1) at time tstep[0] dt + toff, evaluated at the boundary point
-// each ghost node faces (ghost column bx: x = Lx at the node's y; column
-// bx + 1: x = 0; row by: y = Ly; row by + 1: y = 0; corner ghosts zero).
+// the volume array q.  Exact-solution data: the translating vortex of eq.
+// tc_vortex_ic (Sec. 6.1) at time tstep[0] dt + toff, evaluated at the
+// boundary point each ghost node faces (ghost column bx: x = Lx at the
+// node's y; column bx + 1: x = 0; row by: y = Ly; row by + 1: y = 0).
+// Walls (bwall): the reflection (eq. reflection) of the adjacent real
+// element's value at the boundary node the ghost node faces, read from q
+// itself.  Corner ghosts are zero.
 // tstep[0] is the step count of the state (an integer held as a double);
 // with tnext != nullptr the kernel also writes tnext[0] = tstep[0] + 1.
 struct Vortex {

@@ -22,7 +22,7 @@ LAUNCH_GRAPH, LAUNCH_HOST = 0, 1
 GUESS_EXTRAPOLATE, GUESS_LAST = 0, 1
 VARS_DEPTH, VARS_GEOPOTENTIAL = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
-BOUNDARY_PERIODIC, BOUNDARY_VORTEX = 0, 1
+BOUNDARY_PERIODIC, BOUNDARY_VORTEX, BOUNDARY_WALL = 0, 1, 2
 PHASES = ["explicit", "condense", "trace", "recover", "other"]
 
 EXPORTS = [
