@@ -497,6 +497,64 @@ def run_vortex(m, warm=20):
                         "boundary data", "T": 2.0, "cases": rows}
 
 
+# Water-height perturbation of Sec. 6.2 (Table 3) on [0, 2]^2 (the paper's
+# [-1, 1]^2 translated): 20 x 20 elements of degree 8, H_inf = 100, g = 1,
+# drop of width sigma = 0.1 (the paper prints none) at rest, reflecting
+# walls, ARS2, T = 0.16; the paper's wall-clock time per step (its own
+# machine, serial, sparse LU) for context.
+WATER_DROP_PAPER_S_PER_STEP = {0.002: (20 * 60 + 41) / 80.0, 0.02: (2 * 60 + 28) / 8.0}
+
+
+def run_water_drop(m, precision="fp64"):
+    """Both ARS2 time steps of Table 3 to T = 0.16 on one GPU, timed over
+    the whole run (the first steps learn the schedule and capture it) and
+    over the steps after the capture; mass drift of phi_eta."""
+    import torch
+    from paper_1711_02751_amd import workloads as W
+    rows = []
+    for dt in (0.002, 0.02):
+        steps = int(round(0.16 / dt))
+        kw = {}
+        if precision == "mixed":
+            kw = dict(precision=m.PREC_MIXED, krylov_rtol=MIXED_KRYLOV_RTOL,
+                      refine_rtol=MIXED_REFINE_RTOL, refine_max=8)
+        cfg = m.default_config(nx=20, ny=20, Lx=2.0, Ly=2.0, degree=8, g=1.0, H=100.0, dt=dt,
+                               scheme=m.SCHEME_ARS232, physics=m.PHYSICS_NONLINEAR,
+                               boundary=m.BOUNDARY_WALL, **kw)
+        S = m.Solver(cfg)
+        x, y = S.nodes()
+        h, hu, hv = W.water_drop(x, y, H_inf=100.0, sigma=0.1)
+        S.set_state(h, hu, hv, vars=m.VARS_DEPTH)
+        m0 = S.diag()["mass"][0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S.step(steps - 2)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        d = S.diag()
+        from numpy.polynomial import legendre as leg
+        xi = np.concatenate([[-1.0], np.sort(leg.Legendre.basis(8).deriv().roots().real), [1.0]])
+        dx_min = 0.1 / 2.0 * np.min(np.diff(xi))
+        rows.append({"dt": dt, "steps": steps,
+                     "courant": dt * math.sqrt(100.0) / dx_min,   # gravity, sqrt(g H) = 10
+                     "s_whole_run": t2 - t0, "ms_per_step_after_capture": 1e3 * (t2 - t1) / (steps - 2),
+                     "paper_s_per_step": WATER_DROP_PAPER_S_PER_STEP[dt],
+                     "mass_drift": d["mass"][0] - m0,
+                     "krylov_iters_per_stage": d["krylov_iters"] / max(d["stage_solves"], 1),
+                     "graph_steps": d["graph_steps"], "redone_steps": d["redo_steps"]})
+        log(f"[bench] water drop dt={dt} ({precision}): {rows[-1]['ms_per_step_after_capture']:.3f} "
+            f"ms/step, whole run {t2 - t0:.3f} s")
+        S.close()
+        del S
+    return {"workload": "water-height perturbation, Sec. 6.2 (Table 3): 20x20, degree 8, "
+                        "H_inf = 100, g = 1, sigma = 0.1, walls, ARS2, T = 0.16",
+            "precision": precision, "n_dof": 3 * 20 * 20 * 81, "cases": rows,
+            "note": "paper_s_per_step: the paper's own machine (serial code, sparse LU), context only"}
+
+
 def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
     """The 64-member ensemble (meshes 32^2 ... 128^2, k = 3, dt_m = 2 dx_min):
     every launch covers all members, one graph launch per step."""
@@ -569,8 +627,11 @@ def main():
                     help="skip the large-workload measurement")
     ap.add_argument("--vortex-only", action="store_true",
                     help="run only the moving-vortex tables and print their JSON")
+    ap.add_argument("--water-drop-only", action="store_true",
+                    help="run only the water-height perturbation (walls, Sec. 6.2)")
     ap.add_argument("--no-vortex", action="store_true",
-                    help="skip the moving-vortex tables (bounded mesh, Sec. 6.1)")
+                    help="skip the bounded-mesh workloads (moving vortex of Sec. 6.1, "
+                         "water-height perturbation of Sec. 6.2)")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the FP32 / BF16 precision modes")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -591,6 +652,10 @@ def main():
     torch.cuda.set_device(0)
     if args.vortex_only:
         print(json.dumps({"vortex": run_vortex(m)}))
+        return
+    if args.water_drop_only:
+        print(json.dumps({"water_drop": {"fp64": run_water_drop(m),
+                                         "mixed": run_water_drop(m, "mixed")}}))
         return
     if args.calib_copy_mib > 0:
         # one plain elementwise pass over a known size: its FETCH_SIZE and
@@ -672,6 +737,7 @@ def main():
                                  args.tune_cache)
     if not args.no_vortex:
         out["vortex"] = run_vortex(m)
+        out["water_drop"] = {"fp64": run_water_drop(m), "mixed": run_water_drop(m, "mixed")}
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(m, args.steps, args.warmup,
                                        mixed=args.precision == "mixed",
