@@ -157,6 +157,19 @@ typedef struct imexhdg_config {
                                 0 = the default (1 for FP32, 3 for BF16);
                                 ignored by the other precisions           */
     int32_t boundary;        /* IMEXHDG_BOUNDARY_*                         */
+    int32_t variable_depth;  /* 1: the depth B under the reference plane
+                                varies in space, phi_B = g B at the nodes
+                                (imexhdg_set_depth; H until it is called):
+                                the flux tensor and linear flux take the
+                                nodal phi_B and L gains the source
+                                (0, phi_eta grad phi_B) (Sec. 3.1, eq.
+                                psweGov; Sec. 4.3).  The stage system is
+                                solved by defect correction: its FP64
+                                residual, matrix-free with the nodal phi_B,
+                                corrected by the constant-depth (phi_B =
+                                g H) HDG stage solve until its relative
+                                norm is at most refine_rtol.  Periodic,
+                                single contexts; steps run host-driven.   */
     double  vortex[5];       /* u_inf, v_inf, beta, xc, yc of
                                 IMEXHDG_BOUNDARY_VORTEX (finite)           */
 } imexhdg_config;
@@ -189,6 +202,8 @@ typedef struct imexhdg_diag {
      *              (eq. recover_volume_unknowns);
      *   OTHER      diagnostics and operator-level calls.                   */
     double  phase_ms[5];
+    int64_t depth_corrections; /* defect corrections of variable-depth stage
+                                  solves, cumulative                      */
 } imexhdg_diag;
 
 #define IMEXHDG_PHASE_EXPLICIT 0
@@ -251,6 +266,14 @@ int imexhdg_get_nodes(const imexhdg_ctx *ctx, double *x, double *y);
  * sqrt(g h) at its centre.  Resets the trace guess and the step count.  */
 int imexhdg_set_state(imexhdg_ctx *ctx, int vars, const double *a,
                       const double *b, const double *c);
+
+/* Depth under the reference plane at the nodes (variable_depth = 1;
+ * Sec. 3.1: phi_B = g B): host array of n_nodes doubles in the host state
+ * ordering, all finite and positive, copied during the call.  Takes effect
+ * from the next step; VARS_DEPTH state arrays are converted with it
+ * (phi_eta = g (h - B)).  IMEXHDG_E_INVAL for a flat-bottom context or a
+ * bad value.                                                             */
+int imexhdg_set_depth(imexhdg_ctx *ctx, const double *B);
 
 /* The same from device memory without a host copy, e.g. from a torch
  * tensor: d_state holds 3 * n_nodes values of type `dtype`

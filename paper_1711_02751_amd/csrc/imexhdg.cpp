@@ -174,6 +174,14 @@ struct imexhdg_ctx {
     double *tstep = nullptr;
     int tcur = 0;
     std::vector<double> cst;
+    // variable depth: nodal phi_B (device), the host depth for state
+    // conversions, the stage residual and correction, their partial sums
+    bool vdepth = false;
+    double *pB = nullptr, *dres = nullptr, *ddel = nullptr, *dcpart = nullptr;
+    double *hcpart = nullptr;         // pinned host mirror of dcpart
+    int nvb = 0;
+    std::vector<double> hB;
+    int64_t dcorr = 0;
     double *dpart = nullptr;          // [5][pstride] residual / diagnostics partials
     // host mirrors
     KrylovState *hks = nullptr;
@@ -487,6 +495,15 @@ Layout layout_of(const std::vector<imexhdg_config> &cf) {
                            2 * align256(side_frag_count((int)K) * 8) +
                            align256(side_frag_count((int)K) * 4));
     t += align256(3 * 8);                              // step counts of the state ring
+    if (c0.variable_depth) {                           // phi_B, residual, correction, partials
+        size_t nvb = 0;
+        for (const imexhdg_config &c : cf) {
+            int nx, ny;
+            device_dims(c, nx, ny);
+            nvb += (size_t)member_vol_blocks(nx * ny);
+        }
+        t += align256(L.N / 3 * 8) + 2 * align256(L.N * 8) + align256(2 * nvb * 8);
+    }
     t += 8 * align256((size_t)L.pstride * 8) + align256(5 * (size_t)L.pstride * 8);
     t += align256(nm * sizeof(KrylovState));
     t += align256(nm * sizeof(Member));
@@ -530,6 +547,10 @@ int validate(const imexhdg_config *c) {
     if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC && c->boundary != IMEXHDG_BOUNDARY_VORTEX &&
         c->boundary != IMEXHDG_BOUNDARY_WALL)
         return fail(IMEXHDG_E_INVAL, "unknown boundary");
+    if (c->variable_depth != 0 && c->variable_depth != 1)
+        return fail(IMEXHDG_E_INVAL, "variable_depth must be 0 or 1");
+    if (c->variable_depth && c->boundary != IMEXHDG_BOUNDARY_PERIODIC)
+        return fail(IMEXHDG_E_INVAL, "variable depth takes periodic meshes only");
     if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC) {
         if (c->boundary == IMEXHDG_BOUNDARY_VORTEX)
             for (double v : c->vortex)
@@ -556,7 +577,8 @@ int validate_batch(const imexhdg_config *cfgs, int n) {
             a.krylov_rtol != b.krylov_rtol || a.krylov_max_iter != b.krylov_max_iter ||
             a.check_every != b.check_every || a.refine_rtol != b.refine_rtol ||
             a.refine_max != b.refine_max || a.launch != b.launch ||
-            a.trace_guess != b.trace_guess || a.boundary != b.boundary)
+            a.trace_guess != b.trace_guess || a.boundary != b.boundary ||
+            a.variable_depth != b.variable_depth)
             return fail(IMEXHDG_E_INVAL, "member " + std::to_string(m) +
                                              " differs from member 0 in more than nx, ny, "
                                              "Lx, Ly and dt");
@@ -565,6 +587,8 @@ int validate_batch(const imexhdg_config *cfgs, int n) {
         return fail(IMEXHDG_E_INVAL, "an ensemble steps on the fixed launch schedule only");
     if (n > 1 && cfgs[0].boundary != IMEXHDG_BOUNDARY_PERIODIC)
         return fail(IMEXHDG_E_INVAL, "ensemble members must be periodic");
+    if (n > 1 && cfgs[0].variable_depth)
+        return fail(IMEXHDG_E_INVAL, "ensemble members must have a flat bottom");
     return IMEXHDG_OK;
 }
 
@@ -933,8 +957,8 @@ void begin_step(imexhdg_ctx *c, const double *qin) {
 // One implicit stage: Z = A^-1 R, g = C Z, solve G x = g, Q = Z - W x.
 // stage >= 0 (a step's stage i): the trace guess is extrapolated from the
 // last two solutions; stage < 0: x is the guess as it is.
-int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres,
-                int stage) {
+int stage_solve_const(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters,
+                      double *relres, int stage) {
     if (c->lp) {
         LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_lp(c->geom, c->bt, R, nullptr, c->aii, c->Z,
                                                       c->lp_bf16, c->lp_ndc, c->stream));
@@ -960,6 +984,50 @@ int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, doub
     return rc;
 }
 
+// Stage solve with variable depth: the stage system (I - dt a~_ii M^-1 L) Q
+// = R with the nodal phi_B (its DG-LF form, equal to the HDG stage: Sec.
+// 4.3, footnote to eq. linear_hdgflux3) by defect correction, each
+// correction the constant-depth HDG stage solve of the FP64 residual, Q <-
+// Q + S^-1 (R - A Q), until ||R - A Q|| <= refine_rtol ||R||.  Converges
+// at a rate set by how far phi_B strays from g H.  The trace of the stage
+// (the next stage's guess) accumulates the corrections' traces.
+constexpr int kMaxDepthCorrections = 60;
+int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres,
+                int stage) {
+    if (!c->vdepth) return stage_solve_const(c, R, Q, iters, relres, stage);
+    int rc = stage_solve_const(c, R, Q, iters, relres, stage);
+    if (rc && rc != IMEXHDG_E_NOCONV) return rc;
+    int status = rc;
+    HIP_TRY(hipMemcpyAsync(c->xsave, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    for (int it = 0;; ++it) {
+        HIP_TRY(launch_stage_res_var(c->geom, c->bt, Q, c->pB, R, c->aii, c->dres, c->dcpart,
+                                     c->nvb, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->hcpart, c->dcpart, 2 * (size_t)c->nvb * 8,
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(stream_sync(c));
+        double rr = 0.0, RR = 0.0;
+        for (int b = 0; b < c->nvb; ++b) {
+            rr += c->hcpart[b];
+            RR += c->hcpart[c->nvb + b];
+        }
+        if (!std::isfinite(rr)) return fail(IMEXHDG_E_NONFINITE, "non-finite stage residual");
+        const double rel = RR > 0.0 ? std::sqrt(rr / RR) : std::sqrt(rr);
+        if (rel <= c->cfg.refine_rtol) break;
+        if (it >= kMaxDepthCorrections) {
+            status = IMEXHDG_E_NOCONV;
+            break;
+        }
+        HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
+        rc = stage_solve_const(c, c->dres, c->ddel, nullptr, nullptr, -1);
+        if (rc && rc != IMEXHDG_E_NOCONV) return rc;
+        HIP_TRY(launch_axpy(Q, (const double *)c->ddel, 1.0, c->N, c->stream));
+        HIP_TRY(launch_axpy(c->xsave, (const double *)c->x, 1.0, c->T, c->stream));
+        c->dcorr += 1;
+    }
+    HIP_TRY(hipMemcpyAsync(c->x, c->xsave, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
+    return status;
+}
+
 int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
     Comb cb{};
     cb.n = 0;
@@ -978,7 +1046,9 @@ int run_plan(imexhdg_ctx *c, int i, const double *Qi, double *out) {
     // bounded mesh: the explicit flux reads the boundary states from the
     // ghosts of Q_i (Qi is the step's input or a stage buffer, both workspace)
     if (int rf = fill_ghosts(c, const_cast<double *>(Qi), i, i + 1 == c->tab.s)) return rf;
-    if (nonlinear) {
+    if (nonlinear && c->vdepth) {
+        LAUNCH(IMEXHDG_K_NL, launch_nl_var(c->geom, c->bt, Qi, c->pB, cb, true, c->stream));
+    } else if (nonlinear) {
         LAUNCH(IMEXHDG_K_NL, launch_nl(c->geom, c->bt, Qi, cb, true, c->stream, c->nl32));
     } else {
         LAUNCH(IMEXHDG_K_COMBINE, launch_combine(cb, c->N, c->stream));
@@ -1397,7 +1467,8 @@ int state_to_device(const imexhdg_ctx *c, const MemberHost &m, int vars, const d
                          dst = (size_t)n * nel + device_elem(m, e);
             double p, U, V;
             if (vars == IMEXHDG_VARS_DEPTH) {
-                p = g * (a[src] - H);
+                const double Hn = c->vdepth ? c->hB[src] : H;   // one member
+                p = g * (a[src] - Hn);
                 U = g * b[src];
                 V = g * cc[src];
             } else {
@@ -1405,7 +1476,7 @@ int state_to_device(const imexhdg_ctx *c, const MemberHost &m, int vars, const d
                 U = b[src];
                 V = cc[src];
             }
-            const double phi = p + phiB;
+            const double phi = p + (c->vdepth ? g * c->hB[src] : phiB);
             if (!std::isfinite(p) || !std::isfinite(U) || !std::isfinite(V))
                 return fail(IMEXHDG_E_INVAL, "state holds NaN or Inf");
             if (!(phi > 0)) return fail(IMEXHDG_E_INVAL, "total depth must be positive");
@@ -1427,7 +1498,7 @@ void state_from_device(const imexhdg_ctx *c, const MemberHost &m, int vars,
                          src = (size_t)n * nel + device_elem(m, e);
             const double p = h[src], U = h[NN + src], V = h[2 * NN + src];
             if (vars == IMEXHDG_VARS_DEPTH) {
-                a[dst] = H + p / g;
+                a[dst] = (c->vdepth ? c->hB[dst] : H) + p / g;
                 b[dst] = U / g;
                 cc[dst] = V / g;
             } else {
@@ -1467,6 +1538,7 @@ void destroy_ctx(imexhdg_ctx *c) {
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->hks) (void)hipHostFree(c->hks);
     if (c->hpart) (void)hipHostFree(c->hpart);
+    if (c->hcpart) (void)hipHostFree(c->hcpart);
     delete c;
 }
 
@@ -1574,6 +1646,7 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
     g.winvk = 1.0 / c->ref.w[K - 1];
     for (int i = 0; i < K; ++i) g.w[i] = c->ref.w[i];
     for (int i = 0; i < K; ++i) g.xi[i] = c->ref.x[i];
+    for (int i = 0; i < K * K; ++i) g.D[i] = c->ref.D[i];
     for (int m = 0; m < K; ++m)
         for (int a = 0; a < K; ++a)
             g.Dw[m * K + a] = c->ref.w[m] * c->ref.D[m * K + a] / c->ref.w[a];
@@ -1638,6 +1711,15 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         o.dGhf = (float *)take(side_frag_count(K) * 4);
     }
     c->tstep = (double *)take(3 * 8);
+    c->vdepth = cf[0].variable_depth != 0;
+    if (c->vdepth) {
+        c->nvb = 0;
+        for (const MemberHost &h : c->mh) c->nvb += member_vol_blocks(h.nel);
+        c->pB = (double *)take(L.N / 3 * 8);
+        c->dres = (double *)take(L.N * 8);
+        c->ddel = (double *)take(L.N * 8);
+        c->dcpart = (double *)take(2 * (size_t)c->nvb * 8);
+    }
     c->kb.P1 = (double *)take(3 * (size_t)c->pstride * 8);
     c->kb.P2 = (double *)take(3 * (size_t)c->pstride * 8);
     c->kb.P3 = (double *)take(2 * (size_t)c->pstride * 8);
@@ -1657,6 +1739,8 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         hipHostMalloc((void **)&c->hpart, 5 * (size_t)c->pstride * 8) != hipSuccess ||
         hipHostMalloc((void **)&c->hstat, 3 * (size_t)L.s * n * sizeof(StageStatus)) !=
             hipSuccess)
+        return bail(fail(IMEXHDG_E_NOMEM, "hipHostMalloc failed"));
+    if (c->vdepth && hipHostMalloc((void **)&c->hcpart, 2 * (size_t)c->nvb * 8) != hipSuccess)
         return bail(fail(IMEXHDG_E_NOMEM, "hipHostMalloc failed"));
     for (hipEvent_t &e : c->gev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
@@ -1707,6 +1791,14 @@ int create_ctx(const imexhdg_config *cfgs, int n, void *stream, void *workspace,
         hipStreamSynchronize(c->stream))
         return bail(fail(IMEXHDG_E_DEVICE, "workspace initialisation failed"));
     if ((rc = build_batch(c))) return bail(rc);
+    if (c->vdepth) {
+        // flat bottom B = H until imexhdg_set_depth
+        c->hB.assign(c->nnodes, cf[0].H);
+        const std::vector<double> pb(L.N / 3, cf[0].g * cf[0].H);
+        if (hipMemcpyAsync(c->pB, pb.data(), pb.size() * 8, hipMemcpyHostToDevice, c->stream) ||
+            hipStreamSynchronize(c->stream))
+            return bail(fail(IMEXHDG_E_DEVICE, "upload of the depth failed"));
+    }
     *out = c;
     g_last_error.clear();
     return IMEXHDG_OK;
@@ -1728,7 +1820,8 @@ int step_ctx(imexhdg_ctx *c, int nsteps) {
 
 int step_ctx_run(imexhdg_ctx *c, int nsteps) {
     int status = IMEXHDG_OK;
-    if (c->cfg.launch == IMEXHDG_LAUNCH_GRAPH && (c->prof_target == -2 || c->nm > 1)) {
+    if (c->cfg.launch == IMEXHDG_LAUNCH_GRAPH && (c->prof_target == -2 || c->nm > 1) &&
+        !c->vdepth) {
         int rc = step_graph(c, nsteps, &status);
         if (rc) return rc;
     } else {
@@ -1866,6 +1959,7 @@ int member_diag(imexhdg_ctx *c, int m, imexhdg_diag *d) {
     d->graph_steps = c->graph_steps;
     d->redo_steps = c->redos;
     d->step_ms = c->step_ms;
+    d->depth_corrections = c->dcorr;
     for (int k = 0; k < IMEXHDG_K_COUNT; ++k) d->phase_ms[phase_of(k)] += c->prof_ms[k];
     return IMEXHDG_OK;
 }
@@ -1993,6 +2087,25 @@ int imexhdg_set_state(imexhdg_ctx *c, int vars, const double *a, const double *b
     return set_member_state(c, 0, vars, a, b, cc);
 }
 
+int imexhdg_set_depth(imexhdg_ctx *c, const double *B) {
+    if (!c || !B) return fail(IMEXHDG_E_INVAL, "NULL argument");
+    if (!c->vdepth) return fail(IMEXHDG_E_INVAL, "the context has a flat bottom (variable_depth = 0)");
+    const MemberHost &m = c->mh[0];
+    const int K = c->geom.K;
+    std::vector<double> h((size_t)K * K * m.nel);
+    for (int e = 0; e < m.nel; ++e)
+        for (int n = 0; n < K * K; ++n) {
+            const double b = B[(size_t)e * K * K + n];
+            if (!std::isfinite(b) || !(b > 0.0))
+                return fail(IMEXHDG_E_INVAL, "depth must be finite and positive");
+            h[(size_t)n * m.nel + e] = c->cfg.g * b;
+        }
+    HIP_TRY(hipMemcpyAsync(c->pB, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(stream_sync(c));
+    c->hB.assign(B, B + c->nnodes);
+    return IMEXHDG_OK;
+}
+
 int imexhdg_set_state_device(imexhdg_ctx *c, int vars, int dtype, const void *d_state) {
     if (!c) return fail(IMEXHDG_E_INVAL, "NULL argument");
     return set_member_state_device(c, 0, vars, dtype, d_state);
@@ -2021,7 +2134,8 @@ int imexhdg_state_device(imexhdg_ctx *c, double **d_q) {
 
 int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
     if (!c || !d_q || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
+    if (c->box || c->vdepth)
+        return fail(IMEXHDG_E_INVAL, "operator-level calls take flat-bottom periodic meshes only");
     Comb cb{};
     cb.n = 0;
     cb.self = 1.0;
@@ -2034,7 +2148,8 @@ int imexhdg_nl_residual(imexhdg_ctx *c, const double *d_q, double *d_out) {
 int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_qhat,
                             double *d_out) {
     if (!c || !d_Q || !d_qhat || !d_out) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
+    if (c->box || c->vdepth)
+        return fail(IMEXHDG_E_INVAL, "operator-level calls take flat-bottom periodic meshes only");
     LAUNCH(IMEXHDG_K_LINRES,
            launch_linear_residual(c->geom, c->bt, d_Q, d_qhat, d_out, c->stream));
     return IMEXHDG_OK;
@@ -2043,7 +2158,8 @@ int imexhdg_linear_residual(imexhdg_ctx *c, const double *d_Q, const double *d_q
 int imexhdg_stage_solve_noalloc(imexhdg_ctx *c, const double *d_res0, double *d_Q,
                                 double *d_qhat, int32_t *iters, double *relres) {
     if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
+    if (c->box || c->vdepth)
+        return fail(IMEXHDG_E_INVAL, "operator-level calls take flat-bottom periodic meshes only");
     if (c->nm != 1) return fail(IMEXHDG_E_INVAL, "a context of one mesh is required");
     SolveBufs sb;
     const size_t need = carve_scratch(c, nullptr, &sb);
@@ -2079,7 +2195,8 @@ int imexhdg_stage_solve_noalloc(imexhdg_ctx *c, const double *d_res0, double *d_
 int imexhdg_stage_solve(imexhdg_ctx *c, const double *d_res0, double *d_Q, double *d_qhat,
                         int32_t *iters, double *relres) {
     if (!c || !d_res0 || !d_Q || !d_qhat) return fail(IMEXHDG_E_INVAL, "NULL argument");
-    if (c->box) return fail(IMEXHDG_E_INVAL, "operator-level calls take periodic meshes only");
+    if (c->box || c->vdepth)
+        return fail(IMEXHDG_E_INVAL, "operator-level calls take flat-bottom periodic meshes only");
     HIP_TRY(hipMemcpyAsync(c->x, d_qhat, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
     int rc = stage_solve(c, d_res0, d_Q, iters, relres, -1);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;

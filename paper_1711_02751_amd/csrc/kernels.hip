@@ -2624,6 +2624,170 @@ __global__ void k_axpy_guarded(const Batch bt, int K, double *__restrict__ y,
 }
 
 
+// ------------------------------------------- variable bathymetry
+// DG residuals over nodal phi_B (pB, one value per node in the volume
+// layout of one variable).  LIN = false: M^-1 NL(q), the nonlinear flux
+// F_NL = (0, U U / phi + phi_eta^2 / 2, U V / phi | ...) with phi = phi_eta
+// + phi_B at the node and the flux F* - F*_L (Sec. 4.3), tau* = max of
+// |u.n| + sqrt(phi) and tau_L* = max of sqrt(phi_B) over the two sides;
+// the stage combination `comb` as in k_nl.  LIN = true: the stage
+// residual out = R - (Q - c M^-1 L(Q)) of the linear part, L with F_L =
+// (U, phi_B phi_eta I), the Lax-Friedrichs flux with tau_L* and the source
+// (0, phi_eta grad phi_B) (grad of the element's interpolant of phi_B),
+// c = a~_ii dt of the member; partials [2][blocks] of ||out||^2, ||R||^2.
+// One thread per (element, node row j); the y fluxes through LDS.
+template <bool LIN>
+__device__ __forceinline__ void var_flux(double p, double U, double V, double b, double F[2][3]) {
+    if (LIN) {
+        F[0][0] = U; F[0][1] = b * p; F[0][2] = 0.0;
+        F[1][0] = V; F[1][1] = 0.0; F[1][2] = b * p;
+    } else {
+        const double inv = 1.0 / (p + b), hp = 0.5 * p * p;
+        F[0][0] = 0.0; F[0][1] = U * U * inv + hp; F[0][2] = U * V * inv;
+        F[1][0] = 0.0; F[1][1] = V * U * inv; F[1][2] = V * V * inv + hp;
+    }
+}
+
+template <bool LIN>
+__device__ __forceinline__ void var_numflux(const double qm[3], const double qp[3], double bm,
+                                            double bp, double nx, double ny, double f[3]) {
+    double Fm[2][3], Fp[2][3];
+    var_flux<LIN>(qm[0], qm[1], qm[2], bm, Fm);
+    var_flux<LIN>(qp[0], qp[1], qp[2], bp, Fp);
+    const double tl = fmax(sqrt(bm), sqrt(bp));
+    double diss = tl;
+    if (!LIN) {
+        const double sm = fabs((qm[1] * nx + qm[2] * ny) / (qm[0] + bm)) + sqrt(qm[0] + bm);
+        const double sp = fabs((qp[1] * nx + qp[2] * ny) / (qp[0] + bp)) + sqrt(qp[0] + bp);
+        diss = fmax(sm, sp) - tl;
+    }
+    for (int c = 0; c < 3; ++c)
+        f[c] = 0.5 * ((Fm[0][c] + Fp[0][c]) * nx + (Fm[1][c] + Fp[1][c]) * ny) +
+               0.5 * diss * (qm[c] - qp[c]);
+}
+
+template <int K, bool LIN>
+__global__ __launch_bounds__(64 * K) void k_dg_var(const double *__restrict__ q,
+                                                   const double *__restrict__ pB, const Geom g,
+                                                   const Batch bt, const Comb comb, int scale_dt,
+                                                   const double *__restrict__ R,
+                                                   double *__restrict__ out, double cst,
+                                                   double *partials, int stride) {
+    __shared__ double sF[3][K][K][64];
+    const int lane = threadIdx.x & 63;
+    const int j = wave_id();
+    int lb;
+    const Member mb = load_member(bt, member_of<CV>(bt, blockIdx.x, lb));
+    q += mb.vo;
+    pB += mb.vo / 3;
+    const int e = lb * 64 + lane;
+    const bool active = e < mb.nel;
+    const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
+    const size_t nel = mb.nel, NN = (size_t)K * K * nel;
+    auto at = [&](int row, int i, int el, double v[3], double &b) {
+        const size_t o = (size_t)(row * K + i) * nel + el;
+        v[0] = q[o]; v[1] = q[NN + o]; v[2] = q[2 * NN + o];
+        b = pB[o];
+    };
+    double p[K], U[K], V[K], b[K], o[3][K];
+    for (int i = 0; i < K; ++i) {
+        double v[3];
+        at(j, i, nb.e, v, b[i]);
+        p[i] = v[0]; U[i] = v[1]; V[i] = v[2];
+    }
+    double Fx[3][K];
+    for (int i = 0; i < K; ++i) {
+        double F[2][3];
+        var_flux<LIN>(p[i], U[i], V[i], b[i], F);
+        for (int c = 0; c < 3; ++c) {
+            Fx[c][i] = F[0][c];
+            sF[c][j][i][lane] = F[1][c];
+        }
+    }
+    const double sx = mb.sx, sy = mb.sy;
+    for (int a = 0; a < K; ++a)
+        for (int c = 0; c < 3; ++c) {
+            double sacc = 0.0;
+            for (int m = 0; m < K; ++m) sacc += g.Dw[m * K + a] * Fx[c][m];
+            o[c][a] = sx * sacc;
+        }
+    {   // east and west faces of row j
+        double qm[3], qp[3], bp, f[3];
+        qm[0] = p[K - 1]; qm[1] = U[K - 1]; qm[2] = V[K - 1];
+        at(j, 0, nb.east, qp, bp);
+        var_numflux<LIN>(qm, qp, b[K - 1], bp, 1.0, 0.0, f);
+        for (int c = 0; c < 3; ++c) o[c][K - 1] -= sx * g.winvk * f[c];
+        qm[0] = p[0]; qm[1] = U[0]; qm[2] = V[0];
+        at(j, K - 1, nb.west, qp, bp);
+        var_numflux<LIN>(qm, qp, b[0], bp, -1.0, 0.0, f);
+        for (int c = 0; c < 3; ++c) o[c][0] -= sx * g.winv0 * f[c];
+    }
+    __syncthreads();
+    for (int i = 0; i < K; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double sacc = 0.0;
+            for (int m = 0; m < K; ++m) sacc += g.Dw[m * K + j] * sF[c][m][i][lane];
+            o[c][i] += sy * sacc;
+        }
+    if (j == K - 1 || j == 0) {
+        const bool north = j == K - 1;
+        const int other = north ? nb.north : nb.south, orow = north ? 0 : K - 1;
+        const double ny = north ? 1.0 : -1.0, sc = sy * (north ? g.winvk : g.winv0);
+        for (int i = 0; i < K; ++i) {
+            double qm[3] = {p[i], U[i], V[i]}, qp[3], bp, f[3];
+            at(orow, i, other, qp, bp);
+            var_numflux<LIN>(qm, qp, b[i], bp, 0.0, ny, f);
+            for (int c = 0; c < 3; ++c) o[c][i] -= sc * f[c];
+        }
+    }
+    if (LIN) {
+        // source (0, phi_eta d_x phi_B, phi_eta d_y phi_B) with the
+        // derivatives of the element's interpolant of phi_B at the node
+        for (int i = 0; i < K; ++i) {
+            double dx = 0.0, dy = 0.0;
+            for (int m = 0; m < K; ++m) {
+                double bm_;
+                double v[3];
+                at(m, i, nb.e, v, bm_);
+                dx += g.D[i * K + m] * b[m];
+                dy += g.D[j * K + m] * bm_;
+            }
+            o[1][i] += p[i] * sx * dx;
+            o[2][i] += p[i] * sy * dy;
+        }
+    }
+    double acc[2] = {0.0, 0.0};
+    if (active) {
+        const size_t o0 = mb.vo + (size_t)(j * K) * nel + e;
+        if (LIN) {
+            for (int i = 0; i < K; ++i) {
+                const size_t oi = o0 + (size_t)i * nel;
+                const double Qv[3] = {p[i], U[i], V[i]};
+                for (int c = 0; c < 3; ++c) {
+                    const double r = R[c * NN + oi];
+                    const double v = r - (Qv[c] - cst * mb.dt * o[c][i]);
+                    out[c * NN + oi] = v;
+                    acc[0] += v * v;
+                    acc[1] += r * r;
+                }
+            }
+        } else {
+            const double scl = scale_dt ? mb.dt : 1.0;
+            for (int i = 0; i < K; ++i) {
+                const size_t oi = o0 + (size_t)i * nel;
+                for (int c = 0; c < 3; ++c) {
+                    const double x = o[c][i] * scl;
+                    if (comb.store) comb.store[c * NN + oi] = x;
+                    double v = comb.self * x;
+                    for (int t = 0; t < comb.n; ++t) v += comb.coef[t] * comb.in[t][c * NN + oi];
+                    comb.out[c * NN + oi] = v;
+                }
+            }
+        }
+    }
+    if (LIN) store_partials<2>(acc, partials, stride);
+}
+
 // ------------------------------------------------ boundary states
 // The exact translating vortex of Sec. 6.1 (eq. tc_vortex_ic) at (x, y, t)
 // in the geopotential variables: depth h = H - beta^2 / (32 pi^2)
@@ -3153,6 +3317,34 @@ hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, doub
         KLAUNCH(k_state_in<double>, dim3(blocks), dim3(256), 0, s, (const double *)src,
                 depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks, bx, nxp);
     return hipGetLastError();
+}
+
+template <int K> struct RunDgVar {
+    static hipError_t run(const Geom &g, const Batch &b, const double *q, const double *pB,
+                          const Comb &comb, bool scale_dt, const double *R, double *out,
+                          double cst, double *partials, int stride, bool lin, hipStream_t s) {
+        if (lin)
+            KLAUNCH((k_dg_var<K, true>), dim3(b.nbv), dim3(64 * K), 0, s, q, pB, g, b, comb,
+                    scale_dt ? 1 : 0, R, out, cst, partials, stride);
+        else
+            KLAUNCH((k_dg_var<K, false>), dim3(b.nbv), dim3(64 * K), 0, s, q, pB, g, b, comb,
+                    scale_dt ? 1 : 0, R, out, cst, partials, stride);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_nl_var(const Geom &g, const Batch &b, const double *q, const double *pB,
+                         const Comb &comb, bool scale_dt, hipStream_t s) {
+    return dispatch<RunDgVar>(g.K, g, b, q, pB, comb, scale_dt, nullptr, nullptr, 0.0,
+                              nullptr, 0, false, s);
+}
+
+hipError_t launch_stage_res_var(const Geom &g, const Batch &b, const double *Q,
+                                const double *pB, const double *R, double aii, double *out,
+                                double *partials, int stride, hipStream_t s) {
+    Comb none{};
+    return dispatch<RunDgVar>(g.K, g, b, Q, pB, none, false, R, out, aii, partials, stride,
+                              true, s);
 }
 
 hipError_t launch_put(double *p, double v, hipStream_t s) {

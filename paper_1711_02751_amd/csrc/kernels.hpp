@@ -25,6 +25,7 @@ struct Geom {
     double w[kMaxK];            // LGL weights
     double xi[kMaxK];           // LGL nodes on [-1, 1]
     double Dw[kMaxK * kMaxK];   // Dw[m*K + a] = w_m D[m][a] / w_a (weak derivative)
+    double D[kMaxK * kMaxK];    // D[a*K + m] = l_m'(x_a) (strong derivative)
 };
 
 // One member: its mesh, its slices of the concatenated arrays, its element
@@ -237,6 +238,17 @@ struct Vortex {
 };
 hipError_t launch_bc_fill(const Geom &g, const Batch &b, double *q, const double *tstep,
                           double toff, double *tnext, const Vortex &vx, hipStream_t s);
+// Variable bathymetry (nodal phi_B in pB, the volume layout of one
+// variable, N / 3 values): the explicit residual M^-1 NL with the stage
+// combination, as launch_nl; and the stage residual of the linear part,
+// out = R - (Q - a~_ii dt M^-1 L(Q)) with the source term, partials
+// [2][volume blocks] of ||out||^2 and ||R||^2 (see k_dg_var).
+hipError_t launch_nl_var(const Geom &g, const Batch &b, const double *q, const double *pB,
+                         const Comb &comb, bool scale_dt, hipStream_t s);
+hipError_t launch_stage_res_var(const Geom &g, const Batch &b, const double *Q,
+                                const double *pB, const double *R, double aii, double *out,
+                                double *partials, int stride, hipStream_t s);
+
 // p[0] = v (one thread; stream ordered, so a host value can be placed
 // between kernels without a copy from host memory).
 hipError_t launch_put(double *p, double v, hipStream_t s);

@@ -28,7 +28,8 @@ PHASES = ["explicit", "condense", "trace", "recover", "other"]
 EXPORTS = [
     "imexhdg_config_init", "imexhdg_validate", "imexhdg_workspace_bytes",
     "imexhdg_create", "imexhdg_destroy", "imexhdg_sizes", "imexhdg_get_nodes",
-    "imexhdg_set_state", "imexhdg_set_state_device", "imexhdg_get_state", "imexhdg_step",
+    "imexhdg_set_state", "imexhdg_set_state_device", "imexhdg_set_depth", "imexhdg_get_state",
+    "imexhdg_step",
     "imexhdg_get_diag",
     "imexhdg_last_error", "imexhdg_state_device", "imexhdg_nl_residual",
     "imexhdg_linear_residual", "imexhdg_stage_solve", "imexhdg_stage_solve_noalloc",
@@ -62,6 +63,7 @@ class Config(ctypes.Structure):
         ("launch", ctypes.c_int32), ("trace_guess", ctypes.c_int32),
         ("local_sweeps", ctypes.c_int32),
         ("boundary", ctypes.c_int32),
+        ("variable_depth", ctypes.c_int32),
         ("vortex", ctypes.c_double * 5),
     ]
 
@@ -75,6 +77,7 @@ class Diag(ctypes.Structure):
         ("nonfinite", ctypes.c_int32),
         ("graph_steps", ctypes.c_int64), ("redo_steps", ctypes.c_int64),
         ("step_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 5),
+        ("depth_corrections", ctypes.c_int64),
     ]
 
 
@@ -258,6 +261,14 @@ class Solver:
             if v.size != self.n_nodes:
                 raise ValueError("state arrays must hold n_nodes values")
         _check(self.lib.imexhdg_set_state(self._ctx, vars, *[_ptr(v) for v in arrs]))
+
+    def set_depth(self, B):
+        """Nodal depth under the reference plane (variable_depth = 1),
+        n_nodes values in the host state ordering."""
+        b = np.ascontiguousarray(np.asarray(B, dtype=np.float64).ravel())
+        if b.size != self.n_nodes:
+            raise ValueError("depth must hold n_nodes values")
+        _check(self.lib.imexhdg_set_depth(self._ctx, _ptr(b)))
 
     def set_state_device(self, t, vars=VARS_DEPTH):
         """State from a device tensor of shape (3, n_nodes) (host state
