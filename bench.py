@@ -555,6 +555,58 @@ def run_water_drop(m, precision="fp64"):
             "note": "paper_s_per_step: the paper's own machine (serial code, sparse LU), context only"}
 
 
+def run_bathymetry(m, n=128, k=4, amp=0.2, steps=10, warmup=2):
+    """Variable depth B = H (1 + amp sin(2 pi x) cos(2 pi y) + amp / 2 cos(4 pi
+    y)) on the periodic n x n mesh of degree k (g = 9.81, H = 1, the bump
+    recipe's state and time step), host-driven steps with defect-corrected
+    stage solves, beside the flat-bottom path on the same mesh, also
+    host-driven."""
+    import torch
+    from paper_1711_02751_amd import workloads as W
+    dt = W.bump_dt(n, k)
+    out = {"workload": f"variable depth, {n}x{n}, k={k}, bottom +-{amp:.0%} (+-{amp / 2:.0%}), "
+                       f"ARS2, dt={dt:.4g}", "n_dof": 3 * n * n * (k + 1) ** 2, "steps": steps}
+    mixed = dict(precision=m.PREC_MIXED, krylov_rtol=MIXED_KRYLOV_RTOL,
+                 refine_rtol=MIXED_REFINE_RTOL, refine_max=8)
+    for label, vd, kw in (("variable", 1, {}), ("variable_mixed", 1, mixed), ("flat", 0, {}),
+                          ("flat_mixed", 0, mixed)):
+        cfg = m.default_config(nx=n, ny=n, degree=k, g=9.81, H=1.0, dt=dt,
+                               launch=m.LAUNCH_HOST, variable_depth=vd, **kw)
+        S = m.Solver(cfg)
+        x, y = S.nodes()
+        B = np.ones_like(x)
+        if vd:
+            B = (1.0 + amp * np.sin(2 * math.pi * x) * np.cos(2 * math.pi * y)
+                 + 0.5 * amp * np.cos(4 * math.pi * y))
+            S.set_depth(B)
+        h, hu, hv = W.bump_flow(x, y, 3, H=1.0, n_bumps=16)
+        S.set_state(B + (h - 1.0), hu, hv, vars=m.VARS_DEPTH)   # the same surface elevation
+        S.step(warmup)
+        d0 = S.diag()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d = S.diag()
+        solves = d["stage_solves"] - d0["stage_solves"]
+        corr = d["depth_corrections"] - d0["depth_corrections"]
+        stages = solves - corr
+        out[label] = {"ms_per_step": 1e3 * el / steps,
+                      "dof_updates_per_s": out["n_dof"] * steps / el,
+                      "depth_corrections_per_stage": corr / max(stages, 1),
+                      "krylov_iters_per_solve": (d["krylov_iters"] - d0["krylov_iters"]) /
+                      max(solves, 1)}
+        log(f"[bench] bathymetry {label}: {out[label]['ms_per_step']:.3f} ms/step, "
+            f"{out[label]['depth_corrections_per_stage']:.1f} corrections per stage")
+        S.close()
+        del S
+    out["cost_vs_flat"] = out["variable"]["ms_per_step"] / out["flat"]["ms_per_step"]
+    out["cost_vs_flat_mixed"] = (out["variable_mixed"]["ms_per_step"] /
+                                 out["flat_mixed"]["ms_per_step"])
+    return out
+
+
 def run_ensemble(m, steps, warmup, mixed=True, tune_cache=TUNE_CACHE):
     """The 64-member ensemble (meshes 32^2 ... 128^2, k = 3, dt_m = 2 dx_min):
     every launch covers all members, one graph launch per step."""
@@ -627,11 +679,13 @@ def main():
                     help="skip the large-workload measurement")
     ap.add_argument("--vortex-only", action="store_true",
                     help="run only the moving-vortex tables and print their JSON")
+    ap.add_argument("--bathymetry-only", action="store_true",
+                    help="run only the variable-depth measurement (Sec. 3.1 source term)")
     ap.add_argument("--water-drop-only", action="store_true",
                     help="run only the water-height perturbation (walls, Sec. 6.2)")
     ap.add_argument("--no-vortex", action="store_true",
                     help="skip the bounded-mesh workloads (moving vortex of Sec. 6.1, "
-                         "water-height perturbation of Sec. 6.2)")
+                         "water-height perturbation of Sec. 6.2) and the variable depth")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the FP32 / BF16 precision modes")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -652,6 +706,9 @@ def main():
     torch.cuda.set_device(0)
     if args.vortex_only:
         print(json.dumps({"vortex": run_vortex(m)}))
+        return
+    if args.bathymetry_only:
+        print(json.dumps({"bathymetry": run_bathymetry(m)}))
         return
     if args.water_drop_only:
         print(json.dumps({"water_drop": {"fp64": run_water_drop(m),
@@ -738,6 +795,7 @@ def main():
     if not args.no_vortex:
         out["vortex"] = run_vortex(m)
         out["water_drop"] = {"fp64": run_water_drop(m), "mixed": run_water_drop(m, "mixed")}
+        out["bathymetry"] = run_bathymetry(m)
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(m, args.steps, args.warmup,
                                        mixed=args.precision == "mixed",

@@ -989,15 +989,27 @@ int stage_solve_const(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters
 // 4.3, footnote to eq. linear_hdgflux3) by defect correction, each
 // correction the constant-depth HDG stage solve of the FP64 residual, Q <-
 // Q + S^-1 (R - A Q), until ||R - A Q|| <= refine_rtol ||R||.  Converges
-// at a rate set by how far phi_B strays from g H.  The trace of the stage
-// (the next stage's guess) accumulates the corrections' traces.
+// at a rate set by how far phi_B strays from g H.  The constant-depth
+// solves need only be accurate to well below that rate: their trace solves
+// stop at kDepthInnerRtol relative to their own right-hand side (or
+// refine_rtol if looser), the outer loop reaching refine_rtol.  The trace
+// of the stage (the next stage's guess) accumulates the corrections'
+// traces.
 constexpr int kMaxDepthCorrections = 60;
+constexpr double kDepthInnerRtol = 1e-6;
 int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, double *relres,
                 int stage) {
     if (!c->vdepth) return stage_solve_const(c, R, Q, iters, relres, stage);
+    const double outer = c->cfg.refine_rtol;
+    struct Restore {
+        imexhdg_ctx *c;
+        double v;
+        ~Restore() { c->cfg.refine_rtol = v; }
+    } restore{c, outer};
+    c->cfg.refine_rtol = std::max(outer, kDepthInnerRtol);
     int rc = stage_solve_const(c, R, Q, iters, relres, stage);
     if (rc && rc != IMEXHDG_E_NOCONV) return rc;
-    int status = rc;
+    int status = IMEXHDG_OK;
     HIP_TRY(hipMemcpyAsync(c->xsave, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
     for (int it = 0;; ++it) {
         HIP_TRY(launch_stage_res_var(c->geom, c->bt, Q, c->pB, R, c->aii, c->dres, c->dcpart,
@@ -1012,7 +1024,8 @@ int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, doub
         }
         if (!std::isfinite(rr)) return fail(IMEXHDG_E_NONFINITE, "non-finite stage residual");
         const double rel = RR > 0.0 ? std::sqrt(rr / RR) : std::sqrt(rr);
-        if (rel <= c->cfg.refine_rtol) break;
+        if (relres) *relres = rel;
+        if (rel <= outer) break;
         if (it >= kMaxDepthCorrections) {
             status = IMEXHDG_E_NOCONV;
             break;
@@ -1020,6 +1033,7 @@ int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, doub
         HIP_TRY(hipMemsetAsync(c->x, 0, c->T * 8, c->stream));
         rc = stage_solve_const(c, c->dres, c->ddel, nullptr, nullptr, -1);
         if (rc && rc != IMEXHDG_E_NOCONV) return rc;
+        if (rc == IMEXHDG_E_NOCONV) status = rc;
         HIP_TRY(launch_axpy(Q, (const double *)c->ddel, 1.0, c->N, c->stream));
         HIP_TRY(launch_axpy(c->xsave, (const double *)c->x, 1.0, c->T, c->stream));
         c->dcorr += 1;
