@@ -77,10 +77,12 @@ def kernel_symbol(kernel_class, K, mixed):
     host-driven launches."""
     T = "float" if mixed else "double"
     face = {"bicg_k1": "k_bicg_k1", "bicg_k2": "k_bicg_k2", "bicg_k1f": "k_bicg_k1f"}
+    # template flags: the fixed schedule (false: host-driven), the bounded
+    # mesh variant (false: periodic)
     if kernel_class in face:
-        return f"{face[kernel_class]}<{K}, {T}, false>"
+        return f"{face[kernel_class]}<{K}, {T}, false, false>"
     if kernel_class == "trace_residual":
-        return f"k_trace_residual<{K}, {T}>"
+        return f"k_trace_residual<{K}, {T}, false>"
     if kernel_class in ("bicg_init", "axpy"):
         return f"k_{kernel_class}<{T}>"
     if kernel_class == "nl_residual":
