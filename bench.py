@@ -270,6 +270,38 @@ def measure_copy_bandwidth(gib=2, reps=5):
     return 2 * n * 8 / best / 1e9
 
 
+def measure_gemm_peak(n=8192, reps=5):
+    """Matrix-core rate a large library GEMM reaches (torch.matmul of two
+    contiguous n x n matrices, best of `reps`) in FP64, FP32 and BF16
+    (FP32 accumulation): the practical ceiling beside the nominal peaks.
+    TFLOP/s per precision."""
+    import torch
+    out = {}
+    prev = torch.backends.cuda.matmul.allow_tf32
+    torch.backends.cuda.matmul.allow_tf32 = False
+    try:
+        for name, dt in (("fp64", torch.float64), ("fp32", torch.float32),
+                         ("bf16", torch.bfloat16)):
+            a = torch.randn(n, n, device="cuda").to(dt).contiguous()
+            b = torch.randn(n, n, device="cuda").to(dt).contiguous()
+            c = torch.matmul(a, b)
+            best = float("inf")
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                c = torch.matmul(a, b)
+                e1.record()
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1) / 1000.0)
+            out[name] = 2.0 * n ** 3 / best / 1e12
+            del a, b, c
+    finally:
+        torch.backends.cuda.matmul.allow_tf32 = prev
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_path(m, wl, precision, steps, warmup, tune_cache=TUNE_CACHE):
     """Run one precision path; returns (result dict, final state).
 
@@ -728,6 +760,8 @@ def main():
         del src, dst
     hbm_copy = measure_copy_bandwidth()
     log(f"[bench] device copy bandwidth (torch copy of 2 GiB): {hbm_copy:.0f} GB/s")
+    gemm_peak = measure_gemm_peak()
+    log(f"[bench] library GEMM rates (TFLOP/s): {gemm_peak}")
     log(f"[bench] workload {wl.name}: {wl.n}x{wl.n}, k={wl.k}, dt={wl.dt:.6g}")
     fp64, s64 = run_path(m, wl, "fp64", args.steps, args.warmup, args.tune_cache)
     if args.precision == "fp64":
@@ -756,6 +790,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": head["roofline"],
         "hbm_copy_gbs": hbm_copy,
+        "gemm_tflops_measured": gemm_peak,
+        "mfma_peak_tflops_nominal": {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
+                                     "bf16": 2500.0},
         "krylov_iters_per_stage": head["krylov_iters_per_stage"],
         "max_trace_relres": head["max_trace_relres"],
         "launch": {k: head[k] for k in ("schedule", "grid_caps", "graph_steps",
