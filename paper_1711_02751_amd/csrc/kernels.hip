@@ -2438,12 +2438,14 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
     rin += mb.to; t += mb.to; rh += mb.to; pin += mb.to; vin += mb.to;
     pout += mb.to; vout += mb.to; r += mb.to; d += mb.to;
     const T *src[4] = {rin, t, pin, vin};
-    // FP32 with the tile held in registers (K <= 7): the staging thread of
-    // an own face also reads d there and updates r, p and d, and leaves r'
-    // in LDS for the matrix-core lanes (which hold rh) to sum rh.r' and
-    // r'.r'.  FP64 keeps its registers for occupancy and updates the own
-    // faces after the contraction.
-    constexpr bool kOwnStage = sizeof(T) == 4 && StagedTile<K, T, 4>::kHold;
+    // With the tile held in registers (K <= 7): the staging thread of an
+    // own face also reads d there and updates r, p and d, and leaves r' in
+    // LDS for the matrix-core lanes (which hold rh) to sum rh.r' and r'.r'.
+    // FP32 always; FP64 where one block runs per CU anyway (K >= 6).  FP64
+    // at K <= 5 keeps its registers for two blocks per CU and updates the
+    // own faces after the contraction, reading them again.
+    constexpr bool kOwnStage =
+        (sizeof(T) == 4 || MFOcc<K>::value == 1) && StagedTile<K, T, 4>::kHold;
     const T *osrc[1] = {d};
     const TileWalk tw = tile_walk(lb, mb.nbf, face_tiles(mb));
     StagedTile<K, T, 4, kOwnStage ? 1 : 0> st;
