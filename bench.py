@@ -727,8 +727,8 @@ def main():
                     help="run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs and "
-              f"measures a single GPU (the multi-GPU decomposition is design only).",
+        print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs and is "
+              f"measured on a single GPU (the multi-GPU decomposition is design only).",
               file=sys.stderr)
         sys.exit(2)
 
