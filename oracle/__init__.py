@@ -16,6 +16,13 @@ Modules
              step of Algorithm 1 (Sec. 5), stage solve by an LU factored once.
   hdg_dense  Brute-force dense HDG block system (Sec. 5, eq.
              linearizedHDGsystem) for tiny meshes, used to pin the stage solve.
+  box        Bounded rectangle: the exact moving vortex (Sec. 6.1) or
+             reflecting walls (Sec. 4.3, eq. reflection) as the boundary
+             faces' imaginary neighbour.
+  bathy      Variable depth on the periodic grid: nodal phi_B and the source
+             term of the linear part (Sec. 3.1, eq. psweGov).
+  basin      Reflecting walls over a variable depth (box's walls with
+             bathy's depth).
 
 Where the paper is silent the oracle takes these readings (each is listed in
 the design notes of the repository):
