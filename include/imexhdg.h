@@ -15,11 +15,13 @@
  *
  * Discretisation choices (the paper leaves them open): LGL nodes with
  * collocated LGL quadrature on elements and edges, trace nodes = LGL edge
- * nodes, flat bottom phi_B = g H.  Boundaries: periodic, or a bounded
- * rectangle whose boundary faces take the state of an imaginary neighbour
- * in the numerical fluxes and the conservation condition (the principle of
- * Sec. 4.3's wall condition) set from the exact translating vortex of
- * Sec. 6.1 (eq. tc_vortex_ic), as in the paper's vortex test.
+ * nodes; a flat bottom phi_B = g H, or a depth given at the nodes
+ * (config.variable_depth, imexhdg_set_depth).  Boundaries: periodic, or a
+ * bounded rectangle whose boundary faces take the state of an imaginary
+ * neighbour in the numerical fluxes and the conservation condition (the
+ * principle of Sec. 4.3's wall condition), set from the exact translating
+ * vortex of Sec. 6.1 (eq. tc_vortex_ic), as in the paper's vortex test, or
+ * by reflecting walls (Sec. 4.3, eq. reflection).
  *
  * Conventions
  *   - Every call returns an int status: IMEXHDG_OK (0) or a negative code.
@@ -168,8 +170,11 @@ typedef struct imexhdg_config {
                                 residual, matrix-free with the nodal phi_B,
                                 corrected by the constant-depth (phi_B =
                                 g H) HDG stage solve until its relative
-                                norm is at most refine_rtol.  Periodic,
-                                single contexts; steps run host-driven.   */
+                                norm is at most refine_rtol.  Periodic or
+                                walled (IMEXHDG_BOUNDARY_WALL: a closed
+                                basin, the depth mirrored across each
+                                wall), single contexts; steps run
+                                host-driven.                              */
     double  vortex[5];       /* u_inf, v_inf, beta, xc, yc of
                                 IMEXHDG_BOUNDARY_VORTEX (finite)           */
 } imexhdg_config;
@@ -271,8 +276,8 @@ int imexhdg_set_state(imexhdg_ctx *ctx, int vars, const double *a,
  * Sec. 3.1: phi_B = g B): host array of n_nodes doubles in the host state
  * ordering, all finite and positive, copied during the call.  Takes effect
  * from the next step; VARS_DEPTH state arrays are converted with it
- * (phi_eta = g (h - B)).  IMEXHDG_E_INVAL for a flat-bottom context or a
- * bad value.                                                             */
+ * (phi_eta = g (h - B)), on the host and by imexhdg_set_state_device.
+ * IMEXHDG_E_INVAL for a flat-bottom context or a bad value.              */
 int imexhdg_set_depth(imexhdg_ctx *ctx, const double *B);
 
 /* The same from device memory without a host copy, e.g. from a torch

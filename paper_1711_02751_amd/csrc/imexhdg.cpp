@@ -549,8 +549,10 @@ int validate(const imexhdg_config *c) {
         return fail(IMEXHDG_E_INVAL, "unknown boundary");
     if (c->variable_depth != 0 && c->variable_depth != 1)
         return fail(IMEXHDG_E_INVAL, "variable_depth must be 0 or 1");
-    if (c->variable_depth && c->boundary != IMEXHDG_BOUNDARY_PERIODIC)
-        return fail(IMEXHDG_E_INVAL, "variable depth takes periodic meshes only");
+    if (c->variable_depth && c->boundary == IMEXHDG_BOUNDARY_VORTEX)
+        return fail(IMEXHDG_E_INVAL,
+                    "variable depth takes periodic meshes or walls (the vortex is a flat-bottom "
+                    "solution)");
     if (c->boundary != IMEXHDG_BOUNDARY_PERIODIC) {
         if (c->boundary == IMEXHDG_BOUNDARY_VORTEX)
             for (double v : c->vortex)
@@ -965,8 +967,11 @@ int stage_solve_const(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters
     } else {
         LAUNCH(IMEXHDG_K_LOCAL_APPLY, launch_local_apply(c->geom, c->bt, R, c->Z, c->stream));
     }
-    if (stage >= 0) {
-        int rf = fill_ghosts(c, c->Z, stage, false);
+    // the ghosts of Z: the boundary data of the step's stage (exact-solution
+    // boundary), or the reflection of Z (walls: part of the operator, so
+    // also for the corrections of a variable-depth stage, stage < 0)
+    if (stage >= 0 || c->wall) {
+        int rf = fill_ghosts(c, c->Z, stage >= 0 ? stage : 0, false);
         if (rf) return rf;
     }
     LAUNCH(IMEXHDG_K_TRACE_RHS,
@@ -1012,6 +1017,8 @@ int stage_solve(imexhdg_ctx *c, const double *R, double *Q, int32_t *iters, doub
     int status = IMEXHDG_OK;
     HIP_TRY(hipMemcpyAsync(c->xsave, c->x, c->T * 8, hipMemcpyDeviceToDevice, c->stream));
     for (int it = 0;; ++it) {
+        // walls: the residual's boundary flux reads the reflection of Q
+        if (int rf = fill_ghosts(c, Q, stage >= 0 ? stage : 0, false)) return rf;
         HIP_TRY(launch_stage_res_var(c->geom, c->bt, Q, c->pB, R, c->aii, c->dres, c->dcpart,
                                      c->nvb, c->stream));
         HIP_TRY(hipMemcpyAsync(c->hcpart, c->dcpart, 2 * (size_t)c->nvb * 8,
@@ -1481,8 +1488,16 @@ int state_to_device(const imexhdg_ctx *c, const MemberHost &m, int vars, const d
                          dst = (size_t)n * nel + device_elem(m, e);
             double p, U, V;
             if (vars == IMEXHDG_VARS_DEPTH) {
-                const double Hn = c->vdepth ? c->hB[src] : H;   // one member
-                p = g * (a[src] - Hn);
+                // phi_eta = g h - phi_B at the node (one member), the
+                // arithmetic of the device path (set_state_device): both
+                // products rounded before the difference
+                if (c->vdepth) {
+                    const double gh = g * a[src];
+                    const double pb = g * c->hB[src];
+                    p = gh - pb;
+                } else {
+                    p = g * (a[src] - H);
+                }
                 U = g * b[src];
                 V = g * cc[src];
             } else {
@@ -1905,7 +1920,7 @@ int set_member_state_device(imexhdg_ctx *c, int m, int vars, int dtype, const vo
     const int blocks = state_in_blocks(host_elems(mh), K, c->pstride);
     HIP_TRY(launch_state_in(src, dtype == IMEXHDG_DTYPE_F32, vars == IMEXHDG_VARS_DEPTH,
                             c->cfg.g, c->cfg.H, host_elems(mh), K, c->Z + mh.vo, c->dpart,
-                            blocks, c->stream, mh.bx, mh.nx));
+                            blocks, c->stream, mh.bx, mh.nx, c->vdepth ? c->pB : nullptr));
     double bad = 0.0;
     int rc = read_partials(c, 1, 0, blocks, &bad);
     if (rc) return rc;
@@ -2106,13 +2121,29 @@ int imexhdg_set_depth(imexhdg_ctx *c, const double *B) {
     if (!c->vdepth) return fail(IMEXHDG_E_INVAL, "the context has a flat bottom (variable_depth = 0)");
     const MemberHost &m = c->mh[0];
     const int K = c->geom.K;
+    for (size_t i = 0; i < (size_t)host_elems(m) * K * K; ++i)
+        if (!std::isfinite(B[i]) || !(B[i] > 0.0))
+            return fail(IMEXHDG_E_INVAL, "depth must be finite and positive");
+    // device element (ex, ey) takes the depth of host element (sx, sy); a
+    // walled mesh's ghosts take their real neighbour's depth mirrored across
+    // the wall (the face nodes then see one depth on both sides)
+    const int hnx = m.bx > 0 ? m.bx : m.nx;
     std::vector<double> h((size_t)K * K * m.nel);
-    for (int e = 0; e < m.nel; ++e)
-        for (int n = 0; n < K * K; ++n) {
-            const double b = B[(size_t)e * K * K + n];
-            if (!std::isfinite(b) || !(b > 0.0))
-                return fail(IMEXHDG_E_INVAL, "depth must be finite and positive");
-            h[(size_t)n * m.nel + e] = c->cfg.g * b;
+    for (int ey = 0; ey < m.ny; ++ey)
+        for (int ex = 0; ex < m.nx; ++ex) {
+            int sx = ex, sy = ey;
+            bool fx = false, fy = false;
+            if (m.bx > 0) {
+                if (ex >= m.bx) { sx = ex == m.bx ? m.bx - 1 : 0; fx = true; }
+                if (ey >= m.by) { sy = ey == m.by ? m.by - 1 : 0; fy = true; }
+            }
+            const size_t src = ((size_t)sy * hnx + sx) * K * K;
+            const size_t de = (size_t)ey * m.nx + ex;
+            for (int j = 0; j < K; ++j)
+                for (int i = 0; i < K; ++i) {
+                    const int si = fx ? K - 1 - i : i, sj = fy ? K - 1 - j : j;
+                    h[(size_t)(j * K + i) * m.nel + de] = c->cfg.g * B[src + sj * K + si];
+                }
         }
     HIP_TRY(hipMemcpyAsync(c->pB, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(stream_sync(c));

@@ -2683,7 +2683,10 @@ __global__ __launch_bounds__(64 * K) void k_dg_var(const double *__restrict__ q,
     q += mb.vo;
     pB += mb.vo / 3;
     const int e = lb * 64 + lane;
-    const bool active = e < mb.nel;
+    // a bounded member's ghost elements carry boundary states only: no
+    // residual, no contribution to the norms
+    const bool ghost = mb.bx > 0 && (e % mb.nx >= mb.bx || e / mb.nx >= mb.by);
+    const bool active = e < mb.nel && !ghost;
     const Nbr nb = neighbours(active ? e : 0, mb.nx, mb.ny);
     const size_t nel = mb.nel, NN = (size_t)K * K * nel;
     auto at = [&](int row, int i, int el, double v[3], double &b) {
@@ -2917,8 +2920,9 @@ __global__ __launch_bounds__(64 * K) void k_diag(const double *__restrict__ q, c
 // element-fastest device layout; the checks are those of the host path.
 template <typename T>
 __global__ void k_state_in(const T *__restrict__ src, int depth, double g, double H,
-                           double phiB, int nel, int KK, double *__restrict__ dst,
-                           double *partials, int stride, int bx, int nxp) {
+                           double phiB, const double *__restrict__ pBn, int nel, int KK,
+                           double *__restrict__ dst, double *partials, int stride, int bx,
+                           int nxp) {
     const size_t nn = (size_t)nel * KK;
     // bounded member: real element e = ey bx + ex sits at ey nxp + ex of the
     // padded layout of nxp (nel / bx + 2) elements
@@ -2927,15 +2931,23 @@ __global__ void k_state_in(const T *__restrict__ src, int depth, double g, doubl
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
          i += (size_t)gridDim.x * blockDim.x) {
         const double a = (double)src[i], b = (double)src[nn + i], c = (double)src[2 * nn + i];
-        const double p = depth ? g * (a - H) : a;
-        const double U = depth ? g * b : b;
-        const double V = depth ? g * c : c;
-        const double phi = p + phiB;
-        const bool ok = isfinite(p) && isfinite(U) && isfinite(V) && phi > 0.0;
-        if (!ok) bad[0] += 1.0;
         const size_t e = i / KK, n = i - e * KK;
         const size_t ed = bx > 0 ? (e / bx) * nxp + e % bx : e;
         const size_t o = n * nd + ed, nnd = nd * KK;
+        // the node's phi_B: nodal with a variable depth, else g H
+        const double pb = pBn ? pBn[o] : phiB;
+        // g h rounded before the subtraction (no fused multiply-add), as the
+        // host conversion rounds it
+        double p;
+        {
+#pragma clang fp contract(off)
+            p = depth ? (pBn ? g * a - pb : g * (a - H)) : a;
+        }
+        const double U = depth ? g * b : b;
+        const double V = depth ? g * c : c;
+        const double phi = p + pb;
+        const bool ok = isfinite(p) && isfinite(U) && isfinite(V) && phi > 0.0;
+        if (!ok) bad[0] += 1.0;
         dst[o] = p;
         dst[nnd + o] = U;
         dst[2 * nnd + o] = V;
@@ -3310,14 +3322,14 @@ int state_in_blocks(int nel, int K, int cap) {
 
 hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, double H,
                            int nel, int K, double *dst, double *partials, int blocks,
-                           hipStream_t s, int bx, int nxp) {
+                           hipStream_t s, int bx, int nxp, const double *pBn) {
     const double phiB = g * H;
     if (f32)
         KLAUNCH(k_state_in<float>, dim3(blocks), dim3(256), 0, s, (const float *)src,
-                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks, bx, nxp);
+                depth ? 1 : 0, g, H, phiB, pBn, nel, K * K, dst, partials, blocks, bx, nxp);
     else
         KLAUNCH(k_state_in<double>, dim3(blocks), dim3(256), 0, s, (const double *)src,
-                depth ? 1 : 0, g, H, phiB, nel, K * K, dst, partials, blocks, bx, nxp);
+                depth ? 1 : 0, g, H, phiB, pBn, nel, K * K, dst, partials, blocks, bx, nxp);
     return hipGetLastError();
 }
 

@@ -276,10 +276,13 @@ hipError_t launch_zero(void *p, size_t n32, hipStream_t s);
 // partials [1][blocks]: per block, the count of nodes that are not finite
 // or not of positive depth.
 // bx > 0 (bounded member): src holds the bx x (nel / bx) real elements and
-// dst is the padded layout with nxp = bx + 2 elements per row.
+// dst is the padded layout with nxp = bx + 2 elements per row.  pBn: the
+// nodal phi_B in dst's layout (variable depth: phi_eta = g h - phi_B at the
+// node), or nullptr for phi_B = g H.
 hipError_t launch_state_in(const void *src, bool f32, bool depth, double g, double H,
                            int nel, int K, double *dst, double *partials, int blocks,
-                           hipStream_t s, int bx = 0, int nxp = 0);
+                           hipStream_t s, int bx = 0, int nxp = 0,
+                           const double *pBn = nullptr);
 // Blocks launch_state_in uses for nel elements of degree K - 1 (at most cap).
 int state_in_blocks(int nel, int K, int cap);
 

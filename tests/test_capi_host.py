@@ -43,7 +43,7 @@ def test_validation_errors_are_host_only():
            dict(trace_guess=2), dict(local_sweeps=4), dict(local_sweeps=-1),
            dict(precision=2, local_sweeps=3), dict(boundary=3), dict(boundary=-1),
            dict(boundary=1, vortex=(1.0, 0.0, float("nan"), 0.0, 0.0)),
-           dict(variable_depth=2), dict(variable_depth=1, boundary=2)]
+           dict(variable_depth=2), dict(variable_depth=1, boundary=1)]
     for kw in bad:
         base = dict(nx=4, ny=3, degree=3, dt=0.01)
         base.update(kw)

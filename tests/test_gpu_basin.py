@@ -1,0 +1,142 @@
+"""Closed basin: reflecting walls over a variable depth (config boundary =
+WALL with variable_depth, imexhdg_set_depth; Sec. 3.1 eq. psweGov, Sec. 4.3
+eq. reflection) through the C ABI, against the oracle (oracle/basin.py):
+
+  * whole ARS2 / ARS3 steps on square and ragged-tile meshes, every node
+    within 1e-10 of the oracle (FP64) and 1e-8 (MIXED); the defect
+    corrections per stage are counted and bounded;
+  * a constant depth given through set_depth reproduces the flat-bottom
+    walled path; a lake at rest over the uneven bottom stays at rest; mass
+    is conserved;
+  * set_state_device with depth variables converts with the nodal depth,
+    bitwise as set_state does.
+"""
+import numpy as np
+import pytest
+
+from oracle import basin, imex, swe
+from paper_1711_02751_amd import imexhdg as m
+from test_oracle_basin import basin_state, bottom
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def make_basin(nx, ny, k, dt, amp=0.2, L=(1.0, 1.0), g=9.81, scheme=m.SCHEME_ARS232, **kw):
+    tab = imex.ars232() if scheme == m.SCHEME_ARS232 else imex.ars443()
+    mesh = swe.Mesh(nx, ny, L[0], L[1], k)
+    B = bottom(mesh, amp=amp)
+    cfg = m.default_config(nx=nx, ny=ny, Lx=L[0], Ly=L[1], degree=k, g=g, H=1.0, dt=dt,
+                           scheme=scheme, physics=m.PHYSICS_NONLINEAR,
+                           boundary=m.BOUNDARY_WALL, variable_depth=1, **kw)
+    S = m.Solver(cfg)
+    S.set_depth(B.ravel())
+    P = basin.BasinProblem(nx, ny, L[0], L[1], k, g, B, dt, tableau=tab)
+    return P, S, B
+
+
+def state(S, P):
+    return np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)).reshape(P.mesh.shape)
+
+
+def rel_max(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def initial(P, g=9.81):
+    """A tenth of the oracle tests' state: a water-height perturbation and a
+    flow with normal momentum on the walls."""
+    return 0.1 * basin_state(P.mesh, g, 1.0, seed=11)
+
+
+@pytest.mark.parametrize("nx,ny,k,scheme,amp,steps,L", [
+    (5, 5, 3, m.SCHEME_ARS232, 0.2, 4, (1.0, 1.0)),
+    (20, 6, 2, m.SCHEME_ARS443, 0.3, 3, (2.0, 0.8)),
+    (9, 7, 4, m.SCHEME_ARS232, 0.1, 3, (1.0, 1.2)),
+])
+def test_basin_steps_match_oracle(nx, ny, k, scheme, amp, steps, L):
+    print(f"basin steps {nx}x{ny} k={k} scheme={scheme} amp={amp}", flush=True)
+    P, S, _ = make_basin(nx, ny, k, 0.004, amp=amp, L=L, scheme=scheme)
+    q0 = initial(P)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    S.step(steps)
+    d = S.diag()
+    ref = P.run(q0, steps)
+    err = rel_max(state(S, P), ref)
+    stages = d["stage_solves"] - d["depth_corrections"]
+    per_stage = d["depth_corrections"] / max(stages, 1)
+    print("  rel max err", err, "corrections per stage", per_stage, flush=True)
+    assert err < 1e-10
+    assert rel_max(ref, q0) > 1e-3
+    assert 1 <= per_stage <= 20
+
+
+def test_basin_mixed_precision():
+    P, S, _ = make_basin(6, 6, 3, 0.004, precision=m.PREC_MIXED, krylov_rtol=1e-6,
+                         refine_rtol=1e-9, refine_max=8)
+    q0 = initial(P)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    S.step(4)
+    err = rel_max(state(S, P), P.run(q0, 4))
+    print("basin mixed rel max err", err, flush=True)
+    assert err < 1e-8
+
+
+def test_constant_depth_is_the_flat_walled_path():
+    nx, ny, k, g, dt = 7, 5, 3, 9.81, 0.004
+    kw = dict(nx=nx, ny=ny, degree=k, g=g, H=1.0, dt=dt, boundary=m.BOUNDARY_WALL,
+              launch=m.LAUNCH_HOST)
+    flat = m.Solver(m.default_config(**kw))
+    var = m.Solver(m.default_config(variable_depth=1, **kw))
+    var.set_depth(np.full(var.n_nodes, 1.0))
+    q0 = 0.1 * basin_state(swe.Mesh(nx, ny, 1.0, 1.0, k), g, 1.0).reshape(3, -1)
+    for S in (flat, var):
+        S.set_state(*q0, vars=m.VARS_GEOPOTENTIAL)
+        S.step(4)
+    a = np.stack(flat.get_state(vars=m.VARS_GEOPOTENTIAL))
+    b = np.stack(var.get_state(vars=m.VARS_GEOPOTENTIAL))
+    print("constant depth vs flat walls", rel_max(b, a), flush=True)
+    assert rel_max(b, a) < 1e-12
+
+
+def test_lake_at_rest_and_mass():
+    P, S, B = make_basin(6, 5, 4, 0.01, amp=0.3)
+    h = B.ravel() + 0.05             # a flat surface over the uneven bottom
+    z = np.zeros_like(h)
+    S.set_state(h, z, z, vars=m.VARS_DEPTH)
+    q0 = state(S, P)
+    S.step(4)
+    drift = rel_max(state(S, P), q0)
+    print("lake at rest drift", drift, flush=True)
+    assert drift < 1e-10
+    q0 = initial(P)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    m0 = S.diag()["mass"][0]
+    S.step(6)
+    scale = np.sum(P.mesh.mass() * np.abs(q0[0]))
+    assert abs(S.diag()["mass"][0] - m0) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("boundary", [m.BOUNDARY_PERIODIC, m.BOUNDARY_WALL])
+def test_set_state_device_converts_with_the_nodal_depth(boundary):
+    nx, ny, k = 6, 4, 3
+    mesh = swe.Mesh(nx, ny, 1.0, 1.0, k)
+    B = bottom(mesh, amp=0.3).ravel()
+    cfg = m.default_config(nx=nx, ny=ny, degree=k, g=9.81, H=1.0, dt=0.004,
+                           boundary=boundary, variable_depth=1)
+    A, D = m.Solver(cfg), m.Solver(cfg)
+    for S in (A, D):
+        S.set_depth(B)
+    rng = np.random.default_rng(2)
+    host = np.stack([B + 0.05 + 0.01 * rng.standard_normal(B.size),
+                     0.01 * rng.standard_normal(B.size), 0.01 * rng.standard_normal(B.size)])
+    A.set_state(*host, vars=m.VARS_DEPTH)
+    D.set_state_device(torch.from_numpy(host).to(D.device).contiguous(), vars=m.VARS_DEPTH)
+    a = np.stack(A.get_state(vars=m.VARS_GEOPOTENTIAL))
+    b = np.stack(D.get_state(vars=m.VARS_GEOPOTENTIAL))
+    assert np.array_equal(a, b)
+    # a node of negative total depth
+    bad = host.copy()
+    bad[0, 3] = -0.1
+    with pytest.raises(m.ImexError):
+        D.set_state_device(torch.from_numpy(bad).to(D.device).contiguous(), vars=m.VARS_DEPTH)
