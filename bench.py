@@ -594,16 +594,20 @@ def run_bathymetry(m, n=128, k=4, amp=0.2, steps=10, warmup=2):
     y)) on the periodic n x n mesh of degree k (g = 9.81, H = 1, the bump
     recipe's state and time step), host-driven steps with defect-corrected
     stage solves, beside the flat-bottom path on the same mesh, also
-    host-driven."""
+    host-driven; and the same depth and state in a closed basin (reflecting
+    walls on the four sides)."""
     import torch
     from paper_1711_02751_amd import workloads as W
     dt = W.bump_dt(n, k)
     out = {"workload": f"variable depth, {n}x{n}, k={k}, bottom +-{amp:.0%} (+-{amp / 2:.0%}), "
-                       f"ARS2, dt={dt:.4g}", "n_dof": 3 * n * n * (k + 1) ** 2, "steps": steps}
+                       f"ARS2, dt={dt:.4g}; periodic, and a closed basin (walls)",
+           "n_dof": 3 * n * n * (k + 1) ** 2, "steps": steps}
     mixed = dict(precision=m.PREC_MIXED, krylov_rtol=MIXED_KRYLOV_RTOL,
                  refine_rtol=MIXED_REFINE_RTOL, refine_max=8)
+    wall = dict(boundary=m.BOUNDARY_WALL)
     for label, vd, kw in (("variable", 1, {}), ("variable_mixed", 1, mixed), ("flat", 0, {}),
-                          ("flat_mixed", 0, mixed)):
+                          ("flat_mixed", 0, mixed), ("basin", 1, wall),
+                          ("basin_mixed", 1, dict(mixed, **wall))):
         cfg = m.default_config(nx=n, ny=n, degree=k, g=9.81, H=1.0, dt=dt,
                                launch=m.LAUNCH_HOST, variable_depth=vd, **kw)
         S = m.Solver(cfg)
