@@ -1297,6 +1297,14 @@ __global__ __launch_bounds__((LocalLp<K, LP>::THREADS)) void k_local_lp(
 template <int K> struct MFOcc {
     static constexpr int value = K <= 5 ? 2 : 1;
 };
+// The bounded-mesh variants (BND) hold the boundary-row state on top: at
+// K <= 5 they are held to 128 VGPRs (four waves per SIMD) where that costs
+// no spill, so that they keep the periodic kernels' two blocks per CU (K1f;
+// the FP32 K1 and refinement check).
+template <int K, typename T, bool BND, bool K1F> struct FaceOcc {
+    static constexpr int value =
+        (BND && K <= 5 && (K1F || sizeof(T) == 4)) ? 4 : MFOcc<K>::value;
+};
 // The residual kernel at K <= 5 must keep two 512-thread blocks per CU
 // (at most 128 VGPRs: four waves per SIMD).
 template <int K> struct ResidOcc {
@@ -1693,19 +1701,21 @@ __device__ __forceinline__ int side_slot(int side, int e) {
 // Bounded mesh: a boundary row adds its side's corrections, each applied to
 // the staged face of its slot for the lanes whose face is on that side (the
 // B operand is zero for the other lanes): the self slot only with
-// exact-solution data, the real element's four faces with walls.
-template <int K, typename T>
-__device__ __forceinline__ void boundary_rows(const WaveFaces &wf, const T *sB, int nent,
-                                              typename MfmaT<T>::v4 (&acc)[1][MF<K>::NMB]) {
+// exact-solution data (NENT = 1), the real element's four faces with walls
+// (NENT = 4).  The entries are unrolled so that the fragment loads of a
+// side are in flight together (one round trip per side, not per entry).
+template <int K, typename T, int NENT>
+__device__ __forceinline__ void boundary_rows_n(const WaveFaces &wf, const T *sB,
+                                                typename MfmaT<T>::v4 (&acc)[1][MF<K>::NMB]) {
     using TL = Tile<K>;
     constexpr int B3 = TL::B3, NF = TileRow<K, T>::stride, KS = MF<K>::KS, NMB = MF<K>::NMB;
-    if (wf.dfr == nullptr) return;
     const int lane = threadIdx.x & 63, q = lane >> 4, lx = lane & 15;
     const T *dfr = (const T *)wf.dfr;
     for (int h = 0; h < 2; ++h) {
         const int side = 2 * wf.set + h;
         if (!__any(wf.bt == side)) continue;
-        for (int e = 0; e < nent; ++e) {
+#pragma unroll
+        for (int e = 0; e < NENT; ++e) {
             const int li = slot_lds(wf.set, side_slot(side, e), lx, wf.sub, TL::NX, TL::XC,
                                     TL::YC);
 #pragma unroll
@@ -1720,6 +1730,14 @@ __device__ __forceinline__ void boundary_rows(const WaveFaces &wf, const T *sB, 
             }
         }
     }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void boundary_rows(const WaveFaces &wf, const T *sB, int nent,
+                                              typename MfmaT<T>::v4 (&acc)[1][MF<K>::NMB]) {
+    if (wf.dfr == nullptr) return;
+    if (nent == 4) boundary_rows_n<K, T, 4>(wf, sB, acc);
+    else boundary_rows_n<K, T, 1>(wf, sB, acc);
 }
 
 // LDS index of this lane's own face of its wave's set.
@@ -2045,7 +2063,7 @@ __device__ __forceinline__ const float *ghat_frags(const Member &mb, float) { re
 // (p - omega v) at the seven faces of each row block (p = v = 0 here), v =
 // Ghat p; partials P1 = (rh.v, rh.r, r.r) over the own faces.
 template <int K, typename T, bool SCHED, bool BND>
-__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
+__global__ __launch_bounds__(kFaceThreads, (FaceOcc<K, T, BND, false>::value)) void k_bicg_k1(
     const Batch bt, const T *__restrict__ r, const T *__restrict__ rh,
     const T *__restrict__ pin, const T *__restrict__ vin, T *__restrict__ pout,
     T *__restrict__ vout, KrylovState *ks_all, const double *P3, double *P1, int stride) {
@@ -2149,7 +2167,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1(
 // tolerance is max(inner_rtol^2 ||rin||^2, (0.1 refine_rtol)^2 ||ghat||^2)
 // (an inner solve that starts below it is converged at once).
 template <int K, typename T, bool BND>
-__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_refine_k1(
+__global__ __launch_bounds__(kFaceThreads, (FaceOcc<K, T, BND, false>::value)) void k_refine_k1(
     const Batch bt, const T *__restrict__ rin, T *__restrict__ r, T *__restrict__ rh,
     T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ d, KrylovState *ks_all,
     const double *res_partials, int rstride, double refine_rtol, double inner_rtol,
@@ -2408,7 +2426,7 @@ __global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k2(
 // launch would let a block that starts after block 0 has finished skip its
 // updates).
 template <int K, typename T, bool SCHED, bool BND>
-__global__ __launch_bounds__(kFaceThreads, MFOcc<K>::value) void k_bicg_k1f(
+__global__ __launch_bounds__(kFaceThreads, (FaceOcc<K, T, BND, true>::value)) void k_bicg_k1f(
     const Batch bt, const T *__restrict__ rin, const T *__restrict__ t,
     const T *__restrict__ rh, const T *__restrict__ pin, const T *__restrict__ vin,
     T *__restrict__ pout, T *__restrict__ vout, T *__restrict__ r, T *__restrict__ d,
