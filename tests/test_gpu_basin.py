@@ -141,3 +141,30 @@ def test_set_state_device_converts_with_the_nodal_depth(boundary):
     bad[0, 3] = -0.1
     with pytest.raises(m.ImexError):
         D.set_state_device(torch.from_numpy(bad).to(D.device).contiguous(), vars=m.VARS_DEPTH)
+
+
+@pytest.mark.parametrize("boundary", [m.BOUNDARY_PERIODIC, m.BOUNDARY_WALL])
+@pytest.mark.parametrize("prec", [m.PREC_FP32, m.PREC_BF16])
+def test_variable_depth_reduced_precision_modes(boundary, prec):
+    """The FP32 / BF16 local solves inside the defect-corrected stage: the
+    state stays within 1e-6 of the FP64 oracle (the flat-bottom modes'
+    bound)."""
+    nx, ny, k, dt = 6, 6, 3, 0.004
+    mesh = swe.Mesh(nx, ny, 1.0, 1.0, k)
+    B = bottom(mesh, amp=0.2)
+    cfg = m.default_config(nx=nx, ny=ny, degree=k, g=9.81, H=1.0, dt=dt,
+                           physics=m.PHYSICS_NONLINEAR, boundary=boundary, variable_depth=1,
+                           precision=prec, krylov_rtol=1e-6, refine_rtol=1e-9, refine_max=8)
+    S = m.Solver(cfg)
+    S.set_depth(B.ravel())
+    if boundary == m.BOUNDARY_WALL:
+        P = basin.BasinProblem(nx, ny, 1.0, 1.0, k, 9.81, B, dt)
+    else:
+        from oracle import bathy
+        P = bathy.BathyProblem(nx, ny, 1.0, 1.0, k, 9.81, B, dt)
+    q0 = 0.1 * basin_state(mesh, 9.81, 1.0, seed=11)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    S.step(4)
+    err = rel_max(state(S, P), P.run(q0, 4))
+    print(f"variable depth boundary={boundary} precision={prec}: rel max err {err}", flush=True)
+    assert err < 1e-6
