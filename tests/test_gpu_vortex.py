@@ -84,6 +84,21 @@ def test_vortex_mixed_precision_matches_oracle():
     assert err < 1e-8
 
 
+@pytest.mark.parametrize("prec", [m.PREC_FP32, m.PREC_BF16])
+def test_vortex_reduced_precision_modes_match_oracle(prec):
+    """The FP32 / BF16 local solves and FP32 DG residual on a bounded mesh,
+    on the captured schedule: within 1e-6 of the FP64 oracle (the bound of
+    these modes on periodic meshes)."""
+    P, S = make_box(8, 8, 3, DT[3], precision=prec, krylov_rtol=1e-6, refine_rtol=1e-9,
+                    refine_max=8, launch=m.LAUNCH_GRAPH)
+    q0 = start(P, S)
+    S.step(12)
+    err = rel_max(state(S, P), P.run(q0, 12))
+    print(f"vortex precision={prec}: rel max err {err}", flush=True)
+    assert err < 1e-6
+    assert S.diag()["nonfinite"] == 0
+
+
 def test_vortex_nodes_are_the_oracle_nodes():
     P, S = make_box(6, 3, 3, DT[3], Ly=2.0)
     x, y = S.nodes()

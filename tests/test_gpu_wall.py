@@ -71,6 +71,20 @@ def test_wall_mixed_precision_matches_oracle():
     assert err < 1e-8
 
 
+@pytest.mark.parametrize("prec", [m.PREC_FP32, m.PREC_BF16])
+def test_wall_reduced_precision_modes_match_oracle(prec):
+    """The FP32 / BF16 local solves and FP32 DG residual with walls, on the
+    captured schedule: within 1e-6 of the FP64 oracle."""
+    P, S = make_wall(8, 8, 3, 0.004, precision=prec, krylov_rtol=1e-6, refine_rtol=1e-9,
+                     refine_max=8, launch=m.LAUNCH_GRAPH)
+    q0 = drop_state(P.mesh, 1.0, 100.0, sigma=0.2, xc=0.8, yc=1.1, umax=0.02, seed=2)
+    S.set_state(*q0.reshape(3, -1), vars=m.VARS_GEOPOTENTIAL)
+    S.step(10)
+    err = rel_max(state(S, P), P.run(q0, 10))
+    print(f"wall precision={prec}: rel max err {err}", flush=True)
+    assert err < 1e-6
+
+
 @pytest.mark.parametrize("dt", [0.002, 0.02])
 def test_water_height_perturbation_full_size(dt):
     """Sec. 6.2: 20 x 20 elements of degree 8 on [0, 2]^2, H_inf = 100,
