@@ -20,7 +20,7 @@ def _cfg(nx, ny, k, prec, **kw):
     dt = W.bump_dt(max(nx, ny), k)
     cfg = m.default_config(nx=nx, ny=ny, Lx=1.0, Ly=1.0, degree=k, g=9.81, H=1.0, dt=dt,
                            precision=prec, launch=m.LAUNCH_GRAPH, **kw)
-    if prec == m.PREC_MIXED:
+    if prec != m.PREC_FP64:      # MIXED and the FP32 / BF16 modes: FP32 inner solve
         cfg.krylov_rtol = 1e-6
         cfg.refine_rtol = 1e-11
         cfg.refine_max = 8
@@ -41,7 +41,7 @@ def _single(cfg, q0, nsteps):
     return np.stack(S.get_state(vars=m.VARS_GEOPOTENTIAL)).reshape(q0.shape)
 
 
-@pytest.mark.parametrize("prec", [m.PREC_FP64, m.PREC_MIXED])
+@pytest.mark.parametrize("prec", [m.PREC_FP64, m.PREC_MIXED, m.PREC_FP32, m.PREC_BF16])
 def test_members_evolve_as_alone(prec):
     k, nsteps = 3, 12
     print(f"ensemble of {len(MESHES)} prec={prec}", flush=True)
