@@ -54,6 +54,7 @@ def initial(P, g=9.81):
     (20, 6, 2, m.SCHEME_ARS443, 0.3, 3, (2.0, 0.8)),
     (9, 7, 4, m.SCHEME_ARS232, 0.1, 3, (1.0, 1.2)),
     (16, 16, 4, m.SCHEME_ARS232, 0.3, 10, (1.0, 1.0)),
+    (1, 4, 3, m.SCHEME_ARS443, 0.2, 3, (0.3, 1.0)),     # one element wide
 ])
 def test_basin_steps_match_oracle(nx, ny, k, scheme, amp, steps, L):
     print(f"basin steps {nx}x{ny} k={k} scheme={scheme} amp={amp}", flush=True)
